@@ -1,0 +1,251 @@
+/*
+ * hmdd — hierarchical-matrix (H-matrix) form of the 3D collocation
+ * displacement-discontinuity (DD) boundary-element elasticity operator, on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Sec. 3.1, "Solid mechanics" and "Final system"):
+ * for a mesh of flat elements carrying piecewise-constant DD, collocated at
+ * element centroids in an infinite isotropic elastic body (Young's modulus
+ * E, Poisson ratio nu), the traction change at every collocation point is
+ *     T - T0 = E . delta,
+ * written in each element's local frame (s1, s2, n) with element-major
+ * ordering [delta_s1, delta_s2, delta_n] per element (Sec. 3.1, "local
+ * Cartesian coordinate system").  E is compressed as an H-matrix: far-field
+ * admissible blocks become low-rank U V^T factors by adaptive cross
+ * approximation, near-field blocks stay dense (Sec. 3.1, hierarchical
+ * matrices).  The tangent system solved by the Krylov method is
+ *     A11 = E - eta/dt - C^ep
+ * (Sec. 3.1.1, mechanical Jacobian), with eta/dt + C^ep block diagonal.
+ *
+ * Conventions shared by every call:
+ *   - SI units: metres, pascals; coefficients of E in Pa/m.
+ *   - delta = u+ - u-.  Element frame: s1 = unit(v1 - v0),
+ *     n = unit((v1 - v0) x (v2 - v0)), s2 = n x s1; collocation point =
+ *     vertex mean.  A pressure p inside a crack is the load t = -p n.
+ *   - Vectors of DOFs: float64, column c of a block of nrhs vectors starts
+ *     at ptr + c * ld, entries element-major [s1, s2, n].
+ *   - Pointers named d_* are device pointers (HIP, current device); all
+ *     others are host pointers.  The caller owns every array it passes; the
+ *     library owns its opaque handles and the device memory behind them.
+ *   - hip_stream may be NULL (the null stream).  Work is enqueued on it;
+ *     calls return when the work is enqueued unless stated otherwise.
+ *   - Every call returns an hm_status; on failure hm_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this boundary.  NaN in
+ *     inputs is propagated, not detected.
+ */
+#ifndef HMDD_H
+#define HMDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HM_OK = 0,
+    HM_EINVAL = -1,        /* bad argument (null pointer, size, modulus, option) */
+    HM_ENOMEM = -2,        /* host or device allocation failed */
+    HM_EDEVICE = -3,       /* HIP runtime error or no usable gfx950 device */
+    HM_EBADMESH = -4,      /* degenerate, non-planar or non-rectangular element */
+    HM_EUNSUPPORTED = -5,  /* option combination not provided */
+    HM_ENOTCONV = -6,      /* solver did not reach the tolerance (best iterate returned) */
+    HM_EINTERNAL = -7
+} hm_status;
+
+enum { HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2 };
+
+typedef struct hm_mesh hm_mesh;
+typedef struct hm_op hm_op;
+
+/* Last error message of the calling thread ("" if none). */
+const char* hm_last_error(void);
+
+/* Library version string. */
+const char* hm_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Mesh                                                                */
+/* ------------------------------------------------------------------ */
+/*
+ * Create a mesh of flat elements (paper Sec. 3.1: triangles; planar
+ * rectangles are also accepted).
+ *   nv_per_elem : 3 (triangles) or 4 (planar rectangles, right angles)
+ *   xyz         : [n_vert][3] vertex coordinates (global frame, m)
+ *   conn        : [n_elem][nv_per_elem] 0-based vertex ids, counter-
+ *                 clockwise about the intended normal
+ * Errors: HM_EINVAL (sizes, ids out of range), HM_EBADMESH (element area
+ * below 1e-12 diam^2, quad not planar or not a rectangle within 1e-10
+ * relative).  Host-only; no device is touched.
+ */
+hm_status hm_mesh_create(int nv_per_elem, int64_t n_vert, const double* xyz, int64_t n_elem,
+                         const int64_t* conn, hm_mesh** out);
+void hm_mesh_destroy(hm_mesh* mesh);
+int64_t hm_mesh_num_elements(const hm_mesh* mesh);
+
+/*
+ * Element geometry in the stated convention (host arrays, any may be NULL):
+ *   centroid [N][3], frame [N][3][3] (rows s1, s2, n), area [N].
+ * Host-only.
+ */
+hm_status hm_mesh_frames(const hm_mesh* mesh, double* centroid, double* frame, double* area);
+
+/* ------------------------------------------------------------------ */
+/* Planning only                                                        */
+/* ------------------------------------------------------------------ */
+/*
+ * Cluster tree and block tree that hm_operator_build would use for
+ * (leaf_size, eta) (paper Sec. 3.1, hierarchical matrices: far field
+ * low-rank, near field full).  Host-only; no device is touched.
+ *   perm [N] (or NULL): element id at each cluster-order position.
+ */
+typedef struct {
+    int64_t n_leaves, n_dense_blocks, n_lowrank_blocks;
+    int64_t dense_entries;      /* sum of 9 m n over dense blocks */
+    int64_t lowrank_sum_mn;     /* sum of m + n (elements) over low-rank blocks */
+    int64_t max_leaf, min_leaf; /* elements per leaf */
+    int depth;
+    int64_t lowrank_by_level[64];
+} hm_plan_info;
+
+hm_status hm_plan_summary(const hm_mesh* mesh, int leaf_size, double eta, hm_plan_info* info, int64_t* perm);
+
+/* ------------------------------------------------------------------ */
+/* Exact influence coefficients                                        */
+/* ------------------------------------------------------------------ */
+/*
+ * Exact FP64 coefficient blocks of E (paper Sec. 3.1: analytical
+ * integration of the hypersingular kernel over each flat element, taken
+ * before the limit, at the receiver centroid), evaluated on the GPU:
+ *   d_out[r][c][a][b] = E^{ab}_{d_rows[r], d_cols[c]}  (Pa/m)
+ * traction component a (receiver frame) at element rows[r] due to a unit DD
+ * component b (source frame) on element cols[c].
+ *   d_rows [nr], d_cols [nc] : int64 element ids (device)
+ *   d_out  [nr * nc * 9]     : float64 (device)
+ * Errors: HM_EINVAL for bad moduli (E <= 0, nu outside (-1, 1/2)) or
+ * sizes.  Ids are not range-checked on the device; the caller guarantees
+ * 0 <= id < N.
+ */
+hm_status hm_kernel_block(const hm_mesh* mesh, double young, double nu, int64_t nr, const int64_t* d_rows,
+                          int64_t nc, const int64_t* d_cols, double* d_out, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* H-matrix operator                                                    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int leaf_size;          /* max elements per cluster-tree leaf (1..64); default 64 */
+    double eta;             /* admissibility: min(diam) <= eta * dist; default 2 */
+    double aca_tol;         /* relative Frobenius tolerance per block; default 1e-6 */
+    int max_rank;           /* cap on the rank of a low-rank block (<= 192); default 192 */
+    int near_prec;          /* HM_F64 or HM_F32 for dense leaves */
+    int far_prec;           /* HM_F64, HM_F32 or HM_BF16 for low-rank factors */
+    int keep_f64_reference; /* also keep an all-FP64 copy (used by refinement) */
+    int recompress;         /* reserved, must be 0 */
+} hm_build_opts;
+
+/* Fill opts with the defaults above (near = far = HM_F64). */
+void hm_build_opts_default(hm_build_opts* opts);
+
+/*
+ * Build the H-operator of E for (mesh, young, nu) on the current device:
+ * cluster tree (recursive median bisection of centroids), block tree with
+ * the admissibility rule above (vertex bounding boxes), dense leaves and
+ * ACA factors computed by GPU kernels, packed into the requested
+ * precisions.  Blocks on the stream; returns after the build completes.
+ * In mixed forms (near_prec != HM_F64) the element self-blocks are kept
+ * in FP64 and applied in FP64.
+ * Errors: HM_EINVAL, HM_EUNSUPPORTED (precision combination), HM_ENOMEM,
+ * HM_EDEVICE, HM_EINTERNAL (an admissible block did not converge within
+ * max_rank: message names the block).
+ */
+hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const hm_build_opts* opts,
+                            void* hip_stream, hm_op** out);
+void hm_op_destroy(hm_op* op);
+
+typedef struct {
+    int64_t n_elements, n_dof;
+    int64_t n_leaves, n_dense_blocks, n_lowrank_blocks;
+    int64_t dense_entries;        /* stored near-field scalars (excluding padding) */
+    int64_t lowrank_entries;      /* stored U and V scalars, sum 3k(m+n) */
+    int64_t self_f64_entries;     /* FP64 self-block scalars (mixed forms) */
+    int64_t bytes_near, bytes_far, bytes_self, bytes_reference;
+    int min_rank, max_rank;
+    double mean_rank;
+    int near_prec, far_prec;
+    double build_ms, coef_ms, aca_ms, pack_ms;
+    int64_t max_dense_bytes_per_leaf;
+} hm_op_stats;
+
+hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
+
+/* apply flags */
+#define HM_APPLY_REFERENCE 1u   /* use the FP64 reference copy */
+#define HM_APPLY_TANGENT 2u     /* apply A11 = E - D (mask) instead of E */
+
+/*
+ * d_Y = E d_X (or A11 d_X with HM_APPLY_TANGENT) for nrhs vectors
+ * (1 <= nrhs <= 16).  d_X [nrhs][ldx], d_Y [nrhs][ldy] float64 (device),
+ * ldx, ldy >= 3N; d_X and d_Y must not overlap.  The product runs in the
+ * operator's precisions and is returned in FP64.  Not reentrant on one
+ * operator: concurrent applies of the same operator must be serialised.
+ */
+hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
+                            int64_t ldy, unsigned flags, void* hip_stream);
+
+/*
+ * Set the tangent terms: A11 = E - D on active elements, identity rows and
+ * columns on inactive ones (paper Sec. 3.1.1: D = eta/dt + C^ep, block
+ * diagonal 3x3 in local frames).
+ *   d_D    [N][3][3] float64 row-major (device) or NULL for D = 0
+ *   d_mask [N] uint8 (device), 1 = active, or NULL for all active
+ * Copies the data; also rebuilds the block-Jacobi preconditioner.
+ * Synchronises the stream.
+ */
+hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Krylov solve of the tangent system                                   */
+/* ------------------------------------------------------------------ */
+enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2 };
+
+typedef struct {
+    int restart;        /* GMRES(m) restart length, 1..256; default 50 */
+    int max_iter;       /* total inner iterations per right-hand side; default 1000 */
+    double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (FP64); default 1e-8 */
+    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3; default BLOCK3 */
+    int refine;         /* 1: FP64 iterative refinement around a low-precision inner solve */
+    double inner_rtol;  /* inner tolerance when refine = 1; default 1e-4 */
+    int max_refine;     /* refinement sweeps; default 20 */
+} hm_solve_opts;
+
+void hm_solve_opts_default(hm_solve_opts* opts);
+
+typedef struct {
+    int iterations;           /* inner GMRES iterations, max over right-hand sides */
+    int refinements;          /* outer sweeps (refine = 1) */
+    int converged;            /* 1 if every column met rtol */
+    double rel_residual;      /* max over columns of ||b - A11 x|| / ||b||, FP64, reference operator */
+    double solve_ms;
+    int n_history;            /* entries written to history (<= 1024) */
+    double history[1024];     /* max-over-columns relative residual after each inner iteration */
+} hm_solve_report;
+
+/*
+ * Solve A11 X = B for nrhs right-hand sides (1 <= nrhs <= 16) by
+ * right-preconditioned restarted GMRES(m) from X = 0, Arnoldi by classical
+ * Gram-Schmidt with reorthogonalisation in FP64 (the paper's outer/inner
+ * Krylov solves, Sec. 3.3.1, use BiCGSTAB or GMRES).  With refine = 1 the
+ * inner solve uses the operator's own precisions and an FP64 residual with
+ * the FP64 reference copy (built with keep_f64_reference) drives the
+ * correction sweeps.  d_B, d_X: [nrhs][ld] float64 (device).  Synchronous.
+ * Returns HM_ENOTCONV (with the best iterate in d_X and rep filled) when
+ * the tolerance is not met.
+ */
+hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const double* d_B, int64_t ldb,
+                   double* d_X, int64_t ldx, hm_solve_report* rep, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMDD_H */

@@ -1,0 +1,267 @@
+"""Python binding of libhmdd (H-matrix DD-BEM operator for MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and streams.  The functions keep
+the C names (hm_mesh_create, hm_operator_apply, ...); the classes Mesh and
+Operator are thin owners of the opaque handles.  If the library is not
+built, or no gfx950 device is present, calls raise HMError: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmdd.so")
+
+HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCONV, HM_EINTERNAL = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+HM_F64, HM_F32, HM_BF16 = 0, 1, 2
+HM_APPLY_REFERENCE, HM_APPLY_TANGENT = 1, 2
+HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3 = 0, 1, 2
+
+_STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "HM_EBADMESH",
+           -5: "HM_EUNSUPPORTED", -6: "HM_ENOTCONV", -7: "HM_EINTERNAL"}
+
+# symbols declared in include/hmdd.h
+EXPORTS = [
+    "hm_last_error", "hm_version", "hm_mesh_create", "hm_mesh_destroy", "hm_mesh_num_elements",
+    "hm_mesh_frames", "hm_plan_summary", "hm_kernel_block", "hm_build_opts_default",
+    "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_tangent_set",
+    "hm_solve_opts_default", "hm_solve",
+]
+
+
+class HMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
+                ("max_rank", ctypes.c_int), ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int),
+                ("keep_f64_reference", ctypes.c_int), ("recompress", ctypes.c_int)]
+
+
+class OpStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_elements", "n_dof", "n_leaves", "n_dense_blocks", "n_lowrank_blocks", "dense_entries",
+        "lowrank_entries", "self_f64_entries", "bytes_near", "bytes_far", "bytes_self", "bytes_reference")] + [
+        ("min_rank", ctypes.c_int), ("max_rank", ctypes.c_int), ("mean_rank", ctypes.c_double),
+        ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int), ("build_ms", ctypes.c_double),
+        ("coef_ms", ctypes.c_double), ("aca_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
+        ("max_dense_bytes_per_leaf", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("precond", ctypes.c_int), ("refine", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+                ("max_refine", ctypes.c_int)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("n_history", ctypes.c_int),
+                ("history", ctypes.c_double * 1024)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}
+        d["history"] = list(self.history[:self.n_history])
+        return d
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_leaves", "n_dense_blocks", "n_lowrank_blocks", "dense_entries", "lowrank_sum_mn", "max_leaf",
+        "min_leaf")] + [("depth", ctypes.c_int), ("lowrank_by_level", ctypes.c_int64 * 64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhmdd.so (raises HMError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HMError(HM_EDEVICE, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I, D, U = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+        sig = {
+            "hm_last_error": ([], ctypes.c_char_p),
+            "hm_version": ([], ctypes.c_char_p),
+            "hm_mesh_create": ([I, I64, P, I64, P, ctypes.POINTER(P)], I),
+            "hm_mesh_destroy": ([P], None),
+            "hm_mesh_num_elements": ([P], I64),
+            "hm_mesh_frames": ([P, P, P, P], I),
+            "hm_plan_summary": ([P, I, D, ctypes.POINTER(PlanInfo), P], I),
+            "hm_kernel_block": ([P, D, D, I64, P, I64, P, P, P], I),
+            "hm_build_opts_default": ([ctypes.POINTER(BuildOpts)], None),
+            "hm_operator_build": ([P, D, D, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)], I),
+            "hm_op_destroy": ([P], None),
+            "hm_operator_stats": ([P, ctypes.POINTER(OpStats)], I),
+            "hm_operator_apply": ([P, I, P, I64, P, I64, U, P], I),
+            "hm_tangent_set": ([P, P, P, P], I),
+            "hm_solve_opts_default": ([ctypes.POINTER(SolveOpts)], None),
+            "hm_solve": ([P, ctypes.POINTER(SolveOpts), I, P, I64, P, I64, ctypes.POINTER(SolveReport), P], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HM_OK:
+        raise HMError(status, lib().hm_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype):
+        raise HMError(HM_EINVAL, f"expected a CUDA tensor of {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- handles
+class Mesh:
+    """Owner of an hm_mesh handle (host-side geometry)."""
+
+    def __init__(self, xyz, conn):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int64)
+        h = ctypes.c_void_p()
+        _check(lib().hm_mesh_create(conn.shape[1], xyz.shape[0], xyz.ctypes.data, conn.shape[0], conn.ctypes.data,
+                                    ctypes.byref(h)))
+        self._h = h
+        self.ne = conn.shape[0]
+        self.ndof = 3 * self.ne
+
+    @classmethod
+    def from_workload(cls, m):
+        return cls(m.xyz, m.conn)
+
+    def frames(self):
+        cent = np.empty((self.ne, 3))
+        fr = np.empty((self.ne, 3, 3))
+        area = np.empty(self.ne)
+        _check(lib().hm_mesh_frames(self._h, cent.ctypes.data, fr.ctypes.data, area.ctypes.data))
+        return cent, fr, area
+
+    def plan(self, leaf_size=64, eta=2.0, want_perm=False):
+        info = PlanInfo()
+        perm = np.empty(self.ne, dtype=np.int64) if want_perm else None
+        _check(lib().hm_plan_summary(self._h, leaf_size, eta, ctypes.byref(info),
+                                     perm.ctypes.data if want_perm else None))
+        d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k != "lowrank_by_level"}
+        d["lowrank_by_level"] = {lv: int(info.lowrank_by_level[lv]) for lv in range(64) if info.lowrank_by_level[lv]}
+        return (d, perm) if want_perm else d
+
+    def kernel_block(self, young, nu, rows, cols, stream=None):
+        """Exact FP64 blocks E[rows, cols] computed on the GPU: [nr, nc, 3, 3] tensor."""
+        import torch
+
+        rows = torch.as_tensor(rows, dtype=torch.int64, device="cuda").contiguous()
+        cols = torch.as_tensor(cols, dtype=torch.int64, device="cuda").contiguous()
+        out = torch.empty((rows.numel(), cols.numel(), 3, 3), dtype=torch.float64, device="cuda")
+        _check(lib().hm_kernel_block(self._h, young, nu, rows.numel(), _dev_ptr(rows, torch.int64), cols.numel(),
+                                     _dev_ptr(cols, torch.int64), _dev_ptr(out, torch.float64), _stream(stream)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_mesh_destroy(self._h)
+            self._h = None
+
+
+def build_opts(**kw) -> BuildOpts:
+    o = BuildOpts()
+    lib().hm_build_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def solve_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().hm_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Operator:
+    """Owner of an hm_op handle: the H-matrix of E for a mesh and moduli."""
+
+    def __init__(self, mesh: Mesh, young: float, nu: float, stream=None, **opts):
+        self.mesh = mesh
+        self.ne = mesh.ne
+        self.ndof = mesh.ndof
+        h = ctypes.c_void_p()
+        o = build_opts(**opts)
+        _check(lib().hm_operator_build(mesh._h, young, nu, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def stats(self) -> dict:
+        st = OpStats()
+        _check(lib().hm_operator_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def apply(self, X, Y=None, reference=False, tangent=False, stream=None):
+        """Y = E X (or A11 X) for X a CUDA float64 tensor [nrhs, 3N] or [3N]."""
+        import torch
+
+        squeeze = X.dim() == 1
+        X2 = X.reshape(1, -1) if squeeze else X
+        if Y is None:
+            Y = torch.empty_like(X2)
+        flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
+        _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), X2.stride(0),
+                                       _dev_ptr(Y, torch.float64), Y.stride(0), flags, _stream(stream)))
+        return Y.reshape(-1) if squeeze else Y
+
+    def set_tangent(self, D=None, mask=None, stream=None):
+        """A11 = E - D on active elements (D: CUDA float64 [N,3,3]; mask: CUDA uint8 [N])."""
+        import torch
+
+        dp = _dev_ptr(D.contiguous(), torch.float64) if D is not None else None
+        mp = _dev_ptr(mask.contiguous(), torch.uint8) if mask is not None else None
+        self._keep = (D, mask)
+        _check(lib().hm_tangent_set(self._h, dp, mp, _stream(stream)))
+
+    def solve(self, B, stream=None, raise_on_notconv=True, **opts):
+        """Solve A11 X = B (B: CUDA float64 [nrhs, 3N]); returns (X, report dict)."""
+        import torch
+
+        squeeze = B.dim() == 1
+        B2 = (B.reshape(1, -1) if squeeze else B).contiguous()
+        X = torch.empty_like(B2)
+        o = solve_opts(**opts)
+        rep = SolveReport()
+        st = lib().hm_solve(self._h, ctypes.byref(o), B2.shape[0], _dev_ptr(B2, torch.float64), B2.stride(0),
+                            _dev_ptr(X, torch.float64), X.stride(0), ctypes.byref(rep), _stream(stream))
+        if st != HM_OK and (st != HM_ENOTCONV or raise_on_notconv):
+            _check(st)
+        return (X.reshape(-1) if squeeze else X), rep.as_dict()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_op_destroy(self._h)
+            self._h = None

@@ -1,0 +1,921 @@
+// Operator build: influence coefficients of dense leaves, adaptive cross
+// approximation (ACA) of admissible blocks, packing into the apply layout.
+//
+// Paper Sec. 3.1: E is stored as a hierarchical matrix whose far-field
+// blocks are low-rank and near-field blocks full.  Everything that touches
+// coefficients runs in FP64 on the GPU; low precisions appear only when the
+// finished factors are packed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "hm_op.hpp"
+#include "hm_util.hpp"
+
+namespace hm {
+
+// ------------------------------------------------------------------
+// coefficient kernels
+// ------------------------------------------------------------------
+__global__ void k_kernel_block(const ElemGeo* __restrict__ geo, const int64_t* __restrict__ rows,
+                               const int64_t* __restrict__ cols, int64_t nr, int64_t nc, double kG, double kN,
+                               double* __restrict__ out)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nr * nc) return;
+    int64_t r = p / nc, c = p - r * nc;
+    const ElemGeo& R = geo[rows[r]];
+    double x[3] = {R.c[0], R.c[1], R.c[2]};
+    double fr[9];
+    for (int k = 0; k < 9; ++k) fr[k] = R.fr[k];
+    double blk[9];
+    dd_block(x, fr, geo[cols[c]], kG, kN, blk);
+    for (int k = 0; k < 9; ++k) out[p * 9 + k] = blk[k];
+}
+
+struct DenseDesc {
+    int64_t t_begin, s_begin;  // cluster positions
+    int64_t out_off;           // FP64 row-major [3m][3n]
+    int32_t m, n;
+};
+
+// one thread per element pair of one dense leaf block (blockIdx.y)
+__global__ void k_dense_coef(const ElemGeo* __restrict__ geo, const DenseDesc* __restrict__ descs, double kG,
+                             double kN, double* __restrict__ out)
+{
+    const DenseDesc D = descs[blockIdx.y];
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= D.m * D.n) return;
+    int i = p / D.n, j = p - i * D.n;
+    const ElemGeo& R = geo[D.t_begin + i];
+    double x[3] = {R.c[0], R.c[1], R.c[2]};
+    double fr[9];
+    for (int k = 0; k < 9; ++k) fr[k] = R.fr[k];
+    double blk[9];
+    dd_block(x, fr, geo[D.s_begin + j], kG, kN, blk);
+    int64_t ld = 3 * (int64_t)D.n;
+    double* o = out + D.out_off + (3 * (int64_t)i) * ld + 3 * j;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) o[a * ld + b] = blk[3 * a + b];
+}
+
+// ------------------------------------------------------------------
+// adaptive cross approximation, 3x3-block partial pivoting, FP64
+// ------------------------------------------------------------------
+// Each step evaluates the residual of one element row (3 DOF rows) and of
+// the best element column (3 DOF columns).  The 3x3 pivot block is then
+// eliminated by up to three scalar cross steps with complete pivoting, so
+// the rank grows by 1..3 per step and the three DD components are always
+// sampled together (scalar ACA on interleaved components can stop early
+// when the normal and shear parts decouple).  Stop when the update of a
+// step has ||U_k V_k^T||_F <= tol ||S_k||_F on two consecutive steps.
+constexpr int kAcaThreads = 256;
+constexpr int kAcaMaxRank = 192;
+
+struct AcaDesc {
+    int64_t t_begin, s_begin;    // cluster positions
+    int64_t u_off, v_off;        // workspace: U [kmax][3m], V [kmax][3n]
+    int64_t rrow_off, rcol_off;  // scratch: Rrow [3][3n], Rcol [3m][3]
+    int64_t flag_off;            // bytes: row used [m], column used [n]
+    int32_t m, n, first_row, kmax;
+};
+
+__device__ inline void wave_argmax(double& v, int& i)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        double v2 = __shfl_xor(v, off);
+        int i2 = __shfl_xor(i, off);
+        if (v2 > v || (v2 == v && i2 >= 0 && (i < 0 || i2 < i))) {
+            v = v2;
+            i = i2;
+        }
+    }
+}
+
+// block-wide argmax (ties -> smaller index); all threads get the result
+__device__ inline void block_argmax(double& v, int& i, double* s_v, int* s_i)
+{
+    wave_argmax(v, i);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_v[w] = v;
+        s_i[w] = i;
+    }
+    __syncthreads();
+    v = s_v[0];
+    i = s_i[0];
+    for (int q = 1; q < kAcaThreads / 64; ++q) {
+        double v2 = s_v[q];
+        int i2 = s_i[q];
+        if (v2 > v || (v2 == v && i2 >= 0 && (i < 0 || i2 < i))) {
+            v = v2;
+            i = i2;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// out[q] = A[q] . b for q < nq; A rows of length L with stride L.
+// Deterministic: fixed per-thread order, fixed shuffle tree, fixed wave order.
+__device__ void block_dots(const double* A, const double* b, int64_t L, int nq, double* out, double* s_red)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q0 = 0; q0 < nq; q0 += 8) {
+        double acc[8];
+        for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+        for (int64_t x = threadIdx.x; x < L; x += kAcaThreads) {
+            double bx = b[x];
+            for (int t = 0; t < 8; ++t)
+                if (q0 + t < nq) acc[t] += A[(int64_t)(q0 + t) * L + x] * bx;
+        }
+        for (int t = 0; t < 8; ++t) {
+            double s = wave_sum(acc[t]);
+            if (lane == 0) s_red[w * 8 + t] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < 8 && q0 + (int)threadIdx.x < nq) {
+            double s = 0.0;
+            for (int ww = 0; ww < kAcaThreads / 64; ++ww) s += s_red[ww * 8 + threadIdx.x];
+            out[q0 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__ geo, const AcaDesc* __restrict__ descs,
+                                                     double kG, double kN, double tol, double* __restrict__ ws,
+                                                     uint8_t* __restrict__ flags, int* __restrict__ out_rank,
+                                                     int* __restrict__ out_status)
+{
+    const AcaDesc D = descs[blockIdx.x];
+    const int64_t m3 = 3 * (int64_t)D.m, n3 = 3 * (int64_t)D.n;
+    double* U = ws + D.u_off;
+    double* V = ws + D.v_off;
+    double* Rrow = ws + D.rrow_off;
+    double* Rcol = ws + D.rcol_off;
+    uint8_t* rowused = flags + D.flag_off;
+    uint8_t* colused = rowused + D.m;
+
+    __shared__ double s_piv[3 * kAcaMaxRank];   // U rows of the pivot element, then V rows
+    __shared__ double s_red[64];
+    __shared__ int s_ired[8];
+    __shared__ double s_uu[3][kAcaMaxRank], s_vv[3][kAcaMaxRank];
+    __shared__ double s_P[9];
+
+    for (int i = threadIdx.x; i < D.m; i += kAcaThreads) rowused[i] = 0;
+    for (int j = threadIdx.x; j < D.n; j += kAcaThreads) colused[j] = 0;
+    __syncthreads();
+
+    int k = 0, ipiv = D.first_row, conv = 0, misses = 0;
+    bool converged = false;
+    double normS2 = 0.0;
+    while (k + 1 <= D.kmax) {
+        // ---- residual of pivot row element ipiv ----
+        for (int idx = threadIdx.x; idx < 3 * k; idx += kAcaThreads) {
+            int a = idx / k, q = idx - a * k;
+            s_piv[a * kAcaMaxRank + q] = U[(int64_t)q * m3 + 3 * ipiv + a];
+        }
+        __syncthreads();
+        double best = -1.0;
+        int bestj = -1;
+        {
+            const ElemGeo& R = geo[D.t_begin + ipiv];
+            double x[3] = {R.c[0], R.c[1], R.c[2]};
+            double fr[9];
+            for (int t = 0; t < 9; ++t) fr[t] = R.fr[t];
+            for (int j = threadIdx.x; j < D.n; j += kAcaThreads) {
+                double blk[9];
+                dd_block(x, fr, geo[D.s_begin + j], kG, kN, blk);
+                for (int q = 0; q < k; ++q) {
+                    const double* vq = V + (int64_t)q * n3 + 3 * j;
+                    double v0 = vq[0], v1 = vq[1], v2 = vq[2];
+                    for (int a = 0; a < 3; ++a) {
+                        double ua = s_piv[a * kAcaMaxRank + q];
+                        blk[3 * a] -= ua * v0;
+                        blk[3 * a + 1] -= ua * v1;
+                        blk[3 * a + 2] -= ua * v2;
+                    }
+                }
+                double fro = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        Rrow[a * n3 + 3 * j + b] = blk[3 * a + b];
+                        fro += blk[3 * a + b] * blk[3 * a + b];
+                    }
+                if (!colused[j] && (fro > best)) {
+                    best = fro;
+                    bestj = j;
+                }
+            }
+        }
+        block_argmax(best, bestj, s_red, s_ired);
+        const int jpiv = bestj;
+        bool zero_row = (jpiv < 0) || !(best > 0.0);
+        int k0 = k;
+        if (!zero_row) {
+            // ---- residual of pivot column element jpiv ----
+            for (int idx = threadIdx.x; idx < 3 * k; idx += kAcaThreads) {
+                int b = idx / k, q = idx - b * k;
+                s_piv[b * kAcaMaxRank + q] = V[(int64_t)q * n3 + 3 * jpiv + b];
+            }
+            __syncthreads();
+            const ElemGeo& S = geo[D.s_begin + jpiv];
+            for (int i = threadIdx.x; i < D.m; i += kAcaThreads) {
+                const ElemGeo& R = geo[D.t_begin + i];
+                double x[3] = {R.c[0], R.c[1], R.c[2]};
+                double fr[9];
+                for (int t = 0; t < 9; ++t) fr[t] = R.fr[t];
+                double blk[9];
+                dd_block(x, fr, S, kG, kN, blk);
+                for (int q = 0; q < k; ++q) {
+                    const double* uq = U + (int64_t)q * m3 + 3 * i;
+                    for (int a = 0; a < 3; ++a) {
+                        double ua = uq[a];
+                        for (int b = 0; b < 3; ++b) blk[3 * a + b] -= ua * s_piv[b * kAcaMaxRank + q];
+                    }
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Rcol[(3 * (int64_t)i + a) * 3 + b] = blk[3 * a + b];
+            }
+            if (threadIdx.x < 9) s_P[threadIdx.x] = Rrow[(threadIdx.x / 3) * n3 + 3 * jpiv + threadIdx.x % 3];
+            __syncthreads();
+            // ---- eliminate the 3x3 pivot block with complete pivoting ----
+            double P[9];
+            for (int t = 0; t < 9; ++t) P[t] = s_P[t];
+            double pmax0 = 0.0;
+            for (int t = 0; t < 9; ++t) pmax0 = fmax(pmax0, fabs(P[t]));
+            bool rdone[3] = {false, false, false}, cdone[3] = {false, false, false};
+            for (int sub = 0; sub < 3 && k < D.kmax; ++sub) {
+                int r = -1, c = -1;
+                double pm = -1.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        if (!rdone[a] && !cdone[b] && fabs(P[3 * a + b]) > pm) {
+                            pm = fabs(P[3 * a + b]);
+                            r = a;
+                            c = b;
+                        }
+                if (r < 0 || !(pm > 1e-10 * pmax0)) break;
+                const double inv = 1.0 / P[3 * r + c];
+                double* Uk = U + (int64_t)k * m3;
+                double* Vk = V + (int64_t)k * n3;
+                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) Uk[x] = Rcol[x * 3 + c];
+                for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) Vk[y] = Rrow[r * n3 + y] * inv;
+                __syncthreads();
+                double vj[3], ui[3];
+                for (int t = 0; t < 3; ++t) {
+                    vj[t] = Vk[3 * jpiv + t];
+                    ui[t] = Uk[3 * ipiv + t];
+                }
+                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) {
+                    double u = Uk[x];
+                    for (int t = 0; t < 3; ++t) Rcol[x * 3 + t] -= u * vj[t];
+                }
+                for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) {
+                    double v = Vk[y];
+                    for (int t = 0; t < 3; ++t) Rrow[t * n3 + y] -= ui[t] * v;
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) P[3 * a + b] -= ui[a] * vj[b];
+                rdone[r] = true;
+                cdone[c] = true;
+                ++k;
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) {
+            rowused[ipiv] = 1;
+            if (jpiv >= 0) colused[jpiv] = 1;
+        }
+        __syncthreads();
+        if (k == k0) {
+            // nothing gained from this row: try the next unused row in order
+            if (++misses > 8) {
+                converged = (k > 0 && conv >= 1) || k == 0;
+                break;
+            }
+            double v = -1.0;
+            int nxt = -1;
+            for (int i = threadIdx.x; i < D.m; i += kAcaThreads)
+                if (!rowused[i] && nxt < 0) {
+                    v = (double)(D.m - i);  // smallest unused index wins
+                    nxt = i;
+                }
+            block_argmax(v, nxt, s_red, s_ired);
+            if (nxt < 0) {
+                converged = true;
+                break;
+            }
+            ipiv = nxt;
+            continue;
+        }
+        // ---- Frobenius norm of the approximation, updated incrementally ----
+        double step2 = 0.0;
+        for (int qn = k0; qn < k; ++qn) {
+            block_dots(U, U + (int64_t)qn * m3, m3, qn + 1, s_uu[qn - k0], s_red);
+            block_dots(V, V + (int64_t)qn * n3, n3, qn + 1, s_vv[qn - k0], s_red);
+        }
+        for (int qn = k0; qn < k; ++qn) {
+            double cross = 0.0;
+            for (int q = 0; q < qn; ++q) cross += s_uu[qn - k0][q] * s_vv[qn - k0][q];
+            normS2 += 2.0 * cross + s_uu[qn - k0][qn] * s_vv[qn - k0][qn];
+            for (int pn = k0; pn < k; ++pn) {
+                // (U_p . U_q)(V_p . V_q) for p, q in this step
+                int lo = pn < qn ? pn : qn, hi = pn < qn ? qn : pn;
+                step2 += s_uu[hi - k0][lo] * s_vv[hi - k0][lo];
+            }
+        }
+        __syncthreads();
+        conv = (step2 <= tol * tol * normS2) ? conv + 1 : 0;
+        if (conv >= 2) {
+            converged = true;
+            break;
+        }
+        // ---- next pivot row: largest new column block among unused rows ----
+        double v = -1.0;
+        int nxt = -1;
+        for (int i = threadIdx.x; i < D.m; i += kAcaThreads) {
+            if (rowused[i]) continue;
+            double s = 0.0;
+            for (int q = k0; q < k; ++q)
+                for (int a = 0; a < 3; ++a) {
+                    double u = U[(int64_t)q * m3 + 3 * i + a];
+                    s += u * u;
+                }
+            if (s > v) {
+                v = s;
+                nxt = i;
+            }
+        }
+        block_argmax(v, nxt, s_red, s_ired);
+        if (nxt < 0) {
+            converged = true;  // every row has been sampled: the block is reproduced
+            break;
+        }
+        ipiv = nxt;
+        misses = 0;
+    }
+    // a cross approximation of full rank interpolates every row: exact
+    if (k >= 3 * min(D.m, D.n)) converged = true;
+    if (threadIdx.x == 0) {
+        out_rank[blockIdx.x] = k;
+        out_status[blockIdx.x] = converged ? 0 : 1;
+    }
+}
+
+// ------------------------------------------------------------------
+// packing into the apply layout
+// ------------------------------------------------------------------
+struct PackDesc {
+    int64_t src_off;  // FP64 source
+    int64_t dst_off;  // panel start
+    int64_t ld;       // source leading dimension
+    int32_t rows, cols;
+    int32_t mode;     // 0: row-major src[row*ld + col]; 1: src[col*ld + row]
+    int32_t zero_self;  // dense diagonal block: zero element self blocks
+};
+
+template <class T>
+__global__ void k_pack(const PackDesc* __restrict__ descs, const double* __restrict__ src, T* __restrict__ dst, int w)
+{
+    const PackDesc D = descs[blockIdx.y];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)D.rows * D.cols) return;
+    int row = (int)(e / D.cols), col = (int)(e - (int64_t)row * D.cols);
+    double v = D.mode == 0 ? src[D.src_off + row * D.ld + col] : src[D.src_off + (int64_t)col * D.ld + row];
+    if (D.zero_self && row / 3 == col / 3) v = 0.0;
+    dst[D.dst_off + panel_offset(D.rows, D.cols, w, row, col)] = cvt<T>(v);
+}
+
+// FP64 self blocks of each element, written in original element order
+__global__ void k_extract_self(const DenseDesc* __restrict__ descs, const int* __restrict__ diag_ids, int n_diag,
+                               const double* __restrict__ dense, const int64_t* __restrict__ perm,
+                               double* __restrict__ self)
+{
+    int b = blockIdx.y;
+    if (b >= n_diag) return;
+    const DenseDesc D = descs[diag_ids[b]];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= D.m) return;
+    int64_t ld = 3 * (int64_t)D.n;
+    int64_t e = perm[D.t_begin + i];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) self[e * 9 + 3 * a + c] = dense[D.out_off + (3 * (int64_t)i + a) * ld + 3 * i + c];
+}
+
+// ------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------
+static double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void ensure_mesh_geo(Mesh& mesh)
+{
+    int dev = 0;
+    HM_CHECK_HIP(hipGetDevice(&dev));
+    if (mesh.d_geo.get() && mesh.d_geo_device == dev) return;
+    mesh.d_geo.alloc(mesh.geo.size() * sizeof(ElemGeo));
+    HM_CHECK_HIP(hipMemcpy(mesh.d_geo.get(), mesh.geo.data(), mesh.geo.size() * sizeof(ElemGeo), hipMemcpyHostToDevice));
+    mesh.d_geo_device = dev;
+}
+
+static void moduli(double young, double nu, double& G, double& kG, double& kN)
+{
+    HM_REQUIRE(young > 0.0 && std::isfinite(young), HM_EINVAL, "Young's modulus must be positive");
+    HM_REQUIRE(nu > -1.0 && nu < 0.5, HM_EINVAL, "Poisson ratio must lie in (-1, 1/2)");
+    G = young / (2.0 * (1.0 + nu));
+    kG = G / (4.0 * M_PI);
+    kN = G / (4.0 * M_PI * (1.0 - nu));
+}
+
+void kernel_block(Mesh& mesh, double young, double nu, int64_t nr, const int64_t* d_rows, int64_t nc,
+                  const int64_t* d_cols, double* d_out, hipStream_t s)
+{
+    double G, kG, kN;
+    moduli(young, nu, G, kG, kN);
+    HM_REQUIRE(nr >= 0 && nc >= 0, HM_EINVAL, "negative sizes");
+    if (nr == 0 || nc == 0) return;
+    HM_REQUIRE(d_rows && d_cols && d_out, HM_EINVAL, "null pointer");
+    ensure_mesh_geo(mesh);
+    int64_t total = nr * nc;
+    int64_t grid = (total + 255) / 256;
+    HM_REQUIRE(grid < (int64_t)1 << 31, HM_EINVAL, "block too large");
+    hipLaunchKernelGGL(k_kernel_block, dim3((unsigned)grid), dim3(256), 0, s, mesh.d_geo.as<ElemGeo>(), d_rows, d_cols,
+                       nr, nc, kG, kN, d_out);
+    HM_CHECK_HIP(hipGetLastError());
+}
+
+namespace {
+
+struct PackJob {
+    std::vector<PackDesc> descs;
+    int64_t max_entries = 0;
+    void add(const PackDesc& d)
+    {
+        descs.push_back(d);
+        max_entries = std::max<int64_t>(max_entries, (int64_t)d.rows * d.cols);
+    }
+};
+
+template <class T>
+void run_pack(const PackJob& job, const double* src, void* dst, int w, hipStream_t s)
+{
+    if (job.descs.empty()) return;
+    DevBuf d;
+    upload(d, job.descs, s);
+    const size_t chunk = 65535;
+    for (size_t b0 = 0; b0 < job.descs.size(); b0 += chunk) {
+        size_t nb = std::min(chunk, job.descs.size() - b0);
+        dim3 grid((unsigned)((job.max_entries + 255) / 256), (unsigned)nb);
+        hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, s, d.as<PackDesc>() + b0, src, static_cast<T*>(dst), w);
+        HM_CHECK_HIP(hipGetLastError());
+    }
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void pack_dispatch(int prec, const PackJob& job, const double* src, void* dst, hipStream_t s)
+{
+    int w = prec_w(prec);
+    if (prec == HM_F64) run_pack<double>(job, src, dst, w, s);
+    else if (prec == HM_F32) run_pack<float>(job, src, dst, w, s);
+    else run_pack<uint16_t>(job, src, dst, w, s);
+}
+
+}  // namespace
+
+// Pack one precision variant and build its task lists.
+static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, const double* d_dense,
+                         const double* d_fac, hipStream_t s)
+{
+    const Plan& p = op.plan;
+    const int wn = prec_w(v.near_prec), wf = prec_w(v.far_prec);
+    const int nleaf = (int)p.leaves.size();
+    // ---- dense panels ----
+    std::vector<int64_t> dense_off(dd.size());
+    int64_t near_elems = 0;
+    for (size_t b = 0; b < dd.size(); ++b) {
+        dense_off[b] = near_elems;
+        near_elems += panel_elems(3 * dd[b].m, 3 * dd[b].n, wn);
+    }
+    v.near_a.alloc(std::max<int64_t>(1, near_elems) * prec_bytes(v.near_prec));
+    HM_CHECK_HIP(hipMemsetAsync(v.near_a.get(), 0, v.near_a.bytes(), s));
+    {
+        PackJob job;
+        for (size_t b = 0; b < dd.size(); ++b) {
+            bool diag = p.dense[b].first == p.dense[b].second;
+            job.add(PackDesc{dd[b].out_off, dense_off[b], 3 * (int64_t)dd[b].n, 3 * dd[b].m, 3 * dd[b].n, 0,
+                             (diag && v.self_separate) ? 1 : 0});
+        }
+        pack_dispatch(v.near_prec, job, d_dense, v.near_a.get(), s);
+    }
+    v.bytes_near = near_elems * prec_bytes(v.near_prec);
+    // ---- low-rank panels: U slices per target leaf, V^T sub-panels per source leaf ----
+    struct Slice {
+        int64_t off;
+        int block;
+        int leaf;
+    };
+    std::vector<std::vector<Slice>> uslices(nleaf);       // by target leaf
+    std::vector<std::vector<Slice>> vslices(op.lr.size()); // by block
+    int64_t far_elems = 0;
+    PackJob job;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        const Cluster& t = p.nodes[L.t_node];
+        const Cluster& sc = p.nodes[L.s_node];
+        const int k = L.rank;
+        if (k == 0) continue;
+        for (int lf = t.first_leaf; lf < t.first_leaf + t.n_leaves; ++lf) {
+            const Cluster& c = p.nodes[p.leaves[lf]];
+            int rows = 3 * (int)c.size();
+            uslices[lf].push_back(Slice{far_elems, (int)b, lf});
+            job.add(PackDesc{L.u_off + 3 * (c.begin - t.begin), far_elems, 3 * L.m, rows, k, 1, 0});
+            far_elems += panel_elems(rows, k, wf);
+        }
+        for (int lf = sc.first_leaf; lf < sc.first_leaf + sc.n_leaves; ++lf) {
+            const Cluster& c = p.nodes[p.leaves[lf]];
+            int cols = 3 * (int)c.size();
+            vslices[b].push_back(Slice{far_elems, (int)b, lf});
+            job.add(PackDesc{L.v_off + 3 * (c.begin - sc.begin), far_elems, 3 * L.n, k, cols, 0, 0});
+            far_elems += panel_elems(k, cols, wf);
+        }
+    }
+    v.far_a.alloc(std::max<int64_t>(1, far_elems) * prec_bytes(v.far_prec));
+    HM_CHECK_HIP(hipMemsetAsync(v.far_a.get(), 0, v.far_a.bytes(), s));
+    pack_dispatch(v.far_prec, job, d_fac, v.far_a.get(), s);
+    v.bytes_far = far_elems * prec_bytes(v.far_prec);
+
+    // ---- T chunks and phase-A tasks ----
+    std::vector<int64_t> t_off(op.lr.size(), 0);
+    int64_t tfrag = 0, tpart = 0;
+    std::vector<TaskA> ta;
+    std::vector<PanelRef> ia;
+    std::vector<ReduceDesc> red;
+    const int kLeavesPerTaskA = 8;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        if (L.rank == 0) continue;
+        t_off[b] = tfrag;
+        tfrag += round_up(L.rank, kChunkAlign) * kNrhs;
+        const int64_t slot = round_up(L.rank, 16) * kNrhs;
+        ReduceDesc rd{tpart, t_off[b], 0, L.rank};
+        const auto& vs = vslices[b];
+        for (size_t q0 = 0; q0 < vs.size(); q0 += kLeavesPerTaskA) {
+            TaskA t{tpart, L.rank, (int32_t)ia.size(), 0, 0};
+            for (size_t q = q0; q < std::min(vs.size(), q0 + kLeavesPerTaskA); ++q) {
+                const Cluster& c = p.nodes[p.leaves[vs[q].leaf]];
+                ia.push_back(PanelRef{vs[q].off, op.leaf_xoff[vs[q].leaf] * kNrhs, L.rank, 3 * (int32_t)c.size(), 1, 0});
+                t.n_items++;
+            }
+            ta.push_back(t);
+            tpart += slot;
+            rd.n_slots++;
+        }
+        red.push_back(rd);
+    }
+    // ---- phase-B tasks: one per target leaf ----
+    std::vector<std::vector<int>> dense_by_leaf(nleaf);
+    for (size_t b = 0; b < p.dense.size(); ++b) dense_by_leaf[p.nodes[p.dense[b].first].leaf_id].push_back((int)b);
+    std::vector<TaskB> tb;
+    std::vector<PanelRef> ib;
+    for (int lf = 0; lf < nleaf; ++lf) {
+        const Cluster& c = p.nodes[p.leaves[lf]];
+        TaskB t{op.leaf_xoff[lf], 3 * (int32_t)c.size(), (int32_t)ib.size(), 0, 0};
+        for (int b : dense_by_leaf[lf]) {
+            const Cluster& sc = p.nodes[p.dense[b].second];
+            ib.push_back(PanelRef{dense_off[b], op.leaf_xoff[sc.leaf_id] * kNrhs, 3 * (int32_t)c.size(),
+                                  3 * (int32_t)sc.size(), 0, 0});
+        }
+        for (const Slice& sl : uslices[lf])
+            ib.push_back(PanelRef{sl.off, t_off[sl.block], 3 * (int32_t)c.size(), op.lr[sl.block].rank, 1, 0});
+        t.n_items = (int32_t)ib.size() - t.item_begin;
+        tb.push_back(t);
+    }
+    // longest tasks first so the tail of the launch is short
+    std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
+        return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
+    });
+    upload(v.tasksB, tb, s);
+    upload(v.itemsB, ib, s);
+    upload(v.tasksA, ta, s);
+    upload(v.itemsA, ia, s);
+    upload(v.reduce, red, s);
+    v.nTasksB = (int)tb.size();
+    v.nTasksA = (int)ta.size();
+    v.nReduce = (int)red.size();
+    v.tpart_elems = tpart;
+    v.tfrag_elems = tfrag;
+    // ---- workspaces ----
+    const int64_t xel = op.xtot * kNrhs;
+    v.xf_near.alloc(xel * prec_bytes(v.near_prec));
+    HM_CHECK_HIP(hipMemsetAsync(v.xf_near.get(), 0, v.xf_near.bytes(), s));
+    if (!v.far_is_near()) {
+        v.xf_far_hi.alloc(xel * prec_bytes(v.far_prec));
+        HM_CHECK_HIP(hipMemsetAsync(v.xf_far_hi.get(), 0, v.xf_far_hi.bytes(), s));
+        if (v.far_prec == HM_BF16) {
+            v.xf_far_lo.alloc(xel * prec_bytes(v.far_prec));
+            HM_CHECK_HIP(hipMemsetAsync(v.xf_far_lo.get(), 0, v.xf_far_lo.bytes(), s));
+        }
+    }
+    const int acc_bytes = v.acc_f64() ? 8 : 4;
+    v.tpart.alloc(std::max<int64_t>(1, tpart) * acc_bytes);
+    v.tf_hi.alloc(std::max<int64_t>(1, tfrag) * prec_bytes(v.far_prec));
+    HM_CHECK_HIP(hipMemsetAsync(v.tf_hi.get(), 0, v.tf_hi.bytes(), s));
+    if (v.far_prec == HM_BF16) {
+        v.tf_lo.alloc(std::max<int64_t>(1, tfrag) * prec_bytes(v.far_prec));
+        HM_CHECK_HIP(hipMemsetAsync(v.tf_lo.get(), 0, v.tf_lo.bytes(), s));
+    }
+    v.y.alloc(xel * acc_bytes);
+    HM_CHECK_HIP(hipMemsetAsync(v.y.get(), 0, v.y.bytes(), s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStream_t s)
+{
+    Mesh& mesh = const_cast<Mesh&>(mesh_in);
+    double t_start = now_ms();
+    double G, kG, kN;
+    moduli(op.young, op.nu, G, kG, kN);
+    op.G = G;
+    HM_REQUIRE(o.aca_tol > 0.0 && o.aca_tol < 1.0, HM_EINVAL, "aca_tol must be in (0, 1)");
+    HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
+    HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
+    HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16, HM_EUNSUPPORTED,
+               "far_prec must be F64, F32 or BF16");
+    HM_REQUIRE(!(o.near_prec == HM_F64 && o.far_prec != HM_F64), HM_EUNSUPPORTED,
+               "an FP64 near field requires an FP64 far field");
+    HM_REQUIRE(!(o.near_prec == HM_F32 && o.far_prec == HM_F64), HM_EUNSUPPORTED,
+               "an FP32 near field takes an FP32 or BF16 far field");
+    HM_CHECK_HIP(hipGetDevice(&op.device));
+    op.ne = mesh.ne;
+    op.plan = make_plan(mesh, o.leaf_size, o.eta);
+    const Plan& p = op.plan;
+    const int nleaf = (int)p.leaves.size();
+    op.leaf_xoff.resize(nleaf);
+    op.xtot = 0;
+    for (int lf = 0; lf < nleaf; ++lf) {
+        op.leaf_xoff[lf] = op.xtot;
+        op.xtot += round_up(3 * p.nodes[p.leaves[lf]].size(), kChunkAlign);
+    }
+    // element tables
+    std::vector<ElemGeo> geo(mesh.ne);
+    for (int64_t q = 0; q < mesh.ne; ++q) geo[q] = mesh.geo[p.perm[q]];
+    DevBuf d_geo, d_perm;
+    upload(d_geo, geo, s);
+    upload(d_perm, p.perm, s);
+    {
+        std::vector<int64_t> xslot(mesh.ne);
+        std::vector<int32_t> xloc(mesh.ne);
+        for (int lf = 0; lf < nleaf; ++lf) {
+            const Cluster& c = p.nodes[p.leaves[lf]];
+            for (int64_t q = c.begin; q < c.end; ++q) {
+                xslot[p.perm[q]] = op.leaf_xoff[lf];
+                xloc[p.perm[q]] = (int32_t)(3 * (q - c.begin));
+            }
+        }
+        upload(op.d_xslot, xslot, s);
+        upload(op.d_xloc, xloc, s);
+    }
+    // ---- dense leaves: FP64 coefficients ----
+    double t0 = now_ms();
+    std::vector<DenseDesc> dd(p.dense.size());
+    int64_t dense_total = 0, max_pairs = 0;
+    std::vector<int> diag_ids;
+    for (size_t b = 0; b < p.dense.size(); ++b) {
+        const Cluster& t = p.nodes[p.dense[b].first];
+        const Cluster& sc = p.nodes[p.dense[b].second];
+        dd[b] = DenseDesc{t.begin, sc.begin, dense_total, (int32_t)t.size(), (int32_t)sc.size()};
+        dense_total += 9 * t.size() * sc.size();
+        max_pairs = std::max<int64_t>(max_pairs, t.size() * sc.size());
+        if (p.dense[b].first == p.dense[b].second) diag_ids.push_back((int)b);
+    }
+    DevBuf d_dense(std::max<int64_t>(1, dense_total) * sizeof(double));
+    DevBuf d_dd;
+    upload(d_dd, dd, s);
+    for (size_t b0 = 0; b0 < dd.size(); b0 += 65535) {
+        unsigned nb = (unsigned)std::min<size_t>(65535, dd.size() - b0);
+        hipLaunchKernelGGL(k_dense_coef, dim3((unsigned)((max_pairs + 255) / 256), nb), dim3(256), 0, s,
+                           d_geo.as<ElemGeo>(), d_dd.as<DenseDesc>() + b0, kG, kN, d_dense.as<double>());
+        HM_CHECK_HIP(hipGetLastError());
+    }
+    op.d_self.alloc(9 * mesh.ne * sizeof(double));
+    HM_CHECK_HIP(hipMemsetAsync(op.d_self.get(), 0, op.d_self.bytes(), s));
+    if (!diag_ids.empty()) {
+        DevBuf d_diag;
+        upload(d_diag, diag_ids, s);
+        for (size_t b0 = 0; b0 < diag_ids.size(); b0 += 65535) {
+            unsigned nb = (unsigned)std::min<size_t>(65535, diag_ids.size() - b0);
+            hipLaunchKernelGGL(k_extract_self, dim3((unsigned)((p.leaf_size + 255) / 256), nb), dim3(256), 0, s,
+                               d_dd.as<DenseDesc>(), d_diag.as<int>() + b0, (int)nb, d_dense.as<double>(),
+                               d_perm.as<int64_t>(), op.d_self.as<double>());
+            HM_CHECK_HIP(hipGetLastError());
+        }
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    double t1 = now_ms();
+    // ---- low-rank blocks: ACA in batches bounded by a workspace budget ----
+    op.lr.resize(p.lowrank.size());
+    std::vector<AcaDesc> ad(p.lowrank.size());
+    for (size_t b = 0; b < p.lowrank.size(); ++b) {
+        const Cluster& t = p.nodes[p.lowrank[b].first];
+        const Cluster& sc = p.nodes[p.lowrank[b].second];
+        LowRank& L = op.lr[b];
+        L.t_node = p.lowrank[b].first;
+        L.s_node = p.lowrank[b].second;
+        L.m = t.size();
+        L.n = sc.size();
+        // first pivot: element nearest to the target cluster's mean collocation point
+        double cm[3] = {0, 0, 0};
+        for (int64_t q = t.begin; q < t.end; ++q)
+            for (int k = 0; k < 3; ++k) cm[k] += mesh.cent[3 * p.perm[q] + k];
+        for (int k = 0; k < 3; ++k) cm[k] /= (double)t.size();
+        int first = 0;
+        double bd = 1e300;
+        for (int64_t q = t.begin; q < t.end; ++q) {
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double dx = mesh.cent[3 * p.perm[q] + k] - cm[k];
+                d2 += dx * dx;
+            }
+            if (d2 < bd) {
+                bd = d2;
+                first = (int)(q - t.begin);
+            }
+        }
+        int kmax = (int)std::min<int64_t>(o.max_rank, 3 * std::min(L.m, L.n));
+        ad[b] = AcaDesc{t.begin, sc.begin, 0, 0, 0, 0, 0, (int32_t)L.m, (int32_t)L.n, first, kmax};
+    }
+    // order blocks by size inside each batch (large first) for load balance
+    std::vector<int> order(ad.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return ad[a].m + ad[a].n > ad[b].m + ad[b].n;
+    });
+    const int64_t budget = (int64_t)6 << 30;  // bytes of ACA workspace per batch
+    std::vector<std::vector<int>> batches;
+    {
+        int64_t used = 0;
+        std::vector<int> cur;
+        for (int b : order) {
+            int64_t need = 8 * ((int64_t)ad[b].kmax * 3 * (ad[b].m + ad[b].n) + 9 * (int64_t)(ad[b].m + ad[b].n)) +
+                           ad[b].m + ad[b].n + 64;
+            if (!cur.empty() && used + need > budget) {
+                batches.push_back(cur);
+                cur.clear();
+                used = 0;
+            }
+            cur.push_back(b);
+            used += need;
+        }
+        if (!cur.empty()) batches.push_back(cur);
+    }
+    // factors of every block, FP64, compact: first pass computes ranks per batch and copies
+    std::vector<DevBuf> batch_fac;
+    int64_t fac_total = 0;
+    std::vector<std::pair<int, int64_t>> fac_where(op.lr.size(), {-1, 0});  // batch, offset
+    int64_t rank_sum = 0;
+    int rmin = 1 << 30, rmax = 0;
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const auto& bl = batches[bi];
+        std::vector<AcaDesc> bd(bl.size());
+        int64_t off = 0, foff = 0;
+        for (size_t q = 0; q < bl.size(); ++q) {
+            AcaDesc d = ad[bl[q]];
+            d.u_off = off;
+            off += (int64_t)d.kmax * 3 * d.m;
+            d.v_off = off;
+            off += (int64_t)d.kmax * 3 * d.n;
+            d.rrow_off = off;
+            off += 9 * (int64_t)d.n;
+            d.rcol_off = off;
+            off += 9 * (int64_t)d.m;
+            d.flag_off = foff;
+            foff += d.m + d.n;
+            bd[q] = d;
+        }
+        DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff)), d_bd, d_rank(bl.size() * sizeof(int)),
+            d_stat(bl.size() * sizeof(int));
+        upload(d_bd, bd, s);
+        hipLaunchKernelGGL(k_aca, dim3((unsigned)bl.size()), dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(),
+                           d_bd.as<AcaDesc>(), kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(),
+                           d_rank.as<int>(), d_stat.as<int>());
+        HM_CHECK_HIP(hipGetLastError());
+        std::vector<int> rk(bl.size()), st(bl.size());
+        HM_CHECK_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipMemcpyAsync(st.data(), d_stat.get(), st.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        // compact copy of this batch's factors
+        int64_t csz = 0;
+        for (size_t q = 0; q < bl.size(); ++q) {
+            LowRank& L = op.lr[bl[q]];
+            HM_REQUIRE(st[q] == 0, HM_EINTERNAL,
+                       "ACA did not converge within max_rank for block " + std::to_string(bl[q]) + " (" +
+                           std::to_string(L.m) + " x " + std::to_string(L.n) + " elements)");
+            L.rank = rk[q];
+            csz += (int64_t)rk[q] * 3 * (L.m + L.n);
+        }
+        batch_fac.emplace_back(std::max<int64_t>(1, csz) * sizeof(double));
+        int64_t c = 0;
+        for (size_t q = 0; q < bl.size(); ++q) {
+            LowRank& L = op.lr[bl[q]];
+            const AcaDesc& d = bd[q];
+            fac_where[bl[q]] = {(int)bi, c};
+            L.u_off = c;
+            if (L.rank) {
+                HM_CHECK_HIP(hipMemcpyAsync(batch_fac.back().as<double>() + c, ws.as<double>() + d.u_off,
+                                            (size_t)L.rank * 3 * L.m * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            c += (int64_t)L.rank * 3 * L.m;
+            L.v_off = c;
+            if (L.rank) {
+                HM_CHECK_HIP(hipMemcpyAsync(batch_fac.back().as<double>() + c, ws.as<double>() + d.v_off,
+                                            (size_t)L.rank * 3 * L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            c += (int64_t)L.rank * 3 * L.n;
+            rank_sum += L.rank;
+            rmin = std::min(rmin, L.rank);
+            rmax = std::max(rmax, L.rank);
+        }
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        fac_total += csz;
+    }
+    // merge batch stores into one FP64 factor buffer (offsets rebased)
+    DevBuf d_fac(std::max<int64_t>(1, fac_total) * sizeof(double));
+    {
+        int64_t base = 0;
+        std::vector<int64_t> bbase(batch_fac.size());
+        for (size_t bi = 0; bi < batch_fac.size(); ++bi) {
+            bbase[bi] = base;
+            int64_t n = batch_fac[bi].bytes() / sizeof(double);
+            HM_CHECK_HIP(hipMemcpyAsync(d_fac.as<double>() + base, batch_fac[bi].get(), n * sizeof(double),
+                                        hipMemcpyDeviceToDevice, s));
+            base += n;
+        }
+        for (size_t b = 0; b < op.lr.size(); ++b) {
+            op.lr[b].u_off += bbase[fac_where[b].first];
+            op.lr[b].v_off += bbase[fac_where[b].first];
+        }
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        batch_fac.clear();
+    }
+    double t2 = now_ms();
+    // ---- pack variants ----
+    op.main.near_prec = o.near_prec;
+    op.main.far_prec = o.far_prec;
+    op.main.self_separate = o.near_prec != HM_F64;
+    make_variant(op, op.main, dd, d_dense.as<double>(), d_fac.as<double>(), s);
+    if (o.keep_f64_reference && o.near_prec != HM_F64) {
+        op.ref.reset(new Variant());
+        op.ref->near_prec = HM_F64;
+        op.ref->far_prec = HM_F64;
+        op.ref->self_separate = false;
+        make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);
+    }
+    double t3 = now_ms();
+    // ---- statistics ----
+    hm_op_stats& st = op.stats;
+    std::memset(&st, 0, sizeof(st));
+    st.n_elements = mesh.ne;
+    st.n_dof = 3 * mesh.ne;
+    st.n_leaves = nleaf;
+    st.n_dense_blocks = (int64_t)p.dense.size();
+    st.n_lowrank_blocks = (int64_t)p.lowrank.size();
+    st.dense_entries = dense_total;
+    int64_t lre = 0;
+    for (const LowRank& L : op.lr) lre += (int64_t)L.rank * 3 * (L.m + L.n);
+    st.lowrank_entries = lre;
+    st.self_f64_entries = op.main.self_separate ? 9 * mesh.ne : 0;
+    st.bytes_near = op.main.bytes_near;
+    st.bytes_far = op.main.bytes_far;
+    st.bytes_self = st.self_f64_entries * 8;
+    st.bytes_reference = op.ref ? op.ref->bytes_near + op.ref->bytes_far : 0;
+    st.min_rank = op.lr.empty() ? 0 : rmin;
+    st.max_rank = op.lr.empty() ? 0 : rmax;
+    st.mean_rank = op.lr.empty() ? 0.0 : (double)rank_sum / (double)op.lr.size();
+    st.near_prec = o.near_prec;
+    st.far_prec = o.far_prec;
+    st.coef_ms = t1 - t0;
+    st.aca_ms = t2 - t1;
+    st.pack_ms = t3 - t2;
+    st.build_ms = t3 - t_start;
+    int64_t maxleaf = 0;
+    {
+        std::vector<int64_t> per(nleaf, 0);
+        for (size_t b = 0; b < p.dense.size(); ++b)
+            per[p.nodes[p.dense[b].first].leaf_id] += 9 * (int64_t)dd[b].m * dd[b].n * prec_bytes(o.near_prec);
+        for (int64_t x : per) maxleaf = std::max(maxleaf, x);
+    }
+    st.max_dense_bytes_per_leaf = maxleaf;
+}
+
+}  // namespace hm

@@ -1,0 +1,227 @@
+// extern "C" boundary of the hmdd library: argument checks, error codes,
+// thread-local messages.  No C++ exception crosses these functions.
+#include <cstdio>
+#include <new>
+
+#include "hm_op.hpp"
+
+struct hm_mesh {
+    hm::Mesh m;
+};
+struct hm_op {
+    hm::Op op;
+};
+
+namespace hm {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace hm
+
+template <class F>
+static hm_status guarded(F&& f)
+{
+    try {
+        hm::set_last_error("");
+        f();
+        return HM_OK;
+    } catch (const hm::Error& e) {
+        hm::set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        hm::set_last_error("host allocation failed");
+        return HM_ENOMEM;
+    } catch (const std::exception& e) {
+        hm::set_last_error(e.what());
+        return HM_EINTERNAL;
+    } catch (...) {
+        hm::set_last_error("unknown internal error");
+        return HM_EINTERNAL;
+    }
+}
+
+static void require_gfx950()
+{
+    int dev = 0;
+    HM_CHECK_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HM_CHECK_HIP(hipGetDeviceProperties(&prop, dev));
+    HM_REQUIRE(std::string(prop.gcnArchName).find("gfx950") != std::string::npos, HM_EDEVICE,
+               std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950 only");
+}
+
+extern "C" {
+
+const char* hm_last_error(void) { return hm::g_last_error.c_str(); }
+
+const char* hm_version(void) { return "hmdd 0.1 (gfx950)"; }
+
+hm_status hm_mesh_create(int nv_per_elem, int64_t n_vert, const double* xyz, int64_t n_elem, const int64_t* conn,
+                         hm_mesh** out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = nullptr;
+        HM_REQUIRE(xyz && conn, HM_EINVAL, "xyz or conn is null");
+        HM_REQUIRE(n_vert > 0 && n_elem > 0, HM_EINVAL, "empty mesh");
+        HM_REQUIRE(nv_per_elem == 3 || nv_per_elem == 4, HM_EINVAL, "nv_per_elem must be 3 or 4");
+        std::unique_ptr<hm_mesh> h(new hm_mesh());
+        h->m.nvpe = nv_per_elem;
+        h->m.nv = n_vert;
+        h->m.ne = n_elem;
+        h->m.xyz.assign(xyz, xyz + 3 * n_vert);
+        h->m.conn.assign(conn, conn + nv_per_elem * n_elem);
+        hm::mesh_validate_and_frame(h->m);
+        *out = h.release();
+    });
+}
+
+void hm_mesh_destroy(hm_mesh* mesh) { delete mesh; }
+
+int64_t hm_mesh_num_elements(const hm_mesh* mesh) { return mesh ? mesh->m.ne : 0; }
+
+hm_status hm_mesh_frames(const hm_mesh* mesh, double* centroid, double* frame, double* area)
+{
+    return guarded([&] {
+        HM_REQUIRE(mesh, HM_EINVAL, "mesh is null");
+        const hm::Mesh& m = mesh->m;
+        if (centroid) std::memcpy(centroid, m.cent.data(), sizeof(double) * 3 * m.ne);
+        if (frame) std::memcpy(frame, m.frame.data(), sizeof(double) * 9 * m.ne);
+        if (area) std::memcpy(area, m.area.data(), sizeof(double) * m.ne);
+    });
+}
+
+hm_status hm_plan_summary(const hm_mesh* mesh, int leaf_size, double eta, hm_plan_info* info, int64_t* perm)
+{
+    return guarded([&] {
+        HM_REQUIRE(mesh && info, HM_EINVAL, "null argument");
+        hm::Plan p = hm::make_plan(mesh->m, leaf_size, eta);
+        std::memset(info, 0, sizeof(*info));
+        info->n_leaves = (int64_t)p.leaves.size();
+        info->n_dense_blocks = (int64_t)p.dense.size();
+        info->n_lowrank_blocks = (int64_t)p.lowrank.size();
+        info->depth = p.depth;
+        for (const auto& d : p.dense)
+            info->dense_entries += 9 * p.nodes[d.first].size() * p.nodes[d.second].size();
+        for (const auto& l : p.lowrank) {
+            int lev = p.nodes[l.first].level;
+            if (lev < 64) info->lowrank_by_level[lev]++;
+            info->lowrank_sum_mn += p.nodes[l.first].size() + p.nodes[l.second].size();
+        }
+        int64_t mx = 0, mn = INT64_MAX;
+        for (int id : p.leaves) {
+            mx = std::max(mx, p.nodes[id].size());
+            mn = std::min(mn, p.nodes[id].size());
+        }
+        info->max_leaf = mx;
+        info->min_leaf = mn;
+        if (perm) std::memcpy(perm, p.perm.data(), sizeof(int64_t) * p.perm.size());
+    });
+}
+
+hm_status hm_kernel_block(const hm_mesh* mesh, double young, double nu, int64_t nr, const int64_t* d_rows, int64_t nc,
+                          const int64_t* d_cols, double* d_out, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(mesh, HM_EINVAL, "mesh is null");
+        require_gfx950();
+        hm::kernel_block(const_cast<hm::Mesh&>(mesh->m), young, nu, nr, d_rows, nc, d_cols, d_out,
+                         (hipStream_t)hip_stream);
+    });
+}
+
+void hm_build_opts_default(hm_build_opts* o)
+{
+    if (!o) return;
+    o->leaf_size = 64;
+    o->eta = 2.0;
+    o->aca_tol = 1e-6;
+    o->max_rank = 192;
+    o->near_prec = HM_F64;
+    o->far_prec = HM_F64;
+    o->keep_f64_reference = 0;
+    o->recompress = 0;
+}
+
+hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const hm_build_opts* opts, void* hip_stream,
+                            hm_op** out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = nullptr;
+        HM_REQUIRE(mesh, HM_EINVAL, "mesh is null");
+        hm_build_opts o;
+        hm_build_opts_default(&o);
+        if (opts) o = *opts;
+        HM_REQUIRE(!o.recompress, HM_EUNSUPPORTED, "recompression is not provided");
+        require_gfx950();
+        std::unique_ptr<hm_op> h(new hm_op());
+        h->op.young = young;
+        h->op.nu = nu;
+        hipStream_t s = (hipStream_t)hip_stream;
+        hm::build_operator(h->op, mesh->m, o, s);
+        hm::tangent_set(h->op, nullptr, nullptr, s);
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        *out = h.release();
+    });
+}
+
+void hm_op_destroy(hm_op* op) { delete op; }
+
+hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out)
+{
+    return guarded([&] {
+        HM_REQUIRE(op && out, HM_EINVAL, "null argument");
+        *out = op->op.stats;
+    });
+}
+
+hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
+                            unsigned flags, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(op, HM_EINVAL, "op is null");
+        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT)) == 0, HM_EINVAL, "unknown flag");
+        const hm::Op& o = op->op;
+        HM_REQUIRE(!(flags & HM_APPLY_REFERENCE) || o.ref || o.main.near_prec == HM_F64, HM_EINVAL,
+                   "no FP64 reference copy (build with keep_f64_reference)");
+        const hm::Variant& v = (flags & HM_APPLY_REFERENCE) ? o.ref_variant() : o.main;
+        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, (hipStream_t)hip_stream);
+    });
+}
+
+hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(op, HM_EINVAL, "op is null");
+        hm::tangent_set(op->op, d_D, d_mask, (hipStream_t)hip_stream);
+    });
+}
+
+void hm_solve_opts_default(hm_solve_opts* o)
+{
+    if (!o) return;
+    o->restart = 50;
+    o->max_iter = 1000;
+    o->rtol = 1e-8;
+    o->precond = HM_PC_BLOCK3;
+    o->refine = 0;
+    o->inner_rtol = 1e-4;
+    o->max_refine = 20;
+}
+
+hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const double* d_B, int64_t ldb, double* d_X,
+                   int64_t ldx, hm_solve_report* rep, void* hip_stream)
+{
+    hm_status st = HM_OK;
+    hm_status g = guarded([&] {
+        HM_REQUIRE(op, HM_EINVAL, "op is null");
+        hm_solve_opts o;
+        hm_solve_opts_default(&o);
+        if (opts) o = *opts;
+        st = hm::solve(const_cast<hm::Op&>(op->op), o, nrhs, d_B, ldb, d_X, ldx, rep, (hipStream_t)hip_stream);
+        if (st == HM_ENOTCONV) hm::set_last_error("GMRES did not reach rtol (best iterate returned)");
+    });
+    return g != HM_OK ? g : st;
+}
+
+}  // extern "C"

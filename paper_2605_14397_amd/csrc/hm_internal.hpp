@@ -1,0 +1,212 @@
+// Internal structures of the hmdd library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hmdd.h"
+#include "hm_coef.hpp"
+
+namespace hm {
+
+// ------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------
+struct Error : std::runtime_error {
+    hm_status code;
+    Error(hm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define HM_CHECK_HIP(expr)                                                                             \
+    do {                                                                                               \
+        hipError_t _e = (expr);                                                                        \
+        if (_e != hipSuccess)                                                                          \
+            throw ::hm::Error(_e == hipErrorOutOfMemory ? HM_ENOMEM : HM_EDEVICE,                       \
+                              std::string(#expr) + ": " + hipGetErrorString(_e));                      \
+    } while (0)
+
+#define HM_REQUIRE(cond, code, msg)                                                                    \
+    do {                                                                                               \
+        if (!(cond)) throw ::hm::Error(code, msg);                                                     \
+    } while (0)
+
+// ------------------------------------------------------------------
+// device memory owned by a handle
+// ------------------------------------------------------------------
+class DevBuf {
+  public:
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes) { alloc(bytes); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p_ = o.p_;
+            n_ = o.n_;
+            o.p_ = nullptr;
+            o.n_ = 0;
+        }
+        return *this;
+    }
+    void alloc(size_t bytes)
+    {
+        release();
+        if (bytes == 0) return;
+        HM_CHECK_HIP(hipMalloc(&p_, bytes));
+        n_ = bytes;
+    }
+    void release()
+    {
+        if (p_) (void)hipFree(p_);
+        p_ = nullptr;
+        n_ = 0;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p_); }
+    void* get() const { return p_; }
+    size_t bytes() const { return n_; }
+
+  private:
+    void* p_ = nullptr;
+    size_t n_ = 0;
+};
+
+template <class T>
+inline void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s)
+{
+    b.alloc(v.size() * sizeof(T));
+    if (!v.empty()) HM_CHECK_HIP(hipMemcpyAsync(b.get(), v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------
+// mesh (host)
+// ------------------------------------------------------------------
+struct Mesh {
+    int nvpe = 0;
+    int64_t ne = 0, nv = 0;
+    std::vector<double> xyz;
+    std::vector<int64_t> conn;
+    std::vector<double> cent, frame, area;   // per element: [3], [9], [1]
+    std::vector<ElemGeo> geo;                // per element, original order
+    DevBuf d_geo;                            // uploaded on first device use
+    int d_geo_device = -1;
+};
+
+void mesh_validate_and_frame(Mesh& m);
+
+// ------------------------------------------------------------------
+// cluster tree and block tree (host)
+// ------------------------------------------------------------------
+struct Cluster {
+    int64_t begin = 0, end = 0;   // positions in cluster order
+    double bmin[3], bmax[3];      // bounding box of element vertices
+    int child[2] = {-1, -1};
+    int level = 0;
+    int leaf_id = -1;             // index among leaves (leaves only)
+    int first_leaf = 0, n_leaves = 0;  // leaves under this node (contiguous)
+    bool is_leaf() const { return child[0] < 0; }
+    int64_t size() const { return end - begin; }
+};
+
+struct Plan {
+    int leaf_size = 64;
+    double eta = 2.0;
+    std::vector<int64_t> perm;        // cluster position -> element id
+    std::vector<int64_t> iperm;       // element id -> cluster position
+    std::vector<Cluster> nodes;       // nodes[0] = root
+    std::vector<int> leaves;          // node id of each leaf, in position order
+    std::vector<std::pair<int, int>> dense;    // (target leaf node, source leaf node)
+    std::vector<std::pair<int, int>> lowrank;  // (target node, source node)
+    int depth = 0;
+};
+
+Plan make_plan(const Mesh& m, int leaf_size, double eta);
+
+// ------------------------------------------------------------------
+// panel layout shared by pack and apply kernels
+// ------------------------------------------------------------------
+// A panel is a row-major M x K matrix stored in "MFMA fragment" order so
+// that one wavefront streams it with 16-byte per-lane loads.  A granule is
+// 16 bytes (w = 2 doubles, 4 floats or 8 bf16); a k-step covers 4 granules
+// (Kstep = 4 w columns).  Rows are grouped in tiles of 16.  For row tile rt
+// (rr = min(16, M - 16 rt) rows) and k-step ks (gg = min(4, Gr - 4 ks)
+// granules, Gr = ceil(K / w)), the chunk holds rr * gg granules in [g][i]
+// order; lane (g, i) of a wavefront owns granule g of row i.  Padding is
+// only to the granule: the panel occupies M * Gr * w elements.
+__host__ __device__ inline int64_t panel_granules(int K, int w) { return (K + w - 1) / w; }
+__host__ __device__ inline int64_t panel_elems(int M, int K, int w) { return (int64_t)M * panel_granules(K, w) * w; }
+
+__host__ __device__ inline int64_t panel_offset(int M, int K, int w, int row, int col)
+{
+    int64_t Gr = panel_granules(K, w);
+    int rt = row >> 4, i = row & 15;
+    int rr = M - 16 * rt < 16 ? M - 16 * rt : 16;
+    int kstep = 4 * w;
+    int ks = col / kstep;
+    int g = (col % kstep) / w;
+    int t = col % w;
+    return (int64_t)rt * 16 * Gr * w + (int64_t)ks * rr * 4 * w + (int64_t)(g * rr + i) * w + t;
+}
+
+// In-vector chunk ("B fragment") for 16 right-hand sides: dof q, rhs c.
+// Lane l = g*16 + c of k-step ks reads 16 bytes at element (ks*64 + l) * w.
+__host__ __device__ inline int64_t bfrag_offset(int w, int q, int c)
+{
+    int kstep = 4 * w;
+    int ks = q / kstep;
+    int g = (q % kstep) / w;
+    int t = q % w;
+    return ((int64_t)(ks * 4 + g) * 16 + c) * w + t;
+}
+
+constexpr int kChunkAlign = 32;   // dofs; multiple of every k-step
+constexpr int kNrhs = 16;         // right-hand sides per fragment
+constexpr int kRowTilesMax = 12;  // 192 rows: leaf <= 64 elements, rank <= 192
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+inline int prec_w(int prec) { return prec == HM_F64 ? 2 : (prec == HM_F32 ? 4 : 8); }
+inline int prec_bytes(int prec) { return prec == HM_F64 ? 8 : (prec == HM_F32 ? 4 : 2); }
+
+// descriptors consumed by the apply kernels
+struct PanelRef {
+    int64_t a_off;    // panel start (elements of its precision)
+    int64_t b_off;    // in-vector chunk start (elements of the in-vector buffer)
+    int32_t rows, cols;
+    int32_t far;      // 0: near-field buffer / X, 1: far-field buffer / T
+    int32_t pad;
+};
+
+struct TaskB {        // one target leaf
+    int64_t y_off;    // output rows start in Y (padded leaf offset)
+    int32_t rows;     // 3 m
+    int32_t item_begin, n_items;
+    int32_t pad;
+};
+
+struct TaskA {        // part of one low-rank block: T partial = sum V^T X
+    int64_t out_off;  // partial slot start (elements, [rows_pad][16])
+    int32_t rows;     // rank k
+    int32_t item_begin, n_items;
+    int32_t pad;
+};
+
+struct ReduceDesc {   // T_b = sum of partial slots
+    int64_t slot_begin;   // first partial slot (elements)
+    int64_t t_off;        // T fragment chunk start (elements)
+    int32_t n_slots, rank;
+};
+
+}  // namespace hm

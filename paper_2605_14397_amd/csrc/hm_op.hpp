@@ -1,0 +1,73 @@
+// Operator handle: plan, packed H-matrix data per precision variant, and
+// the workspaces of apply and solve.
+#pragma once
+
+#include "hm_internal.hpp"
+
+namespace hm {
+
+// One packed copy of the H-matrix in a given (near, far) precision pair.
+// Accumulation is FP64 when near is FP64, FP32 otherwise.
+struct Variant {
+    int near_prec = HM_F64, far_prec = HM_F64;
+    bool self_separate = false;   // element self blocks applied from the FP64 store
+    DevBuf near_a, far_a;         // panels
+    DevBuf tasksB, itemsB, tasksA, itemsA, reduce;
+    int nTasksB = 0, nTasksA = 0, nReduce = 0;
+    int64_t tpart_elems = 0, tfrag_elems = 0;
+    int64_t bytes_near = 0, bytes_far = 0;
+    // workspaces (sized for 16 right-hand sides)
+    DevBuf xf_near;               // X chunks in near precision
+    DevBuf xf_far_hi, xf_far_lo;  // X chunks in far precision when it differs (bf16 split)
+    DevBuf tpart, tf_hi, tf_lo, y;
+    bool acc_f64() const { return near_prec == HM_F64; }
+    bool far_is_near() const { return far_prec == near_prec; }
+};
+
+struct LowRank {
+    int t_node = 0, s_node = 0;
+    int64_t m = 0, n = 0;       // elements
+    int rank = 0;
+    int64_t u_off = 0, v_off = 0;  // compact FP64 factors: U [rank][3m], V [rank][3n]
+};
+
+struct Op {
+    int device = 0;
+    double young = 0, nu = 0, G = 0;
+    int64_t ne = 0;
+    Plan plan;
+    std::vector<int64_t> leaf_xoff;   // padded dof offset of each leaf chunk
+    int64_t xtot = 0;                 // total padded dofs
+    std::vector<LowRank> lr;
+    // element tables in original order
+    DevBuf d_xslot;                   // int64 [N]: chunk dof offset (leaf_xoff) of the element's leaf
+    DevBuf d_xloc;                    // int32 [N]: local dof of component 0 within its leaf chunk
+    DevBuf d_self;                    // double [N][9]: FP64 self blocks (original order)
+    Variant main;
+    std::unique_ptr<Variant> ref;     // FP64 copy when main is not FP64
+    // tangent
+    bool has_D = false, has_mask = false;
+    DevBuf d_D, d_mask, d_pc_block, d_pc_diag;
+    // solver workspaces (allocated on first solve)
+    DevBuf solve_ws;
+    size_t solve_ws_bytes = 0;
+    hm_op_stats stats{};
+    const Variant& ref_variant() const { return ref ? *ref : main; }
+};
+
+// build helpers (hm_build.hip)
+void build_operator(Op& op, const Mesh& mesh, const hm_build_opts& o, hipStream_t s);
+void kernel_block(Mesh& mesh, double young, double nu, int64_t nr, const int64_t* d_rows, int64_t nc,
+                  const int64_t* d_cols, double* d_out, hipStream_t s);
+void ensure_mesh_geo(Mesh& mesh);
+
+// apply (hm_apply.hip)
+void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
+           bool tangent, hipStream_t s);
+void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
+
+// solve (hm_solve.hip)
+hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
+                int64_t ldx, hm_solve_report* rep, hipStream_t s);
+
+}  // namespace hm

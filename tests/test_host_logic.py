@@ -1,0 +1,182 @@
+"""Host-side logic of the library and its C boundary (no GPU needed).
+
+* the shared library loads and exports every function include/hmdd.h declares;
+* mesh validation errors and the element-frame convention;
+* the cluster/block tree against an independent Python construction of the
+  same rules (median bisection, vertex-box admissibility), and the
+  partition property: every (receiver, source) element pair is covered by
+  exactly one block.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_14397_amd as hm
+from workloads import disk_mesh, rect_grid, square_fault
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "hmdd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hm.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(hm.EXPORTS) == declared
+    assert L.hm_version().decode().startswith("hmdd")
+
+
+def test_mesh_validation_errors():
+    tri = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], float)
+    with pytest.raises(hm.HMError) as e:
+        hm.Mesh(tri, np.array([[0, 1, 2]]))
+    assert e.value.status == hm.HM_EBADMESH
+    quad = np.array([[0, 0, 0], [1, 0, 0], [1.2, 1, 0], [0, 1, 0]], float)
+    with pytest.raises(hm.HMError) as e:
+        hm.Mesh(quad, np.array([[0, 1, 2, 3]]))
+    assert e.value.status == hm.HM_EBADMESH
+    warped = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0.01], [0, 1, 0]], float)
+    with pytest.raises(hm.HMError) as e:
+        hm.Mesh(warped, np.array([[0, 1, 2, 3]]))
+    assert e.value.status == hm.HM_EBADMESH
+    with pytest.raises(hm.HMError) as e:
+        hm.Mesh(tri, np.array([[0, 1, 5]]))
+    assert e.value.status == hm.HM_EINVAL
+    with pytest.raises(hm.HMError) as e:
+        hm.Mesh(tri, np.zeros((1, 2), dtype=np.int64))
+    assert e.value.status == hm.HM_EINVAL
+
+
+def test_error_message_is_thread_local_and_cleared():
+    with pytest.raises(hm.HMError):
+        hm.Mesh(np.zeros((3, 3)), np.array([[0, 1, 2]]))
+    assert "degenerate" in hm.lib().hm_last_error().decode()
+    hm.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float), np.array([[0, 1, 2]]))
+    assert hm.lib().hm_last_error().decode() == ""
+
+
+@pytest.mark.parametrize("make", [lambda: square_fault(8), lambda: disk_mesh(5.0, 6),
+                                  lambda: rect_grid(5, 3, 0.7, 1.3, axes=np.array([[0, 0.6, 0.8], [1, 0, 0], [0, 0.8, -0.6]]))],
+                         ids=["square", "disk", "tilted_rect"])
+def test_frames_follow_the_stated_convention(make):
+    m = make()
+    c, f, a = hm.Mesh.from_workload(m).frames()
+    c2, f2, a2 = oracle.frames(m)
+    assert np.allclose(c, c2, atol=1e-14) and np.allclose(f, f2, atol=1e-14) and np.allclose(a, a2, rtol=1e-14)
+    assert np.allclose(np.einsum("nij,nkj->nik", f, f), np.eye(3), atol=1e-14)   # orthonormal rows
+    assert np.allclose(np.linalg.det(f), 1.0)                                     # right-handed
+
+
+# ---------------------------------------------------------------- planner
+def _py_plan(m, leaf, eta):
+    """Independent construction of the same cluster and block trees."""
+    cent = m.vertex_means()
+    v = m.xyz[m.conn]
+    vmin, vmax = v.min(axis=1), v.max(axis=1)
+    nodes = []
+
+    def build(idx):
+        nid = len(nodes)
+        nodes.append(None)
+        box = (vmin[idx].min(0), vmax[idx].max(0))
+        if len(idx) > leaf:
+            ext = cent[idx].max(0) - cent[idx].min(0)
+            ax = int(np.argmax(ext))
+            order = np.lexsort((idx, cent[idx, ax]))
+            idx = idx[order]
+            h = len(idx) // 2
+            a = build(idx[:h])
+            b = build(idx[h:])
+            nodes[nid] = (idx, box, (a, b))
+        else:
+            nodes[nid] = (np.sort(idx) if False else idx, box, None)
+        return nid
+
+    build(np.arange(m.ne))
+
+    def diam(b):
+        return np.linalg.norm(b[1] - b[0])
+
+    def dist(a, b):
+        g = np.maximum(0, np.maximum(a[0] - b[1], b[0] - a[1]))
+        return np.linalg.norm(g)
+
+    dense, lr = [], []
+
+    def blocks(t, s):
+        bt, bs = nodes[t][1], nodes[s][1]
+        d = dist(bt, bs)
+        if d > 0 and min(diam(bt), diam(bs)) <= eta * d:
+            lr.append((t, s))
+            return
+        ct, cs = nodes[t][2], nodes[s][2]
+        if ct is None and cs is None:
+            dense.append((t, s))
+        elif ct is None:
+            blocks(t, cs[0]); blocks(t, cs[1])
+        elif cs is None:
+            blocks(ct[0], s); blocks(ct[1], s)
+        else:
+            for i in ct:
+                for j in cs:
+                    blocks(i, j)
+
+    blocks(0, 0)
+    return nodes, dense, lr
+
+
+@pytest.mark.parametrize("make,leaf", [(lambda: square_fault(16), 8), (lambda: disk_mesh(10.0, 9), 16),
+                                       (lambda: rect_grid(23, 7, 1.0), 5)], ids=["square16", "disk", "ragged_rect"])
+def test_plan_matches_independent_construction(make, leaf):
+    m = make()
+    info, perm = hm.Mesh.from_workload(m).plan(leaf, 2.0, want_perm=True)
+    nodes, dense, lr = _py_plan(m, leaf, 2.0)
+    leaves = [n for n in nodes if n[2] is None]
+    assert info["n_leaves"] == len(leaves)
+    assert info["n_dense_blocks"] == len(dense)
+    assert info["n_lowrank_blocks"] == len(lr)
+    assert info["dense_entries"] == sum(9 * len(nodes[t][0]) * len(nodes[s][0]) for t, s in dense)
+    assert info["lowrank_sum_mn"] == sum(len(nodes[t][0]) + len(nodes[s][0]) for t, s in lr)
+    assert np.array_equal(np.sort(perm), np.arange(m.ne))
+    assert np.array_equal(perm, np.concatenate([n[0] for n in leaves]))
+    assert info["max_leaf"] <= leaf
+    # partition: every element pair lies in exactly one block
+    cover = np.zeros((m.ne, m.ne), dtype=np.int32)
+    for t, s in dense + lr:
+        cover[np.ix_(nodes[t][0], nodes[s][0])] += 1
+    assert np.all(cover == 1)
+
+
+def test_plan_counts_primary_configuration():
+    # 256 x 256 squares, leaf 64, eta 2: 1,024 leaves of 8 x 8 elements
+    info = hm.Mesh.from_workload(square_fault(256)).plan(64, 2.0)
+    assert info["n_leaves"] == 1024 and info["max_leaf"] == info["min_leaf"] == 64 and info["depth"] == 10
+    assert info["n_dense_blocks"] == 8836
+    assert info["dense_entries"] == 8836 * 192 * 192
+    assert info["n_lowrank_blocks"] == 26652
+    assert info["lowrank_by_level"][3] == 8 and info["lowrank_by_level"][10] == 19500
+
+
+def test_plan_rejects_bad_options():
+    M = hm.Mesh.from_workload(square_fault(4))
+    with pytest.raises(hm.HMError):
+        M.plan(65, 2.0)
+    with pytest.raises(hm.HMError):
+        M.plan(16, -1.0)
+
+
+def test_structs_match_c_layout():
+    # sizes the C side writes through the pointers
+    assert ctypes.sizeof(hm.SolveReport) == 4 * 3 + 4 + 8 * 2 + 4 + 4 + 8 * 1024
+    assert ctypes.sizeof(hm.BuildOpts) == 4 + 4 + 8 + 8 + 4 * 5 + 4

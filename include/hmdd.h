@@ -175,6 +175,8 @@ typedef struct {
     int near_prec, far_prec;
     double build_ms, coef_ms, aca_ms, pack_ms;
     int64_t max_dense_bytes_per_leaf;
+    int64_t bytes_far_u, bytes_far_v;  /* far-field bytes read by phase B (U) and phase A (V) */
+    int64_t rank_sum;                  /* sum of ranks over low-rank blocks */
 } hm_op_stats;
 
 hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
@@ -192,6 +194,18 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
  */
 hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
                             int64_t ldy, unsigned flags, void* hip_stream);
+
+/*
+ * hm_operator_apply that also measures its stages with HIP events recorded
+ * on hip_stream, then synchronises the stream.  stage_ms[5] receives the
+ * durations (ms) of: [0] gather of X into fragment chunks, [1] phase A
+ * (V^T X for every low-rank block), [2] reduction of phase-A partials,
+ * [3] phase B (dense leaves and U T, one workgroup per target leaf),
+ * [4] scatter with self/tangent epilogue.  Same arguments and errors as
+ * hm_operator_apply.
+ */
+hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
+                                  int64_t ldy, unsigned flags, void* hip_stream, double* stage_ms);
 
 /*
  * Set the tangent terms: A11 = E - D on active elements, identity rows and

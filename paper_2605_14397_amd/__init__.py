@@ -30,7 +30,8 @@ _STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "
 EXPORTS = [
     "hm_last_error", "hm_version", "hm_mesh_create", "hm_mesh_destroy", "hm_mesh_num_elements",
     "hm_mesh_frames", "hm_plan_summary", "hm_kernel_block", "hm_build_opts_default",
-    "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_tangent_set",
+    "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_operator_apply_timed",
+    "hm_tangent_set",
     "hm_solve_opts_default", "hm_solve",
 ]
 
@@ -54,7 +55,8 @@ class OpStats(ctypes.Structure):
         ("min_rank", ctypes.c_int), ("max_rank", ctypes.c_int), ("mean_rank", ctypes.c_double),
         ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int), ("build_ms", ctypes.c_double),
         ("coef_ms", ctypes.c_double), ("aca_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
-        ("max_dense_bytes_per_leaf", ctypes.c_int64)]
+        ("max_dense_bytes_per_leaf", ctypes.c_int64), ("bytes_far_u", ctypes.c_int64),
+        ("bytes_far_v", ctypes.c_int64), ("rank_sum", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +110,7 @@ def lib():
             "hm_op_destroy": ([P], None),
             "hm_operator_stats": ([P, ctypes.POINTER(OpStats)], I),
             "hm_operator_apply": ([P, I, P, I64, P, I64, U, P], I),
+            "hm_operator_apply_timed": ([P, I, P, I64, P, I64, U, P, P], I),
             "hm_tangent_set": ([P, P, P, P], I),
             "hm_solve_opts_default": ([ctypes.POINTER(SolveOpts)], None),
             "hm_solve": ([P, ctypes.POINTER(SolveOpts), I, P, I64, P, I64, ctypes.POINTER(SolveReport), P], I),
@@ -236,6 +239,18 @@ class Operator:
         _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), X2.stride(0),
                                        _dev_ptr(Y, torch.float64), Y.stride(0), flags, _stream(stream)))
         return Y.reshape(-1) if squeeze else Y
+
+    STAGES = ("gather", "phaseA", "reduceT", "phaseB", "scatter")
+
+    def apply_timed(self, X, Y, reference=False, tangent=False, stream=None):
+        """apply() with per-stage durations (ms) from HIP events on the stream."""
+        import torch
+
+        flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
+        ms = (ctypes.c_double * 5)()
+        _check(lib().hm_operator_apply_timed(self._h, X.shape[0], _dev_ptr(X, torch.float64), X.stride(0),
+                                             _dev_ptr(Y, torch.float64), Y.stride(0), flags, _stream(stream), ms))
+        return dict(zip(self.STAGES, list(ms)))
 
     def set_tangent(self, D=None, mask=None, stream=None):
         """A11 = E - D on active elements (D: CUDA float64 [N,3,3]; mask: CUDA uint8 [N])."""

@@ -24,17 +24,19 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // ---- per storage type: 16-byte granule and MFMA step ----
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
 template <class T>
 struct Mma;
 
 template <>
 struct Mma<double> {
     static constexpr int w = 2;
-    typedef d2 vec;
     // two 16x16x4 FP64 products: k = 2g + t
     template <class A>
-    __device__ static A run(vec a, vec b, vec, A c)
+    __device__ static A run(u4 ra, u4 rb, u4, A c)
     {
+        d2 a = __builtin_bit_cast(d2, ra), b = __builtin_bit_cast(d2, rb);
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c, 0, 0, 0);
         return c;
@@ -44,11 +46,11 @@ struct Mma<double> {
 template <>
 struct Mma<float> {
     static constexpr int w = 4;
-    typedef f4 vec;
     // four 16x16x4 FP32 products: k = 4g + t
     template <class A>
-    __device__ static A run(vec a, vec b, vec, A c)
+    __device__ static A run(u4 ra, u4 rb, u4, A c)
     {
+        f4 a = __builtin_bit_cast(f4, ra), b = __builtin_bit_cast(f4, rb);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
@@ -60,13 +62,13 @@ struct Mma<float> {
 template <>
 struct Mma<uint16_t> {
     static constexpr int w = 8;
-    typedef bf8 vec;
     // one 16x16x32 BF16 product per half of the split in-vector (hi + lo)
     template <class A>
-    __device__ static A run(vec a, vec bhi, vec blo, A c)
+    __device__ static A run(u4 ra, u4 rbh, u4 rbl, A c)
     {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bhi, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo, c, 0, 0, 0);
+        bf8 a = __builtin_bit_cast(bf8, ra);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8, rbh), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8, rbl), c, 0, 0, 0);
         return c;
     }
 };
@@ -87,20 +89,6 @@ struct AccScalar<d4> {
     __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 
-template <class V, class T>
-__device__ inline V load16(const T* p)
-{
-    return *reinterpret_cast<const V*>(p);
-}
-
-template <class V>
-__device__ inline V zero16()
-{
-    V z;
-    __builtin_memset(&z, 0, sizeof(V));
-    return z;
-}
-
 // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
 // contiguous range of tasks so neighbouring leaves share one L2.
 __device__ inline int xcd_task(int bid, int grid, int ntasks)
@@ -110,50 +98,144 @@ __device__ inline int xcd_task(int bid, int grid, int ntasks)
     return t < ntasks ? t : -1;
 }
 
-// Stream one panel's k-steps owned by this wave into the accumulators.
-template <class ST, class ACC>
-__device__ __attribute__((always_inline)) inline void run_panel(const PanelRef& P, const ST* __restrict__ A, const ST* __restrict__ Bhi,
-                                 const ST* __restrict__ Blo, int R, int wave, int lane, int& unit,
-                                 ACC (&acc)[kRowTilesMax])
-{
-    typedef typename Mma<ST>::vec vec;
-    constexpr int w = Mma<ST>::w;
-    constexpr int kstep = 4 * w;
-    const int nks = (P.cols + kstep - 1) / kstep;
-    const int Gr = (P.cols + w - 1) / w;
-    const int g = lane >> 4, i = lane & 15;
-    int ks = (wave - unit) & 3;
-    const ST* Ap = A + P.a_off;
-    for (; ks < nks; ks += 4) {
-        const int gg = min(4, Gr - 4 * ks);
-        const int64_t boff = P.b_off + ((int64_t)ks * 64 + lane) * w;
-        vec bhi = load16<vec>(Bhi + boff);
-        vec blo = Blo ? load16<vec>(Blo + boff) : zero16<vec>();
-        vec a[kRowTilesMax];
-#pragma unroll
-        for (int r = 0; r < kRowTilesMax; ++r) {
-            if (r < R) {
-                const int rr = min(16, P.rows - 16 * r);
-                const bool ok = (i < rr) && (g < gg);
-                const int64_t off = (int64_t)r * 16 * Gr * w + (int64_t)ks * rr * 4 * w + (int64_t)(g * rr + i) * w;
-                a[r] = ok ? load16<vec>(Ap + off) : zero16<vec>();
+// Buffers of one operand pair: A panels and the in-vector chunks they read.
+struct Side {
+    const char* A;     // panel storage
+    const char* Bhi;   // in-vector chunks (X or T), hi part
+    const char* Blo;   // lo part (BF16 split) or null
+    int es, w;         // element bytes, elements per 16-byte granule
+};
+
+// One unit of work: k-step ks of one panel, all its row tiles.
+struct Unit {
+    const char* a;     // first granule of the k-step
+    const char* bh;    // this lane's in-vector granule
+    const char* bl;
+    int gg;            // granules in this k-step (1..4)
+    int far;
+};
+
+// Walks the flattened sequence of (panel, k-step) units of a task.
+struct Cursor {
+    const PanelRef* items;
+    int n_items, item, base, nks;
+    PanelRef P;
+    __device__ void init(const PanelRef* it, int n, int kstep_near, int kstep_far)
+    {
+        items = it;
+        n_items = n;
+        item = 0;
+        base = 0;
+        if (n > 0) {
+            P = items[0];
+            nks = (P.cols + (P.far ? kstep_far : kstep_near) - 1) / (P.far ? kstep_far : kstep_near);
+        }
+    }
+    // position on unit u (u never decreases); false past the end
+    __device__ bool seek(int u, int kstep_near, int kstep_far)
+    {
+        while (item < n_items && u >= base + nks) {
+            base += nks;
+            ++item;
+            if (item < n_items) {
+                P = items[item];
+                const int ks = P.far ? kstep_far : kstep_near;
+                nks = (P.cols + ks - 1) / ks;
             }
         }
-#pragma unroll
-        for (int r = 0; r < kRowTilesMax; ++r)
-            if (r < R) acc[r] = Mma<ST>::run(a[r], bhi, blo, acc[r]);
+        return item < n_items;
     }
-    unit += nks;
+};
+
+__device__ inline Unit make_unit(const Cursor& c, int u, int rows, const Side& nearS, const Side& farS, int lane)
+{
+    const Side& S = c.P.far ? farS : nearS;
+    const int ks = u - c.base;
+    const int Gr = (c.P.cols + S.w - 1) / S.w;
+    Unit x;
+    x.gg = min(4, Gr - 4 * ks);
+    x.a = S.A + (int64_t)c.P.a_off * S.es + (int64_t)ks * rows * 64;
+    const int64_t boff = (int64_t)c.P.b_off * S.es + ((int64_t)ks * 64 + lane) * 16;
+    x.bh = S.Bhi + boff;
+    x.bl = S.Blo ? S.Blo + boff : nullptr;
+    x.far = c.P.far;
+    return x;
+}
+
+// Branch-free loads of all R row tiles of one unit; lanes outside the panel
+// read the chunk's first granule and are zeroed.
+template <int R>
+__device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int lane, u4 (&a)[R], u4& bh,
+                                                                 u4& bl)
+{
+    const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int rr = min(16, rows - 16 * r);
+        const bool ok = (i < rr) && (g < x.gg);
+        const int64_t gi = ok ? (int64_t)(r * 16 * x.gg + g * rr + i) : 0;
+        u4 v = *reinterpret_cast<const u4*>(x.a + 16 * gi);
+        a[r] = ok ? v : u4{0u, 0u, 0u, 0u};
+    }
+    bh = *reinterpret_cast<const u4*>(x.bh);
+    bl = x.bl ? *reinterpret_cast<const u4*>(x.bl) : u4{0u, 0u, 0u, 0u};
+}
+
+template <int R, class NT, class FT, class ACC>
+__device__ __attribute__((always_inline)) inline void mma_unit(int far, const u4 (&a)[R], u4 bh, u4 bl,
+                                                                ACC (&acc)[R])
+{
+    if (far) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
+    }
+}
+
+// Accumulate this wave's units u0, u0 + step, ... of one task, with the
+// loads of the next unit in flight while the current one is multiplied.
+template <int R, class NT, class FT, class ACC>
+__device__ __attribute__((always_inline)) inline void stream_units(const PanelRef* items, int n_items, int rows,
+                                                                    const Side& nearS, const Side& farS, int u0,
+                                                                    int step, int lane, ACC (&acc)[R])
+{
+    const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
+    Cursor c;
+    c.init(items, n_items, ksn, ksf);
+    u4 a0[R], a1[R], b0h, b0l, b1h, b1l;
+    int u = u0;
+    if (!c.seek(u, ksn, ksf)) return;
+    Unit x0 = make_unit(c, u, rows, nearS, farS, lane);
+    load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+    while (true) {
+        const bool v1 = c.seek(u + step, ksn, ksf);
+        Unit x1;
+        if (v1) {
+            x1 = make_unit(c, u + step, rows, nearS, farS, lane);
+            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+        }
+        mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
+        if (!v1) break;
+        const bool v2 = c.seek(u + 2 * step, ksn, ksf);
+        if (v2) {
+            x0 = make_unit(c, u + 2 * step, rows, nearS, farS, lane);
+            load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+        }
+        mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
+        if (!v2) break;
+        u += 2 * step;
+    }
 }
 
 // Sum the four waves' accumulators in a fixed order; wave 0 writes rows < rows.
-template <class ACC, class S>
-__device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc)[kRowTilesMax], int R, int rows, S* __restrict__ out,
-                                        int64_t row0, S* red, int wave, int lane)
+template <int R, class ACC, class S>
+__device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc)[R], int rows, S* __restrict__ out,
+                                                                        int64_t row0, S* red, int wave, int lane)
 {
 #pragma unroll
-    for (int r = 0; r < kRowTilesMax; ++r) {
-        if (r >= R) break;
+    for (int r = 0; r < R; ++r) {
         if (wave > 0)
             for (int v = 0; v < 4; ++v) red[(wave - 1) * 256 + lane * 4 + v] = acc[r][v];
         __syncthreads();
@@ -170,31 +252,48 @@ __device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc
     }
 }
 
+template <class NT, class FT>
+struct Sides {
+    Side nearS, farS;
+};
+
 // ------------------------------------------------------------------
-// phase A: T partial = sum over this task's V^T sub-panels of V^T X
+// phase A: one wavefront per task; T partial = sum of its V^T sub-panels x X
 // ------------------------------------------------------------------
-template <class FT, class ACC>
+template <int R, class NT, class FT, class ACC>
+__device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& farS,
+                            typename AccScalar<ACC>::type* __restrict__ tpart, int lane)
+{
+    ACC acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
+    auto* out = tpart + T.out_off;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
+}
+
+template <class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const FT* __restrict__ farA,
                                                 const FT* __restrict__ xhi, const FT* __restrict__ xlo,
                                                 typename AccScalar<ACC>::type* __restrict__ tpart)
 {
-    typedef typename AccScalar<ACC>::type S;
-    __shared__ S red[3 * 256];
-    const int bid = blockIdx.x;
-    if (bid >= ntasks) return;
-    const TaskA T = tasks[bid];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    ACC acc[kRowTilesMax];
-#pragma unroll
-    for (int r = 0; r < kRowTilesMax; ++r) acc[r] = ACC{0, 0, 0, 0};
-    const int R = (T.rows + 15) >> 4;
-    int unit = 0;
-    for (int it = 0; it < T.n_items; ++it) {
-        const PanelRef P = items[T.item_begin + it];
-        run_panel<FT, ACC>(P, farA, xhi, xlo, R, wave, lane, unit, acc);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + wave;
+    if (t >= ntasks) return;
+    const TaskA T = tasks[t];
+    const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(xhi),
+                    reinterpret_cast<const char*>(xlo), (int)sizeof(FT), Mma<FT>::w};
+    switch ((T.rows + 15) >> 4) {
+#define HM_CASE(R) \
+    case R: phaseA_wave<R, FT, FT, ACC>(T, items, farS, tpart, lane); break;
+        HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
+        HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
+#undef HM_CASE
+        default: break;
     }
-    reduce_and_store<ACC, S>(acc, R, 16 * R, tpart + T.out_off, 0, red, wave, lane);
 }
 
 // ------------------------------------------------------------------
@@ -226,8 +325,20 @@ __global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const S* __restrict
 }
 
 // ------------------------------------------------------------------
-// phase B: one workgroup per target leaf
+// phase B: one workgroup per target leaf, its four waves share the units
 // ------------------------------------------------------------------
+template <int R, class NT, class FT, class ACC>
+__device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& nearS, const Side& farS,
+                            typename AccScalar<ACC>::type* __restrict__ Y, typename AccScalar<ACC>::type* red,
+                            int wave, int lane)
+{
+    ACC acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
+    reduce_and_store<R, ACC>(acc, T.rows, Y, T.y_off, red, wave, lane);
+}
+
 template <class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const NT* __restrict__ nearA,
@@ -240,20 +351,19 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
     const int t = xcd_task(blockIdx.x, gridDim.x, ntasks);
     if (t < 0) return;
     const TaskB T = tasks[t];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    ACC acc[kRowTilesMax];
-#pragma unroll
-    for (int r = 0; r < kRowTilesMax; ++r) acc[r] = ACC{0, 0, 0, 0};
-    const int R = (T.rows + 15) >> 4;
-    int unit = 0;
-    for (int it = 0; it < T.n_items; ++it) {
-        const PanelRef P = items[T.item_begin + it];
-        if (P.far)
-            run_panel<FT, ACC>(P, farA, thi, tlo, R, wave, lane, unit, acc);
-        else
-            run_panel<NT, ACC>(P, nearA, xnear, nullptr, R, wave, lane, unit, acc);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const Side nearS{reinterpret_cast<const char*>(nearA), reinterpret_cast<const char*>(xnear), nullptr,
+                     (int)sizeof(NT), Mma<NT>::w};
+    const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(thi),
+                    reinterpret_cast<const char*>(tlo), (int)sizeof(FT), Mma<FT>::w};
+    switch ((T.rows + 15) >> 4) {
+#define HM_CASE(R) \
+    case R: phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, Y, red, wave, lane); break;
+        HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
+        HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
+#undef HM_CASE
+        default: break;
     }
-    reduce_and_store<ACC, S>(acc, R, T.rows, Y, T.y_off, red, wave, lane);
 }
 
 // ------------------------------------------------------------------
@@ -324,14 +434,18 @@ __global__ void k_scatter(int64_t ne, int nrhs, const S* __restrict__ Y, const i
 // ------------------------------------------------------------------
 template <class NT, class FT, class ACC>
 static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                    bool tangent, hipStream_t s)
+                    bool tangent, hipStream_t s, hipEvent_t* ev)
 {
+    auto mark = [&](int i) {
+        if (ev) HM_CHECK_HIP(hipEventRecord(ev[i], s));
+    };
     typedef typename AccScalar<ACC>::type S;
     const int64_t ne = op.ne;
     const uint8_t* mask = (tangent && op.has_mask) ? op.d_mask.as<uint8_t>() : nullptr;
     const bool sep = !v.far_is_near();
     FT* xfhi = sep ? v.xf_far_hi.as<FT>() : nullptr;
     FT* xflo = (sep && v.far_prec == HM_BF16) ? v.xf_far_lo.as<FT>() : nullptr;
+    mark(0);
     {
         int64_t n = ne * kNrhs;
         hipLaunchKernelGGL((k_gather<NT, FT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ne, nrhs, X, ldx,
@@ -339,18 +453,22 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
     }
     const FT* xa_hi = sep ? xfhi : reinterpret_cast<const FT*>(v.xf_near.get());
     const FT* xa_lo = xflo;
-    if (v.nTasksA > 0) {
-        hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(v.nTasksA), dim3(256), 0, s, v.tasksA.as<TaskA>(), v.nTasksA,
+    mark(1);
+    if (v.nTasksA > 0)
+        hipLaunchKernelGGL((k_phaseA<NT, FT, ACC>), dim3((v.nTasksA + 3) / 4), dim3(256), 0, s, v.tasksA.as<TaskA>(), v.nTasksA,
                            v.itemsA.as<PanelRef>(), v.far_a.as<FT>(), xa_hi, xa_lo, v.tpart.as<S>());
+    mark(2);
+    if (v.nTasksA > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(v.nReduce), dim3(256), 0, s, v.reduce.as<ReduceDesc>(),
                            v.tpart.as<S>(), v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr);
-    }
+    mark(3);
     {
         int grid = (int)round_up(v.nTasksB, 8);
         hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(grid), dim3(256), 0, s, v.tasksB.as<TaskB>(), v.nTasksB,
                            v.itemsB.as<PanelRef>(), v.near_a.as<NT>(), v.far_a.as<FT>(), v.xf_near.as<NT>(),
                            v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr, v.y.as<S>());
     }
+    mark(4);
     {
         int64_t n = ne * nrhs;
         const double* Dt = (tangent && op.has_D) ? op.d_D.as<double>() : nullptr;
@@ -358,21 +476,22 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
                            op.d_xslot.as<int64_t>(), op.d_xloc.as<int32_t>(), X, ldx, Y, ldy,
                            v.self_separate ? op.d_self.as<double>() : nullptr, Dt, mask, tangent ? 1 : 0);
     }
+    mark(5);
     HM_CHECK_HIP(hipGetLastError());
 }
 
 void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
-           bool tangent, hipStream_t s)
+           bool tangent, hipStream_t s, hipEvent_t* ev)
 {
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
     HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(X && Y, HM_EINVAL, "null vector pointer");
     if (v.near_prec == HM_F64)
-        apply_t<double, double, d4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s);
+        apply_t<double, double, d4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
     else if (v.far_prec == HM_F32)
-        apply_t<float, float, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s);
+        apply_t<float, float, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
     else
-        apply_t<float, uint16_t, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s);
+        apply_t<float, uint16_t, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
 }
 
 // ------------------------------------------------------------------

@@ -540,6 +540,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
             uslices[lf].push_back(Slice{far_elems, (int)b, lf});
             job.add(PackDesc{L.u_off + 3 * (c.begin - t.begin), far_elems, 3 * L.m, rows, k, 1, 0});
             far_elems += panel_elems(rows, k, wf);
+            v.bytes_far_u += panel_elems(rows, k, wf) * prec_bytes(v.far_prec);
         }
         for (int lf = sc.first_leaf; lf < sc.first_leaf + sc.n_leaves; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
@@ -547,6 +548,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
             vslices[b].push_back(Slice{far_elems, (int)b, lf});
             job.add(PackDesc{L.v_off + 3 * (c.begin - sc.begin), far_elems, 3 * L.n, k, cols, 0, 0});
             far_elems += panel_elems(k, cols, wf);
+            v.bytes_far_v += panel_elems(k, cols, wf) * prec_bytes(v.far_prec);
         }
     }
     v.far_a.alloc(std::max<int64_t>(1, far_elems) * prec_bytes(v.far_prec));
@@ -916,6 +918,9 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         for (int64_t x : per) maxleaf = std::max(maxleaf, x);
     }
     st.max_dense_bytes_per_leaf = maxleaf;
+    st.bytes_far_u = op.main.bytes_far_u;
+    st.bytes_far_v = op.main.bytes_far_v;
+    st.rank_sum = rank_sum;
 }
 
 }  // namespace hm

@@ -189,6 +189,37 @@ hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_
     });
 }
 
+hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
+                                  int64_t ldy, unsigned flags, void* hip_stream, double* stage_ms)
+{
+    return guarded([&] {
+        HM_REQUIRE(op && stage_ms, HM_EINVAL, "null argument");
+        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT)) == 0, HM_EINVAL, "unknown flag");
+        const hm::Op& o = op->op;
+        HM_REQUIRE(!(flags & HM_APPLY_REFERENCE) || o.ref || o.main.near_prec == HM_F64, HM_EINVAL,
+                   "no FP64 reference copy (build with keep_f64_reference)");
+        const hm::Variant& v = (flags & HM_APPLY_REFERENCE) ? o.ref_variant() : o.main;
+        hipStream_t s = (hipStream_t)hip_stream;
+        hipEvent_t ev[6] = {};
+        struct Events {
+            hipEvent_t* e;
+            ~Events()
+            {
+                for (int i = 0; i < 6; ++i)
+                    if (e[i]) (void)hipEventDestroy(e[i]);
+            }
+        } guard{ev};
+        for (int i = 0; i < 6; ++i) HM_CHECK_HIP(hipEventCreate(&ev[i]));
+        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, s, ev);
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < 5; ++i) {
+            float ms = 0.f;
+            HM_CHECK_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            stage_ms[i] = ms;
+        }
+    });
+}
+
 hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, void* hip_stream)
 {
     return guarded([&] {

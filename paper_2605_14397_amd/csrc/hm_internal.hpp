@@ -140,24 +140,27 @@ Plan make_plan(const Mesh& m, int leaf_size, double eta);
 // A panel is a row-major M x K matrix stored in "MFMA fragment" order so
 // that one wavefront streams it with 16-byte per-lane loads.  A granule is
 // 16 bytes (w = 2 doubles, 4 floats or 8 bf16); a k-step covers 4 granules
-// (Kstep = 4 w columns).  Rows are grouped in tiles of 16.  For row tile rt
-// (rr = min(16, M - 16 rt) rows) and k-step ks (gg = min(4, Gr - 4 ks)
-// granules, Gr = ceil(K / w)), the chunk holds rr * gg granules in [g][i]
-// order; lane (g, i) of a wavefront owns granule g of row i.  Padding is
-// only to the granule: the panel occupies M * Gr * w elements.
+// (Kstep = 4 w columns).  Storage is k-step major: k-step ks holds all M
+// rows, as row tiles of 16 (rr = min(16, M - 16 rt) rows) times gg =
+// min(4, Gr - 4 ks) granules (Gr = ceil(K / w)) in [g][i] order, so lane
+// (g, i) of a wavefront owns granule g of row i and one k-step of all row
+// tiles is contiguous.  Padding is only to the granule: the panel occupies
+// M * Gr granules.
 __host__ __device__ inline int64_t panel_granules(int K, int w) { return (K + w - 1) / w; }
 __host__ __device__ inline int64_t panel_elems(int M, int K, int w) { return (int64_t)M * panel_granules(K, w) * w; }
 
 __host__ __device__ inline int64_t panel_offset(int M, int K, int w, int row, int col)
 {
     int64_t Gr = panel_granules(K, w);
-    int rt = row >> 4, i = row & 15;
-    int rr = M - 16 * rt < 16 ? M - 16 * rt : 16;
     int kstep = 4 * w;
     int ks = col / kstep;
     int g = (col % kstep) / w;
     int t = col % w;
-    return (int64_t)rt * 16 * Gr * w + (int64_t)ks * rr * 4 * w + (int64_t)(g * rr + i) * w + t;
+    int gg = (int)(Gr - 4 * ks < 4 ? Gr - 4 * ks : 4);
+    int rt = row >> 4, i = row & 15;
+    int rr = M - 16 * rt < 16 ? M - 16 * rt : 16;
+    int64_t gran = (int64_t)ks * M * 4 + (int64_t)rt * 16 * gg + (int64_t)g * rr + i;
+    return gran * w + t;
 }
 
 // In-vector chunk ("B fragment") for 16 right-hand sides: dof q, rhs c.

@@ -15,7 +15,7 @@ struct Variant {
     DevBuf tasksB, itemsB, tasksA, itemsA, reduce;
     int nTasksB = 0, nTasksA = 0, nReduce = 0;
     int64_t tpart_elems = 0, tfrag_elems = 0;
-    int64_t bytes_near = 0, bytes_far = 0;
+    int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
     // workspaces (sized for 16 right-hand sides)
     DevBuf xf_near;               // X chunks in near precision
     DevBuf xf_far_hi, xf_far_lo;  // X chunks in far precision when it differs (bf16 split)
@@ -62,8 +62,9 @@ void kernel_block(Mesh& mesh, double young, double nu, int64_t nr, const int64_t
 void ensure_mesh_geo(Mesh& mesh);
 
 // apply (hm_apply.hip)
+// ev (optional): 6 events recorded before, between and after the 5 stages
 void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
-           bool tangent, hipStream_t s);
+           bool tangent, hipStream_t s, hipEvent_t* ev = nullptr);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 
 // solve (hm_solve.hip)

@@ -162,21 +162,35 @@ __device__ inline Unit make_unit(const Cursor& c, int u, int rows, const Side& n
     return x;
 }
 
-// Branch-free loads of all R row tiles of one unit; lanes outside the panel
-// read the chunk's first granule and are zeroed.
+// Loads of all R row tiles of one unit through a raw buffer resource over
+// the unit's chunk: the row-tile offset is a scalar, lanes outside the
+// panel get an out-of-range offset and read zero (raw buffer range check).
+__device__ inline __amdgpu_buffer_rsrc_t chunk_rsrc(const char* base, uint32_t bytes)
+{
+    // the base and size are wave-uniform by construction; say so explicitly
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    char* p = reinterpret_cast<char*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
 template <int R>
 __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int lane, u4 (&a)[R], u4& bh,
                                                                  u4& bl)
 {
     const int g = lane >> 4, i = lane & 15;
+    const uint32_t kOut = 0x80000000u;
+    const int gg = __builtin_amdgcn_readfirstlane(x.gg);
+    const bool gok = g < gg;
+    const int rr_last = rows - 16 * (R - 1);
+    const uint32_t vfull = gok ? 16u * (uint32_t)(16 * g + i) : kOut;
+    const uint32_t vlast = (gok && i < rr_last) ? 16u * (uint32_t)(g * rr_last + i) : kOut;
+    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(x.a, (uint32_t)(rows * gg * 16));
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int rr = min(16, rows - 16 * r);
-        const bool ok = (i < rr) && (g < x.gg);
-        const int64_t gi = ok ? (int64_t)(r * 16 * x.gg + g * rr + i) : 0;
-        u4 v = *reinterpret_cast<const u4*>(x.a + 16 * gi);
-        a[r] = ok ? v : u4{0u, 0u, 0u, 0u};
-    }
+    for (int r = 0; r < R; ++r)
+        a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rs, r == R - 1 ? vlast : vfull,
+                                                                            r * 256 * gg, 0));
     bh = *reinterpret_cast<const u4*>(x.bh);
     bl = x.bl ? *reinterpret_cast<const u4*>(x.bl) : u4{0u, 0u, 0u, 0u};
 }
@@ -339,7 +353,9 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     reduce_and_store<R, ACC>(acc, T.rows, Y, T.y_off, red, wave, lane);
 }
 
-template <class NT, class FT, class ACC>
+// One launch per row-tile count R (tasks are grouped by R at build time),
+// so each kernel is compiled for its own accumulator size.
+template <int R, class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const NT* __restrict__ nearA,
                                                 const FT* __restrict__ farA, const NT* __restrict__ xnear,
@@ -356,14 +372,7 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
                      (int)sizeof(NT), Mma<NT>::w};
     const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(thi),
                     reinterpret_cast<const char*>(tlo), (int)sizeof(FT), Mma<FT>::w};
-    switch ((T.rows + 15) >> 4) {
-#define HM_CASE(R) \
-    case R: phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, Y, red, wave, lane); break;
-        HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
-        HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
-#undef HM_CASE
-        default: break;
-    }
+    phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, Y, red, wave, lane);
 }
 
 // ------------------------------------------------------------------
@@ -462,11 +471,24 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(v.nReduce), dim3(256), 0, s, v.reduce.as<ReduceDesc>(),
                            v.tpart.as<S>(), v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr);
     mark(3);
-    {
-        int grid = (int)round_up(v.nTasksB, 8);
-        hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(grid), dim3(256), 0, s, v.tasksB.as<TaskB>(), v.nTasksB,
-                           v.itemsB.as<PanelRef>(), v.near_a.as<NT>(), v.far_a.as<FT>(), v.xf_near.as<NT>(),
-                           v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr, v.y.as<S>());
+    for (int R = 1; R <= kRowTilesMax; ++R) {
+        const int begin = v.groupB[R - 1].first, count = v.groupB[R - 1].second;
+        if (count == 0) continue;
+        const int grid = (int)round_up(count, 8);
+        const FT* tlo = v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr;
+        const TaskB* tb = v.tasksB.as<TaskB>() + begin;
+        switch (R) {
+#define HM_CASE(RR)                                                                                            \
+    case RR:                                                                                                   \
+        hipLaunchKernelGGL((k_phaseB<RR, NT, FT, ACC>), dim3(grid), dim3(256), 0, s, tb, count,                \
+                           v.itemsB.as<PanelRef>(), v.near_a.as<NT>(), v.far_a.as<FT>(), v.xf_near.as<NT>(),   \
+                           v.tf_hi.as<FT>(), tlo, v.y.as<S>());                                                 \
+        break;
+            HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
+            HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
+#undef HM_CASE
+            default: break;
+        }
     }
     mark(4);
     {

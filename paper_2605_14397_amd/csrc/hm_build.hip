@@ -602,6 +602,17 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         t.n_items = (int32_t)ib.size() - t.item_begin;
         tb.push_back(t);
     }
+    // group phase-B tasks by row-tile count (one launch per group), leaf order kept inside a group
+    std::stable_sort(tb.begin(), tb.end(), [](const TaskB& a, const TaskB& b) {
+        return (a.rows + 15) / 16 > (b.rows + 15) / 16;
+    });
+    for (int R = 1; R <= kRowTilesMax; ++R) v.groupB[R - 1] = {0, 0};
+    for (size_t q = 0; q < tb.size(); ++q) {
+        const int R = (tb[q].rows + 15) / 16;
+        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "leaf rows out of range");
+        if (v.groupB[R - 1].second == 0) v.groupB[R - 1].first = (int)q;
+        v.groupB[R - 1].second++;
+    }
     // longest tasks first so the tail of the launch is short
     std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
         return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;

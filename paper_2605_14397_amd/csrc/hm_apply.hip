@@ -175,6 +175,7 @@ __device__ inline __amdgpu_buffer_rsrc_t chunk_rsrc(const char* base, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
+// Rt = ceil(rows / 16) <= R tiles hold data; tiles r >= Rt read zero.
 template <int R>
 __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int lane, u4 (&a)[R], u4& bh,
                                                                  u4& bl)
@@ -182,15 +183,16 @@ __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, i
     const int g = lane >> 4, i = lane & 15;
     const uint32_t kOut = 0x80000000u;
     const int gg = __builtin_amdgcn_readfirstlane(x.gg);
+    const int Rt = __builtin_amdgcn_readfirstlane((rows + 15) >> 4);
     const bool gok = g < gg;
-    const int rr_last = rows - 16 * (R - 1);
+    const int rr_last = rows - 16 * (Rt - 1);
     const uint32_t vfull = gok ? 16u * (uint32_t)(16 * g + i) : kOut;
     const uint32_t vlast = (gok && i < rr_last) ? 16u * (uint32_t)(g * rr_last + i) : kOut;
     const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(x.a, (uint32_t)(rows * gg * 16));
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rs, r == R - 1 ? vlast : vfull,
-                                                                            r * 256 * gg, 0));
+        a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(
+                                          rs, r < Rt - 1 ? vfull : (r == Rt - 1 ? vlast : kOut), r * 256 * gg, 0));
     bh = *reinterpret_cast<const u4*>(x.bh);
     bl = x.bl ? *reinterpret_cast<const u4*>(x.bl) : u4{0u, 0u, 0u, 0u};
 }
@@ -274,25 +276,57 @@ struct Sides {
 // ------------------------------------------------------------------
 // phase A: one wavefront per task; T partial = sum of its V^T sub-panels x X
 // ------------------------------------------------------------------
+// T value -> far-precision fragment entry (BF16 as a hi/lo pair)
+template <class FT, class S>
+__device__ inline void store_t(FT* __restrict__ thi, FT* __restrict__ tlo, int64_t off, S v)
+{
+    if constexpr (sizeof(FT) == 2) {
+        float f = (float)v;
+        uint16_t h = f32_to_bf16_bits(f);
+        thi[off] = h;
+        tlo[off] = f32_to_bf16_bits(f - bf16_bits_to_f32(h));
+    } else {
+        thi[off] = (FT)v;
+    }
+}
+
 template <int R, class NT, class FT, class ACC>
 __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& farS,
-                            typename AccScalar<ACC>::type* __restrict__ tpart, int lane)
+                            typename AccScalar<ACC>::type* __restrict__ tpart, FT* __restrict__ thi,
+                            FT* __restrict__ tlo, int lane)
 {
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
     stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
+    // only this task's own tiles are written: its T chunk holds ceil(k / 32) * 32
+    // rows and its partial slot ceil(k / 16) * 16 rows
+    const int Rt = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
+    if (T.direct) {
+        // the task covers the whole block: write its T chunk directly
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < Rt)
+                for (int v = 0; v < 4; ++v)
+                    store_t<FT>(thi, tlo,
+                                T.t_off + bfrag_offset(Mma<FT>::w, 16 * r + AccScalar<ACC>::row(lane, v), lane & 15),
+                                acc[r][v]);
+        return;
+    }
     auto* out = tpart + T.out_off;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
+        if (r < Rt)
+            for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
-template <class NT, class FT, class ACC>
+// One launch per row-tile count R (tasks grouped by R at build time).
+template <int R, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const FT* __restrict__ farA,
                                                 const FT* __restrict__ xhi, const FT* __restrict__ xlo,
-                                                typename AccScalar<ACC>::type* __restrict__ tpart)
+                                                typename AccScalar<ACC>::type* __restrict__ tpart,
+                                                FT* __restrict__ thi, FT* __restrict__ tlo)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int t = blockIdx.x * 4 + wave;
@@ -300,14 +334,7 @@ __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks,
     const TaskA T = tasks[t];
     const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(xhi),
                     reinterpret_cast<const char*>(xlo), (int)sizeof(FT), Mma<FT>::w};
-    switch ((T.rows + 15) >> 4) {
-#define HM_CASE(R) \
-    case R: phaseA_wave<R, FT, FT, ACC>(T, items, farS, tpart, lane); break;
-        HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
-        HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
-#undef HM_CASE
-        default: break;
-    }
+    phaseA_wave<R, FT, FT, ACC>(T, items, farS, tpart, thi, tlo, lane);
 }
 
 // ------------------------------------------------------------------
@@ -326,15 +353,7 @@ __global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const S* __restrict
         S v = 0;
         if (row < D.rank)
             for (int s = 0; s < D.n_slots; ++s) v += tpart[D.slot_begin + s * slot + (int64_t)row * kNrhs + c];
-        const int64_t off = D.t_off + bfrag_offset(w, row, c);
-        if constexpr (sizeof(FT) == 2) {
-            float f = (float)v;
-            uint16_t h = f32_to_bf16_bits(f);
-            thi[off] = h;
-            tlo[off] = f32_to_bf16_bits(f - bf16_bits_to_f32(h));
-        } else {
-            thi[off] = (FT)v;
-        }
+        store_t<FT>(thi, tlo, D.t_off + bfrag_offset(w, row, c), v);
     }
 }
 
@@ -463,11 +482,26 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
     const FT* xa_hi = sep ? xfhi : reinterpret_cast<const FT*>(v.xf_near.get());
     const FT* xa_lo = xflo;
     mark(1);
-    if (v.nTasksA > 0)
-        hipLaunchKernelGGL((k_phaseA<NT, FT, ACC>), dim3((v.nTasksA + 3) / 4), dim3(256), 0, s, v.tasksA.as<TaskA>(), v.nTasksA,
-                           v.itemsA.as<PanelRef>(), v.far_a.as<FT>(), xa_hi, xa_lo, v.tpart.as<S>());
+    if (v.nTasksA > 0) {
+        // one launch sized for the largest rank; smaller ranks leave tiles empty
+        const int R = v.maxRA, count = v.nTasksA;
+        const TaskA* ta = v.tasksA.as<TaskA>();
+        FT* tlo = v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr;
+        switch (R) {
+#define HM_CASE(RR)                                                                                              \
+    case RR:                                                                                                     \
+        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3((count + 3) / 4), dim3(256), 0, s, ta, count,          \
+                           v.itemsA.as<PanelRef>(), v.far_a.as<FT>(), xa_hi, xa_lo, v.tpart.as<S>(),            \
+                           v.tf_hi.as<FT>(), tlo);                                                                \
+        break;
+            HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
+            HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
+#undef HM_CASE
+            default: break;
+        }
+    }
     mark(2);
-    if (v.nTasksA > 0)
+    if (v.nReduce > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(v.nReduce), dim3(256), 0, s, v.reduce.as<ReduceDesc>(),
                            v.tpart.as<S>(), v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr);
     mark(3);

@@ -571,18 +571,21 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         const int64_t slot = round_up(L.rank, 16) * kNrhs;
         ReduceDesc rd{tpart, t_off[b], 0, L.rank};
         const auto& vs = vslices[b];
+        const bool direct = vs.size() <= (size_t)kLeavesPerTaskA;
         for (size_t q0 = 0; q0 < vs.size(); q0 += kLeavesPerTaskA) {
-            TaskA t{tpart, L.rank, (int32_t)ia.size(), 0, 0};
+            TaskA t{direct ? 0 : tpart, t_off[b], L.rank, (int32_t)ia.size(), 0, direct ? 1 : 0};
             for (size_t q = q0; q < std::min(vs.size(), q0 + kLeavesPerTaskA); ++q) {
                 const Cluster& c = p.nodes[p.leaves[vs[q].leaf]];
                 ia.push_back(PanelRef{vs[q].off, op.leaf_xoff[vs[q].leaf] * kNrhs, L.rank, 3 * (int32_t)c.size(), 1, 0});
                 t.n_items++;
             }
             ta.push_back(t);
-            tpart += slot;
-            rd.n_slots++;
+            if (!direct) {
+                tpart += slot;
+                rd.n_slots++;
+            }
         }
-        red.push_back(rd);
+        if (!direct) red.push_back(rd);
     }
     // ---- phase-B tasks: one per target leaf ----
     std::vector<std::vector<int>> dense_by_leaf(nleaf);
@@ -613,10 +616,16 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         if (v.groupB[R - 1].second == 0) v.groupB[R - 1].first = (int)q;
         v.groupB[R - 1].second++;
     }
-    // longest tasks first so the tail of the launch is short
+    // phase-A tasks: longest first so the tail of the launch is short
     std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
         return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
     });
+    v.maxRA = 1;
+    for (const TaskA& t : ta) {
+        const int R = (t.rows + 15) / 16;
+        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
+        v.maxRA = std::max(v.maxRA, R);
+    }
     upload(v.tasksB, tb, s);
     upload(v.itemsB, ib, s);
     upload(v.tasksA, ta, s);

@@ -200,10 +200,11 @@ struct TaskB {        // one target leaf
 };
 
 struct TaskA {        // part of one low-rank block: T partial = sum V^T X
-    int64_t out_off;  // partial slot start (elements, [rows_pad][16])
+    int64_t out_off;  // partial slot start (elements, [rows_pad][16]) when not direct
+    int64_t t_off;    // T fragment chunk of the block (elements) when direct
     int32_t rows;     // rank k
     int32_t item_begin, n_items;
-    int32_t pad;
+    int32_t direct;   // 1: the task covers the whole block and writes T itself
 };
 
 struct ReduceDesc {   // T_b = sum of partial slots

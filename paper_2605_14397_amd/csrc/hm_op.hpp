@@ -15,6 +15,7 @@ struct Variant {
     DevBuf tasksB, itemsB, tasksA, itemsA, reduce;
     int nTasksB = 0, nTasksA = 0, nReduce = 0;
     std::pair<int, int> groupB[kRowTilesMax] = {};  // phase-B tasks with R row tiles: (first, count)
+    int maxRA = 1;                                  // largest row-tile count of a phase-A task
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
     // workspaces (sized for 16 right-hand sides)

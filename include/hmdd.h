@@ -219,6 +219,49 @@ hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, 
 hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Batched products over many operators                                 */
+/* ------------------------------------------------------------------ */
+/*
+ * Several independent operators (e.g. many fault meshes, each its own
+ * E, paper Sec. 3.1) applied together: their work lists are merged so one
+ * gather, one low-rank phase, one reduction, one dense/low-rank phase per
+ * row-tile class and one scatter cover all of them, and the sequence is
+ * captured once as a HIP graph (use_graph) and replayed.  autotune times
+ * candidate phase-A task sizes on the batch at creation and keeps the
+ * fastest (this also changes the member operators' own task size).
+ * The operators must outlive the batch, share one precision form, and not
+ * be applied concurrently with it.
+ */
+typedef struct hm_batch hm_batch;
+typedef struct {
+    int use_graph;  /* 1: capture once, replay (default 1) */
+    int autotune;   /* 1: tune the phase-A task size at creation (default 1) */
+} hm_batch_opts;
+
+typedef struct {
+    int n_ops;
+    int64_t total_elements;
+    int use_graph;
+    int leaves_per_task_a;     /* chosen phase-A task size */
+    int tune_candidates[5];    /* candidate task sizes */
+    double tune_ms[5];         /* measured ms per batched product, 16 columns */
+    int64_t bytes_operators;   /* stored panel bytes of all operators */
+} hm_batch_info;
+
+void hm_batch_opts_default(hm_batch_opts* opts);
+hm_status hm_batch_create(int n_ops, hm_op* const* ops, const hm_batch_opts* opts, void* hip_stream,
+                          hm_batch** out);
+/*
+ * Y_i = E_i X_i for every operator i, nrhs columns each (1..16).
+ *   d_X[i], d_Y[i] : device pointers, [nrhs][ld] float64 (host arrays of pointers)
+ *   ldx, ldy       : per-operator leading dimensions (host arrays) or NULL for 3 N_i
+ */
+hm_status hm_batch_apply(hm_batch* batch, int nrhs, const double* const* d_X, const int64_t* ldx,
+                         double* const* d_Y, const int64_t* ldy, void* hip_stream);
+hm_status hm_batch_get_info(const hm_batch* batch, hm_batch_info* out);
+void hm_batch_destroy(hm_batch* batch);
+
+/* ------------------------------------------------------------------ */
 /* Krylov solve of the tangent system                                   */
 /* ------------------------------------------------------------------ */
 enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2 };

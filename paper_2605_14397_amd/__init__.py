@@ -32,7 +32,8 @@ EXPORTS = [
     "hm_mesh_frames", "hm_plan_summary", "hm_kernel_block", "hm_build_opts_default",
     "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_operator_apply_timed",
     "hm_tangent_set",
-    "hm_solve_opts_default", "hm_solve",
+    "hm_solve_opts_default", "hm_solve", "hm_batch_opts_default", "hm_batch_create", "hm_batch_apply",
+    "hm_batch_get_info", "hm_batch_destroy",
 ]
 
 
@@ -79,6 +80,16 @@ class SolveReport(ctypes.Structure):
         return d
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int), ("autotune", ctypes.c_int)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_ops", ctypes.c_int), ("total_elements", ctypes.c_int64), ("use_graph", ctypes.c_int),
+                ("leaves_per_task_a", ctypes.c_int), ("tune_candidates", ctypes.c_int * 5),
+                ("tune_ms", ctypes.c_double * 5), ("bytes_operators", ctypes.c_int64)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_leaves", "n_dense_blocks", "n_lowrank_blocks", "dense_entries", "lowrank_sum_mn", "max_leaf",
@@ -114,6 +125,11 @@ def lib():
             "hm_tangent_set": ([P, P, P, P], I),
             "hm_solve_opts_default": ([ctypes.POINTER(SolveOpts)], None),
             "hm_solve": ([P, ctypes.POINTER(SolveOpts), I, P, I64, P, I64, ctypes.POINTER(SolveReport), P], I),
+            "hm_batch_opts_default": ([ctypes.POINTER(BatchOpts)], None),
+            "hm_batch_create": ([I, ctypes.POINTER(P), ctypes.POINTER(BatchOpts), P, ctypes.POINTER(P)], I),
+            "hm_batch_apply": ([P, I, ctypes.POINTER(P), P, ctypes.POINTER(P), P, P], I),
+            "hm_batch_get_info": ([P, ctypes.POINTER(BatchInfo)], I),
+            "hm_batch_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -279,4 +295,49 @@ class Operator:
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hm_op_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """Owner of an hm_batch: many operators applied by merged launches
+    (captured as one HIP graph).  Keeps its operators alive."""
+
+    def __init__(self, ops, use_graph=True, autotune=True, stream=None):
+        self.ops = list(ops)
+        o = BatchOpts()
+        lib().hm_batch_opts_default(ctypes.byref(o))
+        o.use_graph = 1 if use_graph else 0
+        o.autotune = 1 if autotune else 0
+        arr = (ctypes.c_void_p * len(self.ops))(*[op._h for op in self.ops])
+        h = ctypes.c_void_p()
+        _check(lib().hm_batch_create(len(self.ops), arr, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def apply(self, Xs, Ys, stream=None):
+        """Ys[i] = E_i Xs[i]; each a CUDA float64 tensor [nrhs, 3 N_i] (same nrhs)."""
+        import torch
+
+        n = len(self.ops)
+        assert len(Xs) == n and len(Ys) == n
+        nrhs = Xs[0].shape[0]
+        xp = (ctypes.c_void_p * n)(*[_dev_ptr(x, torch.float64).value for x in Xs])
+        yp = (ctypes.c_void_p * n)(*[_dev_ptr(y, torch.float64).value for y in Ys])
+        ldx = (ctypes.c_int64 * n)(*[x.stride(0) for x in Xs])
+        ldy = (ctypes.c_int64 * n)(*[y.stride(0) for y in Ys])
+        for x in Xs:
+            if x.shape[0] != nrhs:
+                raise HMError(HM_EINVAL, "all operators take the same number of columns")
+        _check(lib().hm_batch_apply(self._h, nrhs, xp, ldx, yp, ldy, _stream(stream)))
+        return Ys
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib().hm_batch_get_info(self._h, ctypes.byref(i)))
+        return {"n_ops": i.n_ops, "total_elements": i.total_elements, "use_graph": i.use_graph,
+                "leaves_per_task_a": i.leaves_per_task_a, "tune_candidates": list(i.tune_candidates),
+                "tune_ms": list(i.tune_ms), "bytes_operators": i.bytes_operators}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_batch_destroy(self._h)
             self._h = None

@@ -320,31 +320,34 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
             for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
-// One launch per row-tile count R (tasks grouped by R at build time).
+// One launch, sized for the largest rank; one wavefront per task.
 template <int R, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
-                                                const PanelRef* __restrict__ items, const FT* __restrict__ farA,
-                                                const FT* __restrict__ xhi, const FT* __restrict__ xlo,
-                                                typename AccScalar<ACC>::type* __restrict__ tpart,
-                                                FT* __restrict__ thi, FT* __restrict__ tlo)
+                                                const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
 {
+    typedef typename AccScalar<ACC>::type S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int t = blockIdx.x * 4 + wave;
     if (t >= ntasks) return;
     const TaskA T = tasks[t];
-    const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(xhi),
-                    reinterpret_cast<const char*>(xlo), (int)sizeof(FT), Mma<FT>::w};
-    phaseA_wave<R, FT, FT, ACC>(T, items, farS, tpart, thi, tlo, lane);
+    const Bases B = bases[T.op];
+    const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.xfhi),
+                    reinterpret_cast<const char*>(B.xflo), (int)sizeof(FT), Mma<FT>::w};
+    phaseA_wave<R, FT, FT, ACC>(T, items, farS, static_cast<S*>(B.tpart), static_cast<FT*>(B.thi),
+                                static_cast<FT*>(B.tlo), lane);
 }
 
 // ------------------------------------------------------------------
 // reduce phase-A partials into T fragment chunks (far precision)
 // ------------------------------------------------------------------
 template <class FT, class S>
-__global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const S* __restrict__ tpart, FT* __restrict__ thi,
-                          FT* __restrict__ tlo)
+__global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const Bases* __restrict__ bases)
 {
     const ReduceDesc D = rd[blockIdx.x];
+    const Bases B = bases[D.op];
+    const S* tpart = static_cast<const S*>(B.tpart);
+    FT* thi = static_cast<FT*>(B.thi);
+    FT* tlo = static_cast<FT*>(B.tlo);
     const int Kp = (int)round_up(D.rank, kChunkAlign);
     const int64_t slot = (int64_t)((D.rank + 15) / 16) * 16 * kNrhs;
     constexpr int w = Mma<FT>::w;
@@ -376,123 +379,164 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
 // so each kernel is compiled for its own accumulator size.
 template <int R, class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, int ntasks,
-                                                const PanelRef* __restrict__ items, const NT* __restrict__ nearA,
-                                                const FT* __restrict__ farA, const NT* __restrict__ xnear,
-                                                const FT* __restrict__ thi, const FT* __restrict__ tlo,
-                                                typename AccScalar<ACC>::type* __restrict__ Y)
+                                                const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
 {
     typedef typename AccScalar<ACC>::type S;
     __shared__ S red[3 * 256];
     const int t = xcd_task(blockIdx.x, gridDim.x, ntasks);
     if (t < 0) return;
     const TaskB T = tasks[t];
+    const Bases B = bases[T.op];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const Side nearS{reinterpret_cast<const char*>(nearA), reinterpret_cast<const char*>(xnear), nullptr,
+    const Side nearS{reinterpret_cast<const char*>(B.nearA), reinterpret_cast<const char*>(B.xnear), nullptr,
                      (int)sizeof(NT), Mma<NT>::w};
-    const Side farS{reinterpret_cast<const char*>(farA), reinterpret_cast<const char*>(thi),
-                    reinterpret_cast<const char*>(tlo), (int)sizeof(FT), Mma<FT>::w};
-    phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, Y, red, wave, lane);
+    const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.thi),
+                    reinterpret_cast<const char*>(B.tlo), (int)sizeof(FT), Mma<FT>::w};
+    phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, static_cast<S*>(B.y), red, wave, lane);
 }
 
 // ------------------------------------------------------------------
-// gather / scatter
+// gather / scatter (one segment per operator: blockIdx.y)
 // ------------------------------------------------------------------
 template <class NT, class FT>
-__global__ void k_gather(int64_t ne, int nrhs, const double* __restrict__ X, int64_t ldx,
-                         const uint8_t* __restrict__ mask, const int64_t* __restrict__ xslot,
-                         const int32_t* __restrict__ xloc, NT* __restrict__ xnear, FT* __restrict__ xfhi,
-                         FT* __restrict__ xflo)
+__device__ inline void gather_body(const Segment& S, const Bases& B, int nrhs)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ne * kNrhs) return;
-    const int c = (int)(idx / ne);
-    const int64_t e = idx - (int64_t)c * ne;
-    const bool on = c < nrhs && (!mask || mask[e]);
-    const int64_t base = xslot[e] * kNrhs;
-    const int q0 = xloc[e];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= S.ne * kNrhs) return;
+    const int c = (int)(idx / S.ne);
+    const int64_t e = idx - (int64_t)c * S.ne;
+    const bool on = c < nrhs && (!S.mask || S.mask[e]);
+    const int64_t base = S.xslot[e] * kNrhs;
+    const int q0 = S.xloc[e];
+    NT* xnear = static_cast<NT*>(B.xnear);
+    FT* xfhi = B.xfhi != B.xnear ? static_cast<FT*>(B.xfhi) : nullptr;
+    FT* xflo = static_cast<FT*>(B.xflo);
     for (int a = 0; a < 3; ++a) {
-        const double x = on ? X[c * ldx + 3 * e + a] : 0.0;
+        const double x = on ? S.X[c * S.ldx + 3 * e + a] : 0.0;
         xnear[base + bfrag_offset(Mma<NT>::w, q0 + a, c)] = cvt<NT>(x);
-        if (xfhi) {
-            const int64_t off = base + bfrag_offset(Mma<FT>::w, q0 + a, c);
-            if constexpr (sizeof(FT) == 2) {
-                float f = (float)x;
-                uint16_t h = f32_to_bf16_bits(f);
-                xfhi[off] = h;
-                xflo[off] = f32_to_bf16_bits(f - bf16_bits_to_f32(h));
-            } else {
-                xfhi[off] = cvt<FT>(x);
-            }
-        }
+        if (xfhi) store_t<FT>(xfhi, xflo, base + bfrag_offset(Mma<FT>::w, q0 + a, c), x);
     }
 }
 
-template <class S>
-__global__ void k_scatter(int64_t ne, int nrhs, const S* __restrict__ Y, const int64_t* __restrict__ xslot,
-                          const int32_t* __restrict__ xloc, const double* __restrict__ X, int64_t ldx,
-                          double* __restrict__ Yout, int64_t ldy, const double* __restrict__ self,
-                          const double* __restrict__ Dt, const uint8_t* __restrict__ mask, int tangent)
+template <class NT, class FT>
+__global__ void k_gather1(Segment S, const Bases* __restrict__ bases, int nrhs)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ne * nrhs) return;
-    const int c = (int)(idx / ne);
-    const int64_t e = idx - (int64_t)c * ne;
-    const int64_t row = xslot[e] + xloc[e];
+    gather_body<NT, FT>(S, bases[S.op], nrhs);
+}
+
+template <class NT, class FT>
+__global__ void k_gatherN(const Segment* __restrict__ segs, const Bases* __restrict__ bases, int nrhs)
+{
+    const Segment S = segs[blockIdx.y];
+    gather_body<NT, FT>(S, bases[S.op], nrhs);
+}
+
+template <class S_t>
+__device__ inline void scatter_body(const Segment& S, const Bases& B, int nrhs)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= S.ne * nrhs) return;
+    const int c = (int)(idx / S.ne);
+    const int64_t e = idx - (int64_t)c * S.ne;
+    const int64_t row = S.xslot[e] + S.xloc[e];
+    const S_t* Y = static_cast<const S_t*>(B.y);
     double y[3], x[3];
     for (int a = 0; a < 3; ++a) {
         y[a] = (double)Y[(row + a) * kNrhs + c];
-        x[a] = X[c * ldx + 3 * e + a];
+        x[a] = S.X[c * S.ldx + 3 * e + a];
     }
-    if (self)
+    if (S.self)
         for (int a = 0; a < 3; ++a)
-            y[a] += self[9 * e + 3 * a] * x[0] + self[9 * e + 3 * a + 1] * x[1] + self[9 * e + 3 * a + 2] * x[2];
-    if (tangent) {
-        if (mask && !mask[e]) {
+            y[a] += S.self[9 * e + 3 * a] * x[0] + S.self[9 * e + 3 * a + 1] * x[1] + S.self[9 * e + 3 * a + 2] * x[2];
+    if (S.tangent) {
+        if (S.mask && !S.mask[e]) {
             for (int a = 0; a < 3; ++a) y[a] = x[a];
-        } else if (Dt) {
+        } else if (S.D) {
             for (int a = 0; a < 3; ++a)
-                y[a] -= Dt[9 * e + 3 * a] * x[0] + Dt[9 * e + 3 * a + 1] * x[1] + Dt[9 * e + 3 * a + 2] * x[2];
+                y[a] -= S.D[9 * e + 3 * a] * x[0] + S.D[9 * e + 3 * a + 1] * x[1] + S.D[9 * e + 3 * a + 2] * x[2];
         }
     }
-    for (int a = 0; a < 3; ++a) Yout[c * ldy + 3 * e + a] = y[a];
+    for (int a = 0; a < 3; ++a) S.Y[c * S.ldy + 3 * e + a] = y[a];
+}
+
+template <class S_t>
+__global__ void k_scatter1(Segment S, const Bases* __restrict__ bases, int nrhs)
+{
+    scatter_body<S_t>(S, bases[S.op], nrhs);
+}
+
+template <class S_t>
+__global__ void k_scatterN(const Segment* __restrict__ segs, const Bases* __restrict__ bases, int nrhs)
+{
+    const Segment S = segs[blockIdx.y];
+    scatter_body<S_t>(S, bases[S.op], nrhs);
 }
 
 // ------------------------------------------------------------------
 // host driver
 // ------------------------------------------------------------------
-template <class NT, class FT, class ACC>
-static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                    bool tangent, hipStream_t s, hipEvent_t* ev)
+LaunchSet launch_set(const Variant& v)
 {
+    LaunchSet L;
+    L.near_prec = v.near_prec;
+    L.far_prec = v.far_prec;
+    L.bases = v.bases.as<Bases>();
+    L.tasksA = v.tasksA.as<TaskA>();
+    L.nTasksA = v.nTasksA;
+    L.maxRA = v.maxRA;
+    L.itemsA = v.itemsA.as<PanelRef>();
+    L.reduce = v.reduce.as<ReduceDesc>();
+    L.nReduce = v.nReduce;
+    L.tasksB = v.tasksB.as<TaskB>();
+    for (int r = 0; r < kRowTilesMax; ++r) L.groupB[r] = v.groupB[r];
+    L.itemsB = v.itemsB.as<PanelRef>();
+    return L;
+}
+
+Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                     bool tangent, int op_index)
+{
+    Segment g;
+    g.ne = op.ne;
+    g.ldx = ldx;
+    g.ldy = ldy;
+    g.X = X;
+    g.Y = Y;
+    g.xslot = op.d_xslot.as<int64_t>();
+    g.xloc = op.d_xloc.as<int32_t>();
+    g.self = v.self_separate ? op.d_self.as<double>() : nullptr;
+    g.D = (tangent && op.has_D) ? op.d_D.as<double>() : nullptr;
+    g.mask = (tangent && op.has_mask) ? op.d_mask.as<uint8_t>() : nullptr;
+    g.op = op_index;
+    g.tangent = tangent ? 1 : 0;
+    return g;
+}
+
+template <class NT, class FT, class ACC>
+static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg1, int nseg,
+                     int64_t max_ne, hipStream_t s, hipEvent_t* ev)
+{
+    typedef typename AccScalar<ACC>::type S;
     auto mark = [&](int i) {
         if (ev) HM_CHECK_HIP(hipEventRecord(ev[i], s));
     };
-    typedef typename AccScalar<ACC>::type S;
-    const int64_t ne = op.ne;
-    const uint8_t* mask = (tangent && op.has_mask) ? op.d_mask.as<uint8_t>() : nullptr;
-    const bool sep = !v.far_is_near();
-    FT* xfhi = sep ? v.xf_far_hi.as<FT>() : nullptr;
-    FT* xflo = (sep && v.far_prec == HM_BF16) ? v.xf_far_lo.as<FT>() : nullptr;
     mark(0);
     {
-        int64_t n = ne * kNrhs;
-        hipLaunchKernelGGL((k_gather<NT, FT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ne, nrhs, X, ldx,
-                           mask, op.d_xslot.as<int64_t>(), op.d_xloc.as<int32_t>(), v.xf_near.as<NT>(), xfhi, xflo);
+        const unsigned gx = (unsigned)((max_ne * kNrhs + 255) / 256);
+        if (nseg == 1 && seg1)
+            hipLaunchKernelGGL((k_gather1<NT, FT>), dim3(gx), dim3(256), 0, s, *seg1, L.bases, nrhs);
+        else
+            hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
     }
-    const FT* xa_hi = sep ? xfhi : reinterpret_cast<const FT*>(v.xf_near.get());
-    const FT* xa_lo = xflo;
     mark(1);
-    if (v.nTasksA > 0) {
+    if (L.nTasksA > 0) {
         // one launch sized for the largest rank; smaller ranks leave tiles empty
-        const int R = v.maxRA, count = v.nTasksA;
-        const TaskA* ta = v.tasksA.as<TaskA>();
-        FT* tlo = v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr;
-        switch (R) {
+        const unsigned grid = (unsigned)((L.nTasksA + 3) / 4);
+        switch (L.maxRA) {
 #define HM_CASE(RR)                                                                                              \
     case RR:                                                                                                     \
-        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3((count + 3) / 4), dim3(256), 0, s, ta, count,          \
-                           v.itemsA.as<PanelRef>(), v.far_a.as<FT>(), xa_hi, xa_lo, v.tpart.as<S>(),            \
-                           v.tf_hi.as<FT>(), tlo);                                                                \
+        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksA, L.nTasksA, L.itemsA,  \
+                           L.bases);                                                                             \
         break;
             HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
             HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
@@ -501,22 +545,19 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
         }
     }
     mark(2);
-    if (v.nReduce > 0)
-        hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(v.nReduce), dim3(256), 0, s, v.reduce.as<ReduceDesc>(),
-                           v.tpart.as<S>(), v.tf_hi.as<FT>(), v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr);
+    if (L.nReduce > 0)
+        hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(L.nReduce), dim3(256), 0, s, L.reduce, L.bases);
     mark(3);
     for (int R = 1; R <= kRowTilesMax; ++R) {
-        const int begin = v.groupB[R - 1].first, count = v.groupB[R - 1].second;
+        const int begin = L.groupB[R - 1].first, count = L.groupB[R - 1].second;
         if (count == 0) continue;
-        const int grid = (int)round_up(count, 8);
-        const FT* tlo = v.far_prec == HM_BF16 ? v.tf_lo.as<FT>() : nullptr;
-        const TaskB* tb = v.tasksB.as<TaskB>() + begin;
+        const unsigned grid = (unsigned)round_up(count, 8);
+        const TaskB* tb = L.tasksB + begin;
         switch (R) {
 #define HM_CASE(RR)                                                                                            \
     case RR:                                                                                                   \
-        hipLaunchKernelGGL((k_phaseB<RR, NT, FT, ACC>), dim3(grid), dim3(256), 0, s, tb, count,                \
-                           v.itemsB.as<PanelRef>(), v.near_a.as<NT>(), v.far_a.as<FT>(), v.xf_near.as<NT>(),   \
-                           v.tf_hi.as<FT>(), tlo, v.y.as<S>());                                                 \
+        hipLaunchKernelGGL((k_phaseB<RR, NT, FT, ACC>), dim3(grid), dim3(256), 0, s, tb, count, L.itemsB,      \
+                           L.bases);                                                                           \
         break;
             HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
             HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
@@ -526,14 +567,26 @@ static void apply_t(const Op& op, const Variant& v, int nrhs, const double* X, i
     }
     mark(4);
     {
-        int64_t n = ne * nrhs;
-        const double* Dt = (tangent && op.has_D) ? op.d_D.as<double>() : nullptr;
-        hipLaunchKernelGGL((k_scatter<S>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ne, nrhs, v.y.as<S>(),
-                           op.d_xslot.as<int64_t>(), op.d_xloc.as<int32_t>(), X, ldx, Y, ldy,
-                           v.self_separate ? op.d_self.as<double>() : nullptr, Dt, mask, tangent ? 1 : 0);
+        const unsigned gx = (unsigned)((max_ne * nrhs + 255) / 256);
+        if (nseg == 1 && seg1)
+            hipLaunchKernelGGL((k_scatter1<S>), dim3(gx), dim3(256), 0, s, *seg1, L.bases, nrhs);
+        else
+            hipLaunchKernelGGL((k_scatterN<S>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
     }
     mark(5);
     HM_CHECK_HIP(hipGetLastError());
+}
+
+void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg1, int nseg,
+                    int64_t max_ne, hipStream_t s, hipEvent_t* ev)
+{
+    HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
+    if (L.near_prec == HM_F64)
+        launch_t<double, double, d4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+    else if (L.far_prec == HM_F32)
+        launch_t<float, float, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+    else
+        launch_t<float, uint16_t, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
 }
 
 void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -542,12 +595,8 @@ void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ld
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
     HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(X && Y, HM_EINVAL, "null vector pointer");
-    if (v.near_prec == HM_F64)
-        apply_t<double, double, d4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
-    else if (v.far_prec == HM_F32)
-        apply_t<float, float, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
-    else
-        apply_t<float, uint16_t, f4>(op, v, nrhs, X, ldx, Y, ldy, tangent, s, ev);
+    const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0);
+    launch_product(launch_set(v), nrhs, nullptr, &g, 1, op.ne, s, ev);
 }
 
 // ------------------------------------------------------------------

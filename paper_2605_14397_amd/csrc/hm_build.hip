@@ -556,42 +556,24 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     pack_dispatch(v.far_prec, job, d_fac, v.far_a.get(), s);
     v.bytes_far = far_elems * prec_bytes(v.far_prec);
 
-    // ---- T chunks and phase-A tasks ----
-    std::vector<int64_t> t_off(op.lr.size(), 0);
-    int64_t tfrag = 0, tpart = 0;
-    std::vector<TaskA> ta;
-    std::vector<PanelRef> ia;
-    std::vector<ReduceDesc> red;
-    const int kLeavesPerTaskA = 8;
+    // ---- T chunks ----
+    v.t_off.assign(op.lr.size(), 0);
+    v.vslices.assign(op.lr.size(), {});
+    int64_t tfrag = 0;
     for (size_t b = 0; b < op.lr.size(); ++b) {
-        const LowRank& L = op.lr[b];
-        if (L.rank == 0) continue;
-        t_off[b] = tfrag;
-        tfrag += round_up(L.rank, kChunkAlign) * kNrhs;
-        const int64_t slot = round_up(L.rank, 16) * kNrhs;
-        ReduceDesc rd{tpart, t_off[b], 0, L.rank};
-        const auto& vs = vslices[b];
-        const bool direct = vs.size() <= (size_t)kLeavesPerTaskA;
-        for (size_t q0 = 0; q0 < vs.size(); q0 += kLeavesPerTaskA) {
-            TaskA t{direct ? 0 : tpart, t_off[b], L.rank, (int32_t)ia.size(), 0, direct ? 1 : 0};
-            for (size_t q = q0; q < std::min(vs.size(), q0 + kLeavesPerTaskA); ++q) {
-                const Cluster& c = p.nodes[p.leaves[vs[q].leaf]];
-                ia.push_back(PanelRef{vs[q].off, op.leaf_xoff[vs[q].leaf] * kNrhs, L.rank, 3 * (int32_t)c.size(), 1, 0});
-                t.n_items++;
-            }
-            ta.push_back(t);
-            if (!direct) {
-                tpart += slot;
-                rd.n_slots++;
-            }
-        }
-        if (!direct) red.push_back(rd);
+        if (op.lr[b].rank == 0) continue;
+        v.t_off[b] = tfrag;
+        tfrag += round_up(op.lr[b].rank, kChunkAlign) * kNrhs;
+        for (const Slice& sl : vslices[b]) v.vslices[b].push_back({sl.off, sl.leaf});
     }
+    const std::vector<int64_t>& t_off = v.t_off;
     // ---- phase-B tasks: one per target leaf ----
     std::vector<std::vector<int>> dense_by_leaf(nleaf);
     for (size_t b = 0; b < p.dense.size(); ++b) dense_by_leaf[p.nodes[p.dense[b].first].leaf_id].push_back((int)b);
-    std::vector<TaskB> tb;
-    std::vector<PanelRef> ib;
+    std::vector<TaskB>& tb = v.hTasksB;
+    std::vector<PanelRef>& ib = v.hItemsB;
+    tb.clear();
+    ib.clear();
     for (int lf = 0; lf < nleaf; ++lf) {
         const Cluster& c = p.nodes[p.leaves[lf]];
         TaskB t{op.leaf_xoff[lf], 3 * (int32_t)c.size(), (int32_t)ib.size(), 0, 0};
@@ -616,26 +598,9 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         if (v.groupB[R - 1].second == 0) v.groupB[R - 1].first = (int)q;
         v.groupB[R - 1].second++;
     }
-    // phase-A tasks: longest first so the tail of the launch is short
-    std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
-        return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
-    });
-    v.maxRA = 1;
-    for (const TaskA& t : ta) {
-        const int R = (t.rows + 15) / 16;
-        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
-        v.maxRA = std::max(v.maxRA, R);
-    }
-    upload(v.tasksB, tb, s);
-    upload(v.itemsB, ib, s);
-    upload(v.tasksA, ta, s);
-    upload(v.itemsA, ia, s);
-    upload(v.reduce, red, s);
     v.nTasksB = (int)tb.size();
-    v.nTasksA = (int)ta.size();
-    v.nReduce = (int)red.size();
-    v.tpart_elems = tpart;
     v.tfrag_elems = tfrag;
+    build_tasksA(op, v, v.leavesPerTaskA);
     // ---- workspaces ----
     const int64_t xel = op.xtot * kNrhs;
     v.xf_near.alloc(xel * prec_bytes(v.near_prec));
@@ -649,7 +614,6 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         }
     }
     const int acc_bytes = v.acc_f64() ? 8 : 4;
-    v.tpart.alloc(std::max<int64_t>(1, tpart) * acc_bytes);
     v.tf_hi.alloc(std::max<int64_t>(1, tfrag) * prec_bytes(v.far_prec));
     HM_CHECK_HIP(hipMemsetAsync(v.tf_hi.get(), 0, v.tf_hi.bytes(), s));
     if (v.far_prec == HM_BF16) {
@@ -658,6 +622,91 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     }
     v.y.alloc(xel * acc_bytes);
     HM_CHECK_HIP(hipMemsetAsync(v.y.get(), 0, v.y.bytes(), s));
+    upload_tasks(v, s);
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+// Phase-A tasks: each covers at most leaves_per_task V^T sub-panels of one
+// block; a block covered by one task writes its T chunk directly, others
+// go through partial slots and the reduction.
+void build_tasksA(const Op& op, Variant& v, int leaves_per_task)
+{
+    HM_REQUIRE(leaves_per_task >= 1, HM_EINVAL, "leaves per phase-A task must be positive");
+    const Plan& p = op.plan;
+    v.leavesPerTaskA = leaves_per_task;
+    std::vector<TaskA>& ta = v.hTasksA;
+    std::vector<PanelRef>& ia = v.hItemsA;
+    std::vector<ReduceDesc>& red = v.hReduce;
+    ta.clear();
+    ia.clear();
+    red.clear();
+    int64_t tpart = 0;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        if (L.rank == 0) continue;
+        const int64_t slot = round_up(L.rank, 16) * kNrhs;
+        ReduceDesc rd{tpart, v.t_off[b], 0, L.rank, 0, 0};
+        const auto& vs = v.vslices[b];
+        const bool direct = vs.size() <= (size_t)leaves_per_task;
+        for (size_t q0 = 0; q0 < vs.size(); q0 += leaves_per_task) {
+            TaskA t{direct ? 0 : tpart, v.t_off[b], L.rank, (int32_t)ia.size(), 0, direct ? 1 : 0, 0, 0};
+            for (size_t q = q0; q < std::min(vs.size(), q0 + (size_t)leaves_per_task); ++q) {
+                const Cluster& c = p.nodes[p.leaves[vs[q].second]];
+                ia.push_back(PanelRef{vs[q].first, op.leaf_xoff[vs[q].second] * kNrhs, L.rank,
+                                      3 * (int32_t)c.size(), 1, 0});
+                t.n_items++;
+            }
+            ta.push_back(t);
+            if (!direct) {
+                tpart += slot;
+                rd.n_slots++;
+            }
+        }
+        if (!direct) red.push_back(rd);
+    }
+    // longest first so the tail of the launch is short
+    std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
+        return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
+    });
+    v.maxRA = 1;
+    for (const TaskA& t : ta) {
+        const int R = (t.rows + 15) / 16;
+        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
+        v.maxRA = std::max(v.maxRA, R);
+    }
+    v.nTasksA = (int)ta.size();
+    v.nReduce = (int)red.size();
+    v.tpart_elems = tpart;
+}
+
+Bases Variant::host_bases() const
+{
+    Bases b;
+    b.nearA = near_a.get();
+    b.farA = far_a.get();
+    b.xnear = xf_near.get();
+    b.xfhi = far_is_near() ? xf_near.get() : xf_far_hi.get();
+    b.xflo = far_prec == HM_BF16 ? xf_far_lo.get() : nullptr;
+    b.thi = tf_hi.get();
+    b.tlo = far_prec == HM_BF16 ? tf_lo.get() : nullptr;
+    b.tpart = tpart.get();
+    b.y = y.get();
+    return b;
+}
+
+// Upload the task lists, size the partial-slot workspace, refresh the bases.
+void upload_tasks(Variant& v, hipStream_t s)
+{
+    upload(v.tasksB, v.hTasksB, s);
+    upload(v.itemsB, v.hItemsB, s);
+    upload(v.tasksA, v.hTasksA, s);
+    upload(v.itemsA, v.hItemsA, s);
+    upload(v.reduce, v.hReduce, s);
+    const int acc_bytes = v.acc_f64() ? 8 : 4;
+    const size_t need = (size_t)std::max<int64_t>(1, v.tpart_elems) * acc_bytes;
+    if (v.tpart.bytes() < need) v.tpart.alloc(need);
+    std::vector<Bases> b(1, v.host_bases());
+    upload(v.bases, b, s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
 }
 

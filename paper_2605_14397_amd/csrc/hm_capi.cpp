@@ -11,6 +11,10 @@ struct hm_mesh {
 struct hm_op {
     hm::Op op;
 };
+struct hm_batch {
+    hm::Batch* b = nullptr;
+    ~hm_batch() { hm::batch_destroy(b); }
+};
 
 namespace hm {
 static thread_local std::string g_last_error;
@@ -227,6 +231,52 @@ hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, vo
         hm::tangent_set(op->op, d_D, d_mask, (hipStream_t)hip_stream);
     });
 }
+
+void hm_batch_opts_default(hm_batch_opts* o)
+{
+    if (!o) return;
+    o->use_graph = 1;
+    o->autotune = 1;
+}
+
+hm_status hm_batch_create(int n_ops, hm_op* const* ops, const hm_batch_opts* opts, void* hip_stream, hm_batch** out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = nullptr;
+        HM_REQUIRE(n_ops >= 1 && ops, HM_EINVAL, "no operators");
+        hm_batch_opts o;
+        hm_batch_opts_default(&o);
+        if (opts) o = *opts;
+        std::vector<hm::Op*> v;
+        for (int i = 0; i < n_ops; ++i) {
+            HM_REQUIRE(ops[i], HM_EINVAL, "null operator " + std::to_string(i));
+            v.push_back(&ops[i]->op);
+        }
+        std::unique_ptr<hm_batch> h(new hm_batch());
+        h->b = hm::batch_create(v, o, (hipStream_t)hip_stream);
+        *out = h.release();
+    });
+}
+
+hm_status hm_batch_apply(hm_batch* batch, int nrhs, const double* const* d_X, const int64_t* ldx, double* const* d_Y,
+                         const int64_t* ldy, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(batch && batch->b, HM_EINVAL, "batch is null");
+        hm::batch_apply(*batch->b, nrhs, d_X, ldx, d_Y, ldy, (hipStream_t)hip_stream);
+    });
+}
+
+hm_status hm_batch_get_info(const hm_batch* batch, hm_batch_info* out)
+{
+    return guarded([&] {
+        HM_REQUIRE(batch && batch->b && out, HM_EINVAL, "null argument");
+        hm::batch_info(*batch->b, out);
+    });
+}
+
+void hm_batch_destroy(hm_batch* batch) { delete batch; }
 
 void hm_solve_opts_default(hm_solve_opts* o)
 {

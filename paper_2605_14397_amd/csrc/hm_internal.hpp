@@ -196,7 +196,7 @@ struct TaskB {        // one target leaf
     int64_t y_off;    // output rows start in Y (padded leaf offset)
     int32_t rows;     // 3 m
     int32_t item_begin, n_items;
-    int32_t pad;
+    int32_t op;       // operator index into the base-pointer table
 };
 
 struct TaskA {        // part of one low-rank block: T partial = sum V^T X
@@ -205,12 +205,43 @@ struct TaskA {        // part of one low-rank block: T partial = sum V^T X
     int32_t rows;     // rank k
     int32_t item_begin, n_items;
     int32_t direct;   // 1: the task covers the whole block and writes T itself
+    int32_t op;
+    int32_t pad;
 };
 
 struct ReduceDesc {   // T_b = sum of partial slots
     int64_t slot_begin;   // first partial slot (elements)
     int64_t t_off;        // T fragment chunk start (elements)
     int32_t n_slots, rank;
+    int32_t op, pad;
+};
+
+// Device buffers of one operator (one precision variant), looked up by the
+// op index of a task so that several operators can share one launch.
+struct Bases {
+    const void* nearA;   // dense-leaf panels
+    const void* farA;    // U slices and V^T sub-panels
+    void* xnear;         // X chunks, near precision
+    void* xfhi;          // X chunks read by phase A (far precision, or xnear)
+    void* xflo;          // BF16 lo part or null
+    void* thi;           // T chunks
+    void* tlo;
+    void* tpart;         // phase-A partial slots (accumulation precision)
+    void* y;             // phase-B output rows (accumulation precision)
+};
+
+// One operator's share of the gather and scatter of a product.
+struct Segment {
+    int64_t ne, ldx, ldy;
+    const double* X;
+    double* Y;
+    const int64_t* xslot;
+    const int32_t* xloc;
+    const double* self;     // FP64 self blocks or null
+    const double* D;        // tangent blocks or null
+    const uint8_t* mask;    // active mask or null
+    int32_t op;
+    int32_t tangent;
 };
 
 }  // namespace hm

@@ -22,8 +22,33 @@ struct Variant {
     DevBuf xf_near;               // X chunks in near precision
     DevBuf xf_far_hi, xf_far_lo;  // X chunks in far precision when it differs (bf16 split)
     DevBuf tpart, tf_hi, tf_lo, y;
+    DevBuf bases;                 // one Bases entry for this variant
+    // host copies of the task lists (merged by batches)
+    std::vector<TaskA> hTasksA;
+    std::vector<PanelRef> hItemsA;
+    std::vector<ReduceDesc> hReduce;
+    std::vector<TaskB> hTasksB;
+    std::vector<PanelRef> hItemsB;
+    int leavesPerTaskA = 8;
+    std::vector<std::vector<std::pair<int64_t, int>>> vslices;  // per block: (V^T sub-panel offset, source leaf)
+    std::vector<int64_t> t_off;                                 // per block: T chunk offset
     bool acc_f64() const { return near_prec == HM_F64; }
     bool far_is_near() const { return far_prec == near_prec; }
+    Bases host_bases() const;
+};
+
+// Everything one product launches: task lists (single operator or merged).
+struct LaunchSet {
+    int near_prec = HM_F64, far_prec = HM_F64;
+    const Bases* bases = nullptr;
+    const TaskA* tasksA = nullptr;
+    int nTasksA = 0, maxRA = 1;
+    const PanelRef* itemsA = nullptr;
+    const ReduceDesc* reduce = nullptr;
+    int nReduce = 0;
+    const TaskB* tasksB = nullptr;
+    std::pair<int, int> groupB[kRowTilesMax] = {};
+    const PanelRef* itemsB = nullptr;
 };
 
 struct LowRank {
@@ -67,10 +92,27 @@ void ensure_mesh_geo(Mesh& mesh);
 // ev (optional): 6 events recorded before, between and after the 5 stages
 void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
            bool tangent, hipStream_t s, hipEvent_t* ev = nullptr);
+LaunchSet launch_set(const Variant& v);
+Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                     bool tangent, int op_index);
+// gather (one segment per operator, segs on the device when nseg > 1), phases, scatter
+void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg_host, int nseg,
+                    int64_t max_ne, hipStream_t s, hipEvent_t* ev);
+// (re)build the phase-A task list of a variant with a given task size
+void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
+void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
                 int64_t ldx, hm_solve_report* rep, hipStream_t s);
+
+// batches (hm_batch.cpp)
+struct Batch;
+Batch* batch_create(const std::vector<Op*>& ops, const hm_batch_opts& o, hipStream_t s);
+void batch_apply(Batch& b, int nrhs, const double* const* X, const int64_t* ldx, double* const* Y, const int64_t* ldy,
+                 hipStream_t s);
+void batch_info(const Batch& b, hm_batch_info* out);
+void batch_destroy(Batch* b);
 
 }  // namespace hm

@@ -60,8 +60,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched"], default="primary",
-                    help="batched: 64 independent faults in merged, graph-captured launches")
+    ap.add_argument("--form", choices=["primary", "batched", "copy"], default="primary",
+                    help="batched: 64 independent faults in merged, graph-captured launches; "
+                         "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -78,6 +79,22 @@ def main():
     torch.cuda.set_device(0)
     if args.form == "batched":
         bench_batched(args)
+        return
+    if args.form == "copy":
+        src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
+                          "ms": round(ms, 4), "gbs_read_plus_write": round(2 * src.numel() * 4 / ms / 1e6, 1)}))
         return
     m = square_fault(256)
     n = m.ndof

@@ -410,6 +410,19 @@ __global__ void k_extract_self(const DenseDesc* __restrict__ descs, const int* _
         for (int c = 0; c < 3; ++c) self[e * 9 + 3 * a + c] = dense[D.out_off + (3 * (int64_t)i + a) * ld + 3 * i + c];
 }
 
+// Copy each block's ACA factors (rank k) from its workspace slot to the
+// compact FP64 store: one launch per ACA batch instead of one copy per block.
+struct CompactDesc {
+    int64_t src, dst, len;  // doubles
+};
+
+__global__ void k_compact(const CompactDesc* __restrict__ d, const double* __restrict__ ws, double* __restrict__ out)
+{
+    const CompactDesc D = d[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.len; i += (int64_t)gridDim.x * blockDim.x)
+        out[D.dst + i] = ws[D.src + i];
+}
+
 // ------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------
@@ -897,25 +910,31 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         }
         batch_fac.emplace_back(std::max<int64_t>(1, csz) * sizeof(double));
         int64_t c = 0;
+        std::vector<CompactDesc> cd;
         for (size_t q = 0; q < bl.size(); ++q) {
             LowRank& L = op.lr[bl[q]];
             const AcaDesc& d = bd[q];
             fac_where[bl[q]] = {(int)bi, c};
             L.u_off = c;
-            if (L.rank) {
-                HM_CHECK_HIP(hipMemcpyAsync(batch_fac.back().as<double>() + c, ws.as<double>() + d.u_off,
-                                            (size_t)L.rank * 3 * L.m * sizeof(double), hipMemcpyDeviceToDevice, s));
-            }
+            if (L.rank) cd.push_back(CompactDesc{d.u_off, c, (int64_t)L.rank * 3 * L.m});
             c += (int64_t)L.rank * 3 * L.m;
             L.v_off = c;
-            if (L.rank) {
-                HM_CHECK_HIP(hipMemcpyAsync(batch_fac.back().as<double>() + c, ws.as<double>() + d.v_off,
-                                            (size_t)L.rank * 3 * L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-            }
+            if (L.rank) cd.push_back(CompactDesc{d.v_off, c, (int64_t)L.rank * 3 * L.n});
             c += (int64_t)L.rank * 3 * L.n;
             rank_sum += L.rank;
             rmin = std::min(rmin, L.rank);
             rmax = std::max(rmax, L.rank);
+        }
+        if (!cd.empty()) {
+            DevBuf d_cd;
+            upload(d_cd, cd, s);
+            for (size_t c0 = 0; c0 < cd.size(); c0 += 65535) {
+                const unsigned nb = (unsigned)std::min<size_t>(65535, cd.size() - c0);
+                hipLaunchKernelGGL(k_compact, dim3(64, nb), dim3(256), 0, s, d_cd.as<CompactDesc>() + c0,
+                                   ws.as<double>(), batch_fac.back().as<double>());
+                HM_CHECK_HIP(hipGetLastError());
+            }
+            HM_CHECK_HIP(hipStreamSynchronize(s));
         }
         HM_CHECK_HIP(hipStreamSynchronize(s));
         fac_total += csz;

@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "copy"], default="primary",
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "copy"], default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
@@ -79,6 +79,9 @@ def main():
     torch.cuda.set_device(0)
     if args.form == "batched":
         bench_batched(args)
+        return
+    if args.form == "precision":
+        bench_precision(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -263,6 +266,71 @@ def main():
                                "sample": f"exact FP64 rows (coplanar closed form, direct summation) for {nrows} of "
                                          f"{m.ne} elements x 16 RHS in {tc:.1f} s, scaled to whole products"}
         log(f"cpu oracle: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """Three mutually intersecting 40 m disk fractures (103,968 triangles,
+    311,904 DOF), Gaussian pressure bump (peak 5 MPa, sigma 8 m) as the load:
+    GMRES to a relative residual of 1e-8 in the plain FP64 form and in the
+    precision form (FP32 near field, BF16 low-rank factors, FP64 self
+    blocks, FP64 Arnoldi, FP64 iterative refinement with the FP64 operator)."""
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads import gaussian_pressure_traction, rhs_columns, three_disks
+
+    m = three_disks()
+    n = m.ndof
+    log(f"precision form: {m.ne} triangles")
+    b = torch.as_tensor(gaussian_pressure_traction(m)[None, :], device="cuda")
+    X = torch.as_tensor(rhs_columns(n, NRHS, 3101), device="cuda")
+    Y = torch.empty_like(X)
+    out = {"metric": "GMRES time to relative residual 1e-8, precision form vs plain FP64",
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "scaling": "weak",
+           "vs_baseline": None,
+           "config": {"workload": f"three intersecting 40 m disk fractures, {m.ne} triangles, {n} DOF; "
+                                  "leaf 64, eta 2, ACA 1e-6; Gaussian pressure load 5 MPa, sigma 8 m; "
+                                  "GMRES(100), 3x3 block-Jacobi"}}
+    forms = {}
+    for name, kw, sol in (("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
+                          ("precision_bf16", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
+                           dict(refine=1, inner_rtol=1e-4))):
+        t0 = time.perf_counter()
+        op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        st = op.stats()
+        for _ in range(3):
+            op.apply(X, Y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            op.apply(X, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        t0 = time.perf_counter()
+        x, rep = op.solve(b, rtol=1e-8, restart=100, max_iter=3000, raise_on_notconv=False, **sol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        forms[name] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
+                       "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
+                       "converged": bool(rep["converged"]), "build_s": round(build_s, 2),
+                       "matvec16_ms": round(ms, 4), "matvecs_per_s": round(NRHS * 1000.0 / ms, 1),
+                       "bytes_near": st["bytes_near"], "bytes_far": st["bytes_far"],
+                       "ranks": [st["min_rank"], st["max_rank"], round(st["mean_rank"], 1)]}
+        log(f"{name}: {forms[name]}")
+        if name == "fp64_plain":
+            x_plain = x.clone()
+        else:
+            forms[name]["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(x - x_plain) / torch.linalg.norm(x_plain))
+        del op
+        torch.cuda.empty_cache()
+    out["forms"] = forms
+    out["value"] = forms["precision_bf16"]["time_to_1e-8_s"]
+    out["speedup_vs_fp64"] = round(forms["fp64_plain"]["time_to_1e-8_s"] / forms["precision_bf16"]["time_to_1e-8_s"], 3)
     print(json.dumps(out), flush=True)
 
 

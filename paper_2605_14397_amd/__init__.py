@@ -151,6 +151,13 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _ld(t):
+    """Leading dimension of a [rows, n] block of vectors (rows contiguous)."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise HMError(HM_EINVAL, "expected a 2-D tensor with contiguous rows")
+    return t.shape[1] if t.shape[0] == 1 else t.stride(0)
+
+
 def _dev_ptr(t, dtype):
     import torch
 
@@ -252,8 +259,8 @@ class Operator:
         if Y is None:
             Y = torch.empty_like(X2)
         flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
-        _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), X2.stride(0),
-                                       _dev_ptr(Y, torch.float64), Y.stride(0), flags, _stream(stream)))
+        _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), _ld(X2),
+                                       _dev_ptr(Y, torch.float64), _ld(Y), flags, _stream(stream)))
         return Y.reshape(-1) if squeeze else Y
 
     STAGES = ("gather", "phaseA", "reduceT", "phaseB", "scatter")
@@ -264,8 +271,8 @@ class Operator:
 
         flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
         ms = (ctypes.c_double * 5)()
-        _check(lib().hm_operator_apply_timed(self._h, X.shape[0], _dev_ptr(X, torch.float64), X.stride(0),
-                                             _dev_ptr(Y, torch.float64), Y.stride(0), flags, _stream(stream), ms))
+        _check(lib().hm_operator_apply_timed(self._h, X.shape[0], _dev_ptr(X, torch.float64), _ld(X),
+                                             _dev_ptr(Y, torch.float64), _ld(Y), flags, _stream(stream), ms))
         return dict(zip(self.STAGES, list(ms)))
 
     def set_tangent(self, D=None, mask=None, stream=None):
@@ -286,8 +293,8 @@ class Operator:
         X = torch.empty_like(B2)
         o = solve_opts(**opts)
         rep = SolveReport()
-        st = lib().hm_solve(self._h, ctypes.byref(o), B2.shape[0], _dev_ptr(B2, torch.float64), B2.stride(0),
-                            _dev_ptr(X, torch.float64), X.stride(0), ctypes.byref(rep), _stream(stream))
+        st = lib().hm_solve(self._h, ctypes.byref(o), B2.shape[0], _dev_ptr(B2, torch.float64), _ld(B2),
+                            _dev_ptr(X, torch.float64), _ld(X), ctypes.byref(rep), _stream(stream))
         if st != HM_OK and (st != HM_ENOTCONV or raise_on_notconv):
             _check(st)
         return (X.reshape(-1) if squeeze else X), rep.as_dict()
@@ -322,8 +329,8 @@ class Batch:
         nrhs = Xs[0].shape[0]
         xp = (ctypes.c_void_p * n)(*[_dev_ptr(x, torch.float64).value for x in Xs])
         yp = (ctypes.c_void_p * n)(*[_dev_ptr(y, torch.float64).value for y in Ys])
-        ldx = (ctypes.c_int64 * n)(*[x.stride(0) for x in Xs])
-        ldy = (ctypes.c_int64 * n)(*[y.stride(0) for y in Ys])
+        ldx = (ctypes.c_int64 * n)(*[_ld(x) for x in Xs])
+        ldy = (ctypes.c_int64 * n)(*[_ld(y) for y in Ys])
         for x in Xs:
             if x.shape[0] != nrhs:
                 raise HMError(HM_EINVAL, "all operators take the same number of columns")

@@ -769,8 +769,170 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         upload(op.d_xslot, xslot, s);
         upload(op.d_xloc, xloc, s);
     }
-    // ---- dense leaves: FP64 coefficients ----
+    // ---- low-rank blocks: ACA rounds; a block that does not converge within
+    //      max_rank is replaced by its children (leaf pairs that fail become dense) ----
     double t0 = now_ms();
+    Plan& pm = op.plan;
+    std::vector<std::pair<int, int>> cand = pm.lowrank;
+    pm.lowrank.clear();
+    op.lr.clear();
+    std::vector<DevBuf> batch_fac;
+    int64_t fac_total = 0;
+    std::vector<std::pair<int, int64_t>> fac_where;  // per op.lr entry: batch, offset
+    int64_t rank_sum = 0;
+    int rmin = 1 << 30, rmax = 0, rounds = 0;
+    const int64_t budget = (int64_t)6 << 30;  // bytes of ACA workspace per batch
+    while (!cand.empty()) {
+        HM_REQUIRE(++rounds <= 40, HM_EINTERNAL, "block splitting did not terminate");
+        std::vector<LowRank> cl(cand.size());
+        std::vector<AcaDesc> ad(cand.size());
+        for (size_t b = 0; b < cand.size(); ++b) {
+            const Cluster& t = pm.nodes[cand[b].first];
+            const Cluster& sc = pm.nodes[cand[b].second];
+            LowRank& L = cl[b];
+            L.t_node = cand[b].first;
+            L.s_node = cand[b].second;
+            L.m = t.size();
+            L.n = sc.size();
+            // first pivot: element nearest to the target cluster's mean collocation point
+            double cm[3] = {0, 0, 0};
+            for (int64_t q = t.begin; q < t.end; ++q)
+                for (int k = 0; k < 3; ++k) cm[k] += mesh.cent[3 * pm.perm[q] + k];
+            for (int k = 0; k < 3; ++k) cm[k] /= (double)t.size();
+            int first = 0;
+            double bd = 1e300;
+            for (int64_t q = t.begin; q < t.end; ++q) {
+                double d2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double dx = mesh.cent[3 * pm.perm[q] + k] - cm[k];
+                    d2 += dx * dx;
+                }
+                if (d2 < bd) {
+                    bd = d2;
+                    first = (int)(q - t.begin);
+                }
+            }
+            int kmax = (int)std::min<int64_t>(o.max_rank, 3 * std::min(L.m, L.n));
+            ad[b] = AcaDesc{t.begin, sc.begin, 0, 0, 0, 0, 0, (int32_t)L.m, (int32_t)L.n, first, kmax};
+        }
+        // large blocks first inside each batch for load balance
+        std::vector<int> order(ad.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return ad[a].m + ad[a].n > ad[b].m + ad[b].n;
+        });
+        std::vector<std::vector<int>> batches;
+        {
+            int64_t used = 0;
+            std::vector<int> cur;
+            for (int b : order) {
+                int64_t need = 8 * ((int64_t)ad[b].kmax * 3 * (ad[b].m + ad[b].n) +
+                                    9 * (int64_t)(ad[b].m + ad[b].n)) + ad[b].m + ad[b].n + 64;
+                if (!cur.empty() && used + need > budget) {
+                    batches.push_back(cur);
+                    cur.clear();
+                    used = 0;
+                }
+                cur.push_back(b);
+                used += need;
+            }
+            if (!cur.empty()) batches.push_back(cur);
+        }
+        std::vector<std::pair<int, int>> next;
+        for (const auto& bl : batches) {
+            std::vector<AcaDesc> bd(bl.size());
+            int64_t off = 0, foff = 0;
+            for (size_t q = 0; q < bl.size(); ++q) {
+                AcaDesc d = ad[bl[q]];
+                d.u_off = off;
+                off += (int64_t)d.kmax * 3 * d.m;
+                d.v_off = off;
+                off += (int64_t)d.kmax * 3 * d.n;
+                d.rrow_off = off;
+                off += 9 * (int64_t)d.n;
+                d.rcol_off = off;
+                off += 9 * (int64_t)d.m;
+                d.flag_off = foff;
+                foff += d.m + d.n;
+                bd[q] = d;
+            }
+            DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff)), d_bd, d_rank(bl.size() * sizeof(int)),
+                d_stat(bl.size() * sizeof(int));
+            upload(d_bd, bd, s);
+            hipLaunchKernelGGL(k_aca, dim3((unsigned)bl.size()), dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(),
+                               d_bd.as<AcaDesc>(), kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(),
+                               d_rank.as<int>(), d_stat.as<int>());
+            HM_CHECK_HIP(hipGetLastError());
+            std::vector<int> rk(bl.size()), st(bl.size());
+            HM_CHECK_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            HM_CHECK_HIP(hipMemcpyAsync(st.data(), d_stat.get(), st.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            HM_CHECK_HIP(hipStreamSynchronize(s));
+            // keep converged blocks (compact copy of their factors), split the others
+            int64_t csz = 0;
+            for (size_t q = 0; q < bl.size(); ++q)
+                if (st[q] == 0) csz += (int64_t)rk[q] * 3 * (cl[bl[q]].m + cl[bl[q]].n);
+            batch_fac.emplace_back(std::max<int64_t>(1, csz) * sizeof(double));
+            const int bi = (int)batch_fac.size() - 1;
+            int64_t c = 0;
+            std::vector<CompactDesc> cd;
+            for (size_t q = 0; q < bl.size(); ++q) {
+                LowRank L = cl[bl[q]];
+                if (st[q] != 0) {
+                    split_block(pm, L.t_node, L.s_node, next, pm.dense);
+                    continue;
+                }
+                const AcaDesc& d = bd[q];
+                L.rank = rk[q];
+                L.u_off = c;
+                if (L.rank) cd.push_back(CompactDesc{d.u_off, c, (int64_t)L.rank * 3 * L.m});
+                c += (int64_t)L.rank * 3 * L.m;
+                L.v_off = c;
+                if (L.rank) cd.push_back(CompactDesc{d.v_off, c, (int64_t)L.rank * 3 * L.n});
+                c += (int64_t)L.rank * 3 * L.n;
+                fac_where.push_back({bi, 0});
+                op.lr.push_back(L);
+                pm.lowrank.push_back({L.t_node, L.s_node});
+                rank_sum += L.rank;
+                rmin = std::min(rmin, L.rank);
+                rmax = std::max(rmax, L.rank);
+            }
+            if (!cd.empty()) {
+                DevBuf d_cd;
+                upload(d_cd, cd, s);
+                for (size_t c0 = 0; c0 < cd.size(); c0 += 65535) {
+                    const unsigned nb = (unsigned)std::min<size_t>(65535, cd.size() - c0);
+                    hipLaunchKernelGGL(k_compact, dim3(64, nb), dim3(256), 0, s, d_cd.as<CompactDesc>() + c0,
+                                       ws.as<double>(), batch_fac.back().as<double>());
+                    HM_CHECK_HIP(hipGetLastError());
+                }
+            }
+            HM_CHECK_HIP(hipStreamSynchronize(s));
+            fac_total += (int64_t)(batch_fac.back().bytes() / sizeof(double));
+        }
+        cand.swap(next);
+    }
+    // merge batch stores into one FP64 factor buffer (offsets rebased)
+    DevBuf d_fac(std::max<int64_t>(1, fac_total) * sizeof(double));
+    {
+        int64_t base = 0;
+        std::vector<int64_t> bbase(batch_fac.size());
+        for (size_t bi = 0; bi < batch_fac.size(); ++bi) {
+            bbase[bi] = base;
+            int64_t n = batch_fac[bi].bytes() / sizeof(double);
+            HM_CHECK_HIP(hipMemcpyAsync(d_fac.as<double>() + base, batch_fac[bi].get(), n * sizeof(double),
+                                        hipMemcpyDeviceToDevice, s));
+            base += n;
+        }
+        for (size_t b = 0; b < op.lr.size(); ++b) {
+            op.lr[b].u_off += bbase[fac_where[b].first];
+            op.lr[b].v_off += bbase[fac_where[b].first];
+        }
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        batch_fac.clear();
+    }
+    sort_blocks(pm);  // dense list may have grown; keep it in target order
+    double t1 = now_ms();
+    // ---- dense leaves: FP64 coefficients ----
     std::vector<DenseDesc> dd(p.dense.size());
     int64_t dense_total = 0, max_pairs = 0;
     std::vector<int> diag_ids;
@@ -806,159 +968,8 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         HM_CHECK_HIP(hipStreamSynchronize(s));
     }
     HM_CHECK_HIP(hipStreamSynchronize(s));
-    double t1 = now_ms();
-    // ---- low-rank blocks: ACA in batches bounded by a workspace budget ----
-    op.lr.resize(p.lowrank.size());
-    std::vector<AcaDesc> ad(p.lowrank.size());
-    for (size_t b = 0; b < p.lowrank.size(); ++b) {
-        const Cluster& t = p.nodes[p.lowrank[b].first];
-        const Cluster& sc = p.nodes[p.lowrank[b].second];
-        LowRank& L = op.lr[b];
-        L.t_node = p.lowrank[b].first;
-        L.s_node = p.lowrank[b].second;
-        L.m = t.size();
-        L.n = sc.size();
-        // first pivot: element nearest to the target cluster's mean collocation point
-        double cm[3] = {0, 0, 0};
-        for (int64_t q = t.begin; q < t.end; ++q)
-            for (int k = 0; k < 3; ++k) cm[k] += mesh.cent[3 * p.perm[q] + k];
-        for (int k = 0; k < 3; ++k) cm[k] /= (double)t.size();
-        int first = 0;
-        double bd = 1e300;
-        for (int64_t q = t.begin; q < t.end; ++q) {
-            double d2 = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                double dx = mesh.cent[3 * p.perm[q] + k] - cm[k];
-                d2 += dx * dx;
-            }
-            if (d2 < bd) {
-                bd = d2;
-                first = (int)(q - t.begin);
-            }
-        }
-        int kmax = (int)std::min<int64_t>(o.max_rank, 3 * std::min(L.m, L.n));
-        ad[b] = AcaDesc{t.begin, sc.begin, 0, 0, 0, 0, 0, (int32_t)L.m, (int32_t)L.n, first, kmax};
-    }
-    // order blocks by size inside each batch (large first) for load balance
-    std::vector<int> order(ad.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return ad[a].m + ad[a].n > ad[b].m + ad[b].n;
-    });
-    const int64_t budget = (int64_t)6 << 30;  // bytes of ACA workspace per batch
-    std::vector<std::vector<int>> batches;
-    {
-        int64_t used = 0;
-        std::vector<int> cur;
-        for (int b : order) {
-            int64_t need = 8 * ((int64_t)ad[b].kmax * 3 * (ad[b].m + ad[b].n) + 9 * (int64_t)(ad[b].m + ad[b].n)) +
-                           ad[b].m + ad[b].n + 64;
-            if (!cur.empty() && used + need > budget) {
-                batches.push_back(cur);
-                cur.clear();
-                used = 0;
-            }
-            cur.push_back(b);
-            used += need;
-        }
-        if (!cur.empty()) batches.push_back(cur);
-    }
-    // factors of every block, FP64, compact: first pass computes ranks per batch and copies
-    std::vector<DevBuf> batch_fac;
-    int64_t fac_total = 0;
-    std::vector<std::pair<int, int64_t>> fac_where(op.lr.size(), {-1, 0});  // batch, offset
-    int64_t rank_sum = 0;
-    int rmin = 1 << 30, rmax = 0;
-    for (size_t bi = 0; bi < batches.size(); ++bi) {
-        const auto& bl = batches[bi];
-        std::vector<AcaDesc> bd(bl.size());
-        int64_t off = 0, foff = 0;
-        for (size_t q = 0; q < bl.size(); ++q) {
-            AcaDesc d = ad[bl[q]];
-            d.u_off = off;
-            off += (int64_t)d.kmax * 3 * d.m;
-            d.v_off = off;
-            off += (int64_t)d.kmax * 3 * d.n;
-            d.rrow_off = off;
-            off += 9 * (int64_t)d.n;
-            d.rcol_off = off;
-            off += 9 * (int64_t)d.m;
-            d.flag_off = foff;
-            foff += d.m + d.n;
-            bd[q] = d;
-        }
-        DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff)), d_bd, d_rank(bl.size() * sizeof(int)),
-            d_stat(bl.size() * sizeof(int));
-        upload(d_bd, bd, s);
-        hipLaunchKernelGGL(k_aca, dim3((unsigned)bl.size()), dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(),
-                           d_bd.as<AcaDesc>(), kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(),
-                           d_rank.as<int>(), d_stat.as<int>());
-        HM_CHECK_HIP(hipGetLastError());
-        std::vector<int> rk(bl.size()), st(bl.size());
-        HM_CHECK_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        HM_CHECK_HIP(hipMemcpyAsync(st.data(), d_stat.get(), st.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        HM_CHECK_HIP(hipStreamSynchronize(s));
-        // compact copy of this batch's factors
-        int64_t csz = 0;
-        for (size_t q = 0; q < bl.size(); ++q) {
-            LowRank& L = op.lr[bl[q]];
-            HM_REQUIRE(st[q] == 0, HM_EINTERNAL,
-                       "ACA did not converge within max_rank for block " + std::to_string(bl[q]) + " (" +
-                           std::to_string(L.m) + " x " + std::to_string(L.n) + " elements)");
-            L.rank = rk[q];
-            csz += (int64_t)rk[q] * 3 * (L.m + L.n);
-        }
-        batch_fac.emplace_back(std::max<int64_t>(1, csz) * sizeof(double));
-        int64_t c = 0;
-        std::vector<CompactDesc> cd;
-        for (size_t q = 0; q < bl.size(); ++q) {
-            LowRank& L = op.lr[bl[q]];
-            const AcaDesc& d = bd[q];
-            fac_where[bl[q]] = {(int)bi, c};
-            L.u_off = c;
-            if (L.rank) cd.push_back(CompactDesc{d.u_off, c, (int64_t)L.rank * 3 * L.m});
-            c += (int64_t)L.rank * 3 * L.m;
-            L.v_off = c;
-            if (L.rank) cd.push_back(CompactDesc{d.v_off, c, (int64_t)L.rank * 3 * L.n});
-            c += (int64_t)L.rank * 3 * L.n;
-            rank_sum += L.rank;
-            rmin = std::min(rmin, L.rank);
-            rmax = std::max(rmax, L.rank);
-        }
-        if (!cd.empty()) {
-            DevBuf d_cd;
-            upload(d_cd, cd, s);
-            for (size_t c0 = 0; c0 < cd.size(); c0 += 65535) {
-                const unsigned nb = (unsigned)std::min<size_t>(65535, cd.size() - c0);
-                hipLaunchKernelGGL(k_compact, dim3(64, nb), dim3(256), 0, s, d_cd.as<CompactDesc>() + c0,
-                                   ws.as<double>(), batch_fac.back().as<double>());
-                HM_CHECK_HIP(hipGetLastError());
-            }
-            HM_CHECK_HIP(hipStreamSynchronize(s));
-        }
-        HM_CHECK_HIP(hipStreamSynchronize(s));
-        fac_total += csz;
-    }
-    // merge batch stores into one FP64 factor buffer (offsets rebased)
-    DevBuf d_fac(std::max<int64_t>(1, fac_total) * sizeof(double));
-    {
-        int64_t base = 0;
-        std::vector<int64_t> bbase(batch_fac.size());
-        for (size_t bi = 0; bi < batch_fac.size(); ++bi) {
-            bbase[bi] = base;
-            int64_t n = batch_fac[bi].bytes() / sizeof(double);
-            HM_CHECK_HIP(hipMemcpyAsync(d_fac.as<double>() + base, batch_fac[bi].get(), n * sizeof(double),
-                                        hipMemcpyDeviceToDevice, s));
-            base += n;
-        }
-        for (size_t b = 0; b < op.lr.size(); ++b) {
-            op.lr[b].u_off += bbase[fac_where[b].first];
-            op.lr[b].v_off += bbase[fac_where[b].first];
-        }
-        HM_CHECK_HIP(hipStreamSynchronize(s));
-        batch_fac.clear();
-    }
     double t2 = now_ms();
+
     // ---- pack variants ----
     op.main.near_prec = o.near_prec;
     op.main.far_prec = o.far_prec;
@@ -994,8 +1005,8 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     st.mean_rank = op.lr.empty() ? 0.0 : (double)rank_sum / (double)op.lr.size();
     st.near_prec = o.near_prec;
     st.far_prec = o.far_prec;
-    st.coef_ms = t1 - t0;
-    st.aca_ms = t2 - t1;
+    st.coef_ms = t2 - t1;
+    st.aca_ms = t1 - t0;
     st.pack_ms = t3 - t2;
     st.build_ms = t3 - t_start;
     int64_t maxleaf = 0;

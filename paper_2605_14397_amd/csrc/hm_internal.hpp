@@ -133,6 +133,10 @@ struct Plan {
 };
 
 Plan make_plan(const Mesh& m, int leaf_size, double eta);
+// blocks replacing an admissible pair whose compression failed (children, same rules)
+void split_block(Plan& p, int t, int s, std::vector<std::pair<int, int>>& lowrank,
+                 std::vector<std::pair<int, int>>& dense);
+void sort_blocks(Plan& p);
 
 // ------------------------------------------------------------------
 // panel layout shared by pack and apply kernels

@@ -155,6 +155,50 @@ struct Builder {
 
 }  // namespace
 
+// Replace the (admissible) pair (t, s) by the blocks of its children,
+// chosen with the same rules as the initial block tree.
+void split_block(Plan& p, int t, int s, std::vector<std::pair<int, int>>& lowrank,
+                 std::vector<std::pair<int, int>>& dense)
+{
+    const Cluster& a = p.nodes[t];
+    const Cluster& b = p.nodes[s];
+    std::vector<std::pair<int, int>> kids;
+    if (a.is_leaf() && b.is_leaf()) {
+        dense.emplace_back(t, s);
+        return;
+    } else if (a.is_leaf()) {
+        kids = {{t, b.child[0]}, {t, b.child[1]}};
+    } else if (b.is_leaf()) {
+        kids = {{a.child[0], s}, {a.child[1], s}};
+    } else {
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) kids.emplace_back(a.child[i], b.child[j]);
+    }
+    for (auto& k : kids) {
+        const Cluster& ka = p.nodes[k.first];
+        const Cluster& kb = p.nodes[k.second];
+        double d = Builder::dist(ka, kb);
+        if (d > 0.0 && std::fmin(Builder::diam(ka), Builder::diam(kb)) <= p.eta * d)
+            lowrank.push_back(k);
+        else if (ka.is_leaf() && kb.is_leaf())
+            dense.push_back(k);
+        else
+            split_block(p, k.first, k.second, lowrank, dense);
+    }
+}
+
+void sort_blocks(Plan& p)
+{
+    auto by_target = [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+        const Cluster &a = p.nodes[x.first], &b = p.nodes[y.first];
+        if (a.begin != b.begin) return a.begin < b.begin;
+        if (a.end != b.end) return a.end > b.end;
+        return p.nodes[x.second].begin < p.nodes[y.second].begin;
+    };
+    std::sort(p.dense.begin(), p.dense.end(), by_target);
+    std::sort(p.lowrank.begin(), p.lowrank.end(), by_target);
+}
+
 Plan make_plan(const Mesh& m, int leaf_size, double eta)
 {
     HM_REQUIRE(leaf_size >= 1 && leaf_size <= 64, HM_EINVAL, "leaf_size must be in [1, 64]");
@@ -171,14 +215,7 @@ Plan make_plan(const Mesh& m, int leaf_size, double eta)
     b.blocks(0, 0);
     p.iperm.resize(m.ne);
     for (int64_t q = 0; q < m.ne; ++q) p.iperm[p.perm[q]] = q;
-    auto by_target = [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-        const Cluster &a = p.nodes[x.first], &b = p.nodes[y.first];
-        if (a.begin != b.begin) return a.begin < b.begin;
-        if (a.end != b.end) return a.end > b.end;
-        return p.nodes[x.second].begin < p.nodes[y.second].begin;
-    };
-    std::sort(p.dense.begin(), p.dense.end(), by_target);
-    std::sort(p.lowrank.begin(), p.lowrank.end(), by_target);
+    sort_blocks(p);
     return p;
 }
 

@@ -24,4 +24,6 @@ from .meshes import (  # noqa: F401
     rhs_columns,
     penny_active_mask,
     gaussian_pressure_traction,
+    tangent_state,
+    tangent_rhs,
 )

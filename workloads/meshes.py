@@ -396,3 +396,70 @@ def gaussian_pressure_traction(mesh: Mesh, peak: float = 5e6, sigma: float = 8.0
     t = np.zeros((mesh.ne, 3))
     t[:, 2] = -p
     return t.reshape(-1)
+
+
+def tangent_state(mesh: Mesh, k: int, n_states: int = 20, young: float = 30e9, nu: float = 0.25,
+                  rho: float = 2700.0, friction: float = 0.6, dilatancy: float = 0.0,
+                  injection=(20.0, 0.0, 0.0), rmax: float = 60.0, seed: int = 5001) -> np.ndarray:
+    """Synthetic tangent state k of an injection sequence on a multi-part mesh.
+
+    Returns D [ne, 3, 3] = eta/dt + C^ep in each element's local frame
+    (s1, s2, n), the block-diagonal part of the mechanical Jacobian
+    A11 = E - eta/dt - C^ep (paper Sec. 3.1.1).  Inside a front of radius
+    rmax * sqrt((k + 1) / n_states) around the injection point, elements of
+    the first part (the hydraulic fracture) are open (C^ep = 0) and elements
+    of the other parts (the fault) have yielded in Coulomb friction along
+    s1: C^ep = C - (C N)(gradF^T C) / (gradF^T C N) with gradF = s1 + f n,
+    N = s1 + psi n (paper Sec. 2.2).  Elsewhere elements are intact,
+    C = diag(Ks, Ks, Kn) with Ks = Kn = E' / h.  The quasi-dynamic term is
+    eta = (1/2) diag(G/cs, G/cs, G/cp) (paper Sec. 3.1) over a seeded time
+    step 10^U(-1, 2) s.
+    """
+    rng = np.random.default_rng(seed + k)
+    G = young / (2.0 * (1.0 + nu))
+    K = young / (3.0 * (1.0 - 2.0 * nu))
+    Ep = young / (1.0 - nu * nu)
+    cs, cp = np.sqrt(G / rho), np.sqrt((K + 4.0 * G / 3.0) / rho)
+    dt = 10.0 ** rng.uniform(-1.0, 2.0)
+    eta = 0.5 * np.array([G / cs, G / cs, G / cp])
+    x = mesh.vertex_means()
+    v = mesh.xyz[mesh.conn]
+    if mesh.nvpe == 3:
+        area = 0.5 * np.linalg.norm(np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), axis=1)
+    else:
+        area = np.linalg.norm(v[:, 1] - v[:, 0], axis=1) * np.linalg.norm(v[:, 3] - v[:, 0], axis=1)
+    h = np.sqrt(area)
+    kstiff = Ep / h
+    radius = rmax * np.sqrt((k + 1.0) / n_states)
+    inside = np.linalg.norm(x - np.asarray(injection), axis=1) <= radius
+    parts = mesh.meta.get("parts", [(0, mesh.ne)])
+    first = np.zeros(mesh.ne, dtype=bool)
+    first[parts[0][0]:parts[0][0] + parts[0][1]] = True
+    D = np.zeros((mesh.ne, 3, 3))
+    D[:, [0, 1, 2], [0, 1, 2]] = kstiff[:, None]                 # intact
+    D[inside & first] = 0.0                                      # open
+    yielded = inside & ~first
+    # with C = K I: C^ep = K (I - N gradF^T / (gradF . N)), N = (1, 0, psi), gradF = (1, 0, f)
+    Nv = np.array([1.0, 0.0, dilatancy])
+    gF = np.array([1.0, 0.0, friction])
+    Cy = np.eye(3) - np.outer(Nv, gF) / (gF @ Nv)
+    D[yielded] = kstiff[yielded, None, None] * Cy[None]
+    D[:, [0, 1, 2], [0, 1, 2]] += eta[None, :] / dt
+    return D
+
+
+def tangent_rhs(mesh: Mesh, nrhs: int, seed: int, scale: float = 1e6) -> np.ndarray:
+    """Right-hand sides for tangent solves: even columns seeded N(0, 1)
+    tractions, odd columns normal pressure increments (Gaussian bumps of
+    seeded centre and width on the normal component only).  [nrhs, 3 ne]."""
+    rng = np.random.default_rng(seed)
+    x = mesh.vertex_means()
+    out = np.zeros((nrhs, mesh.ne, 3))
+    for c in range(nrhs):
+        if c % 2 == 0:
+            out[c] = rng.standard_normal((mesh.ne, 3))
+        else:
+            x0 = x[rng.integers(mesh.ne)]
+            w = rng.uniform(3.0, 15.0)
+            out[c, :, 2] = -np.exp(-np.sum((x - x0) ** 2, axis=1) / (2.0 * w * w))
+    return scale * out.reshape(nrhs, -1)

@@ -264,13 +264,21 @@ void hm_batch_destroy(hm_batch* batch);
 /* ------------------------------------------------------------------ */
 /* Krylov solve of the tangent system                                   */
 /* ------------------------------------------------------------------ */
-enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2 };
+enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3 };
+
+/* why a solve asked for HM_PC_LEARNED ran with HM_PC_BLOCK3 */
+enum {
+    HM_FALLBACK_NONE = 0,
+    HM_FALLBACK_NOT_ATTACHED = 1,  /* no correction attached for the current tangent */
+    HM_FALLBACK_NONFINITE = 2,     /* a NaN/Inf reached the Arnoldi process or the residual */
+    HM_FALLBACK_NOT_CONVERGED = 3  /* the learned solve missed rtol within max_iter */
+};
 
 typedef struct {
     int restart;        /* GMRES(m) restart length, 1..256; default 50 */
     int max_iter;       /* total inner iterations per right-hand side; default 1000 */
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (FP64); default 1e-8 */
-    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3; default BLOCK3 */
+    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED; default BLOCK3 */
     int refine;         /* 1: FP64 iterative refinement around a low-precision inner solve */
     double inner_rtol;  /* inner tolerance when refine = 1; default 1e-4 */
     int max_refine;     /* refinement sweeps; default 20 */
@@ -286,6 +294,9 @@ typedef struct {
     double solve_ms;
     int n_history;            /* entries written to history (<= 1024) */
     double history[1024];     /* max-over-columns relative residual after each inner iteration */
+    int precond_used;         /* preconditioner of the solve that produced X */
+    int fallback;             /* HM_FALLBACK_* */
+    int discarded_iterations; /* iterations of a learned attempt that was replaced by the fallback */
 } hm_solve_report;
 
 /*
@@ -297,10 +308,100 @@ typedef struct {
  * the FP64 reference copy (built with keep_f64_reference) drives the
  * correction sweeps.  d_B, d_X: [nrhs][ld] float64 (device).  Synchronous.
  * Returns HM_ENOTCONV (with the best iterate in d_X and rep filled) when
- * the tolerance is not met.
+ * the tolerance is not met.  With HM_PC_LEARNED the preconditioner is
+ * block-Jacobi plus the attached learned correction (hm_learned_attach);
+ * the plain block-Jacobi is the fallback: it is used when nothing is
+ * attached, and the solve is run again with it from X = 0 when the learned
+ * attempt meets a NaN/Inf or misses rtol (rep->fallback says which).
+ * Convergence is always judged by the FP64 true residual.
  */
 hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const double* d_B, int64_t ldb,
                    double* d_X, int64_t ldx, hm_solve_report* rep, void* hip_stream);
+
+/*
+ * Z = M^-1 R with the preconditioner the solve would use (HM_PC_*) for op's
+ * current tangent: identity, point Jacobi 1/(A11)_ii, 3x3 block-Jacobi
+ * (A11)_ee^-1, or block-Jacobi plus the attached learned correction
+ * (HM_EINVAL if none is attached).  d_R, d_Z: [nrhs][ld] float64 (device),
+ * 1 <= nrhs <= 16, not aliased.  Synchronises the stream.
+ */
+hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double* d_R, int64_t ldr, double* d_Z,
+                           int64_t ldz, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned correction of the block preconditioner                       */
+/* ------------------------------------------------------------------ */
+/*
+ * The inner A11 solves (paper Sec. 3.3.1) use a cheap approximate inverse
+ * of A11 as preconditioner; the paper uses point Jacobi.  Here the 3x3
+ * block-Jacobi inverse B_e = (E_ee - D_e)^-1 gets a learned linear
+ * correction over each element's K nearest elements f (e itself first,
+ * exact search, ties by id):
+ *     (M^-1 r)_e = B_e r_e + sum_f W_ef r_f,   W_ef = (h_e / E') net(phi_ef),
+ * net a small MLP (32 -> H -> H -> 9, ReLU, FP32) of 20 dimensionless pair
+ * features phi_ef of geometry and tangent stiffness, h_e = sqrt(area_e),
+ * E' = E / (1 - nu^2); W_ef = 0 when e or f is inactive.  M^-1 is linear
+ * and fixed for a given tangent, so right-preconditioned GMRES applies.
+ * Training minimises L = (1/ns) sum_s ||M^-1 b_s - x_s||^2 / ||x_s||^2 over
+ * pairs A11 x_s = b_s with Adam (beta 0.9/0.999, eps 1e-8), all on the GPU
+ * with the library's own forward/backward kernels; loss, residuals and
+ * gradient sums are FP64 in a fixed order (deterministic).
+ *
+ * Parameter layout (float, count from hm_learned_num_params):
+ *   W1 [32][H], b1 [H], W2 [H][H], b2 [H], W3 [H][9], b3 [9],
+ *   layer output o = b[o] + sum_k in[k] W[k][o]; output 3a+b = W_ef(a, b).
+ * Feature k of pair (e, f), dimensionless (entries 20..31 are 0):
+ *   0-2 centroid offset f - e in e's frame (s1, s2, n) / h_e; 3 distance / h_e;
+ *   4 n_e.n_f; 5 s1_e.s1_f; 6 s2_e.s2_f; 7-9 diag(D_e) h_e/E';
+ *   10-12 diag(D_f) h_f/E'; 13 D_e(s1,n) h_e/E'; 14 D_f(s1,n) h_f/E';
+ *   15 D_e(n,s1) h_e/E'; 16 h_f/h_e; 17 [f = e];
+ *   18 mean of D_nn h/E' and 19 mean of (D_s1s1 + D_s2s2) h/(2E') over the
+ *   active elements of e's cluster-tree leaf.
+ * A handle is used by one thread at a time.
+ */
+typedef struct hm_learned hm_learned;
+
+/* hidden: 16, 32 or 64; neighbors: 1..64 (K); seed: initialisation
+ * (Glorot-uniform W1, W2; W3 scaled by 0.01, biases 0, so M^-1 starts
+ * next to block-Jacobi). */
+hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out);
+void hm_learned_destroy(hm_learned* net);
+hm_status hm_learned_num_params(const hm_learned* net, int64_t* n);
+/* host copies of the parameters; set also clears the Adam moments */
+hm_status hm_learned_get_params(const hm_learned* net, float* host_params, int64_t n);
+hm_status hm_learned_set_params(hm_learned* net, const float* host_params, int64_t n);
+
+/*
+ * Pairs and features of op's current tangent for K neighbours (host
+ * outputs).  *n_pairs receives the count (N * min(K, N)); the arrays are
+ * written only when cap >= that count (pass cap = 0 to query).
+ *   pe, pf [P] int32: element and neighbour (pairs of e are contiguous,
+ *   nearest first); feat [P][32] float; scale [P] double (h_e / E', or 0).
+ */
+hm_status hm_learned_features(hm_op* op, int neighbors, int64_t cap, int64_t* n_pairs, int32_t* pe, int32_t* pf,
+                              float* feat, double* scale, void* hip_stream);
+
+/*
+ * Loss L and its gradient at the current parameters for ns samples
+ * (1..16) of op's current tangent: d_B, d_X [ns][ld] float64 (device),
+ * x_s the solution of A11 x_s = b_s.  host_grad [n_params] float receives
+ * dL/dtheta; the parameters do not change.  Synchronous.
+ */
+hm_status hm_learned_loss_grad(hm_learned* net, hm_op* op, int ns, const double* d_B, int64_t ldb,
+                               const double* d_X, int64_t ldx, double* loss, float* host_grad, void* hip_stream);
+
+/*
+ * steps Adam steps (learning rate lr) on n samples of op's current tangent,
+ * `batch` (1..16) samples per step taken cyclically.  host_loss (optional,
+ * [steps]) receives the loss before each step.  Detaches op's correction.
+ */
+hm_status hm_learned_train(hm_learned* net, hm_op* op, int n, const double* d_B, int64_t ldb, const double* d_X,
+                           int64_t ldx, int steps, int batch, double lr, double* host_loss, void* hip_stream);
+
+/* Predict the W blocks for op's current tangent and attach them for
+ * HM_PC_LEARNED; hm_tangent_set detaches them.  Synchronous. */
+hm_status hm_learned_attach(hm_op* op, const hm_learned* net, void* hip_stream);
+void hm_learned_detach(hm_op* op);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCO
     0, -1, -2, -3, -4, -5, -6, -7)
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_APPLY_REFERENCE, HM_APPLY_TANGENT = 1, 2
-HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3 = 0, 1, 2
+HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED = 0, 1, 2, 3
+HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3
 
 _STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "HM_EBADMESH",
            -5: "HM_EUNSUPPORTED", -6: "HM_ENOTCONV", -7: "HM_EINTERNAL"}
@@ -34,6 +35,9 @@ EXPORTS = [
     "hm_tangent_set",
     "hm_solve_opts_default", "hm_solve", "hm_batch_opts_default", "hm_batch_create", "hm_batch_apply",
     "hm_batch_get_info", "hm_batch_destroy",
+    "hm_learned_create", "hm_learned_destroy", "hm_learned_num_params", "hm_learned_get_params",
+    "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
+    "hm_learned_attach", "hm_learned_detach", "hm_precond_apply",
 ]
 
 
@@ -72,7 +76,8 @@ class SolveOpts(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("n_history", ctypes.c_int),
-                ("history", ctypes.c_double * 1024)]
+                ("history", ctypes.c_double * 1024), ("precond_used", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("discarded_iterations", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}
@@ -130,6 +135,17 @@ def lib():
             "hm_batch_apply": ([P, I, ctypes.POINTER(P), P, ctypes.POINTER(P), P, P], I),
             "hm_batch_get_info": ([P, ctypes.POINTER(BatchInfo)], I),
             "hm_batch_destroy": ([P], None),
+            "hm_learned_create": ([I, I, ctypes.c_uint64, ctypes.POINTER(P)], I),
+            "hm_learned_destroy": ([P], None),
+            "hm_learned_num_params": ([P, ctypes.POINTER(I64)], I),
+            "hm_learned_get_params": ([P, P, I64], I),
+            "hm_learned_set_params": ([P, P, I64], I),
+            "hm_learned_features": ([P, I, I64, ctypes.POINTER(I64), P, P, P, P, P], I),
+            "hm_learned_loss_grad": ([P, P, I, P, I64, P, I64, ctypes.POINTER(D), P, P], I),
+            "hm_learned_train": ([P, P, I, P, I64, P, I64, I, I, D, P, P], I),
+            "hm_learned_attach": ([P, P, P], I),
+            "hm_learned_detach": ([P], None),
+            "hm_precond_apply": ([P, I, I, P, I64, P, I64, P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -299,6 +315,15 @@ class Operator:
             _check(st)
         return (X.reshape(-1) if squeeze else X), rep.as_dict()
 
+    def precond_apply(self, R, precond=HM_PC_BLOCK3, stream=None):
+        """Z = M^-1 R (R: CUDA float64 [nrhs, 3N]) with the solve's preconditioner."""
+        import torch
+
+        Z = torch.empty_like(R)
+        _check(lib().hm_precond_apply(self._h, precond, R.shape[0], _dev_ptr(R, torch.float64), _ld(R),
+                                      _dev_ptr(Z, torch.float64), _ld(Z), _stream(stream)))
+        return Z
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hm_op_destroy(self._h)
@@ -348,3 +373,79 @@ class Batch:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hm_batch_destroy(self._h)
             self._h = None
+
+
+class Learned:
+    """Owner of an hm_learned handle: the MLP correction of the block
+    preconditioner (hm_learned_* in the C ABI)."""
+
+    def __init__(self, hidden=64, neighbors=8, seed=0):
+        h = ctypes.c_void_p()
+        _check(lib().hm_learned_create(hidden, neighbors, seed, ctypes.byref(h)))
+        self._h = h
+        self.hidden = hidden
+        self.neighbors = neighbors
+
+    def num_params(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().hm_learned_num_params(self._h, ctypes.byref(n)))
+        return n.value
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params(), np.float32)
+        _check(lib().hm_learned_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p), out.size))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        _check(lib().hm_learned_set_params(self._h, theta.ctypes.data_as(ctypes.c_void_p), theta.size))
+
+    def loss_grad(self, op: Operator, B, X, stream=None):
+        """(loss, dL/dtheta) at the current parameters; B, X CUDA float64 [ns, 3N]."""
+        import torch
+
+        g = np.empty(self.num_params(), np.float32)
+        loss = ctypes.c_double()
+        _check(lib().hm_learned_loss_grad(self._h, op._h, B.shape[0], _dev_ptr(B, torch.float64), _ld(B),
+                                          _dev_ptr(X, torch.float64), _ld(X), ctypes.byref(loss),
+                                          g.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return loss.value, g
+
+    def train(self, op: Operator, B, X, steps, batch=16, lr=1e-3, stream=None) -> np.ndarray:
+        """Adam steps on the samples (B, X) of op's current tangent; returns the loss history."""
+        import torch
+
+        hist = np.zeros(steps)
+        _check(lib().hm_learned_train(self._h, op._h, B.shape[0], _dev_ptr(B, torch.float64), _ld(B),
+                                      _dev_ptr(X, torch.float64), _ld(X), steps, batch, lr,
+                                      hist.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return hist
+
+    def attach(self, op: Operator, stream=None):
+        """Predict the correction for op's current tangent and attach it (HM_PC_LEARNED)."""
+        _check(lib().hm_learned_attach(op._h, self._h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_learned_destroy(self._h)
+            self._h = None
+
+
+def learned_detach(op: Operator):
+    lib().hm_learned_detach(op._h)
+
+
+def learned_features(op: Operator, neighbors: int, stream=None):
+    """Pairs and features of op's current tangent: (pe, pf, feat [P, 32], scale)."""
+    n = ctypes.c_int64()
+    _check(lib().hm_learned_features(op._h, neighbors, 0, ctypes.byref(n), None, None, None, None,
+                                     _stream(stream)))
+    P = n.value
+    pe = np.empty(P, np.int32)
+    pf = np.empty(P, np.int32)
+    feat = np.empty((P, 32), np.float32)
+    scale = np.empty(P, np.float64)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().hm_learned_features(op._h, neighbors, P, ctypes.byref(n), ptr(pe), ptr(pf), ptr(feat), ptr(scale),
+                                     _stream(stream)))
+    return pe, pf, feat, scale

@@ -741,6 +741,10 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
                "an FP32 near field takes an FP32 or BF16 far field");
     HM_CHECK_HIP(hipGetDevice(&op.device));
     op.ne = mesh.ne;
+    op.e_cent = mesh.cent;
+    op.e_frame = mesh.frame;
+    op.e_h.resize(mesh.ne);
+    for (int64_t e = 0; e < mesh.ne; ++e) op.e_h[e] = std::sqrt(mesh.area[e]);
     op.plan = make_plan(mesh, o.leaf_size, o.eta);
     const Plan& p = op.plan;
     const int nleaf = (int)p.leaves.size();

@@ -15,6 +15,10 @@ struct hm_batch {
     hm::Batch* b = nullptr;
     ~hm_batch() { hm::batch_destroy(b); }
 };
+struct hm_learned {
+    hm::Learned net;
+    hm_learned(int h, int k, uint64_t seed) : net(h, k, seed) {}
+};
 
 namespace hm {
 static thread_local std::string g_last_error;
@@ -303,6 +307,107 @@ hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const d
         if (st == HM_ENOTCONV) hm::set_last_error("GMRES did not reach rtol (best iterate returned)");
     });
     return g != HM_OK ? g : st;
+}
+
+hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double* d_R, int64_t ldr, double* d_Z,
+                           int64_t ldz, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(op, HM_EINVAL, "op is null");
+        hm::precond_apply(op->op, precond, nrhs, d_R, ldr, d_Z, ldz, (hipStream_t)hip_stream);
+    });
+}
+
+hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = nullptr;
+        require_gfx950();
+        *out = new hm_learned(hidden, neighbors, seed);
+    });
+}
+
+void hm_learned_destroy(hm_learned* net) { delete net; }
+
+hm_status hm_learned_num_params(const hm_learned* net, int64_t* n)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && n, HM_EINVAL, "null argument");
+        *n = net->net.n;
+    });
+}
+
+hm_status hm_learned_get_params(const hm_learned* net, float* host_params, int64_t n)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && host_params, HM_EINVAL, "null argument");
+        HM_REQUIRE(n == net->net.n, HM_EINVAL, "parameter count mismatch");
+        HM_CHECK_HIP(hipMemcpy(host_params, net->net.params.get(), n * sizeof(float), hipMemcpyDeviceToHost));
+    });
+}
+
+hm_status hm_learned_set_params(hm_learned* net, const float* host_params, int64_t n)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && host_params, HM_EINVAL, "null argument");
+        HM_REQUIRE(n == net->net.n, HM_EINVAL, "parameter count mismatch");
+        HM_CHECK_HIP(hipMemcpy(net->net.params.get(), host_params, n * sizeof(float), hipMemcpyHostToDevice));
+        net->net.reset_moments();
+    });
+}
+
+hm_status hm_learned_features(hm_op* op, int neighbors, int64_t cap, int64_t* n_pairs, int32_t* pe, int32_t* pf,
+                              float* feat, double* scale, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(op && n_pairs, HM_EINVAL, "null argument");
+        hipStream_t s = (hipStream_t)hip_stream;
+        hm::learned_prepare(op->op, neighbors, s);
+        const hm::LearnedPairs& lp = op->op.lp;
+        *n_pairs = lp.P;
+        if (cap < lp.P || lp.P == 0) return;
+        HM_REQUIRE(pe && pf && feat && scale, HM_EINVAL, "null output array");
+        HM_CHECK_HIP(hipMemcpyAsync(pe, lp.pe.get(), lp.P * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipMemcpyAsync(pf, lp.pf.get(), lp.P * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipMemcpyAsync(feat, lp.feat.get(), lp.P * 32 * sizeof(float), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipMemcpyAsync(scale, lp.scale.get(), lp.P * sizeof(double), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+    });
+}
+
+hm_status hm_learned_loss_grad(hm_learned* net, hm_op* op, int ns, const double* d_B, int64_t ldb,
+                               const double* d_X, int64_t ldx, double* loss, float* host_grad, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && op && loss && host_grad, HM_EINVAL, "null argument");
+        hipStream_t s = (hipStream_t)hip_stream;
+        *loss = hm::learned_loss_grad(net->net, op->op, ns, d_B, ldb, d_X, ldx, s);
+        HM_CHECK_HIP(hipMemcpy(host_grad, net->net.grad.get(), net->net.n * sizeof(float), hipMemcpyDeviceToHost));
+    });
+}
+
+hm_status hm_learned_train(hm_learned* net, hm_op* op, int n, const double* d_B, int64_t ldb, const double* d_X,
+                           int64_t ldx, int steps, int batch, double lr, double* host_loss, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && op, HM_EINVAL, "null argument");
+        hm::learned_train(net->net, op->op, n, d_B, ldb, d_X, ldx, steps, batch, lr, host_loss,
+                          (hipStream_t)hip_stream);
+    });
+}
+
+hm_status hm_learned_attach(hm_op* op, const hm_learned* net, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(net && op, HM_EINVAL, "null argument");
+        hm::learned_attach(op->op, net->net, (hipStream_t)hip_stream);
+    });
+}
+
+void hm_learned_detach(hm_op* op)
+{
+    if (op) op->op.lp.attached = false;
 }
 
 }  // extern "C"

@@ -58,6 +58,30 @@ struct LowRank {
     int64_t u_off = 0, v_off = 0;  // compact FP64 factors: U [rank][3m], V [rank][3n]
 };
 
+// Learned correction of the block preconditioner: network parameters and
+// Adam moments (FP32, device), see hm_learned.hip for the layout.
+struct Learned {
+    int H = 64, K = 8;      // hidden width, neighbours per element (self included)
+    int64_t n = 0;          // parameter count
+    int64_t step = 0;       // Adam steps taken
+    DevBuf params, m, v, grad;
+    DevBuf ws;              // training workspace (activations, residuals, partial sums)
+    Learned(int hidden, int neighbors, uint64_t seed);
+    void reset_moments();
+};
+
+// Per-operator pairs (element e, neighbour f), their features for the
+// current tangent, and the predicted 3x3 blocks W_ef (FP32).
+struct LearnedPairs {
+    int K = 0;              // neighbours the pair list was built for (0: none)
+    int64_t P = 0;
+    DevBuf pe, pf, off;     // int32 [P], int32 [P], int64 [N + 1] (pairs of e are off[e] .. off[e+1])
+    DevBuf feat, scale;     // float [P][32], double [P] (h_e / E', 0 when e or f is inactive)
+    bool features_current = false;
+    DevBuf W;               // float [P][9]
+    bool attached = false;
+};
+
 struct Op {
     int device = 0;
     double young = 0, nu = 0, G = 0;
@@ -75,6 +99,9 @@ struct Op {
     // tangent
     bool has_D = false, has_mask = false;
     DevBuf d_D, d_mask, d_pc_block, d_pc_diag;
+    // element geometry kept for the learned preconditioner (original order)
+    std::vector<double> e_cent, e_frame, e_h;  // [N][3], [N][9], [N] (sqrt of area)
+    LearnedPairs lp;
     // solver workspaces (allocated on first solve)
     DevBuf solve_ws;
     size_t solve_ws_bytes = 0;
@@ -106,6 +133,17 @@ void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
                 int64_t ldx, hm_solve_report* rep, hipStream_t s);
+void precond_apply(const Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz,
+                   hipStream_t s);
+
+// learned preconditioner (hm_learned.hip)
+void learned_prepare(Op& op, int K, hipStream_t s);
+double learned_loss_grad(Learned& L, Op& op, int ns, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                         hipStream_t s);
+void learned_train(Learned& L, Op& op, int n, const double* B, int64_t ldb, const double* X, int64_t ldx, int steps,
+                   int batch, double lr, double* hist, hipStream_t s);
+void learned_attach(Op& op, const Learned& L, hipStream_t s);
+void learned_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
 
 // batches (hm_batch.cpp)
 struct Batch;

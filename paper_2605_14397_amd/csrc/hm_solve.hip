@@ -172,6 +172,10 @@ struct Krylov {
     }
     void precond(const double* v, double* z)
     {
+        if (pc == HM_PC_LEARNED) {
+            learned_apply(op, nrhs, v, n, z, n, s);
+            return;
+        }
         hipLaunchKernelGGL(k_precond, dim3(g1(op.ne * nrhs)), dim3(256), 0, s, pc, op.ne, nrhs, v, n, z, n,
                            op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
     }
@@ -229,6 +233,7 @@ struct Ls {
 struct GmresResult {
     int iterations = 0;
     bool converged = false;
+    bool nonfinite = false;  // a NaN or infinity reached the Arnoldi process
 };
 
 // Solve A x = b for every column with the operator variant v; x starts at 0.
@@ -262,6 +267,9 @@ GmresResult gmres(Krylov& K, const Variant& v, const double* b, double* x, const
         K.dots(K.R, 1, K.R);
         K.fetch(1);
         bool all = true;
+        for (int c = 0; c < nrhs; ++c)
+            if (!std::isfinite(K.h_host[c])) res.nonfinite = true;
+        if (res.nonfinite) break;
         for (int c = 0; c < nrhs; ++c) {
             double beta = std::sqrt(std::max(0.0, K.h_host[c]));
             conv[c] = beta <= tol * bnorm[c];
@@ -298,6 +306,15 @@ GmresResult gmres(Krylov& K, const Variant& v, const double* b, double* x, const
             K.fetch(1);
             double worst = 0.0;
             bool all_done = true;
+            for (int c = 0; c < nrhs; ++c) {
+                if (!std::isfinite(K.h_host[c])) res.nonfinite = true;
+                for (int i = 0; i <= j; ++i)
+                    if (!std::isfinite(h1[(size_t)i * nrhs + c] + h2[(size_t)i * nrhs + c])) res.nonfinite = true;
+            }
+            if (res.nonfinite) {
+                res.iterations = total + 1;
+                return res;
+            }
             for (int c = 0; c < nrhs; ++c) {
                 double beta = std::sqrt(std::max(0.0, K.h_host[c]));
                 for (int i = 0; i <= j; ++i) hcol[i] = h1[(size_t)i * nrhs + c] + h2[(size_t)i * nrhs + c];
@@ -345,6 +362,24 @@ double now_ms()
 
 }  // namespace
 
+void precond_apply(const Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz,
+                   hipStream_t s)
+{
+    HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
+    HM_REQUIRE(kind >= HM_PC_NONE && kind <= HM_PC_LEARNED, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(ldr >= 3 * op.ne && ldz >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
+    HM_REQUIRE(R && Z, HM_EINVAL, "null vector pointer");
+    HM_REQUIRE(kind != HM_PC_LEARNED || op.lp.attached, HM_EINVAL, "no learned correction is attached");
+    if (kind == HM_PC_LEARNED) {
+        learned_apply(op, nrhs, R, ldr, Z, ldz, s);
+    } else {
+        hipLaunchKernelGGL(k_precond, dim3((unsigned)((op.ne * nrhs + 255) / 256)), dim3(256), 0, s, kind, op.ne,
+                           nrhs, R, ldr, Z, ldz, op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
+        HM_CHECK_HIP(hipGetLastError());
+    }
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X, int64_t ldx,
                 hm_solve_report* rep, hipStream_t s)
 {
@@ -352,7 +387,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     HM_REQUIRE(o.restart >= 1 && o.restart <= 256, HM_EINVAL, "restart must be in [1, 256]");
     HM_REQUIRE(o.max_iter >= 1, HM_EINVAL, "max_iter must be positive");
     HM_REQUIRE(o.rtol > 0.0 && o.rtol < 1.0, HM_EINVAL, "rtol must be in (0, 1)");
-    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_BLOCK3, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_LEARNED, HM_EINVAL, "unknown preconditioner");
     HM_REQUIRE(ldb >= 3 * op.ne && ldx >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(d_B && d_X, HM_EINVAL, "null vector pointer");
     HM_REQUIRE(!o.refine || op.ref || op.main.near_prec == HM_F64, HM_EINVAL,
@@ -373,7 +408,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     std::vector<double> hist;
     const Variant& ref = op.ref_variant();
     int iters = 0, sweeps = 0;
-    bool ok = false;
+    bool ok = false, nonfinite = false;
     DevBuf xbuf((size_t)nrhs * n * sizeof(double)), rbuf((size_t)nrhs * n * sizeof(double)),
         dbuf((size_t)nrhs * n * sizeof(double)), tbuf((size_t)nrhs * n * sizeof(double));
     double* X = xbuf.as<double>();
@@ -387,16 +422,27 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
         double worst = 0.0;
         for (int c = 0; c < nrhs; ++c) {
             relres[c] = std::sqrt(std::max(0.0, K.h_host[c])) / bnorm[c];
-            worst = std::max(worst, relres[c]);
+            worst = std::isnan(relres[c]) ? relres[c] : std::max(worst, relres[c]);
         }
         return worst;
     };
-    if (!o.refine) {
-        GmresResult g = gmres(K, op.main, B, X, bnorm, o.rtol, o.max_iter, hist, 1.0);
-        iters = g.iterations;
-        double r = true_residual(X, rbuf.as<double>());
-        ok = r <= o.rtol;
-    } else {
+    // one complete solve from x = 0 with preconditioner pc
+    auto attempt = [&](int pc) {
+        K.pc = pc;
+        iters = 0;
+        sweeps = 0;
+        ok = false;
+        nonfinite = false;
+        hist.clear();
+        if (!o.refine) {
+            GmresResult g = gmres(K, op.main, B, X, bnorm, o.rtol, o.max_iter, hist, 1.0);
+            iters = g.iterations;
+            nonfinite = g.nonfinite;
+            double r = true_residual(X, rbuf.as<double>());
+            nonfinite = nonfinite || !std::isfinite(r);
+            ok = !nonfinite && r <= o.rtol;
+            return;
+        }
         // FP64 iterative refinement: x += A_lp^-1 (b - A_ref x)
         HM_CHECK_HIP(hipMemsetAsync(X, 0, sizeof(double) * nrhs * n, s));
         HM_CHECK_HIP(hipMemcpyAsync(rbuf.get(), B, sizeof(double) * nrhs * n, hipMemcpyDeviceToDevice, s));
@@ -414,6 +460,10 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
             HM_CHECK_HIP(hipMemcpyAsync(K.D, rbuf.get(), sizeof(double) * nrhs * n, hipMemcpyDeviceToDevice, s));
             GmresResult g = gmres(K, op.main, K.D, dbuf.as<double>(), rn, inner, o.max_iter - iters, hist, r);
             iters += g.iterations;
+            if (g.nonfinite) {
+                nonfinite = true;
+                break;
+            }
             hipLaunchKernelGGL(k_axpby, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, X, n, 1.0, dbuf.as<double>(),
                                n, 1.0, X, n);
             ++sweeps;
@@ -421,11 +471,34 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
             HM_CHECK_HIP(hipMemcpy2DAsync(B, n * sizeof(double), d_B, ldb * sizeof(double), n * sizeof(double), nrhs,
                                           hipMemcpyDeviceToDevice, s));
             r = true_residual(X, rbuf.as<double>());
+            if (!std::isfinite(r)) {
+                nonfinite = true;
+                break;
+            }
             if (r <= o.rtol) {
                 ok = true;
                 break;
             }
         }
+        // the Krylov b slot held correction right-hand sides: restore b
+        HM_CHECK_HIP(hipMemcpy2DAsync(B, n * sizeof(double), d_B, ldb * sizeof(double), n * sizeof(double), nrhs,
+                                      hipMemcpyDeviceToDevice, s));
+    };
+    // The plain block-Jacobi preconditioner is the fallback of the learned
+    // one: used when no correction is attached for the current tangent, and
+    // run again from x = 0 when the learned solve produced a non-finite
+    // value or did not meet the FP64 residual test.
+    int pc = o.precond, fallback = HM_FALLBACK_NONE, discarded = 0;
+    if (pc == HM_PC_LEARNED && !op.lp.attached) {
+        pc = HM_PC_BLOCK3;
+        fallback = HM_FALLBACK_NOT_ATTACHED;
+    }
+    attempt(pc);
+    if (!ok && pc == HM_PC_LEARNED) {
+        fallback = nonfinite ? HM_FALLBACK_NONFINITE : HM_FALLBACK_NOT_CONVERGED;
+        discarded = iters;
+        pc = HM_PC_BLOCK3;
+        attempt(pc);
     }
     HM_CHECK_HIP(hipMemcpy2DAsync(d_X, ldx * sizeof(double), X, n * sizeof(double), n * sizeof(double), nrhs,
                                   hipMemcpyDeviceToDevice, s));
@@ -440,6 +513,9 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
         rep->rel_residual = worst;
         rep->solve_ms = now_ms() - t0;
         rep->n_history = (int)std::min<size_t>(hist.size(), 1024);
+        rep->precond_used = pc;
+        rep->fallback = fallback;
+        rep->discarded_iterations = discarded;
         for (int i = 0; i < rep->n_history; ++i) rep->history[i] = hist[i];
     }
     return ok ? HM_OK : HM_ENOTCONV;

@@ -176,7 +176,28 @@ def test_plan_rejects_bad_options():
         M.plan(16, -1.0)
 
 
-def test_structs_match_c_layout():
-    # sizes the C side writes through the pointers
-    assert ctypes.sizeof(hm.SolveReport) == 4 * 3 + 4 + 8 * 2 + 4 + 4 + 8 * 1024
-    assert ctypes.sizeof(hm.BuildOpts) == 4 + 4 + 8 + 8 + 4 * 5 + 4
+def test_structs_match_c_layout(tmp_path):
+    """Every struct the binding passes by pointer has the size and field
+    offsets that a C compiler gives the declarations in include/hmdd.h."""
+    import subprocess
+
+    pairs = [("hm_solve_report", hm.SolveReport), ("hm_solve_opts", hm.SolveOpts),
+             ("hm_build_opts", hm.BuildOpts), ("hm_op_stats", hm.OpStats), ("hm_batch_opts", hm.BatchOpts),
+             ("hm_batch_info", hm.BatchInfo), ("hm_plan_info", hm.PlanInfo)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hmdd.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in pairs:
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)

@@ -60,10 +60,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "precision", "copy"], default="primary",
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "copy"], default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
+                         "learned: trained preconditioner correction on the HF x fault tangent solves; "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
+    ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
+    ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the H-matrix path here is built and timed on a single MI355X "
@@ -82,6 +85,9 @@ def main():
         return
     if args.form == "precision":
         bench_precision(args)
+        return
+    if args.form == "learned":
+        bench_learned(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -331,6 +337,114 @@ def bench_precision(args):
     out["forms"] = forms
     out["value"] = forms["precision_bf16"]["time_to_1e-8_s"]
     out["speedup_vs_fp64"] = round(forms["fp64_plain"]["time_to_1e-8_s"] / forms["precision_bf16"]["time_to_1e-8_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned(args):
+    """Learned correction of the block preconditioner on the tangent solves
+    of a synthetic injection sequence on the HF x fault mesh (20 tangent
+    states, paper Sec. 3.1.1 / 3.3.1 shapes).
+
+    Training data: for states 0..15, 16 FP64 GMRES solves each of
+    A11 x = b with b = A11 x0 for seeded white x0 (the method's own tangent
+    solves; white solutions make the loss measure ||M^-1 A11 - I||).
+    Training: Adam, 8 samples per step, 8 steps per state per epoch.
+    Held-out states 16..19, 16 right-hand sides each (white tractions and
+    Gaussian normal-pressure bumps), GMRES(50) to a relative FP64 residual
+    of 1e-8 in four forms: FP64 operator with block-Jacobi (the plain
+    baseline), FP64 with the learned correction, and the precision form
+    (FP32 near / BF16 far, FP64 refinement) with either preconditioner."""
+    import numpy as np
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads import hf_fault_mesh, rhs_columns, tangent_rhs, tangent_state
+
+    t0 = time.perf_counter()
+    m = hf_fault_mesh(h=args.hf_h)
+    n = m.ndof
+    log(f"learned form: {m.ne} triangles ({time.perf_counter() - t0:.1f} s to mesh)")
+    cuda = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    ops = {}
+    for name, kw in (("fp64", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64)),
+                     ("precision_bf16", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1))):
+        t0 = time.perf_counter()
+        ops[name] = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        log(f"built {name} in {time.perf_counter() - t0:.1f} s")
+    op = ops["fp64"]
+    # training pairs from the method's own FP64 solves
+    t0 = time.perf_counter()
+    data = []
+    solve_its = []
+    for k in range(16):
+        op.set_tangent(cuda(tangent_state(m, k)))
+        x0 = cuda(rhs_columns(n, NRHS, 7000 + NRHS * k))
+        b = op.apply(x0, tangent=True)
+        x, rep = op.solve(b, rtol=1e-8, restart=50, max_iter=3000)
+        solve_its.append(rep["iterations"])
+        data.append((b, x))
+        log(f"training state {k}: {rep['iterations']} iterations")
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    net = hm.Learned(hidden=64, neighbors=8, seed=5)
+    t0 = time.perf_counter()
+    hist = []
+    for ep in range(args.train_epochs):
+        for k in range(16):
+            op.set_tangent(cuda(tangent_state(m, k)))
+            b, x = data[k]
+            hist.extend(net.train(op, b, x, steps=8, batch=8, lr=1e-3))
+        log(f"epoch {ep}: mean loss {np.mean(hist[-128:]):.4g}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    steps = len(hist)
+    forms = {f: {"time_s": 0.0, "iterations": [], "rel_residual": 0.0, "fallbacks": 0}
+             for f in ("fp64_block_jacobi", "fp64_learned", "precision_block_jacobi", "precision_learned")}
+    attach_s = 0.0
+    for k in range(16, 20):
+        D = cuda(tangent_state(m, k))
+        rhs = cuda(tangent_rhs(m, NRHS, 9000 + k))
+        for name, o in ops.items():
+            o.set_tangent(D)
+            t0 = time.perf_counter()
+            net.attach(o)
+            attach_s += time.perf_counter() - t0
+            sol = dict(refine=1, inner_rtol=1e-4) if name != "fp64" else {}
+            tag = "fp64" if name == "fp64" else "precision"
+            for pc, pname in ((hm.HM_PC_BLOCK3, "block_jacobi"), (hm.HM_PC_LEARNED, "learned")):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, rep = o.solve(rhs, rtol=1e-8, restart=50, max_iter=3000, precond=pc,
+                                 raise_on_notconv=False, **sol)
+                torch.cuda.synchronize()
+                f = forms[f"{tag}_{pname}"]
+                f["time_s"] += time.perf_counter() - t0
+                f["iterations"].append(rep["iterations"])
+                f["rel_residual"] = max(f["rel_residual"], rep["rel_residual"])
+                f["fallbacks"] += int(rep["fallback"] != 0)
+                f.setdefault("converged", True)
+                f["converged"] = f["converged"] and bool(rep["converged"])
+                log(f"state {k} {tag}_{pname}: {rep['iterations']} iterations, {rep['solve_ms']:.0f} ms, "
+                    f"residual {rep['rel_residual']:.2e}, fallback {rep['fallback']}")
+    for f in forms.values():
+        f["time_s"] = round(f["time_s"], 3)
+    base = forms["fp64_block_jacobi"]["time_s"]
+    out = {"metric": "GMRES time to relative residual 1e-8 on held-out tangent states, learned/precision forms "
+                     "vs plain FP64 block-Jacobi",
+           "value": forms["precision_learned"]["time_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
+           "config": {"workload": f"HF x fault, {m.ne} triangles, {n} DOF; leaf 64, eta 2, ACA 1e-6; "
+                                  "tangent states 16-19 of 20, 16 right-hand sides each; GMRES(50)",
+                      "network": "32-64-64-9 MLP, 8 neighbours", "training_states": 16,
+                      "training_samples": 16 * NRHS, "adam_steps": steps},
+           "forms": forms,
+           "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},
+           "training": {"data_s": round(data_s, 2), "data_solve_iterations": solve_its, "train_s": round(train_s, 2),
+                        "ms_per_step": round(1000 * train_s / max(1, steps), 2),
+                        "loss_first_epoch": round(float(np.mean(hist[:128])), 5),
+                        "loss_last_epoch": round(float(np.mean(hist[-128:])), 5),
+                        "attach_s_total": round(attach_s, 3)}}
     print(json.dumps(out), flush=True)
 
 

@@ -407,14 +407,15 @@ __device__ inline void gather_body(const Segment& S, const Bases& B, int nrhs)
     const int64_t e = idx - (int64_t)c * S.ne;
     const bool on = c < nrhs && (!S.mask || S.mask[e]);
     const int64_t base = S.xslot[e] * kNrhs;
-    const int q0 = S.xloc[e];
+    const int qs = S.xloc[2 * e], qn = S.xloc[2 * e + 1];
     NT* xnear = static_cast<NT*>(B.xnear);
     FT* xfhi = B.xfhi != B.xnear ? static_cast<FT*>(B.xfhi) : nullptr;
     FT* xflo = static_cast<FT*>(B.xflo);
     for (int a = 0; a < 3; ++a) {
         const double x = on ? S.X[c * S.ldx + 3 * e + a] : 0.0;
-        xnear[base + bfrag_offset(Mma<NT>::w, q0 + a, c)] = cvt<NT>(x);
-        if (xfhi) store_t<FT>(xfhi, xflo, base + bfrag_offset(Mma<FT>::w, q0 + a, c), x);
+        const int q = a < 2 ? qs + a : qn;
+        xnear[base + bfrag_offset(Mma<NT>::w, q, c)] = cvt<NT>(x);
+        if (xfhi) store_t<FT>(xfhi, xflo, base + bfrag_offset(Mma<FT>::w, q, c), x);
     }
 }
 
@@ -438,11 +439,11 @@ __device__ inline void scatter_body(const Segment& S, const Bases& B, int nrhs)
     if (idx >= S.ne * nrhs) return;
     const int c = (int)(idx / S.ne);
     const int64_t e = idx - (int64_t)c * S.ne;
-    const int64_t row = S.xslot[e] + S.xloc[e];
+    const int64_t rs = S.xslot[e] + S.xloc[2 * e], rn = S.xslot[e] + S.xloc[2 * e + 1];
     const S_t* Y = static_cast<const S_t*>(B.y);
     double y[3], x[3];
     for (int a = 0; a < 3; ++a) {
-        y[a] = (double)Y[(row + a) * kNrhs + c];
+        y[a] = (double)Y[(a < 2 ? rs + a : rn) * kNrhs + c];
         x[a] = S.X[c * S.ldx + 3 * e + a];
     }
     if (S.self)

@@ -61,24 +61,27 @@ __global__ void k_dense_coef(const ElemGeo* __restrict__ geo, const DenseDesc* _
 }
 
 // ------------------------------------------------------------------
-// adaptive cross approximation, 3x3-block partial pivoting, FP64
+// adaptive cross approximation, element-block partial pivoting, FP64
 // ------------------------------------------------------------------
-// Each step evaluates the residual of one element row (3 DOF rows) and of
-// the best element column (3 DOF columns).  The 3x3 pivot block is then
-// eliminated by up to three scalar cross steps with complete pivoting, so
-// the rank grows by 1..3 per step and the three DD components are always
-// sampled together (scalar ACA on interleaved components can stop early
-// when the normal and shear parts decouple).  Stop when the update of a
-// step has ||U_k V_k^T||_F <= tol ||S_k||_F on two consecutive steps.
+// The block approximated holds components ca .. ca + NC - 1 of every
+// element (NC = 3: the full 3x3 coupling; NC = 2 / 1: the shear / normal
+// part of a coplanar block).  Each step evaluates the residual of one
+// element row (NC DOF rows) and of the best element column (NC DOF
+// columns).  The NC x NC pivot block is then eliminated by up to NC scalar
+// cross steps with complete pivoting, so the rank grows by 1..NC per step
+// and the components of an element are always sampled together.  Stop when
+// the update of a step has ||U_k V_k^T||_F <= tol ||S_k||_F on two
+// consecutive steps.
 constexpr int kAcaThreads = 256;
 constexpr int kAcaMaxRank = 192;
 
 struct AcaDesc {
     int64_t t_begin, s_begin;    // cluster positions
-    int64_t u_off, v_off;        // workspace: U [kmax][3m], V [kmax][3n]
-    int64_t rrow_off, rcol_off;  // scratch: Rrow [3][3n], Rcol [3m][3]
+    int64_t u_off, v_off;        // workspace: U [kmax][NC m], V [kmax][NC n]
+    int64_t rrow_off, rcol_off;  // scratch: Rrow [NC][NC n], Rcol [NC m][NC]
     int64_t flag_off;            // bytes: row used [m], column used [n]
     int32_t m, n, first_row, kmax;
+    int32_t ca, pad;             // first component of the part
 };
 
 __device__ inline void wave_argmax(double& v, int& i)
@@ -149,13 +152,15 @@ __device__ void block_dots(const double* A, const double* b, int64_t L, int nq, 
     }
 }
 
+template <int NC>
 __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__ geo, const AcaDesc* __restrict__ descs,
                                                      double kG, double kN, double tol, double* __restrict__ ws,
                                                      uint8_t* __restrict__ flags, int* __restrict__ out_rank,
                                                      int* __restrict__ out_status)
 {
     const AcaDesc D = descs[blockIdx.x];
-    const int64_t m3 = 3 * (int64_t)D.m, n3 = 3 * (int64_t)D.n;
+    const int ca = D.ca;
+    const int64_t m3 = NC * (int64_t)D.m, n3 = NC * (int64_t)D.n;
     double* U = ws + D.u_off;
     double* V = ws + D.v_off;
     double* Rrow = ws + D.rrow_off;
@@ -163,11 +168,11 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
     uint8_t* rowused = flags + D.flag_off;
     uint8_t* colused = rowused + D.m;
 
-    __shared__ double s_piv[3 * kAcaMaxRank];   // U rows of the pivot element, then V rows
+    __shared__ double s_piv[NC * kAcaMaxRank];   // U rows of the pivot element, then V rows
     __shared__ double s_red[64];
     __shared__ int s_ired[8];
-    __shared__ double s_uu[3][kAcaMaxRank], s_vv[3][kAcaMaxRank];
-    __shared__ double s_P[9];
+    __shared__ double s_uu[NC][kAcaMaxRank], s_vv[NC][kAcaMaxRank];
+    __shared__ double s_P[NC * NC];
 
     for (int i = threadIdx.x; i < D.m; i += kAcaThreads) rowused[i] = 0;
     for (int j = threadIdx.x; j < D.n; j += kAcaThreads) colused[j] = 0;
@@ -178,9 +183,9 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
     double normS2 = 0.0;
     while (k + 1 <= D.kmax) {
         // ---- residual of pivot row element ipiv ----
-        for (int idx = threadIdx.x; idx < 3 * k; idx += kAcaThreads) {
+        for (int idx = threadIdx.x; idx < NC * k; idx += kAcaThreads) {
             int a = idx / k, q = idx - a * k;
-            s_piv[a * kAcaMaxRank + q] = U[(int64_t)q * m3 + 3 * ipiv + a];
+            s_piv[a * kAcaMaxRank + q] = U[(int64_t)q * m3 + NC * ipiv + a];
         }
         __syncthreads();
         double best = -1.0;
@@ -191,23 +196,26 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
             double fr[9];
             for (int t = 0; t < 9; ++t) fr[t] = R.fr[t];
             for (int j = threadIdx.x; j < D.n; j += kAcaThreads) {
-                double blk[9];
-                dd_block(x, fr, geo[D.s_begin + j], kG, kN, blk);
+                double full[9], blk[NC * NC];
+                dd_block(x, fr, geo[D.s_begin + j], kG, kN, full);
+#pragma unroll
+                for (int a = 0; a < NC; ++a)
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) blk[NC * a + b] = full[3 * (ca + a) + ca + b];
                 for (int q = 0; q < k; ++q) {
-                    const double* vq = V + (int64_t)q * n3 + 3 * j;
-                    double v0 = vq[0], v1 = vq[1], v2 = vq[2];
-                    for (int a = 0; a < 3; ++a) {
+                    const double* vq = V + (int64_t)q * n3 + NC * j;
+#pragma unroll
+                    for (int a = 0; a < NC; ++a) {
                         double ua = s_piv[a * kAcaMaxRank + q];
-                        blk[3 * a] -= ua * v0;
-                        blk[3 * a + 1] -= ua * v1;
-                        blk[3 * a + 2] -= ua * v2;
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) blk[NC * a + b] -= ua * vq[b];
                     }
                 }
                 double fro = 0.0;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) {
-                        Rrow[a * n3 + 3 * j + b] = blk[3 * a + b];
-                        fro += blk[3 * a + b] * blk[3 * a + b];
+                for (int a = 0; a < NC; ++a)
+                    for (int b = 0; b < NC; ++b) {
+                        Rrow[a * n3 + NC * j + b] = blk[NC * a + b];
+                        fro += blk[NC * a + b] * blk[NC * a + b];
                     }
                 if (!colused[j] && (fro > best)) {
                     best = fro;
@@ -221,9 +229,9 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
         int k0 = k;
         if (!zero_row) {
             // ---- residual of pivot column element jpiv ----
-            for (int idx = threadIdx.x; idx < 3 * k; idx += kAcaThreads) {
+            for (int idx = threadIdx.x; idx < NC * k; idx += kAcaThreads) {
                 int b = idx / k, q = idx - b * k;
-                s_piv[b * kAcaMaxRank + q] = V[(int64_t)q * n3 + 3 * jpiv + b];
+                s_piv[b * kAcaMaxRank + q] = V[(int64_t)q * n3 + NC * jpiv + b];
             }
             __syncthreads();
             const ElemGeo& S = geo[D.s_begin + jpiv];
@@ -232,58 +240,66 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
                 double x[3] = {R.c[0], R.c[1], R.c[2]};
                 double fr[9];
                 for (int t = 0; t < 9; ++t) fr[t] = R.fr[t];
-                double blk[9];
-                dd_block(x, fr, S, kG, kN, blk);
+                double full[9], blk[NC * NC];
+                dd_block(x, fr, S, kG, kN, full);
+#pragma unroll
+                for (int a = 0; a < NC; ++a)
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) blk[NC * a + b] = full[3 * (ca + a) + ca + b];
                 for (int q = 0; q < k; ++q) {
-                    const double* uq = U + (int64_t)q * m3 + 3 * i;
-                    for (int a = 0; a < 3; ++a) {
+                    const double* uq = U + (int64_t)q * m3 + NC * i;
+#pragma unroll
+                    for (int a = 0; a < NC; ++a) {
                         double ua = uq[a];
-                        for (int b = 0; b < 3; ++b) blk[3 * a + b] -= ua * s_piv[b * kAcaMaxRank + q];
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) blk[NC * a + b] -= ua * s_piv[b * kAcaMaxRank + q];
                     }
                 }
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) Rcol[(3 * (int64_t)i + a) * 3 + b] = blk[3 * a + b];
+                for (int a = 0; a < NC; ++a)
+                    for (int b = 0; b < NC; ++b) Rcol[(NC * (int64_t)i + a) * NC + b] = blk[NC * a + b];
             }
-            if (threadIdx.x < 9) s_P[threadIdx.x] = Rrow[(threadIdx.x / 3) * n3 + 3 * jpiv + threadIdx.x % 3];
+            if (threadIdx.x < NC * NC)
+                s_P[threadIdx.x] = Rrow[(threadIdx.x / NC) * n3 + NC * jpiv + threadIdx.x % NC];
             __syncthreads();
-            // ---- eliminate the 3x3 pivot block with complete pivoting ----
-            double P[9];
-            for (int t = 0; t < 9; ++t) P[t] = s_P[t];
+            // ---- eliminate the pivot block with complete pivoting ----
+            double P[NC * NC];
+            for (int t = 0; t < NC * NC; ++t) P[t] = s_P[t];
             double pmax0 = 0.0;
-            for (int t = 0; t < 9; ++t) pmax0 = fmax(pmax0, fabs(P[t]));
-            bool rdone[3] = {false, false, false}, cdone[3] = {false, false, false};
-            for (int sub = 0; sub < 3 && k < D.kmax; ++sub) {
+            for (int t = 0; t < NC * NC; ++t) pmax0 = fmax(pmax0, fabs(P[t]));
+            bool rdone[NC], cdone[NC];
+            for (int t = 0; t < NC; ++t) rdone[t] = cdone[t] = false;
+            for (int sub = 0; sub < NC && k < D.kmax; ++sub) {
                 int r = -1, c = -1;
                 double pm = -1.0;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b)
-                        if (!rdone[a] && !cdone[b] && fabs(P[3 * a + b]) > pm) {
-                            pm = fabs(P[3 * a + b]);
+                for (int a = 0; a < NC; ++a)
+                    for (int b = 0; b < NC; ++b)
+                        if (!rdone[a] && !cdone[b] && fabs(P[NC * a + b]) > pm) {
+                            pm = fabs(P[NC * a + b]);
                             r = a;
                             c = b;
                         }
                 if (r < 0 || !(pm > 1e-10 * pmax0)) break;
-                const double inv = 1.0 / P[3 * r + c];
+                const double inv = 1.0 / P[NC * r + c];
                 double* Uk = U + (int64_t)k * m3;
                 double* Vk = V + (int64_t)k * n3;
-                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) Uk[x] = Rcol[x * 3 + c];
+                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) Uk[x] = Rcol[x * NC + c];
                 for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) Vk[y] = Rrow[r * n3 + y] * inv;
                 __syncthreads();
-                double vj[3], ui[3];
-                for (int t = 0; t < 3; ++t) {
-                    vj[t] = Vk[3 * jpiv + t];
-                    ui[t] = Uk[3 * ipiv + t];
+                double vj[NC], ui[NC];
+                for (int t = 0; t < NC; ++t) {
+                    vj[t] = Vk[NC * jpiv + t];
+                    ui[t] = Uk[NC * ipiv + t];
                 }
                 for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) {
                     double u = Uk[x];
-                    for (int t = 0; t < 3; ++t) Rcol[x * 3 + t] -= u * vj[t];
+                    for (int t = 0; t < NC; ++t) Rcol[x * NC + t] -= u * vj[t];
                 }
                 for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) {
                     double v = Vk[y];
-                    for (int t = 0; t < 3; ++t) Rrow[t * n3 + y] -= ui[t] * v;
+                    for (int t = 0; t < NC; ++t) Rrow[t * n3 + y] -= ui[t] * v;
                 }
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) P[3 * a + b] -= ui[a] * vj[b];
+                for (int a = 0; a < NC; ++a)
+                    for (int b = 0; b < NC; ++b) P[NC * a + b] -= ui[a] * vj[b];
                 rdone[r] = true;
                 cdone[c] = true;
                 ++k;
@@ -345,8 +361,8 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
             if (rowused[i]) continue;
             double s = 0.0;
             for (int q = k0; q < k; ++q)
-                for (int a = 0; a < 3; ++a) {
-                    double u = U[(int64_t)q * m3 + 3 * i + a];
+                for (int a = 0; a < NC; ++a) {
+                    double u = U[(int64_t)q * m3 + NC * i + a];
                     s += u * u;
                 }
             if (s > v) {
@@ -363,7 +379,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
         misses = 0;
     }
     // a cross approximation of full rank interpolates every row: exact
-    if (k >= 3 * min(D.m, D.n)) converged = true;
+    if (k >= NC * min(D.m, D.n)) converged = true;
     if (threadIdx.x == 0) {
         out_rank[blockIdx.x] = k;
         out_status[blockIdx.x] = converged ? 0 : 1;
@@ -373,13 +389,22 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
 // ------------------------------------------------------------------
 // packing into the apply layout
 // ------------------------------------------------------------------
+// Panel row r reads source row (r / rper) * rstride + roff + r % rper (and
+// likewise for columns): (1, 1, 0) takes every DOF, (2, 3, 0) the shear and
+// (1, 3, 2) the normal components of element-major 3-component data.
+struct Sel {
+    int32_t per, stride, off;
+};
+constexpr Sel kSelAll{1, 1, 0}, kSelShear3{2, 3, 0}, kSelNormal3{1, 3, 2};
+
 struct PackDesc {
     int64_t src_off;  // FP64 source
     int64_t dst_off;  // panel start
     int64_t ld;       // source leading dimension
     int32_t rows, cols;
-    int32_t mode;     // 0: row-major src[row*ld + col]; 1: src[col*ld + row]
-    int32_t zero_self;  // dense diagonal block: zero element self blocks
+    int32_t mode;     // 0: row-major src[row*ld + col]; 1: src[col*ld + row] (source indices)
+    int32_t zero_self;  // dense diagonal block: zero entries whose source row and column are one element
+    Sel rs, cs;
 };
 
 template <class T>
@@ -389,8 +414,10 @@ __global__ void k_pack(const PackDesc* __restrict__ descs, const double* __restr
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)D.rows * D.cols) return;
     int row = (int)(e / D.cols), col = (int)(e - (int64_t)row * D.cols);
-    double v = D.mode == 0 ? src[D.src_off + row * D.ld + col] : src[D.src_off + (int64_t)col * D.ld + row];
-    if (D.zero_self && row / 3 == col / 3) v = 0.0;
+    const int64_t sr = (int64_t)(row / D.rs.per) * D.rs.stride + D.rs.off + row % D.rs.per;
+    const int64_t sc = (int64_t)(col / D.cs.per) * D.cs.stride + D.cs.off + col % D.cs.per;
+    double v = D.mode == 0 ? src[D.src_off + sr * D.ld + sc] : src[D.src_off + sc * D.ld + sr];
+    if (D.zero_self && sr / 3 == sc / 3) v = 0.0;
     dst[D.dst_off + panel_offset(D.rows, D.cols, w, row, col)] = cvt<T>(v);
 }
 
@@ -506,39 +533,71 @@ void pack_dispatch(int prec, const PackJob& job, const double* src, void* dst, h
 }  // namespace
 
 // Pack one precision variant and build its task lists.
+//
+// Every stored piece maps one section (shear: 2 DOF per element, normal: 1)
+// of a target leaf to one section of a source leaf or to a T chunk:
+//   * dense leaf pair: SS, SN, NS, NN pieces; SS and NN only when the two
+//     leaves are coplanar (the SN, NS couplings vanish);
+//   * low-rank factorisation of comps = 3: U split into a shear and a normal
+//     slice per target leaf, V^T into a shear and a normal sub-panel per
+//     source leaf, one T chunk; comps = 2 / 1 (the shear / normal part of a
+//     coplanar block): one slice and one sub-panel per leaf.
+// Phase B has one task per (target leaf, section).
+namespace {
+
+enum Section { kShear = 0, kNormal = 1 };
+
+int sec_rows(int64_t m, int sec) { return sec == kShear ? 2 * (int)m : (int)m; }
+int64_t sec_off(int64_t m, int sec) { return sec == kShear ? 0 : chunk_n_off(m); }
+
+}  // namespace
+
 static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, const double* d_dense,
                          const double* d_fac, hipStream_t s)
 {
     const Plan& p = op.plan;
     const int wn = prec_w(v.near_prec), wf = prec_w(v.far_prec);
     const int nleaf = (int)p.leaves.size();
-    // ---- dense panels ----
-    std::vector<int64_t> dense_off(dd.size());
+    // phase-B items, by (target leaf, section)
+    std::vector<std::vector<PanelRef>> itemsB(2 * (size_t)nleaf);
+    // ---- dense pieces ----
     int64_t near_elems = 0;
-    for (size_t b = 0; b < dd.size(); ++b) {
-        dense_off[b] = near_elems;
-        near_elems += panel_elems(3 * dd[b].m, 3 * dd[b].n, wn);
-    }
-    v.near_a.alloc(std::max<int64_t>(1, near_elems) * prec_bytes(v.near_prec));
-    HM_CHECK_HIP(hipMemsetAsync(v.near_a.get(), 0, v.near_a.bytes(), s));
     {
         PackJob job;
         for (size_t b = 0; b < dd.size(); ++b) {
-            bool diag = p.dense[b].first == p.dense[b].second;
-            job.add(PackDesc{dd[b].out_off, dense_off[b], 3 * (int64_t)dd[b].n, 3 * dd[b].m, 3 * dd[b].n, 0,
-                             (diag && v.self_separate) ? 1 : 0});
+            const Cluster& tc = p.nodes[p.dense[b].first];
+            const Cluster& sc = p.nodes[p.dense[b].second];
+            const bool diag = p.dense[b].first == p.dense[b].second;
+            const bool cop = coplanar_pair(p, p.dense[b].first, p.dense[b].second);
+            for (int ts = 0; ts < 2; ++ts)
+                for (int ss = 0; ss < 2; ++ss) {
+                    if (cop && ts != ss) continue;
+                    const int rows = sec_rows(tc.size(), ts), cols = sec_rows(sc.size(), ss);
+                    job.add(PackDesc{dd[b].out_off, near_elems, 3 * (int64_t)dd[b].n, rows, cols, 0,
+                                     (diag && v.self_separate) ? 1 : 0, ts == kShear ? kSelShear3 : kSelNormal3,
+                                     ss == kShear ? kSelShear3 : kSelNormal3});
+                    itemsB[2 * (size_t)tc.leaf_id + ts].push_back(
+                        PanelRef{near_elems, (op.leaf_xoff[sc.leaf_id] + sec_off(sc.size(), ss)) * kNrhs, rows, cols,
+                                 0, 0});
+                    near_elems += panel_elems(rows, cols, wn);
+                }
         }
+        v.near_a.alloc(std::max<int64_t>(1, near_elems) * prec_bytes(v.near_prec));
+        HM_CHECK_HIP(hipMemsetAsync(v.near_a.get(), 0, v.near_a.bytes(), s));
         pack_dispatch(v.near_prec, job, d_dense, v.near_a.get(), s);
     }
     v.bytes_near = near_elems * prec_bytes(v.near_prec);
-    // ---- low-rank panels: U slices per target leaf, V^T sub-panels per source leaf ----
-    struct Slice {
-        int64_t off;
-        int block;
-        int leaf;
-    };
-    std::vector<std::vector<Slice>> uslices(nleaf);       // by target leaf
-    std::vector<std::vector<Slice>> vslices(op.lr.size()); // by block
+    // ---- T chunks ----
+    v.t_off.assign(op.lr.size(), 0);
+    int64_t tfrag = 0;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        if (op.lr[b].rank == 0) continue;
+        v.t_off[b] = tfrag;
+        tfrag += round_up(op.lr[b].rank, kChunkAlign) * kNrhs;
+    }
+    // ---- low-rank pieces: U slices per target leaf, V^T sub-panels per source leaf ----
+    v.vitems.assign(op.lr.size(), {});
+    v.bytes_far_u = v.bytes_far_v = 0;
     int64_t far_elems = 0;
     PackJob job;
     for (size_t b = 0; b < op.lr.size(); ++b) {
@@ -547,21 +606,35 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         const Cluster& sc = p.nodes[L.s_node];
         const int k = L.rank;
         if (k == 0) continue;
+        const int nc = L.comps;
+        // sections carried by this factorisation and how to read them from it
+        std::vector<std::pair<int, Sel>> secs;
+        if (nc == 3)
+            secs = {{kShear, kSelShear3}, {kNormal, kSelNormal3}};
+        else
+            secs = {{L.comp0 == 2 ? kNormal : kShear, kSelAll}};
         for (int lf = t.first_leaf; lf < t.first_leaf + t.n_leaves; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
-            int rows = 3 * (int)c.size();
-            uslices[lf].push_back(Slice{far_elems, (int)b, lf});
-            job.add(PackDesc{L.u_off + 3 * (c.begin - t.begin), far_elems, 3 * L.m, rows, k, 1, 0});
-            far_elems += panel_elems(rows, k, wf);
-            v.bytes_far_u += panel_elems(rows, k, wf) * prec_bytes(v.far_prec);
+            for (const auto& sec : secs) {
+                const int rows = sec_rows(c.size(), sec.first);
+                job.add(PackDesc{L.u_off + nc * (c.begin - t.begin), far_elems, nc * L.m, rows, k, 1, 0, sec.second,
+                                 kSelAll});
+                itemsB[2 * (size_t)lf + sec.first].push_back(PanelRef{far_elems, v.t_off[b], rows, k, 1, 0});
+                far_elems += panel_elems(rows, k, wf);
+                v.bytes_far_u += panel_elems(rows, k, wf) * prec_bytes(v.far_prec);
+            }
         }
         for (int lf = sc.first_leaf; lf < sc.first_leaf + sc.n_leaves; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
-            int cols = 3 * (int)c.size();
-            vslices[b].push_back(Slice{far_elems, (int)b, lf});
-            job.add(PackDesc{L.v_off + 3 * (c.begin - sc.begin), far_elems, 3 * L.n, k, cols, 0, 0});
-            far_elems += panel_elems(k, cols, wf);
-            v.bytes_far_v += panel_elems(k, cols, wf) * prec_bytes(v.far_prec);
+            for (const auto& sec : secs) {
+                const int cols = sec_rows(c.size(), sec.first);
+                job.add(PackDesc{L.v_off + nc * (c.begin - sc.begin), far_elems, nc * L.n, k, cols, 0, 0, kSelAll,
+                                 sec.second});
+                v.vitems[b].push_back(
+                    PanelRef{far_elems, (op.leaf_xoff[lf] + sec_off(c.size(), sec.first)) * kNrhs, k, cols, 1, 0});
+                far_elems += panel_elems(k, cols, wf);
+                v.bytes_far_v += panel_elems(k, cols, wf) * prec_bytes(v.far_prec);
+            }
         }
     }
     v.far_a.alloc(std::max<int64_t>(1, far_elems) * prec_bytes(v.far_prec));
@@ -569,36 +642,20 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     pack_dispatch(v.far_prec, job, d_fac, v.far_a.get(), s);
     v.bytes_far = far_elems * prec_bytes(v.far_prec);
 
-    // ---- T chunks ----
-    v.t_off.assign(op.lr.size(), 0);
-    v.vslices.assign(op.lr.size(), {});
-    int64_t tfrag = 0;
-    for (size_t b = 0; b < op.lr.size(); ++b) {
-        if (op.lr[b].rank == 0) continue;
-        v.t_off[b] = tfrag;
-        tfrag += round_up(op.lr[b].rank, kChunkAlign) * kNrhs;
-        for (const Slice& sl : vslices[b]) v.vslices[b].push_back({sl.off, sl.leaf});
-    }
-    const std::vector<int64_t>& t_off = v.t_off;
-    // ---- phase-B tasks: one per target leaf ----
-    std::vector<std::vector<int>> dense_by_leaf(nleaf);
-    for (size_t b = 0; b < p.dense.size(); ++b) dense_by_leaf[p.nodes[p.dense[b].first].leaf_id].push_back((int)b);
+    // ---- phase-B tasks: one per (target leaf, section) ----
     std::vector<TaskB>& tb = v.hTasksB;
     std::vector<PanelRef>& ib = v.hItemsB;
     tb.clear();
     ib.clear();
     for (int lf = 0; lf < nleaf; ++lf) {
         const Cluster& c = p.nodes[p.leaves[lf]];
-        TaskB t{op.leaf_xoff[lf], 3 * (int32_t)c.size(), (int32_t)ib.size(), 0, 0};
-        for (int b : dense_by_leaf[lf]) {
-            const Cluster& sc = p.nodes[p.dense[b].second];
-            ib.push_back(PanelRef{dense_off[b], op.leaf_xoff[sc.leaf_id] * kNrhs, 3 * (int32_t)c.size(),
-                                  3 * (int32_t)sc.size(), 0, 0});
+        for (int sec = 0; sec < 2; ++sec) {
+            const auto& its = itemsB[2 * (size_t)lf + sec];
+            TaskB t{op.leaf_xoff[lf] + sec_off(c.size(), sec), sec_rows(c.size(), sec), (int32_t)ib.size(),
+                    (int32_t)its.size(), 0};
+            ib.insert(ib.end(), its.begin(), its.end());
+            tb.push_back(t);
         }
-        for (const Slice& sl : uslices[lf])
-            ib.push_back(PanelRef{sl.off, t_off[sl.block], 3 * (int32_t)c.size(), op.lr[sl.block].rank, 1, 0});
-        t.n_items = (int32_t)ib.size() - t.item_begin;
-        tb.push_back(t);
     }
     // group phase-B tasks by row-tile count (one launch per group), leaf order kept inside a group
     std::stable_sort(tb.begin(), tb.end(), [](const TaskB& a, const TaskB& b) {
@@ -639,14 +696,13 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     HM_CHECK_HIP(hipStreamSynchronize(s));
 }
 
-// Phase-A tasks: each covers at most leaves_per_task V^T sub-panels of one
-// block; a block covered by one task writes its T chunk directly, others
-// go through partial slots and the reduction.
-void build_tasksA(const Op& op, Variant& v, int leaves_per_task)
+// Phase-A tasks: each covers at most items_per_task V^T sub-panels of one
+// factorisation; one covered by a single task writes its T chunk directly,
+// others go through partial slots and the reduction.
+void build_tasksA(const Op& op, Variant& v, int items_per_task)
 {
-    HM_REQUIRE(leaves_per_task >= 1, HM_EINVAL, "leaves per phase-A task must be positive");
-    const Plan& p = op.plan;
-    v.leavesPerTaskA = leaves_per_task;
+    HM_REQUIRE(items_per_task >= 1, HM_EINVAL, "sub-panels per phase-A task must be positive");
+    v.leavesPerTaskA = items_per_task;
     std::vector<TaskA>& ta = v.hTasksA;
     std::vector<PanelRef>& ia = v.hItemsA;
     std::vector<ReduceDesc>& red = v.hReduce;
@@ -659,14 +715,12 @@ void build_tasksA(const Op& op, Variant& v, int leaves_per_task)
         if (L.rank == 0) continue;
         const int64_t slot = round_up(L.rank, 16) * kNrhs;
         ReduceDesc rd{tpart, v.t_off[b], 0, L.rank, 0, 0};
-        const auto& vs = v.vslices[b];
-        const bool direct = vs.size() <= (size_t)leaves_per_task;
-        for (size_t q0 = 0; q0 < vs.size(); q0 += leaves_per_task) {
+        const auto& vs = v.vitems[b];
+        const bool direct = vs.size() <= (size_t)items_per_task;
+        for (size_t q0 = 0; q0 < vs.size(); q0 += items_per_task) {
             TaskA t{direct ? 0 : tpart, v.t_off[b], L.rank, (int32_t)ia.size(), 0, direct ? 1 : 0, 0, 0};
-            for (size_t q = q0; q < std::min(vs.size(), q0 + (size_t)leaves_per_task); ++q) {
-                const Cluster& c = p.nodes[p.leaves[vs[q].second]];
-                ia.push_back(PanelRef{vs[q].first, op.leaf_xoff[vs[q].second] * kNrhs, L.rank,
-                                      3 * (int32_t)c.size(), 1, 0});
+            for (size_t q = q0; q < std::min(vs.size(), q0 + (size_t)items_per_task); ++q) {
+                ia.push_back(vs[q]);
                 t.n_items++;
             }
             ta.push_back(t);
@@ -752,7 +806,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.xtot = 0;
     for (int lf = 0; lf < nleaf; ++lf) {
         op.leaf_xoff[lf] = op.xtot;
-        op.xtot += round_up(3 * p.nodes[p.leaves[lf]].size(), kChunkAlign);
+        op.xtot += chunk_len(p.nodes[p.leaves[lf]].size());
     }
     // element tables
     std::vector<ElemGeo> geo(mesh.ne);
@@ -762,12 +816,13 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     upload(d_perm, p.perm, s);
     {
         std::vector<int64_t> xslot(mesh.ne);
-        std::vector<int32_t> xloc(mesh.ne);
+        std::vector<int32_t> xloc(2 * mesh.ne);
         for (int lf = 0; lf < nleaf; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
             for (int64_t q = c.begin; q < c.end; ++q) {
                 xslot[p.perm[q]] = op.leaf_xoff[lf];
-                xloc[p.perm[q]] = (int32_t)(3 * (q - c.begin));
+                xloc[2 * p.perm[q]] = (int32_t)(2 * (q - c.begin));
+                xloc[2 * p.perm[q] + 1] = (int32_t)(chunk_n_off(c.size()) + (q - c.begin));
             }
         }
         upload(op.d_xslot, xslot, s);
@@ -786,18 +841,21 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     int64_t rank_sum = 0;
     int rmin = 1 << 30, rmax = 0, rounds = 0;
     const int64_t budget = (int64_t)6 << 30;  // bytes of ACA workspace per batch
+    // One ACA job per part of a candidate pair: the full 3-component block,
+    // or its shear and normal parts when the two clusters are coplanar.
+    struct Job {
+        int cand;
+        int nc, ca;
+        AcaDesc d;
+    };
     while (!cand.empty()) {
         HM_REQUIRE(++rounds <= 40, HM_EINTERNAL, "block splitting did not terminate");
-        std::vector<LowRank> cl(cand.size());
-        std::vector<AcaDesc> ad(cand.size());
+        std::vector<std::vector<Job>> jobs(cand.size());
+        std::vector<int64_t> need(cand.size(), 0);
         for (size_t b = 0; b < cand.size(); ++b) {
             const Cluster& t = pm.nodes[cand[b].first];
             const Cluster& sc = pm.nodes[cand[b].second];
-            LowRank& L = cl[b];
-            L.t_node = cand[b].first;
-            L.s_node = cand[b].second;
-            L.m = t.size();
-            L.n = sc.size();
+            const int64_t m = t.size(), n = sc.size();
             // first pivot: element nearest to the target cluster's mean collocation point
             double cm[3] = {0, 0, 0};
             for (int64_t q = t.begin; q < t.end; ++q)
@@ -816,89 +874,143 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
                     first = (int)(q - t.begin);
                 }
             }
-            int kmax = (int)std::min<int64_t>(o.max_rank, 3 * std::min(L.m, L.n));
-            ad[b] = AcaDesc{t.begin, sc.begin, 0, 0, 0, 0, 0, (int32_t)L.m, (int32_t)L.n, first, kmax};
+            std::vector<std::pair<int, int>> parts;
+            if (coplanar_pair(pm, cand[b].first, cand[b].second))
+                parts = {{2, 0}, {1, 2}};
+            else
+                parts = {{3, 0}};
+            for (const auto& pc : parts) {
+                const int nc = pc.first;
+                const int kmax = (int)std::min<int64_t>(o.max_rank, nc * std::min(m, n));
+                AcaDesc d{t.begin, sc.begin, 0, 0, 0, 0, 0, (int32_t)m, (int32_t)n, first, kmax, pc.second, 0};
+                jobs[b].push_back(Job{(int)b, nc, pc.second, d});
+                need[b] += 8 * ((int64_t)kmax * nc * (m + n) + (int64_t)nc * nc * (m + n)) + m + n + 64;
+            }
         }
-        // large blocks first inside each batch for load balance
-        std::vector<int> order(ad.size());
+        // large blocks first inside each batch for load balance; the parts of
+        // one pair stay in one batch
+        std::vector<int> order(cand.size());
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return ad[a].m + ad[a].n > ad[b].m + ad[b].n;
+            return jobs[a][0].d.m + jobs[a][0].d.n > jobs[b][0].d.m + jobs[b][0].d.n;
         });
         std::vector<std::vector<int>> batches;
         {
             int64_t used = 0;
             std::vector<int> cur;
             for (int b : order) {
-                int64_t need = 8 * ((int64_t)ad[b].kmax * 3 * (ad[b].m + ad[b].n) +
-                                    9 * (int64_t)(ad[b].m + ad[b].n)) + ad[b].m + ad[b].n + 64;
-                if (!cur.empty() && used + need > budget) {
+                if (!cur.empty() && used + need[b] > budget) {
                     batches.push_back(cur);
                     cur.clear();
                     used = 0;
                 }
                 cur.push_back(b);
-                used += need;
+                used += need[b];
             }
             if (!cur.empty()) batches.push_back(cur);
         }
         std::vector<std::pair<int, int>> next;
         for (const auto& bl : batches) {
-            std::vector<AcaDesc> bd(bl.size());
+            // workspace offsets for every job of the batch
             int64_t off = 0, foff = 0;
-            for (size_t q = 0; q < bl.size(); ++q) {
-                AcaDesc d = ad[bl[q]];
-                d.u_off = off;
-                off += (int64_t)d.kmax * 3 * d.m;
-                d.v_off = off;
-                off += (int64_t)d.kmax * 3 * d.n;
-                d.rrow_off = off;
-                off += 9 * (int64_t)d.n;
-                d.rcol_off = off;
-                off += 9 * (int64_t)d.m;
-                d.flag_off = foff;
-                foff += d.m + d.n;
-                bd[q] = d;
+            std::vector<Job*> all;
+            for (int b : bl)
+                for (Job& j : jobs[b]) {
+                    AcaDesc& d = j.d;
+                    d.u_off = off;
+                    off += (int64_t)d.kmax * j.nc * d.m;
+                    d.v_off = off;
+                    off += (int64_t)d.kmax * j.nc * d.n;
+                    d.rrow_off = off;
+                    off += (int64_t)j.nc * j.nc * d.n;
+                    d.rcol_off = off;
+                    off += (int64_t)j.nc * j.nc * d.m;
+                    d.flag_off = foff;
+                    foff += d.m + d.n;
+                    all.push_back(&j);
+                }
+            DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff));
+            std::vector<int> rk(all.size()), st(all.size());
+            for (int nc = 3; nc >= 1; --nc) {
+                std::vector<AcaDesc> descs;
+                std::vector<int> idx;
+                for (size_t q = 0; q < all.size(); ++q)
+                    if (all[q]->nc == nc) {
+                        descs.push_back(all[q]->d);
+                        idx.push_back((int)q);
+                    }
+                if (descs.empty()) continue;
+                DevBuf d_bd, d_rank(descs.size() * sizeof(int)), d_stat(descs.size() * sizeof(int));
+                upload(d_bd, descs, s);
+                const dim3 grid((unsigned)descs.size());
+                if (nc == 3)
+                    hipLaunchKernelGGL(k_aca<3>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
+                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
+                                       d_stat.as<int>());
+                else if (nc == 2)
+                    hipLaunchKernelGGL(k_aca<2>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
+                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
+                                       d_stat.as<int>());
+                else
+                    hipLaunchKernelGGL(k_aca<1>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
+                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
+                                       d_stat.as<int>());
+                HM_CHECK_HIP(hipGetLastError());
+                std::vector<int> r(descs.size()), t(descs.size());
+                HM_CHECK_HIP(hipMemcpyAsync(r.data(), d_rank.get(), r.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+                HM_CHECK_HIP(hipMemcpyAsync(t.data(), d_stat.get(), t.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+                HM_CHECK_HIP(hipStreamSynchronize(s));
+                for (size_t q = 0; q < idx.size(); ++q) {
+                    rk[idx[q]] = r[q];
+                    st[idx[q]] = t[q];
+                }
             }
-            DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff)), d_bd, d_rank(bl.size() * sizeof(int)),
-                d_stat(bl.size() * sizeof(int));
-            upload(d_bd, bd, s);
-            hipLaunchKernelGGL(k_aca, dim3((unsigned)bl.size()), dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(),
-                               d_bd.as<AcaDesc>(), kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(),
-                               d_rank.as<int>(), d_stat.as<int>());
-            HM_CHECK_HIP(hipGetLastError());
-            std::vector<int> rk(bl.size()), st(bl.size());
-            HM_CHECK_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-            HM_CHECK_HIP(hipMemcpyAsync(st.data(), d_stat.get(), st.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-            HM_CHECK_HIP(hipStreamSynchronize(s));
-            // keep converged blocks (compact copy of their factors), split the others
+            // a pair is kept when every part converged (compact copy of its
+            // factors); otherwise it is split
+            std::vector<int> jrank(all.size());
+            std::vector<char> pair_ok(cand.size(), 1);
+            for (size_t q = 0; q < all.size(); ++q) {
+                jrank[q] = rk[q];
+                if (st[q] != 0) pair_ok[all[q]->cand] = 0;
+            }
             int64_t csz = 0;
-            for (size_t q = 0; q < bl.size(); ++q)
-                if (st[q] == 0) csz += (int64_t)rk[q] * 3 * (cl[bl[q]].m + cl[bl[q]].n);
+            for (size_t q = 0; q < all.size(); ++q)
+                if (pair_ok[all[q]->cand]) csz += (int64_t)jrank[q] * all[q]->nc * (all[q]->d.m + all[q]->d.n);
             batch_fac.emplace_back(std::max<int64_t>(1, csz) * sizeof(double));
             const int bi = (int)batch_fac.size() - 1;
             int64_t c = 0;
             std::vector<CompactDesc> cd;
-            for (size_t q = 0; q < bl.size(); ++q) {
-                LowRank L = cl[bl[q]];
-                if (st[q] != 0) {
-                    split_block(pm, L.t_node, L.s_node, next, pm.dense);
+            size_t q = 0;
+            for (int b : bl) {
+                const int t_node = cand[b].first, s_node = cand[b].second;
+                if (!pair_ok[b]) {
+                    q += jobs[b].size();
+                    split_block(pm, t_node, s_node, next, pm.dense);
                     continue;
                 }
-                const AcaDesc& d = bd[q];
-                L.rank = rk[q];
-                L.u_off = c;
-                if (L.rank) cd.push_back(CompactDesc{d.u_off, c, (int64_t)L.rank * 3 * L.m});
-                c += (int64_t)L.rank * 3 * L.m;
-                L.v_off = c;
-                if (L.rank) cd.push_back(CompactDesc{d.v_off, c, (int64_t)L.rank * 3 * L.n});
-                c += (int64_t)L.rank * 3 * L.n;
-                fac_where.push_back({bi, 0});
-                op.lr.push_back(L);
-                pm.lowrank.push_back({L.t_node, L.s_node});
-                rank_sum += L.rank;
-                rmin = std::min(rmin, L.rank);
-                rmax = std::max(rmax, L.rank);
+                for (const Job& j : jobs[b]) {
+                    LowRank L;
+                    L.t_node = t_node;
+                    L.s_node = s_node;
+                    L.m = j.d.m;
+                    L.n = j.d.n;
+                    L.comps = j.nc;
+                    L.comp0 = j.ca;
+                    L.rank = jrank[q];
+                    L.u_off = c;
+                    if (L.rank) cd.push_back(CompactDesc{j.d.u_off, c, (int64_t)L.rank * j.nc * L.m});
+                    c += (int64_t)L.rank * j.nc * L.m;
+                    L.v_off = c;
+                    if (L.rank) cd.push_back(CompactDesc{j.d.v_off, c, (int64_t)L.rank * j.nc * L.n});
+                    c += (int64_t)L.rank * j.nc * L.n;
+                    fac_where.push_back({bi, 0});
+                    op.lr.push_back(L);
+                    rank_sum += L.rank;
+                    rmin = std::min(rmin, L.rank);
+                    rmax = std::max(rmax, L.rank);
+                    ++q;
+                }
+                pm.lowrank.push_back({t_node, s_node});
             }
             if (!cd.empty()) {
                 DevBuf d_cd;
@@ -997,7 +1109,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     st.n_lowrank_blocks = (int64_t)p.lowrank.size();
     st.dense_entries = dense_total;
     int64_t lre = 0;
-    for (const LowRank& L : op.lr) lre += (int64_t)L.rank * 3 * (L.m + L.n);
+    for (const LowRank& L : op.lr) lre += (int64_t)L.rank * L.comps * (L.m + L.n);
     st.lowrank_entries = lre;
     st.self_f64_entries = op.main.self_separate ? 9 * mesh.ne : 0;
     st.bytes_near = op.main.bytes_near;
@@ -1017,7 +1129,9 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     {
         std::vector<int64_t> per(nleaf, 0);
         for (size_t b = 0; b < p.dense.size(); ++b)
-            per[p.nodes[p.dense[b].first].leaf_id] += 9 * (int64_t)dd[b].m * dd[b].n * prec_bytes(o.near_prec);
+            per[p.nodes[p.dense[b].first].leaf_id] +=
+                (coplanar_pair(p, p.dense[b].first, p.dense[b].second) ? 5 : 9) * (int64_t)dd[b].m * dd[b].n *
+                prec_bytes(o.near_prec);
         for (int64_t x : per) maxleaf = std::max(maxleaf, x);
     }
     st.max_dense_bytes_per_leaf = maxleaf;

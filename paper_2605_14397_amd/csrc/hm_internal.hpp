@@ -116,6 +116,9 @@ struct Cluster {
     int level = 0;
     int leaf_id = -1;             // index among leaves (leaves only)
     int first_leaf = 0, n_leaves = 0;  // leaves under this node (contiguous)
+    // all elements lie in one plane n . x = d (within the plan's tolerance)
+    bool planar = false;
+    double pn[3] = {0, 0, 0}, pd = 0.0;
     bool is_leaf() const { return child[0] < 0; }
     int64_t size() const { return end - begin; }
 };
@@ -130,6 +133,7 @@ struct Plan {
     std::vector<std::pair<int, int>> dense;    // (target leaf node, source leaf node)
     std::vector<std::pair<int, int>> lowrank;  // (target node, source node)
     int depth = 0;
+    double plane_tol = 0.0;           // distance below which points count as in a plane
 };
 
 Plan make_plan(const Mesh& m, int leaf_size, double eta);
@@ -137,6 +141,11 @@ Plan make_plan(const Mesh& m, int leaf_size, double eta);
 void split_block(Plan& p, int t, int s, std::vector<std::pair<int, int>>& lowrank,
                  std::vector<std::pair<int, int>>& dense);
 void sort_blocks(Plan& p);
+// Both clusters lie in one common plane.  Between elements of one plane
+// the normal DD component and the two shear components do not interact
+// (the planar-crack operator decouples opening from slip), so such a block
+// is stored as a shear part and a normal part.
+bool coplanar_pair(const Plan& p, int t, int s);
 
 // ------------------------------------------------------------------
 // panel layout shared by pack and apply kernels
@@ -179,10 +188,16 @@ __host__ __device__ inline int64_t bfrag_offset(int w, int q, int c)
 }
 
 constexpr int kChunkAlign = 32;   // dofs; multiple of every k-step
-constexpr int kNrhs = 16;         // right-hand sides per fragment
-constexpr int kRowTilesMax = 12;  // 192 rows: leaf <= 64 elements, rank <= 192
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// In-vector chunk of a leaf of m elements: a shear section (s1, s2 of each
+// element, element-major) then a normal section (n of each element), each
+// starting on a k-step boundary.
+__host__ __device__ inline int64_t chunk_n_off(int64_t m) { return round_up(2 * m, kChunkAlign); }
+__host__ __device__ inline int64_t chunk_len(int64_t m) { return chunk_n_off(m) + round_up(m, kChunkAlign); }
+constexpr int kNrhs = 16;         // right-hand sides per fragment
+constexpr int kRowTilesMax = 12;  // 192 rows: leaf <= 64 elements, rank <= 192
 
 inline int prec_w(int prec) { return prec == HM_F64 ? 2 : (prec == HM_F32 ? 4 : 8); }
 inline int prec_bytes(int prec) { return prec == HM_F64 ? 8 : (prec == HM_F32 ? 4 : 2); }
@@ -239,8 +254,8 @@ struct Segment {
     int64_t ne, ldx, ldy;
     const double* X;
     double* Y;
-    const int64_t* xslot;
-    const int32_t* xloc;
+    const int64_t* xslot;   // chunk start of the element's leaf
+    const int32_t* xloc;    // [2N]: dof of s1 (s2 follows) and of n within the chunk
     const double* self;     // FP64 self blocks or null
     const double* D;        // tangent blocks or null
     const uint8_t* mask;    // active mask or null

@@ -30,8 +30,8 @@ struct Variant {
     std::vector<TaskB> hTasksB;
     std::vector<PanelRef> hItemsB;
     int leavesPerTaskA = 8;
-    std::vector<std::vector<std::pair<int64_t, int>>> vslices;  // per block: (V^T sub-panel offset, source leaf)
-    std::vector<int64_t> t_off;                                 // per block: T chunk offset
+    std::vector<std::vector<PanelRef>> vitems;  // per block: its V^T sub-panels (phase-A items)
+    std::vector<int64_t> t_off;                 // per block: T chunk offset
     bool acc_f64() const { return near_prec == HM_F64; }
     bool far_is_near() const { return far_prec == near_prec; }
     Bases host_bases() const;
@@ -51,11 +51,15 @@ struct LaunchSet {
     const PanelRef* itemsB = nullptr;
 };
 
+// One low-rank factorisation U V^T of the components comp0 .. comp0 + comps - 1
+// of every element of a block: comps = 3 for a coupled block, 2 (shear) and
+// 1 (normal) for the two parts of a coplanar one.
 struct LowRank {
     int t_node = 0, s_node = 0;
     int64_t m = 0, n = 0;       // elements
     int rank = 0;
-    int64_t u_off = 0, v_off = 0;  // compact FP64 factors: U [rank][3m], V [rank][3n]
+    int comps = 3, comp0 = 0;
+    int64_t u_off = 0, v_off = 0;  // compact FP64 factors: U [rank][comps m], V [rank][comps n]
 };
 
 // Learned correction of the block preconditioner: network parameters and

@@ -138,6 +138,50 @@ struct Builder {
         }
     }
 
+    // Planarity of every cluster: a leaf is planar when every element's
+    // normal is parallel to the first one's and every vertex lies within
+    // plane_tol of its plane; an inner node when both children lie in one
+    // plane.
+    void planes(int id)
+    {
+        Cluster& c = p.nodes[id];
+        const double ptol = p.plane_tol;
+        if (c.is_leaf()) {
+            const int64_t e0 = p.perm[c.begin];
+            const double* n0 = &m.frame[9 * e0 + 6];
+            double d0 = 0.0;
+            for (int k = 0; k < 3; ++k) d0 += n0[k] * m.cent[3 * e0 + k];
+            bool ok = true;
+            for (int64_t q = c.begin; q < c.end && ok; ++q) {
+                const int64_t e = p.perm[q];
+                const double* ne = &m.frame[9 * e + 6];
+                if (std::fabs(ne[0] * n0[0] + ne[1] * n0[1] + ne[2] * n0[2]) < 1.0 - 1e-12) ok = false;
+                for (int v = 0; v < m.nvpe && ok; ++v) {
+                    const double* x = &m.geo[e].v[3 * v];
+                    if (std::fabs(n0[0] * x[0] + n0[1] * x[1] + n0[2] * x[2] - d0) > ptol) ok = false;
+                }
+            }
+            c.planar = ok;
+            for (int k = 0; k < 3; ++k) c.pn[k] = n0[k];
+            c.pd = d0;
+            return;
+        }
+        planes(c.child[0]);
+        planes(c.child[1]);
+        const Cluster& a = p.nodes[c.child[0]];
+        const Cluster& b = p.nodes[c.child[1]];
+        c.planar = a.planar && b.planar && same_plane(a, b, ptol);
+        for (int k = 0; k < 3; ++k) c.pn[k] = a.pn[k];
+        c.pd = a.pd;
+    }
+
+    static bool same_plane(const Cluster& a, const Cluster& b, double ptol)
+    {
+        const double dot = a.pn[0] * b.pn[0] + a.pn[1] * b.pn[1] + a.pn[2] * b.pn[2];
+        if (std::fabs(dot) < 1.0 - 1e-12) return false;
+        return std::fabs(a.pd - (dot > 0 ? b.pd : -b.pd)) <= ptol;
+    }
+
     void leaf_ranges(int id)
     {
         Cluster& c = p.nodes[id];
@@ -187,6 +231,13 @@ void split_block(Plan& p, int t, int s, std::vector<std::pair<int, int>>& lowran
     }
 }
 
+bool coplanar_pair(const Plan& p, int t, int s)
+{
+    const Cluster& a = p.nodes[t];
+    const Cluster& b = p.nodes[s];
+    return a.planar && b.planar && Builder::same_plane(a, b, p.plane_tol);
+}
+
 void sort_blocks(Plan& p)
 {
     auto by_target = [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
@@ -212,6 +263,8 @@ Plan make_plan(const Mesh& m, int leaf_size, double eta)
     p.nodes.reserve(4 * (m.ne / std::max(1, leaf_size / 2) + 1));
     b.build(0, m.ne, 0);
     b.leaf_ranges(0);
+    p.plane_tol = 1e-10 * Builder::diam(p.nodes[0]);
+    b.planes(0);
     b.blocks(0, 0);
     p.iperm.resize(m.ne);
     for (int64_t q = 0; q < m.ne; ++q) p.iperm[p.perm[q]] = q;

@@ -141,7 +141,7 @@ typedef struct {
     int near_prec;          /* HM_F64 or HM_F32 for dense leaves */
     int far_prec;           /* HM_F64, HM_F32 or HM_BF16 for low-rank factors */
     int keep_f64_reference; /* also keep an all-FP64 copy (used by refinement) */
-    int recompress;         /* reserved, must be 0 */
+    int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 (rank <= 64); default 1 */
 } hm_build_opts;
 
 /* Fill opts with the defaults above (near = far = HM_F64). */
@@ -167,7 +167,7 @@ typedef struct {
     int64_t n_elements, n_dof;
     int64_t n_leaves, n_dense_blocks, n_lowrank_blocks;
     int64_t dense_entries;        /* stored near-field scalars (excluding padding) */
-    int64_t lowrank_entries;      /* stored U and V scalars, sum 3k(m+n) */
+    int64_t lowrank_entries;      /* stored U and V scalars, sum k c (m+n) over factorisations of c components */
     int64_t self_f64_entries;     /* FP64 self-block scalars (mixed forms) */
     int64_t bytes_near, bytes_far, bytes_self, bytes_reference;
     int min_rank, max_rank;
@@ -176,7 +176,9 @@ typedef struct {
     double build_ms, coef_ms, aca_ms, pack_ms;
     int64_t max_dense_bytes_per_leaf;
     int64_t bytes_far_u, bytes_far_v;  /* far-field bytes read by phase B (U) and phase A (V) */
-    int64_t rank_sum;                  /* sum of ranks over low-rank blocks */
+    int64_t rank_sum;                  /* sum of ranks over low-rank factorisations (stored) */
+    int64_t rank_sum_aca;              /* the same before recompression */
+    double recompress_ms;
 } hm_op_stats;
 
 hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);

@@ -61,7 +61,8 @@ class OpStats(ctypes.Structure):
         ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int), ("build_ms", ctypes.c_double),
         ("coef_ms", ctypes.c_double), ("aca_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
         ("max_dense_bytes_per_leaf", ctypes.c_int64), ("bytes_far_u", ctypes.c_int64),
-        ("bytes_far_v", ctypes.c_int64), ("rank_sum", ctypes.c_int64)]
+        ("bytes_far_v", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("rank_sum_aca", ctypes.c_int64),
+        ("recompress_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

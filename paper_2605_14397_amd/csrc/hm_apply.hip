@@ -106,13 +106,18 @@ struct Side {
     int es, w;         // element bytes, elements per 16-byte granule
 };
 
-// One unit of work: k-step ks of one panel, all its row tiles.
+// One unit of work: k-step ks of one panel, all its row tiles.  A unit past
+// the end of a task is "empty": its loads go through zero-size buffer
+// resources and return zeros, so every loop iteration issues the same loads
+// and the compiler can keep the next unit's loads in flight while the
+// current one is multiplied.
 struct Unit {
     const char* a;     // first granule of the k-step
-    const char* bh;    // this lane's in-vector granule
+    const char* bh;    // the k-step's in-vector granules (lane 0)
     const char* bl;
     int gg;            // granules in this k-step (1..4)
     int far;
+    int valid;
 };
 
 // Walks the flattened sequence of (panel, k-step) units of a task.
@@ -147,15 +152,24 @@ struct Cursor {
     }
 };
 
-__device__ inline Unit make_unit(const Cursor& c, int u, int rows, const Side& nearS, const Side& farS, int lane)
+__device__ inline Unit make_unit(const Cursor& c, bool valid, int u, int rows, const Side& nearS, const Side& farS)
 {
+    Unit x;
+    x.valid = valid ? 1 : 0;
+    if (!valid) {
+        x.a = nearS.A;
+        x.bh = nearS.Bhi;
+        x.bl = nullptr;
+        x.gg = 4;
+        x.far = 0;
+        return x;
+    }
     const Side& S = c.P.far ? farS : nearS;
     const int ks = u - c.base;
     const int Gr = (c.P.cols + S.w - 1) / S.w;
-    Unit x;
     x.gg = min(4, Gr - 4 * ks);
     x.a = S.A + (int64_t)c.P.a_off * S.es + (int64_t)ks * rows * 64;
-    const int64_t boff = (int64_t)c.P.b_off * S.es + ((int64_t)ks * 64 + lane) * 16;
+    const int64_t boff = (int64_t)c.P.b_off * S.es + (int64_t)ks * 64 * 16;
     x.bh = S.Bhi + boff;
     x.bl = S.Blo ? S.Blo + boff : nullptr;
     x.far = c.P.far;
@@ -188,60 +202,96 @@ __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, i
     const int rr_last = rows - 16 * (Rt - 1);
     const uint32_t vfull = gok ? 16u * (uint32_t)(16 * g + i) : kOut;
     const uint32_t vlast = (gok && i < rr_last) ? 16u * (uint32_t)(g * rr_last + i) : kOut;
-    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(x.a, (uint32_t)(rows * gg * 16));
+    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(x.a, x.valid ? (uint32_t)(rows * gg * 16) : 0u);
 #pragma unroll
     for (int r = 0; r < R; ++r)
         a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(
                                           rs, r < Rt - 1 ? vfull : (r == Rt - 1 ? vlast : kOut), r * 256 * gg, 0));
-    bh = *reinterpret_cast<const u4*>(x.bh);
-    bl = x.bl ? *reinterpret_cast<const u4*>(x.bl) : u4{0u, 0u, 0u, 0u};
+    // the in-vector k-step: 64 granules, one per lane
+    const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(x.bh, x.valid ? 1024u : 0u);
+    bh = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)lane, 0, 0));
+    const __amdgpu_buffer_rsrc_t rl = chunk_rsrc(x.bl ? x.bl : x.bh, (x.valid && x.bl) ? 1024u : 0u);
+    bl = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * (uint32_t)lane, 0, 0));
 }
 
-template <int R, class NT, class FT, class ACC>
-__device__ __attribute__((always_inline)) inline void mma_unit(int far, const u4 (&a)[R], u4 bh, u4 bl,
+// With SKIP, tiles r >= Rt (wave-uniform) hold no rows of the task and get
+// no MFMA (phase A runs every rank in one launch sized for the largest);
+// phase-B launches are grouped by exact tile count and multiply all R.
+template <int R, class NT, class FT, class ACC, bool SKIP>
+__device__ __attribute__((always_inline)) inline void mma_unit(int far, int Rt, const u4 (&a)[R], u4 bh, u4 bl,
                                                                 ACC (&acc)[R])
 {
     if (far) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
+        for (int r = 0; r < R; ++r)
+            if (!SKIP || r < Rt) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
     } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
+        for (int r = 0; r < R; ++r)
+            if (!SKIP || r < Rt) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
     }
 }
 
-// Accumulate this wave's units u0, u0 + step, ... of one task, with the
-// loads of the next unit in flight while the current one is multiplied.
-template <int R, class NT, class FT, class ACC>
+// Accumulate this wave's units u0, u0 + step, ... of one task.  The loads
+// of the next units are in flight while the current one is multiplied: two
+// units ahead for up to 4 row tiles, one unit ahead for more (register
+// budget).  Loads are issued unconditionally (empty units past the end), so
+// the control flow around them is static.
+template <int R, class NT, class FT, class ACC, bool SKIP>
 __device__ __attribute__((always_inline)) inline void stream_units(const PanelRef* items, int n_items, int rows,
                                                                     const Side& nearS, const Side& farS, int u0,
                                                                     int step, int lane, ACC (&acc)[R])
 {
     const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
+    const int Rt = __builtin_amdgcn_readfirstlane((rows + 15) >> 4);
     Cursor c;
     c.init(items, n_items, ksn, ksf);
-    u4 a0[R], a1[R], b0h, b0l, b1h, b1l;
     int u = u0;
     if (!c.seek(u, ksn, ksf)) return;
-    Unit x0 = make_unit(c, u, rows, nearS, farS, lane);
-    load_unit<R>(x0, rows, lane, a0, b0h, b0l);
-    while (true) {
-        const bool v1 = c.seek(u + step, ksn, ksf);
-        Unit x1;
-        if (v1) {
-            x1 = make_unit(c, u + step, rows, nearS, farS, lane);
-            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
-        }
-        mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
-        if (!v1) break;
-        const bool v2 = c.seek(u + 2 * step, ksn, ksf);
-        if (v2) {
-            x0 = make_unit(c, u + 2 * step, rows, nearS, farS, lane);
+    if constexpr (R <= 4) {
+        u4 a0[R], a1[R], a2[R], b0h, b0l, b1h, b1l, b2h, b2l;
+        Unit x0 = make_unit(c, true, u, rows, nearS, farS);
+        load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+        bool vb = c.seek(u + step, ksn, ksf);
+        Unit x1 = make_unit(c, vb, u + step, rows, nearS, farS);
+        load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+        while (true) {
+            const bool vc = c.seek(u + 2 * step, ksn, ksf);
+            const Unit x2 = make_unit(c, vc, u + 2 * step, rows, nearS, farS);
+            load_unit<R>(x2, rows, lane, a2, b2h, b2l);
+            mma_unit<R, NT, FT, ACC, SKIP>(x0.far, Rt, a0, b0h, b0l, acc);
+            if (!vb) break;
+            const bool vd = c.seek(u + 3 * step, ksn, ksf);
+            x0 = make_unit(c, vd, u + 3 * step, rows, nearS, farS);
             load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+            mma_unit<R, NT, FT, ACC, SKIP>(x1.far, Rt, a1, b1h, b1l, acc);
+            if (!vc) break;
+            const bool ve = c.seek(u + 4 * step, ksn, ksf);
+            x1 = make_unit(c, ve, u + 4 * step, rows, nearS, farS);
+            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+            mma_unit<R, NT, FT, ACC, SKIP>(x2.far, Rt, a2, b2h, b2l, acc);
+            if (!vd) break;
+            // a0 now holds unit u + 3 step, a1 unit u + 4 step
+            u += 3 * step;
+            vb = ve;
         }
-        mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
-        if (!v2) break;
-        u += 2 * step;
+    } else {
+        u4 a0[R], a1[R], b0h, b0l, b1h, b1l;
+        Unit x0 = make_unit(c, true, u, rows, nearS, farS);
+        load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+        while (true) {
+            const bool v1 = c.seek(u + step, ksn, ksf);
+            const Unit x1 = make_unit(c, v1, u + step, rows, nearS, farS);
+            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+            mma_unit<R, NT, FT, ACC, SKIP>(x0.far, Rt, a0, b0h, b0l, acc);
+            if (!v1) break;
+            const bool v2 = c.seek(u + 2 * step, ksn, ksf);
+            x0 = make_unit(c, v2, u + 2 * step, rows, nearS, farS);
+            load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+            mma_unit<R, NT, FT, ACC, SKIP>(x1.far, Rt, a1, b1h, b1l, acc);
+            if (!v2) break;
+            u += 2 * step;
+        }
     }
 }
 
@@ -298,7 +348,7 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
+    stream_units<R, NT, FT, ACC, true>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
     // only this task's own tiles are written: its T chunk holds ceil(k / 32) * 32
     // rows and its partial slot ceil(k / 16) * 16 rows
     const int Rt = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
@@ -327,7 +377,9 @@ __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks,
 {
     typedef typename AccScalar<ACC>::type S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + wave;
+    const int g = xcd_task(blockIdx.x, gridDim.x, (ntasks + 3) / 4);
+    if (g < 0) return;
+    const int t = 4 * g + wave;
     if (t >= ntasks) return;
     const TaskA T = tasks[t];
     const Bases B = bases[T.op];
@@ -371,7 +423,7 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
+    stream_units<R, NT, FT, ACC, false>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
     reduce_and_store<R, ACC>(acc, T.rows, Y, T.y_off, red, wave, lane);
 }
 
@@ -531,8 +583,9 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
     }
     mark(1);
     if (L.nTasksA > 0) {
-        // one launch sized for the largest rank; smaller ranks leave tiles empty
-        const unsigned grid = (unsigned)((L.nTasksA + 3) / 4);
+        // one launch sized for the largest rank; smaller ranks leave tiles empty;
+        // a multiple of 8 workgroups for the XCD-contiguous task map
+        const unsigned grid = (unsigned)round_up((L.nTasksA + 3) / 4, 8);
         switch (L.maxRA) {
 #define HM_CASE(RR)                                                                                              \
     case RR:                                                                                                     \

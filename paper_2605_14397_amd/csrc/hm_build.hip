@@ -387,6 +387,311 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
 }
 
 // ------------------------------------------------------------------
+// recompression of ACA factors (one workgroup per factorisation)
+// ------------------------------------------------------------------
+// For U V^T of rank k <= kRcMax (columns of U and V contiguous): with
+// D = diag(|u_q|), U D^-1 has unit columns and a well-conditioned Gram
+// matrix (cross-approximation columns shrink with the residual; V D takes
+// the scale), so
+//   (U D^-1)^T (U D^-1) = R^T R     (Cholesky),
+//   U V^T = Q R (V D)^T with Q = U D^-1 R^-1 orthonormal, and
+//   R G R^T = W S^2 W^T,  G = (V D)^T (V D)   (parallel cyclic Jacobi)
+// gives the singular values S of U V^T.  Keep the k' largest with the
+// discarded energy sum_{i >= k'} s_i^2 <= tol^2 sum_i s_i^2 and write
+//   T_u = D^-1 R^-1 W_k',  T_v = D R^T W_k',  U' = U T_u, V' = V T_v
+// (U' V'^T = U V^T exactly when k' = k).  A Cholesky pivot that is not
+// clearly positive leaves the block as it is (k' = -1).
+constexpr int kRcMax = 64;
+constexpr int kRcLd = kRcMax + 1;
+constexpr size_t kRcLds = 4 * (size_t)kRcMax * kRcLd * sizeof(double);
+
+struct RcDesc {
+    int64_t u_off, v_off;  // factor columns: U + q * lu, V + q * lv
+    int64_t lu, lv;
+    int64_t t_off;         // workspace: T_u [k][k'] then T_v [k][k']
+    int32_t k, pad;
+};
+
+// A (k x k, upper triangle of a symmetric matrix) -> its Cholesky factor R
+// (upper).  Returns false when a pivot is not clearly positive.
+__device__ bool rc_cholesky(double* A, int k, int* s_flag)
+{
+    double dmax = 0.0;
+    for (int j = 0; j < k; ++j) dmax = fmax(dmax, A[j * kRcLd + j]);
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = A[j * kRcLd + j];
+            if (!(d > 1e-14 * dmax)) {
+                *s_flag = 1;
+            } else {
+                A[j * kRcLd + j] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        if (*s_flag) return false;
+        const double r = A[j * kRcLd + j];
+        for (int l = j + 1 + threadIdx.x; l < k; l += blockDim.x) A[j * kRcLd + l] /= r;
+        __syncthreads();
+        const int nn = k - j - 1;
+        for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x) {
+            const int i = j + 1 + idx / nn, l = j + 1 + idx % nn;
+            if (l >= i) A[i * kRcLd + l] -= A[j * kRcLd + i] * A[j * kRcLd + l];
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Gram matrix G[a][b] = sum_i X[a][i] X[b][i] (a <= b) of k columns of
+// length L, staged through LDS in chunks; fixed summation order.
+__device__ void rc_gram(const double* __restrict__ X, int64_t L, int k, double* G, double* stage, int stage_cap)
+{
+    const int T = max(1, stage_cap / k);
+    const int npair = k * (k + 1) / 2;
+    constexpr int kPer = (kRcMax * (kRcMax + 1) / 2 + 255) / 256;
+    double acc[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) acc[t] = 0.0;
+    for (int64_t i0 = 0; i0 < L; i0 += T) {
+        const int nt = (int)min((int64_t)T, L - i0);
+        for (int idx = threadIdx.x; idx < k * nt; idx += blockDim.x) {
+            const int q = idx / nt, t = idx % nt;
+            stage[q * T + t] = X[(int64_t)q * L + i0 + t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int pr = threadIdx.x + 256 * t;
+            if (pr < npair) {
+                // pair index -> (a, b), a <= b, row-major over the upper triangle
+                int a = 0, rem = pr;
+                while (rem >= k - a) {
+                    rem -= k - a;
+                    ++a;
+                }
+                const int b = a + rem;
+                double sacc = acc[t];
+                for (int tt = 0; tt < nt; ++tt) sacc += stage[a * T + tt] * stage[b * T + tt];
+                acc[t] = sacc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int pr = threadIdx.x + 256 * t;
+        if (pr < npair) {
+            int a = 0, rem = pr;
+            while (rem >= k - a) {
+                rem -= k - a;
+                ++a;
+            }
+            G[a * kRcLd + a + rem] = acc[t];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, const double* __restrict__ fac,
+                                                     double tol, double* __restrict__ tws, int* __restrict__ out_k)
+{
+    extern __shared__ double lds[];
+    double* A = lds;                   // U^T U -> scaled -> R
+    double* B = A + kRcMax * kRcLd;    // V^T V -> scaled (G)
+    double* C = B + kRcMax * kRcLd;    // R G, then W
+    double* S = C + kRcMax * kRcLd;    // R G R^T -> diagonalised
+    __shared__ int s_flag;
+    __shared__ double s_c[kRcMax / 2], s_s[kRcMax / 2];
+    __shared__ int s_p[kRcMax / 2], s_q[kRcMax / 2];
+    __shared__ double s_red[4];
+    __shared__ int s_rank[kRcMax];
+    __shared__ int s_sel[kRcMax];
+    __shared__ int s_kp;
+    __shared__ double s_d[kRcMax];
+    const RcDesc D = descs[blockIdx.x];
+    const int k = D.k;
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    // ---- Gram matrices (C and S serve as the staging area) ----
+    rc_gram(fac + D.u_off, D.lu, k, A, C, 2 * kRcMax * kRcLd);
+    rc_gram(fac + D.v_off, D.lv, k, B, C, 2 * kRcMax * kRcLd);
+    // ---- column scaling D: unit columns of U, the scale moved into V ----
+    for (int a = threadIdx.x; a < k; a += blockDim.x) s_d[a] = sqrt(A[a * kRcLd + a]);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int a = idx / k, b = idx % k;
+        if (b < a) continue;
+        const double dd = s_d[a] * s_d[b];
+        A[a * kRcLd + b] = dd > 0.0 ? A[a * kRcLd + b] / dd : 0.0;
+        B[a * kRcLd + b] *= dd;
+    }
+    __syncthreads();
+    if (!rc_cholesky(A, k, &s_flag)) {
+        if (threadIdx.x == 0) out_k[blockIdx.x] = -1;
+        return;
+    }
+    // ---- C = R G (G symmetric, upper triangle in B), S = C R^T ----
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int a = idx / k, b = idx % k;
+        double sum = 0.0;
+        for (int c = a; c < k; ++c) sum += A[a * kRcLd + c] * (c <= b ? B[c * kRcLd + b] : B[b * kRcLd + c]);
+        C[a * kRcLd + b] = sum;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int a = idx / k, b = idx % k;
+        double sum = 0.0;
+        for (int c = b; c < k; ++c) sum += C[a * kRcLd + c] * A[b * kRcLd + c];
+        S[a * kRcLd + b] = sum;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) C[(idx / k) * kRcLd + idx % k] = (idx / k == idx % k);
+    __syncthreads();
+    // ---- cyclic Jacobi on S (k padded to even kk; the pad index is inert) ----
+    const int kk = k + (k & 1);
+    double fro2 = 0.0;
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) fro2 += S[a * kRcLd + b] * S[a * kRcLd + b];
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        for (int round = 0; round < kk - 1; ++round) {
+            // round-robin pairing: position 0 fixed, the others rotate
+            for (int pi = threadIdx.x; pi < kk / 2; pi += blockDim.x) {
+                int p0 = pi == 0 ? 0 : 1 + (pi - 1 + round) % (kk - 1);
+                int q0 = 1 + (kk - 2 - pi + round) % (kk - 1);
+                int p = min(p0, q0), q = max(p0, q0);
+                double c = 1.0, sn = 0.0;
+                if (q < k) {
+                    const double apq = S[p * kRcLd + q];
+                    if (apq != 0.0) {
+                        const double th = (S[q * kRcLd + q] - S[p * kRcLd + p]) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sn = t * c;
+                    }
+                }
+                s_p[pi] = p;
+                s_q[pi] = q;
+                s_c[pi] = c;
+                s_s[pi] = sn;
+            }
+            __syncthreads();
+            // rows: S <- J^T S
+            for (int idx = threadIdx.x; idx < (kk / 2) * k; idx += blockDim.x) {
+                const int pi = idx / k, j = idx % k;
+                const int p = s_p[pi], q = s_q[pi];
+                if (q >= k) continue;
+                const double c = s_c[pi], sn = s_s[pi];
+                const double xp = S[p * kRcLd + j], xq = S[q * kRcLd + j];
+                S[p * kRcLd + j] = c * xp - sn * xq;
+                S[q * kRcLd + j] = sn * xp + c * xq;
+            }
+            __syncthreads();
+            // columns: S <- S J, W <- W J
+            for (int idx = threadIdx.x; idx < (kk / 2) * k; idx += blockDim.x) {
+                const int pi = idx / k, j = idx % k;
+                const int p = s_p[pi], q = s_q[pi];
+                if (q >= k) continue;
+                const double c = s_c[pi], sn = s_s[pi];
+                const double xp = S[j * kRcLd + p], xq = S[j * kRcLd + q];
+                S[j * kRcLd + p] = c * xp - sn * xq;
+                S[j * kRcLd + q] = sn * xp + c * xq;
+                const double wp = C[j * kRcLd + p], wq = C[j * kRcLd + q];
+                C[j * kRcLd + p] = c * wp - sn * wq;
+                C[j * kRcLd + q] = sn * wp + c * wq;
+            }
+            __syncthreads();
+        }
+        // off-diagonal energy
+        double off = 0.0;
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x)
+            if (idx / k != idx % k) off += S[(idx / k) * kRcLd + idx % k] * S[(idx / k) * kRcLd + idx % k];
+        for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = off;
+        __syncthreads();
+        off = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        __syncthreads();
+        if (!(off > 1e-30 * fro2)) break;
+    }
+    // ---- order eigenvalues (descending, ties by index) and choose k' ----
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const double li = S[i * kRcLd + i];
+        int r = 0;
+        for (int j = 0; j < k; ++j) {
+            const double lj = S[j * kRcLd + j];
+            if (lj > li || (lj == li && j < i)) ++r;
+        }
+        s_rank[i] = r;
+        s_sel[r] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double total = 0.0;
+        for (int r = 0; r < k; ++r) total += fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
+        double tail = 0.0;
+        int kp = k;
+        // drop from the smallest while the discarded energy stays within tol^2
+        for (int r = k - 1; r >= 1; --r) {
+            const double lr = fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
+            if (tail + lr > tol * tol * total) break;
+            tail += lr;
+            kp = r;
+        }
+        s_kp = kp;
+        out_k[blockIdx.x] = kp;
+    }
+    __syncthreads();
+    const int kp = s_kp;
+    if (kp >= k) return;
+    // ---- T_u = D^-1 R^-1 W_k' (back substitution per column), T_v = D R^T W_k' ----
+    double* Tu = tws + D.t_off;
+    double* Tv = Tu + (int64_t)k * kp;
+    for (int col = threadIdx.x; col < kp; col += blockDim.x) {
+        const int e = s_sel[col];
+        for (int i = k - 1; i >= 0; --i) {
+            double sum = C[i * kRcLd + e];
+            for (int c = i + 1; c < k; ++c) sum -= A[i * kRcLd + c] * Tu[(int64_t)c * kp + col];
+            Tu[(int64_t)i * kp + col] = sum / A[i * kRcLd + i];
+        }
+        for (int i = 0; i < k; ++i) Tu[(int64_t)i * kp + col] /= s_d[i];
+    }
+    for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
+        const int q = idx / kp, col = idx % kp;
+        const int e = s_sel[col];
+        double sum = 0.0;
+        for (int c = 0; c <= q; ++c) sum += A[c * kRcLd + q] * C[c * kRcLd + e];
+        Tv[(int64_t)q * kp + col] = sum * s_d[q];
+    }
+}
+
+// X'[q'][i] = sum_q X[q][i] T[q][q'] for the U and V factors of one block
+struct RcApply {
+    int64_t src_u, src_v, dst_u, dst_v, lu, lv, t_off;
+    int32_t k, kp;
+};
+
+__global__ void k_rc_apply(const RcApply* __restrict__ d, const double* __restrict__ fac,
+                           const double* __restrict__ tws, double* __restrict__ out)
+{
+    const RcApply D = d[blockIdx.y];
+    const int64_t nu = D.lu * D.kp, nv = D.lv * D.kp;
+    const double* Tu = tws + D.t_off;
+    const double* Tv = Tu + (int64_t)D.k * D.kp;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nu + nv;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const bool isu = idx < nu;
+        const int64_t e = isu ? idx : idx - nu;
+        const int64_t L = isu ? D.lu : D.lv;
+        const int col = (int)(e / L);
+        const int64_t i = e - (int64_t)col * L;
+        const double* X = fac + (isu ? D.src_u : D.src_v);
+        const double* T = isu ? Tu : Tv;
+        double sum = 0.0;
+        for (int q = 0; q < D.k; ++q) sum += X[(int64_t)q * L + i] * T[(int64_t)q * D.kp + col];
+        out[(isu ? D.dst_u : D.dst_v) + e] = sum;
+    }
+}
+
+// ------------------------------------------------------------------
 // packing into the apply layout
 // ------------------------------------------------------------------
 // Panel row r reads source row (r / rper) * rstride + roff + r % rper (and
@@ -731,10 +1036,18 @@ void build_tasksA(const Op& op, Variant& v, int items_per_task)
         }
         if (!direct) red.push_back(rd);
     }
-    // longest first so the tail of the launch is short
-    std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
-        return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
-    });
+    // The launch gives each XCD one contiguous eighth of the task list (four
+    // tasks per workgroup).  Order the list by the in-vector chunk its first
+    // sub-panel reads, so one XCD's L2 holds only its share of X; inside each
+    // share, longest first so the tail of the launch is short.
+    std::stable_sort(ta.begin(), ta.end(),
+                     [&](const TaskA& a, const TaskA& b) { return ia[a.item_begin].b_off < ia[b.item_begin].b_off; });
+    const size_t share = 4 * (size_t)(round_up((int64_t)(ta.size() + 3) / 4, 8) / 8);
+    for (size_t x0 = 0; x0 < ta.size(); x0 += std::max<size_t>(1, share))
+        std::stable_sort(ta.begin() + x0, ta.begin() + std::min(ta.size(), x0 + share),
+                         [](const TaskA& a, const TaskA& b) {
+                             return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
+                         });
     v.maxRA = 1;
     for (const TaskA& t : ta) {
         const int R = (t.rows + 15) / 16;
@@ -775,6 +1088,94 @@ void upload_tasks(Variant& v, hipStream_t s)
     std::vector<Bases> b(1, v.host_bases());
     upload(v.bases, b, s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+// Recompress every factorisation of rank 2..kRcMax at relative Frobenius
+// tolerance tol; the others are copied unchanged.  Replaces d_fac.
+static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
+{
+    std::vector<RcDesc> rc;
+    std::vector<int> which;
+    int64_t tws = 0;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        if (L.rank < 2 || L.rank > kRcMax) continue;
+        rc.push_back(RcDesc{L.u_off, L.v_off, L.comps * L.m, L.comps * L.n, tws, L.rank, 0});
+        which.push_back((int)b);
+        tws += 2 * (int64_t)L.rank * L.rank;
+    }
+    std::vector<int> kp(rc.size(), -1);
+    DevBuf d_t(std::max<int64_t>(1, tws) * sizeof(double));
+    if (!rc.empty()) {
+        DevBuf d_rc, d_k(rc.size() * sizeof(int));
+        upload(d_rc, rc, s);
+        HM_CHECK_HIP(hipFuncSetAttribute((const void*)k_recompress, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)kRcLds));
+        hipLaunchKernelGGL(k_recompress, dim3((unsigned)rc.size()), dim3(256), kRcLds, s, d_rc.as<RcDesc>(),
+                           d_fac.as<double>(), tol, d_t.as<double>(), d_k.as<int>());
+        HM_CHECK_HIP(hipGetLastError());
+        HM_CHECK_HIP(hipMemcpyAsync(kp.data(), d_k.get(), kp.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    // new compact store: recompressed blocks through k_rc_apply, the rest copied
+    std::vector<int> newk(op.lr.size());
+    for (size_t b = 0; b < op.lr.size(); ++b) newk[b] = op.lr[b].rank;
+    std::vector<int> slot(op.lr.size(), -1);
+    for (size_t q = 0; q < which.size(); ++q)
+        if (kp[q] > 0 && kp[q] < op.lr[which[q]].rank) {
+            newk[which[q]] = kp[q];
+            slot[which[q]] = (int)q;
+        }
+    int64_t total = 0;
+    std::vector<int64_t> nu(op.lr.size()), nv(op.lr.size());
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        nu[b] = total;
+        total += (int64_t)newk[b] * L.comps * L.m;
+        nv[b] = total;
+        total += (int64_t)newk[b] * L.comps * L.n;
+    }
+    DevBuf out(std::max<int64_t>(1, total) * sizeof(double));
+    std::vector<RcApply> ap;
+    std::vector<CompactDesc> cp;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        if (newk[b] == 0) continue;
+        if (slot[b] >= 0) {
+            ap.push_back(RcApply{L.u_off, L.v_off, nu[b], nv[b], L.comps * L.m, L.comps * L.n, rc[slot[b]].t_off,
+                                 L.rank, newk[b]});
+        } else {
+            cp.push_back(CompactDesc{L.u_off, nu[b], (int64_t)L.rank * L.comps * L.m});
+            cp.push_back(CompactDesc{L.v_off, nv[b], (int64_t)L.rank * L.comps * L.n});
+        }
+    }
+    if (!ap.empty()) {
+        DevBuf d_ap;
+        upload(d_ap, ap, s);
+        for (size_t c0 = 0; c0 < ap.size(); c0 += 65535) {
+            const unsigned nb = (unsigned)std::min<size_t>(65535, ap.size() - c0);
+            hipLaunchKernelGGL(k_rc_apply, dim3(32, nb), dim3(256), 0, s, d_ap.as<RcApply>() + c0, d_fac.as<double>(),
+                               d_t.as<double>(), out.as<double>());
+            HM_CHECK_HIP(hipGetLastError());
+        }
+    }
+    if (!cp.empty()) {
+        DevBuf d_cp;
+        upload(d_cp, cp, s);
+        for (size_t c0 = 0; c0 < cp.size(); c0 += 65535) {
+            const unsigned nb = (unsigned)std::min<size_t>(65535, cp.size() - c0);
+            hipLaunchKernelGGL(k_compact, dim3(64, nb), dim3(256), 0, s, d_cp.as<CompactDesc>() + c0,
+                               d_fac.as<double>(), out.as<double>());
+            HM_CHECK_HIP(hipGetLastError());
+        }
+    }
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        op.lr[b].rank = newk[b];
+        op.lr[b].u_off = nu[b];
+        op.lr[b].v_off = nv[b];
+    }
+    d_fac = std::move(out);
 }
 
 void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStream_t s)
@@ -1046,6 +1447,22 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         HM_CHECK_HIP(hipStreamSynchronize(s));
         batch_fac.clear();
     }
+    // SVD truncation of the cross approximations at half the block tolerance
+    // (the cross approximation itself stops near the other half)
+    int64_t rank_sum_aca = rank_sum;
+    double t_rc0 = now_ms();
+    if (o.recompress) {
+        recompress_factors(op, d_fac, 0.5 * o.aca_tol, s);
+        rank_sum = 0;
+        rmin = 1 << 30;
+        rmax = 0;
+        for (const LowRank& L : op.lr) {
+            rank_sum += L.rank;
+            rmin = std::min(rmin, L.rank);
+            rmax = std::max(rmax, L.rank);
+        }
+    }
+    double t_rc1 = now_ms();
     sort_blocks(pm);  // dense list may have grown; keep it in target order
     double t1 = now_ms();
     // ---- dense leaves: FP64 coefficients ----
@@ -1122,7 +1539,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     st.near_prec = o.near_prec;
     st.far_prec = o.far_prec;
     st.coef_ms = t2 - t1;
-    st.aca_ms = t1 - t0;
+    st.aca_ms = t_rc0 - t0;
     st.pack_ms = t3 - t2;
     st.build_ms = t3 - t_start;
     int64_t maxleaf = 0;
@@ -1138,6 +1555,8 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     st.bytes_far_u = op.main.bytes_far_u;
     st.bytes_far_v = op.main.bytes_far_v;
     st.rank_sum = rank_sum;
+    st.rank_sum_aca = rank_sum_aca;
+    st.recompress_ms = t_rc1 - t_rc0;
 }
 
 }  // namespace hm

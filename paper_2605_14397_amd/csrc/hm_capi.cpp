@@ -147,7 +147,7 @@ void hm_build_opts_default(hm_build_opts* o)
     o->near_prec = HM_F64;
     o->far_prec = HM_F64;
     o->keep_f64_reference = 0;
-    o->recompress = 0;
+    o->recompress = 1;
 }
 
 hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const hm_build_opts* opts, void* hip_stream,
@@ -160,7 +160,6 @@ hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const 
         hm_build_opts o;
         hm_build_opts_default(&o);
         if (opts) o = *opts;
-        HM_REQUIRE(!o.recompress, HM_EUNSUPPORTED, "recompression is not provided");
         require_gfx950();
         std::unique_ptr<hm_op> h(new hm_op());
         h->op.young = young;

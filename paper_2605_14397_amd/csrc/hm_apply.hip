@@ -214,21 +214,18 @@ __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, i
     bl = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * (uint32_t)lane, 0, 0));
 }
 
-// With SKIP, tiles r >= Rt (wave-uniform) hold no rows of the task and get
-// no MFMA (phase A runs every rank in one launch sized for the largest);
-// phase-B launches are grouped by exact tile count and multiply all R.
-template <int R, class NT, class FT, class ACC, bool SKIP>
-__device__ __attribute__((always_inline)) inline void mma_unit(int far, int Rt, const u4 (&a)[R], u4 bh, u4 bl,
+// Every launch (phase A and B) is compiled for its tasks' own row-tile
+// count, so all R tiles are multiplied (a partial last tile reads zeros).
+template <int R, class NT, class FT, class ACC>
+__device__ __attribute__((always_inline)) inline void mma_unit(int far, const u4 (&a)[R], u4 bh, u4 bl,
                                                                 ACC (&acc)[R])
 {
     if (far) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (!SKIP || r < Rt) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
+        for (int r = 0; r < R; ++r) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
     } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (!SKIP || r < Rt) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
+        for (int r = 0; r < R; ++r) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
     }
 }
 
@@ -237,13 +234,12 @@ __device__ __attribute__((always_inline)) inline void mma_unit(int far, int Rt, 
 // units ahead for up to 4 row tiles, one unit ahead for more (register
 // budget).  Loads are issued unconditionally (empty units past the end), so
 // the control flow around them is static.
-template <int R, class NT, class FT, class ACC, bool SKIP>
+template <int R, class NT, class FT, class ACC>
 __device__ __attribute__((always_inline)) inline void stream_units(const PanelRef* items, int n_items, int rows,
                                                                     const Side& nearS, const Side& farS, int u0,
                                                                     int step, int lane, ACC (&acc)[R])
 {
     const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
-    const int Rt = __builtin_amdgcn_readfirstlane((rows + 15) >> 4);
     Cursor c;
     c.init(items, n_items, ksn, ksf);
     int u = u0;
@@ -259,17 +255,17 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
             const bool vc = c.seek(u + 2 * step, ksn, ksf);
             const Unit x2 = make_unit(c, vc, u + 2 * step, rows, nearS, farS);
             load_unit<R>(x2, rows, lane, a2, b2h, b2l);
-            mma_unit<R, NT, FT, ACC, SKIP>(x0.far, Rt, a0, b0h, b0l, acc);
+            mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!vb) break;
             const bool vd = c.seek(u + 3 * step, ksn, ksf);
             x0 = make_unit(c, vd, u + 3 * step, rows, nearS, farS);
             load_unit<R>(x0, rows, lane, a0, b0h, b0l);
-            mma_unit<R, NT, FT, ACC, SKIP>(x1.far, Rt, a1, b1h, b1l, acc);
+            mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!vc) break;
             const bool ve = c.seek(u + 4 * step, ksn, ksf);
             x1 = make_unit(c, ve, u + 4 * step, rows, nearS, farS);
             load_unit<R>(x1, rows, lane, a1, b1h, b1l);
-            mma_unit<R, NT, FT, ACC, SKIP>(x2.far, Rt, a2, b2h, b2l, acc);
+            mma_unit<R, NT, FT, ACC>(x2.far, a2, b2h, b2l, acc);
             if (!vd) break;
             // a0 now holds unit u + 3 step, a1 unit u + 4 step
             u += 3 * step;
@@ -283,12 +279,12 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
             const bool v1 = c.seek(u + step, ksn, ksf);
             const Unit x1 = make_unit(c, v1, u + step, rows, nearS, farS);
             load_unit<R>(x1, rows, lane, a1, b1h, b1l);
-            mma_unit<R, NT, FT, ACC, SKIP>(x0.far, Rt, a0, b0h, b0l, acc);
+            mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!v1) break;
             const bool v2 = c.seek(u + 2 * step, ksn, ksf);
             x0 = make_unit(c, v2, u + 2 * step, rows, nearS, farS);
             load_unit<R>(x0, rows, lane, a0, b0h, b0l);
-            mma_unit<R, NT, FT, ACC, SKIP>(x1.far, Rt, a1, b1h, b1l, acc);
+            mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!v2) break;
             u += 2 * step;
         }
@@ -348,7 +344,7 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC, true>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
     // only this task's own tiles are written: its T chunk holds ceil(k / 32) * 32
     // rows and its partial slot ceil(k / 16) * 16 rows
     const int Rt = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
@@ -370,7 +366,8 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
             for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
-// One launch, sized for the largest rank; one wavefront per task.
+// One launch per row-tile count R (tasks grouped by R at build time); one
+// wavefront per task.
 template <int R, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
@@ -423,7 +420,7 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC, false>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
     reduce_and_store<R, ACC>(acc, T.rows, Y, T.y_off, red, wave, lane);
 }
 
@@ -536,7 +533,7 @@ LaunchSet launch_set(const Variant& v)
     L.bases = v.bases.as<Bases>();
     L.tasksA = v.tasksA.as<TaskA>();
     L.nTasksA = v.nTasksA;
-    L.maxRA = v.maxRA;
+    for (int r = 0; r < kRowTilesMax; ++r) L.groupA[r] = v.groupA[r];
     L.itemsA = v.itemsA.as<PanelRef>();
     L.reduce = v.reduce.as<ReduceDesc>();
     L.nReduce = v.nReduce;
@@ -582,15 +579,16 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
             hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
     }
     mark(1);
-    if (L.nTasksA > 0) {
-        // one launch sized for the largest rank; smaller ranks leave tiles empty;
+    for (int R = kRowTilesMax; R >= 1; --R) {
+        const int begin = L.groupA[R - 1].first, count = L.groupA[R - 1].second;
+        if (count == 0) continue;
         // a multiple of 8 workgroups for the XCD-contiguous task map
-        const unsigned grid = (unsigned)round_up((L.nTasksA + 3) / 4, 8);
-        switch (L.maxRA) {
+        const unsigned grid = (unsigned)round_up((count + 3) / 4, 8);
+        const TaskA* ta = L.tasksA + begin;
+        switch (R) {
 #define HM_CASE(RR)                                                                                              \
     case RR:                                                                                                     \
-        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksA, L.nTasksA, L.itemsA,  \
-                           L.bases);                                                                             \
+        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3(grid), dim3(256), 0, s, ta, count, L.itemsA, L.bases);  \
         break;
             HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
             HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)

@@ -50,7 +50,6 @@ struct Batch {
         std::vector<ReduceDesc> rd;
         std::vector<TaskB> tb;
         std::vector<std::vector<TaskB>> byR(kRowTilesMax);
-        int maxRA = 1;
         for (size_t k = 0; k < ops.size(); ++k) {
             const Variant& v = ops[k]->main;
             hb.push_back(v.host_bases());
@@ -71,15 +70,11 @@ struct Batch {
                 t.op = (int32_t)k;
                 byR[(t.rows + 15) / 16 - 1].push_back(t);
             }
-            maxRA = std::max(maxRA, v.maxRA);
         }
-        // the largest tasks of every operator first, so the merged launch ends evenly
-        std::stable_sort(ta.begin(), ta.end(), [](const TaskA& a, const TaskA& b) {
-            return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
-        });
         L = LaunchSet();
         L.near_prec = near_prec;
         L.far_prec = far_prec;
+        order_tasksA(ta, ia, L.groupA);
         for (int R = kRowTilesMax; R >= 1; --R) {
             L.groupB[R - 1] = {(int)tb.size(), (int)byR[R - 1].size()};
             tb.insert(tb.end(), byR[R - 1].begin(), byR[R - 1].end());
@@ -94,7 +89,6 @@ struct Batch {
         L.bases = bases.as<Bases>();
         L.tasksA = tasksA.as<TaskA>();
         L.nTasksA = (int)ta.size();
-        L.maxRA = maxRA;
         L.itemsA = itemsA.as<PanelRef>();
         L.reduce = reduce.as<ReduceDesc>();
         L.nReduce = (int)rd.size();

@@ -1036,27 +1036,38 @@ void build_tasksA(const Op& op, Variant& v, int items_per_task)
         }
         if (!direct) red.push_back(rd);
     }
-    // The launch gives each XCD one contiguous eighth of the task list (four
-    // tasks per workgroup).  Order the list by the in-vector chunk its first
-    // sub-panel reads, so one XCD's L2 holds only its share of X; inside each
-    // share, longest first so the tail of the launch is short.
-    std::stable_sort(ta.begin(), ta.end(),
-                     [&](const TaskA& a, const TaskA& b) { return ia[a.item_begin].b_off < ia[b.item_begin].b_off; });
-    const size_t share = 4 * (size_t)(round_up((int64_t)(ta.size() + 3) / 4, 8) / 8);
-    for (size_t x0 = 0; x0 < ta.size(); x0 += std::max<size_t>(1, share))
-        std::stable_sort(ta.begin() + x0, ta.begin() + std::min(ta.size(), x0 + share),
-                         [](const TaskA& a, const TaskA& b) {
-                             return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
-                         });
-    v.maxRA = 1;
-    for (const TaskA& t : ta) {
-        const int R = (t.rows + 15) / 16;
-        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
-        v.maxRA = std::max(v.maxRA, R);
-    }
+    order_tasksA(ta, ia, v.groupA);
     v.nTasksA = (int)ta.size();
     v.nReduce = (int)red.size();
     v.tpart_elems = tpart;
+}
+
+void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, std::pair<int, int>* groupA)
+{
+    std::vector<std::vector<TaskA>> byR(kRowTilesMax);
+    for (const TaskA& t : ta) {
+        const int R = (t.rows + 15) / 16;
+        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
+        byR[R - 1].push_back(t);
+    }
+    ta.clear();
+    for (int R = kRowTilesMax; R >= 1; --R) {
+        std::vector<TaskA>& g = byR[R - 1];
+        // each XCD runs one contiguous eighth of the group (four tasks per
+        // workgroup): ordered by source chunk, one XCD's L2 holds only its
+        // share of X; longest first inside each share for a short tail
+        std::stable_sort(g.begin(), g.end(), [&](const TaskA& a, const TaskA& b) {
+            return items[a.item_begin].b_off < items[b.item_begin].b_off;
+        });
+        const size_t share = 4 * (size_t)(round_up((int64_t)(g.size() + 3) / 4, 8) / 8);
+        for (size_t x0 = 0; x0 < g.size(); x0 += std::max<size_t>(1, share))
+            std::stable_sort(g.begin() + x0, g.begin() + std::min(g.size(), x0 + share),
+                             [](const TaskA& a, const TaskA& b) {
+                                 return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
+                             });
+        groupA[R - 1] = {(int)ta.size(), (int)g.size()};
+        ta.insert(ta.end(), g.begin(), g.end());
+    }
 }
 
 Bases Variant::host_bases() const

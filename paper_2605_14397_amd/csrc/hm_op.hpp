@@ -15,7 +15,7 @@ struct Variant {
     DevBuf tasksB, itemsB, tasksA, itemsA, reduce;
     int nTasksB = 0, nTasksA = 0, nReduce = 0;
     std::pair<int, int> groupB[kRowTilesMax] = {};  // phase-B tasks with R row tiles: (first, count)
-    int maxRA = 1;                                  // largest row-tile count of a phase-A task
+    std::pair<int, int> groupA[kRowTilesMax] = {};  // phase-A tasks with R row tiles: (first, count)
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
     // workspaces (sized for 16 right-hand sides)
@@ -42,7 +42,8 @@ struct LaunchSet {
     int near_prec = HM_F64, far_prec = HM_F64;
     const Bases* bases = nullptr;
     const TaskA* tasksA = nullptr;
-    int nTasksA = 0, maxRA = 1;
+    int nTasksA = 0;
+    std::pair<int, int> groupA[kRowTilesMax] = {};
     const PanelRef* itemsA = nullptr;
     const ReduceDesc* reduce = nullptr;
     int nReduce = 0;
@@ -131,6 +132,10 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
                     int64_t max_ne, hipStream_t s, hipEvent_t* ev);
 // (re)build the phase-A task list of a variant with a given task size
 void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
+// Order a phase-A task list for launch: grouped by row-tile count (one
+// launch per group, largest first); inside a group ordered by the in-vector
+// chunk of the first sub-panel, then longest first inside each XCD's share.
+void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, std::pair<int, int>* groupA);
 void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 

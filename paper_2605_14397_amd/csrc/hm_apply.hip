@@ -13,6 +13,8 @@
 //            tangent epilogue y = E x - D x, identity on inactive elements
 // The matrix streams from HBM once per product; X and T chunks are small
 // and re-read from cache.
+#include <type_traits>
+
 #include "hm_op.hpp"
 #include "hm_util.hpp"
 
@@ -189,24 +191,28 @@ __device__ inline __amdgpu_buffer_rsrc_t chunk_rsrc(const char* base, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
-// Rt = ceil(rows / 16) <= R tiles hold data; tiles r >= Rt read zero.
+// Tiles r0 .. r0 + R - 1 of the unit's panel (rows rows, Rf = ceil(rows / 16)
+// tiles; the last may be partial); tiles at or past Rf read zero.
 template <int R>
-__device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int lane, u4 (&a)[R], u4& bh,
-                                                                 u4& bl)
+__device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int r0, int lane, u4 (&a)[R],
+                                                                 u4& bh, u4& bl)
 {
     const int g = lane >> 4, i = lane & 15;
     const uint32_t kOut = 0x80000000u;
     const int gg = __builtin_amdgcn_readfirstlane(x.gg);
-    const int Rt = __builtin_amdgcn_readfirstlane((rows + 15) >> 4);
+    const int Rf = __builtin_amdgcn_readfirstlane((rows + 15) >> 4);
+    r0 = __builtin_amdgcn_readfirstlane(r0);
     const bool gok = g < gg;
-    const int rr_last = rows - 16 * (Rt - 1);
+    const int rr_last = rows - 16 * (Rf - 1);
     const uint32_t vfull = gok ? 16u * (uint32_t)(16 * g + i) : kOut;
     const uint32_t vlast = (gok && i < rr_last) ? 16u * (uint32_t)(g * rr_last + i) : kOut;
     const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(x.a, x.valid ? (uint32_t)(rows * gg * 16) : 0u);
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
+        const int t = r0 + r;
         a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(
-                                          rs, r < Rt - 1 ? vfull : (r == Rt - 1 ? vlast : kOut), r * 256 * gg, 0));
+                                          rs, t < Rf - 1 ? vfull : (t == Rf - 1 ? vlast : kOut), t * 256 * gg, 0));
+    }
     // the in-vector k-step: 64 granules, one per lane
     const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(x.bh, x.valid ? 1024u : 0u);
     bh = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)lane, 0, 0));
@@ -220,6 +226,12 @@ template <int R, class NT, class FT, class ACC>
 __device__ __attribute__((always_inline)) inline void mma_unit(int far, const u4 (&a)[R], u4 bh, u4 bl,
                                                                 ACC (&acc)[R])
 {
+    if constexpr (std::is_same<NT, FT>::value) {
+        // one element type: no branch (keeps the loop straight for the wait counters)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = Mma<NT>::run(a[r], bh, bl, acc[r]);
+        return;
+    }
     if (far) {
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = Mma<FT>::run(a[r], bh, bl, acc[r]);
@@ -236,8 +248,8 @@ __device__ __attribute__((always_inline)) inline void mma_unit(int far, const u4
 // the control flow around them is static.
 template <int R, class NT, class FT, class ACC>
 __device__ __attribute__((always_inline)) inline void stream_units(const PanelRef* items, int n_items, int rows,
-                                                                    const Side& nearS, const Side& farS, int u0,
-                                                                    int step, int lane, ACC (&acc)[R])
+                                                                    int r0, const Side& nearS, const Side& farS,
+                                                                    int u0, int step, int lane, ACC (&acc)[R])
 {
     const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
     Cursor c;
@@ -247,24 +259,24 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
     if constexpr (R <= 4) {
         u4 a0[R], a1[R], a2[R], b0h, b0l, b1h, b1l, b2h, b2l;
         Unit x0 = make_unit(c, true, u, rows, nearS, farS);
-        load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+        load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
         bool vb = c.seek(u + step, ksn, ksf);
         Unit x1 = make_unit(c, vb, u + step, rows, nearS, farS);
-        load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+        load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
         while (true) {
             const bool vc = c.seek(u + 2 * step, ksn, ksf);
             const Unit x2 = make_unit(c, vc, u + 2 * step, rows, nearS, farS);
-            load_unit<R>(x2, rows, lane, a2, b2h, b2l);
+            load_unit<R>(x2, rows, r0, lane, a2, b2h, b2l);
             mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!vb) break;
             const bool vd = c.seek(u + 3 * step, ksn, ksf);
             x0 = make_unit(c, vd, u + 3 * step, rows, nearS, farS);
-            load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+            load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
             mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!vc) break;
             const bool ve = c.seek(u + 4 * step, ksn, ksf);
             x1 = make_unit(c, ve, u + 4 * step, rows, nearS, farS);
-            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+            load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
             mma_unit<R, NT, FT, ACC>(x2.far, a2, b2h, b2l, acc);
             if (!vd) break;
             // a0 now holds unit u + 3 step, a1 unit u + 4 step
@@ -274,16 +286,16 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
     } else {
         u4 a0[R], a1[R], b0h, b0l, b1h, b1l;
         Unit x0 = make_unit(c, true, u, rows, nearS, farS);
-        load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+        load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
         while (true) {
             const bool v1 = c.seek(u + step, ksn, ksf);
             const Unit x1 = make_unit(c, v1, u + step, rows, nearS, farS);
-            load_unit<R>(x1, rows, lane, a1, b1h, b1l);
+            load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
             mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!v1) break;
             const bool v2 = c.seek(u + 2 * step, ksn, ksf);
             x0 = make_unit(c, v2, u + 2 * step, rows, nearS, farS);
-            load_unit<R>(x0, rows, lane, a0, b0h, b0l);
+            load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
             mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!v2) break;
             u += 2 * step;
@@ -291,10 +303,12 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
     }
 }
 
-// Sum the four waves' accumulators in a fixed order; wave 0 writes rows < rows.
+// Sum the four waves' accumulators in a fixed order; wave 0 writes the
+// window's rows 16 (r0 + r) + i below rows.
 template <int R, class ACC, class S>
-__device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc)[R], int rows, S* __restrict__ out,
-                                                                        int64_t row0, S* red, int wave, int lane)
+__device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc)[R], int rows, int r0,
+                                                                        S* __restrict__ out, int64_t row0, S* red,
+                                                                        int wave, int lane)
 {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -306,7 +320,7 @@ __device__ __attribute__((always_inline)) inline void reduce_and_store(ACC (&acc
                 S s = acc[r][v] + red[lane * 4 + v];
                 s += red[256 + lane * 4 + v];
                 s += red[512 + lane * 4 + v];
-                int row = 16 * r + AccScalar<ACC>::row(lane, v);
+                int row = 16 * (r0 + r) + AccScalar<ACC>::row(lane, v);
                 if (row < rows) out[(row0 + row) * kNrhs + (lane & 15)] = s;
             }
         }
@@ -344,26 +358,29 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, farS, farS, 0, 1, lane, acc);
-    // only this task's own tiles are written: its T chunk holds ceil(k / 32) * 32
-    // rows and its partial slot ceil(k / 16) * 16 rows
-    const int Rt = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, T.r0, farS, farS, 0, 1, lane, acc);
+    // only this task's own tiles are written (tiles r0 .. r0 + R - 1 below
+    // ceil(k / 16)): its T chunk holds ceil(k / 32) * 32 rows and its partial
+    // slot ceil(k / 16) * 16 rows
+    const int Rf = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
     if (T.direct) {
         // the task covers the whole block: write its T chunk directly
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (r < Rt)
+            if (T.r0 + r < Rf)
                 for (int v = 0; v < 4; ++v)
                     store_t<FT>(thi, tlo,
-                                T.t_off + bfrag_offset(Mma<FT>::w, 16 * r + AccScalar<ACC>::row(lane, v), lane & 15),
+                                T.t_off + bfrag_offset(Mma<FT>::w, 16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v),
+                                                       lane & 15),
                                 acc[r][v]);
         return;
     }
     auto* out = tpart + T.out_off;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (r < Rt)
-            for (int v = 0; v < 4; ++v) out[(16 * r + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
+        if (T.r0 + r < Rf)
+            for (int v = 0; v < 4; ++v)
+                out[(16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
 // One launch per row-tile count R (tasks grouped by R at build time); one
@@ -420,8 +437,8 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
-    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, nearS, farS, wave, 4, lane, acc);
-    reduce_and_store<R, ACC>(acc, T.rows, Y, T.y_off, red, wave, lane);
+    stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, T.r0, nearS, farS, wave, 4, lane, acc);
+    reduce_and_store<R, ACC>(acc, T.rows, T.r0, Y, T.y_off, red, wave, lane);
 }
 
 // One launch per row-tile count R (tasks are grouped by R at build time),

@@ -68,7 +68,7 @@ struct Batch {
             for (TaskB t : v.hTasksB) {
                 t.item_begin += ib0;
                 t.op = (int32_t)k;
-                byR[(t.rows + 15) / 16 - 1].push_back(t);
+                byR[window_tiles(t.rows, t.r0) - 1].push_back(t);
             }
         }
         L = LaunchSet();

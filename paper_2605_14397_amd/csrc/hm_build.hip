@@ -956,19 +956,20 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         const Cluster& c = p.nodes[p.leaves[lf]];
         for (int sec = 0; sec < 2; ++sec) {
             const auto& its = itemsB[2 * (size_t)lf + sec];
-            TaskB t{op.leaf_xoff[lf] + sec_off(c.size(), sec), sec_rows(c.size(), sec), (int32_t)ib.size(),
-                    (int32_t)its.size(), 0};
+            const int rows = sec_rows(c.size(), sec);
+            for (int r0 = 0; r0 < (rows + 15) / 16; r0 += kTileWindow)
+                tb.push_back(TaskB{op.leaf_xoff[lf] + sec_off(c.size(), sec), rows, (int32_t)ib.size(),
+                                   (int32_t)its.size(), 0, r0, 0});
             ib.insert(ib.end(), its.begin(), its.end());
-            tb.push_back(t);
         }
     }
-    // group phase-B tasks by row-tile count (one launch per group), leaf order kept inside a group
+    // group phase-B tasks by window size (one launch per group), leaf order kept inside a group
     std::stable_sort(tb.begin(), tb.end(), [](const TaskB& a, const TaskB& b) {
-        return (a.rows + 15) / 16 > (b.rows + 15) / 16;
+        return window_tiles(a.rows, a.r0) > window_tiles(b.rows, b.r0);
     });
     for (int R = 1; R <= kRowTilesMax; ++R) v.groupB[R - 1] = {0, 0};
     for (size_t q = 0; q < tb.size(); ++q) {
-        const int R = (tb[q].rows + 15) / 16;
+        const int R = window_tiles(tb[q].rows, tb[q].r0);
         HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "leaf rows out of range");
         if (v.groupB[R - 1].second == 0) v.groupB[R - 1].first = (int)q;
         v.groupB[R - 1].second++;
@@ -1028,7 +1029,11 @@ void build_tasksA(const Op& op, Variant& v, int items_per_task)
                 ia.push_back(vs[q]);
                 t.n_items++;
             }
-            ta.push_back(t);
+            // one task per row window; the windows share the items and the slot
+            for (int r0 = 0; r0 < (L.rank + 15) / 16; r0 += kTileWindow) {
+                t.r0 = r0;
+                ta.push_back(t);
+            }
             if (!direct) {
                 tpart += slot;
                 rd.n_slots++;
@@ -1046,7 +1051,7 @@ void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, st
 {
     std::vector<std::vector<TaskA>> byR(kRowTilesMax);
     for (const TaskA& t : ta) {
-        const int R = (t.rows + 15) / 16;
+        const int R = window_tiles(t.rows, t.r0);
         HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
         byR[R - 1].push_back(t);
     }

@@ -211,11 +211,23 @@ struct PanelRef {
     int32_t pad;
 };
 
-struct TaskB {        // one target leaf
-    int64_t y_off;    // output rows start in Y (padded leaf offset)
-    int32_t rows;     // 3 m
+// Tasks cover a window of at most kTileWindow row tiles of their panels
+// (tiles r0 .. r0 + R - 1), so every launch runs a small accumulator set at
+// high occupancy; the windows of one panel set re-read its in-vector chunks.
+constexpr int kTileWindow = 4;
+__host__ __device__ inline int window_tiles(int rows, int r0)
+{
+    const int t = (rows + 15) / 16 - r0;
+    return t < kTileWindow ? t : kTileWindow;
+}
+
+struct TaskB {        // one row window of one section of a target leaf
+    int64_t y_off;    // output rows start in Y (section start)
+    int32_t rows;     // rows of the section (= rows of each of its panels)
     int32_t item_begin, n_items;
     int32_t op;       // operator index into the base-pointer table
+    int32_t r0;       // first row tile of the window
+    int32_t pad;
 };
 
 struct TaskA {        // part of one low-rank block: T partial = sum V^T X
@@ -225,7 +237,7 @@ struct TaskA {        // part of one low-rank block: T partial = sum V^T X
     int32_t item_begin, n_items;
     int32_t direct;   // 1: the task covers the whole block and writes T itself
     int32_t op;
-    int32_t pad;
+    int32_t r0;       // first row tile of the window
 };
 
 struct ReduceDesc {   // T_b = sum of partial slots

@@ -7,7 +7,7 @@ with the GPU path.
 What it computes (paper Sec. 3.1, "Solid mechanics" and "Final system"):
   * the exact collocation matrix E of piecewise-constant DD elements, one
     3x3 block per (receiver, source) pair in local frames, element-major
-    [s1, s2, n] ordering of DOFs ("local Cartesian coordinate system");
+    [s1, s2, n] ordering of DOFs in each element's local frame;
   * Y = E X by direct summation;
   * solutions of the tangent system A11 x = b with A11 = E - eta/dt - C^ep
     (Sec. 3.1.1, mechanical Jacobian) by dense LU, with inactive elements

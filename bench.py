@@ -36,6 +36,100 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o primary -- "
+             "python3 bench.py --only fp32 --steps 20 --warmup 3 --no-gmres --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_phase|k_reduceT|k_gather|k_scatter\" "
+             "--output-format csv -d gpurun_out/prof/fetch -o primary -- "
+             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline",
+    "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_phase|k_reduceT|k_gather|k_scatter\" "
+             "--output-format csv -d gpurun_out/prof/write -o primary -- "
+             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"copy|Copy\" --output-format csv "
+                  "-d gpurun_out/prof/copy_fetch -o copy -- python3 bench.py --form copy --steps 3",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"copy|Copy\" --output-format csv "
+                  "-d gpurun_out/prof/copy_write -o copy -- python3 bench.py --form copy --steps 3",
+}
+PHASE_KERNELS = ("k_gather", "k_phaseA", "k_reduceT", "k_phaseB", "k_scatter")
+
+
+def _kernel_base(name: str) -> str:
+    s = name.split("(")[0].replace("void ", "").replace("hm::", "").strip()
+    return s.split("<")[0]
+
+
+def summarize_profiles(prof_dir: str):
+    """Write profiles/traffic.json, profiles/traffic_primary_fp32.md and
+    profiles/kernel_stats_primary_fp32.md from the CSV output of
+    PROFILE_COMMANDS (run from the repository root with TMPDIR=/tmp)."""
+    import csv
+    import glob
+
+    def counters(sub):
+        f = glob.glob(os.path.join(prof_dir, sub, "*counter_collection.csv"))[0]
+        rows = list(csv.DictReader(open(f)))
+        per = {}
+        for r in rows:
+            k = _kernel_base(r["Kernel_Name"])
+            per.setdefault(k, []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = counters("fetch"), counters("write")
+    cf, cw = counters("copy_fetch"), counters("copy_write")
+    copy_kib = 2 * 1024 * 1024  # 2 GiB read and 2 GiB written per copy dispatch
+    ck = [k for k in cf if "opy" in k][0]
+    fetch_scale = copy_kib / (sum(cf[ck]) / len(cf[ck]))
+    write_scale = copy_kib / (sum(cw[ck]) / len(cw[ck]))
+    products = len(fetch["k_gather1"])  # one gather per product
+    kern = {}
+    for k in PHASE_KERNELS:
+        names = [n for n in fetch if n.startswith(k)]
+        fk = sum(sum(fetch[n]) for n in names) / products
+        wk = sum(sum(write.get(n, [])) for n in names) / products
+        kern[k] = {"fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                   "hbm_bytes_per_launch": int(1024 * (fk * fetch_scale + wk * write_scale))}
+    d = {"source_hash": source_hash(), "fetch_scale": round(fetch_scale, 5), "write_scale": round(write_scale, 5),
+         "workload": "256x256 planar fault, 16 RHS, FP32 form (leaf 64, eta 2, ACA 1e-6)",
+         "per": "one product (all launches of the kernel in one product)", "kernels": kern}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(d, fh, indent=1)
+    lines = ["# HBM traffic per product: 256x256 planar fault, 16 RHS, FP32 form", "",
+             "Commands (one counter per run, from the repository root, `TMPDIR=/tmp`):", "", "```"]
+    lines += [PROFILE_COMMANDS[k] for k in ("fetch", "write", "copy_fetch", "copy_write")]
+    lines += ["```", "", f"Calibration: a plain device copy of 2 GiB (torch `copy_`, 2,097,152 KiB read and written) "
+              f"gives FETCH_SIZE scale {fetch_scale:.4f} and WRITE_SIZE scale {write_scale:.4f}.", "",
+              f"Counters summed over every launch of a kernel in one product ({products} products profiled).", "",
+              "| kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled HBM bytes per product |", "|---|---|---|---|"]
+    for k, v in kern.items():
+        lines.append(f"| `{k}` | {v['fetch_kib']:,.1f} | {v['write_kib']:,.1f} | {v['hbm_bytes_per_launch']:,} |")
+    lines += ["", f"Apply source hash `{d['source_hash']}` (`profiles/traffic.json`); `bench.py` reports "
+              "`roofline.traffic` only while the apply source matches it."]
+    with open(os.path.join(ROOT, "profiles", "traffic_primary_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    f = glob.glob(os.path.join(prof_dir, "trace", "*kernel_stats.csv"))[0]
+    rows = list(csv.DictReader(open(f)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel statistics: 256x256 planar fault, 16 RHS, FP32 form", "", "Command (from the repository root, "
+             "`TMPDIR=/tmp`):", "", "```", PROFILE_COMMANDS["trace"], "```", "",
+             "| kernel | calls | average us | min us | max us | share of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows[:16]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} % |")
+    per_product = {}
+    for r in rows:
+        k = _kernel_base(r["Name"])
+        for p in PHASE_KERNELS:
+            if k.startswith(p):
+                per_product[p] = per_product.get(p, 0.0) + float(r["TotalDurationNs"])
+    calls = sum(int(r["Calls"]) for r in rows if _kernel_base(r["Name"]).startswith("k_gather"))
+    lines += ["", f"Per product ({calls} products; phase kernels summed over their launches of one product):", ""]
+    for p, ns in per_product.items():
+        lines.append(f"* `{p}`: {ns / calls / 1e3:.1f} us")
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_primary_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(d))
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current apply source; else None."""
@@ -67,7 +161,12 @@ def main():
     ap.add_argument("--meshes", type=int, default=64)
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
+    ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
+                    help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the H-matrix path here is built and timed on a single MI355X "
               "(multi-GPU sharding is a design note only); run with --gpus 1.", file=sys.stderr)
@@ -191,7 +290,8 @@ def main():
         "wall_s_timed": round(head["wall"], 4),
         "stage_ms": {k: round(v, 4) for k, v in head["stages"].items()},
         "roofline": {
-            "kernel": "k_phaseB (dense leaves + U T, one workgroup per target leaf)",
+            "kernel": "k_phaseB (dense pieces + U T; one workgroup per leaf section and 4-tile window; "
+                      "all launches of one product)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

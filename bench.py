@@ -329,9 +329,9 @@ def main():
         for name, kw, sol in (
                 ("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
                 ("mixed_bf16_refined", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
-                 dict(refine=1, inner_rtol=1e-4)),
+                 dict(refine=1)),
                 ("fp32_refined", dict(near_prec=hm.HM_F32, far_prec=hm.HM_F32, keep_f64_reference=1),
-                 dict(refine=1, inner_rtol=1e-5))):
+                 dict(refine=1))):
             op = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
             op.set_tangent(None, mask)
             torch.cuda.synchronize()
@@ -401,7 +401,7 @@ def bench_precision(args):
     forms = {}
     for name, kw, sol in (("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
                           ("precision_bf16", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
-                           dict(refine=1, inner_rtol=1e-4))):
+                           dict(refine=1))):
         t0 = time.perf_counter()
         op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
         torch.cuda.synchronize()
@@ -510,7 +510,7 @@ def bench_learned(args):
             t0 = time.perf_counter()
             net.attach(o)
             attach_s += time.perf_counter() - t0
-            sol = dict(refine=1, inner_rtol=1e-4) if name != "fp64" else {}
+            sol = dict(refine=1) if name != "fp64" else {}
             tag = "fp64" if name == "fp64" else "precision"
             for pc, pname in ((hm.HM_PC_BLOCK3, "block_jacobi"), (hm.HM_PC_LEARNED, "learned")):
                 torch.cuda.synchronize()

@@ -282,7 +282,7 @@ typedef struct {
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (FP64); default 1e-8 */
     int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED; default BLOCK3 */
     int refine;         /* 1: FP64 iterative refinement around a low-precision inner solve */
-    double inner_rtol;  /* inner tolerance when refine = 1; default 1e-4 */
+    double inner_rtol;  /* inner tolerance when refine = 1; 0 (default): 1e-2 with BF16 far field, else 1e-5 */
     int max_refine;     /* refinement sweeps; default 20 */
 } hm_solve_opts;
 

@@ -289,7 +289,7 @@ void hm_solve_opts_default(hm_solve_opts* o)
     o->rtol = 1e-8;
     o->precond = HM_PC_BLOCK3;
     o->refine = 0;
-    o->inner_rtol = 1e-4;
+    o->inner_rtol = 0.0;
     o->max_refine = 20;
 }
 

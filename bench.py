@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--meshes", type=int, default=64)
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
+    ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
     ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
@@ -493,7 +494,7 @@ def bench_learned(args):
         log(f"training state {k}: {per_state} solves, {solve_its[-1]} iterations in the last batch")
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
-    net = hm.Learned(hidden=64, neighbors=8, seed=5)
+    net = hm.Learned(hidden=64, neighbors=args.neighbors, seed=5)
     t0 = time.perf_counter()
     hist = []
     for ep in range(args.train_epochs):
@@ -542,7 +543,7 @@ def bench_learned(args):
            "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
            "config": {"workload": f"HF x fault, {m.ne} triangles, {n} DOF; leaf 64, eta 2, ACA 1e-6; "
                                   "tangent states 16-19 of 20, 16 right-hand sides each; GMRES(50)",
-                      "network": "32-64-64-9 MLP, 8 neighbours", "training_states": 16,
+                      "network": f"32-64-64-9 MLP, {args.neighbors} neighbours", "training_states": 16,
                       "training_samples": 16 * per_state, "adam_steps": steps},
            "forms": forms,
            "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},

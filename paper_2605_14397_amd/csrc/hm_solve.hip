@@ -3,8 +3,9 @@
 // iteratively, BiCGSTAB or GMRES, with a diagonal/block preconditioner).
 //
 // Restarted GMRES(m) with right preconditioning, x0 = 0, Arnoldi by
-// classical Gram-Schmidt applied twice, all vector arithmetic in FP64 on
-// the GPU.  nrhs independent systems advance in lock-step so that every
+// classical Gram-Schmidt with selective reorthogonalisation (a second pass
+// when the projection removes more than half of the new vector's energy),
+// all vector arithmetic in FP64 on the GPU.  nrhs independent systems advance in lock-step so that every
 // operator application streams the H-matrix once for all of them.  The
 // Hessenberg least-squares problem (at most (m+1) x m per column) is solved
 // on the host with Givens rotations; only O(m) scalars per column cross to
@@ -94,8 +95,9 @@ __global__ void k_combine(int J, int nrhs, int64_t n, const double* __restrict__
 }
 
 // y[c] = alpha[c] * x[c]  (alpha = 0 where scale is not finite or zero)
-__global__ void k_scale(int nrhs, int64_t n, const double* __restrict__ x, int64_t ldx, const double* __restrict__ inv,
-                        double* __restrict__ y, int64_t ldy)
+// (x and y may be the same vectors)
+__global__ void k_scale(int nrhs, int64_t n, const double* x, int64_t ldx, const double* __restrict__ inv, double* y,
+                        int64_t ldy)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * nrhs) return;
@@ -290,20 +292,50 @@ GmresResult gmres(Krylov& K, const Variant& v, const double* b, double* x, const
             double* Vj = K.V + (size_t)j * nrhs * n;
             double* Vn = K.V + (size_t)(j + 1) * nrhs * n;
             K.precond(Vj, K.Z);
-            K.matvec(v, K.Z, K.W);
-            // classical Gram-Schmidt, twice
-            K.dots(K.V, j + 1, K.W);
-            K.fetch(j + 1);
+            // w = A M^-1 v_j straight into the next basis slot; one pass gives
+            // V^T w and |w|^2 together (w is basis vector j + 1 of the dots)
+            K.matvec(v, K.Z, Vn);
+            K.dots(K.V, j + 2, Vn);
+            K.fetch(j + 2);
             std::vector<double> h1(K.h_host.begin(), K.h_host.begin() + (size_t)(j + 1) * nrhs);
+            std::vector<double> h2((size_t)(j + 1) * nrhs, 0.0);
+            std::vector<double> b2(nrhs);
+            bool reorth = false;
+            for (int c = 0; c < nrhs; ++c) {
+                const double w2 = K.h_host[(size_t)(j + 1) * nrhs + c];
+                double p2 = 0.0;
+                for (int i = 0; i <= j; ++i) p2 += h1[(size_t)i * nrhs + c] * h1[(size_t)i * nrhs + c];
+                b2[c] = w2 - p2;
+                // classical Gram-Schmidt keeps orthogonality unless the
+                // projection removed more than half of w's energy (DGKS)
+                if (!(b2[c] >= 0.5 * w2)) reorth = true;
+            }
             hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j + 1, nrhs, n, K.V,
-                               (int64_t)nrhs * n, n, K.hbuf, K.W, n, 1);
-            K.dots(K.V, j + 1, K.W);
-            K.fetch(j + 1);
-            std::vector<double> h2(K.h_host.begin(), K.h_host.begin() + (size_t)(j + 1) * nrhs);
-            hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j + 1, nrhs, n, K.V,
-                               (int64_t)nrhs * n, n, K.hbuf, K.W, n, 1);
-            K.dots(K.W, 1, K.W);
-            K.fetch(1);
+                               (int64_t)nrhs * n, n, K.hbuf, Vn, n, 1);
+            if (reorth) {
+                K.dots(K.V, j + 2, Vn);
+                K.fetch(j + 2);
+                bool exact = false;
+                for (int c = 0; c < nrhs; ++c) {
+                    const double w2 = K.h_host[(size_t)(j + 1) * nrhs + c];
+                    double p2 = 0.0;
+                    for (int i = 0; i <= j; ++i) {
+                        const double h = K.h_host[(size_t)i * nrhs + c];
+                        h2[(size_t)i * nrhs + c] = h;
+                        p2 += h * h;
+                    }
+                    b2[c] = w2 - p2;
+                    if (!(b2[c] >= 0.5 * w2)) exact = true;  // near breakdown: measure the norm
+                }
+                hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j + 1, nrhs, n, K.V,
+                                   (int64_t)nrhs * n, n, K.hbuf, Vn, n, 1);
+                if (exact) {
+                    K.dots(Vn, 1, Vn);
+                    K.fetch(1);
+                    for (int c = 0; c < nrhs; ++c) b2[c] = K.h_host[c];
+                }
+            }
+            for (int c = 0; c < nrhs; ++c) K.h_host[c] = b2[c];
             double worst = 0.0;
             bool all_done = true;
             for (int c = 0; c < nrhs; ++c) {
@@ -329,7 +361,7 @@ GmresResult gmres(Krylov& K, const Variant& v, const double* b, double* x, const
             }
             if (hist.size() < 1024) hist.push_back(worst * hist_scale);
             HM_CHECK_HIP(hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_scale, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, K.W, n, d_inv, Vn, n);
+            hipLaunchKernelGGL(k_scale, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, Vn, n, d_inv, Vn, n);
             if (all_done) {
                 ++j;
                 ++total;

@@ -168,34 +168,85 @@ __global__ __launch_bounds__(256) void k_layer_bwd(int64_t P, const float* __res
     }
 }
 
-// Weight gradient of one layer, two fixed-order stages:
-// partial[wg][k][o] = sum over the workgroup's rows of [in, 1][k] dOut[o] (FP64).
-constexpr int kRowsPerWg = 1024;
-__global__ __launch_bounds__(256) void k_wgrad_partial(int64_t P, const float* __restrict__ in, int Kin,
-                                                       const float* __restrict__ dOut, int Kout,
-                                                       double* __restrict__ partial)
+// Weight gradient of one layer, gW[k][o] = sum_p in[p][k] dOut[p][o] and
+// gb[o] = sum_p dOut[p][o]: a contraction over the P pairs on MFMA
+// (16x16x4 FP32, the pair index as the reduction dimension).  Each
+// workgroup reduces a chunk of kWgChunk pairs, staging 64-pair slices of
+// both operands through LDS, and writes FP32 partial sums; the partials are
+// then summed in FP64 in a fixed order (deterministic).
+typedef float wf4 __attribute__((ext_vector_type(4)));
+constexpr int kWgChunk = 4096;
+constexpr int kWgStage = 64;
+
+template <int KIN, int KOUT>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(int64_t P, const float* __restrict__ in,
+                                                    const float* __restrict__ dOut, float* __restrict__ partial)
 {
-    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerWg;
-    const int64_t r1 = min(P, r0 + kRowsPerWg);
-    const int n = (Kin + 1) * Kout;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int k = idx / Kout, o = idx - k * Kout;
-        double s = 0.0;
-        for (int64_t p = r0; p < r1; ++p) {
-            const float a = k < Kin ? in[p * Kin + k] : 1.f;
-            s += (double)a * (double)dOut[p * Kout + o];
+    constexpr int KOP = (KOUT + 15) / 16 * 16;  // output columns padded to tiles
+    constexpr int RT = KIN / 16, CT = KOP / 16, NT = RT * CT;
+    constexpr int TPW = (NT + 3) / 4;           // tiles per wave
+    __shared__ float sIn[kWgStage][KIN + 1];
+    __shared__ float sD[kWgStage][KOP + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p0 = (int64_t)blockIdx.x * kWgChunk;
+    const int64_t p1 = min(P, p0 + kWgChunk);
+    wf4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = wf4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;  // bias gradient: thread o < KOUT sums column o
+    for (int64_t q0 = p0; q0 < p1; q0 += kWgStage) {
+        for (int idx = threadIdx.x; idx < kWgStage * KIN; idx += 256) {
+            const int r = idx / KIN, c = idx - r * KIN;
+            sIn[r][c] = q0 + r < p1 ? in[(q0 + r) * KIN + c] : 0.f;
         }
-        partial[(int64_t)blockIdx.x * n + idx] = s;
+        for (int idx = threadIdx.x; idx < kWgStage * KOP; idx += 256) {
+            const int r = idx / KOP, c = idx - r * KOP;
+            sD[r][c] = (q0 + r < p1 && c < KOUT) ? dOut[(q0 + r) * KOUT + c] : 0.f;
+        }
+        __syncthreads();
+        if (threadIdx.x < KOUT)
+            for (int r = 0; r < kWgStage; ++r) bsum += sD[r][threadIdx.x];
+#pragma unroll
+        for (int ks = 0; ks < kWgStage / 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int tile = wave + 4 * t;
+                if (tile < NT) {
+                    const int rt = tile / CT, ct = tile - rt * CT;
+                    const float a = sIn[kr][16 * rt + (lane & 15)];
+                    const float b = sD[kr][16 * ct + (lane & 15)];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
     }
+    // partial[wg][k][o] (k < KIN, o < KOUT), then partial[wg][KIN][o] = bias
+    float* out = partial + (int64_t)blockIdx.x * (KIN + 1) * KOUT;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile < NT) {
+            const int rt = tile / CT, ct = tile - rt * CT;
+            const int o = 16 * ct + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = 16 * rt + 4 * (lane >> 4) + v;
+                if (o < KOUT) out[k * KOUT + o] = acc[t][v];
+            }
+        }
+    }
+    if (threadIdx.x < KOUT) out[KIN * KOUT + threadIdx.x] = bsum;
 }
 
-__global__ void k_wgrad_final(int nwg, int n, const double* __restrict__ partial, float* __restrict__ gW,
+__global__ void k_wgrad_final(int nwg, int n, const float* __restrict__ partial, float* __restrict__ gW,
                               float* __restrict__ gb, int Kin, int Kout)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += partial[(int64_t)w * n + idx];
+    for (int w = 0; w < nwg; ++w) s += (double)partial[(int64_t)w * n + idx];
     const int k = idx / Kout, o = idx - k * Kout;
     if (k < Kin)
         gW[k * Kout + o] = (float)s;
@@ -448,23 +499,25 @@ void forward(const Learned& L, int64_t P, const float* feat, float* a1, float* a
     }
 }
 
-int wgrad_groups(int64_t P) { return (int)std::max<int64_t>(1, (P + kRowsPerWg - 1) / kRowsPerWg); }
+int wgrad_groups(int64_t P) { return (int)std::max<int64_t>(1, (P + kWgChunk - 1) / kWgChunk); }
 
-// doubles of partial sums the weight gradients of a width-H network need
+// doubles of workspace the (FP32) partial sums of a width-H network need
 size_t wgrad_partial_size(int64_t P, int H)
 {
     const int per = std::max({(kF + 1) * H, (H + 1) * H, (H + 1) * kOut});
-    return (size_t)wgrad_groups(P) * per;
+    return ((size_t)wgrad_groups(P) * per + 1) / 2;
 }
 
-void weight_grad(int64_t P, const float* in, int Kin, const float* dOut, int Kout, float* gW, float* gb,
-                 double* part, size_t part_cap, hipStream_t s)
+template <int KIN, int KOUT>
+void weight_grad(int64_t P, const float* in, const float* dOut, float* gW, float* gb, double* part, size_t part_cap,
+                 hipStream_t s)
 {
     const int nwg = wgrad_groups(P);
-    const int n = (Kin + 1) * Kout;
-    HM_REQUIRE((size_t)nwg * n <= part_cap, HM_EINTERNAL, "weight-gradient workspace too small");
-    hipLaunchKernelGGL(k_wgrad_partial, dim3(nwg), dim3(256), 0, s, P, in, Kin, dOut, Kout, part);
-    hipLaunchKernelGGL(k_wgrad_final, dim3(g1(n)), dim3(256), 0, s, nwg, n, part, gW, gb, Kin, Kout);
+    const int n = (KIN + 1) * KOUT;
+    HM_REQUIRE(((size_t)nwg * n + 1) / 2 <= part_cap, HM_EINTERNAL, "weight-gradient workspace too small");
+    float* pf = reinterpret_cast<float*>(part);
+    hipLaunchKernelGGL((k_wgrad_mfma<KIN, KOUT>), dim3(nwg), dim3(256), 0, s, P, in, dOut, pf);
+    hipLaunchKernelGGL(k_wgrad_final, dim3(g1(n)), dim3(256), 0, s, nwg, n, pf, gW, gb, KIN, KOUT);
     HM_CHECK_HIP(hipGetLastError());
 }
 
@@ -475,11 +528,11 @@ void backward_h(Learned& L, int64_t P, const float* feat, const float* a1, const
     NetDims d(H);
     const float* th = L.params.as<float>();
     float* gr = L.grad.as<float>();
-    weight_grad(P, a2, H, dO, kOut, gr + d.oW3, gr + d.ob3, part, cap, s);
+    weight_grad<H, kOut>(P, a2, dO, gr + d.oW3, gr + d.ob3, part, cap, s);
     hipLaunchKernelGGL((k_layer_bwd<H, kOut>), dim3(g1(P)), dim3(256), 0, s, P, dO, th + d.oW3, a2, d2);
-    weight_grad(P, a1, H, d2, H, gr + d.oW2, gr + d.ob2, part, cap, s);
+    weight_grad<H, H>(P, a1, d2, gr + d.oW2, gr + d.ob2, part, cap, s);
     hipLaunchKernelGGL((k_layer_bwd<H, H>), dim3(g1(P)), dim3(256), 0, s, P, d2, th + d.oW2, a1, d1);
-    weight_grad(P, feat, kF, d1, H, gr + d.oW1, gr + d.ob1, part, cap, s);
+    weight_grad<kF, H>(P, feat, d1, gr + d.oW1, gr + d.ob1, part, cap, s);
     HM_CHECK_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,121 @@
+"""GPU edge cases against the CPU FP64 oracle (through the C ABI).
+
+Error metric as in test_gpu_parity: per-column relative 2-norm error,
+max over columns.  Bars:
+  * all-dense operators (a single leaf): FP64 products equal the exact
+    product to rounding, <= 1e-12;
+  * H-matrix at ACA tolerance 1e-6: <= 1e-6; at 1e-12: <= 1e-10 (the
+    product error follows the block tolerance);
+  * FP32 form: <= 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Mesh, rect_grid, rhs_columns
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+YOUNG, NU = 30e9, 0.25
+
+
+def _hm():
+    import paper_2605_14397_amd as hm
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return hm
+
+
+def cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def colerr(Y, R):
+    Y = np.atleast_2d(Y)
+    R = np.atleast_2d(R)
+    return max(np.linalg.norm(Y[c] - R[c]) / np.linalg.norm(R[c]) for c in range(R.shape[0]))
+
+
+def _product_check(m, bar, nrhs=3, seed=4100, **opts):
+    hm = _hm()
+    E = oracle.dense(m, YOUNG, NU)
+    X = rhs_columns(m.ndof, nrhs, seed)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, **opts)
+    Y = op.apply(cuda(X)).cpu().numpy()
+    err = colerr(Y, X @ E.T)
+    assert err <= bar, err
+    return op, err
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (13, 5)])
+def test_tiny_and_just_over_one_leaf(nx, ny):
+    m = rect_grid(nx, ny, 1.0)
+    _product_check(m, 1e-12, nrhs=1, leaf_size=64)
+    _product_check(m, 1e-12, nrhs=16, leaf_size=8 if m.ne > 8 else 1, eta=1e-9)
+    _product_check(m, 1e-5, nrhs=16, leaf_size=64, near_prec=1, far_prec=1)
+
+
+def test_coplanar_and_cross_plane_pieces_in_one_operator():
+    """Four patches: two in the plane z = 0 (one with reversed vertex order,
+    so an antiparallel normal in the same plane), one in the parallel plane
+    z = 3 and one tilted.  Coplanar pairs are split into shear and normal
+    parts, the others keep all nine couplings; the product must match the
+    exact operator either way."""
+    a = rect_grid(8, 8, 1.0, origin=(0.0, 0.0, 0.0))
+    b = rect_grid(8, 8, 1.0, origin=(12.0, 0.0, 0.0))
+    c = rect_grid(8, 8, 1.0, origin=(0.0, 0.0, 3.0))
+    t = 0.6
+    d = rect_grid(8, 8, 1.0, origin=(2.0, 12.0, 1.0),
+                  axes=np.array([[1.0, 0.0, 0.0], [0.0, np.cos(t), np.sin(t)], [0.0, -np.sin(t), np.cos(t)]]))
+    parts = [a, b, c, d]
+    xyz = np.concatenate([p.xyz for p in parts])
+    conn, off = [], 0
+    for k, p in enumerate(parts):
+        cc = p.conn + off
+        if k == 1:
+            cc = cc[:, ::-1]  # reversed orientation: normal -z in the same plane
+        conn.append(cc)
+        off += p.nv
+    m = Mesh(xyz, np.concatenate(conn), "mixed_planes")
+    op, err = _product_check(m, 1e-6, nrhs=4, leaf_size=16, eta=2.0, aca_tol=1e-6)
+    st = op.stats()
+    assert st["n_lowrank_blocks"] > 0 and st["n_dense_blocks"] > 0
+
+
+def test_recompression_keeps_the_block_tolerance():
+    hm = _hm()
+    m = rect_grid(40, 40, 1.0)
+    E = oracle.dense(m, YOUNG, NU)
+    X = rhs_columns(m.ndof, 4, 4200)
+    R = X @ E.T
+    out = {}
+    for rc in (0, 1):
+        op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, eta=2.0, aca_tol=1e-6, recompress=rc)
+        Y = op.apply(cuda(X)).cpu().numpy()
+        out[rc] = (colerr(Y, R), op.stats())
+    assert out[0][0] <= 1e-6 and out[1][0] <= 1e-6, (out[0][0], out[1][0])
+    st0, st1 = out[0][1], out[1][1]
+    assert st0["rank_sum"] == st0["rank_sum_aca"]
+    assert st1["rank_sum_aca"] == st0["rank_sum_aca"]
+    assert st1["rank_sum"] < 0.9 * st1["rank_sum_aca"]
+    assert st1["bytes_far"] < st0["bytes_far"]
+
+
+def test_high_ranks_run_in_row_windows():
+    """At ACA 1e-12 the low-rank blocks of a 48 x 48 fault exceed 64 (more
+    than four row tiles): their phase-A and phase-B tasks are split into
+    windows of four tiles.  The product still follows the tolerance."""
+    m = rect_grid(48, 48, 1.0)
+    op, err = _product_check(m, 1e-10, nrhs=16, leaf_size=32, eta=2.0, aca_tol=1e-12)
+    assert op.stats()["max_rank"] > 64
+
+
+def test_column_count_limits():
+    hm = _hm()
+    m = rect_grid(4, 4, 1.0)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU)
+    with pytest.raises(hm.HMError):
+        op.apply(torch.zeros(0, m.ndof, dtype=torch.float64, device="cuda"))
+    with pytest.raises(hm.HMError):
+        op.apply(torch.zeros(17, m.ndof, dtype=torch.float64, device="cuda"))

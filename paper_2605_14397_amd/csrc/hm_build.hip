@@ -409,6 +409,7 @@ struct RcDesc {
     int64_t u_off, v_off;  // factor columns: U + q * lu, V + q * lv
     int64_t lu, lv;
     int64_t t_off;         // workspace: T_u [k][k'] then T_v [k][k']
+    double abs2;           // > 0: bound on the discarded energy; else tol^2 times the energy of U V^T
     int32_t k, pad;
 };
 
@@ -493,7 +494,8 @@ __device__ void rc_gram(const double* __restrict__ X, int64_t L, int k, double* 
 }
 
 __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, const double* __restrict__ fac,
-                                                     double tol, double* __restrict__ tws, int* __restrict__ out_k)
+                                                     double tol, double* __restrict__ tws, int* __restrict__ out_k,
+                                                     double* __restrict__ out_energy)
 {
     extern __shared__ double lds[];
     double* A = lds;                   // U^T U -> scaled -> R
@@ -527,7 +529,10 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
     }
     __syncthreads();
     if (!rc_cholesky(A, k, &s_flag)) {
-        if (threadIdx.x == 0) out_k[blockIdx.x] = -1;
+        if (threadIdx.x == 0) {
+            out_k[blockIdx.x] = -1;
+            out_energy[blockIdx.x] = 0.0;
+        }
         return;
     }
     // ---- C = R G (G symmetric, upper triangle in B), S = C R^T ----
@@ -627,17 +632,19 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
     if (threadIdx.x == 0) {
         double total = 0.0;
         for (int r = 0; r < k; ++r) total += fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
+        const double budget = D.abs2 > 0.0 ? D.abs2 : tol * tol * total;
         double tail = 0.0;
         int kp = k;
-        // drop from the smallest while the discarded energy stays within tol^2
+        // drop from the smallest while the discarded energy stays within the budget
         for (int r = k - 1; r >= 1; --r) {
             const double lr = fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
-            if (tail + lr > tol * tol * total) break;
+            if (tail + lr > budget) break;
             tail += lr;
             kp = r;
         }
         s_kp = kp;
         out_k[blockIdx.x] = kp;
+        out_energy[blockIdx.x] = total;
     }
     __syncthreads();
     const int kp = s_kp;
@@ -1106,42 +1113,107 @@ void upload_tasks(Variant& v, hipStream_t s)
     HM_CHECK_HIP(hipStreamSynchronize(s));
 }
 
-// Recompress every factorisation of rank 2..kRcMax at relative Frobenius
-// tolerance tol; the others are copied unchanged.  Replaces d_fac.
+// Recompress every factorisation of rank >= 2 at relative Frobenius
+// tolerance tol; the others are copied unchanged.  Ranks above kRcMax are
+// taken in chunks of kRcMax columns (cross-approximation columns come in
+// decreasing order of importance): with G chunks, chunk 0 is truncated at
+// tol / G of its own norm and every later chunk may discard at most
+// (tol / G)^2 times chunk 0's energy, so the discarded part of the block is
+// within tol of chunk 0's norm, which is the block's norm up to the cross
+// approximation's remainder.  Replaces d_fac.
 static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
 {
-    std::vector<RcDesc> rc;
-    std::vector<int> which;
-    int64_t tws = 0;
+    struct Chunk {
+        int block, g, c0, kc;  // chunk g: columns c0 .. c0 + kc - 1 of the block
+        int job = -1;          // index into the launch's descriptors
+        int kp = -1;           // kept columns (-1: unchanged)
+        int64_t t_off = 0;
+    };
+    std::vector<Chunk> ch;
+    std::vector<int> nchunks(op.lr.size(), 0);
     for (size_t b = 0; b < op.lr.size(); ++b) {
-        const LowRank& L = op.lr[b];
-        if (L.rank < 2 || L.rank > kRcMax) continue;
-        rc.push_back(RcDesc{L.u_off, L.v_off, L.comps * L.m, L.comps * L.n, tws, L.rank, 0});
-        which.push_back((int)b);
-        tws += 2 * (int64_t)L.rank * L.rank;
+        const int k = op.lr[b].rank;
+        if (k < 2) continue;
+        const int G = (k + kRcMax - 1) / kRcMax;
+        nchunks[b] = G;
+        for (int g = 0; g < G; ++g) ch.push_back(Chunk{(int)b, g, g * kRcMax, std::min(kRcMax, k - g * kRcMax)});
     }
-    std::vector<int> kp(rc.size(), -1);
+    int64_t tws = 0;
+    for (Chunk& c : ch) {
+        c.t_off = tws;
+        tws += 2 * (int64_t)c.kc * c.kc;
+    }
     DevBuf d_t(std::max<int64_t>(1, tws) * sizeof(double));
-    if (!rc.empty()) {
-        DevBuf d_rc, d_k(rc.size() * sizeof(int));
-        upload(d_rc, rc, s);
-        HM_CHECK_HIP(hipFuncSetAttribute((const void*)k_recompress, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)kRcLds));
-        hipLaunchKernelGGL(k_recompress, dim3((unsigned)rc.size()), dim3(256), kRcLds, s, d_rc.as<RcDesc>(),
-                           d_fac.as<double>(), tol, d_t.as<double>(), d_k.as<int>());
-        HM_CHECK_HIP(hipGetLastError());
-        HM_CHECK_HIP(hipMemcpyAsync(kp.data(), d_k.get(), kp.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        HM_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<double> energy0(op.lr.size(), 0.0);
+    HM_CHECK_HIP(hipFuncSetAttribute((const void*)k_recompress, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kRcLds));
+    // pass 0: chunk 0 of every block (relative budget); pass 1: later chunks
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<RcDesc> rc;
+        std::vector<int> idx;
+        for (size_t q = 0; q < ch.size(); ++q) {
+            Chunk& c = ch[q];
+            if ((pass == 0) != (c.g == 0) || c.kc < 2) continue;
+            const LowRank& L = op.lr[c.block];
+            const int G = nchunks[c.block];
+            const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
+            const double abs2 = pass == 0 ? 0.0 : (tol / G) * (tol / G) * energy0[c.block];
+            if (pass == 1 && !(abs2 > 0.0)) continue;  // chunk 0 failed: keep the rest as it is
+            rc.push_back(RcDesc{L.u_off + c.c0 * lu, L.v_off + c.c0 * lv, lu, lv, c.t_off, abs2, c.kc, 0});
+            idx.push_back((int)q);
+        }
+        if (rc.empty()) continue;
+        std::vector<int> kp(rc.size());
+        std::vector<double> en(rc.size());
+        if (pass == 0) {
+            // chunk 0 is truncated at tol / G of its own norm: one launch per chunk count G
+            for (int G = 1; G <= (kAcaMaxRank + kRcMax - 1) / kRcMax; ++G) {
+                std::vector<RcDesc> sub;
+                std::vector<int> where;
+                for (size_t q = 0; q < rc.size(); ++q)
+                    if (nchunks[ch[idx[q]].block] == G) {
+                        sub.push_back(rc[q]);
+                        where.push_back((int)q);
+                    }
+                if (sub.empty()) continue;
+                DevBuf d_sub, d_ks(sub.size() * sizeof(int)), d_es(sub.size() * sizeof(double));
+                upload(d_sub, sub, s);
+                hipLaunchKernelGGL(k_recompress, dim3((unsigned)sub.size()), dim3(256), kRcLds, s,
+                                   d_sub.as<RcDesc>(), d_fac.as<double>(), tol / G, d_t.as<double>(), d_ks.as<int>(),
+                                   d_es.as<double>());
+                HM_CHECK_HIP(hipGetLastError());
+                std::vector<int> ks(sub.size());
+                std::vector<double> es(sub.size());
+                HM_CHECK_HIP(hipMemcpyAsync(ks.data(), d_ks.get(), ks.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+                HM_CHECK_HIP(
+                    hipMemcpyAsync(es.data(), d_es.get(), es.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+                HM_CHECK_HIP(hipStreamSynchronize(s));
+                for (size_t q = 0; q < sub.size(); ++q) {
+                    kp[where[q]] = ks[q];
+                    en[where[q]] = es[q];
+                }
+            }
+        } else {
+            DevBuf d_rc, d_k(rc.size() * sizeof(int)), d_e(rc.size() * sizeof(double));
+            upload(d_rc, rc, s);
+            hipLaunchKernelGGL(k_recompress, dim3((unsigned)rc.size()), dim3(256), kRcLds, s, d_rc.as<RcDesc>(),
+                               d_fac.as<double>(), tol, d_t.as<double>(), d_k.as<int>(), d_e.as<double>());
+            HM_CHECK_HIP(hipGetLastError());
+            HM_CHECK_HIP(hipMemcpyAsync(kp.data(), d_k.get(), kp.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            HM_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        for (size_t q = 0; q < rc.size(); ++q) {
+            Chunk& c = ch[idx[q]];
+            c.job = (int)q;
+            c.kp = (kp[q] > 0 && kp[q] < c.kc) ? kp[q] : -1;
+            if (pass == 0) energy0[c.block] = kp[q] >= 0 ? en[q] : 0.0;
+        }
     }
-    // new compact store: recompressed blocks through k_rc_apply, the rest copied
+    // new ranks and compact store: recompressed chunks through k_rc_apply, the rest copied
     std::vector<int> newk(op.lr.size());
     for (size_t b = 0; b < op.lr.size(); ++b) newk[b] = op.lr[b].rank;
-    std::vector<int> slot(op.lr.size(), -1);
-    for (size_t q = 0; q < which.size(); ++q)
-        if (kp[q] > 0 && kp[q] < op.lr[which[q]].rank) {
-            newk[which[q]] = kp[q];
-            slot[which[q]] = (int)q;
-        }
+    for (const Chunk& c : ch)
+        if (c.kp > 0) newk[c.block] -= c.kc - c.kp;
     int64_t total = 0;
     std::vector<int64_t> nu(op.lr.size()), nv(op.lr.size());
     for (size_t b = 0; b < op.lr.size(); ++b) {
@@ -1154,17 +1226,37 @@ static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
     DevBuf out(std::max<int64_t>(1, total) * sizeof(double));
     std::vector<RcApply> ap;
     std::vector<CompactDesc> cp;
+    std::vector<int> col(op.lr.size(), 0);  // next output column of each block
+    auto copy_cols = [&](size_t b, int c0, int kc) {
+        const LowRank& L = op.lr[b];
+        const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
+        cp.push_back(CompactDesc{L.u_off + c0 * lu, nu[b] + col[b] * lu, (int64_t)kc * lu});
+        cp.push_back(CompactDesc{L.v_off + c0 * lv, nv[b] + col[b] * lv, (int64_t)kc * lv});
+        col[b] += kc;
+    };
+    size_t q = 0;
     for (size_t b = 0; b < op.lr.size(); ++b) {
         const LowRank& L = op.lr[b];
-        if (newk[b] == 0) continue;
-        if (slot[b] >= 0) {
-            ap.push_back(RcApply{L.u_off, L.v_off, nu[b], nv[b], L.comps * L.m, L.comps * L.n, rc[slot[b]].t_off,
-                                 L.rank, newk[b]});
-        } else {
-            cp.push_back(CompactDesc{L.u_off, nu[b], (int64_t)L.rank * L.comps * L.m});
-            cp.push_back(CompactDesc{L.v_off, nv[b], (int64_t)L.rank * L.comps * L.n});
+        if (L.rank == 0) continue;
+        if (nchunks[b] == 0) {
+            copy_cols(b, 0, L.rank);
+            continue;
+        }
+        const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
+        for (int g = 0; g < nchunks[b]; ++g, ++q) {
+            const Chunk& c = ch[q];
+            if (c.kp > 0) {
+                ap.push_back(RcApply{L.u_off + c.c0 * lu, L.v_off + c.c0 * lv, nu[b] + col[b] * lu,
+                                     nv[b] + col[b] * lv, lu, lv, c.t_off, c.kc, c.kp});
+                col[b] += c.kp;
+            } else {
+                copy_cols(b, c.c0, c.kc);
+            }
         }
     }
+    HM_REQUIRE(q == ch.size(), HM_EINTERNAL, "recompression chunk bookkeeping");
+    for (size_t b = 0; b < op.lr.size(); ++b)
+        HM_REQUIRE(col[b] == newk[b], HM_EINTERNAL, "recompression rank bookkeeping");
     if (!ap.empty()) {
         DevBuf d_ap;
         upload(d_ap, ap, s);

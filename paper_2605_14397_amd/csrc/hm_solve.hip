@@ -3,10 +3,10 @@
 // iteratively, BiCGSTAB or GMRES, with a diagonal/block preconditioner).
 //
 // Restarted GMRES(m) with right preconditioning, x0 = 0, Arnoldi by
-// classical Gram-Schmidt with selective reorthogonalisation (a second pass
-// when the projection removes more than half of the new vector's energy),
-// all vector arithmetic in FP64 on the GPU.  nrhs independent systems advance in lock-step so that every
-// operator application streams the H-matrix once for all of them.  The
+// classical Gram-Schmidt with delayed reorthogonalisation (one projection
+// pass and one update pass over the basis per step), all vector arithmetic
+// in FP64 on the GPU.  nrhs independent systems advance in lock-step so
+// that every operator application streams the H-matrix once for all of them.  The
 // Hessenberg least-squares problem (at most (m+1) x m per column) is solved
 // on the host with Givens rotations; only O(m) scalars per column cross to
 // the host per iteration.  With refinement, an outer loop computes the
@@ -49,24 +49,60 @@ __global__ void k_precond(int kind, int64_t ne, int nrhs, const double* __restri
 }
 
 constexpr int kDotChunk = 4096;
+constexpr int kDotGroup = 4;  // basis vectors per workgroup of the dot kernel
 
-// partial[p][chunk] = sum over the chunk of A_j[c] . w[c], p = j * nrhs + c
-__global__ void k_dot_partial(int nrhs, int64_t n, const double* __restrict__ A, int64_t strideJ, int64_t ldA,
-                              const double* __restrict__ w, int64_t ldw, double* __restrict__ partial, int nchunk)
+// Dot products of J basis vectors A_0 .. A_{J-1} (A_j[c] = A + j strideJ +
+// c ldA) with NT target vectors (u, and w when NT = 2), every column c;
+// each workgroup covers kDotChunk rows of one column and kDotGroup basis
+// vectors, so the targets are read once per group.
+// partial[((t J + j) nrhs + c) nchunk + chunk] = sum over the chunk.
+template <int NT>
+__global__ __launch_bounds__(256) void k_mdot_partial(int nrhs, int64_t n, const double* __restrict__ A,
+                                                      int64_t strideJ, int64_t ldA, int J,
+                                                      const double* __restrict__ u, int64_t ldu,
+                                                      const double* __restrict__ w, int64_t ldw,
+                                                      double* __restrict__ partial, int nchunk)
 {
-    const int p = blockIdx.y;
-    const int j = p / nrhs, c = p - j * nrhs;
-    const double* a = A + j * strideJ + c * ldA;
-    const double* b = w + c * ldw;
+    const int c = blockIdx.y, j0 = blockIdx.z * kDotGroup;
+    const int nj = min(kDotGroup, J - j0);
     const int64_t x0 = (int64_t)blockIdx.x * kDotChunk;
     const int64_t x1 = min(n, x0 + kDotChunk);
-    double s = 0.0;
-    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) s += a[x] * b[x];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    const double* a = A + (int64_t)j0 * strideJ + (int64_t)c * ldA;
+    const double* uc = u + (int64_t)c * ldu;
+    const double* wc = NT == 2 ? w + (int64_t)c * ldw : nullptr;
+    double acc[NT][kDotGroup];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < kDotGroup; ++q) acc[t][q] = 0.0;
+    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+        const double ux = uc[x];
+        const double wx = NT == 2 ? wc[x] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kDotGroup; ++q)
+            if (q < nj) {
+                const double v = a[(int64_t)q * strideJ + x];
+                acc[0][q] += v * ux;
+                if (NT == 2) acc[NT - 1][q] += v * wx;
+            }
+    }
+    __shared__ double red[4][NT * kDotGroup];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < kDotGroup; ++q) {
+            double v = acc[t][q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave][t * kDotGroup + q] = v;
+        }
     __syncthreads();
-    if (threadIdx.x == 0) partial[(int64_t)p * nchunk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x < NT * kDotGroup) {
+        const int t = threadIdx.x / kDotGroup, q = threadIdx.x - t * kDotGroup;
+        if (q < nj)
+            partial[((int64_t)(t * J + j0 + q) * nrhs + c) * nchunk + blockIdx.x] =
+                (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    }
 }
 
 __global__ void k_dot_final(int np, int nchunk, const double* __restrict__ partial, double* __restrict__ out)
@@ -78,9 +114,9 @@ __global__ void k_dot_final(int np, int nchunk, const double* __restrict__ parti
     out[p] = s;
 }
 
-// w[c] -= sum_j A_j[c] h[j][c]   (or out[c] = sum_j A_j[c] h[j][c] when accumulate = 0)
+// out[c] = sum_j A_j[c] h[j][c]  (the solution update: x += M^-1 V y)
 __global__ void k_combine(int J, int nrhs, int64_t n, const double* __restrict__ A, int64_t strideJ, int64_t ldA,
-                          const double* __restrict__ h, double* __restrict__ w, int64_t ldw, int subtract)
+                          const double* __restrict__ h, double* __restrict__ w, int64_t ldw)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * nrhs) return;
@@ -88,10 +124,41 @@ __global__ void k_combine(int J, int nrhs, int64_t n, const double* __restrict__
     int64_t x = idx - (int64_t)c * n;
     double s = 0.0;
     for (int j = 0; j < J; ++j) s += A[j * strideJ + c * ldA + x] * h[j * nrhs + c];
-    if (subtract)
-        w[c * ldw + x] -= s;
-    else
-        w[c * ldw + x] = s;
+    w[c * ldw + x] = s;
+}
+
+// One pass of the delayed reorthogonalisation (basis slots of V: q_0 ..
+// q_{j-1} final, u = slot j tentative, w = slot j + 1 = A M^-1 u).  For
+// column c with coefficients cf = [s (j), d (j), e, gq, gw]:
+//   slot j     <- (u - sum_i s_i q_i) gq          (u reorthogonalised: q_j)
+//   slot j + 1 <- (w - sum_i d_i q_i - e u) gw    (next tentative vector)
+// gq = gw = 0 zeroes a column that has finished.  Rows are independent, so
+// the update is in place.
+__global__ __launch_bounds__(256) void k_dcgs2_update(int j, int64_t n, double* V, int64_t strideJ,
+                                                      const double* __restrict__ coef)
+{
+    const int c = blockIdx.y;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const double* cf = coef + (int64_t)c * (2 * j + 3);
+    const double e = cf[2 * j], gq = cf[2 * j + 1], gw = cf[2 * j + 2];
+    double* col = V + (int64_t)c * n + x;
+    double* uq = col + (int64_t)j * strideJ;
+    double* wn = uq + strideJ;
+    if (gq == 0.0 && gw == 0.0) {
+        *uq = 0.0;
+        *wn = 0.0;
+        return;
+    }
+    double a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double q = col[(int64_t)i * strideJ];
+        a1 += cf[i] * q;
+        a2 += cf[j + i] * q;
+    }
+    const double u = *uq, w = *wn;
+    *uq = (u - a1) * gq;
+    *wn = (w - a2 - e * u) * gw;
 }
 
 // y[c] = alpha[c] * x[c]  (alpha = 0 where scale is not finite or zero)
@@ -126,7 +193,7 @@ struct Krylov {
     int64_t n;
     int m;
     int pc;
-    double *V, *W, *Z, *R, *D, *partial, *hbuf;  // device
+    double *V, *W, *Z, *R, *D, *partial, *hbuf, *coef, *dinv;  // device
     int nchunk;
     std::vector<double> h_host;
 
@@ -134,8 +201,10 @@ struct Krylov {
     {
         n = 3 * op.ne;
         nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
-        size_t vec = (size_t)nrhs * n;
-        size_t need = sizeof(double) * (vec * (m + 1) + 4 * vec + (size_t)(m + 2) * nrhs * nchunk + (m + 2) * nrhs);
+        const size_t vec = (size_t)nrhs * n;
+        const size_t nh = (size_t)2 * (m + 2) * nrhs;  // dot results: two targets, up to m + 2 basis vectors
+        const size_t ncoef = (size_t)(2 * m + 3) * nrhs;
+        size_t need = sizeof(double) * (vec * (m + 1) + 4 * vec + nh * nchunk + nh + ncoef + nrhs);
         if (op.solve_ws_bytes < need) {
             op.solve_ws.alloc(need);
             op.solve_ws_bytes = need;
@@ -152,24 +221,36 @@ struct Krylov {
         D = p;
         p += vec;
         partial = p;
-        p += (size_t)(m + 2) * nrhs * nchunk;
+        p += nh * nchunk;
         hbuf = p;
-        h_host.resize((size_t)(m + 2) * nrhs);
+        p += nh;
+        coef = p;
+        p += ncoef;
+        dinv = p;
+        h_host.resize(nh);
     }
 
     unsigned g1(int64_t total) const { return (unsigned)((total + 255) / 256); }
 
-    // out[j*nrhs + c] = A_j[c] . w[c], j < J  (device result in hbuf, copied to h_host)
-    void dots(const double* A, int J, const double* w)
+    // hbuf[(t J + j) nrhs + c] = A_j[c] . u[c] (t = 0) and A_j[c] . w[c] (t = 1, when w is given), j < J;
+    // A_j = A + j nrhs n, all vectors [nrhs][n]
+    void dots(const double* A, int J, const double* u, const double* w = nullptr)
     {
-        hipLaunchKernelGGL(k_dot_partial, dim3(nchunk, J * nrhs), dim3(256), 0, s, nrhs, n, A, (int64_t)nrhs * n, n, w,
-                           n, partial, nchunk);
-        hipLaunchKernelGGL(k_dot_final, dim3((J * nrhs + 255) / 256), dim3(256), 0, s, J * nrhs, nchunk, partial,
-                           hbuf);
+        const dim3 grid(nchunk, nrhs, (J + kDotGroup - 1) / kDotGroup);
+        if (w)
+            hipLaunchKernelGGL(k_mdot_partial<2>, grid, dim3(256), 0, s, nrhs, n, A, (int64_t)nrhs * n, n, J, u, n, w,
+                               n, partial, nchunk);
+        else
+            hipLaunchKernelGGL(k_mdot_partial<1>, grid, dim3(256), 0, s, nrhs, n, A, (int64_t)nrhs * n, n, J, u, n,
+                               u, n, partial, nchunk);
+        const int np = (w ? 2 : 1) * J * nrhs;
+        hipLaunchKernelGGL(k_dot_final, dim3((np + 255) / 256), dim3(256), 0, s, np, nchunk, partial, hbuf);
     }
-    void fetch(int J)
+    // copy the first entries * nrhs dot results to the host
+    void fetch(int entries)
     {
-        HM_CHECK_HIP(hipMemcpyAsync(h_host.data(), hbuf, sizeof(double) * J * nrhs, hipMemcpyDeviceToHost, s));
+        HM_CHECK_HIP(
+            hipMemcpyAsync(h_host.data(), hbuf, sizeof(double) * entries * nrhs, hipMemcpyDeviceToHost, s));
         HM_CHECK_HIP(hipStreamSynchronize(s));
     }
     void precond(const double* v, double* z)
@@ -195,6 +276,16 @@ struct Ls {
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
+    }
+    // the residual estimate column j (h[0..j+1]) would give, state unchanged
+    double peek(int j, const double* h) const
+    {
+        // only entry j of the rotated column is needed; each rotation i
+        // mixes entries i and i + 1, so carry entry i + 1 forward
+        double carry = h[0];
+        for (int i = 0; i < j; ++i) carry = -sn[i] * carry + cs[i] * h[i + 1];
+        const double r = std::hypot(carry, h[j + 1]);
+        return r == 0.0 ? 0.0 : std::fabs(h[j + 1] / r * g[j]);
     }
     // add column j (h[0..j+1]); returns |g[j+1]|
     double push(int j, const double* h)
@@ -241,147 +332,220 @@ struct GmresResult {
 // Solve A x = b for every column with the operator variant v; x starts at 0.
 // Convergence: true residual (same variant) <= tol * bnorm[c], checked at
 // restarts and when the Arnoldi estimate says so.
+//
+// Arnoldi by classical Gram-Schmidt with delayed reorthogonalisation
+// (DCGS2: Swirydowicz et al., Numer. Linear Algebra Appl. 2021; Bielich et
+// al., Parallel Comput. 2022).  Step j multiplies the tentative vector u
+// (slot j: projected once, not yet reorthogonalised) and then, in one pass
+// over the basis, takes the dot products of q_0 .. q_{j-1}, u and w = A M^-1 u
+// with u and with w.  From them:
+//   s = Q^T u, rho^2 = u.u - s.s        reorthogonalise u: q_j = (u - Q s) / rho,
+//                                       which finishes column j - 1
+//                                       (h += beta s, h_{j,j-1} = beta rho);
+//   A M^-1 q_j = (w - Q_{j+1} H s) / rho gives column j and, with the
+//   Pythagorean norm, the next tentative vector
+//   u' = (w - Q d - e u) / (rho beta').
+// One update pass writes q_j and u'.  Each step thus reads the basis twice
+// (CGS2 reads it four times) with one host synchronisation.  A column is
+// finished with one more dot pass when the step's estimate says the system
+// has converged and at the end of a cycle.
 GmresResult gmres(Krylov& K, const Variant& v, const double* b, double* x, const std::vector<double>& bnorm,
                   double tol, int max_iter, std::vector<double>& hist, double hist_scale)
 {
     const int nrhs = K.nrhs, m = K.m;
     const int64_t n = K.n;
+    const int64_t vs = (int64_t)nrhs * n;  // basis slot stride
     hipStream_t s = K.s;
     GmresResult res;
-    HM_CHECK_HIP(hipMemsetAsync(x, 0, sizeof(double) * nrhs * n, s));
+    HM_CHECK_HIP(hipMemsetAsync(x, 0, sizeof(double) * vs, s));
     std::vector<Ls> ls(nrhs, Ls(m));
-    std::vector<int> done_at(nrhs);
-    std::vector<char> conv(nrhs, 0);
-    std::vector<double> inv(nrhs), y((size_t)m * nrhs), hcol(m + 2);
-    double* d_inv = K.hbuf + (size_t)(m + 1) * nrhs;  // scratch for scale factors
+    // Hessenberg columns before rotation, per right-hand side ((m + 1) x m, column-major)
+    std::vector<double> Hf((size_t)nrhs * m * (m + 1));
+    auto Hc = [&](int c, int j) { return &Hf[((size_t)c * m + j) * (m + 1)]; };
+    std::vector<double> bet(nrhs), inv(nrhs), y((size_t)m * nrhs), coef, p(m + 1), col(m + 1);
+    std::vector<int> ncols(nrhs);
+    std::vector<char> conv(nrhs, 0), active(nrhs, 0);
     int total = 0;
     bool first = true;
     while (true) {
         // r = b - A x
         if (first) {
-            HM_CHECK_HIP(hipMemcpyAsync(K.R, b, sizeof(double) * nrhs * n, hipMemcpyDeviceToDevice, s));
+            HM_CHECK_HIP(hipMemcpyAsync(K.R, b, sizeof(double) * vs, hipMemcpyDeviceToDevice, s));
         } else {
             K.matvec(v, x, K.W);
-            hipLaunchKernelGGL(k_axpby, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, b, n, 1.0, K.W, n, -1.0, K.R,
-                               n);
+            hipLaunchKernelGGL(k_axpby, dim3(K.g1(vs)), dim3(256), 0, s, nrhs, n, b, n, 1.0, K.W, n, -1.0, K.R, n);
         }
         first = false;
         K.dots(K.R, 1, K.R);
         K.fetch(1);
-        bool all = true;
         for (int c = 0; c < nrhs; ++c)
             if (!std::isfinite(K.h_host[c])) res.nonfinite = true;
         if (res.nonfinite) break;
+        bool all = true;
         for (int c = 0; c < nrhs; ++c) {
-            double beta = std::sqrt(std::max(0.0, K.h_host[c]));
+            const double beta = std::sqrt(std::max(0.0, K.h_host[c]));
             conv[c] = beta <= tol * bnorm[c];
             all = all && conv[c];
             ls[c].reset(beta);
             inv[c] = (beta > 0.0 && !conv[c]) ? 1.0 / beta : 0.0;
-            done_at[c] = -1;
+            active[c] = !conv[c];
+            ncols[c] = 0;
+            bet[c] = 1.0;
         }
         if (all) {
             res.converged = true;
             break;
         }
         if (total >= max_iter) break;
-        HM_CHECK_HIP(hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_scale, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, K.R, n, d_inv, K.V, n);
-        int j = 0;
-        for (; j < m && total < max_iter; ++j, ++total) {
-            double* Vj = K.V + (size_t)j * nrhs * n;
-            double* Vn = K.V + (size_t)(j + 1) * nrhs * n;
+        std::fill(Hf.begin(), Hf.end(), 0.0);
+        HM_CHECK_HIP(hipMemcpyAsync(K.dinv, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_scale, dim3(K.g1(vs)), dim3(256), 0, s, nrhs, n, K.R, n, K.dinv, K.V, n);
+        for (int j = 0; j < m && total < max_iter; ++j) {
+            double* Vj = K.V + (size_t)j * vs;
+            double* Vn = Vj + vs;
             K.precond(Vj, K.Z);
-            // w = A M^-1 v_j straight into the next basis slot; one pass gives
-            // V^T w and |w|^2 together (w is basis vector j + 1 of the dots)
             K.matvec(v, K.Z, Vn);
-            K.dots(K.V, j + 2, Vn);
-            K.fetch(j + 2);
-            std::vector<double> h1(K.h_host.begin(), K.h_host.begin() + (size_t)(j + 1) * nrhs);
-            std::vector<double> h2((size_t)(j + 1) * nrhs, 0.0);
-            std::vector<double> b2(nrhs);
-            bool reorth = false;
-            for (int c = 0; c < nrhs; ++c) {
-                const double w2 = K.h_host[(size_t)(j + 1) * nrhs + c];
-                double p2 = 0.0;
-                for (int i = 0; i <= j; ++i) p2 += h1[(size_t)i * nrhs + c] * h1[(size_t)i * nrhs + c];
-                b2[c] = w2 - p2;
-                // classical Gram-Schmidt keeps orthogonality unless the
-                // projection removed more than half of w's energy (DGKS)
-                if (!(b2[c] >= 0.5 * w2)) reorth = true;
-            }
-            hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j + 1, nrhs, n, K.V,
-                               (int64_t)nrhs * n, n, K.hbuf, Vn, n, 1);
-            if (reorth) {
-                K.dots(K.V, j + 2, Vn);
-                K.fetch(j + 2);
-                bool exact = false;
-                for (int c = 0; c < nrhs; ++c) {
-                    const double w2 = K.h_host[(size_t)(j + 1) * nrhs + c];
-                    double p2 = 0.0;
-                    for (int i = 0; i <= j; ++i) {
-                        const double h = K.h_host[(size_t)i * nrhs + c];
-                        h2[(size_t)i * nrhs + c] = h;
-                        p2 += h * h;
-                    }
-                    b2[c] = w2 - p2;
-                    if (!(b2[c] >= 0.5 * w2)) exact = true;  // near breakdown: measure the norm
-                }
-                hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j + 1, nrhs, n, K.V,
-                                   (int64_t)nrhs * n, n, K.hbuf, Vn, n, 1);
-                if (exact) {
-                    K.dots(Vn, 1, Vn);
-                    K.fetch(1);
-                    for (int c = 0; c < nrhs; ++c) b2[c] = K.h_host[c];
-                }
-            }
-            for (int c = 0; c < nrhs; ++c) K.h_host[c] = b2[c];
-            double worst = 0.0;
-            bool all_done = true;
-            for (int c = 0; c < nrhs; ++c) {
-                if (!std::isfinite(K.h_host[c])) res.nonfinite = true;
-                for (int i = 0; i <= j; ++i)
-                    if (!std::isfinite(h1[(size_t)i * nrhs + c] + h2[(size_t)i * nrhs + c])) res.nonfinite = true;
-            }
+            ++total;
+            K.dots(K.V, j + 2, Vj, Vn);
+            K.fetch(2 * (j + 2));
+            for (size_t q = 0; q < (size_t)2 * (j + 2) * nrhs; ++q)
+                if (!std::isfinite(K.h_host[q])) res.nonfinite = true;
             if (res.nonfinite) {
-                res.iterations = total + 1;
+                res.iterations = total;
                 return res;
             }
+            const double* G0 = K.h_host.data();                            // basis . u
+            const double* G1 = K.h_host.data() + (size_t)(j + 2) * nrhs;   // basis . w
+            const size_t nc = (size_t)(2 * j + 3);
+            coef.assign(nc * nrhs, 0.0);
+            double worst = 0.0;
+            bool any = false, all_tentative = true;
             for (int c = 0; c < nrhs; ++c) {
-                double beta = std::sqrt(std::max(0.0, K.h_host[c]));
-                for (int i = 0; i <= j; ++i) hcol[i] = h1[(size_t)i * nrhs + c] + h2[(size_t)i * nrhs + c];
-                hcol[j + 1] = beta;
-                if (done_at[c] < 0 && !conv[c]) {
-                    double est = ls[c].push(j, hcol.data());
-                    if (est <= tol * bnorm[c] || beta == 0.0) done_at[c] = j + 1;
-                    worst = std::max(worst, est / bnorm[c]);
+                if (!active[c]) continue;
+                auto su = [&](int i) { return G0[(size_t)i * nrhs + c]; };  // q_i . u (u . u at i = j)
+                auto sw = [&](int i) { return G1[(size_t)i * nrhs + c]; };  // q_i . w (u . w at j, w . w at j + 1)
+                const double a = su(j);
+                double ss = 0.0;
+                for (int i = 0; i < j; ++i) ss += su(i) * su(i);
+                const double rho2 = a - ss;
+                const double rho = (a > 0.0 && rho2 > 1e-30 * a) ? std::sqrt(rho2) : 0.0;
+                if (j > 0) {
+                    double* hp = Hc(c, j - 1);
+                    for (int i = 0; i < j; ++i) hp[i] += bet[c] * su(i);
+                    hp[j] = bet[c] * rho;
+                    const double est = ls[c].push(j - 1, hp);
+                    ncols[c] = j;
+                    if (est <= tol * bnorm[c] || rho == 0.0) {
+                        active[c] = 0;
+                        continue;
+                    }
+                } else if (rho == 0.0) {
+                    active[c] = 0;
+                    continue;
                 }
-                inv[c] = (beta > 0.0 && done_at[c] < 0 && !conv[c]) ? 1.0 / beta : 0.0;
-                all_done = all_done && (done_at[c] >= 0 || conv[c]);
+                // p = H s over the finished columns 0 .. j - 1 (rows 0 .. j)
+                std::fill(p.begin(), p.begin() + j + 1, 0.0);
+                for (int k = 0; k < j; ++k) {
+                    const double* hk = Hc(c, k);
+                    for (int i = 0; i <= k + 1; ++i) p[i] += hk[i] * su(k);
+                }
+                double sz = 0.0;
+                for (int i = 0; i < j; ++i) sz += su(i) * sw(i);
+                const double qw = (sw(j) - sz) / rho;  // q_j . w
+                double* h = Hc(c, j);
+                double pq = 0.0, pp = 0.0, hh = 0.0;
+                for (int i = 0; i < j; ++i) {
+                    h[i] = (sw(i) - p[i]) / rho;
+                    pq += p[i] * sw(i);
+                }
+                h[j] = (qw - p[j]) / rho;
+                pq += p[j] * qw;
+                for (int i = 0; i <= j; ++i) {
+                    pp += p[i] * p[i];
+                    hh += h[i] * h[i];
+                }
+                const double wt2 = (sw(j + 1) - 2.0 * pq + pp) / (rho * rho);  // |A M^-1 q_j|^2
+                const double bn = std::sqrt(std::max(wt2 - hh, 1e-24 * wt2));
+                double* cf = &coef[(size_t)c * nc];
+                const double cj = p[j] + rho * h[j];
+                for (int i = 0; i < j; ++i) {
+                    cf[i] = su(i);
+                    cf[j + i] = p[i] + rho * h[i] - cj * su(i) / rho;
+                }
+                cf[2 * j] = cj / rho;
+                cf[2 * j + 1] = 1.0 / rho;
+                if (!(bn > 0.0) || !std::isfinite(bn)) {
+                    // A M^-1 q_j lies in the basis: column j is final with a zero subdiagonal
+                    h[j + 1] = 0.0;
+                    ls[c].push(j, h);
+                    ncols[c] = j + 1;
+                    active[c] = 0;
+                    continue;
+                }
+                cf[2 * j + 2] = 1.0 / (rho * bn);
+                bet[c] = bn;
+                h[j + 1] = bn;  // tentative until u' is reorthogonalised
+                const double est = ls[c].peek(j, h);
+                worst = std::max(worst, est / bnorm[c]);
+                any = true;
+                all_tentative = all_tentative && est <= tol * bnorm[c];
             }
+            HM_CHECK_HIP(hipMemcpyAsync(K.coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_dcgs2_update, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, j, n, K.V, vs,
+                               K.coef);
             if (hist.size() < 1024) hist.push_back(worst * hist_scale);
-            HM_CHECK_HIP(hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_scale, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, Vn, n, d_inv, Vn, n);
-            if (all_done) {
-                ++j;
-                ++total;
-                break;
+            if (!any) break;
+            const bool last = j + 1 == m || total >= max_iter;
+            if (!last && !all_tentative) continue;
+            // finish column j: reorthogonalise the tentative vector (slot j + 1)
+            K.dots(K.V, j + 2, Vn);
+            K.fetch(j + 2);
+            for (size_t q = 0; q < (size_t)(j + 2) * nrhs; ++q)
+                if (!std::isfinite(K.h_host[q])) res.nonfinite = true;
+            if (res.nonfinite) {
+                res.iterations = total;
+                return res;
             }
+            bool remaining = false;
+            for (int c = 0; c < nrhs; ++c) {
+                if (!active[c]) continue;
+                const double* h = Hc(c, j);
+                double ss = 0.0;
+                for (int i = 0; i <= j; ++i) {
+                    const double si = K.h_host[(size_t)i * nrhs + c];
+                    col[i] = h[i] + bet[c] * si;
+                    ss += si * si;
+                }
+                col[j + 1] = bet[c] * std::sqrt(std::max(0.0, K.h_host[(size_t)(j + 1) * nrhs + c] - ss));
+                const double est = ls[c].peek(j, col.data());
+                if (last || est <= tol * bnorm[c]) {
+                    std::copy(col.begin(), col.begin() + j + 2, Hc(c, j));
+                    ls[c].push(j, col.data());
+                    ncols[c] = j + 1;
+                    active[c] = 0;
+                } else {
+                    remaining = true;  // estimate was optimistic: keep going, step j + 1 finishes column j
+                }
+            }
+            if (!remaining) break;
         }
-        // x += M^-1 V y  (columns that had converged before this cycle get y = 0)
+        // x += M^-1 Q y  (columns that had converged before this cycle get y = 0)
+        int J = 0;
         std::fill(y.begin(), y.end(), 0.0);
         for (int c = 0; c < nrhs; ++c) {
-            if (conv[c]) continue;
-            int k = done_at[c] >= 0 ? done_at[c] : j;
+            if (conv[c] || ncols[c] == 0) continue;
+            const int k = ncols[c];
             std::vector<double> yc(k);
             ls[c].solve(k, yc.data());
             for (int i = 0; i < k; ++i) y[(size_t)i * nrhs + c] = yc[i];
+            J = std::max(J, k);
         }
-        HM_CHECK_HIP(hipMemcpyAsync(K.hbuf, y.data(), sizeof(double) * j * nrhs, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_combine, dim3(K.g1(n * nrhs)), dim3(256), 0, s, j, nrhs, n, K.V, (int64_t)nrhs * n, n,
-                           K.hbuf, K.W, n, 0);
-        K.precond(K.W, K.Z);
-        hipLaunchKernelGGL(k_axpby, dim3(K.g1(n * nrhs)), dim3(256), 0, s, nrhs, n, x, n, 1.0, K.Z, n, 1.0, x, n);
+        if (J > 0) {
+            HM_CHECK_HIP(hipMemcpyAsync(K.hbuf, y.data(), sizeof(double) * J * nrhs, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_combine, dim3(K.g1(vs)), dim3(256), 0, s, J, nrhs, n, K.V, vs, n, K.hbuf, K.W, n);
+            K.precond(K.W, K.Z);
+            hipLaunchKernelGGL(k_axpby, dim3(K.g1(vs)), dim3(256), 0, s, nrhs, n, x, n, 1.0, K.Z, n, 1.0, x, n);
+        }
     }
     res.iterations = total;
     return res;

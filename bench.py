@@ -327,29 +327,36 @@ def main():
         B = B.reshape(NRHS, m.ne, 3) * act[None, :, None]
         Bt = torch.as_tensor(B.reshape(NRHS, n), device="cuda")
         g = {}
-        for name, kw, sol in (
-                ("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
-                ("mixed_bf16_refined", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
-                 dict(refine=1)),
-                ("fp32_refined", dict(near_prec=hm.HM_F32, far_prec=hm.HM_F32, keep_f64_reference=1),
-                 dict(refine=1))):
+        for name, kw, runs in (
+                ("fp64", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64),
+                 (("fp64_plain", dict(precond=hm.HM_PC_BLOCK3)), ("fp64_leaf", dict(precond=hm.HM_PC_LEAF)))),
+                ("mixed", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
+                 (("mixed_bf16_refined", dict(refine=1, precond=hm.HM_PC_BLOCK3)),
+                  ("mixed_bf16_refined_leaf", dict(refine=1, precond=hm.HM_PC_LEAF)))),
+                ("fp32", dict(near_prec=hm.HM_F32, far_prec=hm.HM_F32, keep_f64_reference=1),
+                 (("fp32_refined", dict(refine=1, precond=hm.HM_PC_BLOCK3)),))):
             op = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
-            op.set_tangent(None, mask)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, rep = op.solve(Bt, rtol=1e-8, restart=100, max_iter=2000, raise_on_notconv=False, **sol)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            g[name] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
-                       "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
-                       "converged": bool(rep["converged"])}
-            log(f"gmres {name}: {g[name]}")
+            for rname, sol in runs:
+                # a fresh tangent per run: the leaf preconditioner's set-up is inside the timed solve
+                op.set_tangent(None, mask)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, rep = op.solve(Bt, rtol=1e-8, restart=100, max_iter=2000, raise_on_notconv=False, **sol)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                g[rname] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
+                            "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
+                            "converged": bool(rep["converged"])}
+                log(f"gmres {rname}: {g[rname]}")
             del op
             torch.cuda.empty_cache()
         g["speedup_mixed_vs_fp64"] = round(g["fp64_plain"]["time_to_1e-8_s"] / g["mixed_bf16_refined"]["time_to_1e-8_s"], 3)
+        g["speedup_mixed_leaf_vs_fp64"] = round(g["fp64_plain"]["time_to_1e-8_s"]
+                                                / g["mixed_bf16_refined_leaf"]["time_to_1e-8_s"], 3)
         g["system"] = ("A11 = E on a penny crack of radius 0.45 x side (41,000 active elements), identity "
                        "elsewhere; 16 RHS (uniform 1 MPa pressure + 15 seeded tractions); GMRES(100), "
-                       "3x3 block-Jacobi, FP64 Arnoldi; residual with the FP64 H-operator")
+                       "3x3 block-Jacobi (plain) or leaf block-Jacobi (_leaf, set-up included), FP64 Arnoldi; "
+                       "residual with the FP64 H-operator")
         out["gmres"] = g
 
     # ---------------------------------------------------------- CPU oracle baseline
@@ -429,6 +436,17 @@ def bench_precision(args):
                        "bytes_near": st["bytes_near"], "bytes_far": st["bytes_far"],
                        "ranks": [st["min_rank"], st["max_rank"], round(st["mean_rank"], 1)]}
         log(f"{name}: {forms[name]}")
+        # the same solve with the leaf block-Jacobi preconditioner, its set-up included
+        op.set_tangent(None, None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xl, rep = op.solve(b, rtol=1e-8, restart=100, max_iter=3000, raise_on_notconv=False,
+                           precond=hm.HM_PC_LEAF, **sol)
+        torch.cuda.synchronize()
+        forms[name]["leaf_block"] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 3),
+                                     "iterations": rep["iterations"], "refinements": rep["refinements"],
+                                     "rel_residual": rep["rel_residual"], "converged": bool(rep["converged"])}
+        log(f"{name} leaf block-Jacobi: {forms[name]['leaf_block']}")
         if name == "fp64_plain":
             x_plain = x.clone()
         else:
@@ -507,7 +525,8 @@ def bench_learned(args):
     train_s = time.perf_counter() - t0
     steps = len(hist)
     forms = {f: {"time_s": 0.0, "iterations": [], "rel_residual": 0.0, "fallbacks": 0}
-             for f in ("fp64_block_jacobi", "fp64_learned", "precision_block_jacobi", "precision_learned")}
+             for f in ("fp64_block_jacobi", "fp64_learned", "fp64_leaf_block", "precision_block_jacobi",
+                       "precision_learned", "precision_leaf_block")}
     attach_s = 0.0
     for k in range(16, 20):
         D = cuda(tangent_state(m, k))
@@ -519,7 +538,9 @@ def bench_learned(args):
             attach_s += time.perf_counter() - t0
             sol = dict(refine=1) if name != "fp64" else {}
             tag = "fp64" if name == "fp64" else "precision"
-            for pc, pname in ((hm.HM_PC_BLOCK3, "block_jacobi"), (hm.HM_PC_LEARNED, "learned")):
+            # the leaf preconditioner's set-up (after the tangent change) is inside its timed solve
+            for pc, pname in ((hm.HM_PC_BLOCK3, "block_jacobi"), (hm.HM_PC_LEARNED, "learned"),
+                              (hm.HM_PC_LEAF, "leaf_block")):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 x, rep = o.solve(rhs, rtol=1e-8, restart=50, max_iter=3000, precond=pc,

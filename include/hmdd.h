@@ -266,7 +266,21 @@ void hm_batch_destroy(hm_batch* batch);
 /* ------------------------------------------------------------------ */
 /* Krylov solve of the tangent system                                   */
 /* ------------------------------------------------------------------ */
-enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3 };
+/*
+ * Preconditioners M of the tangent system (right preconditioning; all FP64):
+ *   HM_PC_JACOBI   1 / (A11)_ii (the paper's diagonal preconditioner, Sec. 3.3.1)
+ *   HM_PC_BLOCK3   (A11)_ee^-1, the 3x3 block of each element
+ *   HM_PC_LEARNED  block-Jacobi plus the attached learned correction
+ *   HM_PC_LEAF     inverse of each cluster-tree leaf's diagonal block of
+ *                  A11 (3m x 3m, m <= 64 elements; E from the collocation
+ *                  coefficients, D subtracted on active elements, identity
+ *                  rows and columns for inactive ones), formed in FP64 by
+ *                  Gauss-Jordan elimination with partial pivoting on first
+ *                  use after each hm_tangent_set; 9 m^2 doubles per leaf.
+ *                  HM_EINVAL if a block is numerically singular (a pivot
+ *                  below 1e-13 of the block's largest |E_ij| + |D_ij|).
+ */
+enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3, HM_PC_LEAF = 4 };
 
 /* why a solve asked for HM_PC_LEARNED ran with HM_PC_BLOCK3 */
 enum {
@@ -280,7 +294,7 @@ typedef struct {
     int restart;        /* GMRES(m) restart length, 1..256; default 50 */
     int max_iter;       /* total inner iterations per right-hand side; default 1000 */
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (FP64); default 1e-8 */
-    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED; default BLOCK3 */
+    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED | HM_PC_LEAF; default BLOCK3 */
     int refine;         /* 1: FP64 iterative refinement around a low-precision inner solve */
     double inner_rtol;  /* inner tolerance when refine = 1; 0 (default): 1e-2 with BF16 far field, else 1e-5 */
     int max_refine;     /* refinement sweeps; default 20 */
@@ -304,7 +318,7 @@ typedef struct {
 /*
  * Solve A11 X = B for nrhs right-hand sides (1 <= nrhs <= 16) by
  * right-preconditioned restarted GMRES(m) from X = 0, Arnoldi by classical
- * Gram-Schmidt with reorthogonalisation in FP64 (the paper's outer/inner
+ * Gram-Schmidt with delayed reorthogonalisation in FP64 (the paper's outer/inner
  * Krylov solves, Sec. 3.3.1, use BiCGSTAB or GMRES).  With refine = 1 the
  * inner solve uses the operator's own precisions and an FP64 residual with
  * the FP64 reference copy (built with keep_f64_reference) drives the
@@ -323,9 +337,11 @@ hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const d
 /*
  * Z = M^-1 R with the preconditioner the solve would use (HM_PC_*) for op's
  * current tangent: identity, point Jacobi 1/(A11)_ii, 3x3 block-Jacobi
- * (A11)_ee^-1, or block-Jacobi plus the attached learned correction
- * (HM_EINVAL if none is attached).  d_R, d_Z: [nrhs][ld] float64 (device),
- * 1 <= nrhs <= 16, not aliased.  Synchronises the stream.
+ * (A11)_ee^-1, block-Jacobi plus the attached learned correction
+ * (HM_EINVAL if none is attached), or the leaf block inverses (formed here
+ * if the tangent changed since they were last formed).  d_R, d_Z:
+ * [nrhs][ld] float64 (device), 1 <= nrhs <= 16, not aliased.  Synchronises
+ * the stream.
  */
 hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double* d_R, int64_t ldr, double* d_Z,
                            int64_t ldz, void* hip_stream);

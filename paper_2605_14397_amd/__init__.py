@@ -21,7 +21,7 @@ HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCO
     0, -1, -2, -3, -4, -5, -6, -7)
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_APPLY_REFERENCE, HM_APPLY_TANGENT = 1, 2
-HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED = 0, 1, 2, 3
+HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF = 0, 1, 2, 3, 4
 HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3
 
 _STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "HM_EBADMESH",

@@ -789,6 +789,32 @@ static void moduli(double young, double nu, double& G, double& kG, double& kN)
     kN = G / (4.0 * M_PI * (1.0 - nu));
 }
 
+void leaf_blocks_coef(const Op& op, double* out, hipStream_t s)
+{
+    double G, kG, kN;
+    moduli(op.young, op.nu, G, kG, kN);
+    const Plan& p = op.plan;
+    std::vector<DenseDesc> dd(p.leaves.size());
+    int64_t off = 0, max_pairs = 0;
+    for (size_t lf = 0; lf < p.leaves.size(); ++lf) {
+        const Cluster& c = p.nodes[p.leaves[lf]];
+        dd[lf] = DenseDesc{c.begin, c.begin, off, (int32_t)c.size(), (int32_t)c.size()};
+        off += 9 * c.size() * c.size();
+        max_pairs = std::max<int64_t>(max_pairs, c.size() * c.size());
+    }
+    HM_REQUIRE(off == op.leaf_inv_elems, HM_EINTERNAL, "leaf block layout mismatch");
+    DevBuf d_dd;
+    upload(d_dd, dd, s);
+    for (size_t b0 = 0; b0 < dd.size(); b0 += 65535) {
+        unsigned nb = (unsigned)std::min<size_t>(65535, dd.size() - b0);
+        hipLaunchKernelGGL(k_dense_coef, dim3((unsigned)((max_pairs + 255) / 256), nb), dim3(256), 0, s,
+                           op.d_geo.as<ElemGeo>(), d_dd.as<DenseDesc>() + b0, kG, kN, out);
+        HM_CHECK_HIP(hipGetLastError());
+    }
+    // d_dd is released on return: finish its readers first
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
 void kernel_block(Mesh& mesh, double young, double nu, int64_t nr, const int64_t* d_rows, int64_t nc,
                   const int64_t* d_cols, double* d_out, hipStream_t s)
 {
@@ -1320,7 +1346,10 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     // element tables
     std::vector<ElemGeo> geo(mesh.ne);
     for (int64_t q = 0; q < mesh.ne; ++q) geo[q] = mesh.geo[p.perm[q]];
-    DevBuf d_geo, d_perm;
+    // cluster-order geometry and permutation stay with the operator (the leaf
+    // preconditioner recomputes its diagonal blocks from them)
+    DevBuf& d_geo = op.d_geo;
+    DevBuf& d_perm = op.d_perm;
     upload(d_geo, geo, s);
     upload(d_perm, p.perm, s);
     {
@@ -1610,6 +1639,22 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     }
     HM_CHECK_HIP(hipStreamSynchronize(s));
     double t2 = now_ms();
+
+    // ---- leaf descriptors of the leaf block-Jacobi preconditioner ----
+    {
+        std::vector<LeafPc> lp(nleaf);
+        int64_t off = 0;
+        for (int lf = 0; lf < nleaf; ++lf) {
+            const Cluster& c = p.nodes[p.leaves[lf]];
+            HM_REQUIRE(3 * c.size() <= kLeafDofMax, HM_EINTERNAL, "leaf larger than the preconditioner supports");
+            lp[lf] = LeafPc{off, c.begin, (int32_t)c.size(), 0};
+            off += 9 * c.size() * c.size();
+        }
+        upload(op.d_leaf_desc, lp, s);
+        op.leaf_inv_elems = off;
+        op.d_leaf_inv.release();
+        op.leaf_pc_current = false;
+    }
 
     // ---- pack variants ----
     op.main.near_prec = o.near_prec;

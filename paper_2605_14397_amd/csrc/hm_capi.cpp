@@ -313,7 +313,8 @@ hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double*
 {
     return guarded([&] {
         HM_REQUIRE(op, HM_EINVAL, "op is null");
-        hm::precond_apply(op->op, precond, nrhs, d_R, ldr, d_Z, ldz, (hipStream_t)hip_stream);
+        // the leaf preconditioner caches its inverses in the operator (as hm_solve's workspaces)
+        hm::precond_apply(const_cast<hm::Op&>(op->op), precond, nrhs, d_R, ldr, d_Z, ldz, (hipStream_t)hip_stream);
     });
 }
 

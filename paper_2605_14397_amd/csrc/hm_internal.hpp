@@ -261,6 +261,14 @@ struct Bases {
     void* y;             // phase-B output rows (accumulation precision)
 };
 
+// One diagonal leaf block of the leaf block-Jacobi preconditioner.
+struct LeafPc {
+    int64_t off;      // block start in the block store (doubles; 9 m^2 per leaf)
+    int64_t begin;    // first cluster position of the leaf
+    int32_t m, pad;   // elements
+};
+constexpr int kLeafDofMax = 192;  // 3 x the largest leaf (64 elements)
+
 // One operator's share of the gather and scatter of a product.
 struct Segment {
     int64_t ne, ldx, ldy;

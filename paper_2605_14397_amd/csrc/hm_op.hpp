@@ -104,6 +104,13 @@ struct Op {
     // tangent
     bool has_D = false, has_mask = false;
     DevBuf d_D, d_mask, d_pc_block, d_pc_diag;
+    // leaf block-Jacobi preconditioner: element geometry and permutation in
+    // cluster order (kept to recompute the diagonal leaf coefficients), leaf
+    // descriptors, and the FP64 inverses (column-major, built on first use
+    // after each tangent change)
+    DevBuf d_geo, d_perm, d_leaf_desc, d_leaf_inv;
+    int64_t leaf_inv_elems = 0;
+    bool leaf_pc_current = false;
     // element geometry kept for the learned preconditioner (original order)
     std::vector<double> e_cent, e_frame, e_h;  // [N][3], [N][9], [N] (sqrt of area)
     LearnedPairs lp;
@@ -119,6 +126,13 @@ void build_operator(Op& op, const Mesh& mesh, const hm_build_opts& o, hipStream_
 void kernel_block(Mesh& mesh, double young, double nu, int64_t nr, const int64_t* d_rows, int64_t nc,
                   const int64_t* d_cols, double* d_out, hipStream_t s);
 void ensure_mesh_geo(Mesh& mesh);
+
+// E on every diagonal leaf block, row-major [3m][3m] at each leaf's offset (hm_build.hip)
+void leaf_blocks_coef(const Op& op, double* out, hipStream_t s);
+
+// leaf block-Jacobi preconditioner (hm_leafpc.hip)
+void leaf_pc_prepare(Op& op, hipStream_t s);
+void leaf_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
 
 // apply (hm_apply.hip)
 // ev (optional): 6 events recorded before, between and after the 5 stages
@@ -142,8 +156,7 @@ void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
                 int64_t ldx, hm_solve_report* rep, hipStream_t s);
-void precond_apply(const Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                   hipStream_t s);
+void precond_apply(Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz, hipStream_t s);
 
 // learned preconditioner (hm_learned.hip)
 void learned_prepare(Op& op, int K, hipStream_t s);

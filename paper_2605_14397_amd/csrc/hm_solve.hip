@@ -259,6 +259,10 @@ struct Krylov {
             learned_apply(op, nrhs, v, n, z, n, s);
             return;
         }
+        if (pc == HM_PC_LEAF) {
+            leaf_pc_apply(op, nrhs, v, n, z, n, s);
+            return;
+        }
         hipLaunchKernelGGL(k_precond, dim3(g1(op.ne * nrhs)), dim3(256), 0, s, pc, op.ne, nrhs, v, n, z, n,
                            op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
     }
@@ -558,16 +562,18 @@ double now_ms()
 
 }  // namespace
 
-void precond_apply(const Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz,
-                   hipStream_t s)
+void precond_apply(Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz, hipStream_t s)
 {
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
-    HM_REQUIRE(kind >= HM_PC_NONE && kind <= HM_PC_LEARNED, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(kind >= HM_PC_NONE && kind <= HM_PC_LEAF, HM_EINVAL, "unknown preconditioner");
     HM_REQUIRE(ldr >= 3 * op.ne && ldz >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(R && Z, HM_EINVAL, "null vector pointer");
     HM_REQUIRE(kind != HM_PC_LEARNED || op.lp.attached, HM_EINVAL, "no learned correction is attached");
     if (kind == HM_PC_LEARNED) {
         learned_apply(op, nrhs, R, ldr, Z, ldz, s);
+    } else if (kind == HM_PC_LEAF) {
+        leaf_pc_prepare(op, s);
+        leaf_pc_apply(op, nrhs, R, ldr, Z, ldz, s);
     } else {
         hipLaunchKernelGGL(k_precond, dim3((unsigned)((op.ne * nrhs + 255) / 256)), dim3(256), 0, s, kind, op.ne,
                            nrhs, R, ldr, Z, ldz, op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
@@ -583,7 +589,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     HM_REQUIRE(o.restart >= 1 && o.restart <= 256, HM_EINVAL, "restart must be in [1, 256]");
     HM_REQUIRE(o.max_iter >= 1, HM_EINVAL, "max_iter must be positive");
     HM_REQUIRE(o.rtol > 0.0 && o.rtol < 1.0, HM_EINVAL, "rtol must be in (0, 1)");
-    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_LEARNED, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_LEAF, HM_EINVAL, "unknown preconditioner");
     HM_REQUIRE(ldb >= 3 * op.ne && ldx >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(d_B && d_X, HM_EINVAL, "null vector pointer");
     HM_REQUIRE(!o.refine || op.ref || op.main.near_prec == HM_F64, HM_EINVAL,
@@ -688,6 +694,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     // run again from x = 0 when the learned solve produced a non-finite
     // value or did not meet the FP64 residual test.
     int pc = o.precond, fallback = HM_FALLBACK_NONE, discarded = 0;
+    if (pc == HM_PC_LEAF) leaf_pc_prepare(op, s);
     if (pc == HM_PC_LEARNED && !op.lp.attached) {
         pc = HM_PC_BLOCK3;
         fallback = HM_FALLBACK_NOT_ATTACHED;

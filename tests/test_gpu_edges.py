@@ -119,3 +119,31 @@ def test_column_count_limits():
         op.apply(torch.zeros(0, m.ndof, dtype=torch.float64, device="cuda"))
     with pytest.raises(hm.HMError):
         op.apply(torch.zeros(17, m.ndof, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("near,far", [(0, 0), (1, 1), (1, 2)], ids=["fp64", "fp32", "mixed"])
+def test_products_are_deterministic(near, far):
+    """Products use a fixed summation order (no atomics): a product with
+    stage timing and plain products agree bit for bit, also for products
+    chained back to back (each one's output feeding the next one's input)
+    with no host synchronisation in between."""
+    hm = _hm()
+    m = rect_grid(40, 40, 1.0)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, eta=2.0, near_prec=near, far_prec=far)
+    assert op.stats()["n_lowrank_blocks"] > 0
+    X0 = cuda(rhs_columns(m.ndof, 16, 4300))
+    ref, x = [], X0
+    for _ in range(3):
+        y = torch.empty_like(x)
+        op.apply_timed(x, y)
+        ref.append(y.clone())
+        x = y * 1e-10
+    for rep in range(3):
+        got, x = [], X0
+        for _ in range(3):
+            y = op.apply(x)
+            got.append(y)
+            x = y * 1e-10
+        torch.cuda.synchronize()
+        for k, (g, r) in enumerate(zip(got, ref)):
+            assert torch.equal(g, r), (rep, k)

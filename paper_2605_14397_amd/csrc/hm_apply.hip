@@ -191,6 +191,11 @@ __device__ inline __amdgpu_buffer_rsrc_t chunk_rsrc(const char* base, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
+// Cache policy of the panel loads: every panel byte is read once per
+// product, so the loads are marked non-temporal (they stream past the
+// caches that keep the X and T chunks, which are re-read).
+constexpr int kPanelAux = 2;
+
 // Tiles r0 .. r0 + R - 1 of the unit's panel (rows rows, Rf = ceil(rows / 16)
 // tiles; the last may be partial); tiles at or past Rf read zero.
 template <int R>
@@ -211,7 +216,8 @@ __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, i
     for (int r = 0; r < R; ++r) {
         const int t = r0 + r;
         a[r] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(
-                                          rs, t < Rf - 1 ? vfull : (t == Rf - 1 ? vlast : kOut), t * 256 * gg, 0));
+                                          rs, t < Rf - 1 ? vfull : (t == Rf - 1 ? vlast : kOut), t * 256 * gg,
+                                          kPanelAux));
     }
     // the in-vector k-step: 64 granules, one per lane
     const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(x.bh, x.valid ? 1024u : 0u);

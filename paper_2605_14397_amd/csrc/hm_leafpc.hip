@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const LeafPc* __restrict__ d
         for (int c = 0; c < kNrhs; ++c) acc[c] = 0.0;
 #pragma unroll 4
         for (int j = 0; j < n; ++j) {
-            const double aij = Ai[(int64_t)j * n + i];
+            const double aij = __builtin_nontemporal_load(&Ai[(int64_t)j * n + i]);  // streamed once
 #pragma unroll
             for (int c = 0; c < kNrhs; ++c) acc[c] += aij * rl[j * kNrhs + c];
         }

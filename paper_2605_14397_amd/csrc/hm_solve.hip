@@ -48,6 +48,9 @@ __global__ void k_precond(int kind, int64_t ne, int nrhs, const double* __restri
     }
 }
 
+// Basis vectors are streamed (read once per pass, far larger than the
+// caches): their loads are non-temporal; the few vectors a pass re-reads
+// (its targets) keep the default policy.
 constexpr int kDotChunk = 4096;
 constexpr int kDotGroup = 4;  // basis vectors per workgroup of the dot kernel
 
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(256) void k_mdot_partial(int nrhs, int64_t n, const
 #pragma unroll
         for (int q = 0; q < kDotGroup; ++q)
             if (q < nj) {
-                const double v = a[(int64_t)q * strideJ + x];
+                const double v = __builtin_nontemporal_load(&a[(int64_t)q * strideJ + x]);
                 acc[0][q] += v * ux;
                 if (NT == 2) acc[NT - 1][q] += v * wx;
             }
@@ -123,7 +126,7 @@ __global__ void k_combine(int J, int nrhs, int64_t n, const double* __restrict__
     int c = (int)(idx / n);
     int64_t x = idx - (int64_t)c * n;
     double s = 0.0;
-    for (int j = 0; j < J; ++j) s += A[j * strideJ + c * ldA + x] * h[j * nrhs + c];
+    for (int j = 0; j < J; ++j) s += __builtin_nontemporal_load(&A[j * strideJ + c * ldA + x]) * h[j * nrhs + c];
     w[c * ldw + x] = s;
 }
 
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(256) void k_dcgs2_update(int j, int64_t n, double* 
     }
     double a1 = 0.0, a2 = 0.0;
     for (int i = 0; i < j; ++i) {
-        const double q = col[(int64_t)i * strideJ];
+        const double q = __builtin_nontemporal_load(&col[(int64_t)i * strideJ]);
         a1 += cf[i] * q;
         a2 += cf[j + i] * q;
     }

@@ -306,6 +306,9 @@ def main():
                                         "bytes_near", "bytes_far", "min_rank", "max_rank", "mean_rank")},
         "build_s": round(head["build_s"], 3) if head["build_s"] else None,
         "build_ms_split": {k: round(st[k], 1) for k in ("coef_ms", "aca_ms", "pack_ms")},
+        # FP64 influence coefficients of the dense leaves (ALU-bound, not a roofline item)
+        "coef_element_pairs_per_s": round(st["dense_entries"] / 9 / (st["coef_ms"] * 1e-3), 0)
+        if st["coef_ms"] > 0 else None,
     })
     if "fp64" in res and forms[0][0] != "fp64":
         r64 = res["fp64"]

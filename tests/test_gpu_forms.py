@@ -1,18 +1,24 @@
-"""GPU parity of the precision form on three intersecting disk fractures
-(103,968 triangles, 311,904 DOF; non-coplanar pairs at the intersections,
-non-uniform leaves).
+"""GPU parity at full size on the non-planar workloads.
+
+Three intersecting disk fractures (103,101 triangles, 309,303 DOF;
+non-coplanar pairs at the intersections, non-uniform leaves):
 
 * sampled exact rows (oracle: Peach-Koehler quadrature) against the FP64
   reference copy (bar 1e-6, ACA 1e-6) and the FP32/BF16 form (bar 5e-3);
 * GMRES with FP64 refinement reaches a relative residual <= 1e-8 measured
   with the FP64 operator, and its solution agrees with the plain FP64
   solve to within the ACA-limited accuracy (1e-5).
+
+Hydraulic fracture crossing a fault (199,880 triangles, 599,640 DOF; the
+planes intersect inside both): sampled exact rows on both fractures,
+including the rows next to the intersection, against the FP64 product
+(bar 1e-6, ACA 1e-6).
 """
 import numpy as np
 import pytest
 
 import oracle
-from workloads import gaussian_pressure_traction, rhs_columns, three_disks
+from workloads import gaussian_pressure_traction, hf_fault_mesh, rhs_columns, three_disks
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,3 +59,28 @@ def test_three_disks_precision_form_rows_and_refined_solve(disks):
     d = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
     print(f"refined: {rep['refinements']} sweeps {rep['iterations']} its; plain FP64 {rep64['iterations']} its; diff {d:.2e}")
     assert rep64["converged"] and d <= 1e-5
+
+
+def test_hf_fault_full_size_sampled_rows():
+    import paper_2605_14397_amd as hm
+
+    m = hf_fault_mesh()
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64)
+    X = rhs_columns(m.ndof, 2, 5101)
+    y = op.apply(torch.as_tensor(X, device="cuda")).cpu().numpy()
+    cent, frame, _ = oracle.frames(m)
+    on_hf = np.abs(np.abs(frame[:, 2, 1]) - 1.0) < 1e-9          # normal along y
+    st = np.deg2rad(30.0)
+    n_fault = np.array([np.sin(st), -np.cos(st), 0.0])
+    d_fault_plane = np.abs((cent - np.array([20.0, 0.0, 0.0])) @ n_fault)
+    hf_ids, fault_ids = np.flatnonzero(on_hf), np.flatnonzero(~on_hf)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([
+        rng.choice(hf_ids, 5, replace=False), rng.choice(fault_ids, 5, replace=False),
+        hf_ids[np.argsort(d_fault_plane[hf_ids])[:3]],            # HF rows next to the fault
+        fault_ids[np.argsort(np.abs(cent[fault_ids, 1]))[:3]]]))  # fault rows next to the HF plane
+    dof = (3 * rows[:, None] + np.arange(3)).ravel()
+    ref = oracle.rows_matvec(m, YOUNG, NU, rows, X, method=1)
+    err = max(np.linalg.norm(y[c, dof] - ref[c]) / np.linalg.norm(ref[c]) for c in range(2))
+    print(f"HF x fault: {len(rows)} sampled rows, FP64 error {err:.2e}")
+    assert len(rows) >= 12 and err <= 1e-6

@@ -198,7 +198,7 @@ constexpr int kPanelAux = 2;
 
 // Tiles r0 .. r0 + R - 1 of the unit's panel (rows rows, Rf = ceil(rows / 16)
 // tiles; the last may be partial); tiles at or past Rf read zero.
-template <int R>
+template <int R, bool LO>
 __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, int rows, int r0, int lane, u4 (&a)[R],
                                                                  u4& bh, u4& bl)
 {
@@ -222,8 +222,12 @@ __device__ __attribute__((always_inline)) inline void load_unit(const Unit& x, i
     // the in-vector k-step: 64 granules, one per lane
     const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(x.bh, x.valid ? 1024u : 0u);
     bh = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)lane, 0, 0));
-    const __amdgpu_buffer_rsrc_t rl = chunk_rsrc(x.bl ? x.bl : x.bh, (x.valid && x.bl) ? 1024u : 0u);
-    bl = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * (uint32_t)lane, 0, 0));
+    if constexpr (LO) {
+        const __amdgpu_buffer_rsrc_t rl = chunk_rsrc(x.bl ? x.bl : x.bh, (x.valid && x.bl) ? 1024u : 0u);
+        bl = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * (uint32_t)lane, 0, 0));
+    } else {
+        bl = u4{0, 0, 0, 0};  // no lo part in this form (only BF16 in-vectors are split)
+    }
 }
 
 // Every launch (phase A and B) is compiled for its tasks' own row-tile
@@ -257,6 +261,8 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
                                                                     int r0, const Side& nearS, const Side& farS,
                                                                     int u0, int step, int lane, ACC (&acc)[R])
 {
+    // only BF16 in-vectors carry a lo part
+    constexpr bool kLo = sizeof(NT) == 2 || sizeof(FT) == 2;
     const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
     Cursor c;
     c.init(items, n_items, ksn, ksf);
@@ -265,24 +271,24 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
     if constexpr (R <= 4) {
         u4 a0[R], a1[R], a2[R], b0h, b0l, b1h, b1l, b2h, b2l;
         Unit x0 = make_unit(c, true, u, rows, nearS, farS);
-        load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
+        load_unit<R, kLo>(x0, rows, r0, lane, a0, b0h, b0l);
         bool vb = c.seek(u + step, ksn, ksf);
         Unit x1 = make_unit(c, vb, u + step, rows, nearS, farS);
-        load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
+        load_unit<R, kLo>(x1, rows, r0, lane, a1, b1h, b1l);
         while (true) {
             const bool vc = c.seek(u + 2 * step, ksn, ksf);
             const Unit x2 = make_unit(c, vc, u + 2 * step, rows, nearS, farS);
-            load_unit<R>(x2, rows, r0, lane, a2, b2h, b2l);
+            load_unit<R, kLo>(x2, rows, r0, lane, a2, b2h, b2l);
             mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!vb) break;
             const bool vd = c.seek(u + 3 * step, ksn, ksf);
             x0 = make_unit(c, vd, u + 3 * step, rows, nearS, farS);
-            load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
+            load_unit<R, kLo>(x0, rows, r0, lane, a0, b0h, b0l);
             mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!vc) break;
             const bool ve = c.seek(u + 4 * step, ksn, ksf);
             x1 = make_unit(c, ve, u + 4 * step, rows, nearS, farS);
-            load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
+            load_unit<R, kLo>(x1, rows, r0, lane, a1, b1h, b1l);
             mma_unit<R, NT, FT, ACC>(x2.far, a2, b2h, b2l, acc);
             if (!vd) break;
             // a0 now holds unit u + 3 step, a1 unit u + 4 step
@@ -292,16 +298,16 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
     } else {
         u4 a0[R], a1[R], b0h, b0l, b1h, b1l;
         Unit x0 = make_unit(c, true, u, rows, nearS, farS);
-        load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
+        load_unit<R, kLo>(x0, rows, r0, lane, a0, b0h, b0l);
         while (true) {
             const bool v1 = c.seek(u + step, ksn, ksf);
             const Unit x1 = make_unit(c, v1, u + step, rows, nearS, farS);
-            load_unit<R>(x1, rows, r0, lane, a1, b1h, b1l);
+            load_unit<R, kLo>(x1, rows, r0, lane, a1, b1h, b1l);
             mma_unit<R, NT, FT, ACC>(x0.far, a0, b0h, b0l, acc);
             if (!v1) break;
             const bool v2 = c.seek(u + 2 * step, ksn, ksf);
             x0 = make_unit(c, v2, u + 2 * step, rows, nearS, farS);
-            load_unit<R>(x0, rows, r0, lane, a0, b0h, b0l);
+            load_unit<R, kLo>(x0, rows, r0, lane, a0, b0h, b0l);
             mma_unit<R, NT, FT, ACC>(x1.far, a1, b1h, b1l, acc);
             if (!v2) break;
             u += 2 * step;

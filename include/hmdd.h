@@ -309,7 +309,9 @@ typedef struct {
     double rel_residual;      /* max over columns of ||b - A11 x|| / ||b||, FP64, reference operator */
     double solve_ms;
     int n_history;            /* entries written to history (<= 1024) */
-    double history[1024];     /* max-over-columns relative residual after each inner iteration */
+    double history[1024];     /* max over columns of the GMRES residual estimate (relative) after each
+                                 inner iteration (the newest Arnoldi column enters with its tentative
+                                 norm; it is finished one iteration later) */
     int precond_used;         /* preconditioner of the solve that produced X */
     int fallback;             /* HM_FALLBACK_* */
     int discarded_iterations; /* iterations of a learned attempt that was replaced by the fallback */

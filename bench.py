@@ -515,35 +515,47 @@ def bench_learned(args):
         log(f"training state {k}: {per_state} solves, {solve_its[-1]} iterations in the last batch")
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
-    net = hm.Learned(hidden=64, neighbors=args.neighbors, seed=5)
+    def train(base):
+        net = hm.Learned(hidden=64, neighbors=args.neighbors, seed=5)
+        net.set_base(base)
+        hist = []
+        for ep in range(args.train_epochs):
+            for k in range(16):
+                op.set_tangent(cuda(tangent_state(m, k)))
+                b, x = data[k]
+                hist.extend(net.train(op, b, x, steps=8, batch=16, lr=1e-3))
+            log(f"epoch {ep} (base {base}): mean loss {np.mean(hist[-128:]):.4g}")
+        torch.cuda.synchronize()
+        return net, hist
+
     t0 = time.perf_counter()
-    hist = []
-    for ep in range(args.train_epochs):
-        for k in range(16):
-            op.set_tangent(cuda(tangent_state(m, k)))
-            b, x = data[k]
-            hist.extend(net.train(op, b, x, steps=8, batch=16, lr=1e-3))
-        log(f"epoch {ep}: mean loss {np.mean(hist[-128:]):.4g}")
-    torch.cuda.synchronize()
+    net, hist = train(hm.HM_PC_BLOCK3)
     train_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net_leaf, hist_leaf = train(hm.HM_PC_LEAF)
+    train_leaf_s = time.perf_counter() - t0
     steps = len(hist)
     forms = {f: {"time_s": 0.0, "iterations": [], "rel_residual": 0.0, "fallbacks": 0}
-             for f in ("fp64_block_jacobi", "fp64_learned", "fp64_leaf_block", "precision_block_jacobi",
-                       "precision_learned", "precision_leaf_block")}
+             for f in ("fp64_block_jacobi", "fp64_learned", "fp64_leaf_block", "fp64_learned_on_leaf",
+                       "precision_block_jacobi", "precision_learned", "precision_leaf_block",
+                       "precision_learned_on_leaf")}
     attach_s = 0.0
     for k in range(16, 20):
         D = cuda(tangent_state(m, k))
         rhs = cuda(tangent_rhs(m, NRHS, 9000 + k))
         for name, o in ops.items():
             o.set_tangent(D)
-            t0 = time.perf_counter()
-            net.attach(o)
-            attach_s += time.perf_counter() - t0
             sol = dict(refine=1) if name != "fp64" else {}
             tag = "fp64" if name == "fp64" else "precision"
-            # the leaf preconditioner's set-up (after the tangent change) is inside its timed solve
+            # the leaf preconditioner's set-up (after the tangent change) is inside its timed solve;
+            # attaching a correction (its forward pass, and for the leaf base the leaf inverses)
+            # is timed apart
             for pc, pname in ((hm.HM_PC_BLOCK3, "block_jacobi"), (hm.HM_PC_LEARNED, "learned"),
-                              (hm.HM_PC_LEAF, "leaf_block")):
+                              (hm.HM_PC_LEAF, "leaf_block"), (hm.HM_PC_LEARNED, "learned_on_leaf")):
+                if pc == hm.HM_PC_LEARNED:
+                    t0 = time.perf_counter()
+                    (net if pname == "learned" else net_leaf).attach(o)
+                    attach_s += time.perf_counter() - t0
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 x, rep = o.solve(rhs, rtol=1e-8, restart=50, max_iter=3000, precond=pc,
@@ -571,7 +583,9 @@ def bench_learned(args):
                       "training_samples": 16 * per_state, "adam_steps": steps},
            "forms": forms,
            "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},
-           "training": {"data_s": round(data_s, 2), "data_solves": 16 * per_state, "data_solve_iterations": {"min": min(solve_its), "mean": round(float(np.mean(solve_its)), 1), "max": max(solve_its)}, "train_s": round(train_s, 2),
+           "training": {"train_leaf_base_s": round(train_leaf_s, 2),
+                        "loss_last_epoch_leaf_base": round(float(np.mean(hist_leaf[-128:])), 5),
+                        "data_s": round(data_s, 2), "data_solves": 16 * per_state, "data_solve_iterations": {"min": min(solve_its), "mean": round(float(np.mean(solve_its)), 1), "max": max(solve_its)}, "train_s": round(train_s, 2),
                         "ms_per_step": round(1000 * train_s / max(1, steps), 2),
                         "loss_first_epoch": round(float(np.mean(hist[:128])), 5),
                         "loss_last_epoch": round(float(np.mean(hist[-128:])), 5),

@@ -326,10 +326,11 @@ typedef struct {
  * the FP64 reference copy (built with keep_f64_reference) drives the
  * correction sweeps.  d_B, d_X: [nrhs][ld] float64 (device).  Synchronous.
  * Returns HM_ENOTCONV (with the best iterate in d_X and rep filled) when
- * the tolerance is not met.  With HM_PC_LEARNED the preconditioner is
- * block-Jacobi plus the attached learned correction (hm_learned_attach);
- * the plain block-Jacobi is the fallback: it is used when nothing is
- * attached, and the solve is run again with it from X = 0 when the learned
+ * the tolerance is not met.  With HM_PC_LEARNED the preconditioner is the
+ * attached correction's base (3x3 or leaf block-Jacobi) plus the learned
+ * correction (hm_learned_attach); the plain preconditioner is the
+ * fallback: 3x3 block-Jacobi when nothing is attached, and the solve is run
+ * again from X = 0 with the attached correction's base when the learned
  * attempt meets a NaN/Inf or misses rtol (rep->fallback says which).
  * Convergence is always judged by the FP64 true residual.
  */
@@ -353,11 +354,14 @@ hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double*
 /* ------------------------------------------------------------------ */
 /*
  * The inner A11 solves (paper Sec. 3.3.1) use a cheap approximate inverse
- * of A11 as preconditioner; the paper uses point Jacobi.  Here the 3x3
- * block-Jacobi inverse B_e = (E_ee - D_e)^-1 gets a learned linear
- * correction over each element's K nearest elements f (e itself first,
- * exact search, ties by id):
- *     (M^-1 r)_e = B_e r_e + sum_f W_ef r_f,   W_ef = (h_e / E') net(phi_ef),
+ * of A11 as preconditioner; the paper uses point Jacobi.  Here a plain
+ * block preconditioner M_base gets a learned linear correction over each
+ * element's K nearest elements f (e itself first, exact search, ties by
+ * id):
+ *     (M^-1 r)_e = (M_base r)_e + sum_f W_ef r_f,   W_ef = (h_e / E') net(phi_ef),
+ * with M_base the 3x3 block-Jacobi inverse, (M_base r)_e = B_e r_e,
+ * B_e = (E_ee - D_e)^-1 (default), or the leaf block inverses of
+ * HM_PC_LEAF (hm_learned_set_base); M_base is also the fallback;
  * net a small MLP (32 -> H -> H -> 9, ReLU, FP32) of 20 dimensionless pair
  * features phi_ef of geometry and tangent stiffness, h_e = sqrt(area_e),
  * E' = E / (1 - nu^2); W_ef = 0 when e or f is inactive.  M^-1 is linear
@@ -387,6 +391,10 @@ typedef struct hm_learned hm_learned;
 hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out);
 void hm_learned_destroy(hm_learned* net);
 hm_status hm_learned_num_params(const hm_learned* net, int64_t* n);
+/* The base M_base of the correction: HM_PC_BLOCK3 (default) or HM_PC_LEAF.
+ * Training, hm_learned_loss_grad and hm_learned_attach use it, and a solve
+ * with the attached correction falls back to it.  Clears the Adam moments. */
+hm_status hm_learned_set_base(hm_learned* net, int base);
 /* host copies of the parameters; set also clears the Adam moments */
 hm_status hm_learned_get_params(const hm_learned* net, float* host_params, int64_t n);
 hm_status hm_learned_set_params(hm_learned* net, const float* host_params, int64_t n);

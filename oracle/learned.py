@@ -18,6 +18,11 @@ training loss over samples (b_s, x_s) with A11 x_s = b_s is
 
     L = (1/ns) sum_s ||M^-1 b_s - x_s||^2 / ||x_s||^2.
 
+The base may also be any fixed matrix M_base in place of the 3x3 blocks
+(the leaf block-Jacobi inverse is one): (M^-1 r) = M_base r + sum over pairs
+W_ef r_f.  Wherever a function below takes Bb, a [N, 3, 3] array means the
+per-element blocks B_e and a [3N, 3N] array means a dense M_base.
+
 Every function here follows those definitions literally: K-nearest search
 by brute force, features from their definitions, the dense preconditioner
 matrix built block by block, the gradient by the chain rule written out
@@ -138,9 +143,12 @@ def blocks(theta, H, F, scale):
 
 def dense_preconditioner(Bb, pe, pf, Wb, ne):
     """M^-1 as a dense [3N, 3N] matrix, block by block."""
-    M = np.zeros((3 * ne, 3 * ne))
-    for e in range(ne):
-        M[3 * e:3 * e + 3, 3 * e:3 * e + 3] += Bb[e]
+    if np.ndim(Bb) == 2:
+        M = np.array(Bb, dtype=np.float64, copy=True)
+    else:
+        M = np.zeros((3 * ne, 3 * ne))
+        for e in range(ne):
+            M[3 * e:3 * e + 3, 3 * e:3 * e + 3] += Bb[e]
     for p in range(len(pe)):
         e, f = int(pe[p]), int(pf[p])
         M[3 * e:3 * e + 3, 3 * f:3 * f + 3] += Wb[p]
@@ -150,11 +158,12 @@ def dense_preconditioner(Bb, pe, pf, Wb, ne):
 def apply(Bb, pe, pf, Wb, R):
     """Z = M^-1 R for R [ns, 3N], by the sum over pairs."""
     R = np.atleast_2d(np.asarray(R, np.float64))
-    ne = len(Bb)
+    dense_base = np.ndim(Bb) == 2
+    ne = R.shape[1] // 3 if dense_base else len(Bb)
     Z = np.zeros_like(R)
     for s in range(R.shape[0]):
         r = R[s].reshape(ne, 3)
-        z = np.einsum("eab,eb->ea", Bb, r)
+        z = (Bb @ R[s]).reshape(ne, 3) if dense_base else np.einsum("eab,eb->ea", Bb, r)
         for p in range(len(pe)):
             z[pe[p]] += Wb[p] @ r[pf[p]]
         Z[s] = z.ravel()
@@ -175,7 +184,7 @@ def loss_grad(theta, H, F, scale, pe, pf, Bb, Bs, Xs):
     Bs = np.atleast_2d(Bs)
     Xs = np.atleast_2d(Xs)
     ns = Bs.shape[0]
-    ne = len(Bb)
+    ne = Bs.shape[1] // 3
     W1, b1, W2, b2, W3, b3 = unpack(theta, H)
     out, (z1, a1, z2, a2) = forward(theta, H, F)
     Wb = (scale[:, None] * out).reshape(-1, 3, 3)

@@ -35,7 +35,8 @@ EXPORTS = [
     "hm_tangent_set",
     "hm_solve_opts_default", "hm_solve", "hm_batch_opts_default", "hm_batch_create", "hm_batch_apply",
     "hm_batch_get_info", "hm_batch_destroy",
-    "hm_learned_create", "hm_learned_destroy", "hm_learned_num_params", "hm_learned_get_params",
+    "hm_learned_create", "hm_learned_destroy", "hm_learned_set_base", "hm_learned_num_params",
+    "hm_learned_get_params",
     "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
     "hm_learned_attach", "hm_learned_detach", "hm_precond_apply",
 ]
@@ -138,6 +139,7 @@ def lib():
             "hm_batch_destroy": ([P], None),
             "hm_learned_create": ([I, I, ctypes.c_uint64, ctypes.POINTER(P)], I),
             "hm_learned_destroy": ([P], None),
+            "hm_learned_set_base": ([P, I], I),
             "hm_learned_num_params": ([P, ctypes.POINTER(I64)], I),
             "hm_learned_get_params": ([P, P, I64], I),
             "hm_learned_set_params": ([P, P, I64], I),
@@ -386,6 +388,12 @@ class Learned:
         self._h = h
         self.hidden = hidden
         self.neighbors = neighbors
+        self.base = HM_PC_BLOCK3
+
+    def set_base(self, base):
+        """Base preconditioner of the correction: HM_PC_BLOCK3 (default) or HM_PC_LEAF."""
+        _check(lib().hm_learned_set_base(self._h, base))
+        self.base = base
 
     def num_params(self) -> int:
         n = ctypes.c_int64()

@@ -330,6 +330,17 @@ hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned
 
 void hm_learned_destroy(hm_learned* net) { delete net; }
 
+hm_status hm_learned_set_base(hm_learned* net, int base)
+{
+    return guarded([&] {
+        HM_REQUIRE(net, HM_EINVAL, "net is null");
+        HM_REQUIRE(base == HM_PC_BLOCK3 || base == HM_PC_LEAF, HM_EINVAL,
+                   "the correction is added to HM_PC_BLOCK3 or HM_PC_LEAF");
+        net->net.base = base;
+        net->net.reset_moments();
+    });
+}
+
 hm_status hm_learned_num_params(const hm_learned* net, int64_t* n)
 {
     return guarded([&] {

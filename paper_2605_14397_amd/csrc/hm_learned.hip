@@ -265,12 +265,15 @@ __global__ void k_out_to_blocks(int64_t P, const float* __restrict__ out, const 
     for (int k = 0; k < kOut; ++k) Wb[p * kOut + k] = (float)(sc * (double)out[p * kOut + k]);
 }
 
-// z_e = B_e r_e + sum_{pairs p of e} W_p r_{f(p)}  [- x_e], every column.
-// One element per thread; each W block is read once for all columns.
+// z_e = (M_base r)_e + sum_{pairs p of e} W_p r_{f(p)}  [- x_e], every
+// column, with (M_base r)_e = B_e r_e (Binv given) or read from base
+// (precomputed leaf block-Jacobi product; base may be z itself: each
+// thread reads its element's base rows before writing them).  One element
+// per thread; each W block is read once for all columns.
 __global__ __launch_bounds__(256) void k_apply_learned(int64_t ne, int nrhs, const double* __restrict__ r,
-                                                       int64_t ldr, double* __restrict__ z, int64_t ldz,
-                                                       const double* __restrict__ Binv,
-                                                       const int64_t* __restrict__ off,
+                                                       int64_t ldr, double* z, int64_t ldz,
+                                                       const double* __restrict__ Binv, const double* base,
+                                                       int64_t ldbase, const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ pf,
                                                        const float* __restrict__ Wb, const double* __restrict__ X,
                                                        int64_t ldx)
@@ -278,17 +281,25 @@ __global__ __launch_bounds__(256) void k_apply_learned(int64_t ne, int nrhs, con
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     double y[kNrhs][3];
-    double Bk[9];
+    if (Binv) {
+        double Bk[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Bk[k] = Binv[9 * e + k];
+        for (int k = 0; k < 9; ++k) Bk[k] = Binv[9 * e + k];
 #pragma unroll
-    for (int c = 0; c < kNrhs; ++c) {
-        if (c < nrhs) {
-            const double* rc = r + c * ldr + 3 * e;
-            const double r0 = rc[0], r1 = rc[1], r2 = rc[2];
+        for (int c = 0; c < kNrhs; ++c) {
+            if (c < nrhs) {
+                const double* rc = r + c * ldr + 3 * e;
+                const double r0 = rc[0], r1 = rc[1], r2 = rc[2];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) y[c][a] = Bk[3 * a] * r0 + Bk[3 * a + 1] * r1 + Bk[3 * a + 2] * r2;
+                for (int a = 0; a < 3; ++a) y[c][a] = Bk[3 * a] * r0 + Bk[3 * a + 1] * r1 + Bk[3 * a + 2] * r2;
+            }
         }
+    } else {
+#pragma unroll
+        for (int c = 0; c < kNrhs; ++c)
+            if (c < nrhs)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) y[c][a] = base[c * ldbase + 3 * e + a];
     }
     const int64_t p1 = off[e + 1];
     for (int64_t p = off[e]; p < p1; ++p) {
@@ -664,7 +675,8 @@ double learned_loss_grad(Learned& L, Op& op, int ns, const double* B, int64_t ld
     // the column sums), sample weights (double)
     const size_t nfl = (size_t)P * (4 * H + 3 * kOut);
     const size_t npart = std::max<size_t>(wgrad_partial_size(P, H), (size_t)kNrhs * kSumsqBlocks);
-    const size_t ndb = (size_t)ns * nd + npart + kNrhs;
+    const bool leaf = L.base == HM_PC_LEAF;
+    const size_t ndb = (size_t)(leaf ? 2 : 1) * ns * nd + npart + kNrhs;
     const size_t need = nfl * sizeof(float) + 256 + ndb * sizeof(double);
     if (L.ws.bytes() < need) L.ws.alloc(need);
     float* a1 = L.ws.as<float>();
@@ -677,11 +689,17 @@ double learned_loss_grad(Learned& L, Op& op, int ns, const double* B, int64_t ld
     double* rho = reinterpret_cast<double*>(round_up((int64_t)(uintptr_t)(Wb + (size_t)P * kOut), (int64_t)256));
     double* part = rho + (size_t)ns * nd;
     double* wdev = part + npart;
+    double* zb = leaf ? wdev + kNrhs : nullptr;  // leaf block-Jacobi times the samples
 
     forward(L, P, lp.feat.as<float>(), a1, a2, out, s);
     hipLaunchKernelGGL(k_out_to_blocks, dim3(g1(P)), dim3(256), 0, s, P, out, lp.scale.as<double>(), Wb);
+    if (leaf) {
+        leaf_pc_prepare(op, s);
+        leaf_pc_apply(op, ns, B, ldb, zb, nd, s);
+    }
     hipLaunchKernelGGL(k_apply_learned, dim3(g1(op.ne)), dim3(256), 0, s, op.ne, ns, B, ldb, rho, nd,
-                       op.d_pc_block.as<double>(), lp.off.as<int64_t>(), lp.pf.as<int32_t>(), Wb, X, ldx);
+                       leaf ? nullptr : op.d_pc_block.as<double>(), zb, nd, lp.off.as<int64_t>(),
+                       lp.pf.as<int32_t>(), Wb, X, ldx);
     HM_CHECK_HIP(hipGetLastError());
     const std::vector<double> xn = sumsq(ns, nd, X, ldx, part, npart, s);
     const std::vector<double> rn = sumsq(ns, nd, rho, nd, part, npart, s);
@@ -736,7 +754,9 @@ void learned_train(Learned& L, Op& op, int n, const double* B, int64_t ldb, cons
 void learned_attach(Op& op, const Learned& L, hipStream_t s)
 {
     learned_prepare(op, L.K, s);
+    if (L.base == HM_PC_LEAF) leaf_pc_prepare(op, s);
     LearnedPairs& lp = op.lp;
+    lp.base = L.base;
     const int64_t P = lp.P;
     if (P > 0) {
         DevBuf act((size_t)P * (2 * L.H + kOut) * sizeof(float));
@@ -755,9 +775,11 @@ void learned_attach(Op& op, const Learned& L, hipStream_t s)
 void learned_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s)
 {
     const LearnedPairs& lp = op.lp;
+    const bool leaf = lp.base == HM_PC_LEAF;
+    if (leaf) leaf_pc_apply(op, nrhs, r, ldr, z, ldz, s);  // z = leaf block-Jacobi r, then the correction
     hipLaunchKernelGGL(k_apply_learned, dim3(g1(op.ne)), dim3(256), 0, s, op.ne, nrhs, r, ldr, z, ldz,
-                       op.d_pc_block.as<double>(), lp.off.as<int64_t>(), lp.pf.as<int32_t>(), lp.W.as<float>(),
-                       nullptr, (int64_t)0);
+                       leaf ? nullptr : op.d_pc_block.as<double>(), leaf ? z : nullptr, ldz, lp.off.as<int64_t>(),
+                       lp.pf.as<int32_t>(), lp.W.as<float>(), nullptr, (int64_t)0);
     HM_CHECK_HIP(hipGetLastError());
 }
 

@@ -67,6 +67,7 @@ struct LowRank {
 // Adam moments (FP32, device), see hm_learned.hip for the layout.
 struct Learned {
     int H = 64, K = 8;      // hidden width, neighbours per element (self included)
+    int base = HM_PC_BLOCK3;  // preconditioner the correction is added to (HM_PC_BLOCK3 or HM_PC_LEAF)
     int64_t n = 0;          // parameter count
     int64_t step = 0;       // Adam steps taken
     DevBuf params, m, v, grad;
@@ -85,6 +86,7 @@ struct LearnedPairs {
     bool features_current = false;
     DevBuf W;               // float [P][9]
     bool attached = false;
+    int base = HM_PC_BLOCK3;  // base preconditioner of the attached correction
 };
 
 struct Op {

@@ -692,8 +692,9 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
         HM_CHECK_HIP(hipMemcpy2DAsync(B, n * sizeof(double), d_B, ldb * sizeof(double), n * sizeof(double), nrhs,
                                       hipMemcpyDeviceToDevice, s));
     };
-    // The plain block-Jacobi preconditioner is the fallback of the learned
-    // one: used when no correction is attached for the current tangent, and
+    // The plain preconditioner under the learned correction (3x3 or leaf
+    // block-Jacobi) is its fallback: 3x3 block-Jacobi when no correction is
+    // attached for the current tangent, and the attached correction's base
     // run again from x = 0 when the learned solve produced a non-finite
     // value or did not meet the FP64 residual test.
     int pc = o.precond, fallback = HM_FALLBACK_NONE, discarded = 0;
@@ -706,7 +707,8 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     if (!ok && pc == HM_PC_LEARNED) {
         fallback = nonfinite ? HM_FALLBACK_NONFINITE : HM_FALLBACK_NOT_CONVERGED;
         discarded = iters;
-        pc = HM_PC_BLOCK3;
+        pc = op.lp.base;
+        if (pc == HM_PC_LEAF) leaf_pc_prepare(op, s);
         attempt(pc);
     }
     HM_CHECK_HIP(hipMemcpy2DAsync(d_X, ldx * sizeof(double), X, n * sizeof(double), n * sizeof(double), nrhs,

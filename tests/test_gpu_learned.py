@@ -10,9 +10,11 @@ element is the whole mesh, and no two centroid distances tie):
     layers of width <= 64: |dL| <= 1e-5 L, ||dg|| <= 1e-4 ||g||;
   * M^-1 R: the W blocks are stored in FP32, so <= 1e-6 per column;
     linearity of M^-1 to FP64 rounding.
-Then, on the HF x fault mesh at h = 4 m: training is deterministic, lowers
-the loss, and the trained correction needs fewer GMRES iterations than
-block-Jacobi on held-out tangent states; and the fallback to block-Jacobi.
+The same with the leaf block-Jacobi inverse as the base (oracle: the dense
+leaf inverse), and its fallback.  Then, on the HF x fault mesh at h = 4 m:
+training is deterministic, lowers the loss, and the trained correction
+needs fewer GMRES iterations than block-Jacobi on held-out tangent states;
+and the fallback to block-Jacobi.
 """
 import numpy as np
 import pytest
@@ -176,6 +178,69 @@ def test_fallback_to_block_jacobi(tiny):
     with pytest.raises(hm.HMError):
         hm.learned_detach(op)
         op.precond_apply(cuda(b), hm.HM_PC_LEARNED)
+
+
+def test_leaf_base_loss_gradient_apply_and_fallback(tiny):
+    """The correction added to the leaf block-Jacobi inverse (four leaves of
+    at most 16 elements) instead of the 3x3 blocks: loss and gradient, and
+    M^-1 R, against the oracle with the dense leaf inverse as its base; a
+    poisoned correction falls back to the leaf blocks."""
+    from test_host_logic import _py_plan
+
+    hm = _hm()
+    m, A = tiny["m"], tiny["A"]
+    leaf = 16
+    nodes, _, _ = _py_plan(m, leaf, 2.0)
+    leaves = [np.asarray(nd[0]) for nd in nodes if nd[2] is None]
+    assert len(leaves) >= 4
+    Mleaf = np.zeros_like(A)
+    for idx in leaves:
+        d = (3 * idx[:, None] + np.arange(3)).ravel()
+        Mleaf[np.ix_(d, d)] = np.linalg.inv(A[np.ix_(d, d)])
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=leaf)
+    op.set_tangent(cuda(tiny["D"]), cuda(tiny["active"].astype(np.uint8), torch.uint8))
+    _, frame, area = oracle.frames(m)
+    F, scale = OL.features(tiny["cent"], frame, area, tiny["D"], tiny["active"], leaves, tiny["pe"], tiny["pf"],
+                           YOUNG, NU)
+    F32 = F.astype(np.float32).astype(np.float64)
+    net = hm.Learned(hidden=H, neighbors=K, seed=1)
+    net.set_base(hm.HM_PC_LEAF)
+    th = _theta(hm)
+    net.set_params(th)
+    rng = np.random.default_rng(24)
+    n = 3 * m.ne
+    X = rng.standard_normal((4, n))
+    B = X @ A.T
+    L, g = net.loss_grad(op, cuda(B), cuda(X))
+    Lo, go = OL.loss_grad(th.astype(np.float64), H, F32, scale, tiny["pe"], tiny["pf"], Mleaf, B, X)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    net.attach(op)
+    R = rng.standard_normal((3, n))
+    Z = op.precond_apply(cuda(R), hm.HM_PC_LEARNED).cpu().numpy()
+    Wb = OL.blocks(th.astype(np.float64), H, F32, scale)
+    Zo = OL.apply(Mleaf, tiny["pe"], tiny["pf"], Wb, R)
+    act = np.repeat(tiny["active"], 3)
+    for c in range(3):
+        assert np.linalg.norm(Z[c, act] - Zo[c, act]) <= 1e-6 * np.linalg.norm(Zo[c, act])
+        assert np.allclose(Z[c, ~act], R[c, ~act], rtol=1e-13, atol=0)
+    # the leaf base differs from the 3x3 base here (the test is not vacuous)
+    Zb3 = OL.apply(tiny["Bb"], tiny["pe"], tiny["pf"], Wb, R)
+    assert np.linalg.norm(Zo[:, act] - Zb3[:, act]) > 1e-2 * np.linalg.norm(Zo[:, act])
+    # a poisoned correction: solved again with the leaf blocks
+    th_bad = th.copy()
+    th_bad[-9:] = np.nan
+    net.set_params(th_bad)
+    net.attach(op)
+    b = rng.standard_normal((2, n))
+    x, rep = op.solve(cuda(b), precond=hm.HM_PC_LEARNED, restart=30, rtol=1e-10)
+    assert rep["fallback"] == hm.HM_FALLBACK_NONFINITE and rep["precond_used"] == hm.HM_PC_LEAF
+    x_ref = oracle.solve_dense(A, b)
+    xc = x.cpu().numpy()
+    for c in range(2):
+        assert np.linalg.norm(xc[c] - x_ref[c]) <= 1e-6 * np.linalg.norm(x_ref[c])
+    with pytest.raises(hm.HMError):
+        net.set_base(hm.HM_PC_JACOBI)
 
 
 # ------------------------------------------------------------ training

@@ -6,7 +6,10 @@ Each pin checks the oracle against something other than itself:
   * the sum over pairs against the dense matrix built block by block
     (swapping element and neighbour fails);
   * block-diagonal systems, where block-Jacobi is the exact inverse, give a
-    zero loss with a zero network;
+    zero loss with a zero network; the same for systems block-diagonal over
+    groups of elements with the group inverse as a dense base;
+  * a dense base equal to the 3x3 blocks reproduces the block form, and the
+    gradient with a general dense base matches central differences;
   * features of a flat square grid, whose values follow from geometry
     (offset one cell along s1 or s2, unit distance, aligned frames);
   * invariance of the dimensionless features under a rigid motion plus a
@@ -64,6 +67,61 @@ def test_pair_sum_matches_dense_matrix():
     M = OL.dense_preconditioner(Bb, pe, pf, Wb, len(Bb))
     Z = OL.apply(Bb, pe, pf, Wb, Bs)
     np.testing.assert_allclose(Z, Bs @ M.T, rtol=0, atol=1e-12 * np.abs(Z).max())
+
+
+def test_dense_base_matches_block_base_and_central_differences():
+    """A dense M_base (the leaf block-Jacobi form) in place of the 3x3 blocks:
+    the block-diagonal matrix of the blocks reproduces the block form
+    exactly, and for a general dense base the gradient still matches
+    central differences of the loss."""
+    theta, H, F, scale, pe, pf, Bb, Bs, Xs = _random_problem(seed=3)
+    ne = len(Bb)
+    Mb = np.zeros((3 * ne, 3 * ne))
+    for e in range(ne):
+        Mb[3 * e:3 * e + 3, 3 * e:3 * e + 3] = Bb[e]
+    Wb = OL.blocks(theta, H, F, scale)
+    np.testing.assert_allclose(OL.apply(Mb, pe, pf, Wb, Bs), OL.apply(Bb, pe, pf, Wb, Bs), rtol=0, atol=1e-13)
+    L1, g1 = OL.loss_grad(theta, H, F, scale, pe, pf, Bb, Bs, Xs)
+    L2, g2 = OL.loss_grad(theta, H, F, scale, pe, pf, Mb, Bs, Xs)
+    assert L2 == pytest.approx(L1, rel=1e-13) and np.allclose(g2, g1, rtol=0, atol=1e-12 * np.abs(g1).max())
+    rng = np.random.default_rng(4)
+    Md = rng.standard_normal((3 * ne, 3 * ne)) * 0.2 + np.eye(3 * ne)
+    L, g = OL.loss_grad(theta, H, F, scale, pe, pf, Md, Bs, Xs)
+    eps = 1e-6
+    fd = np.empty_like(g)
+    for i in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd[i] = (OL.loss(tp, H, F, scale, pe, pf, Md, Bs, Xs) - OL.loss(tm, H, F, scale, pe, pf, Md, Bs, Xs)) / (
+            2 * eps)
+    assert np.max(np.abs(fd - g)) <= 1e-7 * max(1.0, np.max(np.abs(g)))
+    # the dense preconditioner carries the dense base plus the pair blocks
+    M = OL.dense_preconditioner(Md, pe, pf, Wb, ne)
+    np.testing.assert_allclose(OL.apply(Md, pe, pf, Wb, Bs), Bs @ M.T, rtol=0, atol=1e-12 * np.abs(Bs @ M.T).max())
+
+
+def test_leaf_block_system_with_leaf_base_zero_network_is_exact():
+    """A system block-diagonal over groups of elements ("leaves"): the
+    inverse of the group blocks as M_base is exact, so a zero network gives a
+    zero loss, while the 3x3 block base does not."""
+    rng = np.random.default_rng(5)
+    ne, groups = 8, [[0, 1, 2], [3, 4], [5, 6, 7]]
+    A = np.zeros((3 * ne, 3 * ne))
+    for g in groups:
+        d = (3 * np.asarray(g)[:, None] + np.arange(3)).ravel()
+        A[np.ix_(d, d)] = rng.standard_normal((len(d), len(d))) + 6 * np.eye(len(d))
+    Mleaf = np.zeros_like(A)
+    for g in groups:
+        d = (3 * np.asarray(g)[:, None] + np.arange(3)).ravel()
+        Mleaf[np.ix_(d, d)] = np.linalg.inv(A[np.ix_(d, d)])
+    X = rng.standard_normal((4, 3 * ne))
+    Bs = X @ A.T
+    H = 4
+    pe, pf = OL.knn_bruteforce(rng.standard_normal((ne, 3)), 3)
+    F = rng.standard_normal((len(pe), 32))
+    assert OL.loss(np.zeros(OL.n_params(H)), H, F, np.ones(len(pe)), pe, pf, Mleaf, Bs, X) < 1e-26
+    assert OL.loss(np.zeros(OL.n_params(H)), H, F, np.ones(len(pe)), pe, pf, OL.block_jacobi(A, ne), Bs, X) > 1e-6
 
 
 def test_block_diagonal_system_zero_network_is_exact():

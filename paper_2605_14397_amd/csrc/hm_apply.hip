@@ -432,8 +432,19 @@ __global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const Bases* __rest
     for (int e = threadIdx.x; e < Kp * kNrhs; e += blockDim.x) {
         const int row = e / kNrhs, c = e - row * kNrhs;
         S v = 0;
-        if (row < D.rank)
-            for (int s = 0; s < D.n_slots; ++s) v += tpart[D.slot_begin + s * slot + (int64_t)row * kNrhs + c];
+        if (row < D.rank) {
+            // the loads of eight slots go out together; the sum keeps slot order
+            const S* src = tpart + D.slot_begin + (int64_t)row * kNrhs + c;
+            int s = 0;
+            for (; s + 8 <= D.n_slots; s += 8) {
+                S t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t[q] = src[(int64_t)(s + q) * slot];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v += t[q];
+            }
+            for (; s < D.n_slots; ++s) v += src[(int64_t)s * slot];
+        }
         store_t<FT>(thi, tlo, D.t_off + bfrag_offset(w, row, c), v);
     }
 }

@@ -4,8 +4,8 @@ as one HIP graph.
 
 * each operator's columns from the batch equal its own single product bit
   for bit (same kernels, same task lists, fixed summation order);
-* every operator matches the oracle's exact dense product (FP32 form bar
-  1e-5, FP64 form bar 1e-6, ACA 1e-6);
+* every operator matches the oracle's exact dense product (FP64 form bar
+  1e-6, FP32 form 1e-5, FP32 near + BF16 far form 5e-3; ACA 1e-6);
 * graph replays interleaved with eager products and new vector pointers
   give the same result every time.
 """
@@ -38,7 +38,7 @@ def small_faults():
     return batched_faults(n_meshes=7, seed=4001, nmin=300, nmax=1500)
 
 
-@pytest.mark.parametrize("near,far,bar", [(0, 0, 1e-6), (1, 1, 1e-5)], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("near,far,bar", [(0, 0, 1e-6), (1, 1, 1e-5), (1, 2, 5e-3)], ids=["fp64", "fp32", "mixed"])
 def test_batch_equals_single_products_and_oracle(small_faults, near, far, bar):
     hm = _hm()
     ops = [hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, near_prec=near, far_prec=far)

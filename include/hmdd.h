@@ -186,9 +186,11 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
 /* apply flags */
 #define HM_APPLY_REFERENCE 1u   /* use the FP64 reference copy */
 #define HM_APPLY_TANGENT 2u     /* apply A11 = E - D (mask) instead of E */
+#define HM_APPLY_ACCUMULATE 4u  /* add the product to d_Y instead of overwriting it */
 
 /*
- * d_Y = E d_X (or A11 d_X with HM_APPLY_TANGENT) for nrhs vectors
+ * d_Y = E d_X (or A11 d_X with HM_APPLY_TANGENT; d_Y += ... with
+ * HM_APPLY_ACCUMULATE) for nrhs vectors
  * (1 <= nrhs <= 16).  d_X [nrhs][ldx], d_Y [nrhs][ldy] float64 (device),
  * ldx, ldy >= 3N; d_X and d_Y must not overlap.  The product runs in the
  * operator's precisions and is returned in FP64.  Not reentrant on one

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhmdd.so")
 HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCONV, HM_EINTERNAL = (
     0, -1, -2, -3, -4, -5, -6, -7)
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
-HM_APPLY_REFERENCE, HM_APPLY_TANGENT = 1, 2
+HM_APPLY_REFERENCE, HM_APPLY_TANGENT, HM_APPLY_ACCUMULATE = 1, 2, 4
 HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF = 0, 1, 2, 3, 4
 HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3
 
@@ -269,15 +269,21 @@ class Operator:
         _check(lib().hm_operator_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
 
-    def apply(self, X, Y=None, reference=False, tangent=False, stream=None):
-        """Y = E X (or A11 X) for X a CUDA float64 tensor [nrhs, 3N] or [3N]."""
+    def apply(self, X, Y=None, reference=False, tangent=False, accumulate=False, stream=None):
+        """Y = E X (or A11 X; Y += ... with accumulate) for X a CUDA float64
+        tensor [nrhs, 3N] or [3N]."""
         import torch
 
         squeeze = X.dim() == 1
         X2 = X.reshape(1, -1) if squeeze else X
         if Y is None:
+            if accumulate:
+                raise ValueError("accumulate needs Y")
             Y = torch.empty_like(X2)
-        flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
+        elif squeeze:
+            Y = Y.reshape(1, -1)
+        flags = ((HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
+                 | (HM_APPLY_ACCUMULATE if accumulate else 0))
         _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), _ld(X2),
                                        _dev_ptr(Y, torch.float64), _ld(Y), flags, _stream(stream)))
         return Y.reshape(-1) if squeeze else Y

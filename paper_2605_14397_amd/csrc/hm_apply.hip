@@ -546,7 +546,8 @@ __device__ inline void scatter_body(const Segment& S, const Bases& B, int nrhs)
                 y[a] -= S.D[9 * e + 3 * a] * x[0] + S.D[9 * e + 3 * a + 1] * x[1] + S.D[9 * e + 3 * a + 2] * x[2];
         }
     }
-    for (int a = 0; a < 3; ++a) S.Y[c * S.ldy + 3 * e + a] = y[a];
+    double* out = S.Y + c * S.ldy + 3 * e;
+    for (int a = 0; a < 3; ++a) out[a] = S.accumulate ? out[a] + y[a] : y[a];
 }
 
 template <class S_t>
@@ -584,9 +585,11 @@ LaunchSet launch_set(const Variant& v)
 }
 
 Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                     bool tangent, int op_index)
+                     bool tangent, int op_index, bool accumulate)
 {
     Segment g;
+    g.accumulate = accumulate ? 1 : 0;
+    g.pad = 0;
     g.ne = op.ne;
     g.ldx = ldx;
     g.ldy = ldy;
@@ -682,12 +685,12 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
 }
 
 void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
-           bool tangent, hipStream_t s, hipEvent_t* ev)
+           bool tangent, hipStream_t s, hipEvent_t* ev, bool accumulate)
 {
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
     HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(X && Y, HM_EINVAL, "null vector pointer");
-    const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0);
+    const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0, accumulate);
     launch_product(launch_set(v), nrhs, nullptr, &g, 1, op.ne, s, ev);
 }
 

@@ -187,12 +187,14 @@ hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_
 {
     return guarded([&] {
         HM_REQUIRE(op, HM_EINVAL, "op is null");
-        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT)) == 0, HM_EINVAL, "unknown flag");
+        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT | HM_APPLY_ACCUMULATE)) == 0, HM_EINVAL,
+                   "unknown flag");
         const hm::Op& o = op->op;
         HM_REQUIRE(!(flags & HM_APPLY_REFERENCE) || o.ref || o.main.near_prec == HM_F64, HM_EINVAL,
                    "no FP64 reference copy (build with keep_f64_reference)");
         const hm::Variant& v = (flags & HM_APPLY_REFERENCE) ? o.ref_variant() : o.main;
-        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, (hipStream_t)hip_stream);
+        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, (hipStream_t)hip_stream, nullptr,
+                  (flags & HM_APPLY_ACCUMULATE) != 0);
     });
 }
 
@@ -201,7 +203,8 @@ hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, 
 {
     return guarded([&] {
         HM_REQUIRE(op && stage_ms, HM_EINVAL, "null argument");
-        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT)) == 0, HM_EINVAL, "unknown flag");
+        HM_REQUIRE((flags & ~(HM_APPLY_REFERENCE | HM_APPLY_TANGENT | HM_APPLY_ACCUMULATE)) == 0, HM_EINVAL,
+                   "unknown flag");
         const hm::Op& o = op->op;
         HM_REQUIRE(!(flags & HM_APPLY_REFERENCE) || o.ref || o.main.near_prec == HM_F64, HM_EINVAL,
                    "no FP64 reference copy (build with keep_f64_reference)");
@@ -217,7 +220,8 @@ hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, 
             }
         } guard{ev};
         for (int i = 0; i < 6; ++i) HM_CHECK_HIP(hipEventCreate(&ev[i]));
-        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, s, ev);
+        hm::apply(o, v, nrhs, d_X, ldx, d_Y, ldy, (flags & HM_APPLY_TANGENT) != 0, s, ev,
+                  (flags & HM_APPLY_ACCUMULATE) != 0);
         HM_CHECK_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < 5; ++i) {
             float ms = 0.f;

@@ -281,6 +281,8 @@ struct Segment {
     const uint8_t* mask;    // active mask or null
     int32_t op;
     int32_t tangent;
+    int32_t accumulate;     // 1: Y += result
+    int32_t pad;
 };
 
 }  // namespace hm

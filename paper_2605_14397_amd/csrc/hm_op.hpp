@@ -139,10 +139,10 @@ void leaf_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double*
 // apply (hm_apply.hip)
 // ev (optional): 6 events recorded before, between and after the 5 stages
 void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
-           bool tangent, hipStream_t s, hipEvent_t* ev = nullptr);
+           bool tangent, hipStream_t s, hipEvent_t* ev = nullptr, bool accumulate = false);
 LaunchSet launch_set(const Variant& v);
 Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                     bool tangent, int op_index);
+                     bool tangent, int op_index, bool accumulate = false);
 // gather (one segment per operator, segs on the device when nseg > 1), phases, scatter
 void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg_host, int nseg,
                     int64_t max_ne, hipStream_t s, hipEvent_t* ev);

@@ -147,3 +147,29 @@ def test_products_are_deterministic(near, far):
         torch.cuda.synchronize()
         for k, (g, r) in enumerate(zip(got, ref)):
             assert torch.equal(g, r), (rep, k)
+
+
+def test_accumulate_flag_adds_to_y():
+    """HM_APPLY_ACCUMULATE: Y0 + E X, bit for bit the FP64 sum of Y0 and the
+    plain product (plain and tangent products); unknown flags are rejected."""
+    import ctypes
+
+    hm = _hm()
+    m = rect_grid(20, 9, 1.0)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=16)
+    rng = np.random.default_rng(4400)
+    X = cuda(rhs_columns(m.ndof, 3, 4401))
+    Y0 = cuda(rng.standard_normal((3, m.ndof)) * 1e9)
+    for tangent in (False, True):
+        if tangent:
+            D = np.tile(np.eye(3) * 3e9, (m.ne, 1, 1))
+            mask = (rng.random(m.ne) < 0.8).astype(np.uint8)
+            op.set_tangent(cuda(D), torch.as_tensor(mask, device="cuda"))
+        plain = op.apply(X, tangent=tangent)
+        Y = Y0.clone()
+        out = op.apply(X, Y, tangent=tangent, accumulate=True)
+        assert out.data_ptr() == Y.data_ptr()
+        assert torch.equal(Y, Y0 + plain), tangent
+    with pytest.raises(hm.HMError):
+        hm._check(hm.lib().hm_operator_apply(op._h, 3, ctypes.c_void_p(X.data_ptr()), m.ndof,
+                                             ctypes.c_void_p(Y.data_ptr()), m.ndof, 8, None))

@@ -173,3 +173,35 @@ def test_accumulate_flag_adds_to_y():
     with pytest.raises(hm.HMError):
         hm._check(hm.lib().hm_operator_apply(op._h, 3, ctypes.c_void_p(X.data_ptr()), m.ndof,
                                              ctypes.c_void_p(Y.data_ptr()), m.ndof, 8, None))
+
+
+@pytest.mark.parametrize("restart", [1, 2, 5])
+def test_short_restart_cycles_reach_the_dense_solution(restart):
+    """GMRES(1), GMRES(2), GMRES(5): with delayed reorthogonalisation every
+    cycle ends with a finishing pass; the solves still reach the dense LU
+    solution, column by column, for three right-hand sides."""
+    hm = _hm()
+    m = rect_grid(7, 5, 1.0)
+    E = oracle.dense(m, YOUNG, NU)
+    B = rhs_columns(m.ndof, 3, 4500)
+    X_ref = oracle.solve_dense(E, B)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=8, aca_tol=1e-12)
+    X, rep = op.solve(cuda(B), rtol=1e-10, restart=restart, max_iter=3000, precond=hm.HM_PC_LEAF)
+    assert rep["converged"] and rep["rel_residual"] <= 1e-10, rep["iterations"]
+    assert colerr(X.cpu().numpy(), X_ref) <= 1e-8
+
+
+def test_iteration_budget_ending_inside_a_cycle():
+    """max_iter smaller than the restart length: the cycle is cut short, the
+    best iterate is returned with HM_ENOTCONV, and its residual is the true
+    one."""
+    hm = _hm()
+    m = rect_grid(12, 9, 1.0)
+    E = oracle.dense(m, YOUNG, NU)
+    B = rhs_columns(m.ndof, 2, 4600)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=16, aca_tol=1e-12)
+    X, rep = op.solve(cuda(B), rtol=1e-12, restart=50, max_iter=3, raise_on_notconv=False)
+    assert not rep["converged"] and rep["iterations"] == 3
+    R = B - X.cpu().numpy() @ E.T
+    rel = max(np.linalg.norm(R[c]) / np.linalg.norm(B[c]) for c in range(2))
+    assert 0 < rel < 1 and abs(rel - rep["rel_residual"]) <= 1e-6 * rel

@@ -20,8 +20,10 @@ tension and opening positive:
   * a fully damaged interface (damage min(chi_t / w_c, 1) = 1; w_c = 0 for
     a pre-existing fracture) that opens carries zero effective traction
     (both stiffnesses vanish); it closes back into contact once its inelastic
-    opening has returned to the residual width w_R, which starts at
-    alpha_R w_c and grows with the dilatant part psi dlam of shear flow.
+    opening has returned to the residual width w_R, which grows with the
+    dilatant part psi dlam of shear flow; its initial value (the paper's
+    alpha w_c for an intact interface, 0 for a pre-existing fracture) is
+    part of the initial state.
 
 Integration over a step (backward Euler, elastic predictor - plastic
 corrector): given the increment dd of the total DD and the state at the
@@ -69,8 +71,8 @@ import numpy as np
 from scipy.optimize import brentq
 
 # material record fields
-KS, KN, FP, FR, PSIP, DC, CP, SP, WC, AR = range(10)
-N_MAT_FIELDS = 10
+KS, KN, FP, FR, PSIP, DC, CP, SP, WC = range(9)
+N_MAT_FIELDS = 9
 
 ELASTIC, SHEAR, TENSILE, CORNER, OPEN = 0, 1, 2, 3, 4
 MODE_NAMES = {ELASTIC: "elastic", SHEAR: "shear", TENSILE: "tensile", CORNER: "corner", OPEN: "open"}
@@ -78,9 +80,10 @@ MODE_NAMES = {ELASTIC: "elastic", SHEAR: "shear", TENSILE: "tensile", CORNER: "c
 _H = 1e-30  # complex step
 
 
-def material(ks, kn, f_peak, f_res, psi_peak, d_c, c_peak, sigma_peak, w_c, alpha_r):
-    """Material record as a float array (field order KS ... AR)."""
-    return np.array([ks, kn, f_peak, f_res, psi_peak, d_c, c_peak, sigma_peak, w_c, alpha_r], dtype=np.float64)
+def material(ks, kn, f_peak, f_res, psi_peak, d_c, c_peak, sigma_peak, w_c):
+    """Material record as a float array (field order KS ... WC); an infinite
+    critical distance means no weakening."""
+    return np.array([ks, kn, f_peak, f_res, psi_peak, d_c, c_peak, sigma_peak, w_c], dtype=np.float64)
 
 
 # ------------------------------------------------------------------ weakening laws

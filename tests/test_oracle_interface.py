@@ -15,8 +15,8 @@ from oracle import interface as I
 INF = float("inf")
 
 
-def _mat(ks=3.2e10, kn=3.2e10, fp=0.6, fr=0.6, psi=0.0, dc=INF, c=2e6, st=1e6, wc=INF, ar=0.0):
-    return I.material(ks, kn, fp, fr, psi, dc, c, st, wc, ar)
+def _mat(ks=3.2e10, kn=3.2e10, fp=0.6, fr=0.6, psi=0.0, dc=INF, c=2e6, st=1e6, wc=INF):
+    return I.material(ks, kn, fp, fr, psi, dc, c, st, wc)
 
 
 def _upd(m, dd, T0, dp0=(0.0, 0.0, 0.0), chi0=(0.0, 0.0, 0.0)):
@@ -118,7 +118,7 @@ def test_mode_one_cohesive_law_and_fracture_energy():
     """Monotonic opening: T'n = sigma_p (1 - d^p_n / w_c) while weakening,
     zero once fully weakened, and the work of T'n on d^p_n is sigma_p w_c / 2."""
     sp, wc, kn = 1.0e6, 1.0e-3, 1.0e11
-    m = _mat(kn=kn, c=3e6, st=sp, wc=wc, ar=0.0)
+    m = _mat(kn=kn, c=3e6, st=sp, wc=wc)
     T, dp, chi = np.zeros(3), np.zeros(3), np.zeros(3)
     work, steps = 0.0, 4000
     for _ in range(steps):
@@ -222,21 +222,21 @@ def test_vanishing_return_gives_the_continuum_tangent():
 
 def _random_state(rng, m, kind):
     if kind == 0:
-        return np.array([*rng.normal(0, 3e6, 2), rng.uniform(-20e6, 0)]), np.zeros(3), np.array([0, 0, m[I.AR] * m[I.WC]])
+        return np.array([*rng.normal(0, 3e6, 2), rng.uniform(-20e6, 0)]), np.zeros(3), np.array([0, 0, 0.3 * m[I.WC]])
     if kind == 1:
         return (np.array([*rng.normal(0, 0.2e6, 2), rng.uniform(-0.5e6, 0.8e6)]), np.zeros(3),
-                np.array([0, 0, m[I.AR] * m[I.WC]]))
+                np.array([0, 0, 0.3 * m[I.WC]]))
     dp0 = np.array([*rng.normal(0, 2e-4, 2), rng.uniform(0, 3e-4)])
     chi0 = np.array([np.hypot(*dp0[:2]) * rng.uniform(1, 1.5), np.linalg.norm(dp0) * rng.uniform(1, 1.3),
-                     m[I.AR] * m[I.WC]])
+                     0.3 * m[I.WC]])
     return np.array([*rng.normal(0, 1e6, 2), rng.uniform(-5e6, 0.3e6)]), dp0, chi0
 
 
 def test_consistent_tangent_matches_finite_differences():
     """Central differences of the whole algorithm (weakening, dilatancy,
     every mode) against the complex-step tangent."""
-    mats = [I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3, 0.3),
-            I.material(1.0e10, 5.0e10, 0.7, 0.3, 0.2, 2e-3, 0.5e6, 0.4e6, 5e-4, 0.5)]
+    mats = [I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3),
+            I.material(1.0e10, 5.0e10, 0.7, 0.3, 0.2, 2e-3, 0.5e6, 0.4e6, 5e-4)]
     rng = np.random.default_rng(72)
     seen = set()
     for k in range(240):
@@ -257,7 +257,7 @@ def test_consistent_tangent_matches_finite_differences():
 
 
 def test_in_plane_rotation_invariance():
-    m = I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3, 0.3)
+    m = I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3)
     rng = np.random.default_rng(73)
     th = 0.7
     R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
@@ -273,7 +273,7 @@ def test_in_plane_rotation_invariance():
 
 
 def test_yield_consistency_and_flow_direction():
-    m = I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3, 0.3)
+    m = I.material(3.2e10, 3.2e10, 0.6, 0.4, 0.1, 5e-3, 2e6, 1e6, 1e-3)
     rng = np.random.default_rng(74)
     for k in range(200):
         T0, dp0, chi0 = _random_state(rng, m, k % 3)

@@ -352,6 +352,78 @@ hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double*
                            int64_t ldz, void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Interface elasto-plastic law and its consistent tangent              */
+/* ------------------------------------------------------------------ */
+/*
+ * The constitutive law of the fault/fracture interfaces (paper Sec. 2.2.2
+ * "A poroelastoplastic interface law" and Sec. 2.2.3 "Interface yield
+ * criteria, flow rule, and damage"), in each element's local frame
+ * (s1, s2, n), effective tractions, tension and opening positive:
+ *   T' - T'o = C (delta - delta^p), C = diag(k_s, k_s, k_n);
+ *   Coulomb  Fc = |tau| + f(chi_s) T'n - c(chi_t), non-associated flow
+ *            d delta^p = dlam (tau/|tau| + psi(chi_s) n);
+ *   cut-off  Ft = T'n - sigma_t(chi_t), flow along n;
+ *   f = f_res + (f_peak - f_res) W(chi_s/d_c), psi = psi_peak W(chi_s/d_c),
+ *   c = c_peak W(chi_t/w_c), sigma_t = sigma_peak W(chi_t/w_c),
+ *   W(x) = max(0, 1 - x); chi_s = max over time of |delta^p_s|,
+ *   chi_t = max over time of |delta^p|;
+ *   mode selection h = |tau| - (c - f sigma_t) - alpha (T'n - sigma_t),
+ *   alpha = sqrt(1 + f^2) - f: h > 0 Coulomb, else tension;
+ *   a fully damaged interface (chi_t >= w_c, or w_c = 0) that opens carries
+ *   no traction until its inelastic opening has closed back to the
+ *   residual width w_R (which grows by the dilatant part of shear flow).
+ * One step is integrated by an elastic predictor and a backward-Euler
+ * corrector (single-surface returns, corner when both surfaces are active),
+ * and C^ep = dT'/d(delta increment) is the exact derivative of that
+ * algorithm: the consistent tangent of the mechanical Jacobian
+ * J = E - eta/dt - C^ep (Sec. 3.1.1).  The integration details are in the
+ * paper's supplement, which this library does not follow; the scheme above
+ * is its own.  The local problems are assumed well posed: each stiffness
+ * exceeds the softening rate of the strength it controls.
+ */
+typedef struct {
+    double k_s, k_n;          /* shear and normal stiffness (Pa/m), finite, > 0 */
+    double f_peak, f_res;     /* friction coefficient at zero slip and residual: 0 <= f_res <= f_peak */
+    double psi_peak;          /* dilatancy coefficient at zero slip, >= 0 (residual 0) */
+    double d_c;               /* slip-weakening distance (m): 0 = residual from the start, INFINITY = none */
+    double c_peak;            /* cohesion at zero damage (Pa), >= f_peak * sigma_peak */
+    double sigma_peak;        /* tensile strength at zero damage (Pa), >= 0 */
+    double w_c;               /* critical inelastic DD of c and sigma_t (m): 0 = fully damaged
+                                 (pre-existing fracture), INFINITY = no weakening */
+} hm_interface_material;
+
+/* Interface modes reported per element */
+enum { HM_IF_ELASTIC = 0, HM_IF_SHEAR = 1, HM_IF_TENSILE = 2, HM_IF_CORNER = 3, HM_IF_OPEN = 4,
+       HM_IF_BAD_MATERIAL = -1 };
+
+/*
+ * Integrate the interface law of n_elem elements over one step.
+ *   mats       host array of n_mat materials (1 <= n_mat <= 16), validated:
+ *              HM_EINVAL on a violated bound
+ *   d_mat_id   [N] int32 material index per element, or NULL for material 0;
+ *              an element whose index is outside [0, n_mat) gets NaN
+ *              outputs and mode HM_IF_BAD_MATERIAL
+ *   d_ddelta   [N][3] increment of the total DD over the step (m)
+ *   d_t        [N][3] effective traction T' at the start of the step (Pa)
+ *   d_dp       [N][3] inelastic DD delta^p at the start (m)
+ *   d_chi      [N][3] internal variables at the start: chi_s, chi_t (m) and
+ *              the residual width w_R (m; initially the paper's alpha w_c for
+ *              an intact interface, 0 for a pre-existing fracture)
+ *   d_t_new, d_dp_new, d_chi_new  [N][3] the same at the end of the step
+ *   d_cep      [N][3][3] row-major consistent tangent dT'/d(d_ddelta) (Pa/m)
+ *   d_mode     [N] int32 HM_IF_* per element, or NULL
+ *   d_eta_dt   [N][3] diagonal of eta/dt (Pa/m) or NULL for 0
+ *   d_D        [N][3][3] or NULL: D = C^ep + eta/dt, ready for hm_tangent_set
+ * All arrays are FP64/int32 device memory, element-major.  An output may be
+ * the same array as the matching input (in-place update); other overlaps
+ * are not allowed.  Asynchronous on hip_stream; n_elem = 0 is a no-op.
+ */
+hm_status hm_interface_update(int n_mat, const hm_interface_material* mats, int64_t n_elem, const int32_t* d_mat_id,
+                              const double* d_ddelta, const double* d_t, const double* d_dp, const double* d_chi,
+                              double* d_t_new, double* d_dp_new, double* d_chi_new, double* d_cep, int32_t* d_mode,
+                              const double* d_eta_dt, double* d_D, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Learned correction of the block preconditioner                       */
 /* ------------------------------------------------------------------ */
 /*

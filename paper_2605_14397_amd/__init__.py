@@ -23,6 +23,7 @@ HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_APPLY_REFERENCE, HM_APPLY_TANGENT, HM_APPLY_ACCUMULATE = 1, 2, 4
 HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF = 0, 1, 2, 3, 4
 HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3
+HM_IF_ELASTIC, HM_IF_SHEAR, HM_IF_TENSILE, HM_IF_CORNER, HM_IF_OPEN, HM_IF_BAD_MATERIAL = 0, 1, 2, 3, 4, -1
 
 _STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "HM_EBADMESH",
            -5: "HM_EUNSUPPORTED", -6: "HM_ENOTCONV", -7: "HM_EINTERNAL"}
@@ -38,7 +39,7 @@ EXPORTS = [
     "hm_learned_create", "hm_learned_destroy", "hm_learned_set_base", "hm_learned_num_params",
     "hm_learned_get_params",
     "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
-    "hm_learned_attach", "hm_learned_detach", "hm_precond_apply",
+    "hm_learned_attach", "hm_learned_detach", "hm_precond_apply", "hm_interface_update",
 ]
 
 
@@ -97,6 +98,11 @@ class BatchInfo(ctypes.Structure):
                 ("tune_ms", ctypes.c_double * 5), ("bytes_operators", ctypes.c_int64)]
 
 
+class InterfaceMaterial(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "k_s", "k_n", "f_peak", "f_res", "psi_peak", "d_c", "c_peak", "sigma_peak", "w_c")]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_leaves", "n_dense_blocks", "n_lowrank_blocks", "dense_entries", "lowrank_sum_mn", "max_leaf",
@@ -149,6 +155,7 @@ def lib():
             "hm_learned_attach": ([P, P, P], I),
             "hm_learned_detach": ([P], None),
             "hm_precond_apply": ([P, I, I, P, I64, P, I64, P], I),
+            "hm_interface_update": ([I, P, I64, P, P, P, P, P, P, P, P, P, P, P, P, P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -464,3 +471,44 @@ def learned_features(op: Operator, neighbors: int, stream=None):
     _check(lib().hm_learned_features(op._h, neighbors, P, ctypes.byref(n), ptr(pe), ptr(pf), ptr(feat), ptr(scale),
                                      _stream(stream)))
     return pe, pf, feat, scale
+
+
+# ---------------------------------------------------------------- interface law
+def interface_update(mats, dd, t, dp, chi, mat_id=None, eta_dt=None, want_D=False, out=None, stream=None):
+    """One step of the interface elasto-plastic law (hm_interface_update).
+
+    mats: [n_mat, 9] host array (fields of hm_interface_material in order);
+    dd, t, dp, chi: CUDA float64 [N, 3]; mat_id: CUDA int32 [N] or None;
+    eta_dt: CUDA float64 [N, 3] or None.  Returns a dict of CUDA tensors
+    t, dp, chi [N, 3], cep [N, 3, 3], mode [N] (int32) and, with want_D,
+    D = cep + diag(eta_dt).  `out` may supply the output tensors (for
+    in-place updates pass the inputs themselves)."""
+    import torch
+
+    mats = np.ascontiguousarray(np.atleast_2d(mats), dtype=np.float64)
+    n_mat = mats.shape[0]
+    arr = (InterfaceMaterial * max(n_mat, 1))()
+    for i in range(n_mat):
+        for j, (name, _) in enumerate(InterfaceMaterial._fields_):
+            setattr(arr[i], name, float(mats[i, j]))
+    N = dd.shape[0]
+    dev = dd.device
+    o = dict(out or {})
+    for k in ("t", "dp", "chi"):
+        o.setdefault(k, torch.empty(N, 3, dtype=torch.float64, device=dev))
+    o.setdefault("cep", torch.empty(N, 3, 3, dtype=torch.float64, device=dev))
+    o.setdefault("mode", torch.empty(N, dtype=torch.int32, device=dev))
+    if want_D:
+        o.setdefault("D", torch.empty(N, 3, 3, dtype=torch.float64, device=dev))
+    f64 = torch.float64
+    pin = [_dev_ptr(x, f64) for x in (dd, t, dp, chi)]
+    if any(not x.is_contiguous() for x in (dd, t, dp, chi)):
+        raise HMError(HM_EINVAL, "state arrays must be contiguous")
+    mid = _dev_ptr(mat_id, torch.int32) if mat_id is not None else None
+    eta = _dev_ptr(eta_dt, f64) if eta_dt is not None else None
+    Dp = _dev_ptr(o["D"], f64) if want_D else None
+    _check(lib().hm_interface_update(n_mat, ctypes.cast(arr, ctypes.c_void_p), N, mid, *pin,
+                                     _dev_ptr(o["t"], f64), _dev_ptr(o["dp"], f64), _dev_ptr(o["chi"], f64),
+                                     _dev_ptr(o["cep"], f64), _dev_ptr(o["mode"], torch.int32), eta, Dp,
+                                     _stream(stream)))
+    return o

@@ -322,6 +322,18 @@ hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double*
     });
 }
 
+hm_status hm_interface_update(int n_mat, const hm_interface_material* mats, int64_t n_elem, const int32_t* d_mat_id,
+                              const double* d_ddelta, const double* d_t, const double* d_dp, const double* d_chi,
+                              double* d_t_new, double* d_dp_new, double* d_chi_new, double* d_cep, int32_t* d_mode,
+                              const double* d_eta_dt, double* d_D, void* hip_stream)
+{
+    return guarded([&] {
+        require_gfx950();
+        hm::interface_update(n_mat, mats, n_elem, d_mat_id, d_ddelta, d_t, d_dp, d_chi, d_t_new, d_dp_new, d_chi_new,
+                             d_cep, d_mode, d_eta_dt, d_D, (hipStream_t)hip_stream);
+    });
+}
+
 hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out)
 {
     return guarded([&] {

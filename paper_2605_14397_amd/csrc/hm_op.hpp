@@ -154,6 +154,10 @@ void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
 void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, std::pair<int, int>* groupA);
 void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
+void interface_update(int n_mat, const hm_interface_material* mats, int64_t n, const int32_t* d_mat_id,
+                      const double* d_dd, const double* d_t, const double* d_dp, const double* d_chi, double* d_t_new,
+                      double* d_dp_new, double* d_chi_new, double* d_cep, int32_t* d_mode, const double* d_eta_dt,
+                      double* d_D, hipStream_t s);
 
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,

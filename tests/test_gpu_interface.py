@@ -1,0 +1,148 @@
+"""GPU interface law (hm_interface_update) against the CPU FP64 oracle.
+
+Bars: the mode of every element is bit-exact (both sides decide it in FP64
+on the same comparisons); end-of-step traction, inelastic DD and internal
+variables agree to 1e-11 of their scale (the scalar consistency equations
+are solved to a few ulps on both sides: safeguarded Newton here, Brent in
+the oracle); the consistent tangent to 1e-9 of the largest stiffness
+(dual numbers here, complex steps in the oracle).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import interface as ifo
+from workloads import rect_grid, rhs_columns
+from workloads.interface import interface_materials, interface_states
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+YOUNG, NU = 30e9, 0.25
+
+
+def _hm():
+    import paper_2605_14397_amd as hm
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return hm
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _run_gpu(hm, mats, st, **kw):
+    r = hm.interface_update(mats, cuda(st["dd"]), cuda(st["t"]), cuda(st["dp"]), cuda(st["chi"]),
+                            mat_id=cuda(st["mat_id"], torch.int32), **kw)
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def _compare(g, o, idx, mats, st):
+    """g: GPU outputs for all elements; o: oracle outputs for elements idx."""
+    modes = g["mode"][idx]
+    assert np.array_equal(modes, o[4]), np.nonzero(modes != o[4])
+    kmax = mats[:, :2].max()
+    tscale = np.abs(st["t"][idx]).max() + kmax * np.abs(st["dd"][idx]).max()
+    np.testing.assert_allclose(g["t"][idx], o[0], rtol=0, atol=1e-11 * tscale)
+    dscale = np.abs(o[1]).max() + 1e-12
+    np.testing.assert_allclose(g["dp"][idx], o[1], rtol=0, atol=1e-11 * dscale)
+    np.testing.assert_allclose(g["chi"][idx], o[2], rtol=0, atol=1e-11 * (np.abs(o[2]).max() + 1e-12))
+    np.testing.assert_allclose(g["cep"][idx], o[3], rtol=0, atol=1e-9 * kmax)
+
+
+def test_every_mode_matches_the_oracle():
+    hm = _hm()
+    mats = interface_materials()
+    st = interface_states(3000, 9101, mats)
+    g = _run_gpu(hm, mats, st)
+    o = ifo.update(mats, st["mat_id"], st["dd"], st["t"], st["dp"], st["chi"])
+    _compare(g, o, np.arange(3000), mats, st)
+    counts = np.bincount(o[4], minlength=5)
+    print("modes elastic/shear/tensile/corner/open:", counts.tolist(), flush=True)
+    assert (counts > 0).all(), counts
+
+
+def test_hf_fault_size_sampled_against_the_oracle():
+    """199,880 elements (the HF x fault mesh's count), materials by part:
+    fracture elements intact joints, fault elements weakening faults; 1,500
+    sampled elements checked against the oracle."""
+    hm = _hm()
+    mats = interface_materials()
+    n, n_hf = 199_880, 11_180
+    mat_id = np.full(n, 2, np.int32)
+    mat_id[:n_hf] = 0
+    st = interface_states(n, 9102, mats, mat_id)
+    g = _run_gpu(hm, mats, st)
+    assert np.isfinite(g["cep"]).all() and (g["mode"] >= 0).all()
+    idx = np.sort(np.random.default_rng(9103).choice(n, 1500, replace=False))
+    o = ifo.update(mats, st["mat_id"][idx], st["dd"][idx], st["t"][idx], st["dp"][idx], st["chi"][idx])
+    sub = {k: v[idx] for k, v in st.items()}
+    _compare({k: v[idx] for k, v in g.items()}, o, np.arange(len(idx)), mats, sub)
+
+
+def test_in_place_update_and_D_output():
+    hm = _hm()
+    mats = interface_materials()
+    st = interface_states(700, 9104, mats)
+    ref = _run_gpu(hm, mats, st)
+    eta = np.random.default_rng(9105).uniform(1e8, 1e9, (700, 3))
+    T, dp, chi = cuda(st["t"]), cuda(st["dp"]), cuda(st["chi"])
+    r = hm.interface_update(mats, cuda(st["dd"]), T, dp, chi, mat_id=cuda(st["mat_id"], torch.int32),
+                            eta_dt=cuda(eta), want_D=True, out=dict(t=T, dp=dp, chi=chi))
+    assert r["t"].data_ptr() == T.data_ptr()
+    for k in ("t", "dp", "chi", "cep", "mode"):
+        assert np.array_equal(r[k].cpu().numpy(), ref[k]), k
+    D = r["D"].cpu().numpy()
+    expect = ref["cep"].copy()
+    expect[:, [0, 1, 2], [0, 1, 2]] += eta
+    assert np.array_equal(D, expect)
+
+
+def test_empty_bad_ids_and_invalid_materials():
+    hm = _hm()
+    mats = interface_materials()
+    e = torch.empty(0, 3, dtype=torch.float64, device="cuda")
+    r = hm.interface_update(mats, e, e, e, e)
+    assert r["t"].shape == (0, 3)
+    st = interface_states(64, 9106, mats)
+    st["mat_id"][5] = 3
+    st["mat_id"][9] = -1
+    g = _run_gpu(hm, mats, st)
+    assert g["mode"][5] == hm.HM_IF_BAD_MATERIAL and g["mode"][9] == hm.HM_IF_BAD_MATERIAL
+    assert np.isnan(g["t"][5]).all() and np.isnan(g["cep"][9]).all()
+    ok = np.delete(np.arange(64), [5, 9])
+    assert (g["mode"][ok] >= 0).all()
+    for field, value in (("k_s", 0.0), ("f_res", 0.9), ("c_peak", 0.1e6), ("w_c", -1.0), ("k_n", np.inf)):
+        bad = mats.copy()
+        bad[0, list(("k_s", "k_n", "f_peak", "f_res", "psi_peak", "d_c", "c_peak", "sigma_peak", "w_c")).index(field)] = value
+        with pytest.raises(hm.HMError, match="HM_EINVAL"):
+            _run_gpu(hm, bad, st)
+    with pytest.raises(hm.HMError, match="HM_EINVAL"):
+        _run_gpu(hm, np.repeat(mats, 6, axis=0), st)  # 18 > 16 materials
+
+
+def test_tangent_from_the_law_drives_the_solve():
+    """D = C^ep + eta/dt from hm_interface_update fed to hm_tangent_set; the
+    GMRES solution of A11 x = b matches dense LU of E - D with D from the
+    oracle's own interface law."""
+    hm = _hm()
+    m = rect_grid(14, 10, 1.0)
+    ne = m.ne
+    mats = interface_materials()
+    st = interface_states(ne, 9107, mats)
+    eta = np.full((ne, 3), 2.0e8)
+    g = _run_gpu(hm, mats, st, eta_dt=cuda(eta), want_D=True)
+    o = ifo.update(mats, st["mat_id"], st["dd"], st["t"], st["dp"], st["chi"])
+    D_or = o[3].copy()
+    D_or[:, [0, 1, 2], [0, 1, 2]] += eta
+    A = oracle.tangent_dense(oracle.dense(m, YOUNG, NU), D_or, None)
+    b = rhs_columns(m.ndof, 2, 9108) * 1e6
+    x_ref = oracle.solve_dense(A, b)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=16, aca_tol=1e-10)
+    op.set_tangent(cuda(g["D"]))
+    x, rep = op.solve(cuda(b), rtol=1e-12, restart=50, max_iter=2000)
+    x = x.cpu().numpy()
+    err = max(np.linalg.norm(x[c] - x_ref[c]) / np.linalg.norm(x_ref[c]) for c in range(2))
+    print("modes", np.bincount(o[4], minlength=5).tolist(), "iterations", rep["iterations"], "err", err, flush=True)
+    assert err <= 1e-8, err

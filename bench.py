@@ -50,6 +50,16 @@ PROFILE_COMMANDS = {
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"copy|Copy\" --output-format csv "
                   "-d gpurun_out/prof/copy_write -o copy -- python3 bench.py --form copy --steps 3",
 }
+IF_PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_if/trace -o interface -- "
+             "python3 bench.py --form interface --if-states mixed --steps 20 --warmup 3 --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex interface --output-format csv "
+             "-d gpurun_out/prof_if/fetch -o interface -- "
+             "python3 bench.py --form interface --if-states mixed --steps 3 --warmup 1 --no-cpu-baseline",
+    "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex interface --output-format csv "
+             "-d gpurun_out/prof_if/write -o interface -- "
+             "python3 bench.py --form interface --if-states mixed --steps 3 --warmup 1 --no-cpu-baseline",
+}
 PHASE_KERNELS = ("k_gather", "k_phaseA", "k_reduceT", "k_phaseB", "k_scatter")
 
 
@@ -130,6 +140,66 @@ def summarize_profiles(prof_dir: str):
     print(json.dumps(d))
 
 
+def interface_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2605_14397_amd", "csrc", "hm_interface.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def interface_traffic():
+    """HBM bytes per interface-law launch from the committed counter summary,
+    if it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic_interface.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    return d.get("hbm_bytes_per_launch") if d.get("source_hash") == interface_source_hash() else None
+
+
+def summarize_interface_profiles(prof_dir: str):
+    """profiles/ summaries of the interface-law kernel from rocprofv3 CSVs
+    (IF_PROFILE_COMMANDS run with prof_dir as gpurun_out/prof_if)."""
+    import csv
+
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        cal = json.load(fh)
+    fs, ws = cal["fetch_scale"], cal["write_scale"]
+    stats = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "interface_kernel_stats.csv"))))
+    k = [r for r in stats if "k_interface_update" in r["Name"]][0]
+
+    def counter(sub, name):
+        rows = list(csv.DictReader(open(os.path.join(prof_dir, sub, "interface_counter_collection.csv"))))
+        v = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name]
+        return sum(v) / len(v), rows[0]
+
+    fetch, row = counter("fetch", "FETCH_SIZE")
+    write, _ = counter("write", "WRITE_SIZE")
+    n = 199_880
+    traffic = int(round((fetch * fs + write * ws) * 1024))
+    alg = n * IF_BYTES_PER_ELEMENT
+    d = {"source_hash": interface_source_hash(), "fetch_scale": fs, "write_scale": ws,
+         "workload": "199,880 interface elements, every regime mixed (bench.py --form interface --if-states mixed)",
+         "fetch_kib": round(fetch, 1), "write_kib": round(write, 1), "hbm_bytes_per_launch": traffic,
+         "alg_bytes_per_launch": alg}
+    with open(os.path.join(ROOT, "profiles", "traffic_interface.json"), "w") as fh:
+        json.dump(d, fh, indent=1)
+    lines = ["# Interface-law kernel: 199,880 elements, every regime mixed", "",
+             "Commands (from the repository root, `TMPDIR=/tmp`):", "", "```"]
+    lines += [IF_PROFILE_COMMANDS[c] for c in ("trace", "fetch", "write")]
+    lines += ["```", "",
+              f"`k_interface_update`: {k['Calls']} launches, average {float(k['AverageNs']) / 1e3:.1f} us "
+              f"(min {float(k['MinNs']) / 1e3:.1f}, max {float(k['MaxNs']) / 1e3:.1f}); "
+              f"scratch {row['Scratch_Size']} B per lane.", "",
+              f"HBM counters per launch: FETCH_SIZE {fetch:.1f} KiB x {fs} + WRITE_SIZE {write:.1f} KiB x {ws} "
+              f"(scales from the 2 GiB copy calibration in traffic.json) = {traffic / 1e6:.2f} MB, against "
+              f"{alg / 1e6:.2f} MB algorithmic ({IF_BYTES_PER_ELEMENT} B per element: increment, traction, "
+              "inelastic DD, internal variables, material index and eta/dt read; traction, inelastic DD, internal "
+              f"variables, tangent, mode and D written): {traffic / alg:.3f}x.", ""]
+    with open(os.path.join(ROOT, "profiles", "interface_update_hf_fault.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps(d))
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current apply source; else None."""
@@ -154,19 +224,26 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "copy"], default="primary",
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "copy"],
+                    default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
                          "learned: trained preconditioner correction on the HF x fault tangent solves; "
+                         "interface: interface-law update and consistent tangent of 199,880 elements; "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
+    ap.add_argument("--if-states", choices=["both", "mixed", "elastic"], default="both",
+                    help="interface form: which seeded state sets to time (profiling runs use one)")
     ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles)
+        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "interface_kernel_stats.csv")):
+            summarize_interface_profiles(args.summarize_profiles)
+        else:
+            summarize_profiles(args.summarize_profiles)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the H-matrix path here is built and timed on a single MI355X "
@@ -188,6 +265,9 @@ def main():
         return
     if args.form == "learned":
         bench_learned(args)
+        return
+    if args.form == "interface":
+        bench_interface(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -591,6 +671,87 @@ def bench_learned(args):
                         "loss_last_epoch": round(float(np.mean(hist[-128:])), 5),
                         "attach_s_total": round(attach_s, 3)}}
     print(json.dumps(out), flush=True)
+
+
+IF_BYTES_PER_ELEMENT = 4 * 24 + 4 + 24 + 3 * 24 + 72 + 4 + 72
+
+
+def bench_interface(args):
+    """Interface elasto-plastic update with consistent tangent and D = C^ep +
+    eta/dt for 199,880 elements (the HF x fault mesh's element count; the
+    first 11,180 are intact joints of the hydraulic fracture, the rest a
+    weakening fault).  Two seeded state sets: every regime mixed (a quarter
+    each compressed and shear-loaded, near the cut-off, partly weakened, fully
+    damaged) and all elastic (the memory path alone)."""
+    import numpy as np
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads.interface import interface_materials, interface_states
+
+    n, n_hf = 199_880, 11_180
+    mats = interface_materials()
+    mat_id = np.full(n, 2, np.int32)
+    mat_id[:n_hf] = 0
+    cu = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    eta = cu(np.full((n, 3), 2.0e8))
+    res = {}
+    names = ("mixed", "elastic") if args.if_states == "both" else (args.if_states,)
+    for name in names:
+        st = interface_states(n, 9201, mats, mat_id)
+        if name == "elastic":
+            st["dd"][:] = 0.0
+            st["t"][:] = [0.0, 0.0, -20e6]
+            st["dp"][:] = 0.0
+            st["chi"][:] = 0.0
+        dd, t, dp, chi, mid = cu(st["dd"]), cu(st["t"]), cu(st["dp"]), cu(st["chi"]), cu(st["mat_id"], torch.int32)
+        out = hm.interface_update(mats, dd, t, dp, chi, mat_id=mid, eta_dt=eta, want_D=True)
+        for _ in range(args.warmup):
+            hm.interface_update(mats, dd, t, dp, chi, mat_id=mid, eta_dt=eta, want_D=True, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            hm.interface_update(mats, dd, t, dp, chi, mat_id=mid, eta_dt=eta, want_D=True, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        modes = np.bincount(out["mode"].cpu().numpy(), minlength=5)
+        res[name] = {"ms": round(ms, 4), "elements_per_s": round(n / (ms * 1e-3), 1),
+                     "hbm_gbs": round(n * IF_BYTES_PER_ELEMENT / (ms * 1e-3) / 1e9, 1),
+                     "modes_elastic_shear_tensile_corner_open": modes.tolist()}
+        log(f"interface {name}: {res[name]}")
+    if "mixed" not in res:
+        print(json.dumps({"interface_states": res}), flush=True)
+        return
+    ms = res["mixed"]["ms"]
+    alg = n * IF_BYTES_PER_ELEMENT
+    line = {
+        "metric": "interface-law updates/s (return map + consistent tangent + D, one launch)",
+        "value": res["mixed"]["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{n} interface elements (HF x fault count): {n_hf} intact joints, "
+                               f"{n - n_hf} weakening-fault elements; every regime mixed"},
+        "roofline": {"kernel": "k_interface_update", "bound": "hbm",
+                     "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(alg / (ms * 1e-3) / 1e9 / 8000.0, 4), "traffic": interface_traffic(),
+                     "alg_bytes_per_launch": alg, "launch_ms": ms},
+        "states": res,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import interface as ifo
+
+        st = interface_states(n, 9201, mats, mat_id)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds and done < n:
+            sl = slice(done, min(n, done + 2000))
+            ifo.update(mats, st["mat_id"][sl], st["dd"][sl], st["t"][sl], st["dp"][sl], st["chi"][sl])
+            done = sl.stop
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(done / el, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
+                                "sample": f"first {done} of the {n} mixed-regime elements in {el:.1f} s"}
+    print(json.dumps(line), flush=True)
 
 
 def bench_batched(args):

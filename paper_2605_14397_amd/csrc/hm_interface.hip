@@ -39,19 +39,19 @@ struct Dual {
 };
 
 template <int K>
-__device__ inline Dual<K> seeded(double x, int lane)
+__device__ __forceinline__ Dual<K> seeded(double x, int lane)
 {
     Dual<K> r(x);
     r.d[lane] = 1.0;
     return r;
 }
 
-__device__ inline double val(double x) { return x; }
+__device__ __forceinline__ double val(double x) { return x; }
 template <int K>
-__device__ inline double val(const Dual<K>& x) { return x.v; }
+__device__ __forceinline__ double val(const Dual<K>& x) { return x.v; }
 
 template <int K>
-__device__ inline Dual<K> operator+(const Dual<K>& a, const Dual<K>& b)
+__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, const Dual<K>& b)
 {
     Dual<K> r(a.v + b.v);
 #pragma unroll
@@ -59,7 +59,7 @@ __device__ inline Dual<K> operator+(const Dual<K>& a, const Dual<K>& b)
     return r;
 }
 template <int K>
-__device__ inline Dual<K> operator-(const Dual<K>& a, const Dual<K>& b)
+__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, const Dual<K>& b)
 {
     Dual<K> r(a.v - b.v);
 #pragma unroll
@@ -67,7 +67,7 @@ __device__ inline Dual<K> operator-(const Dual<K>& a, const Dual<K>& b)
     return r;
 }
 template <int K>
-__device__ inline Dual<K> operator*(const Dual<K>& a, const Dual<K>& b)
+__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, const Dual<K>& b)
 {
     Dual<K> r(a.v * b.v);
 #pragma unroll
@@ -75,7 +75,7 @@ __device__ inline Dual<K> operator*(const Dual<K>& a, const Dual<K>& b)
     return r;
 }
 template <int K>
-__device__ inline Dual<K> operator/(const Dual<K>& a, const Dual<K>& b)
+__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, const Dual<K>& b)
 {
     Dual<K> r(a.v / b.v);
 #pragma unroll
@@ -83,15 +83,15 @@ __device__ inline Dual<K> operator/(const Dual<K>& a, const Dual<K>& b)
     return r;
 }
 template <int K>
-__device__ inline Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
+__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
 template <int K>
-__device__ inline Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
+__device__ __forceinline__ Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
 template <int K>
-__device__ inline Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
+__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
 template <int K>
-__device__ inline Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
+__device__ __forceinline__ Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
 template <int K>
-__device__ inline Dual<K> operator*(const Dual<K>& a, double b)
+__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, double b)
 {
     Dual<K> r(a.v * b);
 #pragma unroll
@@ -99,13 +99,13 @@ __device__ inline Dual<K> operator*(const Dual<K>& a, double b)
     return r;
 }
 template <int K>
-__device__ inline Dual<K> operator*(double a, const Dual<K>& b) { return b * a; }
+__device__ __forceinline__ Dual<K> operator*(double a, const Dual<K>& b) { return b * a; }
 template <int K>
-__device__ inline Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
+__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
 
-__device__ inline double sq(double x) { return sqrt(x); }
+__device__ __forceinline__ double sq(double x) { return sqrt(x); }
 template <int K>
-__device__ inline Dual<K> sq(const Dual<K>& a)
+__device__ __forceinline__ Dual<K> sq(const Dual<K>& a)
 {
     Dual<K> r(sqrt(a.v));
     const double s = r.v > 0.0 ? 0.5 / r.v : 0.0;
@@ -118,7 +118,7 @@ __device__ inline Dual<K> sq(const Dual<K>& a)
 
 // linear weakening W(x / L) = max(0, 1 - x / L); L = 0: fully weakened; L = inf: none
 template <class S>
-__device__ inline S weaken(const S& x, double L)
+__device__ __forceinline__ S weaken(const S& x, double L)
 {
     if (!(L > 0.0)) return S(0.0);
     S r = 1.0 - x / L;
@@ -127,25 +127,25 @@ __device__ inline S weaken(const S& x, double L)
 
 // running maximum of a magnitude: the new value wins only when strictly larger
 template <class S>
-__device__ inline S grow(double old, const S& nw)
+__device__ __forceinline__ S grow(double old, const S& nw)
 {
     return val(nw) > old ? nw : S(old);
 }
 
 template <class S>
-__device__ inline S friction(const hm_interface_material& m, const S& chi_s)
+__device__ __forceinline__ S friction(const hm_interface_material& m, const S& chi_s)
 {
     return m.f_res + (m.f_peak - m.f_res) * weaken(chi_s, m.d_c);
 }
 
 template <class S>
-__device__ inline S coulomb(const hm_interface_material& m, const S& tau, const S& tn, const S* chi)
+__device__ __forceinline__ S coulomb(const hm_interface_material& m, const S& tau, const S& tn, const S* chi)
 {
     return tau + friction(m, chi[0]) * tn - m.c_peak * weaken(chi[1], m.w_c);
 }
 
 template <class S>
-__device__ inline S cutoff(const hm_interface_material& m, const S& tn, const S* chi)
+__device__ __forceinline__ S cutoff(const hm_interface_material& m, const S& tn, const S* chi)
 {
     return tn - m.sigma_peak * weaken(chi[1], m.w_c);
 }
@@ -162,7 +162,7 @@ struct EndState {
 // multipliers: shear slip lam along tau_tr / |tau_tr|; normal inelastic DD
 // lam * psi (Coulomb flow alone, `dilatant`) or nu.
 template <class S>
-__device__ inline EndState<S> end_state(const hm_interface_material& m, const S* Ttr, const double* dps,
+__device__ __forceinline__ EndState<S> end_state(const hm_interface_material& m, const S* Ttr, const double* dps,
                                         const double* chi0, const S& lam, const S& nu, bool dilatant)
 {
     EndState<S> e;
@@ -197,10 +197,13 @@ __device__ inline EndState<S> end_state(const hm_interface_material& m, const S*
 }
 
 // Root of a function decreasing on [0, hi]: 0 if f(0) <= 0, hi if f(hi) >= 0,
-// else safeguarded Newton (bisection whenever the step leaves the bracket).
-// fn(x, fx) stores f(x) in fx and returns f'(x).
+// else safeguarded Newton from the secant point: it stops once a Newton
+// correction falls below 1e-12 of the iterate (the next error is below
+// rounding), and a bisection step replaces any Newton step that leaves the
+// bracket or does not halve the previous step.  fn(x, fx) stores f(x) in fx
+// and returns f'(x).
 template <class F>
-__device__ double root_dec(F fn, double hi)
+__device__ __forceinline__ double root_dec(F fn, double hi)
 {
     if (!(hi > 0.0)) return 0.0;
     double f0, fh;
@@ -208,30 +211,36 @@ __device__ double root_dec(F fn, double hi)
     if (f0 <= 0.0) return 0.0;
     fn(hi, fh);
     if (fh >= 0.0) return hi;
-    double a = 0.0, b = hi, fa = f0, fb = fh;
-    double x = a + (b - a) * (fa / (fa - fb));
-    for (int it = 0; it < 200; ++it) {
+    double a = 0.0, b = hi;
+    double x = hi * (f0 / (f0 - fh));
+    double step_old = hi;
+    for (int it = 0; it < 100; ++it) {
         double fx;
         const double dfx = fn(x, fx);
         if (fx == 0.0) return x;
-        if (fx > 0.0) {
+        if (fx > 0.0)
             a = x;
-            fa = fx;
-        } else {
+        else
             b = x;
-            fb = fx;
+        double xn = dfx < 0.0 ? x - fx / dfx : a;
+        double step = fabs(xn - x);
+        // a negligible Newton correction: converged (quadratically) to rounding
+        if (dfx < 0.0 && step <= 1e-12 * x) return xn;
+        if (!(xn > a && xn < b) || 2.0 * step > step_old) {
+            xn = 0.5 * (a + b);
+            step = 0.5 * (b - a);
         }
-        double xn = dfx < 0.0 ? x - fx / dfx : 0.5 * (a + b);
-        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
-        if (fabs(xn - x) <= 4e-16 * fabs(xn) || (b - a) <= 4e-16 * b) return xn;
+        if (step <= 4e-16 * xn || (b - a) <= 8e-16 * b) return xn;
+        step_old = step;
         x = xn;
     }
     return x;
 }
 
 template <int K>
-__device__ inline void lift(const double* T, Dual<K>* out)
+__device__ __forceinline__ void lift(const double* T, Dual<K>* out)
 {
+#pragma unroll
     for (int i = 0; i < 3; ++i) out[i] = Dual<K>(T[i]);
 }
 
@@ -240,7 +249,7 @@ struct Element {
     int32_t mode;
 };
 
-__device__ Element update_one(const hm_interface_material& m, const double* dd, const double* T0, const double* dp0,
+__device__ __forceinline__ Element update_one(const hm_interface_material& m, const double* dd, const double* T0, const double* dp0,
                               const double* chi0)
 {
     Element out;
@@ -257,7 +266,9 @@ __device__ Element update_one(const hm_interface_material& m, const double* dd, 
             out.chi[0] = fmax(chi0[0], sqrt(out.dp[0] * out.dp[0] + out.dp[1] * out.dp[1]));
             out.chi[1] = fmax(chi0[1], sqrt(out.dp[0] * out.dp[0] + out.dp[1] * out.dp[1] + out.dp[2] * out.dp[2]));
             out.chi[2] = chi0[2];
+#pragma unroll
             for (int i = 0; i < 3; ++i) out.T[i] = 0.0;
+#pragma unroll
             for (int i = 0; i < 9; ++i) out.cep[i] = 0.0;
             return out;
         }
@@ -366,33 +377,43 @@ __device__ Element update_one(const hm_interface_material& m, const double* dd, 
     if (lam_on) lam5.d[3] = 1.0;
     if (nu_on) nu5.d[4] = 1.0;
     const EndState<Dual<L>> e = end_state(m, T5, dps, chi0, lam5, nu5, mode == kShear);
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         out.T[i] = e.T[i].v;
         out.dp[i] = e.dp[i].v;
         out.chi[i] = e.chi[i].v;
     }
     double cep[3][3];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) cep[i][j] = e.T[i].d[j];
-    if (lam_on && nu_on) {
-        const Dual<L> rc = coulomb(m, e.tau, e.T[2], e.chi);
-        const Dual<L> rt = cutoff(m, e.T[2], e.chi);
-        const double a = rc.d[3], b = rc.d[4], c = rt.d[3], d = rt.d[4];
-        const double det = a * d - b * c;
-        for (int j = 0; j < 3; ++j) {
-            const double yl = -(d * rc.d[j] - b * rt.d[j]) / det;
-            const double yn = -(a * rt.d[j] - c * rc.d[j]) / det;
-            for (int i = 0; i < 3; ++i) cep[i][j] += e.T[i].d[3] * yl + e.T[i].d[4] * yn;
-        }
-    } else if (lam_on || nu_on) {
-        const int u = lam_on ? 3 : 4;
-        const Dual<L> r = lam_on ? coulomb(m, e.tau, e.T[2], e.chi) : cutoff(m, e.T[2], e.chi);
-        for (int j = 0; j < 3; ++j) {
-            const double y = -r.d[j] / r.d[u];
-            for (int i = 0; i < 3; ++i) cep[i][j] += e.T[i].d[u] * y;
-        }
+    // implicit function theorem on the active consistency equations (Fc for
+    // lam, Ft for nu); an inactive multiplier is pinned by an identity row
+    const Dual<L> rc = coulomb(m, e.tau, e.T[2], e.chi);
+    const Dual<L> rt = cutoff(m, e.T[2], e.chi);
+    double a = 1.0, b = 0.0, c = 0.0, d = 1.0;
+    if (lam_on) {
+        a = rc.d[3];
+        b = rc.d[4];
     }
+    if (nu_on) {
+        c = rt.d[3];
+        d = rt.d[4];
+    }
+    const double det = a * d - b * c;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double r1 = lam_on ? rc.d[j] : 0.0;
+        const double r2 = nu_on ? rt.d[j] : 0.0;
+        const double yl = -(d * r1 - b * r2) / det;
+        const double yn = -(a * r2 - c * r1) / det;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) cep[i][j] += e.T[i].d[3] * yl + e.T[i].d[4] * yn;
+    }
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) out.cep[3 * i + j] = cep[i][j];
     return out;
 }
@@ -407,6 +428,7 @@ __global__ __launch_bounds__(256) void k_interface_update(IfMats mats, int n_mat
     if (e >= n) return;
     const int id = mat_id ? mat_id[e] : 0;
     double in_dd[3], in_t[3], in_dp[3], in_chi[3];
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         in_dd[i] = dd[3 * e + i];
         in_t[i] = t0[3 * e + i];
@@ -416,22 +438,28 @@ __global__ __launch_bounds__(256) void k_interface_update(IfMats mats, int n_mat
     Element r;
     if (id < 0 || id >= n_mat) {
         const double nan = __builtin_nan("");
+#pragma unroll
         for (int i = 0; i < 3; ++i) r.T[i] = r.dp[i] = r.chi[i] = nan;
+#pragma unroll
         for (int i = 0; i < 9; ++i) r.cep[i] = nan;
         r.mode = kBadMaterial;
     } else {
         r = update_one(mats.m[id], in_dd, in_t, in_dp, in_chi);
     }
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         t1[3 * e + i] = r.T[i];
         dp1[3 * e + i] = r.dp[i];
         chi1[3 * e + i] = r.chi[i];
     }
+#pragma unroll
     for (int i = 0; i < 9; ++i) cep[9 * e + i] = r.cep[i];
     if (mode) mode[e] = r.mode;
     if (D) {
+#pragma unroll
         for (int i = 0; i < 9; ++i) D[9 * e + i] = r.cep[i];
         if (eta_dt)
+#pragma unroll
             for (int i = 0; i < 3; ++i) D[9 * e + 4 * i] += eta_dt[3 * e + i];
     }
 }

@@ -234,6 +234,9 @@ def main():
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
+    ap.add_argument("--tangents", choices=["law", "closed-form"], default="law",
+                    help="learned form: tangent states from the interface law driven along a seeded injection "
+                         "path (law), or the closed-form synthetic states")
     ap.add_argument("--if-states", choices=["both", "mixed", "elastic"], default="both",
                     help="interface form: which seeded state sets to time (profiling runs use one)")
     ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
@@ -542,10 +545,34 @@ def bench_precision(args):
     print(json.dumps(out), flush=True)
 
 
+def law_tangent_states(hm, m, n_states=20):
+    """D_k = C^ep + eta/dt of the interface law (hm_interface_update, in place
+    on the GPU) after step k of the seeded injection path, k = 0..n_states-1."""
+    import numpy as np
+    import torch
+
+    from workloads.interface import injection_path
+
+    p = injection_path(m, n_states)
+    cu = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    t, dp, chi, mid = cu(p["t"]), cu(p["dp"]), cu(p["chi"]), cu(p["mat_id"], torch.int32)
+    Ds, modes = [], []
+    for k in range(n_states):
+        r = hm.interface_update(p["mats"], cu(p["dd"][k]), t, dp, chi, mat_id=mid, eta_dt=cu(p["eta_dt"][k]),
+                                want_D=True, out=dict(t=t, dp=dp, chi=chi))
+        Ds.append(r["D"])
+        modes.append(np.bincount(r["mode"].cpu().numpy(), minlength=5).tolist())
+    log(f"interface-law tangent states: modes elastic/shear/tensile/corner/open at steps 0, 15, 19: "
+        f"{modes[0]}, {modes[15]}, {modes[-1]}")
+    return Ds, modes
+
+
 def bench_learned(args):
     """Learned correction of the block preconditioner on the tangent solves
-    of a synthetic injection sequence on the HF x fault mesh (20 tangent
-    states, paper Sec. 3.1.1 / 3.3.1 shapes).
+    of an injection sequence on the HF x fault mesh (20 tangent states,
+    paper Sec. 3.1.1 / 3.3.1): by default D = C^ep + eta/dt from the
+    interface law (hm_interface_update) driven along a seeded injection
+    path, else (--tangents closed-form) the closed-form synthetic states.
 
     Training data: for states 0..15, 128 FP64 GMRES solves each (2,048 in
     all) of A11 x = b with b = A11 x0 for seeded white x0 (the method's own
@@ -576,13 +603,19 @@ def bench_learned(args):
         torch.cuda.synchronize()
         log(f"built {name} in {time.perf_counter() - t0:.1f} s")
     op = ops["fp64"]
+    law_modes = None
+    if args.tangents == "law":
+        Ds, law_modes = law_tangent_states(hm, m)
+        tangent = lambda k: Ds[k]
+    else:
+        tangent = lambda k: cuda(tangent_state(m, k))
     # training pairs from the method's own FP64 solves
     t0 = time.perf_counter()
     data = []
     solve_its = []
     per_state = 8 * NRHS
     for k in range(16):
-        op.set_tangent(cuda(tangent_state(m, k)))
+        op.set_tangent(tangent(k))
         bs, xs = [], []
         for j in range(per_state // NRHS):
             x0 = cuda(rhs_columns(n, NRHS, 7000 + per_state * k + NRHS * j))
@@ -601,7 +634,7 @@ def bench_learned(args):
         hist = []
         for ep in range(args.train_epochs):
             for k in range(16):
-                op.set_tangent(cuda(tangent_state(m, k)))
+                op.set_tangent(tangent(k))
                 b, x = data[k]
                 hist.extend(net.train(op, b, x, steps=8, batch=16, lr=1e-3))
             log(f"epoch {ep} (base {base}): mean loss {np.mean(hist[-128:]):.4g}")
@@ -621,7 +654,7 @@ def bench_learned(args):
                        "precision_learned_on_leaf")}
     attach_s = 0.0
     for k in range(16, 20):
-        D = cuda(tangent_state(m, k))
+        D = tangent(k)
         rhs = cuda(tangent_rhs(m, NRHS, 9000 + k))
         for name, o in ops.items():
             o.set_tangent(D)
@@ -659,9 +692,12 @@ def bench_learned(args):
            "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
            "config": {"workload": f"HF x fault, {m.ne} triangles, {n} DOF; leaf 64, eta 2, ACA 1e-6; "
                                   "tangent states 16-19 of 20, 16 right-hand sides each; GMRES(50)",
+                      "tangents": ("interface law along a seeded injection path (D = C^ep + eta/dt from "
+                                   "hm_interface_update)" if args.tangents == "law"
+                                   else "closed-form synthetic states"),
                       "network": f"32-64-64-9 MLP, {args.neighbors} neighbours", "training_states": 16,
                       "training_samples": 16 * per_state, "adam_steps": steps},
-           "forms": forms,
+           "forms": forms, "law_modes_elastic_shear_tensile_corner_open": law_modes,
            "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},
            "training": {"train_leaf_base_s": round(train_leaf_s, 2),
                         "loss_last_epoch_leaf_base": round(float(np.mean(hist_leaf[-128:])), 5),

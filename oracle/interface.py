@@ -37,7 +37,9 @@ mechanical Jacobian J = E - eta/dt - C^ep).  The steps, in order:
      increment inelastic); otherwise the gap closes first (d^p_n -= g,
      T_tr,n += Kn g);
   3. Fc and Ft at the trial state and chi at the start: both <= 0 gives
-     ELASTIC (C^ep = C);
+     ELASTIC (C^ep = C) (every surface test here and below allows 1e-12 of
+     the trial traction scale, so that ties created by the algorithm itself
+     are not decided by rounding);
   4. h at the trial selects SHEAR or TENSILE;
   5. SHEAR: solve Fc(T'(lam), chi(lam)) = 0 for lam in [0, |tau_tr|/Ks],
      T'(lam) = T_tr - lam C (s_hat + psi n), s_hat = tau_tr/|tau_tr|, with
@@ -171,16 +173,24 @@ def _trial(m, dd, T0, dp0, chi0):
 
 # ------------------------------------------------------------------ one element
 
-def _root(fun, hi):
-    """Root of a function decreasing on [0, hi] (0 if fun(0) <= 0, hi if fun(hi) >= 0)."""
-    if hi <= 0.0 or fun(0.0) <= 0.0:
+def yield_tolerance(m, Ttr):
+    """Tolerance of every surface test: 1e-12 of the trial traction scale.
+    States that the algorithm puts exactly on a surface (a return that ends
+    at zero strength, an element left on its surface with no increment)
+    would otherwise be decided by the sign of a rounding error."""
+    return 1e-12 * (abs(Ttr[0]) + abs(Ttr[1]) + abs(Ttr[2]) + m[CP] + m[SP])
+
+
+def _root(fun, hi, tol):
+    """Root of a function decreasing on [0, hi] (0 if fun(0) <= tol, hi if fun(hi) >= -tol)."""
+    if hi <= 0.0 or fun(0.0) <= tol:
         return 0.0
-    if fun(hi) >= 0.0:
+    if fun(hi) >= -tol:
         return hi
     return brentq(fun, 0.0, hi, xtol=1e-300, rtol=8.9e-16, maxiter=400)
 
 
-def _corner(m, Ttr, dps, chi0):
+def _corner(m, Ttr, dps, chi0, tol):
     """Nested scalar solves of the corner: returns (lam, nu)."""
     q = math.hypot(Ttr[0], Ttr[1])
     nu_hi = max(Ttr[2], 0.0) / m[KN]
@@ -189,14 +199,14 @@ def _corner(m, Ttr, dps, chi0):
         def r1(nu):
             T, _, chi, _ = _end_state(m, Ttr, dps, chi0, lam, nu, False)
             return _ft(m, T[2], chi)
-        return _root(r1, nu_hi)
+        return _root(r1, nu_hi, tol)
 
     def r2(lam):
         nu = nu_of(lam)
         T, _, chi, tau = _end_state(m, Ttr, dps, chi0, lam, nu, False)
         return _fc(m, tau, T[2], chi)
 
-    lam = _root(r2, q / m[KS])
+    lam = _root(r2, q / m[KS], tol)
     return lam, nu_of(lam)
 
 
@@ -219,7 +229,8 @@ def update_element(m, dd, T0, dp0, chi0):
                     cep=np.zeros((3, 3)), mode=OPEN)
     q = math.hypot(Ttr[0], Ttr[1])
     lam, nu = 0.0, 0.0
-    if _fc(m, q, Ttr[2], chi0) <= 0.0 and _ft(m, Ttr[2], chi0) <= 0.0:
+    ytol = yield_tolerance(m, Ttr)
+    if _fc(m, q, Ttr[2], chi0) <= ytol and _ft(m, Ttr[2], chi0) <= ytol:
         mode = ELASTIC
     else:
         f0, c0, st0 = friction(m, chi0[0]), cohesion(m, chi0[1]), tensile_strength(m, chi0[1])
@@ -231,23 +242,23 @@ def update_element(m, dd, T0, dp0, chi0):
                 T, _, chi, tau = _end_state(m, Ttr, dps, chi0, x, 0.0, True)
                 return _fc(m, tau, T[2], chi)
             lam_hi = q / m[KS]
-            if rs(lam_hi) > 0.0:
+            if rs(lam_hi) > ytol:
                 mode = CORNER
             else:
-                lam = _root(rs, lam_hi)
+                lam = _root(rs, lam_hi, ytol)
                 T, _, chi, _ = _end_state(m, Ttr, dps, chi0, lam, 0.0, True)
-                if _ft(m, T[2], chi) > 0.0:
+                if _ft(m, T[2], chi) > ytol:
                     mode, lam = CORNER, 0.0
         if mode == TENSILE:
             def rt(x):
                 T, _, chi, _ = _end_state(m, Ttr, dps, chi0, 0.0, x, False)
                 return _ft(m, T[2], chi)
-            nu = _root(rt, Ttr[2] / m[KN])
+            nu = _root(rt, Ttr[2] / m[KN], ytol)
             T, _, chi, tau = _end_state(m, Ttr, dps, chi0, 0.0, nu, False)
-            if _fc(m, tau, T[2], chi) > 0.0:
+            if _fc(m, tau, T[2], chi) > ytol:
                 mode, nu = CORNER, 0.0
         if mode == CORNER:
-            lam, nu = _corner(m, Ttr, dps, chi0)
+            lam, nu = _corner(m, Ttr, dps, chi0, ytol)
     unknowns = active_unknowns(m, Ttr, dps, chi0, mode, lam, nu)
     T, dp, chi, _ = _end_state(m, Ttr, dps, chi0, lam, nu, mode == SHEAR)
     cep = tangent(m, dd, T0, dp0, chi0, mode, lam, nu, unknowns)

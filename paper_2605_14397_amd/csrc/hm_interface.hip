@@ -196,21 +196,21 @@ __device__ __forceinline__ EndState<S> end_state(const hm_interface_material& m,
     return e;
 }
 
-// Root of a function decreasing on [0, hi]: 0 if f(0) <= 0, hi if f(hi) >= 0,
+// Root of a function decreasing on [0, hi]: 0 if f(0) <= tol, hi if f(hi) >= -tol,
 // else safeguarded Newton from the secant point: it stops once a Newton
 // correction falls below 1e-12 of the iterate (the next error is below
 // rounding), and a bisection step replaces any Newton step that leaves the
 // bracket or does not halve the previous step.  fn(x, fx) stores f(x) in fx
 // and returns f'(x).
 template <class F>
-__device__ __forceinline__ double root_dec(F fn, double hi)
+__device__ __forceinline__ double root_dec(F fn, double hi, double tol)
 {
     if (!(hi > 0.0)) return 0.0;
     double f0, fh;
     fn(0.0, f0);
-    if (f0 <= 0.0) return 0.0;
+    if (f0 <= tol) return 0.0;
     fn(hi, fh);
-    if (fh >= 0.0) return hi;
+    if (fh >= -tol) return hi;
     double a = 0.0, b = hi;
     double x = hi * (f0 / (f0 - fh));
     double step_old = hi;
@@ -278,6 +278,11 @@ __device__ __forceinline__ Element update_one(const hm_interface_material& m, co
     const double q = sqrt(Ttr[0] * Ttr[0] + Ttr[1] * Ttr[1]);
     int32_t mode;
     double lam = 0.0, nu = 0.0;
+    // tolerance of every surface test: 1e-12 of the trial traction scale, so
+    // that states the algorithm puts exactly on a surface (a return ending at
+    // zero strength, an element left on its surface without increment) are
+    // not decided by the sign of a rounding error
+    const double ytol = 1e-12 * (fabs(Ttr[0]) + fabs(Ttr[1]) + fabs(Ttr[2]) + m.c_peak + m.sigma_peak);
 
     // scalar consistency functions of the single-surface returns and the corner
     auto f_shear = [&](double x, double& fx) -> double {
@@ -307,7 +312,7 @@ __device__ __forceinline__ Element update_one(const hm_interface_material& m, co
                 fx = r.v;
                 return r.d[0];
             },
-            nu_hi);
+            nu_hi, ytol);
     };
     auto f_corner = [&](double x, double& fx) -> double {
         const double n = nu_of(x);
@@ -323,7 +328,7 @@ __device__ __forceinline__ Element update_one(const hm_interface_material& m, co
 
     const double* c0 = chi0;
     const double fc_tr = coulomb(m, q, Ttr[2], c0), ft_tr = cutoff(m, Ttr[2], c0);
-    if (fc_tr <= 0.0 && ft_tr <= 0.0) {
+    if (fc_tr <= ytol && ft_tr <= ytol) {
         mode = kElastic;
     } else {
         const double f0 = friction(m, chi0[0]);
@@ -336,27 +341,27 @@ __device__ __forceinline__ Element update_one(const hm_interface_material& m, co
             const double lam_hi = q / m.k_s;
             double fh;
             f_shear(lam_hi, fh);
-            if (fh > 0.0) {
+            if (fh > ytol) {
                 mode = kCorner;
             } else {
-                lam = root_dec(f_shear, lam_hi);
+                lam = root_dec(f_shear, lam_hi, ytol);
                 const EndState<double> e = end_state(m, Ttr, dps, chi0, lam, 0.0, true);
-                if (cutoff(m, e.T[2], e.chi) > 0.0) {
+                if (cutoff(m, e.T[2], e.chi) > ytol) {
                     mode = kCorner;
                     lam = 0.0;
                 }
             }
         }
         if (mode == kTensile) {
-            nu = root_dec(f_tens, Ttr[2] / m.k_n);
+            nu = root_dec(f_tens, Ttr[2] / m.k_n, ytol);
             const EndState<double> e = end_state(m, Ttr, dps, chi0, 0.0, nu, false);
-            if (coulomb(m, e.tau, e.T[2], e.chi) > 0.0) {
+            if (coulomb(m, e.tau, e.T[2], e.chi) > ytol) {
                 mode = kCorner;
                 nu = 0.0;
             }
         }
         if (mode == kCorner) {
-            lam = root_dec(f_corner, q / m.k_s);
+            lam = root_dec(f_corner, q / m.k_s, ytol);
             nu = nu_of(lam);
         }
     }

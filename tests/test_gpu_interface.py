@@ -146,3 +146,42 @@ def test_tangent_from_the_law_drives_the_solve():
     err = max(np.linalg.norm(x[c] - x_ref[c]) / np.linalg.norm(x_ref[c]) for c in range(2))
     print("modes", np.bincount(o[4], minlength=5).tolist(), "iterations", rep["iterations"], "err", err, flush=True)
     assert err <= 1e-8, err
+
+
+def test_injection_path_states_match_the_oracle_step_by_step():
+    """Twenty in-place GPU steps of the law along the seeded injection path
+    on a coarse HF x fault mesh (1,696 triangles): D = C^ep + eta/dt and the
+    modes after every step against the oracle run along the same path; the
+    last state's tangent solve converges."""
+    from workloads import hf_fault_mesh
+    from workloads.interface import injection_path
+
+    hm = _hm()
+    m = hf_fault_mesh(h=5.0)
+    p = injection_path(m, weakening_scale=10.0)
+    t, dp, chi = cuda(p["t"]), cuda(p["dp"]), cuda(p["chi"])
+    mid = cuda(p["mat_id"], torch.int32)
+    ot, odp, ochi = p["t"], p["dp"], p["chi"]
+    kmax = p["mats"][:, :2].max()
+    seen = set()
+    for k in range(20):
+        before = (t.cpu().numpy(), dp.cpu().numpy(), chi.cpu().numpy(), ot, odp, ochi)
+        r = hm.interface_update(p["mats"], cuda(p["dd"][k]), t, dp, chi, mat_id=mid, eta_dt=cuda(p["eta_dt"][k]),
+                                want_D=True, out=dict(t=t, dp=dp, chi=chi))
+        ot, odp, ochi, ocep, omode = ifo.update(p["mats"], p["mat_id"], p["dd"][k], ot, odp, ochi)
+        D_or = ocep.copy()
+        D_or[:, [0, 1, 2], [0, 1, 2]] += p["eta_dt"][k]
+        gmode = r["mode"].cpu().numpy()
+        bad = np.nonzero(gmode != omode)[0]
+        assert len(bad) == 0, (k, [(int(e), int(gmode[e]), int(omode[e]), p["dd"][k][e].tolist(),
+                                    [b[e].tolist() for b in before]) for e in bad[:3]])
+        np.testing.assert_allclose(r["D"].cpu().numpy(), D_or, rtol=0, atol=1e-9 * kmax)
+        np.testing.assert_allclose(t.cpu().numpy(), ot, rtol=0, atol=1e-9 * np.abs(ot).max())
+        seen.update(omode.tolist())
+    assert {0, 1, 2, 4} <= seen, seen
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, aca_tol=1e-8)
+    op.set_tangent(r["D"])
+    b = cuda(rhs_columns(m.ndof, 2, 9109) * 1e6)
+    x, rep = op.solve(b, rtol=1e-8, restart=50, max_iter=3000)
+    print("last state: modes", np.bincount(omode, minlength=5).tolist(), "iterations", rep["iterations"], flush=True)
+    assert rep["converged"]

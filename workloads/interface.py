@@ -80,3 +80,60 @@ def interface_states(n: int, seed: int, mats: np.ndarray, mat_id: np.ndarray | N
     t[k3] = tk
     dd = rng.normal(0.0, 3e-4, (n, 3)) * rng.choice([0.01, 0.1, 1.0], n)[:, None]
     return dict(mat_id=np.ascontiguousarray(mat_id, dtype=np.int32), dd=dd, t=t, dp=dp, chi=chi)
+
+
+def injection_path(mesh, n_states: int = 20, young: float = 30e9, nu: float = 0.25, rho: float = 2700.0,
+                   injection=(20.0, 0.0, 0.0), rmax: float = 60.0, step_dd: float = 0.5e-3,
+                   weakening_scale: float = 1.0, seed: int = 5001) -> dict:
+    """Seeded loading path of an injection on a two-part mesh (first part the
+    hydraulic fracture, the rest the fault), to drive the interface law.
+
+    Materials (interface_materials with h = sqrt of the mean element area,
+    weakening lengths d_c and w_c times weakening_scale, which keeps the
+    local problems well posed on coarse test meshes whose stiffness E'/h is
+    small): fracture elements intact joints (0), fault elements a
+    pre-existing fault without strength (1).
+    Initial effective tractions: fracture (0, 0, -5 MPa), fault (4, 0, -10)
+    MPa; inelastic DD and chi_s, chi_t zero; residual width 0.3 w_c.  Step k
+    reaches the elements within rmax sqrt((k + 1) / n_states) of the
+    injection point; there the fracture opens by step_dd and the fault slips
+    by step_dd along s1 (both times U(0.5, 1.5)) and closes by up to a tenth
+    of it; elsewhere the increment is zero.  eta/dt_k: eta = (1/2) diag(G/cs,
+    G/cs, G/cp) with the seeded time step of the synthetic tangent states
+    (10^U(-1, 2) s from default_rng(seed + k))."""
+    v = mesh.xyz[mesh.conn]
+    if mesh.nvpe == 3:
+        area = 0.5 * np.linalg.norm(np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), axis=1)
+    else:
+        area = np.linalg.norm(v[:, 1] - v[:, 0], axis=1) * np.linalg.norm(v[:, 3] - v[:, 0], axis=1)
+    mats = interface_materials(young, nu, float(np.sqrt(area.mean())))
+    mats[:, [5, 8]] *= weakening_scale
+    ne = mesh.ne
+    parts = mesh.meta.get("parts", [(0, ne)])
+    first = np.zeros(ne, dtype=bool)
+    first[parts[0][0]:parts[0][0] + parts[0][1]] = True
+    mat_id = np.where(first, 0, 1).astype(np.int32)
+    t0 = np.zeros((ne, 3))
+    t0[first, 2] = -5e6
+    t0[~first, 0] = 4e6
+    t0[~first, 2] = -10e6
+    chi0 = np.zeros((ne, 3))
+    chi0[:, 2] = 0.3 * mats[mat_id, 8]
+    G = young / (2.0 * (1.0 + nu))
+    K = young / (3.0 * (1.0 - 2.0 * nu))
+    cs, cp = np.sqrt(G / rho), np.sqrt((K + 4.0 * G / 3.0) / rho)
+    eta = 0.5 * np.array([G / cs, G / cs, G / cp])
+    dist = np.linalg.norm(mesh.vertex_means() - np.asarray(injection), axis=1)
+    rng = np.random.default_rng(seed + 1000)
+    dd, eta_dt = [], []
+    for k in range(n_states):
+        dt = 10.0 ** np.random.default_rng(seed + k).uniform(-1.0, 2.0)
+        inside = dist <= rmax * np.sqrt((k + 1.0) / n_states)
+        d = np.zeros((ne, 3))
+        amp = step_dd * rng.uniform(0.5, 1.5, ne)
+        d[inside & first, 2] = amp[inside & first]
+        d[inside & ~first, 0] = amp[inside & ~first]
+        d[inside & ~first, 2] = -0.1 * step_dd * rng.uniform(0.0, 1.0, int((inside & ~first).sum()))
+        dd.append(d)
+        eta_dt.append(np.tile(eta / dt, (ne, 1)))
+    return dict(mats=mats, mat_id=mat_id, t=t0, dp=np.zeros((ne, 3)), chi=chi0, dd=dd, eta_dt=eta_dt)

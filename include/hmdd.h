@@ -424,6 +424,62 @@ hm_status hm_interface_update(int n_mat, const hm_interface_material* mats, int6
                               const double* d_eta_dt, double* d_D, void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* One implicit step of the mechanical problem                          */
+/* ------------------------------------------------------------------ */
+/*
+ * Newton's method on the mechanical residual of a time step (paper Sec.
+ * 3.1.1, "Elasto-plastic solver"), the increment dd of the total DD being
+ * the unknown:
+ *   r(dd) = dT'o - dT'(dd) + E dd + I_n dp - eta (dd - dd_prev) / dt,
+ * dT'(dd) the increment of the interface effective traction given by
+ * hm_interface_update from the start-of-step state, I_n dp the pore-pressure
+ * increment at the collocation points along each element normal; the
+ * Jacobian is J = E - eta/dt - C^ep.  Each iteration evaluates the law, the
+ * FP64 product E dd (the operator's FP64 reference copy when its main form
+ * is lower precision), the residual and its 2-norm, sets the operator's
+ * tangent to D = C^ep + eta/dt and solves J y = r with hm_solve (opts.lin:
+ * preconditioner, restart, tolerance, refinement); then dd -= y.
+ */
+typedef struct {
+    int max_newton;        /* Newton iterations, 0..63; default 25 */
+    double rtol;           /* stop when ||r|| <= max(rtol ||r_0||, atol); default 1e-10 */
+    double atol;           /* absolute residual tolerance (Pa); default 0 */
+    hm_solve_opts lin;     /* linear solves; default hm_solve_opts_default with rtol 1e-10, max_iter 3000 */
+} hm_newton_opts;
+
+typedef struct {
+    int iterations;            /* Newton iterations (linear solves) taken */
+    int converged;             /* 1 when the residual tolerance was met */
+    int n_history;             /* residual evaluations (iterations + 1) */
+    double residual[64];       /* ||r_k|| (Pa, 2-norm over all DOF) */
+    int gmres_iterations[64];  /* GMRES iterations of each linear solve */
+    int64_t modes[5];          /* elements per interface mode (HM_IF_*) at the returned state */
+    double ms;                 /* wall time of the step */
+} hm_newton_report;
+
+void hm_newton_opts_default(hm_newton_opts* opts);
+/*
+ * One step.  Interface materials and state as for hm_interface_update
+ * (d_t, d_dp, d_chi: [N][3] at the start of the step, not modified);
+ *   d_dT0     [N][3] increment of the in-situ effective traction, or NULL
+ *   d_dpress  [N] pore-pressure increment at the collocation points, or NULL
+ *   d_eta_dt  [N][3] diagonal of eta/dt, or NULL
+ *   d_dd_prev [N][3] previous step's DD increment, or NULL (zero)
+ *   d_dd      [N][3] in: initial guess; out: the returned increment
+ *   d_t_new, d_dp_new, d_chi_new  [N][3] the interface state at d_dd
+ * All device FP64 arrays, element-major in local frames; the operator is
+ * the mesh's (N elements).  On return the operator's tangent is D at the
+ * returned state.  HM_ENOTCONV (report filled, last iterate returned) when
+ * the tolerance is not met within max_newton iterations.  Synchronises
+ * the stream; the operator is used by one caller at a time.
+ */
+hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,
+                         const double* d_t, const double* d_dp, const double* d_chi, const double* d_dT0,
+                         const double* d_dpress, const double* d_eta_dt, const double* d_dd_prev, double* d_dd,
+                         double* d_t_new, double* d_dp_new, double* d_chi_new, const hm_newton_opts* opts,
+                         hm_newton_report* rep, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Learned correction of the block preconditioner                       */
 /* ------------------------------------------------------------------ */
 /*

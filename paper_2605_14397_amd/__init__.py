@@ -40,6 +40,7 @@ EXPORTS = [
     "hm_learned_get_params",
     "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
     "hm_learned_attach", "hm_learned_detach", "hm_precond_apply", "hm_interface_update",
+    "hm_newton_opts_default", "hm_newton_step",
 ]
 
 
@@ -74,6 +75,23 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("refine", ctypes.c_int), ("inner_rtol", ctypes.c_double),
                 ("max_refine", ctypes.c_int)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("lin", SolveOpts)]
+
+
+class NewtonReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("n_history", ctypes.c_int),
+                ("residual", ctypes.c_double * 64), ("gmres_iterations", ctypes.c_int * 64),
+                ("modes", ctypes.c_int64 * 5), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "converged": bool(self.converged),
+                "residual": list(self.residual[:self.n_history]),
+                "gmres_iterations": list(self.gmres_iterations[:self.iterations]), "modes": list(self.modes),
+                "ms": self.ms}
 
 
 class SolveReport(ctypes.Structure):
@@ -156,6 +174,9 @@ def lib():
             "hm_learned_detach": ([P], None),
             "hm_precond_apply": ([P, I, I, P, I64, P, I64, P], I),
             "hm_interface_update": ([I, P, I64, P, P, P, P, P, P, P, P, P, P, P, P, P], I),
+            "hm_newton_opts_default": ([ctypes.POINTER(NewtonOpts)], None),
+            "hm_newton_step": ([P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(NewtonOpts),
+                                ctypes.POINTER(NewtonReport), P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -330,6 +351,44 @@ class Operator:
         if st != HM_OK and (st != HM_ENOTCONV or raise_on_notconv):
             _check(st)
         return (X.reshape(-1) if squeeze else X), rep.as_dict()
+
+    def newton_step(self, mats, t, dp, chi, dT0=None, dpress=None, eta_dt=None, dd_prev=None, dd=None,
+                    mat_id=None, raise_on_notconv=True, stream=None, **opts):
+        """One implicit step of the mechanical problem (hm_newton_step).
+
+        mats: [n_mat, 9] host material table; t, dp, chi: CUDA float64 [N, 3]
+        start-of-step interface state; dT0, eta_dt, dd_prev [N, 3], dpress [N]
+        optional CUDA float64; dd: initial guess (zero if None).  opts: fields
+        of hm_newton_opts (max_newton, rtol, atol) and of its linear-solve
+        options prefixed lin_ (lin_precond, lin_rtol, ...).  Returns
+        (dd, t_new, dp_new, chi_new, report dict)."""
+        import torch
+
+        o = NewtonOpts()
+        lib().hm_newton_opts_default(ctypes.byref(o))
+        for k, v in opts.items():
+            if k.startswith("lin_"):
+                setattr(o.lin, k[4:], v)
+            else:
+                setattr(o, k, v)
+        mats = np.ascontiguousarray(np.atleast_2d(mats), dtype=np.float64)
+        arr = (InterfaceMaterial * mats.shape[0])()
+        for i in range(mats.shape[0]):
+            for j, (name, _) in enumerate(InterfaceMaterial._fields_):
+                setattr(arr[i], name, float(mats[i, j]))
+        f64 = torch.float64
+        N = t.shape[0]
+        dd = torch.zeros(N, 3, dtype=f64, device=t.device) if dd is None else dd.clone()
+        outs = [torch.empty(N, 3, dtype=f64, device=t.device) for _ in range(3)]
+        opt = lambda x, dt=f64: _dev_ptr(x.contiguous(), dt) if x is not None else None
+        rep = NewtonReport()
+        st = lib().hm_newton_step(self._h, mats.shape[0], ctypes.cast(arr, ctypes.c_void_p),
+                                  opt(mat_id, torch.int32), opt(t), opt(dp), opt(chi), opt(dT0), opt(dpress),
+                                  opt(eta_dt), opt(dd_prev), _dev_ptr(dd, f64), *[_dev_ptr(x, f64) for x in outs],
+                                  ctypes.byref(o), ctypes.byref(rep), _stream(stream))
+        if st != HM_ENOTCONV or raise_on_notconv:
+            _check(st)
+        return dd, outs[0], outs[1], outs[2], rep.as_dict()
 
     def precond_apply(self, R, precond=HM_PC_BLOCK3, stream=None):
         """Z = M^-1 R (R: CUDA float64 [nrhs, 3N]) with the solve's preconditioner."""

@@ -334,6 +334,37 @@ hm_status hm_interface_update(int n_mat, const hm_interface_material* mats, int6
     });
 }
 
+void hm_newton_opts_default(hm_newton_opts* o)
+{
+    if (!o) return;
+    o->max_newton = 25;
+    o->rtol = 1e-10;
+    o->atol = 0.0;
+    hm_solve_opts_default(&o->lin);
+    o->lin.rtol = 1e-10;
+    o->lin.max_iter = 3000;
+}
+
+hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,
+                         const double* d_t, const double* d_dp, const double* d_chi, const double* d_dT0,
+                         const double* d_dpress, const double* d_eta_dt, const double* d_dd_prev, double* d_dd,
+                         double* d_t_new, double* d_dp_new, double* d_chi_new, const hm_newton_opts* opts,
+                         hm_newton_report* rep, void* hip_stream)
+{
+    hm_status st = HM_OK;
+    const hm_status g = guarded([&] {
+        HM_REQUIRE(op, HM_EINVAL, "op is null");
+        require_gfx950();
+        hm_newton_opts o;
+        hm_newton_opts_default(&o);
+        if (opts) o = *opts;
+        st = hm::newton_step(op->op, n_mat, mats, d_mat_id, d_t, d_dp, d_chi, d_dT0, d_dpress, d_eta_dt, d_dd_prev,
+                             d_dd, d_t_new, d_dp_new, d_chi_new, o, rep, (hipStream_t)hip_stream);
+        if (st == HM_ENOTCONV) hm::set_last_error("Newton did not reach the residual tolerance (last iterate returned)");
+    });
+    return g != HM_OK ? g : st;
+}
+
 hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out)
 {
     return guarded([&] {

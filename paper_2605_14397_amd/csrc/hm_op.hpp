@@ -159,6 +159,12 @@ void interface_update(int n_mat, const hm_interface_material* mats, int64_t n, c
                       double* d_dp_new, double* d_chi_new, double* d_cep, int32_t* d_mode, const double* d_eta_dt,
                       double* d_D, hipStream_t s);
 
+hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,
+                      const double* d_t, const double* d_dp, const double* d_chi, const double* d_dT0,
+                      const double* d_dpress, const double* d_eta_dt, const double* d_dd_prev, double* d_dd,
+                      double* d_t_new, double* d_dp_new, double* d_chi_new, const hm_newton_opts& o,
+                      hm_newton_report* rep, hipStream_t s);
+
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
                 int64_t ldx, hm_solve_report* rep, hipStream_t s);

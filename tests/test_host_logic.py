@@ -184,7 +184,8 @@ def test_structs_match_c_layout(tmp_path):
     pairs = [("hm_solve_report", hm.SolveReport), ("hm_solve_opts", hm.SolveOpts),
              ("hm_build_opts", hm.BuildOpts), ("hm_op_stats", hm.OpStats), ("hm_batch_opts", hm.BatchOpts),
              ("hm_batch_info", hm.BatchInfo), ("hm_plan_info", hm.PlanInfo),
-             ("hm_interface_material", hm.InterfaceMaterial)]
+             ("hm_interface_material", hm.InterfaceMaterial), ("hm_newton_opts", hm.NewtonOpts),
+             ("hm_newton_report", hm.NewtonReport)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hmdd.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')

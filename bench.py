@@ -224,11 +224,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "copy"],
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "newton", "copy"],
                     default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
                          "learned: trained preconditioner correction on the HF x fault tangent solves; "
                          "interface: interface-law update and consistent tangent of 199,880 elements; "
+                         "newton: one implicit mechanical step (Newton) of the HF x fault under a pressure rise; "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
@@ -271,6 +272,9 @@ def main():
         return
     if args.form == "interface":
         bench_interface(args)
+        return
+    if args.form == "newton":
+        bench_newton(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -788,6 +792,73 @@ def bench_interface(args):
         line["cpu_baseline"] = {"value": round(done / el, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
                                 "sample": f"first {done} of the {n} mixed-regime elements in {el:.1f} s"}
     print(json.dumps(line), flush=True)
+
+
+def bench_newton(args):
+    """One implicit step of the mechanical problem on the HF x fault mesh
+    (199,880 triangles): the hydraulic fracture an intact joint, the fault a
+    pre-existing one (friction 0.6), initial effective tractions as on the
+    injection path, and a Gaussian pore-pressure rise (peak 8 MPa, sigma
+    10 m) around the injection point; eta/dt of a 1 s step.  Newton to a
+    residual of 1e-8 of the initial one, each linear solve to 1e-6 of the
+    current residual (a constant forcing term), with FP64 GMRES (3x3 and
+    leaf block-Jacobi) and with the precision form (FP32 near / BF16 far
+    inner solves refined in FP64); the residual always uses the FP64
+    operator."""
+    import numpy as np
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads import hf_fault_mesh
+    from workloads.interface import injection_path
+
+    m = hf_fault_mesh(h=args.hf_h)
+    p = injection_path(m, 1)
+    cu = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    x = m.vertex_means()
+    r2 = ((x - np.array([20.0, 0.0, 0.0])) ** 2).sum(axis=1)
+    dpress = 8e6 * np.exp(-r2 / (2 * 10.0 ** 2))
+    G = YOUNG / (2 * (1 + NU))
+    rho = 2700.0
+    cs, cp = np.sqrt(G / rho), np.sqrt((YOUNG / (3 * (1 - 2 * NU)) + 4 * G / 3) / rho)
+    eta_dt = np.tile(0.5 * np.array([G / cs, G / cs, G / cp]) / 1.0, (m.ne, 1))
+    t, dp, chi, mid = cu(p["t"]), cu(p["dp"]), cu(p["chi"]), cu(p["mat_id"], torch.int32)
+    res = {}
+    for name, kw, lin in (
+            ("fp64_block_jacobi", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict(lin_precond=hm.HM_PC_BLOCK3)),
+            ("fp64_leaf_block", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict(lin_precond=hm.HM_PC_LEAF)),
+            ("precision_leaf_block", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
+             dict(lin_precond=hm.HM_PC_LEAF, lin_refine=1))):
+        op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dd, t_new, _, _, rep = op.newton_step(p["mats"], t, dp, chi, dpress=cu(dpress), eta_dt=cu(eta_dt),
+                                              mat_id=mid, rtol=1e-8, lin_rtol=1e-6, lin_restart=50,
+                                              raise_on_notconv=False, **lin)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"time_s": round(wall, 3), "newton_iterations": rep["iterations"],
+                     "gmres_iterations": rep["gmres_iterations"], "converged": rep["converged"],
+                     "residual_history": [float(f"{h:.4e}") for h in rep["residual"]],
+                     "modes_elastic_shear_tensile_corner_open": rep["modes"],
+                     "max_opening_mm": round(float(dd[:, 2].max()) * 1e3, 4),
+                     "max_slip_mm": round(float(dd[:, :2].norm(dim=1).max()) * 1e3, 4), "dd": dd.cpu().numpy()}
+        log(f"newton {name}: {wall:.3f} s, {rep['iterations']} Newton iterations, GMRES {rep['gmres_iterations']}, "
+            f"residuals {[f'{h:.2e}' for h in rep['residual']]}, modes {rep['modes']}")
+        del op
+    ref = res["fp64_block_jacobi"].pop("dd")
+    for k in list(res)[1:]:
+        d = res[k].pop("dd")
+        res[k]["diff_vs_fp64_block_jacobi"] = float(f"{np.linalg.norm(d - ref) / np.linalg.norm(ref):.3e}")
+    base = res["fp64_block_jacobi"]["time_s"]
+    out = {"metric": "time of one implicit mechanical step (Newton to 1e-8 of the initial residual)",
+           "value": res["precision_leaf_block"]["time_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
+           "config": {"workload": f"HF x fault, {m.ne} triangles, {m.ndof} DOF; intact-joint fracture, "
+                                  "pre-existing fault (friction 0.6); Gaussian pressure rise 8 MPa / 10 m; "
+                                  "leaf 64, eta 2, ACA 1e-6; GMRES(50) to 1e-6 per Newton iteration"},
+           "forms": res, "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in res.items()}}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(args):

@@ -235,9 +235,10 @@ def main():
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
-    ap.add_argument("--tangents", choices=["law", "closed-form"], default="law",
-                    help="learned form: tangent states from the interface law driven along a seeded injection "
-                         "path (law), or the closed-form synthetic states")
+    ap.add_argument("--tangents", choices=["newton", "law", "closed-form"], default="newton",
+                    help="learned form: tangent states at the converged Newton steps of a rising-pressure "
+                         "injection (newton), from the interface law driven along prescribed increments (law), "
+                         "or the closed-form synthetic states")
     ap.add_argument("--if-states", choices=["both", "mixed", "elastic"], default="both",
                     help="interface form: which seeded state sets to time (profiling runs use one)")
     ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
@@ -571,12 +572,69 @@ def law_tangent_states(hm, m, n_states=20):
     return Ds, modes
 
 
+def newton_tangent_states(hm, m, op, n_states=20, max_cuts=3):
+    """D_k = C^ep + eta/dt at the converged implicit step k of an injection
+    whose pore pressure rises over n_states steps (injection_pressure):
+    hm_newton_step (precision form with leaf block-Jacobi, FP64 residual to
+    1e-8), then the state advances; k = 0..n_states-1.  A step whose Newton
+    iteration does not converge is cut into two half steps (half the pressure
+    increment, half the time step; adaptive time stepping, Sec. 3.4), at most
+    max_cuts times in a row; the quasi-dynamic term's previous increment is
+    rescaled to the new time step."""
+    import numpy as np
+    import torch
+
+    from workloads.interface import injection_path, injection_pressure
+
+    p = injection_path(m, n_states)
+    cu = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    st = {"t": cu(p["t"]), "dp": cu(p["dp"]), "chi": cu(p["chi"]), "dd": None, "eta_dt": None}
+    mid = cu(p["mat_id"], torch.int32)
+
+    def advance(dpress, eta_dt, depth, acc):
+        ratio = 1.0 if st["eta_dt"] is None else float(st["eta_dt"][0, 0] / eta_dt[0, 0])
+        dd_prev = torch.zeros_like(st["t"]) if st["dd"] is None else st["dd"] * ratio
+        dd, t_new, dp_new, chi_new, rep = op.newton_step(p["mats"], st["t"], st["dp"], st["chi"], dpress=dpress,
+                                                         eta_dt=eta_dt, dd_prev=dd_prev, mat_id=mid, rtol=1e-8,
+                                                         lin_rtol=1e-6, lin_precond=hm.HM_PC_LEAF, lin_refine=1,
+                                                         raise_on_notconv=False)
+        acc["newton"] += rep["iterations"]
+        acc["gmres"] += sum(rep["gmres_iterations"])
+        if not rep["converged"]:
+            if depth >= max_cuts:
+                raise RuntimeError(f"Newton step not converged after {max_cuts} cuts: {rep['residual']}")
+            acc["cuts"] += 1
+            for _ in range(2):
+                rep = advance(0.5 * dpress, 2.0 * eta_dt, depth + 1, acc)
+            return rep
+        st["last"] = (st["t"], st["dp"], st["chi"], dd, eta_dt)   # start state and increment of this step
+        st.update(t=t_new, dp=dp_new, chi=chi_new, dd=dd, eta_dt=eta_dt)
+        return rep
+
+    Ds, modes, steps = [], [], []
+    for k in range(n_states):
+        dpress = cu(injection_pressure(m, k, n_states) - injection_pressure(m, k - 1, n_states))
+        acc = {"newton": 0, "gmres": 0, "cuts": 0}
+        t0 = time.perf_counter()
+        rep = advance(dpress, cu(p["eta_dt"][k]), 0, acc)
+        # tangent at the converged end of the (last sub)step, evaluated from that step's start state
+        t_s, dp_s, chi_s, dd_s, eta_s = st["last"]
+        r = hm.interface_update(p["mats"], dd_s, t_s, dp_s, chi_s, mat_id=mid, eta_dt=eta_s, want_D=True)
+        Ds.append(r["D"])
+        modes.append(rep["modes"])
+        steps.append({"s": round(time.perf_counter() - t0, 3), "newton": acc["newton"], "gmres": acc["gmres"],
+                      "cuts": acc["cuts"]})
+        log(f"injection step {k}: {steps[-1]}, modes {rep['modes']}")
+    return Ds, modes, steps
+
+
 def bench_learned(args):
     """Learned correction of the block preconditioner on the tangent solves
     of an injection sequence on the HF x fault mesh (20 tangent states,
-    paper Sec. 3.1.1 / 3.3.1): by default D = C^ep + eta/dt from the
-    interface law (hm_interface_update) driven along a seeded injection
-    path, else (--tangents closed-form) the closed-form synthetic states.
+    paper Sec. 3.1.1 / 3.3.1): by default D = C^ep + eta/dt at the
+    converged implicit steps (hm_newton_step) of a rising-pressure
+    injection; --tangents law: the interface law along prescribed
+    increments; --tangents closed-form: the closed-form synthetic states.
 
     Training data: for states 0..15, 128 FP64 GMRES solves each (2,048 in
     all) of A11 x = b with b = A11 x0 for seeded white x0 (the method's own
@@ -608,7 +666,11 @@ def bench_learned(args):
         log(f"built {name} in {time.perf_counter() - t0:.1f} s")
     op = ops["fp64"]
     law_modes = None
-    if args.tangents == "law":
+    newton_log = None
+    if args.tangents == "newton":
+        Ds, law_modes, newton_log = newton_tangent_states(hm, m, ops["precision_bf16"])
+        tangent = lambda k: Ds[k]
+    elif args.tangents == "law":
         Ds, law_modes = law_tangent_states(hm, m)
         tangent = lambda k: Ds[k]
     else:
@@ -696,12 +758,14 @@ def bench_learned(args):
            "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
            "config": {"workload": f"HF x fault, {m.ne} triangles, {n} DOF; leaf 64, eta 2, ACA 1e-6; "
                                   "tangent states 16-19 of 20, 16 right-hand sides each; GMRES(50)",
-                      "tangents": ("interface law along a seeded injection path (D = C^ep + eta/dt from "
-                                   "hm_interface_update)" if args.tangents == "law"
-                                   else "closed-form synthetic states"),
+                      "tangents": {"newton": "converged implicit steps (hm_newton_step) of a rising-pressure "
+                                             "injection, D = C^ep + eta/dt at each",
+                                   "law": "interface law along prescribed increments (hm_interface_update)",
+                                   "closed-form": "closed-form synthetic states"}[args.tangents],
                       "network": f"32-64-64-9 MLP, {args.neighbors} neighbours", "training_states": 16,
                       "training_samples": 16 * per_state, "adam_steps": steps},
            "forms": forms, "law_modes_elastic_shear_tensile_corner_open": law_modes,
+           "injection_steps": newton_log,
            "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},
            "training": {"train_leaf_base_s": round(train_leaf_s, 2),
                         "loss_last_epoch_leaf_base": round(float(np.mean(hist_leaf[-128:])), 5),

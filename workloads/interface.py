@@ -137,3 +137,17 @@ def injection_path(mesh, n_states: int = 20, young: float = 30e9, nu: float = 0.
         dd.append(d)
         eta_dt.append(np.tile(eta / dt, (ne, 1)))
     return dict(mats=mats, mat_id=mat_id, t=t0, dp=np.zeros((ne, 3)), chi=chi0, dd=dd, eta_dt=eta_dt)
+
+
+def injection_pressure(mesh, k: int, n_states: int = 20, peak: float = 8e6, sigma0: float = 6.0,
+                       sigma1: float = 20.0, injection=(20.0, 0.0, 0.0)) -> np.ndarray:
+    """Pore pressure above its initial value at the element vertex means
+    after step k of a growing injection: amplitude peak (k + 1) / n_states,
+    Gaussian of width sigma0 + (sigma1 - sigma0) (k + 1) / n_states (m)
+    around the injection point; k = -1 gives zero."""
+    if k < 0:
+        return np.zeros(mesh.ne)
+    f = (k + 1.0) / n_states
+    r2 = ((mesh.vertex_means() - np.asarray(injection)) ** 2).sum(axis=1)
+    s = sigma0 + (sigma1 - sigma0) * f
+    return peak * f * np.exp(-r2 / (2.0 * s * s))

@@ -865,10 +865,10 @@ def bench_newton(args):
     injection path, and a Gaussian pore-pressure rise (peak 8 MPa, sigma
     10 m) around the injection point; eta/dt of a 1 s step.  Newton to a
     residual of 1e-8 of the initial one, each linear solve to 1e-6 of the
-    current residual (a constant forcing term), with FP64 GMRES (3x3 and
-    leaf block-Jacobi) and with the precision form (FP32 near / BF16 far
-    inner solves refined in FP64); the residual always uses the FP64
-    operator."""
+    current residual (a constant forcing term) or with Eisenstat-Walker
+    forcing (_ew), with FP64 GMRES (3x3 and leaf block-Jacobi) and with the
+    precision form (FP32 near / BF16 far inner solves refined in FP64); the
+    residual always uses the FP64 operator."""
     import numpy as np
     import torch
 
@@ -892,7 +892,9 @@ def bench_newton(args):
             ("fp64_block_jacobi", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict(lin_precond=hm.HM_PC_BLOCK3)),
             ("fp64_leaf_block", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict(lin_precond=hm.HM_PC_LEAF)),
             ("precision_leaf_block", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
-             dict(lin_precond=hm.HM_PC_LEAF, lin_refine=1))):
+             dict(lin_precond=hm.HM_PC_LEAF, lin_refine=1)),
+            ("precision_leaf_block_ew", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
+             dict(lin_precond=hm.HM_PC_LEAF, lin_refine=1, forcing=1))):
         op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -916,7 +918,7 @@ def bench_newton(args):
         res[k]["diff_vs_fp64_block_jacobi"] = float(f"{np.linalg.norm(d - ref) / np.linalg.norm(ref):.3e}")
     base = res["fp64_block_jacobi"]["time_s"]
     out = {"metric": "time of one implicit mechanical step (Newton to 1e-8 of the initial residual)",
-           "value": res["precision_leaf_block"]["time_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "value": res["precision_leaf_block_ew"]["time_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
            "config": {"workload": f"HF x fault, {m.ne} triangles, {m.ndof} DOF; intact-joint fracture, "
                                   "pre-existing fault (friction 0.6); Gaussian pressure rise 8 MPa / 10 m; "

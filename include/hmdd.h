@@ -445,6 +445,9 @@ typedef struct {
     double rtol;           /* stop when ||r|| <= max(rtol ||r_0||, atol); default 1e-10 */
     double atol;           /* absolute residual tolerance (Pa); default 0 */
     hm_solve_opts lin;     /* linear solves; default hm_solve_opts_default with rtol 1e-10, max_iter 3000 */
+    int forcing;           /* 0 (default): every linear solve to lin.rtol; 1: Eisenstat-Walker forcing
+                              (choice 2: 0.9 (||r_k|| / ||r_k-1||)^2, safeguarded, at most 0.1, at least
+                              lin.rtol and half the final tolerance over ||r_k||) */
 } hm_newton_opts;
 
 typedef struct {

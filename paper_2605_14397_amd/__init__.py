@@ -79,7 +79,7 @@ class SolveOpts(ctypes.Structure):
 
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
-                ("lin", SolveOpts)]
+                ("lin", SolveOpts), ("forcing", ctypes.c_int)]
 
 
 class NewtonReport(ctypes.Structure):

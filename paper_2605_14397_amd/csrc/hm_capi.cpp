@@ -343,6 +343,7 @@ void hm_newton_opts_default(hm_newton_opts* o)
     hm_solve_opts_default(&o->lin);
     o->lin.rtol = 1e-10;
     o->lin.max_iter = 3000;
+    o->forcing = 0;
 }
 
 hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,

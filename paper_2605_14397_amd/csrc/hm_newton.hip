@@ -76,6 +76,7 @@ hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, cons
 {
     HM_REQUIRE(o.max_newton >= 0 && o.max_newton <= 63, HM_EINVAL, "max_newton must be in [0, 63]");
     HM_REQUIRE(o.rtol >= 0.0 && o.atol >= 0.0, HM_EINVAL, "tolerances must be >= 0");
+    HM_REQUIRE(o.forcing == 0 || o.forcing == 1, HM_EINVAL, "forcing must be 0 or 1");
     HM_REQUIRE(d_t && d_dp && d_chi && d_dd && d_t_new && d_dp_new && d_chi_new, HM_EINVAL,
                "state and increment arrays must not be null");
     HM_REQUIRE(d_t_new != d_t && d_dp_new != d_dp && d_chi_new != d_chi, HM_EINVAL,
@@ -99,6 +100,7 @@ hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, cons
 
     std::vector<double> hist;
     std::vector<int> its;
+    double eta_prev = 0.1;
     for (int k = 0;; ++k) {
         interface_update(n_mat, mats, ne, d_mat_id, d_dd, d_t, d_dp, d_chi, d_t_new, d_dp_new, d_chi_new, cep, mode,
                          d_eta_dt, D, s);
@@ -115,8 +117,24 @@ hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, cons
         const bool done = hist.back() <= std::max(o.rtol * hist.front(), o.atol);
         if (done || k == o.max_newton || !std::isfinite(hist.back())) break;
         tangent_set(op, D, nullptr, s);
+        hm_solve_opts lin = o.lin;
+        if (o.forcing == 1) {
+            // Eisenstat-Walker choice 2 (gamma 0.9, alpha 2) with the usual
+            // safeguards: no sudden tightening, no oversolving of the last step
+            double eta = 0.1;
+            if (k > 0) {
+                const double ratio = hist[k] / hist[k - 1];
+                eta = 0.9 * ratio * ratio;
+                const double keep = 0.9 * eta_prev * eta_prev;
+                if (keep > 0.1) eta = std::max(eta, keep);
+            }
+            eta = std::max(eta, 0.5 * std::max(o.rtol * hist.front(), o.atol) / hist[k]);
+            eta = std::max(std::min(eta, 0.1), o.lin.rtol);
+            lin.rtol = eta;
+            eta_prev = eta;
+        }
         hm_solve_report sr{};
-        const hm_status st = solve(op, o.lin, 1, r, n3, y, n3, &sr, s);
+        const hm_status st = solve(op, lin, 1, r, n3, y, n3, &sr, s);
         HM_REQUIRE(st == HM_OK || st == HM_ENOTCONV, st, "linear solve failed");
         its.push_back(sr.iterations);
         hipLaunchKernelGGL(k_sub, dim3(vblocks), dim3(256), 0, s, n3, y, d_dd);

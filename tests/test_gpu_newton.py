@@ -137,3 +137,18 @@ def test_newton_argument_errors():
     # no iteration allowed: the report holds the initial residual only
     _, _, _, _, rep = _gpu_newton(hm, op, mats, t_n, dpress, eta_dt, max_newton=0, raise_on_notconv=False)
     assert rep["iterations"] == 0 and len(rep["residual"]) == 1 and not rep["converged"]
+
+
+def test_eisenstat_walker_forcing_reaches_the_same_step_with_fewer_inner_iterations():
+    hm = _hm()
+    m, mats, t_n, dpress, eta_dt = _weakening_case()
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=16, aca_tol=1e-10)
+    res = {}
+    for forcing in (0, 1):
+        dd, _, _, _, rep = _gpu_newton(hm, op, mats, t_n, dpress, eta_dt, rtol=1e-10, lin_rtol=1e-10,
+                                       forcing=forcing)
+        assert rep["converged"] and rep["residual"][-1] <= 1e-10 * rep["residual"][0]
+        res[forcing] = (dd.cpu().numpy(), sum(rep["gmres_iterations"]))
+    err = np.linalg.norm(res[1][0] - res[0][0]) / np.linalg.norm(res[0][0])
+    print("gmres total constant", res[0][1], "forcing", res[1][1], "diff", err, flush=True)
+    assert err <= 1e-8 and res[1][1] < res[0][1]

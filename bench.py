@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
+    ap.add_argument("--train-extra-law", type=int, default=8,
+                    help="learned form with --tangents newton: also train on this many states of the "
+                         "prescribed-increment law path (steps 0-15, evenly spread), a second loading scenario")
     ap.add_argument("--tangents", choices=["newton", "law", "closed-form"], default="newton",
                     help="learned form: tangent states at the converged Newton steps of a rising-pressure "
                          "injection (newton), from the interface law driven along prescribed increments (law), "
@@ -636,9 +639,11 @@ def bench_learned(args):
     injection; --tangents law: the interface law along prescribed
     increments; --tangents closed-form: the closed-form synthetic states.
 
-    Training data: for states 0..15, 128 FP64 GMRES solves each (2,048 in
-    all) of A11 x = b with b = A11 x0 for seeded white x0 (the method's own
-    tangent solves; white solutions make the loss measure ||M^-1 A11 - I||).
+    Training data: for states 0..15 (with the Newton sequence also 8 states
+    of the prescribed-increment law path, a second loading scenario), 128
+    FP64 GMRES solves each of A11 x = b with b = A11 x0 for seeded white x0
+    (the method's own tangent solves; white solutions make the loss measure
+    ||M^-1 A11 - I||).
     Training: Adam, 16 samples per step, 8 steps per state per epoch (one
     pass over the state's samples).
     Held-out states 16..19, 16 right-hand sides each (white tractions and
@@ -675,13 +680,22 @@ def bench_learned(args):
         tangent = lambda k: Ds[k]
     else:
         tangent = lambda k: cuda(tangent_state(m, k))
+    # training states: 0-15 of the sequence, plus (Newton sequence) some states of the
+    # prescribed-increment path, a second loading scenario with open and yielded elements early on
+    train_D = [tangent(k) for k in range(16)]
+    if args.tangents == "newton" and args.train_extra_law > 0:
+        Ds_law, _ = law_tangent_states(hm, m)
+        for i in np.linspace(0, 15, args.train_extra_law).round().astype(int):
+            train_D.append(Ds_law[int(i)])
+        del Ds_law
+    n_train = len(train_D)
     # training pairs from the method's own FP64 solves
     t0 = time.perf_counter()
     data = []
     solve_its = []
     per_state = 8 * NRHS
-    for k in range(16):
-        op.set_tangent(tangent(k))
+    for k in range(n_train):
+        op.set_tangent(train_D[k])
         bs, xs = [], []
         for j in range(per_state // NRHS):
             x0 = cuda(rhs_columns(n, NRHS, 7000 + per_state * k + NRHS * j))
@@ -699,8 +713,8 @@ def bench_learned(args):
         net.set_base(base)
         hist = []
         for ep in range(args.train_epochs):
-            for k in range(16):
-                op.set_tangent(tangent(k))
+            for k in range(n_train):
+                op.set_tangent(train_D[k])
                 b, x = data[k]
                 hist.extend(net.train(op, b, x, steps=8, batch=16, lr=1e-3))
             log(f"epoch {ep} (base {base}): mean loss {np.mean(hist[-128:]):.4g}")
@@ -762,14 +776,14 @@ def bench_learned(args):
                                              "injection, D = C^ep + eta/dt at each",
                                    "law": "interface law along prescribed increments (hm_interface_update)",
                                    "closed-form": "closed-form synthetic states"}[args.tangents],
-                      "network": f"32-64-64-9 MLP, {args.neighbors} neighbours", "training_states": 16,
-                      "training_samples": 16 * per_state, "adam_steps": steps},
+                      "network": f"32-64-64-9 MLP, {args.neighbors} neighbours", "training_states": n_train,
+                      "training_samples": n_train * per_state, "adam_steps": steps},
            "forms": forms, "law_modes_elastic_shear_tensile_corner_open": law_modes,
            "injection_steps": newton_log,
            "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in forms.items()},
            "training": {"train_leaf_base_s": round(train_leaf_s, 2),
                         "loss_last_epoch_leaf_base": round(float(np.mean(hist_leaf[-128:])), 5),
-                        "data_s": round(data_s, 2), "data_solves": 16 * per_state, "data_solve_iterations": {"min": min(solve_its), "mean": round(float(np.mean(solve_its)), 1), "max": max(solve_its)}, "train_s": round(train_s, 2),
+                        "data_s": round(data_s, 2), "data_solves": n_train * per_state, "data_solve_iterations": {"min": min(solve_its), "mean": round(float(np.mean(solve_its)), 1), "max": max(solve_its)}, "train_s": round(train_s, 2),
                         "ms_per_step": round(1000 * train_s / max(1, steps), 2),
                         "loss_first_epoch": round(float(np.mean(hist[:128])), 5),
                         "loss_last_epoch": round(float(np.mean(hist[-128:])), 5),

@@ -140,6 +140,31 @@ def summarize_profiles(prof_dir: str):
     print(json.dumps(d))
 
 
+NEWTON_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_newton/trace "
+                          "-o newton -- python3 bench.py --form newton")
+
+
+def summarize_newton_profile(prof_dir: str):
+    """profiles/ summary of the kernels behind one implicit mechanical step
+    (all four forms of bench.py --form newton, operator builds included)."""
+    import csv
+
+    rows = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "newton_kernel_stats.csv"))))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# Kernel statistics: one implicit mechanical step, HF x fault (599,640 DOF), four forms", "",
+             "Command (from the repository root, `TMPDIR=/tmp`):", "", "```", NEWTON_PROFILE_COMMAND, "```", "",
+             "| kernel | calls | average us | total ms | share of GPU time |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 90:
+            name = name[:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f} % |")
+    lines += ["", f"All kernels: {total / 1e9:.2f} s of GPU time (builds of four operators included)."]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_newton_hf_fault.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def interface_source_hash() -> str:
     with open(os.path.join(ROOT, "paper_2605_14397_amd", "csrc", "hm_interface.hip"), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -248,7 +273,9 @@ def main():
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "interface_kernel_stats.csv")):
+        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "newton_kernel_stats.csv")):
+            summarize_newton_profile(args.summarize_profiles)
+        elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "interface_kernel_stats.csv")):
             summarize_interface_profiles(args.summarize_profiles)
         else:
             summarize_profiles(args.summarize_profiles)

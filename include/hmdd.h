@@ -378,8 +378,11 @@ hm_status hm_precond_apply(const hm_op* op, int precond, int nrhs, const double*
  * algorithm: the consistent tangent of the mechanical Jacobian
  * J = E - eta/dt - C^ep (Sec. 3.1.1).  The integration details are in the
  * paper's supplement, which this library does not follow; the scheme above
- * is its own.  The local problems are assumed well posed: each stiffness
- * exceeds the softening rate of the strength it controls.
+ * is its own.  Every surface test allows 1e-12 of the trial traction scale
+ * (|T_tr| summed over components + c_peak + sigma_peak), so that states the
+ * algorithm puts exactly on a surface are not decided by rounding.  The
+ * local problems are assumed well posed: each stiffness exceeds the
+ * softening rate of the strength it controls.
  */
 typedef struct {
     double k_s, k_n;          /* shear and normal stiffness (Pa/m), finite, > 0 */
@@ -473,8 +476,10 @@ void hm_newton_opts_default(hm_newton_opts* opts);
  * All device FP64 arrays, element-major in local frames; the operator is
  * the mesh's (N elements).  On return the operator's tangent is D at the
  * returned state.  HM_ENOTCONV (report filled, last iterate returned) when
- * the tolerance is not met within max_newton iterations.  Synchronises
- * the stream; the operator is used by one caller at a time.
+ * the tolerance is not met within max_newton iterations; HM_EINVAL when an
+ * output array is one of d_t, d_dp, d_chi (the start-of-step state is read
+ * at every iteration) or the operator has no FP64 form for the residual.
+ * Synchronises the stream; the operator is used by one caller at a time.
  */
 hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,
                          const double* d_t, const double* d_dp, const double* d_chi, const double* d_dT0,

@@ -69,3 +69,20 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
+
+
+def build_c_example() -> str:
+    """Compile tests/c/hm_example.c (plain C against include/hmdd.h and the
+    HIP runtime) into tests/c/hm_example, linked to the in-tree library."""
+    root = os.path.dirname(HERE)
+    src = os.path.join(root, "tests", "c", "hm_example.c")
+    exe = os.path.join(root, "tests", "c", "hm_example")
+    rocm = os.path.dirname(os.path.dirname(_hipcc()))
+    cmd = ["gcc", "-std=c11", "-O1", "-Wall", "-I", os.path.join(root, "include"), "-I",
+           os.path.join(rocm, "include"), "-D__HIP_PLATFORM_AMD__", src, "-o", exe, "-L", HERE, "-lhmdd",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN/../../paper_2605_14397_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return exe

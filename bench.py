@@ -140,6 +140,37 @@ def summarize_profiles(prof_dir: str):
     print(json.dumps(d))
 
 
+MIXED_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_mixed/trace "
+                         "-o mixed -- python3 bench.py --only mixed --steps 20 --warmup 3 --no-gmres "
+                         "--no-cpu-baseline")
+
+
+def summarize_mixed_profile(prof_dir: str):
+    """profiles/ kernel statistics of the precision form's product (FP32 near,
+    BF16 far) on the primary workload."""
+    import csv
+
+    rows = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "mixed_kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel statistics: 256x256 planar fault, 16 RHS, FP32 near / BF16 far form", "",
+             "Command (from the repository root, `TMPDIR=/tmp`):", "", "```", MIXED_PROFILE_COMMAND, "```", "",
+             "| kernel | calls | average us | min us | max us | share of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows[:16]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} % |")
+    per_product = {}
+    for r in rows:
+        k = _kernel_base(r["Name"])
+        for p in PHASE_KERNELS:
+            if k.startswith(p):
+                per_product[p] = per_product.get(p, 0.0) + float(r["TotalDurationNs"])
+    calls = sum(int(r["Calls"]) for r in rows if _kernel_base(r["Name"]).startswith("k_gather"))
+    lines += ["", f"Per product ({calls} products; phase kernels summed over their launches of one product):", ""]
+    lines += [f"* `{p}`: {ns / calls / 1e3:.1f} us" for p, ns in per_product.items()]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_primary_mixed_bf16.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 NEWTON_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_newton/trace "
                           "-o newton -- python3 bench.py --form newton")
 
@@ -273,7 +304,9 @@ def main():
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "newton_kernel_stats.csv")):
+        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "mixed_kernel_stats.csv")):
+            summarize_mixed_profile(args.summarize_profiles)
+        elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "newton_kernel_stats.csv")):
             summarize_newton_profile(args.summarize_profiles)
         elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "interface_kernel_stats.csv")):
             summarize_interface_profiles(args.summarize_profiles)

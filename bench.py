@@ -280,12 +280,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "newton", "copy"],
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "newton",
+                                       "injection", "copy"],
                     default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
                          "learned: trained preconditioner correction on the HF x fault tangent solves; "
                          "interface: interface-law update and consistent tangent of 199,880 elements; "
                          "newton: one implicit mechanical step (Newton) of the HF x fault under a pressure rise; "
+                         "injection: adaptive implicit run of the HF x fault injection (paper's step controller); "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
     ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
@@ -339,6 +341,9 @@ def main():
         return
     if args.form == "newton":
         bench_newton(args)
+        return
+    if args.form == "injection":
+        bench_injection(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -1011,6 +1016,83 @@ def bench_newton(args):
                                   "pre-existing fault (friction 0.6); Gaussian pressure rise 8 MPa / 10 m; "
                                   "leaf 64, eta 2, ACA 1e-6; GMRES(50) to 1e-6 per Newton iteration"},
            "forms": res, "speedup_vs_fp64_block_jacobi": {k: round(base / v["time_s"], 3) for k, v in res.items()}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_injection(args):
+    """Adaptive implicit run of the HF x fault injection (199,880 triangles):
+    pore pressure injection_pressure_time over 20 s, materials and initial
+    tractions of the injection path, eta/dt of the current step.  Each step
+    is one hm_newton_step (precision form, leaf block-Jacobi,
+    Eisenstat-Walker forcing, FP64 residual to 1e-8 of the initial one); a
+    step whose Newton iteration does not converge is rejected and retried
+    with half the step; an accepted step's truncation-error estimate
+    (hm_lte_estimate) and Newton count set the next step
+    (hm_timestep_next: eps 1e-2, 6 target iterations, growth at most 1.2)."""
+    import numpy as np
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads import hf_fault_mesh
+    from workloads.interface import injection_path, injection_pressure_time
+
+    m = hf_fault_mesh(h=args.hf_h)
+    p = injection_path(m, 1)
+    cu = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    G = YOUNG / (2 * (1 + NU))
+    rho = 2700.0
+    cs, cp = np.sqrt(G / rho), np.sqrt((YOUNG / (3 * (1 - 2 * NU)) + 4 * G / 3) / rho)
+    eta = 0.5 * np.array([G / cs, G / cs, G / cp])
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6,
+                     near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1)
+    torch.cuda.synchronize()
+    t_end, t, dt = 20.0, 0.0, 1.0
+    dt_prev, e_prev = 0.0, 0.0
+    st, dp, chi, mid = cu(p["t"]), cu(p["dp"]), cu(p["chi"]), cu(p["mat_id"], torch.int32)
+    total = torch.zeros_like(st)
+    dd_prev = None
+    steps, rejected, newton_its, gmres_its = [], 0, 0, 0
+    t0 = time.perf_counter()
+    while t < t_end - 1e-12 and len(steps) < 400:
+        dt = min(dt, t_end - t)
+        dpress = cu(injection_pressure_time(m, t + dt) - injection_pressure_time(m, t))
+        prev = torch.zeros_like(st) if dd_prev is None else dd_prev * (dt / dt_prev)
+        dd, t_new, dp_new, chi_new, rep = op.newton_step(p["mats"], st, dp, chi, dpress=dpress,
+                                                         eta_dt=cu(np.tile(eta / dt, (m.ne, 1))), dd_prev=prev,
+                                                         mat_id=mid, rtol=1e-8, lin_rtol=1e-6, forcing=1,
+                                                         lin_precond=hm.HM_PC_LEAF, lin_refine=1,
+                                                         raise_on_notconv=False)
+        newton_its += rep["iterations"]
+        gmres_its += sum(rep["gmres_iterations"])
+        if not rep["converged"]:
+            rejected += 1
+            dt *= 0.5
+            log(f"t {t:.4f}: step {dt * 2:.4g} s rejected ({rep['iterations']} Newton iterations)")
+            continue
+        total += dd
+        e = hm.lte_estimate(dd.reshape(-1), dt, dd_prev.reshape(-1) if dd_prev is not None else None,
+                            dt_prev if dd_prev is not None else 1.0, total.reshape(-1))
+        t += dt
+        steps.append({"t": round(t, 5), "dt": round(dt, 5), "newton": rep["iterations"],
+                      "gmres": sum(rep["gmres_iterations"]), "lte": float(f"{e:.3e}"), "modes": rep["modes"]})
+        log(f"t {t:.4f}: dt {dt:.4g} s, {rep['iterations']} Newton, lte {e:.2e}, modes {rep['modes']}")
+        st, dp, chi, dd_prev = t_new, dp_new, chi_new, dd
+        dt_next = hm.timestep_next(dt, dt_prev, e, e_prev, max(1, rep["iterations"]), eps_tol=1e-2, n_target=6,
+                                   growth_max=1.2, dt_min=1e-4)
+        dt_prev, e_prev, dt = dt, e, dt_next
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"metric": "wall time of the adaptive implicit injection run (20 s of injection)",
+           "value": round(wall, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 residual, f32/bf16 operator",
+           "config": {"workload": f"HF x fault, {m.ne} triangles, {m.ndof} DOF; pore pressure rising to 8 MPa "
+                                  "over 20 s (Gaussian, 6 -> 20 m); intact-joint fracture, pre-existing fault; "
+                                  "precision form, leaf block-Jacobi, Eisenstat-Walker forcing; step controller "
+                                  "eps 1e-2, 6 target Newton iterations, growth 1.2"},
+           "accepted_steps": len(steps), "rejected_steps": rejected, "newton_iterations": newton_its,
+           "gmres_iterations": gmres_its, "final_modes_elastic_shear_tensile_corner_open": steps[-1]["modes"],
+           "max_opening_mm": round(float(total[:, 2].max()) * 1e3, 4),
+           "max_slip_mm": round(float(total[:, :2].norm(dim=1).max()) * 1e3, 4), "steps": steps}
     print(json.dumps(out), flush=True)
 
 

@@ -488,6 +488,41 @@ hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats
                          hm_newton_report* rep, void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Adaptive time stepping                                               */
+/* ------------------------------------------------------------------ */
+/*
+ * Paper Sec. 3.4 ("Adaptive time-stepping").  The local truncation error of
+ * a backward-Euler step is estimated from the change of rate,
+ *   e_{n+1} = (dt_n / 2) ||dd_{n+1}/dt_n - dd_n/dt_{n-1}|| / ||d_{n+1}||
+ * (dd the DD increments of the two steps, d the total DD after the step;
+ * 2-norms over all DOF), and the next step size follows the controller
+ *   dt_{n+1} = dt_n (dt_n/dt_{n-1})^(-1/4) (eps/e_{n+1})^(1/4)
+ *              (e_n/eps)^(-1/4) (n_its/n_target)^(-1/3),
+ * written here as the paper prints it, with sqrt(machine epsilon) added to
+ * both errors, the growth limited to dt_{n+1} <= growth_max dt_n and the
+ * result kept in [dt_min, dt_max].  Only the DD estimate is built (pore
+ * pressures are inputs of hm_newton_step, not unknowns).
+ */
+typedef struct {
+    double eps_tol;     /* target relative truncation error; default 1e-3 */
+    int n_target;       /* target Newton iterations per step; default 6 */
+    double growth_max;  /* largest dt_{n+1} / dt_n; default 1.2 */
+    double dt_min;      /* smallest step; default 0 */
+    double dt_max;      /* largest step; default INFINITY */
+} hm_timestep_opts;
+
+void hm_timestep_opts_default(hm_timestep_opts* opts);
+/* Host only.  dt_n > 0 and n_its >= 1 (else HM_EINVAL); a first step passes
+ * dt_prev <= 0 and e_n <= 0, which drops the factors that need them. */
+hm_status hm_timestep_next(const hm_timestep_opts* opts, double dt_n, double dt_prev, double e_next, double e_n,
+                           int n_its, double* dt_next);
+/* e_{n+1} above from device FP64 vectors of length n (d_dd_prev may be NULL
+ * for a first step: zero rate); deterministic reduction; synchronises the
+ * stream.  dt, dt_prev > 0 (dt_prev ignored when d_dd_prev is NULL). */
+hm_status hm_lte_estimate(int64_t n, const double* d_dd, double dt, const double* d_dd_prev, double dt_prev,
+                          const double* d_total, double* e, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Learned correction of the block preconditioner                       */
 /* ------------------------------------------------------------------ */
 /*

@@ -40,7 +40,8 @@ EXPORTS = [
     "hm_learned_get_params",
     "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
     "hm_learned_attach", "hm_learned_detach", "hm_precond_apply", "hm_interface_update",
-    "hm_newton_opts_default", "hm_newton_step",
+    "hm_newton_opts_default", "hm_newton_step", "hm_timestep_opts_default", "hm_timestep_next",
+    "hm_lte_estimate",
 ]
 
 
@@ -80,6 +81,11 @@ class SolveOpts(ctypes.Structure):
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
                 ("lin", SolveOpts), ("forcing", ctypes.c_int)]
+
+
+class TimestepOpts(ctypes.Structure):
+    _fields_ = [("eps_tol", ctypes.c_double), ("n_target", ctypes.c_int), ("growth_max", ctypes.c_double),
+                ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double)]
 
 
 class NewtonReport(ctypes.Structure):
@@ -175,6 +181,9 @@ def lib():
             "hm_precond_apply": ([P, I, I, P, I64, P, I64, P], I),
             "hm_interface_update": ([I, P, I64, P, P, P, P, P, P, P, P, P, P, P, P, P], I),
             "hm_newton_opts_default": ([ctypes.POINTER(NewtonOpts)], None),
+            "hm_timestep_opts_default": ([ctypes.POINTER(TimestepOpts)], None),
+            "hm_timestep_next": ([ctypes.POINTER(TimestepOpts), D, D, D, D, I, ctypes.POINTER(D)], I),
+            "hm_lte_estimate": ([I64, P, D, P, D, P, ctypes.POINTER(D), P], I),
             "hm_newton_step": ([P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(NewtonOpts),
                                 ctypes.POINTER(NewtonReport), P], I),
         }
@@ -571,3 +580,31 @@ def interface_update(mats, dd, t, dp, chi, mat_id=None, eta_dt=None, want_D=Fals
                                      _dev_ptr(o["cep"], f64), _dev_ptr(o["mode"], torch.int32), eta, Dp,
                                      _stream(stream)))
     return o
+
+
+# ---------------------------------------------------------------- adaptive time stepping
+def timestep_next(dt_n, dt_prev, e_next, e_n, n_its, **opts):
+    """Next step size from the paper's controller (hm_timestep_next); opts:
+    eps_tol, n_target, growth_max, dt_min, dt_max."""
+    o = TimestepOpts()
+    lib().hm_timestep_opts_default(ctypes.byref(o))
+    for k, v in opts.items():
+        setattr(o, k, v)
+    out = ctypes.c_double()
+    _check(lib().hm_timestep_next(ctypes.byref(o), float(dt_n), float(dt_prev), float(e_next), float(e_n),
+                                  int(n_its), ctypes.byref(out)))
+    return out.value
+
+
+def lte_estimate(dd, dt, dd_prev, dt_prev, total, stream=None):
+    """Relative truncation-error estimate of a step (hm_lte_estimate); CUDA
+    float64 vectors of one length (dd_prev may be None)."""
+    import torch
+
+    f64 = torch.float64
+    e = ctypes.c_double()
+    _check(lib().hm_lte_estimate(dd.numel(), _dev_ptr(dd.contiguous(), f64), float(dt),
+                                 _dev_ptr(dd_prev.contiguous(), f64) if dd_prev is not None else None,
+                                 float(dt_prev), _dev_ptr(total.contiguous(), f64), ctypes.byref(e),
+                                 _stream(stream)))
+    return e.value

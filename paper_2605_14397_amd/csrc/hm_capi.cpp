@@ -1,5 +1,7 @@
 // extern "C" boundary of the hmdd library: argument checks, error codes,
 // thread-local messages.  No C++ exception crosses these functions.
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <new>
 
@@ -364,6 +366,49 @@ hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats
         if (st == HM_ENOTCONV) hm::set_last_error("Newton did not reach the residual tolerance (last iterate returned)");
     });
     return g != HM_OK ? g : st;
+}
+
+void hm_timestep_opts_default(hm_timestep_opts* o)
+{
+    if (!o) return;
+    o->eps_tol = 1e-3;
+    o->n_target = 6;
+    o->growth_max = 1.2;
+    o->dt_min = 0.0;
+    o->dt_max = INFINITY;
+}
+
+hm_status hm_timestep_next(const hm_timestep_opts* opts, double dt_n, double dt_prev, double e_next, double e_n,
+                           int n_its, double* dt_next)
+{
+    return guarded([&] {
+        HM_REQUIRE(dt_next, HM_EINVAL, "dt_next is null");
+        HM_REQUIRE(dt_n > 0.0 && n_its >= 1, HM_EINVAL, "need dt_n > 0 and n_its >= 1");
+        hm_timestep_opts o;
+        hm_timestep_opts_default(&o);
+        if (opts) o = *opts;
+        HM_REQUIRE(o.eps_tol > 0.0 && o.n_target >= 1 && o.growth_max > 0.0 && o.dt_min >= 0.0 &&
+                       o.dt_max >= o.dt_min,
+                   HM_EINVAL, "invalid controller options");
+        const double floor_e = std::sqrt(2.220446049250313e-16);   // sqrt of the FP64 unit roundoff
+        double dt = dt_n;
+        if (dt_prev > 0.0) dt *= std::pow(dt_n / dt_prev, -0.25);
+        dt *= std::pow(o.eps_tol / (std::max(e_next, 0.0) + floor_e), 0.25);
+        if (e_n > 0.0) dt *= std::pow((e_n + floor_e) / o.eps_tol, -0.25);
+        dt *= std::pow((double)n_its / o.n_target, -1.0 / 3.0);
+        dt = std::min(dt, o.growth_max * dt_n);
+        *dt_next = std::max(o.dt_min, std::min(dt, o.dt_max));
+    });
+}
+
+hm_status hm_lte_estimate(int64_t n, const double* d_dd, double dt, const double* d_dd_prev, double dt_prev,
+                          const double* d_total, double* e, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(e, HM_EINVAL, "e is null");
+        require_gfx950();
+        *e = hm::lte_estimate(n, d_dd, dt, d_dd_prev, dt_prev, d_total, (hipStream_t)hip_stream);
+    });
 }
 
 hm_status hm_learned_create(int hidden, int neighbors, uint64_t seed, hm_learned** out)

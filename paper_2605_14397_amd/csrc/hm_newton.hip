@@ -61,6 +61,39 @@ __global__ __launch_bounds__(256) void k_sub(int64_t n, const double* y, double*
     if (i < n) x[i] -= y[i];
 }
 
+// partial sums of (dd/dt - dd_prev/dt_prev)^2 and total^2 per block, same layout as k_sumsq_partial
+__global__ __launch_bounds__(kNormBlock) void k_lte_partial(int64_t n, const double* dd, double inv_dt,
+                                                            const double* dd_prev, double inv_dt_prev,
+                                                            const double* total, double* partial)
+{
+    __shared__ double ra[kNormBlock], rb[kNormBlock];
+    const int64_t base = (int64_t)blockIdx.x * kNormBlock * kNormPerThread + threadIdx.x;
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int j = 0; j < kNormPerThread; ++j) {
+        const int64_t i = base + (int64_t)j * kNormBlock;
+        if (i < n) {
+            const double r = dd[i] * inv_dt - (dd_prev ? dd_prev[i] * inv_dt_prev : 0.0);
+            sa += r * r;
+            sb += total[i] * total[i];
+        }
+    }
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int w = kNormBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ra[threadIdx.x] += ra[threadIdx.x + w];
+            rb[threadIdx.x] += rb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ra[0];
+        partial[2 * blockIdx.x + 1] = rb[0];
+    }
+}
+
 double now_ms()
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -158,6 +191,28 @@ hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, cons
         rep->ms = now_ms() - t0;
     }
     return converged ? HM_OK : HM_ENOTCONV;
+}
+
+double lte_estimate(int64_t n, const double* d_dd, double dt, const double* d_dd_prev, double dt_prev,
+                    const double* d_total, hipStream_t s)
+{
+    HM_REQUIRE(n >= 1 && d_dd && d_total, HM_EINVAL, "vectors must be non-null and non-empty");
+    HM_REQUIRE(dt > 0.0 && (!d_dd_prev || dt_prev > 0.0), HM_EINVAL, "time steps must be positive");
+    const int64_t nblk = (n + kNormBlock * kNormPerThread - 1) / (kNormBlock * kNormPerThread);
+    DevBuf part(sizeof(double) * 2 * nblk);
+    hipLaunchKernelGGL(k_lte_partial, dim3((unsigned)nblk), dim3(kNormBlock), 0, s, n, d_dd, 1.0 / dt, d_dd_prev,
+                       d_dd_prev ? 1.0 / dt_prev : 0.0, d_total, part.as<double>());
+    HM_CHECK_HIP(hipGetLastError());
+    std::vector<double> h(2 * nblk);
+    HM_CHECK_HIP(hipMemcpyAsync(h.data(), part.get(), sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    double a = 0.0, b = 0.0;
+    for (int64_t i = 0; i < nblk; ++i) {
+        a += h[2 * i];
+        b += h[2 * i + 1];
+    }
+    HM_REQUIRE(b > 0.0, HM_EINVAL, "the total DD is zero");
+    return 0.5 * dt * std::sqrt(a) / std::sqrt(b);
 }
 
 }  // namespace hm

@@ -165,6 +165,9 @@ hm_status newton_step(Op& op, int n_mat, const hm_interface_material* mats, cons
                       double* d_t_new, double* d_dp_new, double* d_chi_new, const hm_newton_opts& o,
                       hm_newton_report* rep, hipStream_t s);
 
+double lte_estimate(int64_t n, const double* d_dd, double dt, const double* d_dd_prev, double dt_prev,
+                    const double* d_total, hipStream_t s);
+
 // solve (hm_solve.hip)
 hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int64_t ldb, double* d_X,
                 int64_t ldx, hm_solve_report* rep, hipStream_t s);

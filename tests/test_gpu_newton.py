@@ -152,3 +152,19 @@ def test_eisenstat_walker_forcing_reaches_the_same_step_with_fewer_inner_iterati
     err = np.linalg.norm(res[1][0] - res[0][0]) / np.linalg.norm(res[0][0])
     print("gmres total constant", res[0][1], "forcing", res[1][1], "diff", err, flush=True)
     assert err <= 1e-8 and res[1][1] < res[0][1]
+
+
+def test_truncation_error_estimate_matches_its_definition():
+    """hm_lte_estimate against (dt/2) ||dd/dt - dd_prev/dt_prev|| / ||d|| in
+    numpy, with and without a previous step."""
+    hm = _hm()
+    rng = np.random.default_rng(9301)
+    n = 3 * 7777
+    dd, dd_prev, tot = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+    e = hm.lte_estimate(cuda(dd), 0.3, cuda(dd_prev), 0.7, cuda(tot))
+    ref = 0.5 * 0.3 * np.linalg.norm(dd / 0.3 - dd_prev / 0.7) / np.linalg.norm(tot)
+    assert e == pytest.approx(ref, rel=1e-13)
+    e0 = hm.lte_estimate(cuda(dd), 0.3, None, 0.0, cuda(tot))
+    assert e0 == pytest.approx(0.5 * np.linalg.norm(dd) / np.linalg.norm(tot), rel=1e-13)
+    with pytest.raises(hm.HMError):
+        hm.lte_estimate(cuda(dd), 0.0, None, 0.0, cuda(tot))

@@ -185,7 +185,7 @@ def test_structs_match_c_layout(tmp_path):
              ("hm_build_opts", hm.BuildOpts), ("hm_op_stats", hm.OpStats), ("hm_batch_opts", hm.BatchOpts),
              ("hm_batch_info", hm.BatchInfo), ("hm_plan_info", hm.PlanInfo),
              ("hm_interface_material", hm.InterfaceMaterial), ("hm_newton_opts", hm.NewtonOpts),
-             ("hm_newton_report", hm.NewtonReport)]
+             ("hm_newton_report", hm.NewtonReport), ("hm_timestep_opts", hm.TimestepOpts)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hmdd.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -203,3 +203,28 @@ def test_structs_match_c_layout(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_timestep_controller_follows_the_printed_formula():
+    """The step-size controller (paper Sec. 3.4) on the host: its fixed point,
+    the exponents of each factor, the growth cap and the bounds."""
+    eps = 1e-3
+    fl = np.sqrt(np.finfo(np.float64).eps)
+    nxt = lambda *a, **k: hm.timestep_next(*a, eps_tol=eps, n_target=6, growth_max=10.0, **k)
+    e_fix = eps - fl      # e + sqrt(machine epsilon) = eps
+    assert nxt(2.0, 2.0, e_fix, e_fix, 6) == pytest.approx(2.0, rel=1e-14)
+    e_half = 0.5 * eps - fl
+    assert nxt(2.0, 2.0, e_half, e_fix, 6) == pytest.approx(2.0 * 2 ** 0.25, rel=1e-13)
+    assert nxt(2.0, 2.0, e_fix, e_half, 6) == pytest.approx(2.0 * 2 ** 0.25, rel=1e-13)
+    assert nxt(2.0, 1.0, e_fix, e_fix, 6) == pytest.approx(2.0 * 2 ** -0.25, rel=1e-13)
+    assert nxt(2.0, 2.0, e_fix, e_fix, 12) == pytest.approx(2.0 * 2 ** (-1 / 3), rel=1e-13)
+    # first step: no previous step, no previous error
+    assert nxt(2.0, 0.0, e_fix, 0.0, 6) == pytest.approx(2.0, rel=1e-14)
+    # growth cap and bounds
+    assert hm.timestep_next(1.0, 1.0, 0.0, 0.0, 1, eps_tol=eps, growth_max=1.2) == pytest.approx(1.2)
+    assert hm.timestep_next(1.0, 1.0, 10.0, 0.0, 50, dt_min=0.5) == 0.5
+    assert hm.timestep_next(1.0, 1.0, 0.0, 0.0, 1, growth_max=100.0, dt_max=3.0) == 3.0
+    with pytest.raises(hm.HMError):
+        hm.timestep_next(0.0, 1.0, 1e-3, 1e-3, 6)
+    with pytest.raises(hm.HMError):
+        hm.timestep_next(1.0, 1.0, 1e-3, 1e-3, 0)

@@ -139,15 +139,21 @@ def injection_path(mesh, n_states: int = 20, young: float = 30e9, nu: float = 0.
     return dict(mats=mats, mat_id=mat_id, t=t0, dp=np.zeros((ne, 3)), chi=chi0, dd=dd, eta_dt=eta_dt)
 
 
-def injection_pressure(mesh, k: int, n_states: int = 20, peak: float = 8e6, sigma0: float = 6.0,
-                       sigma1: float = 20.0, injection=(20.0, 0.0, 0.0)) -> np.ndarray:
-    """Pore pressure above its initial value at the element vertex means
-    after step k of a growing injection: amplitude peak (k + 1) / n_states,
-    Gaussian of width sigma0 + (sigma1 - sigma0) (k + 1) / n_states (m)
-    around the injection point; k = -1 gives zero."""
-    if k < 0:
+def injection_pressure_time(mesh, t: float, duration: float = 20.0, peak: float = 8e6, sigma0: float = 6.0,
+                            sigma1: float = 20.0, injection=(20.0, 0.0, 0.0)) -> np.ndarray:
+    """Pore pressure above its initial value at the element vertex means at
+    time t of a growing injection: amplitude peak t / duration, Gaussian of
+    width sigma0 + (sigma1 - sigma0) t / duration (m) around the injection
+    point; zero for t <= 0."""
+    if t <= 0.0:
         return np.zeros(mesh.ne)
-    f = (k + 1.0) / n_states
+    f = t / duration
     r2 = ((mesh.vertex_means() - np.asarray(injection)) ** 2).sum(axis=1)
     s = sigma0 + (sigma1 - sigma0) * f
     return peak * f * np.exp(-r2 / (2.0 * s * s))
+
+
+def injection_pressure(mesh, k: int, n_states: int = 20, **kw) -> np.ndarray:
+    """The pressure of injection_pressure_time after step k of n_states unit
+    steps (t = k + 1, duration n_states); k = -1 gives zero."""
+    return injection_pressure_time(mesh, k + 1.0, float(n_states), **kw)

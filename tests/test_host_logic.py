@@ -228,3 +228,26 @@ def test_timestep_controller_follows_the_printed_formula():
         hm.timestep_next(0.0, 1.0, 1e-3, 1e-3, 6)
     with pytest.raises(hm.HMError):
         hm.timestep_next(1.0, 1.0, 1e-3, 1e-3, 0)
+
+
+def test_interface_inputs_are_seeded_and_consistent():
+    """The seeded interface states: reproducible, every regime drawn, the
+    internal variables at or above the current inelastic DD (they are
+    maxima over the history), materials inside the library's bounds."""
+    from workloads.interface import injection_path, injection_pressure, interface_materials, interface_states
+
+    mats = interface_materials()
+    assert (mats[:, 6] >= mats[:, 2] * mats[:, 7]).all() and (mats[:, 0] > 0).all() and (mats[:, 1] > 0).all()
+    a, b = interface_states(500, 11, mats), interface_states(500, 11, mats)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    st = a
+    assert st["dd"].shape == (500, 3) and st["mat_id"].dtype == np.int32
+    assert set(np.unique(st["mat_id"])) == {0, 1, 2}
+    assert (st["chi"][:, 0] >= np.hypot(st["dp"][:, 0], st["dp"][:, 1]) * (1 - 1e-15)).all()
+    assert (st["chi"][:, 1] >= np.linalg.norm(st["dp"], axis=1) * (1 - 1e-15)).all()
+    m = square_fault(12)
+    p = injection_path(m, 5)
+    assert len(p["dd"]) == 5 and p["t"].shape == (m.ne, 3)
+    assert np.array_equal(injection_pressure(m, -1, 5), np.zeros(m.ne))
+    assert (injection_pressure(m, 4, 5) >= injection_pressure(m, 3, 5)).all()

@@ -556,8 +556,9 @@ def main():
 
 
 def bench_precision(args):
-    """Three mutually intersecting 40 m disk fractures (103,968 triangles,
-    311,904 DOF), Gaussian pressure bump (peak 5 MPa, sigma 8 m) as the load:
+    """Three mutually intersecting 40 m disk fractures (103,101 triangles,
+    309,303 DOF, after the triangles crossing another disk are dropped),
+    Gaussian pressure bump (peak 5 MPa, sigma 8 m) as the load:
     GMRES to a relative residual of 1e-8 in the plain FP64 form and in the
     precision form (FP32 near field, BF16 low-rank factors, FP64 self
     blocks, FP64 Arnoldi, FP64 iterative refinement with the FP64 operator)."""

@@ -273,20 +273,27 @@ class Mesh:
             self._h = None
 
 
+def _set_fields(o, kw, what):
+    """Set struct fields by name; an unknown name is an error, not a new
+    Python attribute that the library would never see."""
+    names = [f for f, _ in type(o)._fields_]
+    for k, v in kw.items():
+        if k not in names:
+            raise HMError(HM_EINVAL, f"unknown {what} option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
 def build_opts(**kw) -> BuildOpts:
     o = BuildOpts()
     lib().hm_build_opts_default(ctypes.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw, "build")
 
 
 def solve_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     lib().hm_solve_opts_default(ctypes.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw, "solve")
 
 
 class Operator:
@@ -376,10 +383,12 @@ class Operator:
         o = NewtonOpts()
         lib().hm_newton_opts_default(ctypes.byref(o))
         for k, v in opts.items():
+            if k == "lin":
+                raise HMError(HM_EINVAL, "pass linear-solve options as lin_<name>")
             if k.startswith("lin_"):
-                setattr(o.lin, k[4:], v)
+                _set_fields(o.lin, {k[4:]: v}, "Newton linear-solve")
             else:
-                setattr(o, k, v)
+                _set_fields(o, {k: v}, "Newton")
         mats = np.ascontiguousarray(np.atleast_2d(mats), dtype=np.float64)
         arr = (InterfaceMaterial * mats.shape[0])()
         for i in range(mats.shape[0]):
@@ -588,8 +597,7 @@ def timestep_next(dt_n, dt_prev, e_next, e_n, n_its, **opts):
     eps_tol, n_target, growth_max, dt_min, dt_max."""
     o = TimestepOpts()
     lib().hm_timestep_opts_default(ctypes.byref(o))
-    for k, v in opts.items():
-        setattr(o, k, v)
+    _set_fields(o, opts, "time-step")
     out = ctypes.c_double()
     _check(lib().hm_timestep_next(ctypes.byref(o), float(dt_n), float(dt_prev), float(e_next), float(e_n),
                                   int(n_its), ctypes.byref(out)))

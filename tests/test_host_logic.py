@@ -224,6 +224,8 @@ def test_timestep_controller_follows_the_printed_formula():
     assert hm.timestep_next(1.0, 1.0, 0.0, 0.0, 1, eps_tol=eps, growth_max=1.2) == pytest.approx(1.2)
     assert hm.timestep_next(1.0, 1.0, 10.0, 0.0, 50, dt_min=0.5) == 0.5
     assert hm.timestep_next(1.0, 1.0, 0.0, 0.0, 1, growth_max=100.0, dt_max=3.0) == 3.0
+    with pytest.raises(hm.HMError, match="unknown"):
+        hm.timestep_next(1.0, 1.0, 1e-3, 1e-3, 6, eps=1e-3)
     with pytest.raises(hm.HMError):
         hm.timestep_next(0.0, 1.0, 1e-3, 1e-3, 6)
     with pytest.raises(hm.HMError):
@@ -251,3 +253,12 @@ def test_interface_inputs_are_seeded_and_consistent():
     assert len(p["dd"]) == 5 and p["t"].shape == (m.ne, 3)
     assert np.array_equal(injection_pressure(m, -1, 5), np.zeros(m.ne))
     assert (injection_pressure(m, 4, 5) >= injection_pressure(m, 3, 5)).all()
+
+
+def test_unknown_options_are_rejected():
+    """A misspelt option name raises instead of being silently ignored."""
+    with pytest.raises(hm.HMError, match="unknown build option"):
+        hm.build_opts(leafsize=32)
+    with pytest.raises(hm.HMError, match="unknown solve option"):
+        hm.solve_opts(precon=hm.HM_PC_LEAF)
+    assert hm.solve_opts(precond=hm.HM_PC_LEAF).precond == hm.HM_PC_LEAF

@@ -168,3 +168,62 @@ def test_truncation_error_estimate_matches_its_definition():
     assert e0 == pytest.approx(0.5 * np.linalg.norm(dd) / np.linalg.norm(tot), rel=1e-13)
     with pytest.raises(hm.HMError):
         hm.lte_estimate(cuda(dd), 0.0, None, 0.0, cuda(tot))
+
+
+def test_hf_fault_full_size_step_sampled_against_the_oracle():
+    """The timed implicit step at full size (HF x fault, 199,880 triangles,
+    precision form with leaf block-Jacobi and Eisenstat-Walker forcing, FP64
+    residual to 1e-8): at sampled elements of every mode present, the
+    oracle's interface law from the start-of-step state at the returned
+    increment reproduces the returned tractions, inelastic DD and state
+    variables, and the oracle's exact rows of E give a residual within the
+    reported one plus the far-field approximation error."""
+    hm = _hm()
+    from workloads import hf_fault_mesh
+    from workloads.interface import injection_path
+
+    m = hf_fault_mesh()
+    p = injection_path(m, 1)
+    r2 = ((m.vertex_means() - np.array([20.0, 0.0, 0.0])) ** 2).sum(axis=1)
+    dpress = 8e6 * np.exp(-r2 / (2 * 10.0 ** 2))
+    G = YOUNG / (2 * (1 + NU))
+    cs, cp = np.sqrt(G / 2700.0), np.sqrt((YOUNG / (3 * (1 - 2 * NU)) + 4 * G / 3) / 2700.0)
+    eta_dt = np.tile(0.5 * np.array([G / cs, G / cs, G / cp]), (m.ne, 1))
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6,
+                     near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1)
+    z = cuda(np.zeros_like(p["t"]))
+    dd, t_new, dp_new, chi_new, rep = op.newton_step(
+        p["mats"], cuda(p["t"]), cuda(p["dp"]), cuda(p["chi"]), dpress=cuda(dpress), eta_dt=cuda(eta_dt), dd_prev=z,
+        mat_id=cuda(p["mat_id"], torch.int32), rtol=1e-8, lin_rtol=1e-6, lin_restart=50,
+        lin_precond=hm.HM_PC_LEAF, lin_refine=1, forcing=1)
+    # the element modes at the returned increment select the sample (two of every mode present, the most
+    # loaded first); the oracle then decides the modes of the sampled elements itself
+    gmode = hm.interface_update(p["mats"], dd, cuda(p["t"]), cuda(p["dp"]), cuda(p["chi"]),
+                                mat_id=cuda(p["mat_id"], torch.int32))["mode"].cpu().numpy()
+    dd, t_new, dp_new, chi_new = (a.cpu().numpy() for a in (dd, t_new, dp_new, chi_new))
+    print("newton its", rep["iterations"], "gmres", rep["gmres_iterations"], "modes", rep["modes"], flush=True)
+    assert rep["converged"] and rep["residual"][-1] <= 1e-8 * rep["residual"][0]
+    assert rep["modes"] == np.bincount(gmode, minlength=5).tolist()
+    assert rep["modes"][law.SHEAR] > 0 and rep["modes"][law.ELASTIC] > 0
+    rows = []
+    for md in range(5):
+        ids = np.flatnonzero(gmode == md)
+        rows += ids[np.argsort(-dpress[ids])[:2]].tolist()
+    rows = np.array(sorted(rows))
+    T, dp, chi, _, mode = law.update(p["mats"], p["mat_id"][rows], dd[rows], p["t"][rows], p["dp"][rows],
+                                     p["chi"][rows])
+    np.testing.assert_array_equal(mode, gmode[rows])
+    tscale = np.abs(p["t"]).max() + np.abs(T).max()
+    np.testing.assert_allclose(t_new[rows], T, rtol=0, atol=1e-11 * tscale)
+    np.testing.assert_allclose(dp_new[rows], dp, rtol=0, atol=1e-11 * (np.abs(dp).max() + 1e-12))
+    np.testing.assert_allclose(chi_new[rows], chi, rtol=0, atol=1e-11 * (np.abs(chi).max() + 1e-12))
+    # residual rows from the oracle's exact E
+    Edd = oracle.rows_matvec(m, YOUNG, NU, rows, dd.reshape(1, -1), method=1)[0].reshape(-1, 3)
+    r = -(T - p["t"][rows]) + Edd - eta_dt[rows] * dd[rows]
+    r[:, 2] += dpress[rows]
+    # every entry of the H-residual is at most its reported 2-norm; the exact rows add the far-field
+    # approximation error, bounded by the ACA tolerance of the largest sampled E dd
+    bound = rep["residual"][-1] + 1e-6 * np.abs(Edd).max()
+    print("sampled rows", rows.tolist(), "modes", mode.tolist(), "max |r|", np.abs(r).max(), "bound", bound,
+          "final H-residual", rep["residual"][-1], flush=True)
+    assert np.abs(r).max() <= bound

@@ -298,3 +298,77 @@ def test_trained_correction_reduces_gmres_iterations_on_held_out_states(hf):
         its_l.append(r1["iterations"])
     print("block-Jacobi", its_bj, "learned", its_l, "final loss", hist[-16:].mean())
     assert sum(its_l) <= 0.8 * sum(its_bj)
+
+
+def test_full_size_sampled_apply_matches_oracle():
+    """The learned correction at the HF x fault size (199,880 triangles,
+    16 neighbours, 64 hidden units, as timed): at sampled elements whose 16
+    nearest elements are unique (a clear gap to the 17th), the pairs, the
+    features and M^-1 R match the oracle, which finds the neighbours by
+    brute force over all elements, takes the base block from the exact
+    self coefficient and sums the correction over the pairs.  The tangent
+    state has D_e h_e / E' constant, so the patch means (features 18-19)
+    are the same for any grouping of the elements."""
+    hm = _hm()
+    Hf, Kf = 64, 16
+    m = W.hf_fault_mesh()
+    cent, frame, area = oracle.frames(m)
+    h = np.sqrt(area)
+    Ep = YOUNG / (1 - NU * NU)
+    Mfix = np.array([[1.0, 0.0, 0.2], [0.0, 0.8, 0.0], [0.3, 0.0, 2.0]])
+    D = (0.5 * Ep / h)[:, None, None] * Mfix
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6)
+    op.set_tangent(cuda(D))
+    rng = np.random.default_rng(3)
+    th = (rng.uniform(-1, 1, OL.n_params(Hf)) * 0.25).astype(np.float32)
+    net = hm.Learned(hidden=Hf, neighbors=Kf, seed=1)
+    net.set_params(th)
+    net.attach(op)
+    R = np.random.default_rng(31).standard_normal((2, m.ndof))
+    Z = op.precond_apply(cuda(R), hm.HM_PC_LEARNED).cpu().numpy()
+    pe_g, pf_g, feat_g, scale_g = hm.learned_features(op, Kf)
+    # sampled elements with a unique neighbour set, nearest by brute force
+    # (twelve on the hydraulic fracture, twelve on the fault)
+    sample, nbrs = [], []
+    srng = np.random.default_rng(32)
+    for lo, n in m.meta["parts"]:
+        got = 0
+        for e in lo + srng.choice(n, 300, replace=False):
+            d2 = np.sum((cent - cent[e]) ** 2, axis=1)
+            order = np.lexsort((np.arange(m.ne), d2))
+            if d2[order[Kf]] - d2[order[Kf - 1]] > 1e-9 * d2[order[Kf]]:
+                sample.append(int(e))
+                nbrs.append(order[:Kf])
+                got += 1
+            if got == 12:
+                break
+    assert len(sample) == 24
+    pe = np.repeat(np.array(sample, np.int64), Kf)
+    pf = np.concatenate(nbrs).astype(np.int64)
+    for e, nb in zip(sample, nbrs):
+        assert sorted(pf_g[pe_g == e].tolist()) == sorted(nb.tolist()), e
+    F, scale = OL.features(cent, frame, area, D, None, [np.arange(m.ne)], pe, pf, YOUNG, NU)
+    gidx = {(int(a), int(b)): i for i, (a, b) in
+            enumerate(zip(pe_g[np.isin(pe_g, sample)], pf_g[np.isin(pe_g, sample)]))}
+    sel = np.flatnonzero(np.isin(pe_g, sample))
+    rows_g = sel[[gidx[(int(a), int(b))] for a, b in zip(pe, pf)]]
+    np.testing.assert_allclose(feat_g[rows_g].astype(np.float64), F, rtol=2.0 ** -22, atol=1e-12)
+    np.testing.assert_allclose(scale_g[rows_g], scale, rtol=1e-14, atol=0)
+    # M^-1 R on the sampled elements: the oracle's apply over the elements involved
+    U = np.unique(np.concatenate([pe, pf]))
+    loc = {int(u): i for i, u in enumerate(U)}
+    Bb = np.zeros((len(U), 3, 3))
+    for e in sample:
+        Eee = oracle.blocks(m, YOUNG, NU, [e], [e], method=1)[0, 0]
+        Bb[loc[e]] = np.linalg.inv(Eee - D[e])
+    Wb = OL.blocks(th.astype(np.float64), Hf, F.astype(np.float32).astype(np.float64), scale)
+    dof = (3 * U[:, None] + np.arange(3)).ravel()
+    Zo = OL.apply(Bb, np.array([loc[int(a)] for a in pe]), np.array([loc[int(b)] for b in pf]), Wb, R[:, dof])
+    Zb = OL.apply(Bb, np.array([loc[int(a)] for a in pe]), np.array([loc[int(b)] for b in pf]), 0 * Wb, R[:, dof])
+    rows_o = (3 * np.array([loc[e] for e in sample])[:, None] + np.arange(3)).ravel()
+    rows_z = (3 * np.array(sample)[:, None] + np.arange(3)).ravel()
+    for c in range(2):
+        err = np.linalg.norm(Z[c, rows_z] - Zo[c, rows_o]) / np.linalg.norm(Zo[c, rows_o])
+        corr = np.linalg.norm(Zo[c, rows_o] - Zb[c, rows_o]) / np.linalg.norm(Zo[c, rows_o])
+        print(f"column {c}: sampled error {err:.2e}, correction share {corr:.2e}", flush=True)
+        assert err <= 1e-6 and corr > 1e-2

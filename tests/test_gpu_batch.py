@@ -91,3 +91,36 @@ def test_batch_rejects_mixed_precision_forms(small_faults):
     with pytest.raises(hm.HMError) as e:
         hm.Batch([a, b])
     assert e.value.status == hm.HM_EUNSUPPORTED
+
+
+def test_full_size_batch_sampled_rows():
+    """The timed batched configuration (64 faults, 2k-40k elements, FP32,
+    leaf 64, eta 2, ACA 1e-6, graph-captured, autotuned, 16 columns): the
+    largest, the smallest and four seeded meshes equal their own single
+    products bit for bit and match 32 exact rows each from the oracle
+    (FP32 bar 1e-5); a second graph replay repeats the first bit for bit."""
+    hm = _hm()
+    meshes = batched_faults(n_meshes=64, seed=4001)
+    ops = [hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6,
+                       near_prec=hm.HM_F32, far_prec=hm.HM_F32) for m in meshes]
+    batch = hm.Batch(ops, use_graph=True, autotune=True)
+    Xs = [torch.as_tensor(rhs_columns(m.ndof, 16, 4101 + 100 * k), device="cuda") for k, m in enumerate(meshes)]
+    Ys = [torch.empty_like(x) for x in Xs]
+    batch.apply(Xs, Ys)
+    first = [y.cpu().numpy() for y in Ys]
+    batch.apply(Xs, Ys)
+    torch.cuda.synchronize()
+    sizes = np.array([m.ne for m in meshes])
+    rng = np.random.default_rng(4202)
+    picks = [int(np.argmax(sizes)), int(np.argmin(sizes))] + rng.choice(64, 4, replace=False).tolist()
+    for k in picks:
+        got = Ys[k].cpu().numpy()
+        assert np.array_equal(got, first[k]), k
+        assert np.array_equal(got, ops[k].apply(Xs[k]).cpu().numpy()), k
+        rows = np.sort(rng.choice(meshes[k].ne, 32, replace=False))
+        dof = (3 * rows[:, None] + np.arange(3)).ravel()
+        ref = oracle.rows_matvec(meshes[k], YOUNG, NU, rows, Xs[k][:4].cpu().numpy())
+        err = colerr(got[:4, dof], ref)
+        print(f"mesh {k} ({meshes[k].ne} elements): sampled FP32 error {err:.2e}", flush=True)
+        assert err <= 1e-5, (k, err)
+    assert all(np.array_equal(Ys[k].cpu().numpy(), first[k]) for k in range(64))

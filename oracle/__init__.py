@@ -14,6 +14,12 @@ What it computes (paper Sec. 3.1, "Solid mechanics" and "Final system"):
     carried as identity rows and columns;
   * the closed-form penny-shaped crack opening under uniform pressure and
     uniform shear slip used to pin the oracle itself.
+
+Submodules: `learned` (the learned correction of the block preconditioner,
+its loss and gradient), `interface` (the interface elasto-plastic law and
+its consistent tangent, Sec. 2.2), `newton` (one implicit step of the
+mechanical problem, Sec. 3.1.1) and `timestep` (the truncation-error
+estimate and step-size controller, Sec. 3.4).
 """
 from __future__ import annotations
 

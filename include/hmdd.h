@@ -470,7 +470,10 @@ void hm_newton_opts_default(hm_newton_opts* opts);
  *   d_dT0     [N][3] increment of the in-situ effective traction, or NULL
  *   d_dpress  [N] pore-pressure increment at the collocation points, or NULL
  *   d_eta_dt  [N][3] diagonal of eta/dt, or NULL
- *   d_dd_prev [N][3] previous step's DD increment, or NULL (zero)
+ *   d_dd_prev [N][3] dt times the previous step's DD rate, i.e. its increment
+ *             rescaled to this step (increment_prev * dt / dt_prev), so that
+ *             eta (dd - dd_prev) / dt = eta (dd / dt - increment_prev / dt_prev),
+ *             the backward-Euler rate change; NULL for zero (first step)
  *   d_dd      [N][3] in: initial guess; out: the returned increment
  *   d_t_new, d_dp_new, d_chi_new  [N][3] the interface state at d_dd
  * All device FP64 arrays, element-major in local frames; the operator is

@@ -63,8 +63,10 @@ def _load():
         lib.orc_assemble.restype = i32
         lib.orc_rows_matvec.argtypes = [i32, i64, P, i64, P, d, d, i64, P, i32, P, P, i32, d]
         lib.orc_rows_matvec.restype = i32
-        lib.orc_pk_stress.argtypes = [d, d, P, i32, P, P, d, P]
-        lib.orc_pk_stress.restype = None
+        lib.orc_grid_table.argtypes = [d, d, i32, i32, d, d, P]
+        lib.orc_grid_table.restype = None
+        lib.orc_grid_matvec.argtypes = [i32, i32, P, i32, P, P]
+        lib.orc_grid_matvec.restype = i32
         _lib = lib
     return _lib
 
@@ -117,14 +119,6 @@ def pk_block(young, nu, x_recv, frame_recv, verts_src, frame_src, rtol=PK_TOL) -
     return out.reshape(3, 3)
 
 
-def pk_stress(young, nu, x, verts_src, b_global) -> np.ndarray:
-    """Stress tensor at x (global frame) for a uniform global DD b on a polygon."""
-    out = np.empty(9)
-    xx, v, b = _f64(x), _f64(verts_src), _f64(b_global)
-    _load().orc_pk_stress(young, nu, _p(xx), v.shape[0], _p(v), _p(b), PK_TOL, _p(out))
-    return out.reshape(3, 3)
-
-
 def blocks(mesh, young, nu, rows, cols, method: int = 0, tol: float = PK_TOL) -> np.ndarray:
     """Exact coefficient blocks out[r, c, a, b] = E_{rows[r], cols[c]}^{ab}.
 
@@ -163,6 +157,52 @@ def rows_matvec(mesh, young, nu, rows, X, method: int = 0, tol: float = PK_TOL) 
     if st != 0:
         raise ValueError(f"oracle rows failed ({st})")
     return Y
+
+
+def grid_table(young, nu, nx, ny, h=1.0, hy=None) -> np.ndarray:
+    """Coefficient table of a uniform grid of nx x ny rectangles (h x hy)
+    sharing one plane and frame, element e = i + nx j: out[dj + ny - 1,
+    di + nx - 1] = E between a receiver and the source offset by (di, dj)
+    cells (coplanar closed form), shape [2 ny - 1, 2 nx - 1, 3, 3]."""
+    hy = h if hy is None else hy
+    out = np.empty((2 * ny - 1, 2 * nx - 1, 3, 3))
+    _load().orc_grid_table(young, nu, nx, ny, h, hy, _p(out))
+    return out
+
+
+def grid_matvec(table, nx, ny, X) -> np.ndarray:
+    """Exact Y = E X on a uniform grid by direct summation over every pair of
+    the offset table (OpenMP over receivers); X is [nrhs, 3 nx ny]."""
+    X = _f64(np.atleast_2d(X))
+    T = _f64(table)
+    if T.shape != (2 * ny - 1, 2 * nx - 1, 3, 3) or X.shape[1] != 3 * nx * ny:
+        raise ValueError("grid_matvec: shapes do not match the grid")
+    Y = np.empty_like(X)
+    st = _load().orc_grid_matvec(nx, ny, _p(T), X.shape[0], _p(X), _p(Y))
+    if st != 0:
+        raise MemoryError("grid_matvec: allocation failed")
+    return Y
+
+
+def grid_matvec_fft(table, nx, ny, X) -> np.ndarray:
+    """The same product by circulant embedding: the offset table is laid on a
+    (2 ny) x (2 nx) periodic grid (offset d at index -d mod size), so the
+    Toeplitz sum is a circular convolution, taken with 2-D FFTs (numpy).  An
+    independent route to grid_matvec."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    nrhs = X.shape[0]
+    py, px = 2 * ny, 2 * nx
+    dj = np.arange(-(ny - 1), ny)
+    di = np.arange(-(nx - 1), nx)
+    K = np.zeros((3, 3, py, px))
+    K[:, :, (-dj[:, None]) % py, (-di[None, :]) % px] = np.asarray(table).transpose(2, 3, 0, 1)
+    Kf = np.fft.rfft2(K)
+    Xg = np.zeros((nrhs, 3, py, px))
+    Xg[:, :, :ny, :nx] = X.reshape(nrhs, ny, nx, 3).transpose(0, 3, 1, 2)
+    Xf = np.fft.rfft2(Xg)
+    Yf = np.einsum("abyx,cbyx->cayx", Kf, Xf)
+    Yg = np.fft.irfft2(Yf, s=(py, px))[:, :, :ny, :nx]
+    return Yg.transpose(0, 2, 3, 1).reshape(nrhs, 3 * nx * ny)
 
 
 def matvec(E: np.ndarray, X: np.ndarray) -> np.ndarray:

@@ -44,8 +44,6 @@ static void cross3(const double* a, const double* b, double* c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 static double norm3(const double* a) { return sqrt(dot3(a, a)); }
-/* Levi-Civita symbol for indices in {0,1,2} */
-static int levi(int i, int j, int k) { return ((i - j) * (j - k) * (k - i)) / 2; }
 
 /* ------------------------------------------------------------------ */
 /* element geometry                                                    */
@@ -160,6 +158,15 @@ void orc_coplanar_rect_block(double young, double nu, double xi1, double xi2, do
  * the tests check entry by entry.
  */
 
+/*
+ * The sums over the Levi-Civita symbol contract to cross products:
+ *   sum_{i,m} b_m eps_ima D_i = (D x b)_a and sum_{m,k} b_m eps_imk e_k = (b x e)_i,
+ * so with D = grad(lap R) = -2 r / R^3 and w = b x e:
+ *   sig_ac = c1 [(D x b)_a e_c + (D x b)_c e_a]
+ *          + c3 [-(w_a r_c + w_c r_a + delta_ac (w.r)) / R^3 + 3 (w.r) r_a r_c / R^5
+ *                - delta_ac (w.D)],
+ * c1 = -G / (8 pi), c3 = -G / (4 pi (1 - nu)).
+ */
 static void pk_integrand(double G, double nu, const double* x, const double* xp, const double* e,
                          const double* b, double sig[3][3])
 {
@@ -170,21 +177,15 @@ static void pk_integrand(double G, double nu, const double* x, const double* xp,
     for (int i = 0; i < 3; ++i) D1[i] = -2.0 * r[i] / R3;
     double c1 = -G / (8.0 * ORC_PI);
     double c3 = -G / (4.0 * ORC_PI * (1.0 - nu));
+    double Db[3], w[3];
+    cross3(D1, b, Db);
+    cross3(b, e, w);
+    double wr = dot3(w, r), wD = dot3(w, D1);
     for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) {
-            double s = 0.0;
-            for (int i = 0; i < 3; ++i)
-                for (int m = 0; m < 3; ++m) {
-                    s += c1 * b[m] * levi(i, m, a) * D1[i] * e[c];
-                    s += c1 * b[m] * levi(i, m, c) * D1[i] * e[a];
-                    for (int k = 0; k < 3; ++k) {
-                        if (levi(i, m, k) == 0) continue;
-                        double D3 = -((i == a) * r[c] + (i == c) * r[a] + (a == c) * r[i]) / R3
-                                    + 3.0 * r[i] * r[a] * r[c] / R5;
-                        s += c3 * b[m] * levi(i, m, k) * (D3 - (a == c) * D1[i]) * e[k];
-                    }
-                }
-            sig[a][c] = s;
+            double dac = (a == c) ? 1.0 : 0.0;
+            double t3 = -(w[a] * r[c] + w[c] * r[a] + dac * wr) / R3 + 3.0 * wr * r[a] * r[c] / R5 - dac * wD;
+            sig[a][c] = c1 * (Db[a] * e[c] + Db[c] * e[a]) + c3 * t3;
         }
 }
 
@@ -445,34 +446,68 @@ int orc_rows_matvec(int nvpe, int64_t nv, const double* xyz, int64_t ne, const i
     return 0;
 }
 
-/* stress tensor (global components) at an arbitrary point x from a uniform
- * global-frame DD b on one polygon: used for field checks (closed surfaces). */
-void orc_pk_stress(double young, double nu, const double* x, int nvs, const double* vsrc, const double* b,
-                   double rtol, double* sig_out /* [3][3] */)
+/* ------------------------------------------------------------------ */
+/* (3) uniform grids: exact product by Toeplitz summation              */
+/* ------------------------------------------------------------------ */
+/*
+ * A uniform grid of nx x ny rectangles of sides h (first in-plane axis) and
+ * hy, all in one plane and one frame, element e = i + nx j centred at
+ * (i h, j hy) in that frame.  The coefficient between receiver (i, j) and
+ * source (k, l) depends only on the offset (k - i, l - j): it is the coplanar
+ * closed form (1) for the source rectangle [di h - h/2, di h + h/2] x
+ * [dj hy - hy/2, dj hy + hy/2] seen from the receiver centroid.  So the whole
+ * operator is the table of the (2 nx - 1)(2 ny - 1) offsets, and E X is a
+ * direct sum over all (receiver, source) pairs of that table.
+ *
+ * table[(dj + ny - 1)][(di + nx - 1)][a][b], di in [-(nx-1), nx-1], dj likewise.
+ */
+void orc_grid_table(double young, double nu, int nx, int ny, double h, double hy, double* table)
 {
-    gl_init();
-    double G = young / (2.0 * (1.0 + nu));
-    /* use the identity frames so that out9 holds sig.e_c projected on e_a:
-       receiver frame = identity rows would give traction on the plane of
-       normal e3 only; instead integrate the full tensor directly. */
-    for (int k = 0; k < 9; ++k) sig_out[k] = 0.0;
-    for (int q = 0; q < nvs; ++q) {
-        const double* a = vsrc + 3 * q;
-        const double* bb = vsrc + 3 * ((q + 1) % nvs);
-        double d[3] = {bb[0] - a[0], bb[1] - a[1], bb[2] - a[2]};
-        double L = norm3(d), e[3] = {d[0] / L, d[1] / L, d[2] / L};
-        /* fixed high-order composite rule: 64 panels of GL_N points */
-        const int P = 64;
-        for (int p = 0; p < P; ++p) {
-            double s0 = L * p / P, s1 = L * (p + 1) / P, mid = 0.5 * (s0 + s1), half = 0.5 * (s1 - s0);
-            for (int i = 0; i < GL_N; ++i) {
-                double xp[3], sig[3][3], s = mid + half * gl_x[i];
-                for (int k = 0; k < 3; ++k) xp[k] = a[k] + s * e[k];
-                pk_integrand(G, nu, x, xp, e, b, sig);
-                for (int u = 0; u < 3; ++u)
-                    for (int w = 0; w < 3; ++w) sig_out[3 * u + w] += half * gl_w[i] * sig[u][w];
-            }
-        }
+    const int64_t wx = 2 * (int64_t)nx - 1, wy = 2 * (int64_t)ny - 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < wx * wy; ++q) {
+        const double di = (double)(q % wx - (nx - 1)), dj = (double)(q / wx - (ny - 1));
+        orc_coplanar_rect_block(young, nu, di * h - 0.5 * h, di * h + 0.5 * h, dj * hy - 0.5 * hy,
+                                dj * hy + 0.5 * hy, table + 9 * q);
     }
-    (void)rtol;
+}
+
+/*
+ * Y[c][3 e + a] = sum over sources s = k + nx l and b of
+ *     table[l - j][k - i][a][b] X[c][3 s + b],  receiver e = i + nx j.
+ * X, Y are [nrhs][3 nx ny].  Direct summation over every pair, one receiver
+ * per loop iteration (rows in parallel).
+ */
+int orc_grid_matvec(int nx, int ny, const double* table, int nrhs, const double* X, double* Y)
+{
+    const int64_t ne = (int64_t)nx * ny, wx = 2 * (int64_t)nx - 1;
+    /* X transposed to [element][column][component] so each source is contiguous */
+    double* xt = (double*)malloc(sizeof(double) * 3 * (size_t)nrhs * ne);
+    if (!xt) return -2;
+    for (int c = 0; c < nrhs; ++c)
+        for (int64_t s = 0; s < ne; ++s)
+            for (int b = 0; b < 3; ++b) xt[(s * nrhs + c) * 3 + b] = X[(size_t)c * 3 * ne + 3 * s + b];
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t i = e % nx, j = e / nx;
+        double* acc = (double*)calloc((size_t)3 * nrhs, sizeof(double));
+        if (!acc) {
+            fail = 1;
+            continue;
+        }
+        for (int64_t l = 0; l < ny; ++l)
+            for (int64_t k = 0; k < nx; ++k) {
+                const double* K = table + 9 * ((l - j + ny - 1) * wx + (k - i + nx - 1));
+                const double* x = xt + (l * nx + k) * nrhs * 3;
+                for (int c = 0; c < nrhs; ++c)
+                    for (int a = 0; a < 3; ++a)
+                        acc[3 * c + a] += K[3 * a] * x[3 * c] + K[3 * a + 1] * x[3 * c + 1] + K[3 * a + 2] * x[3 * c + 2];
+            }
+        for (int c = 0; c < nrhs; ++c)
+            for (int a = 0; a < 3; ++a) Y[(size_t)c * 3 * ne + 3 * e + a] = acc[3 * c + a];
+        free(acc);
+    }
+    free(xt);
+    return fail ? -2 : 0;
 }

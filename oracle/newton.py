@@ -13,7 +13,9 @@ dT'o the increment of the in-situ effective traction, dT'(dd) the increment
 of the interface effective traction given by the interface law from the
 state at the start of the step, I_n dp the pore-pressure increment at the
 collocation points acting along each element normal, eta/dt the
-quasi-dynamic term and dd_prev the previous step's increment.  Newton's
+quasi-dynamic term and dd_prev the previous step's increment rescaled to
+this step (times dt / dt_prev), so that eta (dd - dd_prev) / dt is eta
+times the backward-Euler change of rate.  Newton's
 method with the mechanical Jacobian J = E - eta/dt - C^ep:
 
     dd <- dd - J^-1 r(dd),

@@ -214,6 +214,20 @@ def _ld(t):
     return t.shape[1] if t.shape[0] == 1 else t.stride(0)
 
 
+def _shape(t, shape, name):
+    """Raise HMError unless tensor t has exactly the given shape (checked
+    before anything is launched: the C ABI cannot see buffer sizes)."""
+    if tuple(t.shape) != tuple(shape):
+        raise HMError(HM_EINVAL, f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _vecs(t, n, name, rows=None):
+    """A [rows, n] block of vectors (rows contiguous) with n = 3N."""
+    if t.dim() != 2 or t.shape[1] != n or (rows is not None and t.shape[0] != rows):
+        want = f"[{rows if rows is not None else 'nrhs'}, {n}]"
+        raise HMError(HM_EINVAL, f"{name}: expected shape {want}, got {tuple(t.shape)}")
+
+
 def _dev_ptr(t, dtype):
     import torch
 
@@ -326,6 +340,8 @@ class Operator:
             Y = torch.empty_like(X2)
         elif squeeze:
             Y = Y.reshape(1, -1)
+        _vecs(X2, self.ndof, "X")
+        _vecs(Y, self.ndof, "Y", X2.shape[0])
         flags = ((HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
                  | (HM_APPLY_ACCUMULATE if accumulate else 0))
         _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), _ld(X2),
@@ -338,6 +354,8 @@ class Operator:
         """apply() with per-stage durations (ms) from HIP events on the stream."""
         import torch
 
+        _vecs(X, self.ndof, "X")
+        _vecs(Y, self.ndof, "Y", X.shape[0])
         flags = (HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
         ms = (ctypes.c_double * 5)()
         _check(lib().hm_operator_apply_timed(self._h, X.shape[0], _dev_ptr(X, torch.float64), _ld(X),
@@ -348,10 +366,16 @@ class Operator:
         """A11 = E - D on active elements (D: CUDA float64 [N,3,3]; mask: CUDA uint8 [N])."""
         import torch
 
-        dp = _dev_ptr(D.contiguous(), torch.float64) if D is not None else None
-        mp = _dev_ptr(mask.contiguous(), torch.uint8) if mask is not None else None
-        self._keep = (D, mask)
+        Dc = D.contiguous() if D is not None else None
+        Mc = mask.contiguous() if mask is not None else None
+        if Dc is not None and Dc.numel() != 9 * self.ne:
+            raise HMError(HM_EINVAL, f"D: expected {self.ne} x 3 x 3 entries, got {tuple(D.shape)}")
+        if Mc is not None and Mc.numel() != self.ne:
+            raise HMError(HM_EINVAL, f"mask: expected {self.ne} entries, got {tuple(mask.shape)}")
+        dp = _dev_ptr(Dc, torch.float64) if Dc is not None else None
+        mp = _dev_ptr(Mc, torch.uint8) if Mc is not None else None
         _check(lib().hm_tangent_set(self._h, dp, mp, _stream(stream)))
+        del Dc, Mc  # the library copied them (the call synchronises the stream)
 
     def solve(self, B, stream=None, raise_on_notconv=True, **opts):
         """Solve A11 X = B (B: CUDA float64 [nrhs, 3N]); returns (X, report dict)."""
@@ -359,6 +383,7 @@ class Operator:
 
         squeeze = B.dim() == 1
         B2 = (B.reshape(1, -1) if squeeze else B).contiguous()
+        _vecs(B2, self.ndof, "B")
         X = torch.empty_like(B2)
         o = solve_opts(**opts)
         rep = SolveReport()
@@ -395,15 +420,27 @@ class Operator:
             for j, (name, _) in enumerate(InterfaceMaterial._fields_):
                 setattr(arr[i], name, float(mats[i, j]))
         f64 = torch.float64
-        N = t.shape[0]
+        N = self.ne
+        for name, x in (("t", t), ("dp", dp), ("chi", chi), ("dT0", dT0), ("eta_dt", eta_dt),
+                        ("dd_prev", dd_prev), ("dd", dd)):
+            if x is not None:
+                _shape(x, (N, 3), name)
+        for name, x in (("dpress", dpress), ("mat_id", mat_id)):
+            if x is not None:
+                _shape(x, (N,), name)
         dd = torch.zeros(N, 3, dtype=f64, device=t.device) if dd is None else dd.clone()
         outs = [torch.empty(N, 3, dtype=f64, device=t.device) for _ in range(3)]
-        opt = lambda x, dt=f64: _dev_ptr(x.contiguous(), dt) if x is not None else None
+        # contiguous copies stay referenced here until the call returns, so
+        # torch's allocator cannot hand their memory to the next copy
+        keep = [x.contiguous() if x is not None else None
+                for x in (mat_id, t, dp, chi, dT0, dpress, eta_dt, dd_prev)]
+        ptrs = [_dev_ptr(x, torch.int32 if i == 0 else f64) if x is not None else None
+                for i, x in enumerate(keep)]
         rep = NewtonReport()
-        st = lib().hm_newton_step(self._h, mats.shape[0], ctypes.cast(arr, ctypes.c_void_p),
-                                  opt(mat_id, torch.int32), opt(t), opt(dp), opt(chi), opt(dT0), opt(dpress),
-                                  opt(eta_dt), opt(dd_prev), _dev_ptr(dd, f64), *[_dev_ptr(x, f64) for x in outs],
+        st = lib().hm_newton_step(self._h, mats.shape[0], ctypes.cast(arr, ctypes.c_void_p), *ptrs,
+                                  _dev_ptr(dd, f64), *[_dev_ptr(x, f64) for x in outs],
                                   ctypes.byref(o), ctypes.byref(rep), _stream(stream))
+        del keep
         if st != HM_ENOTCONV or raise_on_notconv:
             _check(st)
         return dd, outs[0], outs[1], outs[2], rep.as_dict()
@@ -412,6 +449,7 @@ class Operator:
         """Z = M^-1 R (R: CUDA float64 [nrhs, 3N]) with the solve's preconditioner."""
         import torch
 
+        _vecs(R, self.ndof, "R")
         Z = torch.empty_like(R)
         _check(lib().hm_precond_apply(self._h, precond, R.shape[0], _dev_ptr(R, torch.float64), _ld(R),
                                       _dev_ptr(Z, torch.float64), _ld(Z), _stream(stream)))
@@ -443,8 +481,12 @@ class Batch:
         import torch
 
         n = len(self.ops)
-        assert len(Xs) == n and len(Ys) == n
+        if len(Xs) != n or len(Ys) != n:
+            raise HMError(HM_EINVAL, f"expected {n} input and output blocks")
         nrhs = Xs[0].shape[0]
+        for k, (op, x, y) in enumerate(zip(self.ops, Xs, Ys)):
+            _vecs(x, op.ndof, f"Xs[{k}]", nrhs)
+            _vecs(y, op.ndof, f"Ys[{k}]", nrhs)
         xp = (ctypes.c_void_p * n)(*[_dev_ptr(x, torch.float64).value for x in Xs])
         yp = (ctypes.c_void_p * n)(*[_dev_ptr(y, torch.float64).value for y in Ys])
         ldx = (ctypes.c_int64 * n)(*[_ld(x) for x in Xs])
@@ -503,6 +545,8 @@ class Learned:
         """(loss, dL/dtheta) at the current parameters; B, X CUDA float64 [ns, 3N]."""
         import torch
 
+        _vecs(B, op.ndof, "B")
+        _vecs(X, op.ndof, "X", B.shape[0])
         g = np.empty(self.num_params(), np.float32)
         loss = ctypes.c_double()
         _check(lib().hm_learned_loss_grad(self._h, op._h, B.shape[0], _dev_ptr(B, torch.float64), _ld(B),
@@ -514,6 +558,8 @@ class Learned:
         """Adam steps on the samples (B, X) of op's current tangent; returns the loss history."""
         import torch
 
+        _vecs(B, op.ndof, "B")
+        _vecs(X, op.ndof, "X", B.shape[0])
         hist = np.zeros(steps)
         _check(lib().hm_learned_train(self._h, op._h, B.shape[0], _dev_ptr(B, torch.float64), _ld(B),
                                       _dev_ptr(X, torch.float64), _ld(X), steps, batch, lr,
@@ -578,9 +624,20 @@ def interface_update(mats, dd, t, dp, chi, mat_id=None, eta_dt=None, want_D=Fals
     if want_D:
         o.setdefault("D", torch.empty(N, 3, 3, dtype=torch.float64, device=dev))
     f64 = torch.float64
+    for name, x in (("dd", dd), ("t", t), ("dp", dp), ("chi", chi), ("eta_dt", eta_dt), ("out t", o["t"]),
+                    ("out dp", o["dp"]), ("out chi", o["chi"])):
+        if x is not None:
+            _shape(x, (N, 3), name)
+    for name, x in (("mat_id", mat_id), ("out mode", o["mode"])):
+        if x is not None:
+            _shape(x, (N,), name)
+    _shape(o["cep"], (N, 3, 3), "out cep")
+    if want_D:
+        _shape(o["D"], (N, 3, 3), "out D")
+    arrays = [dd, t, dp, chi, mat_id, eta_dt, o["t"], o["dp"], o["chi"], o["cep"], o["mode"]]
+    if any(x is not None and not x.is_contiguous() for x in arrays + [o.get("D")]):
+        raise HMError(HM_EINVAL, "interface arrays must be contiguous")
     pin = [_dev_ptr(x, f64) for x in (dd, t, dp, chi)]
-    if any(not x.is_contiguous() for x in (dd, t, dp, chi)):
-        raise HMError(HM_EINVAL, "state arrays must be contiguous")
     mid = _dev_ptr(mat_id, torch.int32) if mat_id is not None else None
     eta = _dev_ptr(eta_dt, f64) if eta_dt is not None else None
     Dp = _dev_ptr(o["D"], f64) if want_D else None
@@ -610,9 +667,16 @@ def lte_estimate(dd, dt, dd_prev, dt_prev, total, stream=None):
     import torch
 
     f64 = torch.float64
+    for name, x in (("dd_prev", dd_prev), ("total", total)):
+        if x is not None and x.numel() != dd.numel():
+            raise HMError(HM_EINVAL, f"{name}: expected {dd.numel()} entries, got {x.numel()}")
+    # the contiguous copies are bound to names that live until the call returns
+    ddc = dd.contiguous()
+    prevc = dd_prev.contiguous() if dd_prev is not None else None
+    totc = total.contiguous()
     e = ctypes.c_double()
-    _check(lib().hm_lte_estimate(dd.numel(), _dev_ptr(dd.contiguous(), f64), float(dt),
-                                 _dev_ptr(dd_prev.contiguous(), f64) if dd_prev is not None else None,
-                                 float(dt_prev), _dev_ptr(total.contiguous(), f64), ctypes.byref(e),
-                                 _stream(stream)))
+    _check(lib().hm_lte_estimate(ddc.numel(), _dev_ptr(ddc, f64), float(dt),
+                                 _dev_ptr(prevc, f64) if prevc is not None else None,
+                                 float(dt_prev), _dev_ptr(totc, f64), ctypes.byref(e), _stream(stream)))
+    del ddc, prevc, totc
     return e.value

@@ -1,0 +1,61 @@
+"""GPU parity against the exact operator at every row of the primary
+configuration.
+
+The 256 x 256 planar fault (65,536 squares, 196,608 DOF) is a uniform grid:
+its exact collocation operator is a Toeplitz sum over the offset table,
+which the oracle evaluates by circulant embedding and FFTs (pinned equal to
+the direct Toeplitz sum and to the dense matrix in the CPU tests).  The
+16-column product of the benchmark is compared with it entry by entry in
+the three forms:
+  * FP64 H-matrix (the reference copy), ACA 1e-6: per-column bar 1e-6;
+  * FP32 near and far field, FP32 accumulation: bar 1e-5;
+  * FP32 near, BF16 far (hi/lo split in-vector), FP32 accumulation, FP64
+    self blocks: bar 5e-3.
+Per column: ||Y - Y_ref||_2 / ||Y_ref||_2; max entry error relative to the
+largest |Y_ref| of its column is printed beside it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import rhs_columns, square_fault
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+YOUNG, NU = 30e9, 0.25
+
+
+def _errors(Y, R):
+    col = np.array([np.linalg.norm(Y[c] - R[c]) / np.linalg.norm(R[c]) for c in range(R.shape[0])])
+    ent = np.array([np.abs(Y[c] - R[c]).max() / np.abs(R[c]).max() for c in range(R.shape[0])])
+    return col, ent
+
+
+def test_primary_configuration_full_product_exact():
+    import paper_2605_14397_amd as hm
+
+    assert torch.cuda.is_available()
+    n = 256
+    m = square_fault(n)
+    X = rhs_columns(m.ndof, 16, 2001)
+    ref = oracle.grid_matvec_fft(oracle.grid_table(YOUNG, NU, n, n), n, n, X)
+    Xd = torch.as_tensor(X, device="cuda")
+    mesh = hm.Mesh.from_workload(m)
+    op32 = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
+                       far_prec=hm.HM_F32, keep_f64_reference=1)
+    y64 = op32.apply(Xd, reference=True).cpu().numpy()
+    y32 = op32.apply(Xd).cpu().numpy()
+    del op32
+    opbf = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
+                       far_prec=hm.HM_BF16)
+    ybf = opbf.apply(Xd).cpu().numpy()
+    results = {}
+    for name, y, bar in (("fp64", y64, 1e-6), ("fp32", y32, 1e-5), ("fp32_near_bf16_far", ybf, 5e-3)):
+        col, ent = _errors(y, ref)
+        results[name] = (col.max(), ent.max())
+        print(f"256x256 {name}: per-column rel err max {col.max():.3e} (min {col.min():.3e}), "
+              f"max entry err {ent.max():.3e}", flush=True)
+        assert col.max() <= bar, (name, col)
+    # the forms order as their precisions do
+    assert results["fp64"][0] < results["fp32"][0] < results["fp32_near_bf16_far"][0]

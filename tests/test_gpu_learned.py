@@ -372,3 +372,20 @@ def test_full_size_sampled_apply_matches_oracle():
         corr = np.linalg.norm(Zo[c, rows_o] - Zb[c, rows_o]) / np.linalg.norm(Zo[c, rows_o])
         print(f"column {c}: sampled error {err:.2e}, correction share {corr:.2e}", flush=True)
         assert err <= 1e-6 and corr > 1e-2
+    # a learned-form solve at this size (a fresh network: the library's own
+    # initialisation), judged by the exact operator: b - (E x - D x) on 64
+    # sampled rows, exact rows by the oracle's Peach-Koehler quadrature
+    net2 = hm.Learned(hidden=Hf, neighbors=Kf, seed=2)
+    net2.attach(op)
+    b = np.random.default_rng(33).standard_normal((1, m.ndof)) * 1e6
+    x, rep = op.solve(cuda(b), precond=hm.HM_PC_LEARNED, restart=50, rtol=1e-8, max_iter=2000)
+    assert rep["converged"] and rep["fallback"] == hm.HM_FALLBACK_NONE
+    assert rep["precond_used"] == hm.HM_PC_LEARNED and rep["rel_residual"] <= 1e-8
+    xh = x.cpu().numpy()
+    rows = np.sort(np.random.default_rng(34).choice(m.ne, 64, replace=False))
+    dof = (3 * rows[:, None] + np.arange(3)).ravel()
+    Ax = oracle.rows_matvec(m, YOUNG, NU, rows, xh, method=1)[0] - np.einsum(
+        "eab,eb->ea", D[rows], xh[0].reshape(-1, 3)[rows]).ravel()
+    r_exact = np.linalg.norm(b[0, dof] - Ax) / np.linalg.norm(b[0, dof])
+    print(f"learned-form solve: {rep['iterations']} its; exact residual on 64 rows {r_exact:.2e}", flush=True)
+    assert r_exact <= 1e-5

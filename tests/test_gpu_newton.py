@@ -227,3 +227,47 @@ def test_hf_fault_full_size_step_sampled_against_the_oracle():
     print("sampled rows", rows.tolist(), "modes", mode.tolist(), "max |r|", np.abs(r).max(), "bound", bound,
           "final H-residual", rep["residual"][-1], flush=True)
     assert np.abs(r).max() <= bound
+
+
+def test_non_contiguous_inputs_and_shape_errors():
+    """Non-contiguous views of the state arrays give the same Newton step and
+    truncation-error estimate as contiguous copies (the binding keeps its
+    own contiguous copies alive through the call), and arrays of the wrong
+    shape are rejected with HMError before anything is launched."""
+    hm = _hm()
+    m, mats, t_n, dpress, eta_dt = _weakening_case()
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=16, aca_tol=1e-12)
+    N = m.ne
+
+    def strided(a):
+        # the same values as a [N, 3] view with a row stride of 5
+        w = torch.zeros(N, 5, dtype=torch.float64, device="cuda")
+        w[:, 1:4] = cuda(a)
+        return w[:, 1:4]
+
+    z = np.zeros_like(t_n)
+    prev = np.random.default_rng(5).standard_normal((N, 3)) * 1e-5
+    ref = op.newton_step(mats, cuda(t_n), cuda(z), cuda(z), dpress=cuda(dpress), eta_dt=cuda(eta_dt),
+                         dd_prev=cuda(prev))
+    got = op.newton_step(mats, strided(t_n), strided(z), strided(z), dpress=cuda(dpress), eta_dt=strided(eta_dt),
+                         dd_prev=strided(prev))
+    assert not strided(t_n).is_contiguous()
+    for a, b in zip(ref[:4], got[:4]):
+        assert torch.equal(a, b)
+    dd = ref[0]
+    e_ref = hm.lte_estimate(dd.reshape(-1), 0.5, cuda(prev).reshape(-1), 0.25, dd.reshape(-1) + 1.0)
+    e_got = hm.lte_estimate(strided(dd.cpu().numpy()), 0.5, strided(prev), 0.25, strided(dd.cpu().numpy() + 1.0))
+    assert e_got == e_ref
+    # shapes checked on the host
+    X = torch.zeros(16, 3 * N, dtype=torch.float64, device="cuda")
+    for bad in (lambda: op.apply(X, Y=torch.empty(1, 3 * N, dtype=torch.float64, device="cuda")),
+                lambda: op.apply(X[:, :-3]),
+                lambda: op.set_tangent(torch.zeros(N - 1, 3, 3, dtype=torch.float64, device="cuda")),
+                lambda: op.set_tangent(None, torch.ones(N + 1, dtype=torch.uint8, device="cuda")),
+                lambda: op.newton_step(mats, cuda(t_n[:-1]), cuda(z[:-1]), cuda(z[:-1])),
+                lambda: op.solve(X[:, :-3]),
+                lambda: op.precond_apply(X[:2, :6]),
+                lambda: hm.lte_estimate(dd.reshape(-1), 0.5, cuda(prev[:-1]).reshape(-1), 0.25, dd.reshape(-1))):
+        with pytest.raises(hm.HMError) as ei:
+            bad()
+        assert ei.value.status == hm.HM_EINVAL

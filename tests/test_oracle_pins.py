@@ -301,3 +301,59 @@ def test_frames_follow_stated_convention(oracle_lib):
     cent, fr, area = oracle.frames(m)
     assert np.allclose(fr[0], np.eye(3))
     assert np.allclose(area, 1.0) and np.allclose(cent[0], [0.5, 0.5, 0.0])
+
+
+def test_grid_toeplitz_product_equals_dense(oracle_lib):
+    # The uniform-grid product (offset table + direct summation) against the
+    # dense oracle: square grid, and a ragged grid of non-square rectangles
+    # (nx != ny, h != hy), which catches a swapped (di, dj) or a transposed
+    # offset sign; and against the PK quadrature alone (method 1), an
+    # independent derivation of every table entry.
+    from workloads import rhs_columns
+
+    for nx, ny, h, hy in ((32, 32, 1.0, 1.0), (13, 7, 0.5, 1.3)):
+        m = rect_grid(nx, ny, h, hy)
+        X = rhs_columns(m.ndof, 3, 11)
+        ref = oracle.matvec(oracle.dense(m, YOUNG, NU), X)
+        T = oracle.grid_table(YOUNG, NU, nx, ny, h, hy)
+        Y = oracle.grid_matvec(T, nx, ny, X)
+        assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
+    m = rect_grid(8, 6, 1.0, 0.6)
+    X = rhs_columns(m.ndof, 2, 12)
+    ref = oracle.matvec(oracle.dense(m, YOUNG, NU, method=1), X)
+    Y = oracle.grid_matvec(oracle.grid_table(YOUNG, NU, 8, 6, 1.0, 0.6), 8, 6, X)
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_grid_fft_product_equals_direct_sum(oracle_lib):
+    # circulant embedding + FFT against the direct Toeplitz sum, ragged sizes
+    from workloads import rhs_columns
+
+    for nx, ny, hy in ((40, 23, 1.0), (5, 17, 2.0), (1, 9, 1.0)):
+        T = oracle.grid_table(YOUNG, NU, nx, ny, 1.0, hy)
+        X = rhs_columns(3 * nx * ny, 3, 13)
+        Yd = oracle.grid_matvec(T, nx, ny, X)
+        Yf = oracle.grid_matvec_fft(T, nx, ny, X)
+        assert np.abs(Yf - Yd).max() <= 1e-12 * np.abs(Yd).max()
+
+
+def test_grid_product_symmetric_and_planted_mistakes_fail(oracle_lib):
+    # x.(E y) = y.(E x) on a grid of identical elements (E symmetric), and a
+    # table with a mirrored offset axis (flips the odd s1-s2 coupling) or
+    # with the two shear components swapped (h != hy) is caught by the dense
+    # comparison above on the ragged grid
+    from workloads import rhs_columns
+
+    nx, ny = 11, 6
+    T = oracle.grid_table(YOUNG, NU, nx, ny, 1.0, 0.7)
+    x, y = rhs_columns(3 * nx * ny, 2, 14)
+    Ex = oracle.grid_matvec(T, nx, ny, x)[0]
+    Ey = oracle.grid_matvec(T, nx, ny, y)[0]
+    assert abs(x @ Ey - y @ Ex) <= 1e-13 * abs(x @ Ey)
+    m = rect_grid(nx, ny, 1.0, 0.7)
+    ref = oracle.matvec(oracle.dense(m, YOUNG, NU), x)
+    swapped = T.copy()
+    swapped[..., 0, 0], swapped[..., 1, 1] = T[..., 1, 1], T[..., 0, 0]
+    for bad in (T[:, ::-1].copy(), swapped):
+        Yb = oracle.grid_matvec(bad, nx, ny, x)
+        assert np.abs(Yb - ref).max() > 1e-6 * np.abs(ref).max()

@@ -179,6 +179,8 @@ typedef struct {
     int64_t rank_sum;                  /* sum of ranks over low-rank factorisations (stored) */
     int64_t rank_sum_aca;              /* the same before recompression */
     double recompress_ms;
+    int64_t apply_workspace_bytes;     /* device workspace of one product of the main form (16 columns): each
+                                          stream's own, or the part of the no-allocation scratch it needs */
 } hm_op_stats;
 
 hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
@@ -193,8 +195,12 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
  * HM_APPLY_ACCUMULATE) for nrhs vectors
  * (1 <= nrhs <= 16).  d_X [nrhs][ldx], d_Y [nrhs][ldy] float64 (device),
  * ldx, ldy >= 3N; d_X and d_Y must not overlap.  The product runs in the
- * operator's precisions and is returned in FP64.  Not reentrant on one
- * operator: concurrent applies of the same operator must be serialised.
+ * operator's precisions and is returned in FP64.  Reentrant across
+ * streams: the operator keeps one workspace per stream (its in-vector and
+ * partial-product buffers, hm_op_stats.apply_workspace_bytes), allocated by
+ * the first product on that stream, so products of one operator on
+ * different streams (and host threads) may overlap; products on one stream
+ * run in order.  The first product on a stream allocates device memory.
  */
 hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
                             int64_t ldy, unsigned flags, void* hip_stream);
@@ -334,7 +340,12 @@ typedef struct {
  * fallback: 3x3 block-Jacobi when nothing is attached, and the solve is run
  * again from X = 0 with the attached correction's base when the learned
  * attempt meets a NaN/Inf or misses rtol (rep->fallback says which).
- * Convergence is always judged by the FP64 true residual.
+ * Convergence is always judged by the FP64 true residual.  Reentrant
+ * across streams like hm_operator_apply (each stream has its own Krylov
+ * workspace, allocated by the first solve on it; the leaf inverses are
+ * formed once per tangent by whichever solve needs them first, the others
+ * wait for them); hm_tangent_set and the hm_learned_* calls that change the
+ * operator must not overlap a solve.
  */
 hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const double* d_B, int64_t ldb,
                    double* d_X, int64_t ldx, hm_solve_report* rep, void* hip_stream);

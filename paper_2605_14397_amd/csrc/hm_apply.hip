@@ -566,12 +566,107 @@ __global__ void k_scatterN(const Segment* __restrict__ segs, const Bases* __rest
 // ------------------------------------------------------------------
 // host driver
 // ------------------------------------------------------------------
-LaunchSet launch_set(const Variant& v)
+// ------------------------------------------------------------------
+// workspaces
+// ------------------------------------------------------------------
+WsLayout Variant::ws_layout() const
+{
+    WsLayout w;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = at;
+        at = (size_t)round_up((int64_t)(at + bytes), 256);
+        return off;
+    };
+    const size_t tfrag = (size_t)std::max<int64_t>(1, tfrag_elems);
+    w.xn = take((size_t)xel * prec_bytes(near_prec));
+    w.xfh = far_is_near() ? w.xn : take((size_t)xel * prec_bytes(far_prec));
+    w.xfl = far_prec == HM_BF16 ? take((size_t)xel * prec_bytes(far_prec)) : 0;
+    w.tph = take(tfrag * prec_bytes(far_prec));
+    w.tpl = far_prec == HM_BF16 ? take(tfrag * prec_bytes(far_prec)) : 0;
+    w.zero_end = at;
+    const int acc_bytes = acc_f64() ? 8 : 4;
+    w.tpart = take((size_t)std::max<int64_t>(1, tpart_elems) * acc_bytes);
+    w.y = take((size_t)xel * acc_bytes);
+    w.bases = take(sizeof(Bases));
+    w.total = at;
+    return w;
+}
+
+Bases Variant::host_bases(void* block) const
+{
+    const WsLayout w = ws_layout();
+    char* p = static_cast<char*>(block);
+    Bases b;
+    b.nearA = near_a.get();
+    b.farA = far_a.get();
+    b.xnear = p + w.xn;
+    b.xfhi = p + w.xfh;
+    b.xflo = far_prec == HM_BF16 ? p + w.xfl : nullptr;
+    b.thi = p + w.tph;
+    b.tlo = far_prec == HM_BF16 ? p + w.tpl : nullptr;
+    b.tpart = p + w.tpart;
+    b.y = p + w.y;
+    return b;
+}
+
+__global__ void k_zero16(uint4* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_set_bases(Bases b, Bases* __restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = b;
+}
+
+void Variant::prepare_block(void* block, hipStream_t s) const
+{
+    const WsLayout w = ws_layout();
+    const int64_t words = (int64_t)(w.zero_end / 16);
+    if (words > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_zero16, dim3(grid), dim3(64 * 4), 0, s, static_cast<uint4*>(block), words);
+    }
+    hipLaunchKernelGGL(k_set_bases, dim3(1), dim3(64), 0, s, host_bases(block),
+                       reinterpret_cast<Bases*>(static_cast<char*>(block) + w.bases));
+    HM_CHECK_HIP(hipGetLastError());
+}
+
+std::unique_ptr<ApplyWs> Variant::new_workspace(hipStream_t s) const
+{
+    std::unique_ptr<ApplyWs> ws(new ApplyWs());
+    ws->block.alloc(ws_layout().total);
+    prepare_block(ws->block.get(), s);
+    ws->gen = gen;
+    return ws;
+}
+
+void* Variant::workspace(hipStream_t s) const
+{
+    std::lock_guard<std::mutex> g(ws_mu);
+    std::unique_ptr<ApplyWs>& w = ws_pool[s];
+    if (!w) {
+        w = new_workspace(s);
+    } else if (w->gen != gen) {
+        // the task lists changed: the partial-slot section may have grown
+        if (w->block.bytes() < ws_layout().total) {
+            HM_CHECK_HIP(hipStreamSynchronize(s));
+            w->block.alloc(ws_layout().total);
+        }
+        prepare_block(w->block.get(), s);
+        w->gen = gen;
+    }
+    return w->block.get();
+}
+
+LaunchSet launch_set(const Variant& v, const void* block)
 {
     LaunchSet L;
     L.near_prec = v.near_prec;
     L.far_prec = v.far_prec;
-    L.bases = v.bases.as<Bases>();
+    L.bases = reinterpret_cast<const Bases*>(static_cast<const char*>(block) + v.ws_layout().bases);
     L.tasksA = v.tasksA.as<TaskA>();
     L.nTasksA = v.nTasksA;
     for (int r = 0; r < kRowTilesMax; ++r) L.groupA[r] = v.groupA[r];
@@ -691,7 +786,19 @@ void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ld
     HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(X && Y, HM_EINVAL, "null vector pointer");
     const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0, accumulate);
-    launch_product(launch_set(v), nrhs, nullptr, &g, 1, op.ne, s, ev);
+    launch_product(launch_set(v, v.workspace(s)), nrhs, nullptr, &g, 1, op.ne, s, ev);
+}
+
+void apply_in(const Op& op, const Variant& v, void* block, int nrhs, const double* X, int64_t ldx, double* Y,
+              int64_t ldy, bool tangent, hipStream_t s, bool accumulate)
+{
+    HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
+    HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
+    HM_REQUIRE(X && Y && block, HM_EINVAL, "null pointer");
+    HM_REQUIRE(((uintptr_t)block & 255) == 0, HM_EINVAL, "workspace block not 256-byte aligned");
+    v.prepare_block(block, s);
+    const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0, accumulate);
+    launch_product(launch_set(v, block), nrhs, nullptr, &g, 1, op.ne, s, nullptr);
 }
 
 // ------------------------------------------------------------------

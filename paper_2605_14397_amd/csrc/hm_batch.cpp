@@ -15,6 +15,7 @@ struct Batch {
     std::vector<Op*> ops;
     int near_prec = HM_F64, far_prec = HM_F64;
     DevBuf bases, tasksA, itemsA, reduce, tasksB, itemsB, segs;
+    std::vector<std::unique_ptr<ApplyWs>> ws;  // the batch's own workspace per operator
     LaunchSet L;
     int64_t max_ne = 0, total_ne = 0;
     std::vector<Segment> hsegs;
@@ -50,9 +51,11 @@ struct Batch {
         std::vector<ReduceDesc> rd;
         std::vector<TaskB> tb;
         std::vector<std::vector<TaskB>> byR(kRowTilesMax);
+        ws.resize(ops.size());
         for (size_t k = 0; k < ops.size(); ++k) {
             const Variant& v = ops[k]->main;
-            hb.push_back(v.host_bases());
+            ws[k] = v.new_workspace(s);
+            hb.push_back(v.host_bases(ws[k]->block.get()));
             const int ia0 = (int)ia.size(), ib0 = (int)ib.size();
             ia.insert(ia.end(), v.hItemsA.begin(), v.hItemsA.end());
             ib.insert(ib.end(), v.hItemsB.begin(), v.hItemsB.end());

@@ -1010,28 +1010,10 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     v.nTasksB = (int)tb.size();
     v.tfrag_elems = tfrag;
     build_tasksA(op, v, v.leavesPerTaskA);
-    // ---- workspaces ----
-    const int64_t xel = op.xtot * kNrhs;
-    v.xf_near.alloc(xel * prec_bytes(v.near_prec));
-    HM_CHECK_HIP(hipMemsetAsync(v.xf_near.get(), 0, v.xf_near.bytes(), s));
-    if (!v.far_is_near()) {
-        v.xf_far_hi.alloc(xel * prec_bytes(v.far_prec));
-        HM_CHECK_HIP(hipMemsetAsync(v.xf_far_hi.get(), 0, v.xf_far_hi.bytes(), s));
-        if (v.far_prec == HM_BF16) {
-            v.xf_far_lo.alloc(xel * prec_bytes(v.far_prec));
-            HM_CHECK_HIP(hipMemsetAsync(v.xf_far_lo.get(), 0, v.xf_far_lo.bytes(), s));
-        }
-    }
-    const int acc_bytes = v.acc_f64() ? 8 : 4;
-    v.tf_hi.alloc(std::max<int64_t>(1, tfrag) * prec_bytes(v.far_prec));
-    HM_CHECK_HIP(hipMemsetAsync(v.tf_hi.get(), 0, v.tf_hi.bytes(), s));
-    if (v.far_prec == HM_BF16) {
-        v.tf_lo.alloc(std::max<int64_t>(1, tfrag) * prec_bytes(v.far_prec));
-        HM_CHECK_HIP(hipMemsetAsync(v.tf_lo.get(), 0, v.tf_lo.bytes(), s));
-    }
-    v.y.alloc(xel * acc_bytes);
-    HM_CHECK_HIP(hipMemsetAsync(v.y.get(), 0, v.y.bytes(), s));
+    // ---- workspaces: the build stream's own is made now ----
+    v.xel = op.xtot * kNrhs;
     upload_tasks(v, s);
+    (void)v.workspace(s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
 }
 
@@ -1108,22 +1090,8 @@ void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, st
     }
 }
 
-Bases Variant::host_bases() const
-{
-    Bases b;
-    b.nearA = near_a.get();
-    b.farA = far_a.get();
-    b.xnear = xf_near.get();
-    b.xfhi = far_is_near() ? xf_near.get() : xf_far_hi.get();
-    b.xflo = far_prec == HM_BF16 ? xf_far_lo.get() : nullptr;
-    b.thi = tf_hi.get();
-    b.tlo = far_prec == HM_BF16 ? tf_lo.get() : nullptr;
-    b.tpart = tpart.get();
-    b.y = y.get();
-    return b;
-}
-
-// Upload the task lists, size the partial-slot workspace, refresh the bases.
+// Upload the task lists; the workspaces are resized on their next use (the
+// partial-slot section depends on the phase-A task list).
 void upload_tasks(Variant& v, hipStream_t s)
 {
     upload(v.tasksB, v.hTasksB, s);
@@ -1131,12 +1099,9 @@ void upload_tasks(Variant& v, hipStream_t s)
     upload(v.tasksA, v.hTasksA, s);
     upload(v.itemsA, v.hItemsA, s);
     upload(v.reduce, v.hReduce, s);
-    const int acc_bytes = v.acc_f64() ? 8 : 4;
-    const size_t need = (size_t)std::max<int64_t>(1, v.tpart_elems) * acc_bytes;
-    if (v.tpart.bytes() < need) v.tpart.alloc(need);
-    std::vector<Bases> b(1, v.host_bases());
-    upload(v.bases, b, s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> g(v.ws_mu);
+    ++v.gen;
 }
 
 // Recompress every factorisation of rank >= 2 at relative Frobenius

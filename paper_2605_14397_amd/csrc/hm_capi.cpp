@@ -5,49 +5,12 @@
 #include <cstdio>
 #include <new>
 
-#include "hm_op.hpp"
-
-struct hm_mesh {
-    hm::Mesh m;
-};
-struct hm_op {
-    hm::Op op;
-};
-struct hm_batch {
-    hm::Batch* b = nullptr;
-    ~hm_batch() { hm::batch_destroy(b); }
-};
-struct hm_learned {
-    hm::Learned net;
-    hm_learned(int h, int k, uint64_t seed) : net(h, k, seed) {}
-};
+#include "hm_handles.hpp"
 
 namespace hm {
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace hm
-
-template <class F>
-static hm_status guarded(F&& f)
-{
-    try {
-        hm::set_last_error("");
-        f();
-        return HM_OK;
-    } catch (const hm::Error& e) {
-        hm::set_last_error(e.what());
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        hm::set_last_error("host allocation failed");
-        return HM_ENOMEM;
-    } catch (const std::exception& e) {
-        hm::set_last_error(e.what());
-        return HM_EINTERNAL;
-    } catch (...) {
-        hm::set_last_error("unknown internal error");
-        return HM_EINTERNAL;
-    }
-}
 
 static void require_gfx950()
 {
@@ -181,6 +144,7 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out)
     return guarded([&] {
         HM_REQUIRE(op && out, HM_EINVAL, "null argument");
         *out = op->op.stats;
+        out->apply_workspace_bytes = (int64_t)op->op.main.ws_layout().total;
     });
 }
 

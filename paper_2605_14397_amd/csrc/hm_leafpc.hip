@@ -225,6 +225,9 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const LeafPc* __restrict__ d
 
 void leaf_pc_prepare(Op& op, hipStream_t s)
 {
+    // concurrent solves on several streams: the first forms the inverses
+    // (and waits for them), the others find them current
+    std::lock_guard<std::mutex> g(op.pc_mu);
     if (op.leaf_pc_current) return;
     const int nleaf = (int)op.plan.leaves.size();
     if (!op.d_leaf_inv.get()) op.d_leaf_inv.alloc((size_t)std::max<int64_t>(1, op.leaf_inv_elems) * sizeof(double));

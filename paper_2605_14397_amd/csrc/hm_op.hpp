@@ -2,9 +2,31 @@
 // the workspaces of apply and solve.
 #pragma once
 
+#include <map>
+#include <mutex>
+
 #include "hm_internal.hpp"
 
 namespace hm {
+
+// Layout of the workspace of one product of a variant, as one contiguous
+// block: in-vector chunks (near precision; far hi/lo when the far field has
+// its own precision), T chunks (hi/lo), phase-A partial slots, phase-B
+// output rows, and the device table of base pointers the kernels read.
+// Sections start on 256-byte boundaries.  The chunk sections (xf_*, tf_*)
+// must be zero where no element writes (padding of every leaf section and
+// of every rank); the others are written before they are read.
+struct WsLayout {
+    size_t xn = 0, xfh = 0, xfl = 0, tph = 0, tpl = 0, tpart = 0, y = 0, bases = 0;
+    size_t zero_end = 0;   // [0, zero_end) holds every section that must start at zero
+    size_t total = 0;
+};
+
+// A workspace owned by a stream's pool or by a batch.
+struct ApplyWs {
+    DevBuf block;
+    uint64_t gen = 0;      // task-list generation its sizes and base table were made for
+};
 
 // One packed copy of the H-matrix in a given (near, far) precision pair.
 // Accumulation is FP64 when near is FP64, FP32 otherwise.
@@ -18,11 +40,12 @@ struct Variant {
     std::pair<int, int> groupA[kRowTilesMax] = {};  // phase-A tasks with R row tiles: (first, count)
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
-    // workspaces (sized for 16 right-hand sides)
-    DevBuf xf_near;               // X chunks in near precision
-    DevBuf xf_far_hi, xf_far_lo;  // X chunks in far precision when it differs (bf16 split)
-    DevBuf tpart, tf_hi, tf_lo, y;
-    DevBuf bases;                 // one Bases entry for this variant
+    int64_t xel = 0;              // elements of one in-vector buffer (padded dofs x 16 columns)
+    uint64_t gen = 1;             // bumped when the task lists are rebuilt (partial slots resize)
+    // per-stream workspaces: a product on stream s uses the pool's block of
+    // s, allocated and zeroed on the first product on s
+    mutable std::mutex ws_mu;
+    mutable std::map<hipStream_t, std::unique_ptr<ApplyWs>> ws_pool;
     // host copies of the task lists (merged by batches)
     std::vector<TaskA> hTasksA;
     std::vector<PanelRef> hItemsA;
@@ -34,10 +57,20 @@ struct Variant {
     std::vector<int64_t> t_off;                 // per block: T chunk offset
     bool acc_f64() const { return near_prec == HM_F64; }
     bool far_is_near() const { return far_prec == near_prec; }
-    Bases host_bases() const;
+    WsLayout ws_layout() const;
+    Bases host_bases(void* block) const;
+    // the workspace of stream s (created on first use; resized and its base
+    // table rewritten after the task lists changed); returns the block base
+    void* workspace(hipStream_t s) const;
+    // a workspace owned by the caller (batches), zeroed and with its table
+    std::unique_ptr<ApplyWs> new_workspace(hipStream_t s) const;
+    // zero the chunk sections of a block and write its base table (kernels
+    // only: usable on memory the library did not allocate)
+    void prepare_block(void* block, hipStream_t s) const;
 };
 
 // Everything one product launches: task lists (single operator or merged).
+// bases points at the device table of base pointers (one entry per operator).
 struct LaunchSet {
     int near_prec = HM_F64, far_prec = HM_F64;
     const Bases* bases = nullptr;
@@ -116,9 +149,12 @@ struct Op {
     // element geometry kept for the learned preconditioner (original order)
     std::vector<double> e_cent, e_frame, e_h;  // [N][3], [N][9], [N] (sqrt of area)
     LearnedPairs lp;
-    // solver workspaces (allocated on first solve)
-    DevBuf solve_ws;
-    size_t solve_ws_bytes = 0;
+    // solver workspaces, one per stream (allocated on the first solve on it)
+    std::mutex solve_mu;
+    std::map<hipStream_t, std::unique_ptr<DevBuf>> solve_ws;
+    double* solve_workspace(hipStream_t s, size_t bytes);
+    // serialises the lazy preconditioner set-up of concurrent solves
+    std::mutex pc_mu;
     hm_op_stats stats{};
     const Variant& ref_variant() const { return ref ? *ref : main; }
 };
@@ -140,7 +176,11 @@ void leaf_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double*
 // ev (optional): 6 events recorded before, between and after the 5 stages
 void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy,
            bool tangent, hipStream_t s, hipEvent_t* ev = nullptr, bool accumulate = false);
-LaunchSet launch_set(const Variant& v);
+// the same product in a workspace block supplied by the caller (ws_layout()
+// bytes at least, 256-byte aligned); zeroes its chunk sections first
+void apply_in(const Op& op, const Variant& v, void* block, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
+              int64_t ldy, bool tangent, hipStream_t s, bool accumulate);
+LaunchSet launch_set(const Variant& v, const void* block);
 Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
                      bool tangent, int op_index, bool accumulate = false);
 // gather (one segment per operator, segs on the device when nseg > 1), phases, scatter

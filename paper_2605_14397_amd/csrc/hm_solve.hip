@@ -187,6 +187,18 @@ __global__ void k_axpby(int nrhs, int64_t n, const double* __restrict__ a, int64
     y[c * ldy + i] = alpha * a[c * lda + i] + beta * b[c * ldb + i];
 }
 
+double* Op::solve_workspace(hipStream_t s, size_t bytes)
+{
+    std::lock_guard<std::mutex> g(solve_mu);
+    std::unique_ptr<DevBuf>& b = solve_ws[s];
+    if (!b) b.reset(new DevBuf());
+    if (b->bytes() < bytes) {
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+        b->alloc(bytes);
+    }
+    return b->as<double>();
+}
+
 namespace {
 
 struct Krylov {
@@ -208,11 +220,7 @@ struct Krylov {
         const size_t nh = (size_t)2 * (m + 2) * nrhs;  // dot results: two targets, up to m + 2 basis vectors
         const size_t ncoef = (size_t)(2 * m + 3) * nrhs;
         size_t need = sizeof(double) * (vec * (m + 1) + 4 * vec + nh * nchunk + nh + ncoef + nrhs);
-        if (op.solve_ws_bytes < need) {
-            op.solve_ws.alloc(need);
-            op.solve_ws_bytes = need;
-        }
-        double* p = op.solve_ws.as<double>();
+        double* p = op.solve_workspace(s, need);
         V = p;
         p += vec * (m + 1);
         W = p;

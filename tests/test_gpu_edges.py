@@ -205,3 +205,54 @@ def test_iteration_budget_ending_inside_a_cycle():
     R = B - X.cpu().numpy() @ E.T
     rel = max(np.linalg.norm(R[c]) / np.linalg.norm(B[c]) for c in range(2))
     assert 0 < rel < 1 and abs(rel - rep["rel_residual"]) <= 1e-6 * rel
+
+
+def test_two_streams_share_one_operator():
+    """hm_operator_apply and hm_solve on one operator from two streams at
+    once (each stream has its own workspace; solves run in two host threads
+    so they overlap): every result equals the serial one bit for bit."""
+    import threading
+
+    hm = _hm()
+    m = rect_grid(40, 26, 1.0)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, near_prec=1, far_prec=1,
+                     keep_f64_reference=1)
+    rng = np.random.default_rng(81)
+    D = np.zeros((m.ne, 3, 3))
+    D[:, [0, 1, 2], [0, 1, 2]] = 2e9 * rng.random((m.ne, 3))
+    op.set_tangent(cuda(D))
+    X1 = cuda(rhs_columns(m.ndof, 16, 82))
+    X2 = cuda(rhs_columns(m.ndof, 7, 83))
+    r1 = op.apply(X1).clone()
+    r2 = op.apply(X2, tangent=True).clone()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    Y1 = [torch.empty_like(X1) for _ in range(4)]
+    Y2 = [torch.empty_like(X2) for _ in range(4)]
+    torch.cuda.synchronize()
+    for k in range(4):
+        op.apply(X1, Y1[k], stream=s1)
+        op.apply(X2, Y2[k], tangent=True, stream=s2)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert torch.equal(Y1[k], r1) and torch.equal(Y2[k], r2), k
+    # solves: serial references, then two threads on two streams
+    B1, B2 = cuda(rhs_columns(m.ndof, 4, 84)), cuda(rhs_columns(m.ndof, 3, 85))
+    opts = dict(precond=hm.HM_PC_LEAF, refine=1, rtol=1e-9, restart=30)
+    x1, _ = op.solve(B1, **opts)
+    x2, _ = op.solve(B2, **opts)
+    op.set_tangent(cuda(D))  # the leaf inverses are formed again, by the first thread to need them
+    out = {}
+
+    def run(name, B, stream):
+        out[name] = op.solve(B, stream=stream, **opts)
+
+    t1 = threading.Thread(target=run, args=("a", B1, s1))
+    t2 = threading.Thread(target=run, args=("b", B2, s2))
+    t1.start()
+    t2.start()
+    t1.join()
+    t2.join()
+    torch.cuda.synchronize()
+    assert out["a"][1]["converged"] and out["b"][1]["converged"]
+    assert torch.equal(out["a"][0], x1) and torch.equal(out["b"][0], x2)

@@ -200,7 +200,8 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);
  * partial-product buffers, hm_op_stats.apply_workspace_bytes), allocated by
  * the first product on that stream, so products of one operator on
  * different streams (and host threads) may overlap; products on one stream
- * run in order.  The first product on a stream allocates device memory.
+ * run in order.  The first product on a stream allocates device memory
+ * (see hm_operator_apply_noalloc).
  */
 hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
                             int64_t ldy, unsigned flags, void* hip_stream);
@@ -216,6 +217,24 @@ hm_status hm_operator_apply(const hm_op* op, int nrhs, const double* d_X, int64_
  */
 hm_status hm_operator_apply_timed(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
                                   int64_t ldy, unsigned flags, void* hip_stream, double* stage_ms);
+
+/*
+ * hm_operator_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the product's workspace is a fixed array of
+ * HM_NOALLOC_SCRATCH_BYTES in the library's device code, one per device,
+ * held from the library's load on that device until the process ends.
+ * Same arguments, flags and results as hm_operator_apply; allocates nothing
+ * and frees nothing.  HM_EINVAL when the operator's workspace
+ * (hm_op_stats.apply_workspace_bytes, or the reference copy's with
+ * HM_APPLY_REFERENCE) exceeds the array.  Every call on a device shares its
+ * array: calls that overlap on one device (several streams or threads) race
+ * and must be serialised by the caller.  Each call clears the parts of the
+ * array that must start at zero with kernels on hip_stream.
+ */
+#define HM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+hm_status hm_operator_apply_noalloc(const hm_op* op, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
+                                    int64_t ldy, unsigned flags, void* hip_stream);
 
 /*
  * Set the tangent terms: A11 = E - D on active elements, identity rows and

@@ -33,6 +33,7 @@ EXPORTS = [
     "hm_last_error", "hm_version", "hm_mesh_create", "hm_mesh_destroy", "hm_mesh_num_elements",
     "hm_mesh_frames", "hm_plan_summary", "hm_kernel_block", "hm_build_opts_default",
     "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_operator_apply_timed",
+    "hm_operator_apply_noalloc",
     "hm_tangent_set",
     "hm_solve_opts_default", "hm_solve", "hm_batch_opts_default", "hm_batch_create", "hm_batch_apply",
     "hm_batch_get_info", "hm_batch_destroy",
@@ -159,6 +160,7 @@ def lib():
             "hm_operator_stats": ([P, ctypes.POINTER(OpStats)], I),
             "hm_operator_apply": ([P, I, P, I64, P, I64, U, P], I),
             "hm_operator_apply_timed": ([P, I, P, I64, P, I64, U, P, P], I),
+            "hm_operator_apply_noalloc": ([P, I, P, I64, P, I64, U, P], I),
             "hm_tangent_set": ([P, P, P, P], I),
             "hm_solve_opts_default": ([ctypes.POINTER(SolveOpts)], None),
             "hm_solve": ([P, ctypes.POINTER(SolveOpts), I, P, I64, P, I64, ctypes.POINTER(SolveReport), P], I),
@@ -347,6 +349,19 @@ class Operator:
         _check(lib().hm_operator_apply(self._h, X2.shape[0], _dev_ptr(X2, torch.float64), _ld(X2),
                                        _dev_ptr(Y, torch.float64), _ld(Y), flags, _stream(stream)))
         return Y.reshape(-1) if squeeze else Y
+
+    def apply_noalloc(self, X, Y, reference=False, tangent=False, accumulate=False, stream=None):
+        """apply() through hm_operator_apply_noalloc (workspace in the
+        library's fixed device array; Y must be given)."""
+        import torch
+
+        _vecs(X, self.ndof, "X")
+        _vecs(Y, self.ndof, "Y", X.shape[0])
+        flags = ((HM_APPLY_REFERENCE if reference else 0) | (HM_APPLY_TANGENT if tangent else 0)
+                 | (HM_APPLY_ACCUMULATE if accumulate else 0))
+        _check(lib().hm_operator_apply_noalloc(self._h, X.shape[0], _dev_ptr(X, torch.float64), _ld(X),
+                                               _dev_ptr(Y, torch.float64), _ld(Y), flags, _stream(stream)))
+        return Y
 
     STAGES = ("gather", "phaseA", "reduceT", "phaseB", "scatter")
 

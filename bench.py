@@ -38,13 +38,13 @@ def source_hash() -> str:
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/trace -o primary -- "
-             "python3 bench.py --only fp32 --steps 20 --warmup 3 --no-gmres --no-cpu-baseline",
+             "python3 bench.py --only fp32 --steps 20 --warmup 3 --no-gmres --no-cpu-baseline --no-forms",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_phase|k_reduceT|k_gather|k_scatter\" "
              "--output-format csv -d gpurun_out/prof/fetch -o primary -- "
-             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline",
+             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline --no-forms",
     "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_phase|k_reduceT|k_gather|k_scatter\" "
              "--output-format csv -d gpurun_out/prof/write -o primary -- "
-             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline",
+             "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline --no-forms",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"copy|Copy\" --output-format csv "
                   "-d gpurun_out/prof/copy_fetch -o copy -- python3 bench.py --form copy --steps 3",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"copy|Copy\" --output-format csv "
@@ -59,6 +59,15 @@ IF_PROFILE_COMMANDS = {
     "write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex interface --output-format csv "
              "-d gpurun_out/prof_if/write -o interface -- "
              "python3 bench.py --form interface --if-states mixed --steps 3 --warmup 1 --no-cpu-baseline",
+}
+# MFMA activity and L2 hits of the phase kernels (one counter group per run)
+COUNTER_COMMANDS = {
+    "mfma": "rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE --kernel-include-regex "
+            "\"k_phase\" --output-format csv -d gpurun_out/prof/mfma -o primary -- "
+            "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline --no-forms",
+    "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --kernel-include-regex \"k_phase\" --output-format csv "
+          "-d gpurun_out/prof/l2 -o primary -- "
+          "python3 bench.py --only fp32 --steps 3 --warmup 1 --no-gmres --no-cpu-baseline --no-forms",
 }
 PHASE_KERNELS = ("k_gather", "k_phaseA", "k_reduceT", "k_phaseB", "k_scatter")
 
@@ -142,7 +151,7 @@ def summarize_profiles(prof_dir: str):
 
 MIXED_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_mixed/trace "
                          "-o mixed -- python3 bench.py --only mixed --steps 20 --warmup 3 --no-gmres "
-                         "--no-cpu-baseline")
+                         "--no-cpu-baseline --no-forms")
 
 
 def summarize_mixed_profile(prof_dir: str):
@@ -193,6 +202,56 @@ def summarize_newton_profile(prof_dir: str):
                      f"{float(r['TotalDurationNs']) / 1e6:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f} % |")
     lines += ["", f"All kernels: {total / 1e9:.2f} s of GPU time (builds of four operators included)."]
     with open(os.path.join(ROOT, "profiles", "kernel_stats_newton_hf_fault.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_counters(prof_dir: str):
+    """profiles/mfma_busy_primary_fp32.md and profiles/l2_hits_primary_fp32.md
+    from the CSV output of COUNTER_COMMANDS (MFMA busy cycles and L2 hits of
+    the phase kernels)."""
+    import csv
+
+    def load(sub):
+        rows = list(csv.DictReader(open(os.path.join(prof_dir, sub, "primary_counter_collection.csv"))))
+        agg, disp = {}, {}
+        for r in rows:
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hm::", "").strip()
+            agg.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp.setdefault(k, {})[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        return agg, {k: (len(v), sum(v.values())) for k, v in disp.items()}
+
+    xcds, simds = 8, 1024   # MI355X: 8 XCDs, 256 CUs x 4 SIMDs
+    agg, disp = load("mfma")
+    lines = ["# MFMA activity of the product kernels: 256x256 planar fault, 16 RHS, FP32 form", "",
+             "Command (from the repository root, `TMPDIR=/tmp`):", "", "```", COUNTER_COMMANDS["mfma"], "```", "",
+             "MFMA utilisation as rocprofv3 defines it (`MfmaUtil`): SQ_VALU_MFMA_BUSY_CYCLES summed over the",
+             f"SIMDs / (GRBM_GUI_ACTIVE of one XCD x {simds} SIMDs); the CSV's GRBM_GUI_ACTIVE is the sum over the",
+             f"{xcds} XCDs, so one XCD's value is that sum / {xcds}.  Summed over every profiled dispatch.", "",
+             "| kernel | dispatches | kernel time (us) | MFMA busy cycles | GRBM_GUI_ACTIVE (sum of XCDs) | MFMA util |",
+             "|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items()):
+        util = 100.0 * v["SQ_VALU_MFMA_BUSY_CYCLES"] / (v["GRBM_GUI_ACTIVE"] / xcds * simds)
+        lines.append(f"| `{k}` | {disp[k][0]} | {disp[k][1] / 1e3:.0f} | {v['SQ_VALU_MFMA_BUSY_CYCLES']:.3e} | "
+                     f"{v['GRBM_GUI_ACTIVE']:.3e} | {util:.1f} % |")
+    lines += ["", "At 16 right-hand sides an FP32 panel entry meets 16 multiply-adds (8 flop per byte), so streaming",
+              "at 5.3 TB/s needs about 42 TFLOP/s of FP32 MFMA, 27 % of its 157.3 TFLOP/s peak: the MFMA units",
+              "are about a third busy, the kernels are bound by HBM, not by the matrix cores."]
+    with open(os.path.join(ROOT, "profiles", "mfma_busy_primary_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    agg, disp = load("l2")
+    lines = ["# L2 (TCC) hits of the product kernels: 256x256 planar fault, 16 RHS, FP32 form", "",
+             "Command (from the repository root, `TMPDIR=/tmp`):", "", "```", COUNTER_COMMANDS["l2"], "```", "",
+             "Summed over every profiled dispatch; a request is one 128-byte line.", "",
+             "| kernel | dispatches | TCC_HIT | TCC_MISS | hit rate | miss bytes per dispatch |",
+             "|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items()):
+        h, m_ = v["TCC_HIT_sum"], v["TCC_MISS_sum"]
+        lines.append(f"| `{k}` | {disp[k][0]} | {h:.3e} | {m_:.3e} | {100 * h / (h + m_):.1f} % | "
+                     f"{128 * m_ / disp[k][0] / 1e6:.1f} MB |")
+    lines += ["", "Phase B streams its panels once (misses) and re-reads X and T chunks from L2 (hits); phase A",
+              "re-reads the X chunks of its source leaves across tasks (more hits)."]
+    with open(os.path.join(ROOT, "profiles", "l2_hits_primary_fp32.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 
@@ -276,6 +335,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the three-disk and 64-mesh sub-records")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
@@ -306,6 +366,9 @@ def main():
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_profiles:
+        if os.path.exists(os.path.join(args.summarize_profiles, "mfma")):
+            summarize_counters(args.summarize_profiles)
+            return
         if os.path.exists(os.path.join(args.summarize_profiles, "trace", "mixed_kernel_stats.csv")):
             summarize_mixed_profile(args.summarize_profiles)
         elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "newton_kernel_stats.csv")):
@@ -404,26 +467,24 @@ def main():
         st = op.stats()
         ms, wall, stages = time_form(op)
         log(f"{name}: {ms:.3f} ms/step, stages {stages}")
-        res[name] = dict(op=op, stats=st, ms=ms, wall=wall, stages=stages, build_s=build_s)
+        res[name] = dict(op=op, stats=st, ms=ms, wall=wall, stages=stages, build_s=build_s, Y=Y.cpu().numpy())
         if name == "fp32" and args.only is None:
             ms64, wall64, st64 = time_form(op, reference=True)
             log(f"fp64 (reference copy): {ms64:.3f} ms/step, stages {st64}")
-            res["fp64"] = dict(op=op, stats=st, ms=ms64, wall=wall64, stages=st64, build_s=None, ref=True)
+            res["fp64"] = dict(op=op, stats=st, ms=ms64, wall=wall64, stages=st64, build_s=None, ref=True,
+                               Y=Y.cpu().numpy())
 
     head = res[forms[0][0]]
     st = head["stats"]
     ms = head["ms"]
-    sx = 8  # FP64 vectors at the boundary
-    bytes_near, bytes_far = st["bytes_near"], st["bytes_far"]
-    b_alg = bytes_near + bytes_far + NRHS * n * (sx + sx)
-    wbytes = 4 if st["near_prec"] != hm.HM_F64 else 8
-    fbytes = {hm.HM_F64: 8, hm.HM_F32: 4, hm.HM_BF16: 2}[st["far_prec"]]
-    # phase B (dominant kernel): dense leaves + U slices + X chunks + T chunks + Y, each once
-    phaseB_alg = (bytes_near + st["bytes_far_u"] + NRHS * n * wbytes + st["rank_sum"] * NRHS * fbytes
-                  + NRHS * n * wbytes)
+    snear = {hm.HM_F64: 8, hm.HM_F32: 4, hm.HM_BF16: 2}[st["near_prec"]]
+    sfar = {hm.HM_F64: 8, hm.HM_F32: 4, hm.HM_BF16: 2}[st["far_prec"]]
+    sacc = 8 if st["near_prec"] == hm.HM_F64 else 4
+    alg = product_bytes(st, n, snear, sfar, sacc)
     phaseB_ms = head["stages"]["phaseB"]
-    achieved = phaseB_alg / (phaseB_ms * 1e-3) / 1e9
+    achieved = alg["phaseB"] / (phaseB_ms * 1e-3) / 1e9
     value = NRHS * 1000.0 / ms
+    product_gbs = alg["product"] / (ms * 1e-3) / 1e9
     out.update({
         "metric": "H-matvecs/s at 196,608 DOF (16-RHS batched H-matrix product)",
         "value": round(value, 2),
@@ -442,8 +503,10 @@ def main():
                         "H-matrix leaf 64, eta 2, ACA 1e-6; FP32 near and far field, FP32 accumulation",
             "n_dof": n, "nrhs": NRHS, "leaf_size": 64, "eta": 2.0, "aca_tol": 1e-6,
         },
-        "hbm_gbs": round(b_alg / (ms * 1e-3) / 1e9, 1),
-        "alg_bytes_per_step": b_alg,
+        # whole product: stored entries without padding + FP64 vectors in and out
+        "hbm_gbs": round(product_gbs, 1),
+        "alg_bytes_per_step": alg["product"],
+        "product_roofline_frac": round(product_gbs / HBM_PEAK_GBS, 4),
         "wall_s_timed": round(head["wall"], 4),
         "stage_ms": {k: round(v, 4) for k, v in head["stages"].items()},
         "roofline": {
@@ -455,38 +518,57 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profile("k_phaseB"),
-            "alg_bytes_per_launch": phaseB_alg,
+            "alg_bytes_per_launch": alg["phaseB"],
+            "alg_bytes_formula": "stored dense entries x s_near + U entries (sum k c m) x s_far + X chunks "
+                                 "(16 x 3N x s_near) + Y rows (16 x 3N x s_acc); no padding",
+            "t_chunk_bytes_per_launch": alg["t_chunks"],
+            "padding_bytes_per_launch": alg["phaseB_padding"],
             "launch_ms": round(phaseB_ms, 4),
         },
-        "operator": {k: st[k] for k in ("n_dense_blocks", "n_lowrank_blocks", "dense_entries", "lowrank_entries",
-                                        "bytes_near", "bytes_far", "min_rank", "max_rank", "mean_rank")},
+        "phaseA": {"ms": round(head["stages"]["phaseA"], 4), "alg_bytes": alg["phaseA"],
+                   "gbs": round(alg["phaseA"] / (head["stages"]["phaseA"] * 1e-3) / 1e9, 1),
+                   "frac": round(alg["phaseA"] / (head["stages"]["phaseA"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "formula": "V entries (sum k c n) x s_far + X chunks (16 x 3N x s_far); no padding"},
+        "operator": {k: st[k] for k in ("n_dense_blocks", "n_lowrank_blocks", "dense_entries", "dense_entries_stored",
+                                        "lowrank_entries",
+                                        "lowrank_entries_u", "bytes_near", "bytes_far", "min_rank", "max_rank",
+                                        "mean_rank", "apply_workspace_bytes")},
         "build_s": round(head["build_s"], 3) if head["build_s"] else None,
-        "build_ms_split": {k: round(st[k], 1) for k in ("coef_ms", "aca_ms", "pack_ms")},
+        "build_ms_split": {k: round(st[k], 1) for k in ("coef_ms", "aca_ms", "recompress_ms", "pack_ms")},
         # FP64 influence coefficients of the dense leaves (ALU-bound, not a roofline item)
         "coef_element_pairs_per_s": round(st["dense_entries"] / 9 / (st["coef_ms"] * 1e-3), 0)
         if st["coef_ms"] > 0 else None,
     })
+    outputs = {forms[0][0]: head["Y"]}
     if "fp64" in res and forms[0][0] != "fp64":
         r64 = res["fp64"]
-        b64 = st["bytes_reference"] + NRHS * n * 16
+        a64 = product_bytes(st, n, 8, 8, 8, reference=True)
         out["fp64_form"] = {"value": round(NRHS * 1000.0 / r64["ms"], 2), "unit": "matvecs/s",
-                            "ms_per_step": round(r64["ms"], 4), "hbm_gbs": round(b64 / (r64["ms"] * 1e-3) / 1e9, 1),
+                            "ms_per_step": round(r64["ms"], 4),
+                            "hbm_gbs": round(a64["product"] / (r64["ms"] * 1e-3) / 1e9, 1),
+                            "product_roofline_frac": round(a64["product"] / (r64["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "stage_ms": {k: round(v, 4) for k, v in r64["stages"].items()}}
+        outputs["fp64"] = r64["Y"]
     if args.only is None:
         # the precision form's operator: FP32 near field, BF16 far field, FP32 accumulation
         opm = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
                           far_prec=hm.HM_BF16)
         stm = opm.stats()
         msm, _, stgm = time_form(opm)
-        bm = stm["bytes_near"] + stm["bytes_far"] + NRHS * n * 16
-        out["mixed_bf16_form"] = {"value": round(NRHS * 1000.0 / msm, 2), "unit": "matvecs/s",
-                                  "ms_per_step": round(msm, 4), "hbm_gbs": round(bm / (msm * 1e-3) / 1e9, 1),
-                                  "bytes_far": stm["bytes_far"],
-                                  "stage_ms": {k: round(v, 4) for k, v in stgm.items()}}
+        am = product_bytes(stm, n, 4, 2, 4)
+        out["mixed_bf16_form"] = {
+            "value": round(NRHS * 1000.0 / msm, 2), "unit": "matvecs/s", "ms_per_step": round(msm, 4),
+            "hbm_gbs": round(am["product"] / (msm * 1e-3) / 1e9, 1),
+            "product_roofline_frac": round(am["product"] / (msm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phaseA_frac": round(am["phaseA"] / (stgm["phaseA"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phaseB_frac": round(am["phaseB"] / (stgm["phaseB"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_far": stm["bytes_far"], "stage_ms": {k: round(v, 4) for k, v in stgm.items()}}
+        outputs["mixed_bf16"] = Y.cpu().numpy()
         log(f"mixed (FP32 near / BF16 far): {msm:.3f} ms/step, stages {stgm}")
         del opm
 
     # ---------------------------------------------------------- GMRES time to 1e-8
+    solutions = {}
     if not args.no_gmres and args.only is None:
         del res
         head = None
@@ -519,6 +601,7 @@ def main():
                 g[rname] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
                             "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
                             "converged": bool(rep["converged"])}
+                solutions[rname] = x.cpu().numpy()
                 log(f"gmres {rname}: {g[rname]}")
             del op
             torch.cuda.empty_cache()
@@ -528,40 +611,154 @@ def main():
         g["system"] = ("A11 = E on a penny crack of radius 0.45 x side (41,000 active elements), identity "
                        "elsewhere; 16 RHS (uniform 1 MPa pressure + 15 seeded tractions); GMRES(100), "
                        "3x3 block-Jacobi (plain) or leaf block-Jacobi (_leaf, set-up included), FP64 Arnoldi; "
-                       "residual with the FP64 H-operator")
+                       "rel_residual with the FP64 H-operator")
         out["gmres"] = g
 
-    # ---------------------------------------------------------- CPU oracle baseline
-    if not args.no_cpu_baseline and args.only is None:
-        import oracle
+    # ---------------------------------------------------------- the other configurations
+    extra = {}
+    if not args.no_forms and args.only is None:
+        torch.cuda.empty_cache()
+        out["precision_form"], extra["precision"] = precision_record(steps=10)
+        torch.cuda.empty_cache()
+        out["batched_form"], extra["batched"] = batched_record(steps=10, warmup=3, n_meshes=args.meshes)
+        torch.cuda.empty_cache()
 
-        Xh = rhs_columns(n, NRHS, 2001)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        rng = np.random.default_rng(0)
-        t0 = time.perf_counter()
-        probe = rng.choice(m.ne, 64, replace=False)
-        oracle.rows_matvec(m, YOUNG, NU, probe, Xh)
-        tp = time.perf_counter() - t0
-        nrows = int(min(m.ne, max(64, 64 * args.cpu_seconds / max(tp, 1e-3))))
-        rows = rng.choice(m.ne, nrows, replace=False)
-        t0 = time.perf_counter()
-        oracle.rows_matvec(m, YOUNG, NU, rows, Xh)
-        tc = time.perf_counter() - t0
-        cpu_value = NRHS * (nrows / m.ne) / tc
-        out["cpu_baseline"] = {"value": round(cpu_value, 6), "unit": "matvecs/s", "cores": threads, "kind": "oracle",
-                               "sample": f"exact FP64 rows (coplanar closed form, direct summation) for {nrows} of "
-                                         f"{m.ne} elements x 16 RHS in {tc:.1f} s, scaled to whole products"}
-        log(f"cpu oracle: {out['cpu_baseline']}")
+    # ---------------------------------------------------------- CPU oracle leg
+    # the oracle timed on this host's cores (cpu_baseline), and every result
+    # above stated against it
+    if not args.no_cpu_baseline and args.only is None:
+        oracle_leg(args, out, m, X.cpu().numpy(), outputs, solutions, B if solutions else None, extra)
     print(json.dumps(out), flush=True)
 
 
-def bench_precision(args):
-    """Three mutually intersecting 40 m disk fractures (103,101 triangles,
-    309,303 DOF, after the triangles crossing another disk are dropped),
-    Gaussian pressure bump (peak 5 MPa, sigma 8 m) as the load:
-    GMRES to a relative residual of 1e-8 in the plain FP64 form and in the
-    precision form (FP32 near field, BF16 low-rank factors, FP64 self
-    blocks, FP64 Arnoldi, FP64 iterative refinement with the FP64 operator)."""
+def product_bytes(st, n, snear, sfar, sacc, reference=False):
+    """Algorithmic bytes of one 16-column product from the operator's stored
+    entries, without padding: the whole product (panels once, the FP64
+    self blocks of mixed forms once, FP64 vectors in and out at the
+    boundary), phase B (dense entries, U entries, X chunks in near
+    precision, Y rows in accumulation precision), phase A (V entries, X
+    chunks in far precision), the T chunks phase B reads, and the padding
+    phase B's panels carry beyond that."""
+    dense, lr, lr_u = st["dense_entries_stored"], st["lowrank_entries"], st["lowrank_entries_u"]
+    selfb = 0 if reference else st["self_f64_entries"] * 8
+    vec = NRHS * n
+    d = {"product": dense * snear + lr * sfar + selfb + vec * 16,
+         "phaseB": dense * snear + lr_u * sfar + vec * snear + vec * sacc,
+         "phaseA": (lr - lr_u) * sfar + vec * sfar,
+         "t_chunks": st["rank_sum"] * NRHS * sfar}
+    if not reference:
+        d["phaseB_padding"] = st["bytes_near"] + st["bytes_far_u"] - (dense * snear + lr_u * sfar)
+    return d
+
+
+def cpu_model() -> str:
+    """lscpu's model name (with family/model numbers), else /proc/cpuinfo's."""
+    import subprocess
+
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in txt.splitlines() if ":" in l)}
+        if "Model name" in f:
+            return f"{f['Model name']} (family {f.get('CPU family', '?')}, model {f.get('Model', '?')}, " \
+                   f"{f.get('Socket(s)', '?')} socket(s), {f.get('CPU(s)', '?')} CPUs listed)"
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_leg(args, out, m, Xh, outputs, solutions, B, extra):
+    """The CPU oracle on this host: its exact-row product timed on a bounded
+    sample (cpu_baseline), and the errors of every GPU result above against
+    the oracle's exact operator (Toeplitz sum of the uniform grids by FFT,
+    exact rows of the triangle meshes by Peach-Koehler quadrature)."""
+    import numpy as np
+
+    import oracle
+
+    n = m.ndof
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    probe = rng.choice(m.ne, 64, replace=False)
+    oracle.rows_matvec(m, YOUNG, NU, probe, Xh)
+    tp = time.perf_counter() - t0
+    nrows = int(min(m.ne, max(64, 64 * args.cpu_seconds / max(tp, 1e-3))))
+    rows = rng.choice(m.ne, nrows, replace=False)
+    t0 = time.perf_counter()
+    oracle.rows_matvec(m, YOUNG, NU, rows, Xh)
+    tc = time.perf_counter() - t0
+    cpu_value = NRHS * (nrows / m.ne) / tc
+    out["cpu_baseline"] = {"value": round(cpu_value, 6), "unit": "matvecs/s", "cores": threads, "kind": "oracle",
+                           "cpu_model": cpu_model(),
+                           "sample": f"exact FP64 rows (coplanar closed form, direct summation) for {nrows} of "
+                                     f"{m.ne} elements x 16 RHS in {tc:.1f} s, scaled to whole products"}
+    log(f"cpu oracle: {out['cpu_baseline']}")
+    # 256 x 256 products of every form against the exact Toeplitz product
+    nx = m.meta["nx"]
+    table = oracle.grid_table(YOUNG, NU, nx, nx)
+    ref = oracle.grid_matvec_fft(table, nx, nx, Xh)
+
+    def errs(Y, R):
+        col = [float(np.linalg.norm(Y[c] - R[c]) / np.linalg.norm(R[c])) for c in range(R.shape[0])]
+        ent = [float(np.abs(Y[c] - R[c]).max() / np.abs(R[c]).max()) for c in range(R.shape[0])]
+        return {"max_column_rel_err": max(col), "max_entry_rel_err": max(ent)}
+
+    err = {k: errs(v, ref) for k, v in outputs.items()}
+    for k, v in err.items():
+        rec = out if k == "fp32" else out.get({"fp64": "fp64_form", "mixed_bf16": "mixed_bf16_form"}[k], {})
+        rec["error_vs_oracle"] = v
+    log(f"product errors vs exact operator: {err}")
+    # GMRES solutions: exact residual b - A11 x with A11 = E on the crack, identity elsewhere
+    if solutions:
+        from workloads import penny_active_mask
+
+        act3 = np.repeat(penny_active_mask(m).astype(bool), 3)
+        for k, x in solutions.items():
+            Ex = oracle.grid_matvec_fft(table, nx, nx, x)
+            Bf = B.reshape(NRHS, n)
+            r = np.where(act3[None, :], Bf - Ex, Bf - x)
+            rel = max(float(np.linalg.norm(r[c]) / np.linalg.norm(Bf[c])) for c in range(NRHS))
+            out["gmres"][k]["exact_rel_residual"] = rel
+        log("gmres exact residuals: " + str({k: out["gmres"][k]["exact_rel_residual"] for k in solutions}))
+    if "precision" in extra:
+        d = extra["precision"]
+        rows = d["rows"]
+        t0 = time.perf_counter()
+        R = oracle.rows_matvec(d["mesh"], YOUNG, NU, rows, np.concatenate([d["X"], d["x"]]), method=1)
+        dof = (3 * rows[:, None] + np.arange(3)).ravel()
+        rec = out["precision_form"]
+        rec["product_error_vs_oracle_rows"] = {k: errs(Y[:, dof], R[:NRHS]) for k, Y in d["Y"].items()}
+        bh = d["b"][0, dof]
+        rec["precision_bf16"]["exact_rel_residual_rows"] = float(np.linalg.norm(bh - R[NRHS]) / np.linalg.norm(bh))
+        rec["oracle_rows"] = f"{rows.size} rows (32 at the largest load, the rest seeded), PK quadrature, " \
+                             f"{time.perf_counter() - t0:.1f} s"
+        log(f"precision form vs oracle rows: {rec['product_error_vs_oracle_rows']}, "
+            f"refined residual {rec['precision_bf16']['exact_rel_residual_rows']:.2e}")
+    if "batched" in extra:
+        d = extra["batched"]
+        worst = 0.0
+        for mesh, X1, Y1 in zip(d["meshes"], d["X"], d["Y"]):
+            t = oracle.grid_table(YOUNG, NU, mesh.meta["nx"], mesh.meta["ny"])
+            R1 = oracle.grid_matvec_fft(t, mesh.meta["nx"], mesh.meta["ny"], X1)
+            worst = max(worst, errs(Y1, R1)["max_column_rel_err"])
+        out["batched_form"]["error_vs_oracle"] = {"max_column_rel_err_all_meshes": worst,
+                                                  "columns": int(d["X"][0].shape[0])}
+        log(f"batched vs exact Toeplitz products: worst {worst:.2e}")
+
+
+def precision_record(steps=10):
+    """Three intersecting disk fractures (the precision form's workload):
+    GMRES to 1e-8 in the plain FP64 form and in the precision form (FP32
+    near, BF16 far, FP64 refinement), each with 3x3 and leaf block-Jacobi;
+    products of 16 columns timed.  Returns (record, arrays for the oracle
+    leg)."""
+    import numpy as np
     import torch
 
     import paper_2605_14397_amd as hm
@@ -570,16 +767,15 @@ def bench_precision(args):
     m = three_disks()
     n = m.ndof
     log(f"precision form: {m.ne} triangles")
-    b = torch.as_tensor(gaussian_pressure_traction(m)[None, :], device="cuda")
-    X = torch.as_tensor(rhs_columns(n, NRHS, 3101), device="cuda")
+    bh = gaussian_pressure_traction(m)[None, :]
+    b = torch.as_tensor(bh, device="cuda")
+    Xh = rhs_columns(n, NRHS, 3101)
+    X = torch.as_tensor(Xh, device="cuda")
     Y = torch.empty_like(X)
-    out = {"metric": "GMRES time to relative residual 1e-8, precision form vs plain FP64",
-           "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "scaling": "weak",
-           "vs_baseline": None,
-           "config": {"workload": f"three intersecting 40 m disk fractures, {m.ne} triangles, {n} DOF; "
-                                  "leaf 64, eta 2, ACA 1e-6; Gaussian pressure load 5 MPa, sigma 8 m; "
-                                  "GMRES(100), 3x3 block-Jacobi"}}
-    forms = {}
+    rec = {"workload": f"three intersecting 40 m disk fractures, {m.ne} triangles, {n} DOF; leaf 64, eta 2, "
+                       "ACA 1e-6; Gaussian pressure load 5 MPa, sigma 8 m; GMRES(100) to 1e-8 (FP64 residual "
+                       "with the FP64 H-operator); set-up of the leaf preconditioner inside the timed solve"}
+    keep = {"mesh": m, "X": Xh, "b": bh, "Y": {}}
     for name, kw, sol in (("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
                           ("precision_bf16", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
                            dict(refine=1))):
@@ -593,42 +789,120 @@ def bench_precision(args):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(10):
+        for _ in range(steps):
             op.apply(X, Y)
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 10
-        t0 = time.perf_counter()
-        x, rep = op.solve(b, rtol=1e-8, restart=100, max_iter=3000, raise_on_notconv=False, **sol)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        forms[name] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
-                       "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
-                       "converged": bool(rep["converged"]), "build_s": round(build_s, 2),
-                       "matvec16_ms": round(ms, 4), "matvecs_per_s": round(NRHS * 1000.0 / ms, 1),
-                       "bytes_near": st["bytes_near"], "bytes_far": st["bytes_far"],
-                       "ranks": [st["min_rank"], st["max_rank"], round(st["mean_rank"], 1)]}
-        log(f"{name}: {forms[name]}")
-        # the same solve with the leaf block-Jacobi preconditioner, its set-up included
-        op.set_tangent(None, None)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xl, rep = op.solve(b, rtol=1e-8, restart=100, max_iter=3000, raise_on_notconv=False,
-                           precond=hm.HM_PC_LEAF, **sol)
-        torch.cuda.synchronize()
-        forms[name]["leaf_block"] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 3),
-                                     "iterations": rep["iterations"], "refinements": rep["refinements"],
-                                     "rel_residual": rep["rel_residual"], "converged": bool(rep["converged"])}
-        log(f"{name} leaf block-Jacobi: {forms[name]['leaf_block']}")
-        if name == "fp64_plain":
-            x_plain = x.clone()
-        else:
-            forms[name]["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(x - x_plain) / torch.linalg.norm(x_plain))
+        ms = e0.elapsed_time(e1) / steps
+        keep["Y"][name] = Y.cpu().numpy()
+        snear = 8 if kw["near_prec"] == hm.HM_F64 else 4
+        sfar = {hm.HM_F64: 8, hm.HM_BF16: 2}[kw["far_prec"]]
+        alg = product_bytes(st, n, snear, sfar, snear)
+        r = {"matvec16_ms": round(ms, 4), "matvecs_per_s": round(NRHS * 1000.0 / ms, 1),
+             "hbm_gbs": round(alg["product"] / (ms * 1e-3) / 1e9, 1),
+             "product_roofline_frac": round(alg["product"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "build_s": round(build_s, 2), "bytes_near": st["bytes_near"], "bytes_far": st["bytes_far"]}
+        for pname, pc in (("block3", hm.HM_PC_BLOCK3), ("leaf", hm.HM_PC_LEAF)):
+            op.set_tangent(None, None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, rep = op.solve(b, rtol=1e-8, restart=100, max_iter=3000, raise_on_notconv=False, precond=pc, **sol)
+            torch.cuda.synchronize()
+            r[pname] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 3), "iterations": rep["iterations"],
+                        "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
+                        "converged": bool(rep["converged"])}
+            if name == "precision_bf16" and pname == "leaf":
+                keep["x"] = x.cpu().numpy()
+        log(f"{name}: {r}")
+        rec[name] = r
         del op
         torch.cuda.empty_cache()
-    out["forms"] = forms
-    out["value"] = forms["precision_bf16"]["time_to_1e-8_s"]
-    out["speedup_vs_fp64"] = round(forms["fp64_plain"]["time_to_1e-8_s"] / forms["precision_bf16"]["time_to_1e-8_s"], 3)
+    base = rec["fp64_plain"]["block3"]["time_to_1e-8_s"]
+    rec["speedup_vs_fp64_plain"] = {f"{f}_{p}": round(base / rec[f][p]["time_to_1e-8_s"], 3)
+                                    for f in ("fp64_plain", "precision_bf16") for p in ("block3", "leaf")}
+    rng = np.random.default_rng(3)
+    big = np.argsort(-np.abs(bh[0, 2::3]))[:32]
+    rows = np.unique(np.concatenate([big, rng.choice(m.ne, 40, replace=False)]))[:64]
+    keep["rows"] = rows
+    return rec, keep
+
+
+def batched_record(steps=10, warmup=3, n_meshes=64):
+    """The batched form's workload (64 planar faults, 2k-40k elements, FP32):
+    one merged graph-captured product vs one product per mesh, 1 and 16
+    columns.  Returns (record, arrays for the oracle leg)."""
+    import torch
+
+    import paper_2605_14397_amd as hm
+    from workloads import batched_faults, rhs_columns
+
+    meshes = batched_faults(n_meshes=n_meshes, seed=4001)
+    ne = sum(m.ne for m in meshes)
+    log(f"batched: {len(meshes)} meshes, {ne} elements")
+    t0 = time.perf_counter()
+    ops = [hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6,
+                       near_prec=hm.HM_F32, far_prec=hm.HM_F32) for m in meshes]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = hm.Batch(ops, use_graph=True, autotune=True)
+    tune_s = time.perf_counter() - t0
+    info = batch.info()
+    stats = [op.stats() for op in ops]
+    alg16 = sum(product_bytes(st, m.ndof, 4, 4, 4)["product"] for st, m in zip(stats, meshes))
+    res, keep = {}, {"meshes": meshes}
+    for nrhs in (1, 16):
+        Xs = [torch.as_tensor(rhs_columns(m.ndof, nrhs, 4101 + 100 * k), device="cuda") for k, m in enumerate(meshes)]
+        Ys = [torch.empty_like(x) for x in Xs]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(warmup):
+            batch.apply(Xs, Ys)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            batch.apply(Xs, Ys)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        if nrhs == 16:
+            keep["X"] = [x[:4].cpu().numpy() for x in Xs]
+            keep["Y"] = [y[:4].cpu().numpy() for y in Ys]
+        for _ in range(warmup):
+            for op, x, y in zip(ops, Xs, Ys):
+                op.apply(x, y)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            for op, x, y in zip(ops, Xs, Ys):
+                op.apply(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / steps
+        r = {"batched_graph_ms": round(ms_b, 4), "per_mesh_ms": round(ms_s, 4), "speedup": round(ms_s / ms_b, 3),
+             "batched_matvecs_per_s": round(nrhs * len(meshes) * 1000.0 / ms_b, 1)}
+        if nrhs == 16:
+            r["hbm_gbs"] = round(alg16 / (ms_b * 1e-3) / 1e9, 1)
+            r["product_roofline_frac"] = round(alg16 / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        res[nrhs] = r
+        log(f"batched nrhs {nrhs}: {r}")
+    rec = {"workload": f"{len(meshes)} planar faults, {ne} square elements in total, 2k-40k each, aspect 1-4, "
+                       "random orientations; leaf 64, eta 2, ACA 1e-6, FP32 form",
+           "nrhs": {str(k): v for k, v in res.items()}, "build_s": round(build_s, 2), "autotune_s": round(tune_s, 2),
+           "autotune": {"candidates": info["tune_candidates"], "ms": [round(x, 4) for x in info["tune_ms"]],
+                        "chosen_leaves_per_task": info["leaves_per_task_a"]},
+           "alg_bytes_16": alg16}
+    del batch, ops
+    return rec, keep
+
+
+def bench_precision(args):
+    """The precision form on its own (bench.py --form precision): the
+    three-disk record of the default run as its own JSON line."""
+    rec, _ = precision_record(steps=args.steps)
+    out = {"metric": "GMRES time to relative residual 1e-8, precision form vs plain FP64", "unit": "s",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "scaling": "weak", "vs_baseline": None,
+           "value": rec["precision_bf16"]["leaf"]["time_to_1e-8_s"], "config": {"workload": rec["workload"]},
+           "forms": rec}
     print(json.dumps(out), flush=True)
 
 
@@ -1100,74 +1374,14 @@ def bench_injection(args):
 
 
 def bench_batched(args):
-    """64 independent planar faults (2k-40k square elements each, seeded
-    aspect ratios 1-4 and orientations), FP32 form, leaf 64, eta 2, ACA
-    1e-6: one merged graph-captured product of all meshes vs one product
-    per mesh, for 1 and 16 columns per mesh."""
-    import torch
-
-    import paper_2605_14397_amd as hm
-    from workloads import batched_faults, rhs_columns
-
-    meshes = batched_faults(n_meshes=args.meshes, seed=4001)
-    ne = sum(m.ne for m in meshes)
-    log(f"batched: {len(meshes)} meshes, {ne} elements")
-    t0 = time.perf_counter()
-    ops = []
-    for k, m in enumerate(meshes):
-        ops.append(hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6,
-                               near_prec=hm.HM_F32, far_prec=hm.HM_F32))
-        if k % 8 == 7:
-            log(f"  built {k + 1} operators, {time.perf_counter() - t0:.1f} s")
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    batch = hm.Batch(ops, use_graph=True, autotune=True)
-    tune_s = time.perf_counter() - t0
-    info = batch.info()
-    log(f"batch info {info}")
-    res = {}
-    for nrhs in (1, 16):
-        Xs = [torch.as_tensor(rhs_columns(m.ndof, nrhs, 4101 + 100 * k), device="cuda") for k, m in enumerate(meshes)]
-        Ys = [torch.empty_like(x) for x in Xs]
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for _ in range(args.warmup):
-            batch.apply(Xs, Ys)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            batch.apply(Xs, Ys)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_b = e0.elapsed_time(e1) / args.steps
-        for _ in range(args.warmup):
-            for op, x, y in zip(ops, Xs, Ys):
-                op.apply(x, y)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            for op, x, y in zip(ops, Xs, Ys):
-                op.apply(x, y)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_s = e0.elapsed_time(e1) / args.steps
-        res[nrhs] = {"batched_graph_ms": round(ms_b, 4), "per_mesh_ms": round(ms_s, 4),
-                     "speedup": round(ms_s / ms_b, 3),
-                     "batched_matvecs_per_s": round(nrhs * len(meshes) * 1000.0 / ms_b, 1),
-                     "hbm_gbs": round(info["bytes_operators"] / (ms_b * 1e-3) / 1e9, 1)}
-        log(f"nrhs {nrhs}: {res[nrhs]}")
-    out = {
-        "metric": "batched H-matvecs/s (64 meshes, one graph-captured merged launch set)",
-        "value": res[16]["batched_matvecs_per_s"], "unit": "mesh-matvecs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": res[16]["batched_graph_ms"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(meshes)} planar faults, {ne} square elements in total, 2k-40k each, "
-                               "aspect 1-4, random orientations; leaf 64, eta 2, ACA 1e-6, FP32 form"},
-        "nrhs": {str(k): v for k, v in res.items()}, "build_s": round(build_s, 2), "autotune_s": round(tune_s, 2),
-        "autotune": {"candidates": info["tune_candidates"], "ms": [round(x, 4) for x in info["tune_ms"]],
-                     "chosen_leaves_per_task": info["leaves_per_task_a"]},
-        "bytes_operators": info["bytes_operators"],
-    }
+    """The batched form on its own (bench.py --form batched)."""
+    rec, _ = batched_record(steps=args.steps, warmup=args.warmup, n_meshes=args.meshes)
+    r16 = rec["nrhs"]["16"]
+    out = {"metric": "batched H-matvecs/s (64 meshes, one graph-captured merged launch set)",
+           "value": r16["batched_matvecs_per_s"], "unit": "mesh-matvecs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r16["batched_graph_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": rec["workload"]}, "batched": rec}
     print(json.dumps(out), flush=True)
 
 

@@ -166,7 +166,7 @@ void hm_op_destroy(hm_op* op);
 typedef struct {
     int64_t n_elements, n_dof;
     int64_t n_leaves, n_dense_blocks, n_lowrank_blocks;
-    int64_t dense_entries;        /* stored near-field scalars (excluding padding) */
+    int64_t dense_entries;        /* near-field scalars 9 m n of the dense blocks (see dense_entries_stored) */
     int64_t lowrank_entries;      /* stored U and V scalars, sum k c (m+n) over factorisations of c components */
     int64_t self_f64_entries;     /* FP64 self-block scalars (mixed forms) */
     int64_t bytes_near, bytes_far, bytes_self, bytes_reference;
@@ -181,6 +181,9 @@ typedef struct {
     double recompress_ms;
     int64_t apply_workspace_bytes;     /* device workspace of one product of the main form (16 columns): each
                                           stream's own, or the part of the no-allocation scratch it needs */
+    int64_t lowrank_entries_u;         /* the U part of lowrank_entries: sum k c m (read by phase B) */
+    int64_t dense_entries_stored;      /* near-field entries stored (coplanar leaf pairs keep only their
+                                          shear-shear and normal-normal parts), without padding */
 } hm_op_stats;
 
 hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);

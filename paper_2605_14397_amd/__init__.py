@@ -67,7 +67,8 @@ class OpStats(ctypes.Structure):
         ("coef_ms", ctypes.c_double), ("aca_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
         ("max_dense_bytes_per_leaf", ctypes.c_int64), ("bytes_far_u", ctypes.c_int64),
         ("bytes_far_v", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("rank_sum_aca", ctypes.c_int64),
-        ("recompress_ms", ctypes.c_double), ("apply_workspace_bytes", ctypes.c_int64)]
+        ("recompress_ms", ctypes.c_double), ("apply_workspace_bytes", ctypes.c_int64),
+        ("lowrank_entries_u", ctypes.c_int64), ("dense_entries_stored", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -900,6 +900,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     std::vector<std::vector<PanelRef>> itemsB(2 * (size_t)nleaf);
     // ---- dense pieces ----
     int64_t near_elems = 0;
+    v.near_entries = 0;
     {
         PackJob job;
         for (size_t b = 0; b < dd.size(); ++b) {
@@ -918,6 +919,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
                         PanelRef{near_elems, (op.leaf_xoff[sc.leaf_id] + sec_off(sc.size(), ss)) * kNrhs, rows, cols,
                                  0, 0});
                     near_elems += panel_elems(rows, cols, wn);
+                    v.near_entries += (int64_t)rows * cols;
                 }
         }
         v.near_a.alloc(std::max<int64_t>(1, near_elems) * prec_bytes(v.near_prec));
@@ -1643,9 +1645,14 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     st.n_dense_blocks = (int64_t)p.dense.size();
     st.n_lowrank_blocks = (int64_t)p.lowrank.size();
     st.dense_entries = dense_total;
-    int64_t lre = 0;
-    for (const LowRank& L : op.lr) lre += (int64_t)L.rank * L.comps * (L.m + L.n);
+    int64_t lre = 0, lre_u = 0;
+    for (const LowRank& L : op.lr) {
+        lre += (int64_t)L.rank * L.comps * (L.m + L.n);
+        lre_u += (int64_t)L.rank * L.comps * L.m;
+    }
     st.lowrank_entries = lre;
+    st.lowrank_entries_u = lre_u;
+    st.dense_entries_stored = op.main.near_entries;
     st.self_f64_entries = op.main.self_separate ? 9 * mesh.ne : 0;
     st.bytes_near = op.main.bytes_near;
     st.bytes_far = op.main.bytes_far;

@@ -40,6 +40,7 @@ struct Variant {
     std::pair<int, int> groupA[kRowTilesMax] = {};  // phase-A tasks with R row tiles: (first, count)
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
+    int64_t near_entries = 0;     // dense-piece entries stored, without padding
     int64_t xel = 0;              // elements of one in-vector buffer (padded dofs x 16 columns)
     uint64_t gen = 1;             // bumped when the task lists are rebuilt (partial slots resize)
     // per-stream workspaces: a product on stream s uses the pool's block of

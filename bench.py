@@ -340,7 +340,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64", "mixed"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "newton",
+    ap.add_argument("--form", choices=["primary", "batched", "precision", "learned", "interface", "newton", "precond",
                                        "injection", "copy"],
                     default="primary",
                     help="batched: 64 independent faults in merged, graph-captured launches; "
@@ -407,6 +407,9 @@ def main():
         return
     if args.form == "injection":
         bench_injection(args)
+        return
+    if args.form == "precond":
+        bench_precond(args)
         return
     if args.form == "copy":
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -583,7 +586,8 @@ def main():
         g = {}
         for name, kw, runs in (
                 ("fp64", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64),
-                 (("fp64_plain", dict(precond=hm.HM_PC_BLOCK3)), ("fp64_leaf", dict(precond=hm.HM_PC_LEAF)))),
+                 (("fp64_plain", dict(precond=hm.HM_PC_BLOCK3)), ("fp64_leaf", dict(precond=hm.HM_PC_LEAF)),
+                  ("fp64_ilu", dict(precond=hm.HM_PC_ILU)), ("fp64_jacobi", dict(precond=hm.HM_PC_JACOBI)))),
                 ("mixed", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
                  (("mixed_bf16_refined", dict(refine=1, precond=hm.HM_PC_BLOCK3)),
                   ("mixed_bf16_refined_leaf", dict(refine=1, precond=hm.HM_PC_LEAF)))),
@@ -600,7 +604,10 @@ def main():
                 dt = time.perf_counter() - t0
                 g[rname] = {"time_to_1e-8_s": round(dt, 3), "iterations": rep["iterations"],
                             "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
-                            "converged": bool(rep["converged"])}
+                            "converged": bool(rep["converged"]),
+                            "precond_setup_ms": round(rep["precond_setup_ms"], 2)}
+                if sol.get("precond") == hm.HM_PC_ILU:
+                    g[rname].update(ilu_nnz=rep["precond_nnz"], ilu_colours=rep["precond_colors"])
                 solutions[rname] = x.cpu().numpy()
                 log(f"gmres {rname}: {g[rname]}")
             del op
@@ -610,7 +617,8 @@ def main():
                                                 / g["mixed_bf16_refined_leaf"]["time_to_1e-8_s"], 3)
         g["system"] = ("A11 = E on a penny crack of radius 0.45 x side (41,000 active elements), identity "
                        "elsewhere; 16 RHS (uniform 1 MPa pressure + 15 seeded tractions); GMRES(100), "
-                       "3x3 block-Jacobi (plain) or leaf block-Jacobi (_leaf, set-up included), FP64 Arnoldi; "
+                       "3x3 block-Jacobi (plain), leaf block-Jacobi (_leaf), ILU(0) of the 1 % largest near-field "
+                       "entries (_ilu) or point Jacobi (_jacobi), set-up included, FP64 Arnoldi; "
                        "rel_residual with the FP64 H-operator")
         out["gmres"] = g
 
@@ -802,7 +810,7 @@ def precision_record(steps=10):
              "hbm_gbs": round(alg["product"] / (ms * 1e-3) / 1e9, 1),
              "product_roofline_frac": round(alg["product"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "build_s": round(build_s, 2), "bytes_near": st["bytes_near"], "bytes_far": st["bytes_far"]}
-        for pname, pc in (("block3", hm.HM_PC_BLOCK3), ("leaf", hm.HM_PC_LEAF)):
+        for pname, pc in (("block3", hm.HM_PC_BLOCK3), ("leaf", hm.HM_PC_LEAF), ("ilu", hm.HM_PC_ILU)):
             op.set_tangent(None, None)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -810,7 +818,7 @@ def precision_record(steps=10):
             torch.cuda.synchronize()
             r[pname] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 3), "iterations": rep["iterations"],
                         "refinements": rep["refinements"], "rel_residual": rep["rel_residual"],
-                        "converged": bool(rep["converged"])}
+                        "converged": bool(rep["converged"]), "precond_setup_ms": round(rep["precond_setup_ms"], 2)}
             if name == "precision_bf16" and pname == "leaf":
                 keep["x"] = x.cpu().numpy()
         log(f"{name}: {r}")
@@ -819,7 +827,7 @@ def precision_record(steps=10):
         torch.cuda.empty_cache()
     base = rec["fp64_plain"]["block3"]["time_to_1e-8_s"]
     rec["speedup_vs_fp64_plain"] = {f"{f}_{p}": round(base / rec[f][p]["time_to_1e-8_s"], 3)
-                                    for f in ("fp64_plain", "precision_bf16") for p in ("block3", "leaf")}
+                                    for f in ("fp64_plain", "precision_bf16") for p in ("block3", "leaf", "ilu")}
     rng = np.random.default_rng(3)
     big = np.argsort(-np.abs(bh[0, 2::3]))[:32]
     rows = np.unique(np.concatenate([big, rng.choice(m.ne, 40, replace=False)]))[:64]
@@ -1370,6 +1378,64 @@ def bench_injection(args):
            "gmres_iterations": gmres_its, "final_modes_elastic_shear_tensile_corner_open": steps[-1]["modes"],
            "max_opening_mm": round(float(total[:, 2].max()) * 1e3, 4),
            "max_slip_mm": round(float(total[:, :2].norm(dim=1).max()) * 1e3, 4), "steps": steps}
+    print(json.dumps(out), flush=True)
+
+
+def bench_precond(args):
+    """The plain preconditioners of the A11 solves side by side on the HF x
+    fault mesh (199,880 triangles at the default leg): point Jacobi (the
+    paper's first choice), 3x3 block-Jacobi, leaf block-Jacobi and the
+    paper's ILU(0) of C^ep plus the 1 % largest near-field entries (its
+    second choice), in the FP64 form and the precision form, on the
+    closed-form tangent states 16-19 of the injection sequence, 16
+    right-hand sides each, GMRES(50) to 1e-8; set-up inside the timed solve."""
+    import numpy as np
+    import torch
+
+    import paper_2605_14397_amd as hm
+    import workloads as W
+
+    m = W.hf_fault_mesh(h=args.hf_h)
+    log(f"preconditioners: HF x fault, {m.ne} triangles")
+    pcs = (("jacobi", hm.HM_PC_JACOBI), ("block3", hm.HM_PC_BLOCK3), ("leaf", hm.HM_PC_LEAF), ("ilu", hm.HM_PC_ILU))
+    forms = {}
+    for fname, kw, sol in (("fp64", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
+                           ("precision", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
+                            dict(refine=1))):
+        op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
+        res = {p: {"time_s": 0.0, "iterations": [], "setup_ms": [], "converged": True} for p, _ in pcs}
+        for k in range(16, 20):
+            D = torch.as_tensor(W.tangent_state(m, k), device="cuda")
+            b = torch.as_tensor(W.tangent_rhs(m, NRHS, 9000 + k), device="cuda")
+            for pname, pc in pcs:
+                op.set_tangent(D)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, rep = op.solve(b, precond=pc, restart=50, rtol=1e-8, max_iter=3000, raise_on_notconv=False,
+                                  **sol)
+                torch.cuda.synchronize()
+                r = res[pname]
+                r["time_s"] += time.perf_counter() - t0
+                r["iterations"].append(rep["iterations"])
+                r["setup_ms"].append(round(rep["precond_setup_ms"], 1))
+                r["converged"] &= bool(rep["converged"])
+                if pc == hm.HM_PC_ILU:
+                    r["nnz"], r["colours"] = rep["precond_nnz"], rep["precond_colors"]
+                log(f"{fname} state {k} {pname}: {rep['iterations']} its, {time.perf_counter() - t0:.3f} s")
+        for r in res.values():
+            r["time_s"] = round(r["time_s"], 3)
+        forms[fname] = res
+        del op
+        torch.cuda.empty_cache()
+    base = forms["fp64"]["jacobi"]["time_s"]
+    out = {"metric": "A11 solve time to 1e-8 by preconditioner (4 tangent states x 16 RHS)", "unit": "s",
+           "value": forms["precision"]["ilu"]["time_s"], "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": f"HF x fault, {m.ne} triangles, {m.ndof} DOF; leaf 64, eta 2, ACA 1e-6; "
+                                  "closed-form tangent states 16-19; GMRES(50)"},
+           "forms": forms,
+           "speedup_vs_fp64_jacobi": {f"{f}_{p}": round(base / forms[f][p]["time_s"], 3)
+                                      for f in forms for p, _ in pcs}}
     print(json.dumps(out), flush=True)
 
 

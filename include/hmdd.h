@@ -309,8 +309,27 @@ void hm_batch_destroy(hm_batch* batch);
  *                  use after each hm_tangent_set; 9 m^2 doubles per leaf.
  *                  HM_EINVAL if a block is numerically singular (a pivot
  *                  below 1e-13 of the block's largest |E_ij| + |D_ij|).
+ *   HM_PC_ILU      the paper's second approximation of A11 (Sec. 3.3.1,
+ *                  solution of the Jacobian system): the fraction p
+ *                  (hm_solve_opts.ilu_fraction, default 1 %) of the
+ *                  near-field entries of E (entries of the dense leaf
+ *                  blocks) of largest magnitude, minus D on every 3x3
+ *                  diagonal block (identity rows and columns for inactive
+ *                  elements), factorised by ILU(0) and applied by forward and
+ *                  backward substitution.  Kept: k = ceil(p x 9 sum m n)
+ *                  entries and all ties, compared by a 48-bit magnitude key
+ *                  (|a|'s bit pattern without its last 15 bits).  Elimination
+ *                  order: elements coloured greedily in increasing id
+ *                  (smallest colour free among lower-id neighbours of the
+ *                  pattern), by colour then id, DOFs s1, s2, n; each colour is
+ *                  one parallel step of the factorisation and of each
+ *                  substitution.  Formed on first use after each
+ *                  hm_tangent_set (coefficients, threshold and
+ *                  factorisation on the GPU, the pattern's colouring and
+ *                  row sort on the host); HM_EINVAL on a zero or non-finite
+ *                  pivot.
  */
-enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3, HM_PC_LEAF = 4 };
+enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3, HM_PC_LEAF = 4, HM_PC_ILU = 5 };
 
 /* why a solve asked for HM_PC_LEARNED ran with HM_PC_BLOCK3 */
 enum {
@@ -324,10 +343,12 @@ typedef struct {
     int restart;        /* GMRES(m) restart length, 1..256; default 50 */
     int max_iter;       /* total inner iterations per right-hand side; default 1000 */
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (FP64); default 1e-8 */
-    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED | HM_PC_LEAF; default BLOCK3 */
+    int precond;        /* HM_PC_NONE | HM_PC_JACOBI | HM_PC_BLOCK3 | HM_PC_LEARNED | HM_PC_LEAF | HM_PC_ILU;
+                           default BLOCK3 */
     int refine;         /* 1: FP64 iterative refinement around a low-precision inner solve */
     double inner_rtol;  /* inner tolerance when refine = 1; 0 (default): 1e-2 with BF16 far field, else 1e-5 */
     int max_refine;     /* refinement sweeps; default 20 */
+    double ilu_fraction;/* HM_PC_ILU: fraction p of the near-field entries kept, (0, 1]; 0 or the default: 0.01 */
 } hm_solve_opts;
 
 void hm_solve_opts_default(hm_solve_opts* opts);
@@ -345,6 +366,9 @@ typedef struct {
     int precond_used;         /* preconditioner of the solve that produced X */
     int fallback;             /* HM_FALLBACK_* */
     int discarded_iterations; /* iterations of a learned attempt that was replaced by the fallback */
+    double precond_setup_ms;  /* time this solve spent forming its preconditioner (0 when it was current) */
+    int64_t precond_nnz;      /* HM_PC_ILU: entries of the factors */
+    int precond_colors;       /* HM_PC_ILU: colours (parallel steps of each substitution) */
 } hm_solve_report;
 
 /*

@@ -21,7 +21,7 @@ HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCO
     0, -1, -2, -3, -4, -5, -6, -7)
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_APPLY_REFERENCE, HM_APPLY_TANGENT, HM_APPLY_ACCUMULATE = 1, 2, 4
-HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF = 0, 1, 2, 3, 4
+HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF, HM_PC_ILU = 0, 1, 2, 3, 4, 5
 HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3
 HM_IF_ELASTIC, HM_IF_SHEAR, HM_IF_TENSILE, HM_IF_CORNER, HM_IF_OPEN, HM_IF_BAD_MATERIAL = 0, 1, 2, 3, 4, -1
 
@@ -77,7 +77,7 @@ class OpStats(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("refine", ctypes.c_int), ("inner_rtol", ctypes.c_double),
-                ("max_refine", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("ilu_fraction", ctypes.c_double)]
 
 
 class NewtonOpts(ctypes.Structure):
@@ -106,7 +106,8 @@ class SolveReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("n_history", ctypes.c_int),
                 ("history", ctypes.c_double * 1024), ("precond_used", ctypes.c_int), ("fallback", ctypes.c_int),
-                ("discarded_iterations", ctypes.c_int)]
+                ("discarded_iterations", ctypes.c_int), ("precond_setup_ms", ctypes.c_double),
+                ("precond_nnz", ctypes.c_int64), ("precond_colors", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}

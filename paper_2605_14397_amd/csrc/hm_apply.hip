@@ -855,6 +855,7 @@ void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s
     op.lp.features_current = false;
     op.lp.attached = false;
     op.leaf_pc_current = false;
+    op.ilu.current = false;
     if (!op.d_pc_block.get()) op.d_pc_block.alloc(9 * ne * sizeof(double));
     if (!op.d_pc_diag.get()) op.d_pc_diag.alloc(3 * ne * sizeof(double));
     hipLaunchKernelGGL(k_precond_setup, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne,

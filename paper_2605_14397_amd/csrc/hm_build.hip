@@ -780,7 +780,7 @@ void ensure_mesh_geo(Mesh& mesh)
     mesh.d_geo_device = dev;
 }
 
-static void moduli(double young, double nu, double& G, double& kG, double& kN)
+void moduli(double young, double nu, double& G, double& kG, double& kN)
 {
     HM_REQUIRE(young > 0.0 && std::isfinite(young), HM_EINVAL, "Young's modulus must be positive");
     HM_REQUIRE(nu > -1.0 && nu < 0.5, HM_EINVAL, "Poisson ratio must lie in (-1, 1/2)");

@@ -261,6 +261,7 @@ void hm_solve_opts_default(hm_solve_opts* o)
     o->refine = 0;
     o->inner_rtol = 0.0;
     o->max_refine = 20;
+    o->ilu_fraction = 0.01;
 }
 
 hm_status hm_solve(const hm_op* op, const hm_solve_opts* opts, int nrhs, const double* d_B, int64_t ldb, double* d_X,

@@ -123,6 +123,22 @@ struct LearnedPairs {
     int base = HM_PC_BLOCK3;  // base preconditioner of the attached correction
 };
 
+// The ILU(0) preconditioner of the sparse approximation of A11 (hm_ilu.hip):
+// CSR rows in the original DOF numbering, each row's entries in
+// elimination order (elements by colour then id), factors in place.
+struct IluPc {
+    double fraction = -1.0;           // p the factors were built for
+    bool current = false;
+    int n_colors = 0;
+    std::vector<int64_t> color_begin; // offsets of each colour in `order`
+    DevBuf order;                     // int32 [N]: elements by (colour, id)
+    DevBuf pos;                       // int32 [N]: each element's place in that order
+    DevBuf rowptr, col, diag, val;    // int64 [3N+1], int32 [nnz], int64 [3N], double [nnz]
+    int64_t nnz = 0, n_kept = 0, near_entries = 0;
+    uint64_t threshold_key = 0;
+    double setup_ms = 0.0;
+};
+
 struct Op {
     int device = 0;
     double young = 0, nu = 0, G = 0;
@@ -147,6 +163,7 @@ struct Op {
     DevBuf d_geo, d_perm, d_leaf_desc, d_leaf_inv;
     int64_t leaf_inv_elems = 0;
     bool leaf_pc_current = false;
+    IluPc ilu;
     // element geometry kept for the learned preconditioner (original order)
     std::vector<double> e_cent, e_frame, e_h;  // [N][3], [N][9], [N] (sqrt of area)
     LearnedPairs lp;
@@ -168,6 +185,13 @@ void ensure_mesh_geo(Mesh& mesh);
 
 // E on every diagonal leaf block, row-major [3m][3m] at each leaf's offset (hm_build.hip)
 void leaf_blocks_coef(const Op& op, double* out, hipStream_t s);
+
+// G, G / (4 pi), G / (4 pi (1 - nu)) from Young's modulus and Poisson's ratio
+void moduli(double young, double nu, double& G, double& kG, double& kN);
+
+// ILU(0) of the sparse approximation of A11 (hm_ilu.hip)
+void ilu_pc_prepare(Op& op, double fraction, hipStream_t s);
+void ilu_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
 
 // leaf block-Jacobi preconditioner (hm_leafpc.hip)
 void leaf_pc_prepare(Op& op, hipStream_t s);

@@ -274,6 +274,10 @@ struct Krylov {
             leaf_pc_apply(op, nrhs, v, n, z, n, s);
             return;
         }
+        if (pc == HM_PC_ILU) {
+            ilu_pc_apply(op, nrhs, v, n, z, n, s);
+            return;
+        }
         hipLaunchKernelGGL(k_precond, dim3(g1(op.ne * nrhs)), dim3(256), 0, s, pc, op.ne, nrhs, v, n, z, n,
                            op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
     }
@@ -576,7 +580,7 @@ double now_ms()
 void precond_apply(Op& op, int kind, int nrhs, const double* R, int64_t ldr, double* Z, int64_t ldz, hipStream_t s)
 {
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
-    HM_REQUIRE(kind >= HM_PC_NONE && kind <= HM_PC_LEAF, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(kind >= HM_PC_NONE && kind <= HM_PC_ILU, HM_EINVAL, "unknown preconditioner");
     HM_REQUIRE(ldr >= 3 * op.ne && ldz >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(R && Z, HM_EINVAL, "null vector pointer");
     HM_REQUIRE(kind != HM_PC_LEARNED || op.lp.attached, HM_EINVAL, "no learned correction is attached");
@@ -585,6 +589,10 @@ void precond_apply(Op& op, int kind, int nrhs, const double* R, int64_t ldr, dou
     } else if (kind == HM_PC_LEAF) {
         leaf_pc_prepare(op, s);
         leaf_pc_apply(op, nrhs, R, ldr, Z, ldz, s);
+    } else if (kind == HM_PC_ILU) {
+        // the factors of the last solve's fraction, or of the default 1 %
+        ilu_pc_prepare(op, op.ilu.fraction > 0.0 ? op.ilu.fraction : 0.01, s);
+        ilu_pc_apply(op, nrhs, R, ldr, Z, ldz, s);
     } else {
         hipLaunchKernelGGL(k_precond, dim3((unsigned)((op.ne * nrhs + 255) / 256)), dim3(256), 0, s, kind, op.ne,
                            nrhs, R, ldr, Z, ldz, op.d_pc_block.as<double>(), op.d_pc_diag.as<double>());
@@ -600,7 +608,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     HM_REQUIRE(o.restart >= 1 && o.restart <= 256, HM_EINVAL, "restart must be in [1, 256]");
     HM_REQUIRE(o.max_iter >= 1, HM_EINVAL, "max_iter must be positive");
     HM_REQUIRE(o.rtol > 0.0 && o.rtol < 1.0, HM_EINVAL, "rtol must be in (0, 1)");
-    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_LEAF, HM_EINVAL, "unknown preconditioner");
+    HM_REQUIRE(o.precond >= HM_PC_NONE && o.precond <= HM_PC_ILU, HM_EINVAL, "unknown preconditioner");
     HM_REQUIRE(ldb >= 3 * op.ne && ldx >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(d_B && d_X, HM_EINVAL, "null vector pointer");
     HM_REQUIRE(!o.refine || op.ref || op.main.near_prec == HM_F64, HM_EINVAL,
@@ -706,7 +714,10 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
     // run again from x = 0 when the learned solve produced a non-finite
     // value or did not meet the FP64 residual test.
     int pc = o.precond, fallback = HM_FALLBACK_NONE, discarded = 0;
+    const double t_pc = now_ms();
     if (pc == HM_PC_LEAF) leaf_pc_prepare(op, s);
+    if (pc == HM_PC_ILU) ilu_pc_prepare(op, o.ilu_fraction == 0.0 ? 0.01 : o.ilu_fraction, s);
+    const double pc_ms = now_ms() - t_pc;
     if (pc == HM_PC_LEARNED && !op.lp.attached) {
         pc = HM_PC_BLOCK3;
         fallback = HM_FALLBACK_NOT_ATTACHED;
@@ -735,6 +746,11 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
         rep->precond_used = pc;
         rep->fallback = fallback;
         rep->discarded_iterations = discarded;
+        rep->precond_setup_ms = pc_ms;
+        if (pc == HM_PC_ILU) {
+            rep->precond_nnz = op.ilu.nnz;
+            rep->precond_colors = op.ilu.n_colors;
+        }
         for (int i = 0; i < rep->n_history; ++i) rep->history[i] = hist[i];
     }
     return ok ? HM_OK : HM_ENOTCONV;

@@ -323,10 +323,13 @@ void hm_batch_destroy(hm_batch* batch);
  *                  (smallest colour free among lower-id neighbours of the
  *                  pattern), by colour then id, DOFs s1, s2, n; each colour is
  *                  one parallel step of the factorisation and of each
- *                  substitution.  Formed on first use after each
- *                  hm_tangent_set (coefficients, threshold and
- *                  factorisation on the GPU, the pattern's colouring and
- *                  row sort on the host); HM_EINVAL on a zero or non-finite
+ *                  substitution.  The selection, pattern and order depend
+ *                  on E, p and the active mask only: they are formed once
+ *                  (coefficients and threshold on the GPU, colouring and
+ *                  row sort on the host) and kept while p and the mask
+ *                  stay the same; the values and the factorisation are
+ *                  redone on the GPU on first use after each
+ *                  hm_tangent_set.  HM_EINVAL on a zero or non-finite
  *                  pivot.
  */
 enum { HM_PC_NONE = 0, HM_PC_JACOBI = 1, HM_PC_BLOCK3 = 2, HM_PC_LEARNED = 3, HM_PC_LEAF = 4, HM_PC_ILU = 5 };

@@ -16,11 +16,15 @@
 //      greedily (increasing id, smallest colour free among lower-id
 //      neighbours) and sorts each row by elimination order: elements by
 //      (colour, id), DOFs s1, s2, n.
+//      Steps 1-2 depend on E, p and the active mask only and are kept
+//      across tangents; a new D refreshes the values (E's part minus D on
+//      the diagonal blocks) and redoes step 3.
 //   3. ILU(0) on the GPU, one launch per colour: an element's three rows
 //      only meet rows of earlier colours or its own earlier rows, so the
 //      elements of a colour are factorised concurrently, one thread each.
 //   4. Application: forward (unit L) and backward (U) substitution, one
-//      launch per colour each, one thread per (element, column).
+//      launch per colour each, on a DOF-major copy of the vectors (16
+//      lanes per element, one per column).
 // Everything is FP64.  Rows keep the operator's original DOF numbering;
 // only the order of entries inside a row follows the elimination order.
 #include <algorithm>
@@ -159,42 +163,78 @@ __global__ void k_ilu_factor(const int32_t* __restrict__ elems, int n, const int
     }
 }
 
-// z = L^-1 r on the rows of one colour (unit L; earlier colours final)
-__global__ void k_ilu_forward(const int32_t* __restrict__ elems, int n, int nrhs, const int64_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, const int64_t* __restrict__ diag,
-                              const double* __restrict__ val, const double* __restrict__ r, int64_t ldr,
-                              double* __restrict__ z, int64_t ldz)
+// The substitutions run on a DOF-major copy of the vectors: column c of
+// DOF i at zt[16 i + c], so the 16 columns of a neighbour are one 128-byte
+// line and one row entry (value, column) serves 16 lanes.
+constexpr int kCols = 16;
+
+// r [nrhs][ldr] -> zt [n][16] (columns >= nrhs zero), through an LDS tile
+// of 64 DOFs so both sides are read and written contiguously
+__global__ void k_ilu_to_dof_major(int64_t n, int nrhs, const double* __restrict__ r, int64_t ldr,
+                                   double* __restrict__ zt)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nrhs) return;
-    const int c = t % nrhs;
-    const int e = elems[t / nrhs];
-    const double* rc = r + (int64_t)c * ldr;
-    double* zc = z + (int64_t)c * ldz;
-    for (int a = 0; a < 3; ++a) {
-        const int64_t i = 3 * (int64_t)e + a;
-        double s = rc[i];
-        for (int64_t x = rowptr[i]; x < diag[i]; ++x) s -= val[x] * zc[col[x]];
-        zc[i] = s;
+    __shared__ double tile[64][kCols + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    for (int q = threadIdx.x; q < 64 * kCols; q += blockDim.x) {
+        const int c = q / 64, i = q % 64;
+        tile[i][c] = (c < nrhs && i0 + i < n) ? r[(int64_t)c * ldr + i0 + i] : 0.0;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * kCols; q += blockDim.x) {
+        const int i = q / kCols, c = q % kCols;
+        if (i0 + i < n) zt[(i0 + i) * kCols + c] = tile[i][c];
     }
 }
 
-// z = U^-1 z on the rows of one colour (later colours final)
-__global__ void k_ilu_backward(const int32_t* __restrict__ elems, int n, int nrhs, const int64_t* __restrict__ rowptr,
-                               const int32_t* __restrict__ col, const int64_t* __restrict__ diag,
-                               const double* __restrict__ val, double* __restrict__ z, int64_t ldz)
+__global__ void k_ilu_from_dof_major(int64_t n, int nrhs, const double* __restrict__ zt, double* __restrict__ z,
+                                     int64_t ldz)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nrhs) return;
-    const int c = t % nrhs;
-    const int e = elems[t / nrhs];
-    double* zc = z + (int64_t)c * ldz;
+    __shared__ double tile[64][kCols + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    for (int q = threadIdx.x; q < 64 * kCols; q += blockDim.x) {
+        const int i = q / kCols, c = q % kCols;
+        if (i0 + i < n) tile[i][c] = zt[(i0 + i) * kCols + c];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * kCols; q += blockDim.x) {
+        const int c = q / 64, i = q % 64;
+        if (c < nrhs && i0 + i < n) z[(int64_t)c * ldz + i0 + i] = tile[i][c];
+    }
+}
+
+// forward substitution (unit L) on the elements of one colour, in place in
+// zt: 16 elements per workgroup, lane c of an element's 16 lanes = column c
+__global__ void k_ilu_forward(const int32_t* __restrict__ elems, int n, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, const int64_t* __restrict__ diag,
+                              const double* __restrict__ val, double* __restrict__ zt)
+{
+    const int slot = blockIdx.x * (blockDim.x / kCols) + threadIdx.x / kCols;
+    const int c = threadIdx.x % kCols;
+    if (slot >= n) return;
+    const int e = elems[slot];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t i = 3 * (int64_t)e + a;
+        double s = zt[i * kCols + c];
+        for (int64_t x = rowptr[i]; x < diag[i]; ++x) s -= val[x] * zt[(int64_t)col[x] * kCols + c];
+        zt[i * kCols + c] = s;
+    }
+}
+
+// backward substitution (U) on the elements of one colour, in place in zt
+__global__ void k_ilu_backward(const int32_t* __restrict__ elems, int n, const int64_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const int64_t* __restrict__ diag,
+                               const double* __restrict__ val, double* __restrict__ zt)
+{
+    const int slot = blockIdx.x * (blockDim.x / kCols) + threadIdx.x / kCols;
+    const int c = threadIdx.x % kCols;
+    if (slot >= n) return;
+    const int e = elems[slot];
     for (int a = 2; a >= 0; --a) {
         const int64_t i = 3 * (int64_t)e + a;
-        double s = zc[i];
         const int64_t di = diag[i];
-        for (int64_t x = di + 1; x < rowptr[i + 1]; ++x) s -= val[x] * zc[col[x]];
-        zc[i] = s / val[di];
+        double s = zt[i * kCols + c];
+        for (int64_t x = di + 1; x < rowptr[i + 1]; ++x) s -= val[x] * zt[(int64_t)col[x] * kCols + c];
+        zt[i * kCols + c] = s / val[di];
     }
 }
 
@@ -205,14 +245,15 @@ double now_ms()
 
 }  // namespace
 
-void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
+// The structure of the approximation for (fraction, active mask): the kept
+// entries of E, the pattern, its colouring and elimination order, the CSR
+// rows with E's part of the values (val0) and, per element, where its
+// 3x3 diagonal block sits in them (dpos).  D does not enter: a new tangent
+// with the same mask only refreshes the values.
+void ilu_structure(Op& op, double fraction, const std::vector<uint8_t>& mask, hipStream_t s)
 {
-    HM_REQUIRE(fraction > 0.0 && fraction <= 1.0, HM_EINVAL, "ILU fraction must be in (0, 1]");
-    std::lock_guard<std::mutex> guard(op.pc_mu);
     IluPc& F = op.ilu;
-    if (F.current && F.fraction == fraction) return;
-    const double t0 = now_ms();
-    F.current = false;
+    F.structure = false;
     const int64_t ne = op.ne, nd = 3 * ne;
     HM_REQUIRE(nd < (int64_t)1 << 31, HM_EUNSUPPORTED, "ILU preconditioner: more than 2^31 DOFs");
     double G, kG, kN;
@@ -277,10 +318,6 @@ void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
     HM_CHECK_HIP(hipMemcpyAsync(&got, d_cnt.get(), sizeof(got), hipMemcpyDeviceToHost, s));
     if (n_keep > 0)
         HM_CHECK_HIP(hipMemcpyAsync(coo.data(), d_coo.get(), n_keep * sizeof(Coo), hipMemcpyDeviceToHost, s));
-    std::vector<double> D(op.has_D ? 9 * ne : 0);
-    std::vector<uint8_t> mask(op.has_mask ? ne : 0);
-    if (op.has_D) HM_CHECK_HIP(hipMemcpyAsync(D.data(), op.d_D.get(), D.size() * 8, hipMemcpyDeviceToHost, s));
-    if (op.has_mask) HM_CHECK_HIP(hipMemcpyAsync(mask.data(), op.d_mask.get(), ne, hipMemcpyDeviceToHost, s));
     HM_CHECK_HIP(hipStreamSynchronize(s));
     HM_REQUIRE((int64_t)got == n_keep, HM_EINTERNAL, "ILU: kept-entry count differs between passes");
     auto active = [&](int64_t e) { return mask.empty() || mask[e] != 0; };
@@ -292,33 +329,41 @@ void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
     for (int64_t e = 0; e < ne; ++e)
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
-                double v = 0.0;
-                if (!active(e))
-                    v = a == b ? 1.0 : 0.0;
-                else if (op.has_D)
-                    v = -D[9 * e + 3 * a + b];
                 if (!active(e) && a != b) continue;
-                ent.push_back(Coo{3 * e + a, 3 * e + b, v});
+                ent.push_back(Coo{3 * e + a, 3 * e + b, active(e) ? 0.0 : 1.0});
             }
-    // element graph (both directions) and greedy colouring in increasing id
-    std::vector<std::vector<int32_t>> adj(ne);
+    // element graph in both directions (CSR by a counting sort; duplicates kept)
+    std::vector<int64_t> gptr(ne + 1, 0);
     for (const Coo& c : ent) {
         const int64_t e = c.row / 3, f = c.col / 3;
         if (e == f) continue;
-        adj[e].push_back((int32_t)f);
-        adj[f].push_back((int32_t)e);
+        gptr[e + 1]++;
+        gptr[f + 1]++;
     }
+    for (int64_t e = 0; e < ne; ++e) gptr[e + 1] += gptr[e];
+    std::vector<int32_t> gadj(gptr[ne]);
+    {
+        std::vector<int64_t> at(gptr.begin(), gptr.end() - 1);
+        for (const Coo& c : ent) {
+            const int64_t e = c.row / 3, f = c.col / 3;
+            if (e == f) continue;
+            gadj[at[e]++] = (int32_t)f;
+            gadj[at[f]++] = (int32_t)e;
+        }
+    }
+    // greedy colouring in increasing id
     std::vector<int32_t> colour(ne, -1);
     int n_colors = 0;
     {
         std::vector<int64_t> seen;   // seen[c] == e: colour c held by a lower-id neighbour of e
         for (int64_t e = 0; e < ne; ++e) {
-            for (int32_t f : adj[e])
-                if (f < e) {
-                    const int32_t c = colour[f];
-                    if ((size_t)c >= seen.size()) seen.resize(c + 1, -1);
-                    seen[c] = e;
-                }
+            for (int64_t q = gptr[e]; q < gptr[e + 1]; ++q) {
+                const int32_t f = gadj[q];
+                if (f >= e) continue;
+                const int32_t c = colour[f];
+                if ((size_t)c >= seen.size()) seen.resize(c + 1, -1);
+                seen[c] = e;
+            }
             int32_t c = 0;
             while ((size_t)c < seen.size() && seen[c] == e) ++c;
             colour[e] = c;
@@ -332,48 +377,67 @@ void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
     std::vector<int64_t> color_begin(n_colors + 1, 0);
     for (int64_t e = 0; e < ne; ++e) color_begin[colour[e] + 1]++;
     for (int c = 0; c < n_colors; ++c) color_begin[c + 1] += color_begin[c];
-    // rows sorted by elimination order, duplicates (kept diagonal-block entries and -D) summed
-    auto ekey = [&](int64_t d) { return 3 * (int64_t)pos[d / 3] + d % 3; };
-    std::sort(ent.begin(), ent.end(), [&](const Coo& a, const Coo& b) {
-        return a.row != b.row ? a.row < b.row : ekey(a.col) < ekey(b.col);
-    });
+    // rows: bucket the entries by row, sort each row by elimination order,
+    // sum duplicates (kept diagonal-block entries and -D)
+    std::vector<int64_t> bptr(nd + 1, 0);
+    for (const Coo& c : ent) bptr[c.row + 1]++;
+    for (int64_t i = 0; i < nd; ++i) bptr[i + 1] += bptr[i];
+    std::vector<std::pair<int64_t, double>> bucket(ent.size());   // (elimination key, value)
+    std::vector<int32_t> bcol(ent.size());
+    {
+        std::vector<int64_t> at(bptr.begin(), bptr.end() - 1);
+        for (const Coo& c : ent) {
+            const int64_t q = at[c.row]++;
+            bucket[q] = {3 * (int64_t)pos[c.col / 3] + c.col % 3, c.v};
+            bcol[q] = (int32_t)c.col;
+        }
+    }
+    std::vector<int64_t>().swap(gptr);
+    std::vector<int32_t>().swap(gadj);
     std::vector<int64_t> rowptr(nd + 1, 0), diag(nd, -1);
     std::vector<int32_t> col;
     std::vector<double> val;
     col.reserve(ent.size());
     val.reserve(ent.size());
-    for (size_t q = 0; q < ent.size(); ++q) {
-        if (!col.empty() && q > 0 && ent[q].row == ent[q - 1].row && ent[q].col == ent[q - 1].col) {
-            val.back() += ent[q].v;
-            continue;
+    std::vector<int64_t> idx;
+    for (int64_t i = 0; i < nd; ++i) {
+        const int64_t b = bptr[i], e = bptr[i + 1];
+        idx.resize(e - b);
+        std::iota(idx.begin(), idx.end(), b);
+        std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return bucket[x].first < bucket[y].first; });
+        const int64_t ikey = 3 * (int64_t)pos[i / 3] + i % 3;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const int64_t x = idx[q];
+            if (q > 0 && bucket[x].first == bucket[idx[q - 1]].first) {
+                val.back() += bucket[x].second;
+                continue;
+            }
+            if (bucket[x].first == ikey) diag[i] = (int64_t)col.size();
+            col.push_back(bcol[x]);
+            val.push_back(bucket[x].second);
         }
-        rowptr[ent[q].row + 1]++;
-        if (ent[q].col == ent[q].row) diag[ent[q].row] = (int64_t)col.size();
-        col.push_back((int32_t)ent[q].col);
-        val.push_back(ent[q].v);
+        rowptr[i + 1] = (int64_t)col.size();
     }
-    for (int64_t i = 0; i < nd; ++i) rowptr[i + 1] += rowptr[i];
     for (int64_t i = 0; i < nd; ++i) HM_REQUIRE(diag[i] >= 0, HM_EINTERNAL, "ILU: row without a diagonal entry");
-    // ---- upload and factorise colour by colour ----
+    // where each active element's diagonal block sits in its three rows
+    std::vector<int64_t> dpos(9 * ne, -1);
+    for (int64_t e = 0; e < ne; ++e) {
+        if (!active(e)) continue;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t i = 3 * e + a;
+            for (int64_t x = rowptr[i]; x < rowptr[i + 1]; ++x)
+                if (col[x] / 3 == e) dpos[9 * e + 3 * a + col[x] % 3] = x;
+        }
+    }
     upload(F.order, order, s);
     upload(F.pos, pos, s);
     upload(F.rowptr, rowptr, s);
     upload(F.col, col, s);
     upload(F.diag, diag, s);
-    upload(F.val, val, s);
-    DevBuf d_status(sizeof(int));
-    HM_CHECK_HIP(hipMemsetAsync(d_status.get(), 0, sizeof(int), s));
-    for (int c = 0; c < n_colors; ++c) {
-        const int n = (int)(color_begin[c + 1] - color_begin[c]);
-        hipLaunchKernelGGL(k_ilu_factor, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s,
-                           F.order.as<int32_t>() + color_begin[c], n, F.pos.as<int32_t>(), F.rowptr.as<int64_t>(),
-                           F.col.as<int32_t>(), F.diag.as<int64_t>(), F.val.as<double>(), d_status.as<int>());
-    }
-    HM_CHECK_HIP(hipGetLastError());
-    int status = 0;
-    HM_CHECK_HIP(hipMemcpyAsync(&status, d_status.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    upload(F.val0, val, s);
+    upload(F.dpos, dpos, s);
+    F.val.alloc(val.size() * sizeof(double));
     HM_CHECK_HIP(hipStreamSynchronize(s));
-    HM_REQUIRE(status == 0, HM_EINVAL, "ILU(0) of the approximate tangent met a zero or non-finite pivot");
     F.color_begin = color_begin;
     F.n_colors = n_colors;
     F.nnz = (int64_t)col.size();
@@ -381,26 +445,84 @@ void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
     F.near_entries = near_entries;
     F.threshold_key = kth;
     F.fraction = fraction;
+    F.structure = true;
+}
+
+// val = val0 - D on the diagonal blocks of active elements (one thread per element)
+__global__ void k_ilu_values(int64_t ne, const int64_t* __restrict__ dpos, const double* __restrict__ D,
+                             double* __restrict__ val)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    for (int q = 0; q < 9; ++q) {
+        const int64_t x = dpos[9 * e + q];
+        if (x >= 0) val[x] -= D[9 * e + q];
+    }
+}
+
+void ilu_pc_prepare(Op& op, double fraction, hipStream_t s)
+{
+    HM_REQUIRE(fraction > 0.0 && fraction <= 1.0, HM_EINVAL, "ILU fraction must be in (0, 1]");
+    std::lock_guard<std::mutex> guard(op.pc_mu);
+    IluPc& F = op.ilu;
+    if (F.current && F.fraction == fraction) return;
+    const double t0 = now_ms();
+    F.current = false;
+    const int64_t ne = op.ne;
+    // the structure is kept while the fraction and the active mask stay the same
+    std::vector<uint8_t> mask(op.has_mask ? ne : 0);
+    if (op.has_mask) HM_CHECK_HIP(hipMemcpyAsync(mask.data(), op.d_mask.get(), ne, hipMemcpyDeviceToHost, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    uint64_t key = 1469598103934665603ull ^ (uint64_t)op.has_mask;   // FNV-1a of the mask
+    for (uint8_t b : mask) key = (key ^ (uint64_t)(b != 0)) * 1099511628211ull;
+    if (!F.structure || F.fraction != fraction || F.mask_key != key) {
+        ilu_structure(op, fraction, mask, s);
+        F.mask_key = key;
+    }
+    // numeric factorisation of val0 - D, colour by colour
+    HM_CHECK_HIP(hipMemcpyAsync(F.val.get(), F.val0.get(), F.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (op.has_D)
+        hipLaunchKernelGGL(k_ilu_values, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne,
+                           F.dpos.as<int64_t>(), op.d_D.as<double>(), F.val.as<double>());
+    DevBuf d_status(sizeof(int));
+    HM_CHECK_HIP(hipMemsetAsync(d_status.get(), 0, sizeof(int), s));
+    for (int c = 0; c < F.n_colors; ++c) {
+        const int n = (int)(F.color_begin[c + 1] - F.color_begin[c]);
+        hipLaunchKernelGGL(k_ilu_factor, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s,
+                           F.order.as<int32_t>() + F.color_begin[c], n, F.pos.as<int32_t>(), F.rowptr.as<int64_t>(),
+                           F.col.as<int32_t>(), F.diag.as<int64_t>(), F.val.as<double>(), d_status.as<int>());
+    }
+    HM_CHECK_HIP(hipGetLastError());
+    int status = 0;
+    HM_CHECK_HIP(hipMemcpyAsync(&status, d_status.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    HM_REQUIRE(status == 0, HM_EINVAL, "ILU(0) of the approximate tangent met a zero or non-finite pivot");
     F.setup_ms = now_ms() - t0;
     F.current = true;
 }
 
-void ilu_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s)
+void ilu_pc_apply(Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s)
 {
     const IluPc& F = op.ilu;
     HM_REQUIRE(F.current, HM_EINTERNAL, "ILU preconditioner not prepared");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= kCols, HM_EINVAL, "nrhs must be in [1, 16]");
+    const int64_t n = 3 * op.ne;
+    double* zt = op.solve_workspace(s, (size_t)n * kCols * sizeof(double), kWsIlu);
+    const unsigned tiles = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_ilu_to_dof_major, dim3(tiles), dim3(256), 0, s, n, nrhs, r, ldr, zt);
     for (int c = 0; c < F.n_colors; ++c) {
-        const int n = (int)(F.color_begin[c + 1] - F.color_begin[c]);
-        hipLaunchKernelGGL(k_ilu_forward, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, s,
-                           F.order.as<int32_t>() + F.color_begin[c], n, nrhs, F.rowptr.as<int64_t>(),
-                           F.col.as<int32_t>(), F.diag.as<int64_t>(), F.val.as<double>(), r, ldr, z, ldz);
+        const int m = (int)(F.color_begin[c + 1] - F.color_begin[c]);
+        hipLaunchKernelGGL(k_ilu_forward, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s,
+                           F.order.as<int32_t>() + F.color_begin[c], m, F.rowptr.as<int64_t>(), F.col.as<int32_t>(),
+                           F.diag.as<int64_t>(), F.val.as<double>(), zt);
     }
     for (int c = F.n_colors - 1; c >= 0; --c) {
-        const int n = (int)(F.color_begin[c + 1] - F.color_begin[c]);
-        hipLaunchKernelGGL(k_ilu_backward, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, s,
-                           F.order.as<int32_t>() + F.color_begin[c], n, nrhs, F.rowptr.as<int64_t>(),
-                           F.col.as<int32_t>(), F.diag.as<int64_t>(), F.val.as<double>(), z, ldz);
+        const int m = (int)(F.color_begin[c + 1] - F.color_begin[c]);
+        hipLaunchKernelGGL(k_ilu_backward, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s,
+                           F.order.as<int32_t>() + F.color_begin[c], m, F.rowptr.as<int64_t>(), F.col.as<int32_t>(),
+                           F.diag.as<int64_t>(), F.val.as<double>(), zt);
     }
+    hipLaunchKernelGGL(k_ilu_from_dof_major, dim3(tiles), dim3(256), 0, s, n, nrhs, zt, z, ldz);
     HM_CHECK_HIP(hipGetLastError());
 }
 

@@ -127,17 +127,23 @@ struct LearnedPairs {
 // CSR rows in the original DOF numbering, each row's entries in
 // elimination order (elements by colour then id), factors in place.
 struct IluPc {
-    double fraction = -1.0;           // p the factors were built for
-    bool current = false;
+    double fraction = -1.0;           // p the structure was built for
+    bool structure = false;           // selection, pattern and order valid for (fraction, mask_key)
+    uint64_t mask_key = 0;            // hash of the active mask the structure was built for
+    bool current = false;             // factors valid for the current tangent
     int n_colors = 0;
     std::vector<int64_t> color_begin; // offsets of each colour in `order`
     DevBuf order;                     // int32 [N]: elements by (colour, id)
     DevBuf pos;                       // int32 [N]: each element's place in that order
-    DevBuf rowptr, col, diag, val;    // int64 [3N+1], int32 [nnz], int64 [3N], double [nnz]
+    DevBuf rowptr, col, diag, val;    // int64 [3N+1], int32 [nnz], int64 [3N], double [nnz] (factors)
+    DevBuf val0;                      // double [nnz]: E's kept entries (identity rows of inactive elements)
+    DevBuf dpos;                      // int64 [9N]: position of each diagonal-block entry in val (-1: none)
     int64_t nnz = 0, n_kept = 0, near_entries = 0;
     uint64_t threshold_key = 0;
     double setup_ms = 0.0;
 };
+
+enum { kWsKrylov = 0, kWsIlu = 1 };
 
 struct Op {
     int device = 0;
@@ -167,10 +173,11 @@ struct Op {
     // element geometry kept for the learned preconditioner (original order)
     std::vector<double> e_cent, e_frame, e_h;  // [N][3], [N][9], [N] (sqrt of area)
     LearnedPairs lp;
-    // solver workspaces, one per stream (allocated on the first solve on it)
+    // solver workspaces, one per (stream, purpose), allocated on first use:
+    // kWsKrylov for GMRES, kWsIlu for the ILU substitutions
     std::mutex solve_mu;
-    std::map<hipStream_t, std::unique_ptr<DevBuf>> solve_ws;
-    double* solve_workspace(hipStream_t s, size_t bytes);
+    std::map<std::pair<hipStream_t, int>, std::unique_ptr<DevBuf>> solve_ws;
+    double* solve_workspace(hipStream_t s, size_t bytes, int purpose = 0);
     // serialises the lazy preconditioner set-up of concurrent solves
     std::mutex pc_mu;
     hm_op_stats stats{};
@@ -191,7 +198,7 @@ void moduli(double young, double nu, double& G, double& kG, double& kN);
 
 // ILU(0) of the sparse approximation of A11 (hm_ilu.hip)
 void ilu_pc_prepare(Op& op, double fraction, hipStream_t s);
-void ilu_pc_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
+void ilu_pc_apply(Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
 
 // leaf block-Jacobi preconditioner (hm_leafpc.hip)
 void leaf_pc_prepare(Op& op, hipStream_t s);

@@ -187,10 +187,10 @@ __global__ void k_axpby(int nrhs, int64_t n, const double* __restrict__ a, int64
     y[c * ldy + i] = alpha * a[c * lda + i] + beta * b[c * ldb + i];
 }
 
-double* Op::solve_workspace(hipStream_t s, size_t bytes)
+double* Op::solve_workspace(hipStream_t s, size_t bytes, int purpose)
 {
     std::lock_guard<std::mutex> g(solve_mu);
-    std::unique_ptr<DevBuf>& b = solve_ws[s];
+    std::unique_ptr<DevBuf>& b = solve_ws[{s, purpose}];
     if (!b) b.reset(new DevBuf());
     if (b->bytes() < bytes) {
         HM_CHECK_HIP(hipStreamSynchronize(s));

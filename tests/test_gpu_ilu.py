@@ -8,7 +8,9 @@ rounding) with a tangent D and inactive elements:
   * the factors' entry count and colour count equal the oracle's exactly;
   * M^-1 R equals the oracle's triangular solves (bar 1e-10 per column: the
     factors are FP64, the coefficients agree to ~1e-13);
-  * two set-ups give bit-identical results;
+  * two set-ups give bit-identical results; a new tangent (the kept
+    structure with new values) and a new active mask (a new structure)
+    match the oracle again;
   * GMRES with it reaches the dense-LU solution of the exact tangent system
     (ACA 1e-10: bar 1e-8) in fewer iterations than point Jacobi;
   * a fraction outside (0, 1] is rejected (0 selects the default 1 %).
@@ -101,6 +103,22 @@ def test_ilu_matches_the_oracle(case, p):
     _, _ = op.solve(b, precond=hm.HM_PC_ILU, ilu_fraction=p, rtol=1e-10, restart=60, max_iter=600)
     Z2 = op.precond_apply(cuda(R), hm.HM_PC_ILU).cpu().numpy()
     assert np.array_equal(Z, Z2)
+    # a new tangent (other D, same mask: the kept structure, new values),
+    # then a new mask (the structure is formed again)
+    D2 = case["D"] * 1.7
+    D2[:, 2, 0] = 3e8
+    act2 = case["active"].copy()
+    act2[[9, 140]] = False
+    for D_, act_ in ((D2, case["active"]), (D2, act2)):
+        op.set_tangent(cuda(D_), cuda(act_.astype(np.uint8), torch.uint8))
+        _, _ = op.solve(b, precond=hm.HM_PC_ILU, ilu_fraction=p, rtol=1e-10, restart=60, max_iter=600)
+        Zn = op.precond_apply(cuda(R), hm.HM_PC_ILU).cpu().numpy()
+        Fn, on, _, _ = _oracle_precond(dict(case, D=D_, active=act_), p)
+        Zon = OI.ilu0_apply(Fn, on, R)
+        a3 = act_.repeat(3)
+        assert np.array_equal(Zn[:, ~a3], R[:, ~a3])
+        errn = max(np.linalg.norm(Zn[c, a3] - Zon[c, a3]) / np.linalg.norm(Zon[c, a3]) for c in range(5))
+        assert errn <= 1e-10, errn
 
 
 def test_ilu_gmres_reaches_the_dense_solution(case):

@@ -551,6 +551,112 @@ hm_status hm_newton_step(hm_op* op, int n_mat, const hm_interface_material* mats
                          hm_newton_report* rep, void* hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Fluid flow in the discontinuities and the fully coupled step         */
+/* ------------------------------------------------------------------ */
+/*
+ * Paper Sec. 3.2 ("Fluid-flow in the discontinuities"): Galerkin P1
+ * finite elements on the triangles of the mesh, pressure at its vertices
+ * (nodes).  Per element e (area A_e): V picks the normal DD, V_e[a] = A_e/3;
+ * storage S_e = (w_e / M) A_e (1 + [a = b]) / 12; transmissibility
+ * L_e = (w_e k(w_e) / mu) A_e grad N_a . grad N_b, with the hydraulic width
+ * w_e = w0_e + delta_n,e and k(w) = w^2 / 12 (cubic law) or k0; N_p takes
+ * the mean of an element's nodes to its collocation point (normal row).  A
+ * vertex no element uses carries a decoupled unit storage row.  Only
+ * meshes of triangles (HM_EUNSUPPORTED otherwise).  Independently meshed
+ * fractures do not share nodes, so no fluid passes between them.
+ */
+enum { HM_PERM_CUBIC = 0, HM_PERM_CONSTANT = 1 };
+typedef struct {
+    double M;        /* storage modulus (Pa) of the storage term, > 0 */
+    double mu;       /* fluid viscosity (Pa s), > 0 */
+    int perm_law;    /* HM_PERM_CUBIC (k = w^2 / 12) or HM_PERM_CONSTANT (k = k0) */
+    double k0;       /* permeability (m^2) of HM_PERM_CONSTANT, > 0 */
+} hm_flow_params;
+
+typedef struct hm_flow hm_flow;
+/* Flow problem on the mesh's triangles (host connectivity copied; the
+ * pattern, its node colouring and the assembly maps are built here). */
+hm_status hm_flow_create(const hm_mesh* mesh, const hm_flow_params* params, void* hip_stream, hm_flow** out);
+void hm_flow_destroy(hm_flow* flow);
+int64_t hm_flow_num_nodes(const hm_flow* flow);
+int64_t hm_flow_nnz(const hm_flow* flow);
+/*
+ * S and L assembled on the GPU at hydraulic widths d_w [N] (device), as
+ * CSR copies on the host: rowptr [n + 1], col [nnz] (node ids; each row's
+ * columns in the order of the node colouring), S [nnz], L [nnz]; any
+ * output may be NULL.  Synchronous.
+ */
+hm_status hm_flow_matrices(const hm_flow* flow, const double* d_w, int64_t* rowptr, int32_t* col, double* S,
+                           double* L, void* hip_stream);
+
+/*
+ * One implicit step of the coupled hydro-mechanical problem (Sec. 3.3):
+ * Newton's method on the unknowns (dd [N][3], dp [n]) of
+ *   r_m = dT'o - dT'(dd) + E dd + N_p dp - eta (dd - dd_prev) / dt
+ *   r_f = V dd + (S + dt L)(w) dp + dt L(w) (p_n - p_o) - dt f
+ * (w at the end of the step, dT'(dd) from hm_interface_update), with the
+ * exact Jacobian [A11 N_p; A21 S + dt L], A11 = E - eta/dt - C^ep,
+ * A21 = V + dS/dd dp + dt dL/dd (dp + p_n - p_o).  Each Jacobian system is
+ * solved by right-preconditioned flexible GMRES with the paper's upper
+ * block-triangular preconditioner P_up = [A11 N_p; 0 S~],
+ * S~ = S + dt L - A21 diag(A11)^-1 N_p (Sec. 3.3.1): z2 = S~^-1 y2 by ILU(0)
+ * of S~ (nodes coloured greedily, elimination by colour), then
+ * A11 z1 = y1 - N_p z2 by GMRES on the operator's tangent system
+ * (opts.inner).  Unknowns and residuals are scaled per block (Sec. 3.3.2):
+ * the solver works on diag(s_R) J diag(1/s_X); convergence is judged on
+ * sqrt(|s_R,m r_m|^2 + |s_R,f r_f|^2).
+ *   d_p_n, d_p_o [n]  pressure at the start of the step and the initial one
+ *   d_source [n]      fluid source rate per node (m^3/s), or NULL
+ *   d_w0 [N]          hydraulic width at zero normal DD (m)
+ *   d_dn_start [N]    total normal DD at the start of the step, or NULL (0)
+ *   d_dd, d_dpn       in: initial guess; out: the increments
+ * Other arguments as hm_newton_step (no inactive elements: HM_EUNSUPPORTED
+ * if the operator has a mask).  Synchronises the stream; the operator's
+ * tangent is left at the returned state.  HM_ENOTCONV when the tolerance
+ * is not met within max_newton iterations.
+ */
+typedef struct {
+    int max_newton;        /* Newton iterations, 0..63; default 25 */
+    double rtol, atol;     /* stop when the scaled norm <= max(rtol x first, atol); default 1e-8, 0 */
+    double scales[4];      /* s_X mechanics (1/m), s_X flow (1/Pa), s_R mechanics (1/Pa), s_R flow (1/m^3);
+                              <= 0: 1 */
+    int outer_restart;     /* FGMRES restart, 1..200; default 30 */
+    int outer_max_iter;    /* FGMRES iterations per Jacobian solve; default 300 */
+    double outer_rtol;     /* relative tolerance of each Jacobian solve (scaled); default 1e-6 */
+    hm_solve_opts inner;   /* the A11 solves inside P_up; default: 3x3 block-Jacobi, rtol 1e-4, max_iter 500 */
+} hm_coupled_opts;
+
+typedef struct {
+    int iterations;            /* Newton iterations (Jacobian solves) */
+    int converged;
+    int n_history;             /* residual evaluations */
+    double residual[64];       /* scaled residual norm */
+    double residual_mech[64];  /* ||r_m|| (Pa) */
+    double residual_flow[64];  /* ||r_f|| (m^3) */
+    int outer_iterations[64];  /* FGMRES iterations of each Jacobian solve */
+    int inner_iterations[64];  /* A11 GMRES iterations summed over that solve's preconditioner applications */
+    int64_t modes[5];          /* elements per interface mode at the returned state */
+    double ms;
+} hm_coupled_report;
+
+void hm_coupled_opts_default(hm_coupled_opts* opts);
+hm_status hm_coupled_step(hm_op* op, const hm_flow* flow, int n_mat, const hm_interface_material* mats,
+                          const int32_t* d_mat_id, const double* d_t, const double* d_dp, const double* d_chi,
+                          const double* d_dT0, const double* d_eta_dt, const double* d_dd_prev, const double* d_p_n,
+                          const double* d_p_o, const double* d_source, const double* d_w0, const double* d_dn_start,
+                          double dt, double* d_dd, double* d_dpn, double* d_t_new, double* d_dp_new,
+                          double* d_chi_new, const hm_coupled_opts* opts, hm_coupled_report* rep, void* hip_stream);
+
+/*
+ * Scale update of Sec. 3.3.2 (host): L = alpha L_old + (1 - alpha) L_new,
+ * then L_old times its ratio to L_old clipped to [rho_min, rho_max] (the
+ * paper uses alpha 0.62, rho_min 0.84, rho_max 1.16); the scaling factors
+ * are s_X = 1 / (L_rate dt_next) and s_R = 1 / L_residual.  HM_EINVAL when
+ * L_old <= 0, L_new < 0, alpha outside [0, 1] or rho_min > 1 > rho_max.
+ */
+hm_status hm_scale_update(double L_old, double L_new, double alpha, double rho_min, double rho_max, double* out);
+
+/* ------------------------------------------------------------------ */
 /* Adaptive time stepping                                               */
 /* ------------------------------------------------------------------ */
 /*

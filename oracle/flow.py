@@ -14,7 +14,9 @@ x_0, x_1, x_2, shape-function gradients grad N_a = n_e x (x_{a+2} - x_{a+1})
   L_e[a][b]   = (w_e k(w_e) / mu) A_e grad N_a . grad N_b   (transmissibility)
   N_p[3e+2][a] = 1 / 3                       (pressure at the collocation point)
 with w_e = w0_e + delta_n,e the hydraulic width (delta_n the total normal
-DD) and k(w) = w^2 / 12 (cubic law) or a constant k0.  Residuals of a
+DD) and k(w) = w^2 / 12 (cubic law) or a constant k0.  A vertex that no
+element uses carries a decoupled unit storage row (its pressure increment
+stays zero).  Residuals of a
 backward-Euler step with unknowns (dd, dp):
   r_m = dT'o - dT'(dd) + E dd + N_p dp - eta (dd - dd_prev) / dt
   r_f = V dd + (S + dt L)(dd) dp + dt L(dd) (p_n - p_o) - dt f
@@ -87,6 +89,9 @@ def assemble(mesh, coef):
         S[np.ix_(nodes, nodes)] += s[e] * mass[e]
         L[np.ix_(nodes, nodes)] += t[e] * stiff[e]
         Np[3 * e + 2, nodes] += 1.0 / 3.0
+    # a vertex no element uses: a decoupled unit storage row
+    unused = np.setdiff1d(np.arange(nn), mesh.conn.ravel())
+    S[unused, unused] = 1.0
     return V, S, L, Np
 
 

@@ -48,3 +48,12 @@ def next_step(dt_n, dt_prev, e_next, e_n, n_its, eps_tol=1e-3, n_target=6, growt
     dt *= (n_its / n_target) ** (-1.0 / 3.0)
     dt = min(dt, growth_max * dt_n)
     return min(max(dt, dt_min), dt_max)
+
+
+def scale_update(L_old, L_new, alpha=0.62, rho_min=0.84, rho_max=1.16):
+    """Scaling of unknowns and residuals (paper Sec. 3.3.2): smooth the new
+    scale with the old one, L = alpha L_old + (1 - alpha) L_new, then keep
+    its ratio to the old one within [rho_min, rho_max].  (The paper names
+    the upper bound rho_min a second time; read as rho_max.)"""
+    smooth = alpha * L_old + (1.0 - alpha) * L_new
+    return L_old * min(max(smooth / L_old, rho_min), rho_max)

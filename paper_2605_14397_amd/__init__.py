@@ -42,8 +42,10 @@ EXPORTS = [
     "hm_learned_set_params", "hm_learned_features", "hm_learned_loss_grad", "hm_learned_train",
     "hm_learned_attach", "hm_learned_detach", "hm_precond_apply", "hm_interface_update",
     "hm_newton_opts_default", "hm_newton_step", "hm_timestep_opts_default", "hm_timestep_next",
-    "hm_lte_estimate",
+    "hm_lte_estimate", "hm_flow_create", "hm_flow_destroy", "hm_flow_num_nodes", "hm_flow_nnz",
+    "hm_flow_matrices", "hm_coupled_opts_default", "hm_coupled_step", "hm_scale_update",
 ]
+HM_PERM_CUBIC, HM_PERM_CONSTANT = 0, 1
 
 
 class HMError(RuntimeError):
@@ -125,6 +127,30 @@ class BatchInfo(ctypes.Structure):
                 ("tune_ms", ctypes.c_double * 5), ("bytes_operators", ctypes.c_int64)]
 
 
+class FlowParams(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_double), ("mu", ctypes.c_double), ("perm_law", ctypes.c_int), ("k0", ctypes.c_double)]
+
+
+class CoupledOpts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("scales", ctypes.c_double * 4), ("outer_restart", ctypes.c_int), ("outer_max_iter", ctypes.c_int),
+                ("outer_rtol", ctypes.c_double), ("inner", SolveOpts)]
+
+
+class CoupledReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("n_history", ctypes.c_int),
+                ("residual", ctypes.c_double * 64), ("residual_mech", ctypes.c_double * 64),
+                ("residual_flow", ctypes.c_double * 64), ("outer_iterations", ctypes.c_int * 64),
+                ("inner_iterations", ctypes.c_int * 64), ("modes", ctypes.c_int64 * 5), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        n, k = self.n_history, self.iterations
+        return {"iterations": k, "converged": bool(self.converged), "residual": list(self.residual[:n]),
+                "residual_mech": list(self.residual_mech[:n]), "residual_flow": list(self.residual_flow[:n]),
+                "outer_iterations": list(self.outer_iterations[:k]), "inner_iterations": list(self.inner_iterations[:k]),
+                "modes": list(self.modes), "ms": self.ms}
+
+
 class InterfaceMaterial(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "k_s", "k_n", "f_peak", "f_res", "psi_peak", "d_c", "c_peak", "sigma_peak", "w_c")]
@@ -190,6 +216,15 @@ def lib():
             "hm_lte_estimate": ([I64, P, D, P, D, P, ctypes.POINTER(D), P], I),
             "hm_newton_step": ([P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(NewtonOpts),
                                 ctypes.POINTER(NewtonReport), P], I),
+            "hm_flow_create": ([P, ctypes.POINTER(FlowParams), P, ctypes.POINTER(P)], I),
+            "hm_flow_destroy": ([P], None),
+            "hm_flow_num_nodes": ([P], I64),
+            "hm_flow_nnz": ([P], I64),
+            "hm_flow_matrices": ([P, P, P, P, P, P, P], I),
+            "hm_coupled_opts_default": ([ctypes.POINTER(CoupledOpts)], None),
+            "hm_coupled_step": ([P, P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
+                                 ctypes.POINTER(CoupledOpts), ctypes.POINTER(CoupledReport), P], I),
+            "hm_scale_update": ([D, D, D, D, D, ctypes.POINTER(D)], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -611,6 +646,112 @@ def learned_features(op: Operator, neighbors: int, stream=None):
     _check(lib().hm_learned_features(op._h, neighbors, P, ctypes.byref(n), ptr(pe), ptr(pf), ptr(feat), ptr(scale),
                                      _stream(stream)))
     return pe, pf, feat, scale
+
+
+# ---------------------------------------------------------------- flow and the coupled step
+def _materials(mats):
+    mats = np.ascontiguousarray(np.atleast_2d(mats), dtype=np.float64)
+    arr = (InterfaceMaterial * max(mats.shape[0], 1))()
+    for i in range(mats.shape[0]):
+        for j, (name, _) in enumerate(InterfaceMaterial._fields_):
+            setattr(arr[i], name, float(mats[i, j]))
+    return mats.shape[0], arr
+
+
+class Flow:
+    """Owner of an hm_flow handle: P1 flow on the triangles of a mesh."""
+
+    def __init__(self, mesh: Mesh, M, mu, perm_law=HM_PERM_CUBIC, k0=0.0, stream=None):
+        p = FlowParams(float(M), float(mu), int(perm_law), float(k0))
+        h = ctypes.c_void_p()
+        _check(lib().hm_flow_create(mesh._h, ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.mesh = mesh
+        self.nn = lib().hm_flow_num_nodes(h)
+        self.nnz = lib().hm_flow_nnz(h)
+
+    def matrices(self, w, stream=None):
+        """(rowptr, col, S, L) host CSR at the hydraulic widths w (CUDA float64 [N])."""
+        import torch
+
+        wc = w.contiguous()
+        _shape(wc, (self.mesh.ne,), "w")
+        rowptr = np.empty(self.nn + 1, np.int64)
+        col = np.empty(self.nnz, np.int32)
+        S = np.empty(self.nnz)
+        L = np.empty(self.nnz)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().hm_flow_matrices(self._h, _dev_ptr(wc, torch.float64), ptr(rowptr), ptr(col), ptr(S), ptr(L),
+                                      _stream(stream)))
+        return rowptr, col, S, L
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_flow_destroy(self._h)
+            self._h = None
+
+
+def coupled_opts(**kw) -> CoupledOpts:
+    o = CoupledOpts()
+    lib().hm_coupled_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k.startswith("inner_"):
+            _set_fields(o.inner, {k[6:]: v}, "inner solve")
+        elif k == "scales":
+            for i, x in enumerate(v):
+                o.scales[i] = float(x)
+        else:
+            _set_fields(o, {k: v}, "coupled")
+    return o
+
+
+def coupled_step(op: Operator, flow: Flow, mats, t, dp, chi, p_n, w0, dt, dT0=None, eta_dt=None, dd_prev=None,
+                 p_o=None, source=None, dn_start=None, dd=None, dpn=None, mat_id=None, raise_on_notconv=True,
+                 stream=None, **opts):
+    """One coupled implicit step (hm_coupled_step).  Element arrays CUDA
+    float64 [N, 3] (t, dp, chi, dT0, eta_dt, dd_prev, dd) or [N] (w0,
+    dn_start); nodal arrays [n] (p_n, p_o, source, dpn).  opts: fields of
+    hm_coupled_opts (scales as a 4-sequence, inner solve fields as inner_*).
+    Returns (dd, dpn, t_new, dp_new, chi_new, report dict)."""
+    import torch
+
+    f64 = torch.float64
+    N, n = op.ne, flow.nn
+    for name, x in (("t", t), ("dp", dp), ("chi", chi), ("dT0", dT0), ("eta_dt", eta_dt), ("dd_prev", dd_prev),
+                    ("dd", dd)):
+        if x is not None:
+            _shape(x, (N, 3), name)
+    for name, x in (("w0", w0), ("dn_start", dn_start), ("mat_id", mat_id)):
+        if x is not None:
+            _shape(x, (N,), name)
+    for name, x in (("p_n", p_n), ("p_o", p_o), ("source", source), ("dpn", dpn)):
+        if x is not None:
+            _shape(x, (n,), name)
+    o = coupled_opts(**opts)
+    n_mat, arr = _materials(mats)
+    dev = t.device
+    dd = torch.zeros(N, 3, dtype=f64, device=dev) if dd is None else dd.clone()
+    dpn = torch.zeros(n, dtype=f64, device=dev) if dpn is None else dpn.clone()
+    outs = [torch.empty(N, 3, dtype=f64, device=dev) for _ in range(3)]
+    keep = [x.contiguous() if x is not None else None
+            for x in (mat_id, t, dp, chi, dT0, eta_dt, dd_prev, p_n, p_o, source, w0, dn_start)]
+    ptrs = [_dev_ptr(x, torch.int32 if i == 0 else f64) if x is not None else None for i, x in enumerate(keep)]
+    rep = CoupledReport()
+    st = lib().hm_coupled_step(op._h, flow._h, n_mat, ctypes.cast(arr, ctypes.c_void_p), *ptrs, float(dt),
+                               _dev_ptr(dd, f64), _dev_ptr(dpn, f64), *[_dev_ptr(x, f64) for x in outs],
+                               ctypes.byref(o), ctypes.byref(rep), _stream(stream))
+    del keep
+    if st != HM_ENOTCONV or raise_on_notconv:
+        _check(st)
+    return dd, dpn, outs[0], outs[1], outs[2], rep.as_dict()
+
+
+def scale_update(L_old, L_new, alpha=0.62, rho_min=0.84, rho_max=1.16):
+    """The smoothed and clipped scale of Sec. 3.3.2 (hm_scale_update)."""
+    out = ctypes.c_double()
+    _check(lib().hm_scale_update(float(L_old), float(L_new), float(alpha), float(rho_min), float(rho_max),
+                                 ctypes.byref(out)))
+    return out.value
 
 
 # ---------------------------------------------------------------- interface law

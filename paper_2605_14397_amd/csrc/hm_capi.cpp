@@ -205,6 +205,76 @@ hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, vo
     });
 }
 
+hm_status hm_flow_create(const hm_mesh* mesh, const hm_flow_params* params, void* hip_stream, hm_flow** out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = nullptr;
+        HM_REQUIRE(mesh && params, HM_EINVAL, "null argument");
+        require_gfx950();
+        std::unique_ptr<hm_flow> h(new hm_flow());
+        h->f = hm::flow_create(mesh->m, *params, (hipStream_t)hip_stream);
+        *out = h.release();
+    });
+}
+
+void hm_flow_destroy(hm_flow* flow) { delete flow; }
+int64_t hm_flow_num_nodes(const hm_flow* flow) { return flow ? hm::flow_num_nodes(*flow->f) : 0; }
+int64_t hm_flow_nnz(const hm_flow* flow) { return flow ? hm::flow_nnz(*flow->f) : 0; }
+
+hm_status hm_flow_matrices(const hm_flow* flow, const double* d_w, int64_t* rowptr, int32_t* col, double* S,
+                           double* L, void* hip_stream)
+{
+    return guarded([&] {
+        HM_REQUIRE(flow && d_w, HM_EINVAL, "null argument");
+        hm::flow_matrices(*flow->f, d_w, rowptr, col, S, L, (hipStream_t)hip_stream);
+    });
+}
+
+void hm_coupled_opts_default(hm_coupled_opts* o)
+{
+    if (!o) return;
+    o->max_newton = 25;
+    o->rtol = 1e-8;
+    o->atol = 0.0;
+    for (int k = 0; k < 4; ++k) o->scales[k] = 1.0;
+    o->outer_restart = 30;
+    o->outer_max_iter = 300;
+    o->outer_rtol = 1e-6;
+    hm_solve_opts_default(&o->inner);
+    o->inner.rtol = 1e-4;
+    o->inner.max_iter = 500;
+}
+
+hm_status hm_coupled_step(hm_op* op, const hm_flow* flow, int n_mat, const hm_interface_material* mats,
+                          const int32_t* d_mat_id, const double* d_t, const double* d_dp, const double* d_chi,
+                          const double* d_dT0, const double* d_eta_dt, const double* d_dd_prev, const double* d_p_n,
+                          const double* d_p_o, const double* d_source, const double* d_w0, const double* d_dn_start,
+                          double dt, double* d_dd, double* d_dpn, double* d_t_new, double* d_dp_new,
+                          double* d_chi_new, const hm_coupled_opts* opts, hm_coupled_report* rep, void* hip_stream)
+{
+    hm_status st = HM_OK;
+    hm_status g = guarded([&] {
+        HM_REQUIRE(op && flow, HM_EINVAL, "null operator or flow problem");
+        hm_coupled_opts o;
+        hm_coupled_opts_default(&o);
+        if (opts) o = *opts;
+        st = hm::coupled_step(op->op, *flow->f, n_mat, mats, d_mat_id, d_t, d_dp, d_chi, d_dT0, d_eta_dt, d_dd_prev,
+                              d_p_n, d_p_o, d_source, d_w0, d_dn_start, dt, d_dd, d_dpn, d_t_new, d_dp_new, d_chi_new,
+                              o, rep, (hipStream_t)hip_stream);
+        if (st == HM_ENOTCONV) hm::set_last_error("the coupled Newton iteration did not reach rtol");
+    });
+    return g != HM_OK ? g : st;
+}
+
+hm_status hm_scale_update(double L_old, double L_new, double alpha, double rho_min, double rho_max, double* out)
+{
+    return guarded([&] {
+        HM_REQUIRE(out, HM_EINVAL, "out is null");
+        *out = hm::scale_update(L_old, L_new, alpha, rho_min, rho_max);
+    });
+}
+
 void hm_batch_opts_default(hm_batch_opts* o)
 {
     if (!o) return;

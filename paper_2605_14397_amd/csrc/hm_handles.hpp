@@ -17,6 +17,10 @@ struct hm_batch {
     hm::Batch* b = nullptr;
     ~hm_batch() { hm::batch_destroy(b); }
 };
+struct hm_flow {
+    hm::Flow* f = nullptr;
+    ~hm_flow() { hm::flow_destroy(f); }
+};
 struct hm_learned {
     hm::Learned net;
     hm_learned(int h, int k, uint64_t seed) : net(h, k, seed) {}

@@ -254,6 +254,22 @@ void learned_train(Learned& L, Op& op, int n, const double* B, int64_t ldb, cons
 void learned_attach(Op& op, const Learned& L, hipStream_t s);
 void learned_apply(const Op& op, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, hipStream_t s);
 
+// flow in the discontinuities and the coupled step (hm_flow.hip)
+struct Flow;
+Flow* flow_create(const Mesh& m, const hm_flow_params& p, hipStream_t s);
+void flow_destroy(Flow* f);
+int64_t flow_num_nodes(const Flow& f);
+int64_t flow_nnz(const Flow& f);
+void flow_matrices(const Flow& F, const double* d_w, int64_t* rowptr, int32_t* col, double* S, double* L,
+                   hipStream_t s);
+hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_material* mats, const int32_t* d_mat_id,
+                       const double* d_t, const double* d_dp, const double* d_chi, const double* d_dT0,
+                       const double* d_eta_dt, const double* d_dd_prev, const double* d_p_n, const double* d_p_o,
+                       const double* d_source, const double* d_w0, const double* d_dn_start, double dt, double* d_dd,
+                       double* d_dpn, double* d_t_new, double* d_dp_new, double* d_chi_new, const hm_coupled_opts& o,
+                       hm_coupled_report* rep, hipStream_t s);
+double scale_update(double L_old, double L_new, double alpha, double rho_min, double rho_max);
+
 // batches (hm_batch.cpp)
 struct Batch;
 Batch* batch_create(const std::vector<Op*>& ops, const hm_batch_opts& o, hipStream_t s);

@@ -185,7 +185,9 @@ def test_structs_match_c_layout(tmp_path):
              ("hm_build_opts", hm.BuildOpts), ("hm_op_stats", hm.OpStats), ("hm_batch_opts", hm.BatchOpts),
              ("hm_batch_info", hm.BatchInfo), ("hm_plan_info", hm.PlanInfo),
              ("hm_interface_material", hm.InterfaceMaterial), ("hm_newton_opts", hm.NewtonOpts),
-             ("hm_newton_report", hm.NewtonReport), ("hm_timestep_opts", hm.TimestepOpts)]
+             ("hm_newton_report", hm.NewtonReport), ("hm_timestep_opts", hm.TimestepOpts),
+             ("hm_flow_params", hm.FlowParams), ("hm_coupled_opts", hm.CoupledOpts),
+             ("hm_coupled_report", hm.CoupledReport)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hmdd.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -262,3 +264,20 @@ def test_unknown_options_are_rejected():
     with pytest.raises(hm.HMError, match="unknown solve option"):
         hm.solve_opts(precon=hm.HM_PC_LEAF)
     assert hm.solve_opts(precond=hm.HM_PC_LEAF).precond == hm.HM_PC_LEAF
+
+
+def test_scale_update_matches_the_oracle():
+    """The scale update of Sec. 3.3.2 on the host against the oracle's
+    restatement, on seeded inputs spanning both clips and the open range."""
+    from oracle import timestep as OT
+
+    rng = np.random.default_rng(77)
+    for _ in range(200):
+        old = 10 ** rng.uniform(-6, 6)
+        new = old * 10 ** rng.uniform(-1, 1)
+        a, lo, hi = rng.uniform(0, 1), rng.uniform(0.5, 1.0), rng.uniform(1.0, 2.0)
+        assert hm.scale_update(old, new, a, lo, hi) == pytest.approx(OT.scale_update(old, new, a, lo, hi), rel=1e-15)
+    for bad in ((0.0, 1.0, 0.5, 0.8, 1.2), (1.0, -1.0, 0.5, 0.8, 1.2), (1.0, 1.0, 1.5, 0.8, 1.2),
+                (1.0, 1.0, 0.5, 1.1, 1.2), (1.0, 1.0, 0.5, 0.8, 0.9)):
+        with pytest.raises(hm.HMError):
+            hm.scale_update(*bad)

@@ -77,3 +77,16 @@ def test_library_controller_matches_the_oracle():
                   growth_max=float(rng.uniform(1.05, 2.0)), dt_min=1e-3, dt_max=5.0)
         assert hm.timestep_next(dt_n, dt_prev, e_next, e_n, n_its, **kw) == pytest.approx(
             ts.next_step(dt_n, dt_prev, e_next, e_n, n_its, **kw), rel=1e-13)
+
+
+def test_scale_update_fixed_point_clipping_and_smoothing():
+    """The scale update of Sec. 3.3.2: an unchanged scale stays, the ratio
+    to the old scale never leaves [rho_min, rho_max], and inside the clips it
+    is the alpha-weighted mean."""
+    from oracle.timestep import scale_update
+
+    assert scale_update(3.0, 3.0) == 3.0
+    assert scale_update(1.0, 100.0) == pytest.approx(1.16)
+    assert scale_update(1.0, 0.0) == pytest.approx(0.84)
+    assert scale_update(2.0, 2.2, alpha=0.62) == pytest.approx(0.62 * 2.0 + 0.38 * 2.2)
+    assert scale_update(2.0, 2.2, alpha=1.0) == 2.0

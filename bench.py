@@ -1454,8 +1454,10 @@ def bench_coupled(args):
     FGMRES(30) with P_up to 1e-4, its A11 solves by GMRES(50) to 1e-3 with
     the paper's point Jacobi, 3x3 or leaf block-Jacobi or ILU(0) of the 1 %
     largest near-field entries; scales of Sec. 3.3.2 carried from step to
-    step.  Reports Newton iterations per step, outer (Jacobian) and inner
-    (A11) iterations per solve and the time per step, as in Tab. 1-2."""
+    step; the ILU variant also with the paper's second Schur complement (S~
+    from the ILU approximation of A11, applied matrix-free, inverted by
+    GMRES to 1e-2).  Reports Newton iterations per step, outer (Jacobian) and
+    inner (A11) iterations per solve and the time per step, as in Tab. 1-2."""
     import numpy as np
     import torch
 
@@ -1481,8 +1483,8 @@ def bench_coupled(args):
     log(f"coupled: HF x fault {m.ne} triangles, {m.nv} nodes, injection {src.sum()} m^3/s, dt {dt} s")
     steps = max(1, min(args.steps, 12))
     res = {}
-    for name, pc in (("jacobi", hm.HM_PC_JACOBI), ("block3", hm.HM_PC_BLOCK3), ("leaf", hm.HM_PC_LEAF),
-                     ("ilu", hm.HM_PC_ILU)):
+    for name, pc, schur in (("jacobi", hm.HM_PC_JACOBI, 0), ("block3", hm.HM_PC_BLOCK3, 0),
+                            ("leaf", hm.HM_PC_LEAF, 0), ("ilu", hm.HM_PC_ILU, 0), ("ilu_schur_ilu", hm.HM_PC_ILU, 1)):
         op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6)
         fl = hm.Flow(hm.Mesh.from_workload(m), 2.2e9, 1e-3, hm.HM_PERM_CUBIC)
         t, dp, chi, mid = cu(p["t"]), cu(p["dp"]), cu(p["chi"]), cu(p["mat_id"], torch.int32)
@@ -1499,7 +1501,8 @@ def bench_coupled(args):
                 op, fl, p["mats"], t, dp, chi, p_n, cu(w0), dt, eta_dt=eta_dt, dd_prev=dd_prev,
                 p_o=torch.zeros_like(p_n), source=cu(src), dn_start=dn, mat_id=mid, scales=scales, rtol=1e-6,
                 outer_rtol=1e-4, outer_restart=30, outer_max_iter=200, inner_precond=pc, inner_rtol=1e-3,
-                inner_restart=50, inner_max_iter=1000, max_newton=20, raise_on_notconv=False)
+                inner_restart=50, inner_max_iter=1000, max_newton=20, schur=schur, schur_rtol=1e-2,
+                schur_max_iter=30, raise_on_notconv=False)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             rec["time_s"].append(round(wall, 3))
@@ -1508,8 +1511,10 @@ def bench_coupled(args):
             rec["outer_per_solve"].append(round(its / max(1, rep["iterations"]), 2))
             rec["inner_per_a11_solve"].append(round(sum(rep["inner_iterations"]) / its, 2))
             rec["converged"] &= rep["converged"]
+            rec.setdefault("schur_per_solve", []).append(round(sum(rep["schur_iterations"]) / its, 2))
             log(f"coupled {name} step {k}: {wall:.3f} s, Newton {rep['iterations']}, outer {rep['outer_iterations']}, "
-                f"inner {rep['inner_iterations']}, modes {rep['modes']}, max dp {float(dpn.max()) / 1e6:.3f} MPa")
+                f"inner {rep['inner_iterations']}, schur {rep['schur_iterations']}, modes {rep['modes']}, "
+                f"max dp {float(dpn.max()) / 1e6:.3f} MPa")
             # the next step starts from this one's end; scales follow Sec. 3.3.2
             rate_x = [float(dd.abs().max()) / dt, float(dpn.abs().max()) / dt]
             Lx = [hm.scale_update(Lx[i], max(rate_x[i], 1e-30)) for i in range(2)]

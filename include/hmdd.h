@@ -624,6 +624,12 @@ typedef struct {
     int outer_max_iter;    /* FGMRES iterations per Jacobian solve; default 300 */
     double outer_rtol;     /* relative tolerance of each Jacobian solve (scaled); default 1e-6 */
     hm_solve_opts inner;   /* the A11 solves inside P_up; default: 3x3 block-Jacobi, rtol 1e-4, max_iter 500 */
+    int schur;             /* 0 (default): S~ = S + dt L - A21 diag(A11)^-1 N_p, sparse, applied by its ILU(0);
+                              1: the paper's second choice, S~ = S + dt L - A21 A~11^-1 N_p with A~11 the ILU(0)
+                              of C^ep plus the fraction inner.ilu_fraction of the near field (HM_PC_ILU), applied
+                              matrix-free and inverted by GMRES preconditioned with the first choice */
+    double schur_rtol;     /* relative tolerance of that GMRES; default 1e-2 */
+    int schur_max_iter;    /* its iterations, 1..200 (no restart); default 30 */
 } hm_coupled_opts;
 
 typedef struct {
@@ -637,6 +643,7 @@ typedef struct {
     int inner_iterations[64];  /* A11 GMRES iterations summed over that solve's preconditioner applications */
     int64_t modes[5];          /* elements per interface mode at the returned state */
     double ms;
+    int schur_iterations[64];  /* schur = 1: S~ GMRES iterations summed over that solve's applications */
 } hm_coupled_report;
 
 void hm_coupled_opts_default(hm_coupled_opts* opts);

@@ -134,20 +134,23 @@ class FlowParams(ctypes.Structure):
 class CoupledOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
                 ("scales", ctypes.c_double * 4), ("outer_restart", ctypes.c_int), ("outer_max_iter", ctypes.c_int),
-                ("outer_rtol", ctypes.c_double), ("inner", SolveOpts)]
+                ("outer_rtol", ctypes.c_double), ("inner", SolveOpts), ("schur", ctypes.c_int),
+                ("schur_rtol", ctypes.c_double), ("schur_max_iter", ctypes.c_int)]
 
 
 class CoupledReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("n_history", ctypes.c_int),
                 ("residual", ctypes.c_double * 64), ("residual_mech", ctypes.c_double * 64),
                 ("residual_flow", ctypes.c_double * 64), ("outer_iterations", ctypes.c_int * 64),
-                ("inner_iterations", ctypes.c_int * 64), ("modes", ctypes.c_int64 * 5), ("ms", ctypes.c_double)]
+                ("inner_iterations", ctypes.c_int * 64), ("modes", ctypes.c_int64 * 5), ("ms", ctypes.c_double),
+                ("schur_iterations", ctypes.c_int * 64)]
 
     def as_dict(self):
         n, k = self.n_history, self.iterations
         return {"iterations": k, "converged": bool(self.converged), "residual": list(self.residual[:n]),
                 "residual_mech": list(self.residual_mech[:n]), "residual_flow": list(self.residual_flow[:n]),
                 "outer_iterations": list(self.outer_iterations[:k]), "inner_iterations": list(self.inner_iterations[:k]),
+                "schur_iterations": list(self.schur_iterations[:k]),
                 "modes": list(self.modes), "ms": self.ms}
 
 

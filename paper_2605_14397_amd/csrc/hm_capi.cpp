@@ -244,6 +244,9 @@ void hm_coupled_opts_default(hm_coupled_opts* o)
     hm_solve_opts_default(&o->inner);
     o->inner.rtol = 1e-4;
     o->inner.max_iter = 500;
+    o->schur = 0;
+    o->schur_rtol = 1e-2;
+    o->schur_max_iter = 30;
 }
 
 hm_status hm_coupled_step(hm_op* op, const hm_flow* flow, int n_mat, const hm_interface_material* mats,

@@ -513,8 +513,9 @@ struct CoupledWs {
     DevBuf buf;
     double *Ex, *r, *dpress, *cep, *D, *coef, *S, *L, *A22, *St, *Sf, *a21, *pnpo;
     double *V, *Z, *w, *t1, *t2, *partial, *hdev, *x;
+    double *Vs, *sq, *sx, *u3;   // the Schur-complement GMRES of the second choice
     int32_t* mode;
-    int m;
+    int m, ms;
 };
 
 struct Coupled {
@@ -526,6 +527,9 @@ struct Coupled {
     double dt;
     hm_solve_opts inner;
     int inner_its = 0;
+    int schur = 0;             // 0: S~ from diag(A11); 1: S~ from the ILU approximation of A11
+    double schur_rtol = 1e-2;
+    int schur_its = 0;
 
     unsigned g(int64_t n) const { return (unsigned)((n + 255) / 256); }
 
@@ -546,25 +550,111 @@ struct Coupled {
         hipLaunchKernelGGL(k_axpy, dim3(g(W.nn)), dim3(256), 0, s, W.nn, sR[1], y + n3, y + n3, 0);
     }
 
-    // z = diag(sX) P_up^-1 diag(1/sR) y
-    void prec(const double* y, double* z)
+    // z = ILU(0)(S~ of the first choice)^-1 r, colour by colour
+    void schur_diag_solve(const double* r, double* z)
     {
-        const int64_t n3 = W.n3;
-        // z2 = S~^-1 (y2 / sR_f) by ILU(0): forward then backward, colour by colour
-        hipLaunchKernelGGL(k_axpy, dim3(g(W.nn)), dim3(256), 0, s, W.nn, 1.0 / sR[1], y + n3, W.t2, 0);
-        double* z2 = z + n3;
         for (int c = 0; c < F.n_colors; ++c) {
             const int n = (int)(F.color_begin[c + 1] - F.color_begin[c]);
             hipLaunchKernelGGL(k_node_ilu_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                                F.order.as<int32_t>() + F.color_begin[c], n, F.rowptr.as<int64_t>(),
-                               F.col.as<int32_t>(), F.diag.as<int64_t>(), W.Sf, W.t2, z2);
+                               F.col.as<int32_t>(), F.diag.as<int64_t>(), W.Sf, r, z);
         }
         for (int c = F.n_colors - 1; c >= 0; --c) {
             const int n = (int)(F.color_begin[c + 1] - F.color_begin[c]);
             hipLaunchKernelGGL(k_node_ilu_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                                F.order.as<int32_t>() + F.color_begin[c], n, F.rowptr.as<int64_t>(),
-                               F.col.as<int32_t>(), F.diag.as<int64_t>(), W.Sf, z2);
+                               F.col.as<int32_t>(), F.diag.as<int64_t>(), W.Sf, z);
         }
+    }
+
+    // y = S~ x of the second choice: A22 x - A21 A~11^-1 N_p x, with A~11^-1
+    // the ILU solve of C^ep plus the kept near-field entries
+    void schur_apply(const double* x, double* y)
+    {
+        const int64_t n3 = W.n3;
+        HM_CHECK_HIP(hipMemsetAsync(W.t1, 0, sizeof(double) * n3, s));
+        hipLaunchKernelGGL(k_np_add, dim3(g(op.ne)), dim3(256), 0, s, op.ne, F.conn.as<int32_t>(), x, 1.0, W.t1);
+        ilu_pc_apply(op, 1, W.t1, n3, W.u3, n3, s);
+        hipLaunchKernelGGL(k_axpy, dim3(g(n3)), dim3(256), 0, s, n3, -1.0, W.u3, W.u3, 0);
+        hipLaunchKernelGGL(k_flow_rows, dim3(g(W.nn)), dim3(256), 0, s, W.nn, F.nptr.as<int64_t>(),
+                           F.nel.as<int32_t>(), F.na.as<uint8_t>(), W.a21, F.rowptr.as<int64_t>(), F.col.as<int32_t>(),
+                           W.A22, W.u3, x, y);
+    }
+
+    // x = S~^-1 b (second choice) by GMRES without restart, right-preconditioned
+    // with the first choice's ILU(0), to schur_rtol
+    void schur_solve(const double* b, double* x)
+    {
+        const int64_t nn = W.nn;
+        const int m = W.ms;
+        std::vector<double> h, h2, nrm, H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+        dots_n(nn, b, nn, 1, b, nrm);
+        const double beta = std::sqrt(nrm[0]);
+        if (beta == 0.0) {
+            HM_CHECK_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
+            return;
+        }
+        hipLaunchKernelGGL(k_axpy, dim3(g(nn)), dim3(256), 0, s, nn, 1.0 / beta, b, W.Vs, 0);
+        gv[0] = beta;
+        int k = 0;
+        for (; k < m; ++k) {
+            double* vk = W.Vs + (int64_t)k * nn;
+            double* vn = W.Vs + (int64_t)(k + 1) * nn;
+            schur_diag_solve(vk, W.sq);
+            schur_apply(W.sq, vn);
+            dots_n(nn, W.Vs, nn, k + 1, vn, h);
+            HM_CHECK_HIP(hipMemcpyAsync(W.hdev, h.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_vsub, dim3(g(nn)), dim3(256), 0, s, nn, W.Vs, nn, k + 1, W.hdev, vn);
+            dots_n(nn, W.Vs, nn, k + 1, vn, h2);
+            HM_CHECK_HIP(hipMemcpyAsync(W.hdev, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_vsub, dim3(g(nn)), dim3(256), 0, s, nn, W.Vs, nn, k + 1, W.hdev, vn);
+            dots_n(nn, vn, nn, 1, vn, nrm);
+            double* col = &H[(size_t)k * (m + 1)];
+            for (int i = 0; i <= k; ++i) col[i] = h[i] + h2[i];
+            col[k + 1] = std::sqrt(nrm[0]);
+            if (col[k + 1] > 0.0)
+                hipLaunchKernelGGL(k_axpy, dim3(g(nn)), dim3(256), 0, s, nn, 1.0 / col[k + 1], vn, vn, 0);
+            for (int i = 0; i < k; ++i) {
+                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const double r = std::hypot(col[k], col[k + 1]);
+            cs[k] = r == 0.0 ? 1.0 : col[k] / r;
+            sn[k] = r == 0.0 ? 0.0 : col[k + 1] / r;
+            col[k] = r;
+            col[k + 1] = 0.0;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            ++schur_its;
+            if (std::fabs(gv[k + 1]) <= schur_rtol * beta || !std::isfinite(gv[k + 1])) {
+                ++k;
+                break;
+            }
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double sum = gv[i];
+            for (int l = i + 1; l < k; ++l) sum -= H[(size_t)l * (m + 1) + i] * y[l];
+            const double d = H[(size_t)i * (m + 1) + i];
+            y[i] = d != 0.0 ? sum / d : 0.0;
+        }
+        HM_CHECK_HIP(hipMemsetAsync(W.sx, 0, sizeof(double) * nn, s));
+        HM_CHECK_HIP(hipMemcpyAsync(W.hdev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_vadd, dim3(g(nn)), dim3(256), 0, s, nn, W.Vs, nn, k, W.hdev, W.sx);
+        schur_diag_solve(W.sx, x);
+    }
+
+    // z = diag(sX) P_up^-1 diag(1/sR) y
+    void prec(const double* y, double* z)
+    {
+        const int64_t n3 = W.n3;
+        // z2 = S~^-1 (y2 / sR_f)
+        hipLaunchKernelGGL(k_axpy, dim3(g(W.nn)), dim3(256), 0, s, W.nn, 1.0 / sR[1], y + n3, W.t2, 0);
+        double* z2 = z + n3;
+        if (schur == 1)
+            schur_solve(W.t2, z2);
+        else
+            schur_diag_solve(W.t2, z2);
         // A11 z1 = y1 / sR_m - N_p z2
         hipLaunchKernelGGL(k_axpy, dim3(g(n3)), dim3(256), 0, s, n3, 1.0 / sR[0], y, W.t1, 0);
         hipLaunchKernelGGL(k_np_add, dim3(g(op.ne)), dim3(256), 0, s, op.ne, F.conn.as<int32_t>(), z2, -1.0, W.t1);
@@ -577,18 +667,20 @@ struct Coupled {
         hipLaunchKernelGGL(k_axpy, dim3(g(W.nn)), dim3(256), 0, s, W.nn, sX[1], z2, z2, 0);
     }
 
-    // h[j] = V_j . w for j < J (deterministic: fixed blocks, host sum in order)
-    void dots(const double* V, int J, const double* w, std::vector<double>& h)
+    // h[j] = V_j . w for j < J, vectors of length n with stride ld
+    // (deterministic: fixed blocks, host sum in order)
+    void dots_n(int64_t n, const double* V, int64_t ld, int J, const double* w, std::vector<double>& h)
     {
-        hipLaunchKernelGGL(k_mdot, dim3((unsigned)W.nblk, J), dim3(kRedBlock), 0, s, W.ntot, V, W.ntot, J, w,
-                           W.partial, (int)W.nblk);
-        std::vector<double> part((size_t)J * W.nblk);
+        const int64_t nb = (n + kRedBlock * kRedPer - 1) / (kRedBlock * kRedPer);
+        hipLaunchKernelGGL(k_mdot, dim3((unsigned)nb, J), dim3(kRedBlock), 0, s, n, V, ld, J, w, W.partial, (int)nb);
+        std::vector<double> part((size_t)J * nb);
         HM_CHECK_HIP(hipMemcpyAsync(part.data(), W.partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
         HM_CHECK_HIP(hipStreamSynchronize(s));
         h.assign(J, 0.0);
         for (int j = 0; j < J; ++j)
-            for (int64_t b = 0; b < W.nblk; ++b) h[j] += part[(size_t)j * W.nblk + b];
+            for (int64_t b = 0; b < nb; ++b) h[j] += part[(size_t)j * nb + b];
     }
+    void dots(const double* V, int J, const double* w, std::vector<double>& h) { dots_n(W.ntot, V, W.ntot, J, w, h); }
 
     // right-preconditioned restarted FGMRES with CGS2 on diag(sR) J diag(1/sX) x^ = b^ (x0 = 0);
     // returns iterations, writes x^ to W.x
@@ -695,6 +787,8 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
     HM_REQUIRE(op.ref || op.main.near_prec == HM_F64, HM_EINVAL,
                "the residual needs the FP64 operator (build FP64 or with keep_f64_reference)");
     HM_REQUIRE(!op.has_mask, HM_EUNSUPPORTED, "the coupled step runs on an operator without inactive elements");
+    HM_REQUIRE(o.schur == 0 || (o.schur == 1 && o.schur_max_iter >= 1 && o.schur_max_iter <= 200 && o.schur_rtol > 0),
+               HM_EINVAL, "schur: 0, or 1 with schur_max_iter in [1, 200] and schur_rtol > 0");
     const double t0 = now_ms();
     const int64_t ne = op.ne, n3 = 3 * ne, nn = F.nn;
     Coupled C{op, F, s, {}, {1, 1}, {1, 1}, dt, o.inner, 0};
@@ -708,6 +802,9 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
     W.ntot = n3 + nn;
     W.nblk = (W.ntot + kRedBlock * kRedPer - 1) / (kRedBlock * kRedPer);
     W.m = o.outer_restart;
+    W.ms = o.schur == 1 ? o.schur_max_iter : 0;
+    C.schur = o.schur;
+    C.schur_rtol = o.schur_rtol;
     const int64_t nnz = F.nnz;
     // carve the workspace: the same sequence sizes it (base = null) and then places it
     auto carve = [&](double* base) -> size_t {
@@ -735,8 +832,12 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
         W.x = take(W.ntot);
         W.t1 = take(n3);
         W.t2 = take(nn);
-        W.partial = take((size_t)(W.m + 2) * W.nblk);
-        W.hdev = take(W.m + 2);
+        W.partial = take((size_t)(std::max(W.m, W.ms) + 2) * W.nblk);
+        W.hdev = take(std::max(W.m, W.ms) + 2);
+        W.Vs = take((size_t)(W.ms + 1) * nn);
+        W.sq = take(nn);
+        W.sx = take(nn);
+        W.u3 = take(n3);
         double* mode = take((ne + 1) / 2);   // int32 [N]
         W.mode = reinterpret_cast<int32_t*>(mode);
         return at;
@@ -755,7 +856,7 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
     double* cs = W.coef;   // s, ds, t, dtr
     const Variant& vref = op.ref_variant();
     std::vector<double> hist, hm_, hf_;
-    std::vector<int> outer, inner;
+    std::vector<int> outer, inner, schur_its;
     std::vector<double> rr;
     for (int k = 0;; ++k) {
         // residuals at (dd, dp)
@@ -793,6 +894,7 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
         if (done || k == o.max_newton || !std::isfinite(hist.back())) break;
         // Jacobian: tangent of A11, flow blocks, S~ and its ILU(0)
         tangent_set(op, W.D, nullptr, s);
+        if (o.schur == 1) ilu_pc_prepare(op, o.inner.ilu_fraction == 0.0 ? 0.01 : o.inner.ilu_fraction, s);
         hipLaunchKernelGGL(k_flow_a21, dim3(ge), dim3(256), 0, s, ne, F.conn.as<int32_t>(), F.area.as<double>(),
                            F.stiff.as<double>(), cs + ne, cs + 3 * ne, d_dpn, W.pnpo, dt, W.a21);
         hipLaunchKernelGGL(k_flow_schur, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz,
@@ -818,9 +920,11 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
         // b^ lives in W.w; fgmres uses W.w as scratch only after the first cycle, so keep b^ in r
         HM_CHECK_HIP(hipMemcpyAsync(W.r, W.w, sizeof(double) * W.ntot, hipMemcpyDeviceToDevice, s));
         C.inner_its = 0;
+        C.schur_its = 0;
         const int its = C.fgmres(W.r, o.outer_rtol, o.outer_restart, o.outer_max_iter);
         outer.push_back(its);
         inner.push_back(C.inner_its);
+        schur_its.push_back(C.schur_its);
         // unknowns += diag(1/sX) x^
         hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, 1.0 / C.sX[0], W.x, d_dd,
                            1);
@@ -842,6 +946,7 @@ hm_status coupled_step(Op& op, const Flow& F, int n_mat, const hm_interface_mate
         for (size_t i = 0; i < outer.size() && i < 64; ++i) {
             rep->outer_iterations[i] = outer[i];
             rep->inner_iterations[i] = inner[i];
+            rep->schur_iterations[i] = schur_its[i];
         }
         std::vector<int32_t> hmode(ne);
         HM_CHECK_HIP(hipMemcpyAsync(hmode.data(), W.mode, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, s));

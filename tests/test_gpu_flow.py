@@ -146,3 +146,27 @@ def test_scaling_leaves_the_solution_and_p_up_keeps_outer_iterations_low():
         res.append((dd.cpu().numpy(), dpn.cpu().numpy()))
     assert np.linalg.norm(res[0][0] - res[1][0]) <= 1e-7 * np.linalg.norm(res[0][0])
     assert np.linalg.norm(res[0][1] - res[1][1]) <= 1e-7 * np.linalg.norm(res[0][1])
+
+
+def test_second_schur_choice_gives_the_same_step():
+    """The paper's second approximation of the Schur complement (A~11 the ILU
+    of C^ep plus the largest near-field entries, S~ applied matrix-free and
+    inverted by GMRES preconditioned with the first choice): the same
+    converged step, with no more outer iterations than the first choice."""
+    hm = _hm()
+    m, mech, flow = _case(6)
+    injected = flow["dt"] * flow["f"].sum()
+    sc = (1.0, 1.0, 1e-6, 1.0 / injected)
+    out = {}
+    for schur in (0, 1):
+        dd, dpn, _, _, _, rep = _gpu_step(hm, m, mech, flow, scales=sc, rtol=1e-11, outer_rtol=1e-9,
+                                          inner_rtol=1e-10, inner_max_iter=2000, inner_precond=hm.HM_PC_ILU,
+                                          inner_ilu_fraction=0.05, schur=schur, schur_rtol=1e-6, schur_max_iter=60)
+        assert rep["converged"]
+        out[schur] = (dd.cpu().numpy(), dpn.cpu().numpy(), rep)
+    print("outer iterations: first choice", out[0][2]["outer_iterations"], "second", out[1][2]["outer_iterations"],
+          "schur GMRES", out[1][2]["schur_iterations"], flush=True)
+    assert np.linalg.norm(out[0][0] - out[1][0]) <= 1e-7 * np.linalg.norm(out[0][0])
+    assert np.linalg.norm(out[0][1] - out[1][1]) <= 1e-7 * np.linalg.norm(out[0][1])
+    assert sum(out[1][2]["outer_iterations"]) <= sum(out[0][2]["outer_iterations"])
+    assert all(k > 0 for k in out[1][2]["schur_iterations"])

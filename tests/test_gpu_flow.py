@@ -170,3 +170,63 @@ def test_second_schur_choice_gives_the_same_step():
     assert np.linalg.norm(out[0][1] - out[1][1]) <= 1e-7 * np.linalg.norm(out[0][1])
     assert sum(out[1][2]["outer_iterations"]) <= sum(out[0][2]["outer_iterations"])
     assert all(k > 0 for k in out[1][2]["schur_iterations"])
+
+
+def test_adaptive_coupled_steps_match_the_oracle():
+    """Adaptive time stepping of the coupled problem (Sec. 3.4): each step's
+    truncation error is the larger of the DD estimate and the pressure
+    estimate (each the rate change over the step, relative to the current
+    solution); the controller sets the next step.  Library (coupled step,
+    GPU estimates, host controller) against the oracle's driver (dense
+    coupled Newton, its own estimate and controller) over four steps: the
+    same step sizes, Newton counts and states."""
+    from oracle import timestep as OT
+
+    hm = _hm()
+    m, mech, flow = _case(6)
+    N, nn = m.ne, m.nv
+    E = oracle.dense(m, YOUNG, NU)
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, aca_tol=1e-12)
+    fl = hm.Flow(hm.Mesh.from_workload(m), flow["M"], flow["mu"], hm.HM_PERM_CUBIC)
+    ctl = dict(eps_tol=1e-2, n_target=4, growth_max=1.5)
+    q = float(flow["f"].sum())
+    # oracle state
+    o = dict(t=mech["t_n"].copy(), dpl=np.zeros((N, 3)), chi=np.zeros((N, 3)), p=np.zeros(nn), dn=np.zeros(N),
+             d=np.zeros((N, 3)), dd_prev=None, dp_prev=None)
+    g = dict(t=cuda(mech["t_n"]), dpl=cuda(np.zeros((N, 3))), chi=cuda(np.zeros((N, 3))),
+             p=cuda(np.zeros(nn)), dn=cuda(np.zeros(N)), d=cuda(np.zeros((N, 3))), dd_prev=None, dp_prev=None)
+    dt, dt_prev, e_prev = 0.5, 0.0, 0.0
+    for k in range(4):
+        eta = mech["eta_dt"] * (2.0 / dt)       # eta / dt for this step (eta_dt was given for dt = 2 s)
+        prev_o = np.zeros((N, 3)) if o["dd_prev"] is None else o["dd_prev"] * dt / dt_prev
+        mo = dict(mech, t_n=o["t"], dp_n=o["dpl"], chi_n=o["chi"], eta_dt=eta, dd_prev=prev_o)
+        fo = dict(flow, p_n=o["p"], dt=dt, dn_start=o["dn"])
+        dd_o, dp_o, st_o, hist_o = OF.coupled_newton_step(E, m, mo, fo, (1e6, q * dt), rtol=1e-12)
+        prev_g = cuda(prev_o) if g["dd_prev"] is None else g["dd_prev"] * (dt / dt_prev)
+        dd, dpn, t_new, dpl_new, chi_new, rep = hm.coupled_step(
+            op, fl, mech["mats"], g["t"], g["dpl"], g["chi"], g["p"], cuda(flow["w0"]), dt, eta_dt=cuda(eta),
+            dd_prev=prev_g, p_o=cuda(flow["p_o"]), source=cuda(flow["f"]), dn_start=g["dn"],
+            scales=(1.0, 1.0, 1e-6, 1.0 / (q * dt)), rtol=1e-12, outer_rtol=1e-10, inner_rtol=1e-10,
+            inner_max_iter=2000, max_newton=30)
+        assert rep["converged"] and abs(rep["iterations"] - (len(hist_o) - 1)) <= 1
+        assert np.linalg.norm(dd.cpu().numpy() - dd_o) <= 1e-8 * np.linalg.norm(dd_o)
+        assert np.linalg.norm(dpn.cpu().numpy() - dp_o) <= 1e-8 * np.linalg.norm(dp_o)
+        # truncation errors: DD and pressure, the larger one drives the controller
+        e_o = max(OT.truncation_error(dd_o, dt, o["dd_prev"], dt_prev, o["d"] + dd_o),
+                  OT.truncation_error(dp_o, dt, o["dp_prev"], dt_prev, o["p"] + dp_o))
+        e_g = max(hm.lte_estimate(dd.reshape(-1), dt, None if g["dd_prev"] is None else g["dd_prev"].reshape(-1),
+                                  dt_prev, (g["d"] + dd).reshape(-1)),
+                  hm.lte_estimate(dpn, dt, g["dp_prev"], dt_prev, g["p"] + dpn))
+        assert e_g == pytest.approx(e_o, rel=1e-6), (k, e_g, e_o)
+        n_it = max(1, len(hist_o) - 1)
+        dt_next_o = OT.next_step(dt, dt_prev, e_o, e_prev, n_it, **ctl)
+        dt_next_g = hm.timestep_next(dt, dt_prev, e_g, e_prev, max(1, rep["iterations"]), **ctl)
+        assert dt_next_g == pytest.approx(dt_next_o, rel=1e-6)
+        print(f"step {k}: dt {dt:.4f} s, Newton {rep['iterations']}, e {e_g:.3e}, next {dt_next_g:.4f} s", flush=True)
+        # advance both
+        o.update(t=st_o[0], dpl=st_o[1], chi=st_o[2], p=o["p"] + dp_o, dn=o["dn"] + dd_o[:, 2], d=o["d"] + dd_o,
+                 dd_prev=dd_o, dp_prev=dp_o)
+        g.update(t=t_new, dpl=dpl_new, chi=chi_new, p=g["p"] + dpn, dn=g["dn"] + dd[:, 2], d=g["d"] + dd,
+                 dd_prev=dd, dp_prev=dpn)
+        dt_prev, e_prev, dt = dt, e_g, dt_next_g
+    assert np.linalg.norm(g["p"].cpu().numpy() - o["p"]) <= 1e-8 * np.linalg.norm(o["p"])

@@ -65,6 +65,19 @@ const char* hm_last_error(void);
 /* Library version string. */
 const char* hm_version(void);
 
+/*
+ * Layout check between a caller's copy of this header and the library.
+ *   n     : number of entries in sizes (HM_ABI_N_STRUCTS for this header)
+ *   sizes : host array of sizeof() of the public structs in the order of
+ *           HM_ABI_SIZES below
+ * Returns HM_OK when every size matches the library's own, HM_EINVAL (with
+ * the first mismatching struct named in hm_last_error) otherwise: a program
+ * compiled against an older or newer header would otherwise let the library
+ * write past the end of its report structs.  Typical use:
+ *   size_t s[] = HM_ABI_SIZES;  if (hm_abi_check(HM_ABI_N_STRUCTS, s)) ...
+ */
+hm_status hm_abi_check(int n, const size_t* sizes);
+
 /* ------------------------------------------------------------------ */
 /* Mesh                                                                */
 /* ------------------------------------------------------------------ */
@@ -779,6 +792,15 @@ hm_status hm_learned_train(hm_learned* net, hm_op* op, int n, const double* d_B,
  * HM_PC_LEARNED; hm_tangent_set detaches them.  Synchronous. */
 hm_status hm_learned_attach(hm_op* op, const hm_learned* net, void* hip_stream);
 void hm_learned_detach(hm_op* op);
+
+/* Struct sizes in the order hm_abi_check expects. */
+#define HM_ABI_N_STRUCTS 14
+#define HM_ABI_SIZES                                                                                   \
+    {sizeof(hm_plan_info),       sizeof(hm_build_opts),   sizeof(hm_op_stats),    sizeof(hm_batch_opts), \
+     sizeof(hm_batch_info),      sizeof(hm_solve_opts),   sizeof(hm_solve_report),                        \
+     sizeof(hm_interface_material), sizeof(hm_newton_opts), sizeof(hm_newton_report),                    \
+     sizeof(hm_flow_params),     sizeof(hm_coupled_opts), sizeof(hm_coupled_report),                      \
+     sizeof(hm_timestep_opts)}
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,7 @@ _STATUS = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_ENOMEM", -3: "HM_EDEVICE", -4: "
 
 # symbols declared in include/hmdd.h
 EXPORTS = [
-    "hm_last_error", "hm_version", "hm_mesh_create", "hm_mesh_destroy", "hm_mesh_num_elements",
+    "hm_last_error", "hm_version", "hm_abi_check", "hm_mesh_create", "hm_mesh_destroy", "hm_mesh_num_elements",
     "hm_mesh_frames", "hm_plan_summary", "hm_kernel_block", "hm_build_opts_default",
     "hm_operator_build", "hm_op_destroy", "hm_operator_stats", "hm_operator_apply", "hm_operator_apply_timed",
     "hm_operator_apply_noalloc",
@@ -179,6 +179,7 @@ def lib():
         sig = {
             "hm_last_error": ([], ctypes.c_char_p),
             "hm_version": ([], ctypes.c_char_p),
+            "hm_abi_check": ([I, P], I),
             "hm_mesh_create": ([I, I64, P, I64, P, ctypes.POINTER(P)], I),
             "hm_mesh_destroy": ([P], None),
             "hm_mesh_num_elements": ([P], I64),
@@ -233,6 +234,13 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        # the ctypes mirrors below must have the header's layout, else the
+        # library would write past the end of a report
+        mirrors = (PlanInfo, BuildOpts, OpStats, BatchOpts, BatchInfo, SolveOpts, SolveReport, InterfaceMaterial,
+                   NewtonOpts, NewtonReport, FlowParams, CoupledOpts, CoupledReport, TimestepOpts)
+        sizes = (ctypes.c_size_t * len(mirrors))(*[ctypes.sizeof(m) for m in mirrors])
+        if L.hm_abi_check(len(mirrors), sizes) != HM_OK:
+            raise HMError(HM_EINVAL, "binding and library disagree: " + L.hm_last_error().decode())
         _lib = L
     return _lib
 

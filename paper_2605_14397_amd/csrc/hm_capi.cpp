@@ -28,6 +28,28 @@ const char* hm_last_error(void) { return hm::g_last_error.c_str(); }
 
 const char* hm_version(void) { return "hmdd 0.1 (gfx950)"; }
 
+hm_status hm_abi_check(int n, const size_t* sizes)
+{
+    return guarded([&] {
+        static const size_t mine[] = HM_ABI_SIZES;
+        static const char* names[] = {"hm_plan_info",   "hm_build_opts",          "hm_op_stats",
+                                      "hm_batch_opts",  "hm_batch_info",          "hm_solve_opts",
+                                      "hm_solve_report", "hm_interface_material", "hm_newton_opts",
+                                      "hm_newton_report", "hm_flow_params",       "hm_coupled_opts",
+                                      "hm_coupled_report", "hm_timestep_opts"};
+        static_assert(sizeof(mine) / sizeof(mine[0]) == HM_ABI_N_STRUCTS, "HM_ABI_SIZES length");
+        static_assert(sizeof(names) / sizeof(names[0]) == HM_ABI_N_STRUCTS, "struct name table length");
+        HM_REQUIRE(sizes, HM_EINVAL, "sizes is null");
+        HM_REQUIRE(n == HM_ABI_N_STRUCTS, HM_EINVAL,
+                   "caller lists " + std::to_string(n) + " structs, the library " +
+                       std::to_string(HM_ABI_N_STRUCTS) + ": header and library differ");
+        for (int i = 0; i < n; ++i)
+            HM_REQUIRE(sizes[i] == mine[i], HM_EINVAL,
+                       std::string(names[i]) + " is " + std::to_string(sizes[i]) + " bytes in the caller, " +
+                           std::to_string(mine[i]) + " in the library: rebuild against this header");
+    });
+}
+
 hm_status hm_mesh_create(int nv_per_elem, int64_t n_vert, const double* xyz, int64_t n_elem, const int64_t* conn,
                          hm_mesh** out)
 {

@@ -52,6 +52,8 @@ int main(void)
             c[3] = c[0] + nx + 1;
         }
 
+    size_t sizes[] = HM_ABI_SIZES;
+    CHECK(hm_abi_check(HM_ABI_N_STRUCTS, sizes));
     hm_mesh* mesh = NULL;
     CHECK(hm_mesh_create(4, nv, xyz, ne, conn, &mesh));
     hm_build_opts bo;

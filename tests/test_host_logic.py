@@ -37,6 +37,22 @@ def test_library_exports_every_declared_symbol():
     assert L.hm_version().decode().startswith("hmdd")
 
 
+def test_abi_check_accepts_the_mirrors_and_names_a_mismatch():
+    import ctypes
+    L = hm.lib()            # loading already ran the check with the binding's mirrors
+    mirrors = (hm.PlanInfo, hm.BuildOpts, hm.OpStats, hm.BatchOpts, hm.BatchInfo, hm.SolveOpts, hm.SolveReport,
+               hm.InterfaceMaterial, hm.NewtonOpts, hm.NewtonReport, hm.FlowParams, hm.CoupledOpts,
+               hm.CoupledReport, hm.TimestepOpts)
+    sizes = [ctypes.sizeof(m) for m in mirrors]
+    arr = (ctypes.c_size_t * len(sizes))(*sizes)
+    assert L.hm_abi_check(len(sizes), arr) == hm.HM_OK
+    arr[6] -= 8             # a report struct from an older header
+    assert L.hm_abi_check(len(sizes), arr) == hm.HM_EINVAL
+    assert "hm_solve_report" in L.hm_last_error().decode()
+    assert L.hm_abi_check(len(sizes) - 1, arr) == hm.HM_EINVAL
+    assert L.hm_abi_check(len(sizes), None) == hm.HM_EINVAL
+
+
 def test_mesh_validation_errors():
     tri = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], float)
     with pytest.raises(hm.HMError) as e:

@@ -155,6 +155,9 @@ typedef struct {
     int far_prec;           /* HM_F64, HM_F32 or HM_BF16 for low-rank factors */
     int keep_f64_reference; /* also keep an all-FP64 copy (used by refinement) */
     int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 (rank <= 64); default 1 */
+    int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
+                               as stacked panels of at most this many rows (0: no cap, 1: no stacking); default 64 */
+    int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
 } hm_build_opts;
 
 /* Fill opts with the defaults above (near = far = HM_F64). */
@@ -197,6 +200,10 @@ typedef struct {
     int64_t lowrank_entries_u;         /* the U part of lowrank_entries: sum k c m (read by phase B) */
     int64_t dense_entries_stored;      /* near-field entries stored (coplanar leaf pairs keep only their
                                           shear-shear and normal-normal parts), without padding */
+    int64_t phase_a_tasks;             /* V^T X tasks of one product (main form) */
+    int64_t phase_b_tasks;             /* dense + U T tasks of one product (main form) */
+    int64_t phase_a_stacks;            /* stacked V^T panel sets */
+    int64_t phase_a_partial_bytes;     /* partial sums of V^T X written and re-read per product */
 } hm_op_stats;
 
 hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out);

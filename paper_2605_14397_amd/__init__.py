@@ -57,7 +57,8 @@ class HMError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int), ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int),
-                ("keep_f64_reference", ctypes.c_int), ("recompress", ctypes.c_int)]
+                ("keep_f64_reference", ctypes.c_int), ("recompress", ctypes.c_int), ("stack_rows", ctypes.c_int),
+                ("phase_a_items", ctypes.c_int)]
 
 
 class OpStats(ctypes.Structure):
@@ -70,7 +71,9 @@ class OpStats(ctypes.Structure):
         ("max_dense_bytes_per_leaf", ctypes.c_int64), ("bytes_far_u", ctypes.c_int64),
         ("bytes_far_v", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("rank_sum_aca", ctypes.c_int64),
         ("recompress_ms", ctypes.c_double), ("apply_workspace_bytes", ctypes.c_int64),
-        ("lowrank_entries_u", ctypes.c_int64), ("dense_entries_stored", ctypes.c_int64)]
+        ("lowrank_entries_u", ctypes.c_int64), ("dense_entries_stored", ctypes.c_int64),
+        ("phase_a_tasks", ctypes.c_int64), ("phase_b_tasks", ctypes.c_int64), ("phase_a_stacks", ctypes.c_int64),
+        ("phase_a_partial_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -363,28 +363,31 @@ __device__ inline void store_t(FT* __restrict__ thi, FT* __restrict__ tlo, int64
 }
 
 template <int R, class NT, class FT, class ACC>
-__device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& farS,
-                            typename AccScalar<ACC>::type* __restrict__ tpart, FT* __restrict__ thi,
-                            FT* __restrict__ tlo, int lane)
+__device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const MemberT* __restrict__ members,
+                            const Side& farS, typename AccScalar<ACC>::type* __restrict__ tpart,
+                            FT* __restrict__ thi, FT* __restrict__ tlo, int lane)
 {
     ACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = ACC{0, 0, 0, 0};
     stream_units<R, NT, FT, ACC>(items + T.item_begin, T.n_items, T.rows, T.r0, farS, farS, 0, 1, lane, acc);
-    // only this task's own tiles are written (tiles r0 .. r0 + R - 1 below
-    // ceil(k / 16)): its T chunk holds ceil(k / 32) * 32 rows and its partial
-    // slot ceil(k / 16) * 16 rows
+    // only the window's own tiles (r0 .. r0 + R - 1 below ceil(K / 16)) are
+    // written; rows past the stacked K hold zeros and belong to no member
     const int Rf = __builtin_amdgcn_readfirstlane((T.rows + 15) >> 4);
     if (T.direct) {
-        // the task covers the whole block: write its T chunk directly
+        // the task covers every source leaf: each member's rows go to its
+        // own T chunk (a member's T rows past its rank stay zero)
+        for (int j = 0; j < T.n_mem; ++j) {
+            const MemberT M = members[T.mem_begin + j];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (T.r0 + r < Rf)
-                for (int v = 0; v < 4; ++v)
-                    store_t<FT>(thi, tlo,
-                                T.t_off + bfrag_offset(Mma<FT>::w, 16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v),
-                                                       lane & 15),
-                                acc[r][v]);
+            for (int r = 0; r < R; ++r)
+                if (T.r0 + r < Rf)
+                    for (int v = 0; v < 4; ++v) {
+                        const int q = 16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v) - M.lo;
+                        if (q >= 0 && q < M.rows)
+                            store_t<FT>(thi, tlo, M.t_off + bfrag_offset(Mma<FT>::w, q, lane & 15), acc[r][v]);
+                    }
+        }
         return;
     }
     auto* out = tpart + T.out_off;
@@ -395,11 +398,14 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const Side& f
                 out[(16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
-// One launch per row-tile count R (tasks grouped by R at build time); one
-// wavefront per task.
-template <int R, class FT, class ACC>
+// One launch for every task; one wavefront per task, compiled for each
+// window height (1 to 4 row tiles) and picked per task (wave-uniform).
+// The hardware deals the workgroups out as slots free up, which balances
+// the uneven task lengths.
+template <class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
-                                                const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
+                                                const PanelRef* __restrict__ items,
+                                                const MemberT* __restrict__ members, const Bases* __restrict__ bases)
 {
     typedef typename AccScalar<ACC>::type S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -411,8 +417,15 @@ __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks,
     const Bases B = bases[T.op];
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.xfhi),
                     reinterpret_cast<const char*>(B.xflo), (int)sizeof(FT), Mma<FT>::w};
-    phaseA_wave<R, FT, FT, ACC>(T, items, farS, static_cast<S*>(B.tpart), static_cast<FT*>(B.thi),
-                                static_cast<FT*>(B.tlo), lane);
+    S* tp = static_cast<S*>(B.tpart);
+    FT* th = static_cast<FT*>(B.thi);
+    FT* tl = static_cast<FT*>(B.tlo);
+    switch (__builtin_amdgcn_readfirstlane(window_tiles(T.rows, T.r0))) {
+        case 1: phaseA_wave<1, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
+        case 2: phaseA_wave<2, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
+        case 3: phaseA_wave<3, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
+        default: phaseA_wave<4, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
+    }
 }
 
 // ------------------------------------------------------------------
@@ -427,7 +440,7 @@ __global__ void k_reduceT(const ReduceDesc* __restrict__ rd, const Bases* __rest
     FT* thi = static_cast<FT*>(B.thi);
     FT* tlo = static_cast<FT*>(B.tlo);
     const int Kp = (int)round_up(D.rank, kChunkAlign);
-    const int64_t slot = (int64_t)((D.rank + 15) / 16) * 16 * kNrhs;
+    const int64_t slot = D.slot_stride;
     constexpr int w = Mma<FT>::w;
     for (int e = threadIdx.x; e < Kp * kNrhs; e += blockDim.x) {
         const int row = e / kNrhs, c = e - row * kNrhs;
@@ -464,9 +477,9 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     reduce_and_store<R, ACC>(acc, T.rows, T.r0, Y, T.y_off, red, wave, lane);
 }
 
-// One launch per row-tile count R (tasks are grouped by R at build time),
-// so each kernel is compiled for its own accumulator size.
-template <int R, class NT, class FT, class ACC>
+// One launch for every task (one workgroup each), compiled for each window
+// height and picked per task.
+template <class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, int ntasks,
                                                 const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
 {
@@ -481,7 +494,13 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
                      (int)sizeof(NT), Mma<NT>::w};
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.thi),
                     reinterpret_cast<const char*>(B.tlo), (int)sizeof(FT), Mma<FT>::w};
-    phaseB_task<R, NT, FT, ACC>(T, items, nearS, farS, static_cast<S*>(B.y), red, wave, lane);
+    S* y = static_cast<S*>(B.y);
+    switch (__builtin_amdgcn_readfirstlane(window_tiles(T.rows, T.r0))) {
+        case 1: phaseB_task<1, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 2: phaseB_task<2, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 3: phaseB_task<3, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        default: phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+    }
 }
 
 // ------------------------------------------------------------------
@@ -669,12 +688,12 @@ LaunchSet launch_set(const Variant& v, const void* block)
     L.bases = reinterpret_cast<const Bases*>(static_cast<const char*>(block) + v.ws_layout().bases);
     L.tasksA = v.tasksA.as<TaskA>();
     L.nTasksA = v.nTasksA;
-    for (int r = 0; r < kRowTilesMax; ++r) L.groupA[r] = v.groupA[r];
     L.itemsA = v.itemsA.as<PanelRef>();
+    L.membersA = v.membersA.as<MemberT>();
     L.reduce = v.reduce.as<ReduceDesc>();
     L.nReduce = v.nReduce;
     L.tasksB = v.tasksB.as<TaskB>();
-    for (int r = 0; r < kRowTilesMax; ++r) L.groupB[r] = v.groupB[r];
+    L.nTasksB = v.nTasksB;
     L.itemsB = v.itemsB.as<PanelRef>();
     return L;
 }
@@ -717,43 +736,20 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
             hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
     }
     mark(1);
-    for (int R = kRowTilesMax; R >= 1; --R) {
-        const int begin = L.groupA[R - 1].first, count = L.groupA[R - 1].second;
-        if (count == 0) continue;
+    if (L.nTasksA > 0) {
         // a multiple of 8 workgroups for the XCD-contiguous task map
-        const unsigned grid = (unsigned)round_up((count + 3) / 4, 8);
-        const TaskA* ta = L.tasksA + begin;
-        switch (R) {
-#define HM_CASE(RR)                                                                                              \
-    case RR:                                                                                                     \
-        hipLaunchKernelGGL((k_phaseA<RR, FT, ACC>), dim3(grid), dim3(256), 0, s, ta, count, L.itemsA, L.bases);  \
-        break;
-            HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
-            HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
-#undef HM_CASE
-            default: break;
-        }
+        const unsigned grid = (unsigned)round_up((L.nTasksA + 3) / 4, 8);
+        hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksA, L.nTasksA, L.itemsA,
+                           L.membersA, L.bases);
     }
     mark(2);
     if (L.nReduce > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(L.nReduce), dim3(256), 0, s, L.reduce, L.bases);
     mark(3);
-    for (int R = 1; R <= kRowTilesMax; ++R) {
-        const int begin = L.groupB[R - 1].first, count = L.groupB[R - 1].second;
-        if (count == 0) continue;
-        const unsigned grid = (unsigned)round_up(count, 8);
-        const TaskB* tb = L.tasksB + begin;
-        switch (R) {
-#define HM_CASE(RR)                                                                                            \
-    case RR:                                                                                                   \
-        hipLaunchKernelGGL((k_phaseB<RR, NT, FT, ACC>), dim3(grid), dim3(256), 0, s, tb, count, L.itemsB,      \
-                           L.bases);                                                                           \
-        break;
-            HM_CASE(1) HM_CASE(2) HM_CASE(3) HM_CASE(4) HM_CASE(5) HM_CASE(6)
-            HM_CASE(7) HM_CASE(8) HM_CASE(9) HM_CASE(10) HM_CASE(11) HM_CASE(12)
-#undef HM_CASE
-            default: break;
-        }
+    if (L.nTasksB > 0) {
+        const unsigned grid = (unsigned)round_up(L.nTasksB, 8);
+        hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksB, L.nTasksB, L.itemsB,
+                           L.bases);
     }
     mark(4);
     {

@@ -14,7 +14,7 @@ namespace hm {
 struct Batch {
     std::vector<Op*> ops;
     int near_prec = HM_F64, far_prec = HM_F64;
-    DevBuf bases, tasksA, itemsA, reduce, tasksB, itemsB, segs;
+    DevBuf bases, tasksA, itemsA, membersA, reduce, tasksB, itemsB, segs;
     std::vector<std::unique_ptr<ApplyWs>> ws;  // the batch's own workspace per operator
     LaunchSet L;
     int64_t max_ne = 0, total_ne = 0;
@@ -48,19 +48,21 @@ struct Batch {
         std::vector<Bases> hb;
         std::vector<TaskA> ta;
         std::vector<PanelRef> ia, ib;
+        std::vector<MemberT> ma;
         std::vector<ReduceDesc> rd;
         std::vector<TaskB> tb;
-        std::vector<std::vector<TaskB>> byR(kRowTilesMax);
         ws.resize(ops.size());
         for (size_t k = 0; k < ops.size(); ++k) {
             const Variant& v = ops[k]->main;
             ws[k] = v.new_workspace(s);
             hb.push_back(v.host_bases(ws[k]->block.get()));
-            const int ia0 = (int)ia.size(), ib0 = (int)ib.size();
+            const int ia0 = (int)ia.size(), ib0 = (int)ib.size(), ma0 = (int)ma.size();
             ia.insert(ia.end(), v.hItemsA.begin(), v.hItemsA.end());
+            ma.insert(ma.end(), v.hMembersA.begin(), v.hMembersA.end());
             ib.insert(ib.end(), v.hItemsB.begin(), v.hItemsB.end());
             for (TaskA t : v.hTasksA) {
                 t.item_begin += ia0;
+                t.mem_begin += ma0;
                 t.op = (int32_t)k;
                 ta.push_back(t);
             }
@@ -71,20 +73,17 @@ struct Batch {
             for (TaskB t : v.hTasksB) {
                 t.item_begin += ib0;
                 t.op = (int32_t)k;
-                byR[window_tiles(t.rows, t.r0) - 1].push_back(t);
+                tb.push_back(t);
             }
         }
         L = LaunchSet();
         L.near_prec = near_prec;
         L.far_prec = far_prec;
-        order_tasksA(ta, ia, L.groupA);
-        for (int R = kRowTilesMax; R >= 1; --R) {
-            L.groupB[R - 1] = {(int)tb.size(), (int)byR[R - 1].size()};
-            tb.insert(tb.end(), byR[R - 1].begin(), byR[R - 1].end());
-        }
+        order_tasksA(ta, ia);
         upload(bases, hb, s);
         upload(tasksA, ta, s);
         upload(itemsA, ia, s);
+        upload(membersA, ma, s);
         upload(reduce, rd, s);
         upload(tasksB, tb, s);
         upload(itemsB, ib, s);
@@ -93,9 +92,12 @@ struct Batch {
         L.tasksA = tasksA.as<TaskA>();
         L.nTasksA = (int)ta.size();
         L.itemsA = itemsA.as<PanelRef>();
+        L.membersA = membersA.as<MemberT>();
+
         L.reduce = reduce.as<ReduceDesc>();
         L.nReduce = (int)rd.size();
         L.tasksB = tasksB.as<TaskB>();
+        L.nTasksB = (int)tb.size();
         L.itemsB = itemsB.as<PanelRef>();
         drop_graph();
     }

@@ -717,6 +717,8 @@ struct PackDesc {
     int32_t mode;     // 0: row-major src[row*ld + col]; 1: src[col*ld + row] (source indices)
     int32_t zero_self;  // dense diagonal block: zero entries whose source row and column are one element
     Sel rs, cs;
+    int32_t prow0;    // first row inside the destination panel (stacked panels)
+    int32_t prows;    // destination panel rows (0: rows)
 };
 
 template <class T>
@@ -730,7 +732,8 @@ __global__ void k_pack(const PackDesc* __restrict__ descs, const double* __restr
     const int64_t sc = (int64_t)(col / D.cs.per) * D.cs.stride + D.cs.off + col % D.cs.per;
     double v = D.mode == 0 ? src[D.src_off + sr * D.ld + sc] : src[D.src_off + sc * D.ld + sr];
     if (D.zero_self && sr / 3 == sc / 3) v = 0.0;
-    dst[D.dst_off + panel_offset(D.rows, D.cols, w, row, col)] = cvt<T>(v);
+    const int M = D.prows ? D.prows : D.rows;
+    dst[D.dst_off + panel_offset(M, D.cols, w, D.prow0 + row, col)] = cvt<T>(v);
 }
 
 // FP64 self blocks of each element, written in original element order
@@ -935,24 +938,29 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         v.t_off[b] = tfrag;
         tfrag += round_up(op.lr[b].rank, kChunkAlign) * kNrhs;
     }
-    // ---- low-rank pieces: U slices per target leaf, V^T sub-panels per source leaf ----
-    v.vitems.assign(op.lr.size(), {});
+    // ---- low-rank pieces: U slices per target leaf, stacked V^T sub-panels per source leaf ----
+    v.vgroups.clear();
     v.bytes_far_u = v.bytes_far_v = 0;
     int64_t far_elems = 0;
     PackJob job;
-    for (size_t b = 0; b < op.lr.size(); ++b) {
-        const LowRank& L = op.lr[b];
-        const Cluster& t = p.nodes[L.t_node];
-        const Cluster& sc = p.nodes[L.s_node];
-        const int k = L.rank;
-        if (k == 0) continue;
-        const int nc = L.comps;
-        // sections carried by this factorisation and how to read them from it
+    // sections carried by a factorisation and how to read them from it
+    auto sections = [](const LowRank& L) {
         std::vector<std::pair<int, Sel>> secs;
-        if (nc == 3)
+        if (L.comps == 3)
             secs = {{kShear, kSelShear3}, {kNormal, kSelNormal3}};
         else
             secs = {{L.comp0 == 2 ? kNormal : kShear, kSelAll}};
+        return secs;
+    };
+    // stack key: source cluster and section set (0 both, 1 shear, 2 normal)
+    std::map<std::pair<int, int>, int> group_of;
+    for (size_t b = 0; b < op.lr.size(); ++b) {
+        const LowRank& L = op.lr[b];
+        const Cluster& t = p.nodes[L.t_node];
+        const int k = L.rank;
+        if (k == 0) continue;
+        const int nc = L.comps;
+        const auto secs = sections(L);
         for (int lf = t.first_leaf; lf < t.first_leaf + t.n_leaves; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
             for (const auto& sec : secs) {
@@ -964,16 +972,38 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
                 v.bytes_far_u += panel_elems(rows, k, wf) * prec_bytes(v.far_prec);
             }
         }
+        const int kind = nc == 3 ? 0 : (L.comp0 == 2 ? 2 : 1);
+        // join the open stack of (source cluster, sections) unless it would
+        // pass the row cap, else open a new one
+        auto it = group_of.emplace(std::make_pair(L.s_node, kind), (int)v.vgroups.size());
+        if (it.second) {
+            v.vgroups.emplace_back();
+        } else if (v.stackRowsA > 0 && v.vgroups[it.first->second].K + k > v.stackRowsA) {
+            it.first->second = (int)v.vgroups.size();
+            v.vgroups.emplace_back();
+        }
+        Variant::VGroup& G = v.vgroups[it.first->second];
+        G.blocks.push_back((int)b);
+        G.lo.push_back(G.K);
+        G.K += k;
+    }
+    for (Variant::VGroup& G : v.vgroups) {
+        const LowRank& L0 = op.lr[G.blocks[0]];
+        const Cluster& sc = p.nodes[L0.s_node];
+        const auto secs = sections(L0);
         for (int lf = sc.first_leaf; lf < sc.first_leaf + sc.n_leaves; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
             for (const auto& sec : secs) {
                 const int cols = sec_rows(c.size(), sec.first);
-                job.add(PackDesc{L.v_off + nc * (c.begin - sc.begin), far_elems, nc * L.n, k, cols, 0, 0, kSelAll,
-                                 sec.second});
-                v.vitems[b].push_back(
-                    PanelRef{far_elems, (op.leaf_xoff[lf] + sec_off(c.size(), sec.first)) * kNrhs, k, cols, 1, 0});
-                far_elems += panel_elems(k, cols, wf);
-                v.bytes_far_v += panel_elems(k, cols, wf) * prec_bytes(v.far_prec);
+                for (size_t j = 0; j < G.blocks.size(); ++j) {
+                    const LowRank& L = op.lr[G.blocks[j]];
+                    job.add(PackDesc{L.v_off + L.comps * (c.begin - sc.begin), far_elems, L.comps * L.n, L.rank,
+                                     cols, 0, 0, kSelAll, sec.second, G.lo[j], G.K});
+                }
+                G.items.push_back(
+                    PanelRef{far_elems, (op.leaf_xoff[lf] + sec_off(c.size(), sec.first)) * kNrhs, G.K, cols, 1, 0});
+                far_elems += panel_elems(G.K, cols, wf);
+                v.bytes_far_v += panel_elems(G.K, cols, wf) * prec_bytes(v.far_prec);
             }
         }
     }
@@ -998,16 +1028,10 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
             ib.insert(ib.end(), its.begin(), its.end());
         }
     }
-    // group phase-B tasks by window size (one launch per group), leaf order kept inside a group
-    std::stable_sort(tb.begin(), tb.end(), [](const TaskB& a, const TaskB& b) {
-        return window_tiles(a.rows, a.r0) > window_tiles(b.rows, b.r0);
-    });
-    for (int R = 1; R <= kRowTilesMax; ++R) v.groupB[R - 1] = {0, 0};
-    for (size_t q = 0; q < tb.size(); ++q) {
-        const int R = window_tiles(tb[q].rows, tb[q].r0);
-        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "leaf rows out of range");
-        if (v.groupB[R - 1].second == 0) v.groupB[R - 1].first = (int)q;
-        v.groupB[R - 1].second++;
+    // one launch in leaf order: each XCD runs a contiguous run of leaves
+    for (const TaskB& t : tb) {
+        const int R = window_tiles(t.rows, t.r0);
+        HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "leaf rows out of range");
     }
     v.nTasksB = (int)tb.size();
     v.tfrag_elems = tfrag;
@@ -1019,76 +1043,98 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     HM_CHECK_HIP(hipStreamSynchronize(s));
 }
 
-// Phase-A tasks: each covers at most items_per_task V^T sub-panels of one
-// factorisation; one covered by a single task writes its T chunk directly,
-// others go through partial slots and the reduction.
+// Phase-A tasks: one per row window of a stacked panel set and run of at
+// most items_per_task of its sub-panels.  A set covered by one run writes the
+// members' T chunks directly; the others go through partial slots (one per
+// run, stacked rows) and the reduction.
 void build_tasksA(const Op& op, Variant& v, int items_per_task)
 {
+    (void)op;
     HM_REQUIRE(items_per_task >= 1, HM_EINVAL, "sub-panels per phase-A task must be positive");
     v.leavesPerTaskA = items_per_task;
     std::vector<TaskA>& ta = v.hTasksA;
     std::vector<PanelRef>& ia = v.hItemsA;
+    std::vector<MemberT>& mt = v.hMembersA;
     std::vector<ReduceDesc>& red = v.hReduce;
     ta.clear();
     ia.clear();
+    mt.clear();
     red.clear();
     int64_t tpart = 0;
-    for (size_t b = 0; b < op.lr.size(); ++b) {
-        const LowRank& L = op.lr[b];
-        if (L.rank == 0) continue;
-        const int64_t slot = round_up(L.rank, 16) * kNrhs;
-        ReduceDesc rd{tpart, v.t_off[b], 0, L.rank, 0, 0};
-        const auto& vs = v.vitems[b];
+    for (const Variant::VGroup& G : v.vgroups) {
+        const int64_t slot = round_up(G.K, 16) * kNrhs;
+        HM_REQUIRE(slot < (int64_t)1 << 31, HM_EINTERNAL, "stacked panel too tall");
+        const auto& vs = G.items;
         const bool direct = vs.size() <= (size_t)items_per_task;
+        const int64_t slot0 = tpart;
+        int n_slots = 0;
         for (size_t q0 = 0; q0 < vs.size(); q0 += items_per_task) {
-            TaskA t{direct ? 0 : tpart, v.t_off[b], L.rank, (int32_t)ia.size(), 0, direct ? 1 : 0, 0, 0};
+            TaskA t{direct ? 0 : tpart, G.K, (int32_t)ia.size(), 0, direct ? 1 : 0, 0, 0, 0, 0};
             for (size_t q = q0; q < std::min(vs.size(), q0 + (size_t)items_per_task); ++q) {
                 ia.push_back(vs[q]);
                 t.n_items++;
             }
             // one task per row window; the windows share the items and the slot
-            for (int r0 = 0; r0 < (L.rank + 15) / 16; r0 += kTileWindow) {
+            for (int r0 = 0; r0 < (G.K + 15) / 16; r0 += kTileWindow) {
                 t.r0 = r0;
+                if (direct) {
+                    const int w_lo = 16 * r0, w_hi = 16 * (r0 + window_tiles(G.K, r0));
+                    t.mem_begin = (int32_t)mt.size();
+                    t.n_mem = 0;
+                    for (size_t j = 0; j < G.blocks.size(); ++j) {
+                        const int k = op.lr[G.blocks[j]].rank;
+                        if (G.lo[j] < w_hi && G.lo[j] + k > w_lo) {
+                            mt.push_back(MemberT{v.t_off[G.blocks[j]], G.lo[j], k});
+                            t.n_mem++;
+                        }
+                    }
+                }
                 ta.push_back(t);
             }
             if (!direct) {
                 tpart += slot;
-                rd.n_slots++;
+                n_slots++;
             }
         }
-        if (!direct) red.push_back(rd);
+        if (!direct)
+            for (size_t j = 0; j < G.blocks.size(); ++j)
+                red.push_back(ReduceDesc{slot0 + (int64_t)G.lo[j] * kNrhs, v.t_off[G.blocks[j]], n_slots,
+                                         op.lr[G.blocks[j]].rank, 0, (int32_t)slot});
     }
-    order_tasksA(ta, ia, v.groupA);
+    order_tasksA(ta, ia);
     v.nTasksA = (int)ta.size();
     v.nReduce = (int)red.size();
     v.tpart_elems = tpart;
 }
 
-void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, std::pair<int, int>* groupA)
+void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items)
 {
-    std::vector<std::vector<TaskA>> byR(kRowTilesMax);
+    // loads of a task: its sub-panels' columns times (window tiles + the in-vector)
+    auto cost = [&](const TaskA& t) {
+        int64_t c = 0;
+        for (int q = 0; q < t.n_items; ++q) c += items[t.item_begin + q].cols;
+        return c * (window_tiles(t.rows, t.r0) + 1);
+    };
     for (const TaskA& t : ta) {
         const int R = window_tiles(t.rows, t.r0);
-        HM_REQUIRE(R >= 1 && R <= kRowTilesMax, HM_EINTERNAL, "rank out of range");
-        byR[R - 1].push_back(t);
+        HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "phase-A window out of range");
     }
-    ta.clear();
-    for (int R = kRowTilesMax; R >= 1; --R) {
-        std::vector<TaskA>& g = byR[R - 1];
-        // each XCD runs one contiguous eighth of the group (four tasks per
-        // workgroup): ordered by source chunk, one XCD's L2 holds only its
-        // share of X; longest first inside each share for a short tail
-        std::stable_sort(g.begin(), g.end(), [&](const TaskA& a, const TaskA& b) {
-            return items[a.item_begin].b_off < items[b.item_begin].b_off;
-        });
-        const size_t share = 4 * (size_t)(round_up((int64_t)(g.size() + 3) / 4, 8) / 8);
-        for (size_t x0 = 0; x0 < g.size(); x0 += std::max<size_t>(1, share))
-            std::stable_sort(g.begin() + x0, g.begin() + std::min(g.size(), x0 + share),
-                             [](const TaskA& a, const TaskA& b) {
-                                 return (int64_t)a.n_items * a.rows > (int64_t)b.n_items * b.rows;
-                             });
-        groupA[R - 1] = {(int)ta.size(), (int)g.size()};
-        ta.insert(ta.end(), g.begin(), g.end());
+    // each XCD runs one contiguous eighth of the tasks (four per workgroup):
+    // ordered by source chunk, one XCD's L2 holds only its share of X;
+    // longest first inside each share for a short tail
+    std::stable_sort(ta.begin(), ta.end(), [&](const TaskA& a, const TaskA& b) {
+        return items[a.item_begin].b_off < items[b.item_begin].b_off;
+    });
+    const size_t share = 4 * (size_t)(round_up((int64_t)(ta.size() + 3) / 4, 8) / 8);
+    for (size_t x0 = 0; x0 < ta.size(); x0 += std::max<size_t>(1, share)) {
+        const size_t x1 = std::min(ta.size(), x0 + share);
+        std::vector<std::pair<int64_t, TaskA>> part;
+        for (size_t q = x0; q < x1; ++q) part.push_back({cost(ta[q]), ta[q]});
+        std::stable_sort(part.begin(), part.end(),
+                         [](const std::pair<int64_t, TaskA>& a, const std::pair<int64_t, TaskA>& b) {
+                             return a.first > b.first;
+                         });
+        for (size_t q = x0; q < x1; ++q) ta[q] = part[q - x0].second;
     }
 }
 
@@ -1100,6 +1146,7 @@ void upload_tasks(Variant& v, hipStream_t s)
     upload(v.itemsB, v.hItemsB, s);
     upload(v.tasksA, v.hTasksA, s);
     upload(v.itemsA, v.hItemsA, s);
+    upload(v.membersA, v.hMembersA, s);
     upload(v.reduce, v.hReduce, s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
     std::lock_guard<std::mutex> g(v.ws_mu);
@@ -1288,6 +1335,8 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.G = G;
     HM_REQUIRE(o.aca_tol > 0.0 && o.aca_tol < 1.0, HM_EINVAL, "aca_tol must be in (0, 1)");
     HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
+    HM_REQUIRE(o.stack_rows >= 0, HM_EINVAL, "stack_rows must be >= 0");
+    HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
     HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16, HM_EUNSUPPORTED,
                "far_prec must be F64, F32 or BF16");
@@ -1627,12 +1676,16 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.main.near_prec = o.near_prec;
     op.main.far_prec = o.far_prec;
     op.main.self_separate = o.near_prec != HM_F64;
+    op.main.stackRowsA = o.stack_rows;
+    op.main.leavesPerTaskA = o.phase_a_items;
     make_variant(op, op.main, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     if (o.keep_f64_reference && o.near_prec != HM_F64) {
         op.ref.reset(new Variant());
         op.ref->near_prec = HM_F64;
         op.ref->far_prec = HM_F64;
         op.ref->self_separate = false;
+        op.ref->stackRowsA = o.stack_rows;
+        op.ref->leavesPerTaskA = o.phase_a_items;
         make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     }
     double t3 = now_ms();

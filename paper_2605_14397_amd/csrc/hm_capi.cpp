@@ -135,6 +135,8 @@ void hm_build_opts_default(hm_build_opts* o)
     o->far_prec = HM_F64;
     o->keep_f64_reference = 0;
     o->recompress = 1;
+    o->stack_rows = 64;
+    o->phase_a_items = 8;
 }
 
 hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const hm_build_opts* opts, void* hip_stream,
@@ -166,7 +168,12 @@ hm_status hm_operator_stats(const hm_op* op, hm_op_stats* out)
     return guarded([&] {
         HM_REQUIRE(op && out, HM_EINVAL, "null argument");
         *out = op->op.stats;
-        out->apply_workspace_bytes = (int64_t)op->op.main.ws_layout().total;
+        const hm::Variant& v = op->op.main;
+        out->apply_workspace_bytes = (int64_t)v.ws_layout().total;
+        out->phase_a_tasks = v.nTasksA;
+        out->phase_b_tasks = v.nTasksB;
+        out->phase_a_stacks = (int64_t)v.vgroups.size();
+        out->phase_a_partial_bytes = v.tpart_elems * (v.acc_f64() ? 8 : 4);
     });
 }
 

@@ -197,7 +197,6 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + 
 __host__ __device__ inline int64_t chunk_n_off(int64_t m) { return round_up(2 * m, kChunkAlign); }
 __host__ __device__ inline int64_t chunk_len(int64_t m) { return chunk_n_off(m) + round_up(m, kChunkAlign); }
 constexpr int kNrhs = 16;         // right-hand sides per fragment
-constexpr int kRowTilesMax = 12;  // 192 rows: leaf <= 64 elements, rank <= 192
 
 inline int prec_w(int prec) { return prec == HM_F64 ? 2 : (prec == HM_F32 ? 4 : 8); }
 inline int prec_bytes(int prec) { return prec == HM_F64 ? 8 : (prec == HM_F32 ? 4 : 2); }
@@ -230,21 +229,32 @@ struct TaskB {        // one row window of one section of a target leaf
     int32_t pad;
 };
 
-struct TaskA {        // part of one low-rank block: T partial = sum V^T X
+// Phase A works on stacked V^T panels: the factorisations that share a
+// source cluster (and carry the same sections) have their V^T sub-panels of
+// each source leaf stored as one panel of sum-of-ranks rows, so one load of
+// an in-vector k-step feeds every row tile of the window.
+struct TaskA {        // one row window of a stacked panel set: T partial = sum V^T X
     int64_t out_off;  // partial slot start (elements, [rows_pad][16]) when not direct
-    int64_t t_off;    // T fragment chunk of the block (elements) when direct
-    int32_t rows;     // rank k
+    int32_t rows;     // stacked rows (sum of the members' ranks)
     int32_t item_begin, n_items;
-    int32_t direct;   // 1: the task covers the whole block and writes T itself
+    int32_t direct;   // 1: the task covers every source leaf and writes the members' T chunks
     int32_t op;
     int32_t r0;       // first row tile of the window
+    int32_t mem_begin, n_mem;  // members meeting the window (direct tasks)
+};
+
+struct MemberT {      // one factorisation inside a stacked panel
+    int64_t t_off;    // its T fragment chunk (elements)
+    int32_t lo;       // its first stacked row
+    int32_t rows;     // its rank
 };
 
 struct ReduceDesc {   // T_b = sum of partial slots
-    int64_t slot_begin;   // first partial slot (elements)
+    int64_t slot_begin;   // member's first row in the first partial slot (elements)
     int64_t t_off;        // T fragment chunk start (elements)
     int32_t n_slots, rank;
-    int32_t op, pad;
+    int32_t op;
+    int32_t slot_stride;  // elements between consecutive slots of the stack
 };
 
 // Device buffers of one operator (one precision variant), looked up by the

@@ -34,10 +34,8 @@ struct Variant {
     int near_prec = HM_F64, far_prec = HM_F64;
     bool self_separate = false;   // element self blocks applied from the FP64 store
     DevBuf near_a, far_a;         // panels
-    DevBuf tasksB, itemsB, tasksA, itemsA, reduce;
+    DevBuf tasksB, itemsB, tasksA, itemsA, membersA, reduce;
     int nTasksB = 0, nTasksA = 0, nReduce = 0;
-    std::pair<int, int> groupB[kRowTilesMax] = {};  // phase-B tasks with R row tiles: (first, count)
-    std::pair<int, int> groupA[kRowTilesMax] = {};  // phase-A tasks with R row tiles: (first, count)
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
     int64_t near_entries = 0;     // dense-piece entries stored, without padding
@@ -50,11 +48,21 @@ struct Variant {
     // host copies of the task lists (merged by batches)
     std::vector<TaskA> hTasksA;
     std::vector<PanelRef> hItemsA;
+    std::vector<MemberT> hMembersA;
     std::vector<ReduceDesc> hReduce;
     std::vector<TaskB> hTasksB;
     std::vector<PanelRef> hItemsB;
     int leavesPerTaskA = 8;
-    std::vector<std::vector<PanelRef>> vitems;  // per block: its V^T sub-panels (phase-A items)
+    int stackRowsA = 64;                        // row cap of a stacked V^T panel set (0: none)
+    // factorisations with one source cluster and one section set: their
+    // V^T sub-panels are stacked (phase-A items)
+    struct VGroup {
+        int K = 0;                    // stacked rows (sum of the members' ranks)
+        std::vector<int> blocks;      // member factorisations
+        std::vector<int> lo;          // first stacked row of each member
+        std::vector<PanelRef> items;  // one stacked sub-panel per (source leaf, section)
+    };
+    std::vector<VGroup> vgroups;
     std::vector<int64_t> t_off;                 // per block: T chunk offset
     bool acc_f64() const { return near_prec == HM_F64; }
     bool far_is_near() const { return far_prec == near_prec; }
@@ -77,12 +85,12 @@ struct LaunchSet {
     const Bases* bases = nullptr;
     const TaskA* tasksA = nullptr;
     int nTasksA = 0;
-    std::pair<int, int> groupA[kRowTilesMax] = {};
     const PanelRef* itemsA = nullptr;
+    const MemberT* membersA = nullptr;
     const ReduceDesc* reduce = nullptr;
     int nReduce = 0;
     const TaskB* tasksB = nullptr;
-    std::pair<int, int> groupB[kRowTilesMax] = {};
+    int nTasksB = 0;
     const PanelRef* itemsB = nullptr;
 };
 
@@ -223,7 +231,9 @@ void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
 // Order a phase-A task list for launch: grouped by row-tile count (one
 // launch per group, largest first); inside a group ordered by the in-vector
 // chunk of the first sub-panel, then longest first inside each XCD's share.
-void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, std::pair<int, int>* groupA);
+// sort phase-A tasks for one launch (XCD shares by source chunk, longest
+// first inside each share)
+void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items);
 void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 void interface_update(int n_mat, const hm_interface_material* mats, int64_t n, const int32_t* d_mat_id,

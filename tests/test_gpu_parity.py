@@ -141,6 +141,38 @@ def test_apply_ragged_triangles_non_coplanar(two_disks):
         assert err <= bar
 
 
+@pytest.mark.parametrize("stack_rows,items", [(1, 8), (0, 8), (64, 1), (0, 1), (17, 3)],
+                         ids=["unstacked", "one_stack_per_cluster", "stacked_partials", "tall_partials", "odd"])
+def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items):
+    # stacked V^T panels (any row cap) and phase-A runs split into partial
+    # slots change only the summation order: every layout meets the FP64 bar
+    # on the coplanar grid and on the coupled (three-component) disks
+    hm = _hm()
+    m, E, X = c1
+    op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, aca_tol=1e-6, stack_rows=stack_rows,
+                     phase_a_items=items)
+    st = op.stats()
+    err = colerr(op.apply(cuda(X)).cpu().numpy(), oracle.matvec(E, X))
+    print(f"C1 stack_rows {stack_rows} items {items}: {st['phase_a_stacks']} stacks, {st['phase_a_tasks']} tasks, "
+          f"{st['phase_a_partial_bytes']} partial bytes, rel err {err:.3e}")
+    assert err <= 1e-6
+    if stack_rows == 1:      # one factorisation per stack: the shear and normal parts of each coplanar block
+        assert st["phase_a_stacks"] >= st["n_lowrank_blocks"]
+    elif stack_rows in (0, 64):
+        assert st["phase_a_stacks"] < st["n_lowrank_blocks"]
+    if items == 1:
+        assert st["phase_a_partial_bytes"] > 0
+    md, Ed = two_disks
+    Xd = rhs_columns(md.ndof, 5, 78)
+    opd = hm.Operator(hm.Mesh.from_workload(md), YOUNG, NU, leaf_size=16, aca_tol=1e-9, stack_rows=stack_rows,
+                      phase_a_items=items, near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1)
+    ref = oracle.matvec(Ed, Xd)
+    e64 = colerr(opd.apply(cuda(Xd), reference=True).cpu().numpy(), ref)
+    ebf = colerr(opd.apply(cuda(Xd)).cpu().numpy(), ref)
+    print(f"two disks stack_rows {stack_rows} items {items}: FP64 {e64:.3e}, BF16 far {ebf:.3e}")
+    assert e64 <= 1e-9 and ebf <= 5e-3
+
+
 def test_apply_column_independence_and_determinism(c1):
     hm = _hm()
     m, E, X = c1

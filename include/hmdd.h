@@ -150,11 +150,13 @@ typedef struct {
     int leaf_size;          /* max elements per cluster-tree leaf (1..64); default 64 */
     double eta;             /* admissibility: min(diam) <= eta * dist; default 2 */
     double aca_tol;         /* relative Frobenius tolerance per block; default 1e-6 */
-    int max_rank;           /* cap on the rank of a low-rank block (<= 192); default 192 */
+    int max_rank;           /* cap on the rank of a low-rank block (<= 192): a block whose cross approximation
+                               needs more is split into its children; default 128 */
     int near_prec;          /* HM_F64 or HM_F32 for dense leaves */
     int far_prec;           /* HM_F64, HM_F32 or HM_BF16 for low-rank factors */
     int keep_f64_reference; /* also keep an all-FP64 copy (used by refinement) */
-    int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 (rank <= 64); default 1 */
+    int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 and store it with
+                               orthonormal left factors (any rank); default 1 */
     int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
                                as stacked panels of at most this many rows (0: no cap, 1: no stacking); default 64 */
     int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */

@@ -389,54 +389,75 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
 // ------------------------------------------------------------------
 // recompression of ACA factors (one workgroup per factorisation)
 // ------------------------------------------------------------------
-// For U V^T of rank k <= kRcMax (columns of U and V contiguous): with
-// D = diag(|u_q|), U D^-1 has unit columns and a well-conditioned Gram
-// matrix (cross-approximation columns shrink with the residual; V D takes
-// the scale), so
-//   (U D^-1)^T (U D^-1) = R^T R     (Cholesky),
-//   U V^T = Q R (V D)^T with Q = U D^-1 R^-1 orthonormal, and
-//   R G R^T = W S^2 W^T,  G = (V D)^T (V D)   (parallel cyclic Jacobi)
-// gives the singular values S of U V^T.  Keep the k' largest with the
-// discarded energy sum_{i >= k'} s_i^2 <= tol^2 sum_i s_i^2 and write
-//   T_u = D^-1 R^-1 W_k',  T_v = D R^T W_k',  U' = U T_u, V' = V T_v
-// (U' V'^T = U V^T exactly when k' = k).  A Cholesky pivot that is not
-// clearly positive leaves the block as it is (k' = -1).
-constexpr int kRcMax = 64;
-constexpr int kRcLd = kRcMax + 1;
-constexpr size_t kRcLds = 4 * (size_t)kRcMax * kRcLd * sizeof(double);
+// For U V^T of rank k (columns of U and V contiguous): with D = diag(|u_q|),
+// U D^-1 has unit columns; its Gram matrix A = (U D^-1)^T (U D^-1) and
+// G = (V D)^T (V D) give the singular values of U V^T without another pass
+// over the long factors:
+//   * A = R^T R (Cholesky): U D^-1 = Q R with Q orthonormal, and the core
+//     R G R^T = W S^2 W^T (cyclic Jacobi): T_u = D^-1 R^-1 W, T_v = D R^T W;
+//   * when a Cholesky pivot is not clearly positive (nearly dependent cross
+//     columns), A = Z L Z^T (Jacobi) instead; directions with eigenvalues
+//     below 1e-14 of the largest are dropped (U has no component there), and
+//     the core L^1/2 Z^T G Z L^1/2 = W S^2 W^T gives
+//     T_u = D^-1 Z L^-1/2 W, T_v = D Z L^1/2 W.
+// The k' largest singular values are kept with discarded energy
+// sum_{i >= k'} s_i^2 <= tol^2 sum_i s_i^2, and U' = U T_u, V' = V T_v are
+// always written (also when k' = k): U' has orthonormal columns and V'
+// carries the singular values, so rounding the factors to a short format
+// perturbs the block by that format's relative precision times its norm,
+// whatever cancellation the cross approximation's columns had.
+// Work matrices (k x k each): ranks up to 64 keep all four in LDS; ranks up
+// to 128 keep the Jacobi target in LDS and the rest in a global slot of the
+// workgroup; higher ranks (up to the cross-approximation cap) keep all four
+// in the slot and stage the Gram products through LDS.  Eigenvector
+// matrices are stored transposed (one eigenvector per row), so a rotation
+// updates two contiguous rows.
+constexpr int kRcSmall = 64;
+constexpr int kRcMid = 128;
+constexpr int kRcThreads = 1024;  // one workgroup per factorisation (the LDS use allows one per CU)
+constexpr int kRcStage = 6144;    // doubles of LDS staging for the all-global kernel
+
+template <int KMAX>
+struct RcShape {
+    static constexpr int LD = KMAX + 1;
+    static constexpr size_t kMat = (size_t)KMAX * LD;          // doubles per work matrix
+    static constexpr int kInLds = KMAX <= kRcSmall ? 4 : (KMAX <= kRcMid ? 1 : 0);  // matrices in LDS
+    static constexpr size_t kSlot = (size_t)(4 - kInLds) * kMat;                      // doubles per global slot
+    static constexpr size_t kLds = (kInLds ? kInLds * kMat : (size_t)kRcStage) * sizeof(double);
+};
 
 struct RcDesc {
     int64_t u_off, v_off;  // factor columns: U + q * lu, V + q * lv
     int64_t lu, lv;
     int64_t t_off;         // workspace: T_u [k][k'] then T_v [k][k']
-    double abs2;           // > 0: bound on the discarded energy; else tol^2 times the energy of U V^T
     int32_t k, pad;
 };
 
 // A (k x k, upper triangle of a symmetric matrix) -> its Cholesky factor R
 // (upper).  Returns false when a pivot is not clearly positive.
+template <int LD>
 __device__ bool rc_cholesky(double* A, int k, int* s_flag)
 {
     double dmax = 0.0;
-    for (int j = 0; j < k; ++j) dmax = fmax(dmax, A[j * kRcLd + j]);
+    for (int j = 0; j < k; ++j) dmax = fmax(dmax, A[j * LD + j]);
     for (int j = 0; j < k; ++j) {
         if (threadIdx.x == 0) {
-            const double d = A[j * kRcLd + j];
+            const double d = A[j * LD + j];
             if (!(d > 1e-14 * dmax)) {
                 *s_flag = 1;
             } else {
-                A[j * kRcLd + j] = sqrt(d);
+                A[j * LD + j] = sqrt(d);
             }
         }
         __syncthreads();
         if (*s_flag) return false;
-        const double r = A[j * kRcLd + j];
-        for (int l = j + 1 + threadIdx.x; l < k; l += blockDim.x) A[j * kRcLd + l] /= r;
+        const double r = A[j * LD + j];
+        for (int l = j + 1 + threadIdx.x; l < k; l += blockDim.x) A[j * LD + l] /= r;
         __syncthreads();
         const int nn = k - j - 1;
         for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x) {
             const int i = j + 1 + idx / nn, l = j + 1 + idx % nn;
-            if (l >= i) A[i * kRcLd + l] -= A[j * kRcLd + i] * A[j * kRcLd + l];
+            if (l >= i) A[i * LD + l] -= A[j * LD + i] * A[j * LD + l];
         }
         __syncthreads();
     }
@@ -444,131 +465,83 @@ __device__ bool rc_cholesky(double* A, int k, int* s_flag)
 }
 
 // Gram matrix G[a][b] = sum_i X[a][i] X[b][i] (a <= b) of k columns of
-// length L, staged through LDS in chunks; fixed summation order.
+// length L, staged through LDS in column chunks; the pairs are taken in
+// passes of (threads x kPer); fixed summation order.
+template <int LD>
 __device__ void rc_gram(const double* __restrict__ X, int64_t L, int k, double* G, double* stage, int stage_cap)
 {
     const int T = max(1, stage_cap / k);
     const int npair = k * (k + 1) / 2;
-    constexpr int kPer = (kRcMax * (kRcMax + 1) / 2 + 255) / 256;
-    double acc[kPer];
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) acc[t] = 0.0;
-    for (int64_t i0 = 0; i0 < L; i0 += T) {
-        const int nt = (int)min((int64_t)T, L - i0);
-        for (int idx = threadIdx.x; idx < k * nt; idx += blockDim.x) {
-            const int q = idx / nt, t = idx % nt;
-            stage[q * T + t] = X[(int64_t)q * L + i0 + t];
-        }
-        __syncthreads();
+    constexpr int kPer = 4;
+    for (int p0 = 0; p0 < npair; p0 += (int)blockDim.x * kPer) {
+        double acc[kPer];
+        int pa[kPer], pb[kPer];
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
-            const int pr = threadIdx.x + 256 * t;
-            if (pr < npair) {
-                // pair index -> (a, b), a <= b, row-major over the upper triangle
-                int a = 0, rem = pr;
-                while (rem >= k - a) {
-                    rem -= k - a;
-                    ++a;
-                }
-                const int b = a + rem;
-                double sacc = acc[t];
-                for (int tt = 0; tt < nt; ++tt) sacc += stage[a * T + tt] * stage[b * T + tt];
-                acc[t] = sacc;
+            acc[t] = 0.0;
+            // pair index -> (a, b), a <= b, row-major over the upper triangle
+            int a = 0, rem = p0 + threadIdx.x + (int)blockDim.x * t;
+            if (rem >= npair) {
+                pa[t] = -1;
+                pb[t] = -1;
+                continue;
             }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-        const int pr = threadIdx.x + 256 * t;
-        if (pr < npair) {
-            int a = 0, rem = pr;
             while (rem >= k - a) {
                 rem -= k - a;
                 ++a;
             }
-            G[a * kRcLd + a + rem] = acc[t];
+            pa[t] = a;
+            pb[t] = a + rem;
         }
+        for (int64_t i0 = 0; i0 < L; i0 += T) {
+            const int nt = (int)min((int64_t)T, L - i0);
+            for (int idx = threadIdx.x; idx < k * nt; idx += blockDim.x) {
+                const int q = idx / nt, t = idx % nt;
+                stage[q * T + t] = X[(int64_t)q * L + i0 + t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                if (pa[t] < 0) continue;
+                const double* xa = stage + pa[t] * T;
+                const double* xb = stage + pb[t] * T;
+                double sacc = acc[t];
+                for (int tt = 0; tt < nt; ++tt) sacc += xa[tt] * xb[tt];
+                acc[t] = sacc;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < kPer; ++t)
+            if (pa[t] >= 0) G[pa[t] * LD + pb[t]] = acc[t];
     }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ descs, const double* __restrict__ fac,
-                                                     double tol, double* __restrict__ tws, int* __restrict__ out_k,
-                                                     double* __restrict__ out_energy)
+// Eigen-decomposition of the symmetric k x k matrix S (full storage) by
+// parallel cyclic Jacobi; Wt (k x k) must hold the identity on entry and
+// receives the eigenvectors as rows (Wt[e][i] = component i of eigenvector
+// e); the eigenvalues are left on the diagonal of S.
+template <int LD>
+__device__ void rc_jacobi(double* S, double* Wt, int k, double* s_c, double* s_s, int* s_p, int* s_q, double* s_red)
 {
-    extern __shared__ double lds[];
-    double* A = lds;                   // U^T U -> scaled -> R
-    double* B = A + kRcMax * kRcLd;    // V^T V -> scaled (G)
-    double* C = B + kRcMax * kRcLd;    // R G, then W
-    double* S = C + kRcMax * kRcLd;    // R G R^T -> diagonalised
-    __shared__ int s_flag;
-    __shared__ double s_c[kRcMax / 2], s_s[kRcMax / 2];
-    __shared__ int s_p[kRcMax / 2], s_q[kRcMax / 2];
-    __shared__ double s_red[4];
-    __shared__ int s_rank[kRcMax];
-    __shared__ int s_sel[kRcMax];
-    __shared__ int s_kp;
-    __shared__ double s_d[kRcMax];
-    const RcDesc D = descs[blockIdx.x];
-    const int k = D.k;
-    if (threadIdx.x == 0) s_flag = 0;
-    __syncthreads();
-    // ---- Gram matrices (C and S serve as the staging area) ----
-    rc_gram(fac + D.u_off, D.lu, k, A, C, 2 * kRcMax * kRcLd);
-    rc_gram(fac + D.v_off, D.lv, k, B, C, 2 * kRcMax * kRcLd);
-    // ---- column scaling D: unit columns of U, the scale moved into V ----
-    for (int a = threadIdx.x; a < k; a += blockDim.x) s_d[a] = sqrt(A[a * kRcLd + a]);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int a = idx / k, b = idx % k;
-        if (b < a) continue;
-        const double dd = s_d[a] * s_d[b];
-        A[a * kRcLd + b] = dd > 0.0 ? A[a * kRcLd + b] / dd : 0.0;
-        B[a * kRcLd + b] *= dd;
-    }
-    __syncthreads();
-    if (!rc_cholesky(A, k, &s_flag)) {
-        if (threadIdx.x == 0) {
-            out_k[blockIdx.x] = -1;
-            out_energy[blockIdx.x] = 0.0;
-        }
-        return;
-    }
-    // ---- C = R G (G symmetric, upper triangle in B), S = C R^T ----
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int a = idx / k, b = idx % k;
-        double sum = 0.0;
-        for (int c = a; c < k; ++c) sum += A[a * kRcLd + c] * (c <= b ? B[c * kRcLd + b] : B[b * kRcLd + c]);
-        C[a * kRcLd + b] = sum;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int a = idx / k, b = idx % k;
-        double sum = 0.0;
-        for (int c = b; c < k; ++c) sum += C[a * kRcLd + c] * A[b * kRcLd + c];
-        S[a * kRcLd + b] = sum;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) C[(idx / k) * kRcLd + idx % k] = (idx / k == idx % k);
-    __syncthreads();
-    // ---- cyclic Jacobi on S (k padded to even kk; the pad index is inert) ----
+    // round-robin pairing over kk = k rounded up to even (the pad index is inert)
     const int kk = k + (k & 1);
     double fro2 = 0.0;
     for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) fro2 += S[a * kRcLd + b] * S[a * kRcLd + b];
+        for (int b = 0; b < k; ++b) fro2 += S[a * LD + b] * S[a * LD + b];
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int round = 0; round < kk - 1; ++round) {
-            // round-robin pairing: position 0 fixed, the others rotate
+            // position 0 fixed, the others rotate
             for (int pi = threadIdx.x; pi < kk / 2; pi += blockDim.x) {
                 int p0 = pi == 0 ? 0 : 1 + (pi - 1 + round) % (kk - 1);
                 int q0 = 1 + (kk - 2 - pi + round) % (kk - 1);
                 int p = min(p0, q0), q = max(p0, q0);
                 double c = 1.0, sn = 0.0;
                 if (q < k) {
-                    const double apq = S[p * kRcLd + q];
+                    const double apq = S[p * LD + q];
                     if (apq != 0.0) {
-                        const double th = (S[q * kRcLd + q] - S[p * kRcLd + p]) / (2.0 * apq);
+                        const double th = (S[q * LD + q] - S[p * LD + p]) / (2.0 * apq);
                         const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
                         sn = t * c;
@@ -586,87 +559,242 @@ __global__ __launch_bounds__(256) void k_recompress(const RcDesc* __restrict__ d
                 const int p = s_p[pi], q = s_q[pi];
                 if (q >= k) continue;
                 const double c = s_c[pi], sn = s_s[pi];
-                const double xp = S[p * kRcLd + j], xq = S[q * kRcLd + j];
-                S[p * kRcLd + j] = c * xp - sn * xq;
-                S[q * kRcLd + j] = sn * xp + c * xq;
+                const double xp = S[p * LD + j], xq = S[q * LD + j];
+                S[p * LD + j] = c * xp - sn * xq;
+                S[q * LD + j] = sn * xp + c * xq;
             }
             __syncthreads();
-            // columns: S <- S J, W <- W J
+            // columns: S <- S J; eigenvectors: rows p, q of Wt <- J^T (rows p, q)
             for (int idx = threadIdx.x; idx < (kk / 2) * k; idx += blockDim.x) {
                 const int pi = idx / k, j = idx % k;
                 const int p = s_p[pi], q = s_q[pi];
                 if (q >= k) continue;
                 const double c = s_c[pi], sn = s_s[pi];
-                const double xp = S[j * kRcLd + p], xq = S[j * kRcLd + q];
-                S[j * kRcLd + p] = c * xp - sn * xq;
-                S[j * kRcLd + q] = sn * xp + c * xq;
-                const double wp = C[j * kRcLd + p], wq = C[j * kRcLd + q];
-                C[j * kRcLd + p] = c * wp - sn * wq;
-                C[j * kRcLd + q] = sn * wp + c * wq;
+                const double xp = S[j * LD + p], xq = S[j * LD + q];
+                S[j * LD + p] = c * xp - sn * xq;
+                S[j * LD + q] = sn * xp + c * xq;
+                const double wp = Wt[p * LD + j], wq = Wt[q * LD + j];
+                Wt[p * LD + j] = c * wp - sn * wq;
+                Wt[q * LD + j] = sn * wp + c * wq;
             }
             __syncthreads();
         }
         // off-diagonal energy
         double off = 0.0;
         for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x)
-            if (idx / k != idx % k) off += S[(idx / k) * kRcLd + idx % k] * S[(idx / k) * kRcLd + idx % k];
+            if (idx / k != idx % k) off += S[(idx / k) * LD + idx % k] * S[(idx / k) * LD + idx % k];
         for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
         if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = off;
         __syncthreads();
-        off = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        off = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) off += s_red[w];
         __syncthreads();
         if (!(off > 1e-30 * fro2)) break;
     }
-    // ---- order eigenvalues (descending, ties by index) and choose k' ----
+}
+
+// Order of the diagonal of S (descending, ties by index): sel[r] is the
+// index of the r-th largest.
+template <int LD>
+__device__ void rc_order(const double* S, int k, int* sel)
+{
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
-        const double li = S[i * kRcLd + i];
+        const double li = S[i * LD + i];
         int r = 0;
         for (int j = 0; j < k; ++j) {
-            const double lj = S[j * kRcLd + j];
+            const double lj = S[j * LD + j];
             if (lj > li || (lj == li && j < i)) ++r;
         }
-        s_rank[i] = r;
-        s_sel[r] = i;
+        sel[r] = i;
     }
     __syncthreads();
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kRcThreads) void k_recompress(const RcDesc* __restrict__ descs, const double* __restrict__ fac,
+                                                     double tol, double* __restrict__ tws, int* __restrict__ out_k,
+                                                     double* __restrict__ out_energy, double* __restrict__ slots)
+{
+    typedef RcShape<KMAX> Sh;
+    constexpr int LD = Sh::LD;
+    extern __shared__ double lds[];
+    double* slot = slots + (size_t)blockIdx.x * Sh::kSlot;
+    // A: U^T U -> R (or Z^T G); B: V^T V -> scaled (G), or W' of the eigen
+    // route; C: R G, then W^T (or Z^T); S: the scaled U Gram, then the core
+    double *A, *B, *C, *S, *stage;
+    int stage_cap;
+    if (Sh::kInLds == 4) {
+        A = lds;
+        B = A + Sh::kMat;
+        C = B + Sh::kMat;
+        S = C + Sh::kMat;
+        stage = C;
+        stage_cap = (int)(2 * Sh::kMat);
+    } else if (Sh::kInLds == 1) {
+        S = lds;
+        A = slot;
+        B = A + Sh::kMat;
+        C = B + Sh::kMat;
+        stage = S;
+        stage_cap = (int)Sh::kMat;
+    } else {
+        A = slot;
+        B = A + Sh::kMat;
+        C = B + Sh::kMat;
+        S = C + Sh::kMat;
+        stage = lds;
+        stage_cap = kRcStage;
+    }
+    __shared__ int s_flag;
+    __shared__ double s_c[KMAX / 2], s_s[KMAX / 2];
+    __shared__ int s_p[KMAX / 2], s_q[KMAX / 2];
+    __shared__ double s_red[kRcThreads / 64];
+    __shared__ int s_sel[KMAX], s_sel2[KMAX];
+    __shared__ int s_kp, s_r;
+    __shared__ double s_d[KMAX], s_l[KMAX];
+    const RcDesc D = descs[blockIdx.x];
+    const int k = D.k;
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    // ---- Gram matrices ----
+    rc_gram<LD>(fac + D.u_off, D.lu, k, A, stage, stage_cap);
+    rc_gram<LD>(fac + D.v_off, D.lv, k, B, stage, stage_cap);
+    // ---- column scaling D: unit columns of U, the scale moved into V ----
+    for (int a = threadIdx.x; a < k; a += blockDim.x) s_d[a] = sqrt(A[a * LD + a]);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int a = idx / k, b = idx % k;
+        if (b < a) continue;
+        const double dd = s_d[a] * s_d[b];
+        A[a * LD + b] = dd > 0.0 ? A[a * LD + b] / dd : 0.0;
+        B[a * LD + b] *= dd;
+        B[b * LD + a] = B[a * LD + b];   // G in full storage
+        S[a * LD + b] = A[a * LD + b];   // full symmetric copy for the eigen route
+        S[b * LD + a] = A[a * LD + b];
+    }
+    __syncthreads();
+    const bool chol = rc_cholesky<LD>(A, k, &s_flag);
+    int r = k;
+    if (chol) {
+        // ---- C = R G, then B = R^T (G is not needed again) and S = C R^T;
+        // each thread walks a row of the broadcast operand and a column of
+        // the other, so a wavefront reads contiguous rows ----
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+            const int a = idx / k, b = idx % k;
+            double sum = 0.0;
+            for (int c = a; c < k; ++c) sum += A[a * LD + c] * B[c * LD + b];
+            C[a * LD + b] = sum;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+            const int c = idx / k, b = idx % k;
+            B[c * LD + b] = c >= b ? A[b * LD + c] : 0.0;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+            const int a = idx / k, b = idx % k;
+            double sum = 0.0;
+            for (int c = b; c < k; ++c) sum += C[a * LD + c] * B[c * LD + b];
+            S[a * LD + b] = sum;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) C[(idx / k) * LD + idx % k] = (idx / k == idx % k);
+        __syncthreads();
+        rc_jacobi<LD>(S, C, k, s_c, s_s, s_p, s_q, s_red);
+        rc_order<LD>(S, k, s_sel2);
+    } else {
+        // ---- eigen route: S = Z L Z^T (Z into C) ----
+        for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) C[(idx / k) * LD + idx % k] = (idx / k == idx % k);
+        __syncthreads();
+        rc_jacobi<LD>(S, C, k, s_c, s_s, s_p, s_q, s_red);
+        rc_order<LD>(S, k, s_sel);
+        if (threadIdx.x == 0) {
+            const double lmax = S[s_sel[0] * LD + s_sel[0]];
+            int rr = 0;
+            while (rr < k && S[s_sel[rr] * LD + s_sel[rr]] > 1e-14 * lmax && lmax > 0.0) ++rr;
+            s_r = rr;
+        }
+        __syncthreads();
+        r = s_r;
+        for (int a = threadIdx.x; a < r; a += blockDim.x) s_l[a] = S[s_sel[a] * LD + s_sel[a]];
+        __syncthreads();
+        // A = Z_r^T G (r x k), then S = L^1/2 (A Z_r) L^1/2 (r x r), B = I
+        for (int idx = threadIdx.x; idx < r * k; idx += blockDim.x) {
+            const int a = idx / k, j = idx % k;
+            double sum = 0.0;
+            for (int c = 0; c < k; ++c) sum += C[s_sel[a] * LD + c] * B[c * LD + j];
+            A[a * LD + j] = sum;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+            const int a = idx / r, b = idx % r;
+            double sum = 0.0;
+            for (int j = 0; j < k; ++j) sum += A[a * LD + j] * C[s_sel[b] * LD + j];
+            S[a * LD + b] = sqrt(s_l[a] * s_l[b]) * sum;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) B[(idx / r) * LD + idx % r] = (idx / r == idx % r);
+        __syncthreads();
+        if (r > 0) rc_jacobi<LD>(S, B, r, s_c, s_s, s_p, s_q, s_red);
+        rc_order<LD>(S, r, s_sel2);
+    }
+    // ---- choose k' on the core's eigenvalues (the squared singular values) ----
     if (threadIdx.x == 0) {
         double total = 0.0;
-        for (int r = 0; r < k; ++r) total += fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
-        const double budget = D.abs2 > 0.0 ? D.abs2 : tol * tol * total;
+        for (int q = 0; q < r; ++q) total += fmax(0.0, S[s_sel2[q] * LD + s_sel2[q]]);
+        const double budget = tol * tol * total;
         double tail = 0.0;
-        int kp = k;
+        int kp = r;
         // drop from the smallest while the discarded energy stays within the budget
-        for (int r = k - 1; r >= 1; --r) {
-            const double lr = fmax(0.0, S[s_sel[r] * kRcLd + s_sel[r]]);
-            if (tail + lr > budget) break;
-            tail += lr;
-            kp = r;
+        for (int q = r - 1; q >= 1; --q) {
+            const double lq = fmax(0.0, S[s_sel2[q] * LD + s_sel2[q]]);
+            if (tail + lq > budget) break;
+            tail += lq;
+            kp = q;
         }
+        if (r == 0) kp = -1;   // a numerically zero block stays as it is
         s_kp = kp;
         out_k[blockIdx.x] = kp;
         out_energy[blockIdx.x] = total;
     }
     __syncthreads();
     const int kp = s_kp;
-    if (kp >= k) return;
-    // ---- T_u = D^-1 R^-1 W_k' (back substitution per column), T_v = D R^T W_k' ----
+    if (kp < 1) return;
     double* Tu = tws + D.t_off;
     double* Tv = Tu + (int64_t)k * kp;
-    for (int col = threadIdx.x; col < kp; col += blockDim.x) {
-        const int e = s_sel[col];
-        for (int i = k - 1; i >= 0; --i) {
-            double sum = C[i * kRcLd + e];
-            for (int c = i + 1; c < k; ++c) sum -= A[i * kRcLd + c] * Tu[(int64_t)c * kp + col];
-            Tu[(int64_t)i * kp + col] = sum / A[i * kRcLd + i];
+    if (chol) {
+        // ---- T_u = D^-1 R^-1 W_k' (back substitution per column), T_v = D R^T W_k' ----
+        for (int col = threadIdx.x; col < kp; col += blockDim.x) {
+            const int e = s_sel2[col];
+            for (int i = k - 1; i >= 0; --i) {
+                double sum = C[e * LD + i];
+                for (int c = i + 1; c < k; ++c) sum -= A[i * LD + c] * Tu[(int64_t)c * kp + col];
+                Tu[(int64_t)i * kp + col] = sum / A[i * LD + i];
+            }
+            for (int i = 0; i < k; ++i) Tu[(int64_t)i * kp + col] /= s_d[i];
         }
-        for (int i = 0; i < k; ++i) Tu[(int64_t)i * kp + col] /= s_d[i];
-    }
-    for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
-        const int q = idx / kp, col = idx % kp;
-        const int e = s_sel[col];
-        double sum = 0.0;
-        for (int c = 0; c <= q; ++c) sum += A[c * kRcLd + q] * C[c * kRcLd + e];
-        Tv[(int64_t)q * kp + col] = sum * s_d[q];
+        for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
+            const int col = idx / k, q = idx % k;
+            const int e = s_sel2[col];
+            double sum = 0.0;
+            for (int c = 0; c <= q; ++c) sum += A[c * LD + q] * C[e * LD + c];
+            Tv[(int64_t)q * kp + col] = sum * s_d[q];
+        }
+    } else {
+        // ---- T_u = D^-1 Z_r L^-1/2 W_k', T_v = D Z_r L^1/2 W_k' ----
+        for (int idx = threadIdx.x; idx < k * kp; idx += blockDim.x) {
+            const int i = idx / kp, col = idx % kp;
+            const int e = s_sel2[col];
+            double su = 0.0, sv = 0.0;
+            for (int a = 0; a < r; ++a) {
+                const double zw = C[s_sel[a] * LD + i] * B[e * LD + a];
+                const double sl = sqrt(s_l[a]);
+                su += zw / sl;
+                sv += zw * sl;
+            }
+            Tu[(int64_t)i * kp + col] = s_d[i] > 0.0 ? su / s_d[i] : 0.0;
+            Tv[(int64_t)i * kp + col] = sv * s_d[i];
+        }
     }
 }
 
@@ -676,11 +804,16 @@ struct RcApply {
     int32_t k, kp;
 };
 
+// One item: an entry i of a factor and a tile of up to kRcCols output
+// columns, so each X[q][i] is read once per tile; fixed summation order.
+constexpr int kRcCols = 16;
+
 __global__ void k_rc_apply(const RcApply* __restrict__ d, const double* __restrict__ fac,
                            const double* __restrict__ tws, double* __restrict__ out)
 {
     const RcApply D = d[blockIdx.y];
-    const int64_t nu = D.lu * D.kp, nv = D.lv * D.kp;
+    const int ntile = (D.kp + kRcCols - 1) / kRcCols;
+    const int64_t nu = D.lu * ntile, nv = D.lv * ntile;
     const double* Tu = tws + D.t_off;
     const double* Tv = Tu + (int64_t)D.k * D.kp;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nu + nv;
@@ -688,13 +821,25 @@ __global__ void k_rc_apply(const RcApply* __restrict__ d, const double* __restri
         const bool isu = idx < nu;
         const int64_t e = isu ? idx : idx - nu;
         const int64_t L = isu ? D.lu : D.lv;
-        const int col = (int)(e / L);
-        const int64_t i = e - (int64_t)col * L;
+        const int tile = (int)(e / L);
+        const int64_t i = e - (int64_t)tile * L;
         const double* X = fac + (isu ? D.src_u : D.src_v);
-        const double* T = isu ? Tu : Tv;
-        double sum = 0.0;
-        for (int q = 0; q < D.k; ++q) sum += X[(int64_t)q * L + i] * T[(int64_t)q * D.kp + col];
-        out[(isu ? D.dst_u : D.dst_v) + e] = sum;
+        const double* T = (isu ? Tu : Tv) + tile * kRcCols;
+        const int nc = min(kRcCols, D.kp - tile * kRcCols);
+        double acc[kRcCols];
+#pragma unroll
+        for (int c = 0; c < kRcCols; ++c) acc[c] = 0.0;
+        for (int q = 0; q < D.k; ++q) {
+            const double x = X[(int64_t)q * L + i];
+            const double* t = T + (int64_t)q * D.kp;
+#pragma unroll
+            for (int c = 0; c < kRcCols; ++c)
+                if (c < nc) acc[c] += x * t[c];
+        }
+        double* o = out + (isu ? D.dst_u : D.dst_v) + (int64_t)tile * kRcCols * L + i;
+#pragma unroll
+        for (int c = 0; c < kRcCols; ++c)
+            if (c < nc) o[(int64_t)c * L] = acc[c];
     }
 }
 
@@ -1154,109 +1299,59 @@ void upload_tasks(Variant& v, hipStream_t s)
 }
 
 // Recompress every factorisation of rank >= 2 at relative Frobenius
-// tolerance tol; the others are copied unchanged.  Ranks above kRcMax are
-// taken in chunks of kRcMax columns (cross-approximation columns come in
-// decreasing order of importance): with G chunks, chunk 0 is truncated at
-// tol / G of its own norm and every later chunk may discard at most
-// (tol / G)^2 times chunk 0's energy, so the discarded part of the block is
-// within tol of chunk 0's norm, which is the block's norm up to the cross
-// approximation's remainder.  Replaces d_fac.
+// tolerance tol (one workgroup each, one kernel per rank class: up to 64,
+// up to 128, above, the larger in batches); the factors of every
+// block with a usable result are rewritten as U T_u, V T_v, the rest (a
+// numerically zero block) copied unchanged.  Replaces d_fac.
 static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
 {
-    struct Chunk {
-        int block, g, c0, kc;  // chunk g: columns c0 .. c0 + kc - 1 of the block
-        int job = -1;          // index into the launch's descriptors
-        int kp = -1;           // kept columns (-1: unchanged)
-        int64_t t_off = 0;
-    };
-    std::vector<Chunk> ch;
-    std::vector<int> nchunks(op.lr.size(), 0);
-    for (size_t b = 0; b < op.lr.size(); ++b) {
+    const size_t nb = op.lr.size();
+    std::vector<int64_t> t_off(nb, -1);
+    int64_t tws = 0;
+    std::vector<int> small, mid, large;
+    for (size_t b = 0; b < nb; ++b) {
         const int k = op.lr[b].rank;
         if (k < 2) continue;
-        const int G = (k + kRcMax - 1) / kRcMax;
-        nchunks[b] = G;
-        for (int g = 0; g < G; ++g) ch.push_back(Chunk{(int)b, g, g * kRcMax, std::min(kRcMax, k - g * kRcMax)});
-    }
-    int64_t tws = 0;
-    for (Chunk& c : ch) {
-        c.t_off = tws;
-        tws += 2 * (int64_t)c.kc * c.kc;
+        HM_REQUIRE(k <= kAcaMaxRank, HM_EINTERNAL, "rank above the cross-approximation cap");
+        t_off[b] = tws;
+        tws += 2 * (int64_t)k * k;
+        (k <= kRcSmall ? small : (k <= kRcMid ? mid : large)).push_back((int)b);
     }
     DevBuf d_t(std::max<int64_t>(1, tws) * sizeof(double));
-    std::vector<double> energy0(op.lr.size(), 0.0);
-    HM_CHECK_HIP(hipFuncSetAttribute((const void*)k_recompress, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)kRcLds));
-    // pass 0: chunk 0 of every block (relative budget); pass 1: later chunks
-    for (int pass = 0; pass < 2; ++pass) {
-        std::vector<RcDesc> rc;
-        std::vector<int> idx;
-        for (size_t q = 0; q < ch.size(); ++q) {
-            Chunk& c = ch[q];
-            if ((pass == 0) != (c.g == 0) || c.kc < 2) continue;
-            const LowRank& L = op.lr[c.block];
-            const int G = nchunks[c.block];
-            const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
-            const double abs2 = pass == 0 ? 0.0 : (tol / G) * (tol / G) * energy0[c.block];
-            if (pass == 1 && !(abs2 > 0.0)) continue;  // chunk 0 failed: keep the rest as it is
-            rc.push_back(RcDesc{L.u_off + c.c0 * lu, L.v_off + c.c0 * lv, lu, lv, c.t_off, abs2, c.kc, 0});
-            idx.push_back((int)q);
-        }
-        if (rc.empty()) continue;
-        std::vector<int> kp(rc.size());
-        std::vector<double> en(rc.size());
-        if (pass == 0) {
-            // chunk 0 is truncated at tol / G of its own norm: one launch per chunk count G
-            for (int G = 1; G <= (kAcaMaxRank + kRcMax - 1) / kRcMax; ++G) {
-                std::vector<RcDesc> sub;
-                std::vector<int> where;
-                for (size_t q = 0; q < rc.size(); ++q)
-                    if (nchunks[ch[idx[q]].block] == G) {
-                        sub.push_back(rc[q]);
-                        where.push_back((int)q);
-                    }
-                if (sub.empty()) continue;
-                DevBuf d_sub, d_ks(sub.size() * sizeof(int)), d_es(sub.size() * sizeof(double));
-                upload(d_sub, sub, s);
-                hipLaunchKernelGGL(k_recompress, dim3((unsigned)sub.size()), dim3(256), kRcLds, s,
-                                   d_sub.as<RcDesc>(), d_fac.as<double>(), tol / G, d_t.as<double>(), d_ks.as<int>(),
-                                   d_es.as<double>());
-                HM_CHECK_HIP(hipGetLastError());
-                std::vector<int> ks(sub.size());
-                std::vector<double> es(sub.size());
-                HM_CHECK_HIP(hipMemcpyAsync(ks.data(), d_ks.get(), ks.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-                HM_CHECK_HIP(
-                    hipMemcpyAsync(es.data(), d_es.get(), es.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-                HM_CHECK_HIP(hipStreamSynchronize(s));
-                for (size_t q = 0; q < sub.size(); ++q) {
-                    kp[where[q]] = ks[q];
-                    en[where[q]] = es[q];
-                }
+    std::vector<int> kp(nb, -1);
+    auto run = [&](const std::vector<int>& ids, auto kernel, size_t lds, size_t slot_doubles, size_t per_launch) {
+        if (ids.empty()) return;
+        HM_CHECK_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        DevBuf d_slots(std::max<size_t>(1, slot_doubles * std::min(per_launch, ids.size())) * sizeof(double));
+        for (size_t c0 = 0; c0 < ids.size(); c0 += per_launch) {
+            const size_t n = std::min(per_launch, ids.size() - c0);
+            std::vector<RcDesc> rc;
+            for (size_t q = c0; q < c0 + n; ++q) {
+                const LowRank& L = op.lr[ids[q]];
+                const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
+                rc.push_back(RcDesc{L.u_off, L.v_off, lu, lv, t_off[ids[q]], L.rank, 0});
             }
-        } else {
-            DevBuf d_rc, d_k(rc.size() * sizeof(int)), d_e(rc.size() * sizeof(double));
+            DevBuf d_rc, d_k(n * sizeof(int)), d_e(n * sizeof(double));
             upload(d_rc, rc, s);
-            hipLaunchKernelGGL(k_recompress, dim3((unsigned)rc.size()), dim3(256), kRcLds, s, d_rc.as<RcDesc>(),
-                               d_fac.as<double>(), tol, d_t.as<double>(), d_k.as<int>(), d_e.as<double>());
+            hipLaunchKernelGGL(kernel, dim3((unsigned)n), dim3(kRcThreads), lds, s, d_rc.as<RcDesc>(), d_fac.as<double>(),
+                               tol, d_t.as<double>(), d_k.as<int>(), d_e.as<double>(), d_slots.as<double>());
             HM_CHECK_HIP(hipGetLastError());
-            HM_CHECK_HIP(hipMemcpyAsync(kp.data(), d_k.get(), kp.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            std::vector<int> ks(n);
+            HM_CHECK_HIP(hipMemcpyAsync(ks.data(), d_k.get(), n * sizeof(int), hipMemcpyDeviceToHost, s));
             HM_CHECK_HIP(hipStreamSynchronize(s));
+            for (size_t q = 0; q < n; ++q) kp[ids[c0 + q]] = ks[q];
         }
-        for (size_t q = 0; q < rc.size(); ++q) {
-            Chunk& c = ch[idx[q]];
-            c.job = (int)q;
-            c.kp = (kp[q] > 0 && kp[q] < c.kc) ? kp[q] : -1;
-            if (pass == 0) energy0[c.block] = kp[q] >= 0 ? en[q] : 0.0;
-        }
-    }
-    // new ranks and compact store: recompressed chunks through k_rc_apply, the rest copied
-    std::vector<int> newk(op.lr.size());
-    for (size_t b = 0; b < op.lr.size(); ++b) newk[b] = op.lr[b].rank;
-    for (const Chunk& c : ch)
-        if (c.kp > 0) newk[c.block] -= c.kc - c.kp;
+    };
+    run(small, k_recompress<kRcSmall>, RcShape<kRcSmall>::kLds, 0, 1 << 20);
+    // global slots of the work matrices outside LDS, 1024 workgroups per launch
+    run(mid, k_recompress<kRcMid>, RcShape<kRcMid>::kLds, RcShape<kRcMid>::kSlot, 1024);
+    run(large, k_recompress<kAcaMaxRank>, RcShape<kAcaMaxRank>::kLds, RcShape<kAcaMaxRank>::kSlot, 512);
+    // new ranks and compact store: recompressed blocks through k_rc_apply, the rest copied
+    std::vector<int> newk(nb);
+    for (size_t b = 0; b < nb; ++b) newk[b] = kp[b] >= 1 ? kp[b] : op.lr[b].rank;
     int64_t total = 0;
-    std::vector<int64_t> nu(op.lr.size()), nv(op.lr.size());
-    for (size_t b = 0; b < op.lr.size(); ++b) {
+    std::vector<int64_t> nu(nb), nv(nb);
+    for (size_t b = 0; b < nb; ++b) {
         const LowRank& L = op.lr[b];
         nu[b] = total;
         total += (int64_t)newk[b] * L.comps * L.m;
@@ -1266,43 +1361,23 @@ static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
     DevBuf out(std::max<int64_t>(1, total) * sizeof(double));
     std::vector<RcApply> ap;
     std::vector<CompactDesc> cp;
-    std::vector<int> col(op.lr.size(), 0);  // next output column of each block
-    auto copy_cols = [&](size_t b, int c0, int kc) {
-        const LowRank& L = op.lr[b];
-        const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
-        cp.push_back(CompactDesc{L.u_off + c0 * lu, nu[b] + col[b] * lu, (int64_t)kc * lu});
-        cp.push_back(CompactDesc{L.v_off + c0 * lv, nv[b] + col[b] * lv, (int64_t)kc * lv});
-        col[b] += kc;
-    };
-    size_t q = 0;
-    for (size_t b = 0; b < op.lr.size(); ++b) {
+    for (size_t b = 0; b < nb; ++b) {
         const LowRank& L = op.lr[b];
         if (L.rank == 0) continue;
-        if (nchunks[b] == 0) {
-            copy_cols(b, 0, L.rank);
-            continue;
-        }
         const int64_t lu = (int64_t)L.comps * L.m, lv = (int64_t)L.comps * L.n;
-        for (int g = 0; g < nchunks[b]; ++g, ++q) {
-            const Chunk& c = ch[q];
-            if (c.kp > 0) {
-                ap.push_back(RcApply{L.u_off + c.c0 * lu, L.v_off + c.c0 * lv, nu[b] + col[b] * lu,
-                                     nv[b] + col[b] * lv, lu, lv, c.t_off, c.kc, c.kp});
-                col[b] += c.kp;
-            } else {
-                copy_cols(b, c.c0, c.kc);
-            }
+        if (kp[b] >= 1) {
+            ap.push_back(RcApply{L.u_off, L.v_off, nu[b], nv[b], lu, lv, t_off[b], L.rank, kp[b]});
+        } else {
+            cp.push_back(CompactDesc{L.u_off, nu[b], (int64_t)L.rank * lu});
+            cp.push_back(CompactDesc{L.v_off, nv[b], (int64_t)L.rank * lv});
         }
     }
-    HM_REQUIRE(q == ch.size(), HM_EINTERNAL, "recompression chunk bookkeeping");
-    for (size_t b = 0; b < op.lr.size(); ++b)
-        HM_REQUIRE(col[b] == newk[b], HM_EINTERNAL, "recompression rank bookkeeping");
     if (!ap.empty()) {
         DevBuf d_ap;
         upload(d_ap, ap, s);
         for (size_t c0 = 0; c0 < ap.size(); c0 += 65535) {
-            const unsigned nb = (unsigned)std::min<size_t>(65535, ap.size() - c0);
-            hipLaunchKernelGGL(k_rc_apply, dim3(32, nb), dim3(256), 0, s, d_ap.as<RcApply>() + c0, d_fac.as<double>(),
+            const unsigned n = (unsigned)std::min<size_t>(65535, ap.size() - c0);
+            hipLaunchKernelGGL(k_rc_apply, dim3(32, n), dim3(256), 0, s, d_ap.as<RcApply>() + c0, d_fac.as<double>(),
                                d_t.as<double>(), out.as<double>());
             HM_CHECK_HIP(hipGetLastError());
         }
@@ -1311,14 +1386,14 @@ static void recompress_factors(Op& op, DevBuf& d_fac, double tol, hipStream_t s)
         DevBuf d_cp;
         upload(d_cp, cp, s);
         for (size_t c0 = 0; c0 < cp.size(); c0 += 65535) {
-            const unsigned nb = (unsigned)std::min<size_t>(65535, cp.size() - c0);
-            hipLaunchKernelGGL(k_compact, dim3(64, nb), dim3(256), 0, s, d_cp.as<CompactDesc>() + c0,
+            const unsigned n = (unsigned)std::min<size_t>(65535, cp.size() - c0);
+            hipLaunchKernelGGL(k_compact, dim3(64, n), dim3(256), 0, s, d_cp.as<CompactDesc>() + c0,
                                d_fac.as<double>(), out.as<double>());
             HM_CHECK_HIP(hipGetLastError());
         }
     }
     HM_CHECK_HIP(hipStreamSynchronize(s));
-    for (size_t b = 0; b < op.lr.size(); ++b) {
+    for (size_t b = 0; b < nb; ++b) {
         op.lr[b].rank = newk[b];
         op.lr[b].u_off = nu[b];
         op.lr[b].v_off = nv[b];

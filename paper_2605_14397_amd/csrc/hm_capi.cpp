@@ -130,7 +130,7 @@ void hm_build_opts_default(hm_build_opts* o)
     o->leaf_size = 64;
     o->eta = 2.0;
     o->aca_tol = 1e-6;
-    o->max_rank = 192;
+    o->max_rank = 128;
     o->near_prec = HM_F64;
     o->far_prec = HM_F64;
     o->keep_f64_reference = 0;

@@ -102,6 +102,38 @@ def test_recompression_keeps_the_block_tolerance():
     assert st1["bytes_far"] < st0["bytes_far"]
 
 
+def test_recompressed_factors_survive_short_formats_at_every_rank_class():
+    """Three intersecting disks at ACA 1e-9, rank cap 192: the cross
+    approximations reach past 64 and 128, so all three recompression
+    kernels run.  Every block is stored with orthonormal left factors, so the
+    BF16 far field perturbs each block by about BF16's relative precision
+    times its norm: the BF16-far product stays within 1e-4 of the FP64 one,
+    and the FP64 product meets the tolerance on exact oracle rows."""
+    hm = _hm()
+    from workloads import three_disks
+
+    m = three_disks(rings=24)
+    X = rhs_columns(m.ndof, 4, 4300)
+    mesh = hm.Mesh.from_workload(m)
+    op = hm.Operator(mesh, YOUNG, NU, leaf_size=64, aca_tol=1e-9, max_rank=192, near_prec=hm.HM_F32,
+                     far_prec=hm.HM_BF16, keep_f64_reference=1)
+    st = op.stats()
+    y64 = op.apply(cuda(X), reference=True).cpu().numpy()
+    ybf = op.apply(cuda(X)).cpu().numpy()
+    rng = np.random.default_rng(4301)
+    rows = np.sort(rng.choice(m.ne, 48, replace=False))
+    R = oracle.rows_matvec(m, YOUNG, NU, rows, X, method=1)
+    dof = (3 * rows[:, None] + np.arange(3)).ravel()
+    e64 = colerr(y64[:, dof], R)
+    ebf = colerr(ybf, y64)
+    print(f"three disks ({m.ne} triangles) ACA 1e-9: ranks {st['min_rank']}..{st['max_rank']} "
+          f"(cross approximations {st['rank_sum_aca']} -> {st['rank_sum']}); FP64 vs oracle rows {e64:.3e}, "
+          f"BF16 far vs FP64 {ebf:.3e}")
+    assert st["rank_sum"] < st["rank_sum_aca"] and st["max_rank"] > 128
+    assert e64 <= 1e-7
+    assert ebf <= 1e-4
+
+
 def test_high_ranks_run_in_row_windows():
     """At ACA 1e-12 the low-rank blocks of a 48 x 48 fault exceed 64 (more
     than four row tiles): their phase-A and phase-B tasks are split into

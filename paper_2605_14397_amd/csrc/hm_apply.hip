@@ -91,13 +91,22 @@ struct AccScalar<d4> {
     __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 
-// Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-// contiguous range of tasks so neighbouring leaves share one L2.
-__device__ inline int xcd_task(int bid, int grid, int ntasks)
+// Workgroups are dealt to the 8 XCDs round-robin: workgroup bid runs on
+// XCD bid & 7 as that XCD's (bid >> 3)-th.  Each XCD takes its own
+// contiguous task range (neighbouring leaves share one L2), per = tasks per
+// workgroup.
+__device__ inline int xcd_task(int bid, const XcdSplit& sp, int per, int sub)
 {
-    int per = grid >> 3;
-    int t = (bid & 7) * per + (bid >> 3);
-    return t < ntasks ? t : -1;
+    const int x = bid & 7;
+    const int t = sp.begin[x] + per * (bid >> 3) + sub;
+    return t < sp.begin[x + 1] ? t : -1;
+}
+
+__host__ inline unsigned xcd_grid(const XcdSplit& sp, int per)
+{
+    int m = 0;
+    for (int x = 0; x < 8; ++x) m = std::max(m, (sp.begin[x + 1] - sp.begin[x] + per - 1) / per);
+    return 8u * (unsigned)m;
 }
 
 // Buffers of one operand pair: A panels and the in-vector chunks they read.
@@ -403,16 +412,14 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const MemberT
 // The hardware deals the workgroups out as slots free up, which balances
 // the uneven task lengths.
 template <class FT, class ACC>
-__global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, XcdSplit sp,
                                                 const PanelRef* __restrict__ items,
                                                 const MemberT* __restrict__ members, const Bases* __restrict__ bases)
 {
     typedef typename AccScalar<ACC>::type S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int g = xcd_task(blockIdx.x, gridDim.x, (ntasks + 3) / 4);
-    if (g < 0) return;
-    const int t = 4 * g + wave;
-    if (t >= ntasks) return;
+    const int t = xcd_task(blockIdx.x, sp, 4, wave);
+    if (t < 0) return;
     const TaskA T = tasks[t];
     const Bases B = bases[T.op];
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.xfhi),
@@ -480,12 +487,12 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
 // One launch for every task (one workgroup each), compiled for each window
 // height and picked per task.
 template <class NT, class FT, class ACC>
-__global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, int ntasks,
+__global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, XcdSplit sp,
                                                 const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
 {
     typedef typename AccScalar<ACC>::type S;
     __shared__ S red[3 * 256];
-    const int t = xcd_task(blockIdx.x, gridDim.x, ntasks);
+    const int t = xcd_task(blockIdx.x, sp, 1, 0);
     if (t < 0) return;
     const TaskB T = tasks[t];
     const Bases B = bases[T.op];
@@ -688,6 +695,8 @@ LaunchSet launch_set(const Variant& v, const void* block)
     L.bases = reinterpret_cast<const Bases*>(static_cast<const char*>(block) + v.ws_layout().bases);
     L.tasksA = v.tasksA.as<TaskA>();
     L.nTasksA = v.nTasksA;
+    L.splitA = v.splitA;
+    L.splitB = v.splitB;
     L.itemsA = v.itemsA.as<PanelRef>();
     L.membersA = v.membersA.as<MemberT>();
     L.reduce = v.reduce.as<ReduceDesc>();
@@ -736,21 +745,16 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
             hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
     }
     mark(1);
-    if (L.nTasksA > 0) {
-        // a multiple of 8 workgroups for the XCD-contiguous task map
-        const unsigned grid = (unsigned)round_up((L.nTasksA + 3) / 4, 8);
-        hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksA, L.nTasksA, L.itemsA,
-                           L.membersA, L.bases);
-    }
+    if (L.nTasksA > 0)
+        hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(xcd_grid(L.splitA, 4)), dim3(256), 0, s, L.tasksA, L.splitA,
+                           L.itemsA, L.membersA, L.bases);
     mark(2);
     if (L.nReduce > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(L.nReduce), dim3(256), 0, s, L.reduce, L.bases);
     mark(3);
-    if (L.nTasksB > 0) {
-        const unsigned grid = (unsigned)round_up(L.nTasksB, 8);
-        hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(grid), dim3(256), 0, s, L.tasksB, L.nTasksB, L.itemsB,
-                           L.bases);
-    }
+    if (L.nTasksB > 0)
+        hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(xcd_grid(L.splitB, 1)), dim3(256), 0, s, L.tasksB, L.splitB,
+                           L.itemsB, L.bases);
     mark(4);
     {
         const unsigned gx = (unsigned)((max_ne * nrhs + 255) / 256);

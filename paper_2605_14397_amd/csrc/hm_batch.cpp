@@ -79,7 +79,8 @@ struct Batch {
         L = LaunchSet();
         L.near_prec = near_prec;
         L.far_prec = far_prec;
-        order_tasksA(ta, ia);
+        L.splitA = order_tasksA(ta, ia);
+        L.splitB = order_tasksB(tb, ib, near_prec, far_prec);
         upload(bases, hb, s);
         upload(tasksA, ta, s);
         upload(itemsA, ia, s);

@@ -1173,11 +1173,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
             ib.insert(ib.end(), its.begin(), its.end());
         }
     }
-    // one launch in leaf order: each XCD runs a contiguous run of leaves
-    for (const TaskB& t : tb) {
-        const int R = window_tiles(t.rows, t.r0);
-        HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "leaf rows out of range");
-    }
+    v.splitB = order_tasksB(tb, ib, v.near_prec, v.far_prec);
     v.nTasksB = (int)tb.size();
     v.tfrag_elems = tfrag;
     build_tasksA(op, v, v.leavesPerTaskA);
@@ -1246,41 +1242,84 @@ void build_tasksA(const Op& op, Variant& v, int items_per_task)
                 red.push_back(ReduceDesc{slot0 + (int64_t)G.lo[j] * kNrhs, v.t_off[G.blocks[j]], n_slots,
                                          op.lr[G.blocks[j]].rank, 0, (int32_t)slot});
     }
-    order_tasksA(ta, ia);
+    v.splitA = order_tasksA(ta, ia);
     v.nTasksA = (int)ta.size();
     v.nReduce = (int)red.size();
     v.tpart_elems = tpart;
 }
 
-void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items)
+// Cut tasks (in their current order) into 8 contiguous ranges of about
+// equal cost and sort each range by cost, longest first (stable).
+template <class T>
+static XcdSplit xcd_balance(std::vector<T>& tasks, const std::vector<int64_t>& cost)
 {
-    // loads of a task: its sub-panels' columns times (window tiles + the in-vector)
-    auto cost = [&](const TaskA& t) {
-        int64_t c = 0;
-        for (int q = 0; q < t.n_items; ++q) c += items[t.item_begin + q].cols;
-        return c * (window_tiles(t.rows, t.r0) + 1);
-    };
+    XcdSplit sp{};
+    const size_t n = tasks.size();
+    std::vector<int64_t> pre(n + 1, 0);
+    for (size_t q = 0; q < n; ++q) pre[q + 1] = pre[q] + cost[q];
+    sp.begin[0] = 0;
+    size_t q = 0;
+    for (int x = 1; x < 8; ++x) {
+        const int64_t target = pre[n] * x / 8;
+        while (q < n && pre[q + 1] <= target) ++q;
+        sp.begin[x] = (int32_t)q;
+    }
+    sp.begin[8] = (int32_t)n;
+    for (int x = 0; x < 8; ++x) {
+        std::vector<std::pair<int64_t, T>> part;
+        for (int32_t t = sp.begin[x]; t < sp.begin[x + 1]; ++t) part.push_back({cost[t], tasks[t]});
+        std::stable_sort(part.begin(), part.end(),
+                         [](const std::pair<int64_t, T>& a, const std::pair<int64_t, T>& b) { return a.first > b.first; });
+        for (size_t i = 0; i < part.size(); ++i) tasks[sp.begin[x] + i] = part[i].second;
+    }
+    return sp;
+}
+
+// bytes a task streams: its panels' rows inside the window times their
+// granules, plus one 1 KB in-vector k-step per unit
+static int64_t task_bytes(const PanelRef* it, int n_items, int rows, int r0, int wn, int wf)
+{
+    const int R = window_tiles(rows, r0);
+    int64_t c = 0;
+    for (int q = 0; q < n_items; ++q) {
+        const PanelRef& P = it[q];
+        const int w = P.far ? wf : wn;
+        const int64_t gran = (P.cols + w - 1) / w;
+        c += (int64_t)std::min(16 * R, P.rows - 16 * r0) * gran * 16 + (gran + 3) / 4 * 1024;
+    }
+    return c;
+}
+
+XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items)
+{
     for (const TaskA& t : ta) {
         const int R = window_tiles(t.rows, t.r0);
         HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "phase-A window out of range");
     }
-    // each XCD runs one contiguous eighth of the tasks (four per workgroup):
-    // ordered by source chunk, one XCD's L2 holds only its share of X;
-    // longest first inside each share for a short tail
+    // by source chunk: one XCD's L2 holds only its share of X
     std::stable_sort(ta.begin(), ta.end(), [&](const TaskA& a, const TaskA& b) {
         return items[a.item_begin].b_off < items[b.item_begin].b_off;
     });
-    const size_t share = 4 * (size_t)(round_up((int64_t)(ta.size() + 3) / 4, 8) / 8);
-    for (size_t x0 = 0; x0 < ta.size(); x0 += std::max<size_t>(1, share)) {
-        const size_t x1 = std::min(ta.size(), x0 + share);
-        std::vector<std::pair<int64_t, TaskA>> part;
-        for (size_t q = x0; q < x1; ++q) part.push_back({cost(ta[q]), ta[q]});
-        std::stable_sort(part.begin(), part.end(),
-                         [](const std::pair<int64_t, TaskA>& a, const std::pair<int64_t, TaskA>& b) {
-                             return a.first > b.first;
-                         });
-        for (size_t q = x0; q < x1; ++q) ta[q] = part[q - x0].second;
+    std::vector<int64_t> cost(ta.size());
+    for (size_t q = 0; q < ta.size(); ++q) {
+        const TaskA& t = ta[q];
+        // every sub-panel is far; the element width only scales the cost
+        cost[q] = task_bytes(items.data() + t.item_begin, t.n_items, t.rows, t.r0, 4, 4);
     }
+    return xcd_balance(ta, cost);
+}
+
+XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec)
+{
+    for (const TaskB& t : tb) {
+        const int R = window_tiles(t.rows, t.r0);
+        HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "leaf rows out of range");
+    }
+    const int wn = prec_w(near_prec), wf = prec_w(far_prec);
+    std::vector<int64_t> cost(tb.size());
+    for (size_t q = 0; q < tb.size(); ++q)
+        cost[q] = task_bytes(items.data() + tb[q].item_begin, tb[q].n_items, tb[q].rows, tb[q].r0, wn, wf);
+    return xcd_balance(tb, cost);
 }
 
 // Upload the task lists; the workspaces are resized on their next use (the

@@ -220,6 +220,13 @@ __host__ __device__ inline int window_tiles(int rows, int r0)
     return t < kTileWindow ? t : kTileWindow;
 }
 
+// Contiguous task ranges of the 8 XCDs (workgroups are dealt to the XCDs
+// round-robin): XCD x runs tasks begin[x] .. begin[x + 1] - 1, cut so that
+// the ranges carry about equal loads, longest task first inside a range.
+struct XcdSplit {
+    int32_t begin[9];
+};
+
 struct TaskB {        // one row window of one section of a target leaf
     int64_t y_off;    // output rows start in Y (section start)
     int32_t rows;     // rows of the section (= rows of each of its panels)

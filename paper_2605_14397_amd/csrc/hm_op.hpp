@@ -36,6 +36,7 @@ struct Variant {
     DevBuf near_a, far_a;         // panels
     DevBuf tasksB, itemsB, tasksA, itemsA, membersA, reduce;
     int nTasksB = 0, nTasksA = 0, nReduce = 0;
+    XcdSplit splitA{}, splitB{};
     int64_t tpart_elems = 0, tfrag_elems = 0;
     int64_t bytes_near = 0, bytes_far = 0, bytes_far_u = 0, bytes_far_v = 0;
     int64_t near_entries = 0;     // dense-piece entries stored, without padding
@@ -91,6 +92,7 @@ struct LaunchSet {
     int nReduce = 0;
     const TaskB* tasksB = nullptr;
     int nTasksB = 0;
+    XcdSplit splitA{}, splitB{};
     const PanelRef* itemsB = nullptr;
 };
 
@@ -231,9 +233,11 @@ void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
 // Order a phase-A task list for launch: grouped by row-tile count (one
 // launch per group, largest first); inside a group ordered by the in-vector
 // chunk of the first sub-panel, then longest first inside each XCD's share.
-// sort phase-A tasks for one launch (XCD shares by source chunk, longest
-// first inside each share)
-void order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items);
+// sort phase-A tasks for one launch (by source chunk, then XCD ranges of
+// equal load, longest first inside each) and return the ranges
+XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items);
+// the same for phase-B tasks (leaf order, then XCD ranges of equal load)
+XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec);
 void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 void interface_update(int n_mat, const hm_interface_material* mats, int64_t n, const int32_t* d_mat_id,

@@ -54,7 +54,12 @@ typedef enum {
     HM_EINTERNAL = -7
 } hm_status;
 
-enum { HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2 };
+/* Storage precisions.  HM_BF16 (far field only): BF16 factors, the vectors
+ * they multiply carried as a BF16 hi/lo pair (two MFMA products), so the
+ * factors alone set the rounding error.  HM_BF16_1: BF16 factors and
+ * vectors rounded to one BF16 each (half the vector traffic and MFMA work;
+ * the far field's rounding error grows by about sqrt(2)). */
+enum { HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2, HM_BF16_1 = 3 };
 
 typedef struct hm_mesh hm_mesh;
 typedef struct hm_op hm_op;
@@ -153,7 +158,7 @@ typedef struct {
     int max_rank;           /* cap on the rank of a low-rank block (<= 192): a block whose cross approximation
                                needs more is split into its children; default 128 */
     int near_prec;          /* HM_F64 or HM_F32 for dense leaves */
-    int far_prec;           /* HM_F64, HM_F32 or HM_BF16 for low-rank factors */
+    int far_prec;           /* HM_F64, HM_F32, HM_BF16 or HM_BF16_1 for low-rank factors */
     int keep_f64_reference; /* also keep an all-FP64 copy (used by refinement) */
     int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 and store it with
                                orthonormal left factors (any rank); default 1 */

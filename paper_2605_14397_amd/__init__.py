@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhmdd.so")
 
 HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_EBADMESH, HM_EUNSUPPORTED, HM_ENOTCONV, HM_EINTERNAL = (
     0, -1, -2, -3, -4, -5, -6, -7)
-HM_F64, HM_F32, HM_BF16 = 0, 1, 2
+HM_F64, HM_F32, HM_BF16, HM_BF16_1 = 0, 1, 2, 3
 HM_APPLY_REFERENCE, HM_APPLY_TANGENT, HM_APPLY_ACCUMULATE = 1, 2, 4
 HM_PC_NONE, HM_PC_JACOBI, HM_PC_BLOCK3, HM_PC_LEARNED, HM_PC_LEAF, HM_PC_ILU = 0, 1, 2, 3, 4, 5
 HM_FALLBACK_NONE, HM_FALLBACK_NOT_ATTACHED, HM_FALLBACK_NONFINITE, HM_FALLBACK_NOT_CONVERGED = 0, 1, 2, 3

@@ -75,6 +75,22 @@ struct Mma<uint16_t> {
     }
 };
 
+// BF16 in-vectors without a lo half (one product per k-step)
+struct bf16s {
+    uint16_t bits;
+};
+
+template <>
+struct Mma<bf16s> {
+    static constexpr int w = 8;
+    template <class A>
+    __device__ static A run(u4 ra, u4 rb, u4, A c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ra), __builtin_bit_cast(bf8, rb), c, 0,
+                                                        0, 0);
+    }
+};
+
 template <class A>
 struct AccScalar;
 // Row of the 16x16 result held by (lane, register v); the column is lane % 16.
@@ -271,7 +287,7 @@ __device__ __attribute__((always_inline)) inline void stream_units(const PanelRe
                                                                     int u0, int step, int lane, ACC (&acc)[R])
 {
     // only BF16 in-vectors carry a lo part
-    constexpr bool kLo = sizeof(NT) == 2 || sizeof(FT) == 2;
+    constexpr bool kLo = std::is_same<FT, uint16_t>::value;
     const int ksn = 4 * nearS.w, ksf = 4 * farS.w;
     Cursor c;
     c.init(items, n_items, ksn, ksf);
@@ -361,11 +377,13 @@ struct Sides {
 template <class FT, class S>
 __device__ inline void store_t(FT* __restrict__ thi, FT* __restrict__ tlo, int64_t off, S v)
 {
-    if constexpr (sizeof(FT) == 2) {
+    if constexpr (std::is_same<FT, uint16_t>::value) {
         float f = (float)v;
         uint16_t h = f32_to_bf16_bits(f);
         thi[off] = h;
         tlo[off] = f32_to_bf16_bits(f - bf16_bits_to_f32(h));
+    } else if constexpr (std::is_same<FT, bf16s>::value) {
+        thi[off] = bf16s{f32_to_bf16_bits((float)v)};
     } else {
         thi[off] = (FT)v;
     }
@@ -775,8 +793,10 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
         launch_t<double, double, d4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
     else if (L.far_prec == HM_F32)
         launch_t<float, float, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
-    else
+    else if (L.far_prec == HM_BF16)
         launch_t<float, uint16_t, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+    else
+        launch_t<float, bf16s, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
 }
 
 void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,

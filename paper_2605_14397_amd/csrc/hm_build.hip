@@ -1452,8 +1452,8 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     HM_REQUIRE(o.stack_rows >= 0, HM_EINVAL, "stack_rows must be >= 0");
     HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
-    HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16, HM_EUNSUPPORTED,
-               "far_prec must be F64, F32 or BF16");
+    HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1,
+               HM_EUNSUPPORTED, "far_prec must be F64, F32, BF16 or BF16_1");
     HM_REQUIRE(!(o.near_prec == HM_F64 && o.far_prec != HM_F64), HM_EUNSUPPORTED,
                "an FP64 near field requires an FP64 far field");
     HM_REQUIRE(!(o.near_prec == HM_F32 && o.far_prec == HM_F64), HM_EUNSUPPORTED,

@@ -671,7 +671,7 @@ hm_status solve(Op& op, const hm_solve_opts& o, int nrhs, const double* d_B, int
         // A sweep cannot reduce the FP64 residual by more than the
         // low-precision operator's own error allows (about 1e-2 with BF16
         // factors, 1e-5 with FP32), so by default the inner solve stops there.
-        const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : (op.main.far_prec == HM_BF16 ? 1e-2 : 1e-5);
+        const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : (op.main.far_prec == HM_BF16 || op.main.far_prec == HM_BF16_1 ? 1e-2 : 1e-5);
         while (sweeps < o.max_refine && iters < o.max_iter) {
             K.dots(rbuf.as<double>(), 1, rbuf.as<double>());
             K.fetch(1);

@@ -10,7 +10,8 @@ the three forms:
   * FP64 H-matrix (the reference copy), ACA 1e-6: per-column bar 1e-6;
   * FP32 near and far field, FP32 accumulation: bar 1e-5;
   * FP32 near, BF16 far (hi/lo split in-vector), FP32 accumulation, FP64
-    self blocks: bar 5e-3.
+    self blocks: bar 5e-3;
+  * the same with single BF16 in-vectors: bar 5e-3.
 Per column: ||Y - Y_ref||_2 / ||Y_ref||_2; max entry error relative to the
 largest |Y_ref| of its column is printed beside it.
 """
@@ -50,8 +51,14 @@ def test_primary_configuration_full_product_exact():
     opbf = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
                        far_prec=hm.HM_BF16)
     ybf = opbf.apply(Xd).cpu().numpy()
+    del opbf
+    opb1 = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
+                       far_prec=hm.HM_BF16_1)
+    yb1 = opb1.apply(Xd).cpu().numpy()
+    del opb1
     results = {}
-    for name, y, bar in (("fp64", y64, 1e-6), ("fp32", y32, 1e-5), ("fp32_near_bf16_far", ybf, 5e-3)):
+    for name, y, bar in (("fp64", y64, 1e-6), ("fp32", y32, 1e-5), ("fp32_near_bf16_far", ybf, 5e-3),
+                         ("fp32_near_bf16_far_single", yb1, 5e-3)):
         col, ent = _errors(y, ref)
         results[name] = (col.max(), ent.max())
         print(f"256x256 {name}: per-column rel err max {col.max():.3e} (min {col.min():.3e}), "
@@ -59,3 +66,5 @@ def test_primary_configuration_full_product_exact():
         assert col.max() <= bar, (name, col)
     # the forms order as their precisions do
     assert results["fp64"][0] < results["fp32"][0] < results["fp32_near_bf16_far"][0]
+    assert results["fp32_near_bf16_far"][0] <= results["fp32_near_bf16_far_single"][0] <= 4 * results[
+        "fp32_near_bf16_far"][0]

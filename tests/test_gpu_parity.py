@@ -115,7 +115,8 @@ def test_apply_all_dense_is_exact_to_rounding(c1):
     assert colerr(Y, oracle.matvec(E, X)) <= 1e-13
 
 
-@pytest.mark.parametrize("near,far,bar", [(1, 1, 1e-5), (1, 2, 5e-3)], ids=["fp32", "fp32_bf16"])
+@pytest.mark.parametrize("near,far,bar", [(1, 1, 1e-5), (1, 2, 5e-3), (1, 3, 5e-3)],
+                         ids=["fp32", "fp32_bf16", "fp32_bf16_single"])
 def test_apply_low_precision_forms(c1, near, far, bar):
     hm = _hm()
     m, E, X = c1

@@ -573,6 +573,23 @@ def main():
         outputs["mixed_bf16"] = Y.cpu().numpy()
         log(f"mixed (FP32 near / BF16 far): {msm:.3f} ms/step, stages {stgm}")
         del opm
+        # the same with single BF16 in-vectors (no lo half)
+        ops1 = hm.Operator(mesh, YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, near_prec=hm.HM_F32,
+                           far_prec=hm.HM_BF16_1)
+        sts1 = ops1.stats()
+        mss1, _, stgs1 = time_form(ops1)
+        as1 = product_bytes(sts1, n, 4, 2, 4)
+        out["mixed_bf16_single_form"] = {
+            "value": round(NRHS * 1000.0 / mss1, 2), "unit": "matvecs/s", "ms_per_step": round(mss1, 4),
+            "hbm_gbs": round(as1["product"] / (mss1 * 1e-3) / 1e9, 1),
+            "product_roofline_frac": round(as1["product"] / (mss1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phaseA_frac": round(as1["phaseA"] / (stgs1["phaseA"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phaseB_frac": round(as1["phaseB"] / (stgs1["phaseB"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_far": sts1["bytes_far"], "stage_ms": {k: round(v, 4) for k, v in stgs1.items()},
+            "form": "FP32 near field, BF16 far factors, X and T rounded to one BF16 each (HM_BF16_1)"}
+        outputs["mixed_bf16_single"] = Y.cpu().numpy()
+        log(f"mixed (FP32 near / BF16 far, single in-vectors): {mss1:.3f} ms/step, stages {stgs1}")
+        del ops1
 
     # ---------------------------------------------------------- GMRES time to 1e-8
     solutions = {}
@@ -723,7 +740,8 @@ def oracle_leg(args, out, m, Xh, outputs, solutions, B, extra):
 
     err = {k: errs(v, ref) for k, v in outputs.items()}
     for k, v in err.items():
-        rec = out if k == "fp32" else out.get({"fp64": "fp64_form", "mixed_bf16": "mixed_bf16_form"}[k], {})
+        rec = out if k == "fp32" else out.get({"fp64": "fp64_form", "mixed_bf16": "mixed_bf16_form",
+                                               "mixed_bf16_single": "mixed_bf16_single_form"}[k], {})
         rec["error_vs_oracle"] = v
     log(f"product errors vs exact operator: {err}")
     # GMRES solutions: exact residual b - A11 x with A11 = E on the crack, identity elsewhere
@@ -790,7 +808,9 @@ def precision_record(steps=10):
     keep = {"mesh": m, "X": Xh, "b": bh, "Y": {}}
     for name, kw, sol in (("fp64_plain", dict(near_prec=hm.HM_F64, far_prec=hm.HM_F64), dict()),
                           ("precision_bf16", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1),
-                           dict(refine=1))):
+                           dict(refine=1)),
+                          ("precision_bf16_single", dict(near_prec=hm.HM_F32, far_prec=hm.HM_BF16_1,
+                                                         keep_f64_reference=1), dict(refine=1))):
         t0 = time.perf_counter()
         op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=64, eta=2.0, aca_tol=1e-6, **kw)
         torch.cuda.synchronize()
@@ -808,7 +828,7 @@ def precision_record(steps=10):
         ms = e0.elapsed_time(e1) / steps
         keep["Y"][name] = Y.cpu().numpy()
         snear = 8 if kw["near_prec"] == hm.HM_F64 else 4
-        sfar = {hm.HM_F64: 8, hm.HM_BF16: 2}[kw["far_prec"]]
+        sfar = {hm.HM_F64: 8, hm.HM_BF16: 2, hm.HM_BF16_1: 2}[kw["far_prec"]]
         alg = product_bytes(st, n, snear, sfar, snear)
         r = {"matvec16_ms": round(ms, 4), "matvecs_per_s": round(NRHS * 1000.0 / ms, 1),
              "hbm_gbs": round(alg["product"] / (ms * 1e-3) / 1e9, 1),
@@ -831,7 +851,8 @@ def precision_record(steps=10):
         torch.cuda.empty_cache()
     base = rec["fp64_plain"]["block3"]["time_to_1e-8_s"]
     rec["speedup_vs_fp64_plain"] = {f"{f}_{p}": round(base / rec[f][p]["time_to_1e-8_s"], 3)
-                                    for f in ("fp64_plain", "precision_bf16") for p in ("block3", "leaf", "ilu")}
+                                    for f in ("fp64_plain", "precision_bf16", "precision_bf16_single")
+                                    for p in ("block3", "leaf", "ilu")}
     rng = np.random.default_rng(3)
     big = np.argsort(-np.abs(bh[0, 2::3]))[:32]
     rows = np.unique(np.concatenate([big, rng.choice(m.ne, 40, replace=False)]))[:64]
@@ -901,7 +922,10 @@ def batched_record(steps=10, warmup=3, n_meshes=64):
                        "random orientations; leaf 64, eta 2, ACA 1e-6, FP32 form",
            "nrhs": {str(k): v for k, v in res.items()}, "build_s": round(build_s, 2), "autotune_s": round(tune_s, 2),
            "autotune": {"candidates": info["tune_candidates"], "ms": [round(x, 4) for x in info["tune_ms"]],
-                        "chosen_leaves_per_task": info["leaves_per_task_a"]},
+                        "chosen_leaves_per_task": info["leaves_per_task_a"],
+                        "phase_b_window_candidates": info["tune_b_candidates"],
+                        "phase_b_window_ms": [round(x, 4) for x in info["tune_b_ms"]],
+                        "chosen_phase_b_window": info["phase_b_window"]},
            "alg_bytes_16": alg16}
     del batch, ops
     return rec, keep

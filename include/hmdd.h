@@ -165,6 +165,7 @@ typedef struct {
     int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
                                as stacked panels of at most this many rows (0: no cap, 1: no stacking); default 64 */
     int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
+    int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..4); default 4 */
 } hm_build_opts;
 
 /* Fill opts with the defaults above (near = far = HM_F64). */
@@ -286,15 +287,16 @@ hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, vo
  * gather, one low-rank phase, one reduction, one dense/low-rank phase per
  * row-tile class and one scatter cover all of them, and the sequence is
  * captured once as a HIP graph (use_graph) and replayed.  autotune times
- * candidate phase-A task sizes on the batch at creation and keeps the
- * fastest (this also changes the member operators' own task size).
+ * candidate phase-A task sizes, then phase-B window heights, on the batch
+ * at creation and keeps the fastest of each (this also changes the member
+ * operators' own task lists).
  * The operators must outlive the batch, share one precision form, and not
  * be applied concurrently with it.
  */
 typedef struct hm_batch hm_batch;
 typedef struct {
     int use_graph;  /* 1: capture once, replay (default 1) */
-    int autotune;   /* 1: tune the phase-A task size at creation (default 1) */
+    int autotune;   /* 1: tune the phase-A task size and the phase-B window at creation (default 1) */
 } hm_batch_opts;
 
 typedef struct {
@@ -305,6 +307,9 @@ typedef struct {
     int tune_candidates[5];    /* candidate task sizes */
     double tune_ms[5];         /* measured ms per batched product, 16 columns */
     int64_t bytes_operators;   /* stored panel bytes of all operators */
+    int phase_b_window;        /* chosen phase-B window (16-row tiles) */
+    int tune_b_candidates[3];  /* candidate phase-B windows (timed with the chosen phase-A size) */
+    double tune_b_ms[3];       /* measured ms per batched product, 16 columns */
 } hm_batch_info;
 
 void hm_batch_opts_default(hm_batch_opts* opts);

@@ -58,7 +58,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int), ("near_prec", ctypes.c_int), ("far_prec", ctypes.c_int),
                 ("keep_f64_reference", ctypes.c_int), ("recompress", ctypes.c_int), ("stack_rows", ctypes.c_int),
-                ("phase_a_items", ctypes.c_int)]
+                ("phase_a_items", ctypes.c_int), ("phase_b_window", ctypes.c_int)]
 
 
 class OpStats(ctypes.Structure):
@@ -127,7 +127,9 @@ class BatchOpts(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_ops", ctypes.c_int), ("total_elements", ctypes.c_int64), ("use_graph", ctypes.c_int),
                 ("leaves_per_task_a", ctypes.c_int), ("tune_candidates", ctypes.c_int * 5),
-                ("tune_ms", ctypes.c_double * 5), ("bytes_operators", ctypes.c_int64)]
+                ("tune_ms", ctypes.c_double * 5), ("bytes_operators", ctypes.c_int64),
+                ("phase_b_window", ctypes.c_int), ("tune_b_candidates", ctypes.c_int * 3),
+                ("tune_b_ms", ctypes.c_double * 3)]
 
 
 class FlowParams(ctypes.Structure):
@@ -568,7 +570,9 @@ class Batch:
         _check(lib().hm_batch_get_info(self._h, ctypes.byref(i)))
         return {"n_ops": i.n_ops, "total_elements": i.total_elements, "use_graph": i.use_graph,
                 "leaves_per_task_a": i.leaves_per_task_a, "tune_candidates": list(i.tune_candidates),
-                "tune_ms": list(i.tune_ms), "bytes_operators": i.bytes_operators}
+                "tune_ms": list(i.tune_ms), "bytes_operators": i.bytes_operators,
+                "phase_b_window": i.phase_b_window, "tune_b_candidates": list(i.tune_b_candidates),
+                "tune_b_ms": list(i.tune_b_ms)}
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

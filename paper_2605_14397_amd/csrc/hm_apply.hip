@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.thi),
                     reinterpret_cast<const char*>(B.tlo), (int)sizeof(FT), Mma<FT>::w};
     S* y = static_cast<S*>(B.y);
-    switch (__builtin_amdgcn_readfirstlane(window_tiles(T.rows, T.r0))) {
+    switch (__builtin_amdgcn_readfirstlane(T.nt)) {
         case 1: phaseB_task<1, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 2: phaseB_task<2, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 3: phaseB_task<3, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;

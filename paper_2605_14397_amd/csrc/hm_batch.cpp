@@ -27,6 +27,9 @@ struct Batch {
     int tuned_leaves = 8;
     double tune_ms[5] = {0, 0, 0, 0, 0};
     int tune_cand[5] = {2, 4, 8, 16, 32};
+    int tuned_window = kTileWindow;
+    double tune_b_ms[3] = {0, 0, 0};
+    int tune_b_cand[3] = {4, 3, 2};
 
     ~Batch()
     {
@@ -70,17 +73,26 @@ struct Batch {
                 r.op = (int32_t)k;
                 rd.push_back(r);
             }
-            for (TaskB t : v.hTasksB) {
-                t.item_begin += ib0;
-                t.op = (int32_t)k;
-                tb.push_back(t);
+            // phase-B windows in leaf order (the operator's own list is
+            // sorted for a launch of its own)
+            for (const TaskB& sec : v.sectionsB) {
+                const int tiles = (sec.rows + 15) / 16;
+                for (int r0 = 0; r0 < tiles; r0 += v.windowB) {
+                    TaskB t = sec;
+                    t.item_begin += ib0;
+                    t.op = (int32_t)k;
+                    t.r0 = r0;
+                    t.nt = std::min(v.windowB, tiles - r0);
+                    tb.push_back(t);
+                }
             }
         }
         L = LaunchSet();
         L.near_prec = near_prec;
         L.far_prec = far_prec;
-        L.splitA = order_tasksA(ta, ia);
-        L.splitB = order_tasksB(tb, ib, near_prec, far_prec);
+        // a merged batch keeps its natural order inside each XCD range
+        L.splitA = order_tasksA(ta, ia, false);
+        L.splitB = order_tasksB(tb, ib, near_prec, far_prec, false);
         upload(bases, hb, s);
         upload(tasksA, ta, s);
         upload(itemsA, ia, s);
@@ -219,11 +231,33 @@ Batch* batch_create(const std::vector<Op*>& ops, const hm_batch_opts& o, hipStre
                 best_l = lpt;
             }
         }
+        // then the phase-B window height with the chosen phase-A task size
+        double best_b = 1e300;
+        int best_w = kTileWindow;
+        for (int c = 0; c < 3; ++c) {
+            const int wnd = b->tune_b_cand[c];
+            for (Op* op : ops) {
+                build_tasksA(*op, op->main, best_l);
+                build_tasksB(op->main, wnd);
+                upload_tasks(op->main, s);
+            }
+            b->merge(s);
+            b->hsegs.clear();
+            b->set_vectors(kNrhs, X.data(), nullptr, Y.data(), nullptr, s);
+            const double ms = time_runs(*b, kNrhs, 3, s);
+            b->tune_b_ms[c] = ms;
+            if (ms < best_b) {
+                best_b = ms;
+                best_w = wnd;
+            }
+        }
         for (Op* op : ops) {
             build_tasksA(*op, op->main, best_l);
+            build_tasksB(op->main, best_w);
             upload_tasks(op->main, s);
         }
         b->tuned_leaves = best_l;
+        b->tuned_window = best_w;
         b->merge(s);
         b->hsegs.clear();
         HM_CHECK_HIP(hipStreamSynchronize(s));
@@ -247,6 +281,11 @@ void batch_info(const Batch& b, hm_batch_info* out)
     out->total_elements = b.total_ne;
     out->use_graph = b.use_graph ? 1 : 0;
     out->leaves_per_task_a = b.tuned_leaves;
+    out->phase_b_window = b.tuned_window;
+    for (int c = 0; c < 3; ++c) {
+        out->tune_b_candidates[c] = b.tune_b_cand[c];
+        out->tune_b_ms[c] = b.tune_b_ms[c];
+    }
     for (int c = 0; c < 5; ++c) {
         out->tune_candidates[c] = b.tune_cand[c];
         out->tune_ms[c] = b.tune_ms[c];

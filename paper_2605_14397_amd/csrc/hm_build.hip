@@ -1157,24 +1157,20 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     pack_dispatch(v.far_prec, job, d_fac, v.far_a.get(), s);
     v.bytes_far = far_elems * prec_bytes(v.far_prec);
 
-    // ---- phase-B tasks: one per (target leaf, section) ----
-    std::vector<TaskB>& tb = v.hTasksB;
+    // ---- phase-B sections: one per (target leaf, section), cut into row windows ----
     std::vector<PanelRef>& ib = v.hItemsB;
-    tb.clear();
+    v.sectionsB.clear();
     ib.clear();
     for (int lf = 0; lf < nleaf; ++lf) {
         const Cluster& c = p.nodes[p.leaves[lf]];
         for (int sec = 0; sec < 2; ++sec) {
             const auto& its = itemsB[2 * (size_t)lf + sec];
-            const int rows = sec_rows(c.size(), sec);
-            for (int r0 = 0; r0 < (rows + 15) / 16; r0 += kTileWindow)
-                tb.push_back(TaskB{op.leaf_xoff[lf] + sec_off(c.size(), sec), rows, (int32_t)ib.size(),
-                                   (int32_t)its.size(), 0, r0, 0});
+            v.sectionsB.push_back(TaskB{op.leaf_xoff[lf] + sec_off(c.size(), sec), sec_rows(c.size(), sec),
+                                        (int32_t)ib.size(), (int32_t)its.size(), 0, 0, 0});
             ib.insert(ib.end(), its.begin(), its.end());
         }
     }
-    v.splitB = order_tasksB(tb, ib, v.near_prec, v.far_prec);
-    v.nTasksB = (int)tb.size();
+    build_tasksB(v, v.windowB);
     v.tfrag_elems = tfrag;
     build_tasksA(op, v, v.leavesPerTaskA);
     // ---- workspaces: the build stream's own is made now ----
@@ -1182,6 +1178,25 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     upload_tasks(v, s);
     (void)v.workspace(s);
     HM_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void build_tasksB(Variant& v, int window)
+{
+    HM_REQUIRE(window >= 1 && window <= kTileWindow, HM_EINVAL, "phase-B window must be 1 to 4 row tiles");
+    v.windowB = window;
+    std::vector<TaskB>& tb = v.hTasksB;
+    tb.clear();
+    for (const TaskB& sec : v.sectionsB) {
+        const int tiles = (sec.rows + 15) / 16;
+        for (int r0 = 0; r0 < tiles; r0 += window) {
+            TaskB t = sec;
+            t.r0 = r0;
+            t.nt = std::min(window, tiles - r0);
+            tb.push_back(t);
+        }
+    }
+    v.splitB = order_tasksB(tb, v.hItemsB, v.near_prec, v.far_prec, true);
+    v.nTasksB = (int)tb.size();
 }
 
 // Phase-A tasks: one per row window of a stacked panel set and run of at
@@ -1242,16 +1257,21 @@ void build_tasksA(const Op& op, Variant& v, int items_per_task)
                 red.push_back(ReduceDesc{slot0 + (int64_t)G.lo[j] * kNrhs, v.t_off[G.blocks[j]], n_slots,
                                          op.lr[G.blocks[j]].rank, 0, (int32_t)slot});
     }
-    v.splitA = order_tasksA(ta, ia);
+    v.splitA = order_tasksA(ta, ia, true);
     v.nTasksA = (int)ta.size();
     v.nReduce = (int)red.size();
     v.tpart_elems = tpart;
 }
 
 // Cut tasks (in their current order) into 8 contiguous ranges of about
-// equal cost and sort each range by cost, longest first (stable).
+// equal cost; with longest_first, sort each range by cost, longest first
+// (stable).  Measured: sorting shortens one operator's product (the long
+// tasks start first, the tail is short), while a merged batch of many
+// operators runs faster in its natural order (each operator's tasks
+// together, in leaf or source order, so an XCD's L2 holds one operator's
+// vectors at a time).
 template <class T>
-static XcdSplit xcd_balance(std::vector<T>& tasks, const std::vector<int64_t>& cost)
+static XcdSplit xcd_balance(std::vector<T>& tasks, const std::vector<int64_t>& cost, bool longest_first)
 {
     XcdSplit sp{};
     const size_t n = tasks.size();
@@ -1265,6 +1285,7 @@ static XcdSplit xcd_balance(std::vector<T>& tasks, const std::vector<int64_t>& c
         sp.begin[x] = (int32_t)q;
     }
     sp.begin[8] = (int32_t)n;
+    if (!longest_first) return sp;
     for (int x = 0; x < 8; ++x) {
         std::vector<std::pair<int64_t, T>> part;
         for (int32_t t = sp.begin[x]; t < sp.begin[x + 1]; ++t) part.push_back({cost[t], tasks[t]});
@@ -1277,9 +1298,8 @@ static XcdSplit xcd_balance(std::vector<T>& tasks, const std::vector<int64_t>& c
 
 // bytes a task streams: its panels' rows inside the window times their
 // granules, plus one 1 KB in-vector k-step per unit
-static int64_t task_bytes(const PanelRef* it, int n_items, int rows, int r0, int wn, int wf)
+static int64_t task_bytes(const PanelRef* it, int n_items, int R, int r0, int wn, int wf)
 {
-    const int R = window_tiles(rows, r0);
     int64_t c = 0;
     for (int q = 0; q < n_items; ++q) {
         const PanelRef& P = it[q];
@@ -1290,36 +1310,36 @@ static int64_t task_bytes(const PanelRef* it, int n_items, int rows, int r0, int
     return c;
 }
 
-XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items)
+XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, bool longest_first)
 {
     for (const TaskA& t : ta) {
         const int R = window_tiles(t.rows, t.r0);
         HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "phase-A window out of range");
     }
-    // by source chunk: one XCD's L2 holds only its share of X
+    // by operator, then source chunk: one XCD's L2 holds only its share of X
     std::stable_sort(ta.begin(), ta.end(), [&](const TaskA& a, const TaskA& b) {
-        return items[a.item_begin].b_off < items[b.item_begin].b_off;
+        return a.op != b.op ? a.op < b.op : items[a.item_begin].b_off < items[b.item_begin].b_off;
     });
     std::vector<int64_t> cost(ta.size());
     for (size_t q = 0; q < ta.size(); ++q) {
         const TaskA& t = ta[q];
         // every sub-panel is far; the element width only scales the cost
-        cost[q] = task_bytes(items.data() + t.item_begin, t.n_items, t.rows, t.r0, 4, 4);
+        cost[q] = task_bytes(items.data() + t.item_begin, t.n_items, window_tiles(t.rows, t.r0), t.r0, 4, 4);
     }
-    return xcd_balance(ta, cost);
+    return xcd_balance(ta, cost, longest_first);
 }
 
-XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec)
+XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec,
+                      bool longest_first)
 {
-    for (const TaskB& t : tb) {
-        const int R = window_tiles(t.rows, t.r0);
-        HM_REQUIRE(R >= 1 && R <= kTileWindow, HM_EINTERNAL, "leaf rows out of range");
-    }
+    for (const TaskB& t : tb)
+        HM_REQUIRE(t.nt >= 1 && t.nt <= kTileWindow && 16 * (t.r0 + t.nt) < t.rows + 16, HM_EINTERNAL,
+                   "phase-B window out of range");
     const int wn = prec_w(near_prec), wf = prec_w(far_prec);
     std::vector<int64_t> cost(tb.size());
     for (size_t q = 0; q < tb.size(); ++q)
-        cost[q] = task_bytes(items.data() + tb[q].item_begin, tb[q].n_items, tb[q].rows, tb[q].r0, wn, wf);
-    return xcd_balance(tb, cost);
+        cost[q] = task_bytes(items.data() + tb[q].item_begin, tb[q].n_items, tb[q].nt, tb[q].r0, wn, wf);
+    return xcd_balance(tb, cost, longest_first);
 }
 
 // Upload the task lists; the workspaces are resized on their next use (the
@@ -1451,6 +1471,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
     HM_REQUIRE(o.stack_rows >= 0, HM_EINVAL, "stack_rows must be >= 0");
     HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
+    HM_REQUIRE(o.phase_b_window >= 1 && o.phase_b_window <= kTileWindow, HM_EINVAL, "phase_b_window must be in [1, 4]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
     HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1,
                HM_EUNSUPPORTED, "far_prec must be F64, F32, BF16 or BF16_1");
@@ -1792,6 +1813,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.main.self_separate = o.near_prec != HM_F64;
     op.main.stackRowsA = o.stack_rows;
     op.main.leavesPerTaskA = o.phase_a_items;
+    op.main.windowB = o.phase_b_window;
     make_variant(op, op.main, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     if (o.keep_f64_reference && o.near_prec != HM_F64) {
         op.ref.reset(new Variant());
@@ -1800,6 +1822,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         op.ref->self_separate = false;
         op.ref->stackRowsA = o.stack_rows;
         op.ref->leavesPerTaskA = o.phase_a_items;
+        op.ref->windowB = o.phase_b_window;
         make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     }
     double t3 = now_ms();

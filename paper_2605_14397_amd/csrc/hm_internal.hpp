@@ -233,7 +233,7 @@ struct TaskB {        // one row window of one section of a target leaf
     int32_t item_begin, n_items;
     int32_t op;       // operator index into the base-pointer table
     int32_t r0;       // first row tile of the window
-    int32_t pad;
+    int32_t nt;       // row tiles of the window (1 .. kTileWindow)
 };
 
 // Phase A works on stacked V^T panels: the factorisations that share a

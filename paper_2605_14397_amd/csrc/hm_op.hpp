@@ -55,6 +55,8 @@ struct Variant {
     std::vector<PanelRef> hItemsB;
     int leavesPerTaskA = 8;
     int stackRowsA = 64;                        // row cap of a stacked V^T panel set (0: none)
+    int windowB = kTileWindow;                  // row tiles per phase-B task window
+    std::vector<TaskB> sectionsB;               // one per (target leaf, section): its rows and items (r0 = 0)
     // factorisations with one source cluster and one section set: their
     // V^T sub-panels are stacked (phase-A items)
     struct VGroup {
@@ -230,14 +232,18 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
                     int64_t max_ne, hipStream_t s, hipEvent_t* ev);
 // (re)build the phase-A task list of a variant with a given task size
 void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
+// phase-B tasks: windows of `window` row tiles (1 .. kTileWindow) over each section
+void build_tasksB(Variant& v, int window);
 // Order a phase-A task list for launch: grouped by row-tile count (one
 // launch per group, largest first); inside a group ordered by the in-vector
 // chunk of the first sub-panel, then longest first inside each XCD's share.
-// sort phase-A tasks for one launch (by source chunk, then XCD ranges of
-// equal load, longest first inside each) and return the ranges
-XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items);
+// sort phase-A tasks for one launch (by operator and source chunk, then XCD
+// ranges of equal load, longest first inside each when asked) and return
+// the ranges
+XcdSplit order_tasksA(std::vector<TaskA>& ta, const std::vector<PanelRef>& items, bool longest_first);
 // the same for phase-B tasks (leaf order, then XCD ranges of equal load)
-XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec);
+XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items, int near_prec, int far_prec,
+                      bool longest_first);
 void upload_tasks(Variant& v, hipStream_t s);
 void tangent_set(Op& op, const double* d_D, const uint8_t* d_mask, hipStream_t s);
 void interface_update(int n_mat, const hm_interface_material* mats, int64_t n, const int32_t* d_mat_id,

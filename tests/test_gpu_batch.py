@@ -46,6 +46,7 @@ def test_batch_equals_single_products_and_oracle(small_faults, near, far, bar):
     batch = hm.Batch(ops, use_graph=True, autotune=True)
     info = batch.info()
     assert info["n_ops"] == len(ops) and info["leaves_per_task_a"] in info["tune_candidates"]
+    assert info["phase_b_window"] in info["tune_b_candidates"] and min(info["tune_b_ms"]) > 0
     nrhs = 5
     Xs = [torch.as_tensor(rhs_columns(m.ndof, nrhs, 4101 + k), device="cuda") for k, m in enumerate(small_faults)]
     Ys = [torch.empty_like(x) for x in Xs]

@@ -142,16 +142,17 @@ def test_apply_ragged_triangles_non_coplanar(two_disks):
         assert err <= bar
 
 
-@pytest.mark.parametrize("stack_rows,items", [(1, 8), (0, 8), (64, 1), (0, 1), (17, 3)],
+@pytest.mark.parametrize("stack_rows,items,window", [(1, 8, 4), (0, 8, 3), (64, 1, 2), (0, 1, 1), (17, 3, 4)],
                          ids=["unstacked", "one_stack_per_cluster", "stacked_partials", "tall_partials", "odd"])
-def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items):
-    # stacked V^T panels (any row cap) and phase-A runs split into partial
-    # slots change only the summation order: every layout meets the FP64 bar
+def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items, window):
+    # stacked V^T panels (any row cap), phase-A runs split into partial
+    # slots and phase-B windows of 1 to 4 row tiles change only the
+    # summation order: every layout meets the FP64 bar
     # on the coplanar grid and on the coupled (three-component) disks
     hm = _hm()
     m, E, X = c1
     op = hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, aca_tol=1e-6, stack_rows=stack_rows,
-                     phase_a_items=items)
+                     phase_a_items=items, phase_b_window=window)
     st = op.stats()
     err = colerr(op.apply(cuda(X)).cpu().numpy(), oracle.matvec(E, X))
     print(f"C1 stack_rows {stack_rows} items {items}: {st['phase_a_stacks']} stacks, {st['phase_a_tasks']} tasks, "
@@ -166,7 +167,8 @@ def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items):
     md, Ed = two_disks
     Xd = rhs_columns(md.ndof, 5, 78)
     opd = hm.Operator(hm.Mesh.from_workload(md), YOUNG, NU, leaf_size=16, aca_tol=1e-9, stack_rows=stack_rows,
-                      phase_a_items=items, near_prec=hm.HM_F32, far_prec=hm.HM_BF16, keep_f64_reference=1)
+                      phase_a_items=items, phase_b_window=window, near_prec=hm.HM_F32, far_prec=hm.HM_BF16,
+                      keep_f64_reference=1)
     ref = oracle.matvec(Ed, Xd)
     e64 = colerr(opd.apply(cuda(Xd), reference=True).cpu().numpy(), ref)
     ebf = colerr(opd.apply(cuda(Xd)).cpu().numpy(), ref)

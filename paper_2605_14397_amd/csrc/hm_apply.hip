@@ -529,82 +529,127 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
 }
 
 // ------------------------------------------------------------------
-// gather / scatter (one segment per operator: blockIdx.y)
+// gather / scatter: one workgroup per leaf, through an LDS tile of the
+// leaf's chunk (dofs x 16 columns), so the fragment-ordered chunk is read or
+// written in memory order and the FP64 vectors element by element
 // ------------------------------------------------------------------
-template <class NT, class FT>
-__device__ inline void gather_body(const Segment& S, const Bases& B, int nrhs)
+// The workgroup's segment: the last one whose first leaf is at or below b.
+__device__ inline int segment_of(const Segment* __restrict__ segs, int nseg, int b)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= S.ne * kNrhs) return;
-    const int c = (int)(idx / S.ne);
-    const int64_t e = idx - (int64_t)c * S.ne;
-    const bool on = c < nrhs && (!S.mask || S.mask[e]);
-    const int64_t base = S.xslot[e] * kNrhs;
-    const int qs = S.xloc[2 * e], qn = S.xloc[2 * e + 1];
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].leaf0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// dof q of a chunk and column c at fragment offset o (inverse of bfrag_offset)
+template <int W>
+__device__ inline void frag_dof(int64_t o, int& q, int& c)
+{
+    const int t = (int)(o % W);
+    const int64_t r = o / W;
+    c = (int)(r % kNrhs);
+    q = (int)(r / kNrhs) * W + t;
+}
+
+template <class NT, class FT>
+__device__ inline void gather_leaf(const Segment& S, const Bases& B, int nrhs, int l)
+{
+    __shared__ double xs[kLeafDofMax][kNrhs + 1];
+    const LeafIo L = S.leaves[l];
+    const int m = L.m;
+    const int n_off = (int)chunk_n_off(m), len = (int)chunk_len(m);
+    for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) xs[idx / kNrhs][idx % kNrhs] = 0.0;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kNrhs * 3 * m; idx += blockDim.x) {
+        const int c = idx / (3 * m), r = idx - c * 3 * m, i = r / 3, a = r - 3 * i;
+        const int64_t e = S.perm[L.begin + i];
+        const bool on = c < nrhs && (!S.mask || S.mask[e]);
+        xs[a < 2 ? 2 * i + a : n_off + i][c] = on ? S.X[c * S.ldx + 3 * e + a] : 0.0;
+    }
+    __syncthreads();
+    const int64_t base = L.xoff * kNrhs;
     NT* xnear = static_cast<NT*>(B.xnear);
-    FT* xfhi = B.xfhi != B.xnear ? static_cast<FT*>(B.xfhi) : nullptr;
-    FT* xflo = static_cast<FT*>(B.xflo);
-    for (int a = 0; a < 3; ++a) {
-        const double x = on ? S.X[c * S.ldx + 3 * e + a] : 0.0;
-        const int q = a < 2 ? qs + a : qn;
-        xnear[base + bfrag_offset(Mma<NT>::w, q, c)] = cvt<NT>(x);
-        if (xfhi) store_t<FT>(xfhi, xflo, base + bfrag_offset(Mma<FT>::w, q, c), x);
+    for (int64_t o = threadIdx.x; o < (int64_t)len * kNrhs; o += blockDim.x) {
+        int q, c;
+        frag_dof<Mma<NT>::w>(o, q, c);
+        xnear[base + o] = cvt<NT>(xs[q][c]);
     }
-}
-
-template <class NT, class FT>
-__global__ void k_gather1(Segment S, const Bases* __restrict__ bases, int nrhs)
-{
-    gather_body<NT, FT>(S, bases[S.op], nrhs);
-}
-
-template <class NT, class FT>
-__global__ void k_gatherN(const Segment* __restrict__ segs, const Bases* __restrict__ bases, int nrhs)
-{
-    const Segment S = segs[blockIdx.y];
-    gather_body<NT, FT>(S, bases[S.op], nrhs);
-}
-
-template <class S_t>
-__device__ inline void scatter_body(const Segment& S, const Bases& B, int nrhs)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= S.ne * nrhs) return;
-    const int c = (int)(idx / S.ne);
-    const int64_t e = idx - (int64_t)c * S.ne;
-    const int64_t rs = S.xslot[e] + S.xloc[2 * e], rn = S.xslot[e] + S.xloc[2 * e + 1];
-    const S_t* Y = static_cast<const S_t*>(B.y);
-    double y[3], x[3];
-    for (int a = 0; a < 3; ++a) {
-        y[a] = (double)Y[(a < 2 ? rs + a : rn) * kNrhs + c];
-        x[a] = S.X[c * S.ldx + 3 * e + a];
-    }
-    if (S.self)
-        for (int a = 0; a < 3; ++a)
-            y[a] += S.self[9 * e + 3 * a] * x[0] + S.self[9 * e + 3 * a + 1] * x[1] + S.self[9 * e + 3 * a + 2] * x[2];
-    if (S.tangent) {
-        if (S.mask && !S.mask[e]) {
-            for (int a = 0; a < 3; ++a) y[a] = x[a];
-        } else if (S.D) {
-            for (int a = 0; a < 3; ++a)
-                y[a] -= S.D[9 * e + 3 * a] * x[0] + S.D[9 * e + 3 * a + 1] * x[1] + S.D[9 * e + 3 * a + 2] * x[2];
+    if (B.xfhi != B.xnear) {
+        FT* xfhi = static_cast<FT*>(B.xfhi);
+        FT* xflo = static_cast<FT*>(B.xflo);
+        for (int64_t o = threadIdx.x; o < (int64_t)len * kNrhs; o += blockDim.x) {
+            int q, c;
+            frag_dof<Mma<FT>::w>(o, q, c);
+            store_t<FT>(xfhi, xflo, base + o, xs[q][c]);
         }
     }
-    double* out = S.Y + c * S.ldy + 3 * e;
-    for (int a = 0; a < 3; ++a) out[a] = S.accumulate ? out[a] + y[a] : y[a];
+}
+
+template <class NT, class FT>
+__global__ __launch_bounds__(256) void k_gather1(Segment S, const Bases* __restrict__ bases, int nrhs)
+{
+    gather_leaf<NT, FT>(S, bases[S.op], nrhs, blockIdx.x);
+}
+
+template <class NT, class FT>
+__global__ __launch_bounds__(256) void k_gatherN(const Segment* __restrict__ segs, int nseg,
+                                                 const Bases* __restrict__ bases, int nrhs)
+{
+    const Segment S = segs[segment_of(segs, nseg, blockIdx.x)];
+    gather_leaf<NT, FT>(S, bases[S.op], nrhs, blockIdx.x - S.leaf0);
 }
 
 template <class S_t>
-__global__ void k_scatter1(Segment S, const Bases* __restrict__ bases, int nrhs)
+__device__ inline void scatter_leaf(const Segment& S, const Bases& B, int nrhs, int l)
 {
-    scatter_body<S_t>(S, bases[S.op], nrhs);
+    __shared__ S_t ys[kLeafDofMax][kNrhs + 1];
+    const LeafIo L = S.leaves[l];
+    const int m = L.m;
+    const int n_off = (int)chunk_n_off(m), len = (int)chunk_len(m);
+    const S_t* Y = static_cast<const S_t*>(B.y) + L.xoff * kNrhs;
+    for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) ys[idx / kNrhs][idx % kNrhs] = Y[idx];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nrhs * m; idx += blockDim.x) {
+        const int c = idx / m, i = idx - c * m;
+        const int64_t e = S.perm[L.begin + i];
+        double y[3], x[3];
+        for (int a = 0; a < 3; ++a) {
+            y[a] = (double)ys[a < 2 ? 2 * i + a : n_off + i][c];
+            x[a] = S.X[c * S.ldx + 3 * e + a];
+        }
+        if (S.self)
+            for (int a = 0; a < 3; ++a)
+                y[a] += S.self[9 * e + 3 * a] * x[0] + S.self[9 * e + 3 * a + 1] * x[1] +
+                        S.self[9 * e + 3 * a + 2] * x[2];
+        if (S.tangent) {
+            if (S.mask && !S.mask[e]) {
+                for (int a = 0; a < 3; ++a) y[a] = x[a];
+            } else if (S.D) {
+                for (int a = 0; a < 3; ++a)
+                    y[a] -= S.D[9 * e + 3 * a] * x[0] + S.D[9 * e + 3 * a + 1] * x[1] + S.D[9 * e + 3 * a + 2] * x[2];
+            }
+        }
+        double* out = S.Y + c * S.ldy + 3 * e;
+        for (int a = 0; a < 3; ++a) out[a] = S.accumulate ? out[a] + y[a] : y[a];
+    }
 }
 
 template <class S_t>
-__global__ void k_scatterN(const Segment* __restrict__ segs, const Bases* __restrict__ bases, int nrhs)
+__global__ __launch_bounds__(256) void k_scatter1(Segment S, const Bases* __restrict__ bases, int nrhs)
 {
-    const Segment S = segs[blockIdx.y];
-    scatter_body<S_t>(S, bases[S.op], nrhs);
+    scatter_leaf<S_t>(S, bases[S.op], nrhs, blockIdx.x);
+}
+
+template <class S_t>
+__global__ __launch_bounds__(256) void k_scatterN(const Segment* __restrict__ segs, int nseg,
+                                                  const Bases* __restrict__ bases, int nrhs)
+{
+    const Segment S = segs[segment_of(segs, nseg, blockIdx.x)];
+    scatter_leaf<S_t>(S, bases[S.op], nrhs, blockIdx.x - S.leaf0);
 }
 
 // ------------------------------------------------------------------
@@ -736,8 +781,10 @@ Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ld
     g.ldy = ldy;
     g.X = X;
     g.Y = Y;
-    g.xslot = op.d_xslot.as<int64_t>();
-    g.xloc = op.d_xloc.as<int32_t>();
+    g.perm = op.d_perm.as<int64_t>();
+    g.leaves = op.d_leaf_io.as<LeafIo>();
+    g.nleaf = (int32_t)op.plan.leaves.size();
+    g.leaf0 = 0;
     g.self = v.self_separate ? op.d_self.as<double>() : nullptr;
     g.D = (tangent && op.has_D) ? op.d_D.as<double>() : nullptr;
     g.mask = (tangent && op.has_mask) ? op.d_mask.as<uint8_t>() : nullptr;
@@ -748,20 +795,18 @@ Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ld
 
 template <class NT, class FT, class ACC>
 static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg1, int nseg,
-                     int64_t max_ne, hipStream_t s, hipEvent_t* ev)
+                     int64_t total_leaves, hipStream_t s, hipEvent_t* ev)
 {
     typedef typename AccScalar<ACC>::type S;
     auto mark = [&](int i) {
         if (ev) HM_CHECK_HIP(hipEventRecord(ev[i], s));
     };
     mark(0);
-    {
-        const unsigned gx = (unsigned)((max_ne * kNrhs + 255) / 256);
-        if (nseg == 1 && seg1)
-            hipLaunchKernelGGL((k_gather1<NT, FT>), dim3(gx), dim3(256), 0, s, *seg1, L.bases, nrhs);
-        else
-            hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
-    }
+    if (nseg == 1 && seg1)
+        hipLaunchKernelGGL((k_gather1<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs);
+    else
+        hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, segs_dev, nseg,
+                           L.bases, nrhs);
     mark(1);
     if (L.nTasksA > 0)
         hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(xcd_grid(L.splitA, 4)), dim3(256), 0, s, L.tasksA, L.splitA,
@@ -774,29 +819,27 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
         hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(xcd_grid(L.splitB, 1)), dim3(256), 0, s, L.tasksB, L.splitB,
                            L.itemsB, L.bases);
     mark(4);
-    {
-        const unsigned gx = (unsigned)((max_ne * nrhs + 255) / 256);
-        if (nseg == 1 && seg1)
-            hipLaunchKernelGGL((k_scatter1<S>), dim3(gx), dim3(256), 0, s, *seg1, L.bases, nrhs);
-        else
-            hipLaunchKernelGGL((k_scatterN<S>), dim3(gx, nseg), dim3(256), 0, s, segs_dev, L.bases, nrhs);
-    }
+    if (nseg == 1 && seg1)
+        hipLaunchKernelGGL((k_scatter1<S>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs);
+    else
+        hipLaunchKernelGGL((k_scatterN<S>), dim3((unsigned)total_leaves), dim3(256), 0, s, segs_dev, nseg, L.bases,
+                           nrhs);
     mark(5);
     HM_CHECK_HIP(hipGetLastError());
 }
 
 void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg1, int nseg,
-                    int64_t max_ne, hipStream_t s, hipEvent_t* ev)
+                    int64_t total_leaves, hipStream_t s, hipEvent_t* ev)
 {
     HM_REQUIRE(nrhs >= 1 && nrhs <= kNrhs, HM_EINVAL, "nrhs must be in [1, 16]");
     if (L.near_prec == HM_F64)
-        launch_t<double, double, d4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+        launch_t<double, double, d4>(L, nrhs, segs_dev, seg1, nseg, total_leaves, s, ev);
     else if (L.far_prec == HM_F32)
-        launch_t<float, float, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+        launch_t<float, float, f4>(L, nrhs, segs_dev, seg1, nseg, total_leaves, s, ev);
     else if (L.far_prec == HM_BF16)
-        launch_t<float, uint16_t, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+        launch_t<float, uint16_t, f4>(L, nrhs, segs_dev, seg1, nseg, total_leaves, s, ev);
     else
-        launch_t<float, bf16s, f4>(L, nrhs, segs_dev, seg1, nseg, max_ne, s, ev);
+        launch_t<float, bf16s, f4>(L, nrhs, segs_dev, seg1, nseg, total_leaves, s, ev);
 }
 
 void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -806,7 +849,7 @@ void apply(const Op& op, const Variant& v, int nrhs, const double* X, int64_t ld
     HM_REQUIRE(ldx >= 3 * op.ne && ldy >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
     HM_REQUIRE(X && Y, HM_EINVAL, "null vector pointer");
     const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0, accumulate);
-    launch_product(launch_set(v, v.workspace(s)), nrhs, nullptr, &g, 1, op.ne, s, ev);
+    launch_product(launch_set(v, v.workspace(s)), nrhs, nullptr, &g, 1, g.nleaf, s, ev);
 }
 
 void apply_in(const Op& op, const Variant& v, void* block, int nrhs, const double* X, int64_t ldx, double* Y,
@@ -818,7 +861,7 @@ void apply_in(const Op& op, const Variant& v, void* block, int nrhs, const doubl
     HM_REQUIRE(((uintptr_t)block & 255) == 0, HM_EINVAL, "workspace block not 256-byte aligned");
     v.prepare_block(block, s);
     const Segment g = make_segment(op, v, X, ldx, Y, ldy, tangent, 0, accumulate);
-    launch_product(launch_set(v, block), nrhs, nullptr, &g, 1, op.ne, s, nullptr);
+    launch_product(launch_set(v, block), nrhs, nullptr, &g, 1, g.nleaf, s, nullptr);
 }
 
 // ------------------------------------------------------------------

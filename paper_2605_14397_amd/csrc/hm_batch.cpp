@@ -115,17 +115,27 @@ struct Batch {
         drop_graph();
     }
 
+    int64_t total_leaves() const
+    {
+        int64_t n = 0;
+        for (const Op* op : ops) n += (int64_t)op->plan.leaves.size();
+        return n;
+    }
+
     void set_vectors(int nrhs, const double* const* X, const int64_t* ldx, double* const* Y, const int64_t* ldy,
                      hipStream_t s)
     {
         bool changed = hsegs.size() != ops.size();
         hsegs.resize(ops.size());
+        int32_t leaf0 = 0;
         for (size_t k = 0; k < ops.size(); ++k) {
             const Op& op = *ops[k];
             const int64_t lx = ldx ? ldx[k] : 3 * op.ne, ly = ldy ? ldy[k] : 3 * op.ne;
             HM_REQUIRE(X[k] && Y[k], HM_EINVAL, "null vector pointer for operator " + std::to_string(k));
             HM_REQUIRE(lx >= 3 * op.ne && ly >= 3 * op.ne, HM_EINVAL, "leading dimension below 3N");
             Segment g = make_segment(op, op.main, X[k], lx, Y[k], ly, false, (int)k);
+            g.leaf0 = leaf0;
+            leaf0 += g.nleaf;
             if (std::memcmp(&g, &hsegs[k], sizeof(Segment)) != 0) changed = true;
             hsegs[k] = g;
         }
@@ -140,7 +150,7 @@ struct Batch {
     void run(int nrhs, hipStream_t s, hipEvent_t* ev = nullptr)
     {
         if (!use_graph || ev) {
-            launch_product(L, nrhs, segs.as<Segment>(), nullptr, (int)ops.size(), max_ne, s, ev);
+            launch_product(L, nrhs, segs.as<Segment>(), nullptr, (int)ops.size(), total_leaves(), s, ev);
             return;
         }
         if (!exec || graph_nrhs != nrhs) {
@@ -149,7 +159,7 @@ struct Batch {
             HM_CHECK_HIP(hipStreamSynchronize(s));
             HM_CHECK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
             try {
-                launch_product(L, nrhs, segs.as<Segment>(), nullptr, (int)ops.size(), max_ne, cap, nullptr);
+                launch_product(L, nrhs, segs.as<Segment>(), nullptr, (int)ops.size(), total_leaves(), cap, nullptr);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(cap, &g);

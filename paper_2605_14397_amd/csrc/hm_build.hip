@@ -1504,18 +1504,13 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     upload(d_geo, geo, s);
     upload(d_perm, p.perm, s);
     {
-        std::vector<int64_t> xslot(mesh.ne);
-        std::vector<int32_t> xloc(2 * mesh.ne);
+        std::vector<LeafIo> io(nleaf);
         for (int lf = 0; lf < nleaf; ++lf) {
             const Cluster& c = p.nodes[p.leaves[lf]];
-            for (int64_t q = c.begin; q < c.end; ++q) {
-                xslot[p.perm[q]] = op.leaf_xoff[lf];
-                xloc[2 * p.perm[q]] = (int32_t)(2 * (q - c.begin));
-                xloc[2 * p.perm[q] + 1] = (int32_t)(chunk_n_off(c.size()) + (q - c.begin));
-            }
+            HM_REQUIRE(chunk_len(c.size()) <= kLeafDofMax, HM_EINTERNAL, "leaf chunk larger than the gather tile");
+            io[lf] = LeafIo{op.leaf_xoff[lf], c.begin, (int32_t)c.size(), 0};
         }
-        upload(op.d_xslot, xslot, s);
-        upload(op.d_xloc, xloc, s);
+        upload(op.d_leaf_io, io, s);
     }
     // ---- low-rank blocks: ACA rounds; a block that does not converge within
     //      max_rank is replaced by its children (leaf pairs that fail become dense) ----

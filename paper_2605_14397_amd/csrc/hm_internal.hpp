@@ -286,13 +286,22 @@ struct LeafPc {
 };
 constexpr int kLeafDofMax = 192;  // 3 x the largest leaf (64 elements)
 
-// One operator's share of the gather and scatter of a product.
+// One leaf's in-vector chunk: where it starts and which elements it holds.
+struct LeafIo {
+    int64_t xoff;     // chunk start (padded dofs)
+    int64_t begin;    // first cluster position of the leaf
+    int32_t m, pad;   // elements
+};
+
+// One operator's share of the gather and scatter of a product (one
+// workgroup per leaf: global leaf index leaf0 + l).
 struct Segment {
     int64_t ne, ldx, ldy;
     const double* X;
     double* Y;
-    const int64_t* xslot;   // chunk start of the element's leaf
-    const int32_t* xloc;    // [2N]: dof of s1 (s2 follows) and of n within the chunk
+    const int64_t* perm;    // cluster position -> element
+    const LeafIo* leaves;   // [nleaf]
+    int32_t nleaf, leaf0;
     const double* self;     // FP64 self blocks or null
     const double* D;        // tangent blocks or null
     const uint8_t* mask;    // active mask or null

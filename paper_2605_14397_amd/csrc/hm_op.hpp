@@ -166,8 +166,7 @@ struct Op {
     int64_t xtot = 0;                 // total padded dofs
     std::vector<LowRank> lr;
     // element tables in original order
-    DevBuf d_xslot;                   // int64 [N]: chunk dof offset (leaf_xoff) of the element's leaf
-    DevBuf d_xloc;                    // int32 [N]: local dof of component 0 within its leaf chunk
+    DevBuf d_leaf_io;                 // LeafIo [leaves]: chunk offset, first cluster position, size
     DevBuf d_self;                    // double [N][9]: FP64 self blocks (original order)
     Variant main;
     std::unique_ptr<Variant> ref;     // FP64 copy when main is not FP64
@@ -229,7 +228,7 @@ Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ld
                      bool tangent, int op_index, bool accumulate = false);
 // gather (one segment per operator, segs on the device when nseg > 1), phases, scatter
 void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg_host, int nseg,
-                    int64_t max_ne, hipStream_t s, hipEvent_t* ev);
+                    int64_t total_leaves, hipStream_t s, hipEvent_t* ev);
 // (re)build the phase-A task list of a variant with a given task size
 void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
 // phase-B tasks: windows of `window` row tiles (1 .. kTileWindow) over each section

@@ -165,7 +165,8 @@ typedef struct {
     int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
                                as stacked panels of at most this many rows (0: no cap, 1: no stacking); default 64 */
     int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
-    int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..4); default 4 */
+    int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..8; 0: 8 for a BF16
+                               far field, 4 otherwise); default 0 */
 } hm_build_opts;
 
 /* Fill opts with the defaults above (near = far = HM_F64). */

@@ -503,7 +503,7 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
 }
 
 // One launch for every task (one workgroup each), compiled for each window
-// height and picked per task.
+// height (1 to 8 row tiles) and picked per task.
 template <class NT, class FT, class ACC>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, XcdSplit sp,
                                                 const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
@@ -524,7 +524,11 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
         case 1: phaseB_task<1, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 2: phaseB_task<2, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 3: phaseB_task<3, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        default: phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 4: phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 5: phaseB_task<5, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 6: phaseB_task<6, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        case 7: phaseB_task<7, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        default: phaseB_task<8, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
     }
 }
 

@@ -29,7 +29,7 @@ struct Batch {
     int tune_cand[5] = {2, 4, 8, 16, 32};
     int tuned_window = kTileWindow;
     double tune_b_ms[3] = {0, 0, 0};
-    int tune_b_cand[3] = {4, 3, 2};
+    int tune_b_cand[3] = {8, 4, 2};
 
     ~Batch()
     {

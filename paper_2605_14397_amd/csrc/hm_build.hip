@@ -1182,7 +1182,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
 
 void build_tasksB(Variant& v, int window)
 {
-    HM_REQUIRE(window >= 1 && window <= kTileWindow, HM_EINVAL, "phase-B window must be 1 to 4 row tiles");
+    HM_REQUIRE(window >= 1 && window <= kTileWindowB, HM_EINVAL, "phase-B window must be 1 to 8 row tiles");
     v.windowB = window;
     std::vector<TaskB>& tb = v.hTasksB;
     tb.clear();
@@ -1333,7 +1333,7 @@ XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items
                       bool longest_first)
 {
     for (const TaskB& t : tb)
-        HM_REQUIRE(t.nt >= 1 && t.nt <= kTileWindow && 16 * (t.r0 + t.nt) < t.rows + 16, HM_EINTERNAL,
+        HM_REQUIRE(t.nt >= 1 && t.nt <= kTileWindowB && 16 * (t.r0 + t.nt) < t.rows + 16, HM_EINTERNAL,
                    "phase-B window out of range");
     const int wn = prec_w(near_prec), wf = prec_w(far_prec);
     std::vector<int64_t> cost(tb.size());
@@ -1471,7 +1471,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
     HM_REQUIRE(o.stack_rows >= 0, HM_EINVAL, "stack_rows must be >= 0");
     HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
-    HM_REQUIRE(o.phase_b_window >= 1 && o.phase_b_window <= kTileWindow, HM_EINVAL, "phase_b_window must be in [1, 4]");
+    HM_REQUIRE(o.phase_b_window >= 0 && o.phase_b_window <= kTileWindowB, HM_EINVAL, "phase_b_window must be in [0, 8]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
     HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1,
                HM_EUNSUPPORTED, "far_prec must be F64, F32, BF16 or BF16_1");
@@ -1808,7 +1808,10 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.main.self_separate = o.near_prec != HM_F64;
     op.main.stackRowsA = o.stack_rows;
     op.main.leavesPerTaskA = o.phase_a_items;
-    op.main.windowB = o.phase_b_window;
+    // 0: 8-tile windows when the far field is BF16 (its in-vectors cost the
+    // most per panel byte), 4 otherwise
+    const int wdef = (o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1) ? kTileWindowB : kTileWindow;
+    op.main.windowB = o.phase_b_window ? o.phase_b_window : wdef;
     make_variant(op, op.main, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     if (o.keep_f64_reference && o.near_prec != HM_F64) {
         op.ref.reset(new Variant());
@@ -1817,7 +1820,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         op.ref->self_separate = false;
         op.ref->stackRowsA = o.stack_rows;
         op.ref->leavesPerTaskA = o.phase_a_items;
-        op.ref->windowB = o.phase_b_window;
+        op.ref->windowB = o.phase_b_window ? o.phase_b_window : kTileWindow;
         make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     }
     double t3 = now_ms();

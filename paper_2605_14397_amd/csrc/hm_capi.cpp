@@ -137,7 +137,7 @@ void hm_build_opts_default(hm_build_opts* o)
     o->recompress = 1;
     o->stack_rows = 64;
     o->phase_a_items = 8;
-    o->phase_b_window = 4;
+    o->phase_b_window = 0;
 }
 
 hm_status hm_operator_build(const hm_mesh* mesh, double young, double nu, const hm_build_opts* opts, void* hip_stream,

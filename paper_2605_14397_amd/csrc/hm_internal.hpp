@@ -214,6 +214,9 @@ struct PanelRef {
 // (tiles r0 .. r0 + R - 1), so every launch runs a small accumulator set at
 // high occupancy; the windows of one panel set re-read its in-vector chunks.
 constexpr int kTileWindow = 4;
+// phase-B windows may be taller (whole 128-row shear sections): each unit's
+// in-vector load then feeds up to eight row tiles
+constexpr int kTileWindowB = 8;
 __host__ __device__ inline int window_tiles(int rows, int r0)
 {
     const int t = (rows + 15) / 16 - r0;
@@ -233,7 +236,7 @@ struct TaskB {        // one row window of one section of a target leaf
     int32_t item_begin, n_items;
     int32_t op;       // operator index into the base-pointer table
     int32_t r0;       // first row tile of the window
-    int32_t nt;       // row tiles of the window (1 .. kTileWindow)
+    int32_t nt;       // row tiles of the window (1 .. kTileWindowB)
 };
 
 // Phase A works on stacked V^T panels: the factorisations that share a

@@ -142,11 +142,11 @@ def test_apply_ragged_triangles_non_coplanar(two_disks):
         assert err <= bar
 
 
-@pytest.mark.parametrize("stack_rows,items,window", [(1, 8, 4), (0, 8, 3), (64, 1, 2), (0, 1, 1), (17, 3, 4)],
+@pytest.mark.parametrize("stack_rows,items,window", [(1, 8, 8), (0, 8, 3), (64, 1, 2), (0, 1, 1), (17, 3, 6)],
                          ids=["unstacked", "one_stack_per_cluster", "stacked_partials", "tall_partials", "odd"])
 def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items, window):
     # stacked V^T panels (any row cap), phase-A runs split into partial
-    # slots and phase-B windows of 1 to 4 row tiles change only the
+    # slots and phase-B windows of 1 to 8 row tiles change only the
     # summation order: every layout meets the FP64 bar
     # on the coplanar grid and on the coupled (three-component) disks
     hm = _hm()

@@ -367,17 +367,19 @@ def main():
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        if os.path.exists(os.path.join(args.summarize_profiles, "mfma")):
-            summarize_counters(args.summarize_profiles)
-            return
-        if os.path.exists(os.path.join(args.summarize_profiles, "trace", "mixed_kernel_stats.csv")):
-            summarize_mixed_profile(args.summarize_profiles)
-        elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "newton_kernel_stats.csv")):
-            summarize_newton_profile(args.summarize_profiles)
-        elif os.path.exists(os.path.join(args.summarize_profiles, "trace", "interface_kernel_stats.csv")):
-            summarize_interface_profiles(args.summarize_profiles)
-        else:
-            summarize_profiles(args.summarize_profiles)
+        d = args.summarize_profiles
+        # every summary whose raw output is under d
+        if os.path.exists(os.path.join(d, "mfma")) and os.path.exists(os.path.join(d, "l2")):
+            summarize_counters(d)
+        if os.path.exists(os.path.join(d, "trace", "mixed_kernel_stats.csv")):
+            summarize_mixed_profile(d)
+        if os.path.exists(os.path.join(d, "trace", "newton_kernel_stats.csv")):
+            summarize_newton_profile(d)
+        if os.path.exists(os.path.join(d, "trace", "interface_kernel_stats.csv")):
+            summarize_interface_profiles(d)
+        if os.path.exists(os.path.join(d, "trace", "primary_kernel_stats.csv")) and os.path.exists(
+                os.path.join(d, "fetch")):
+            summarize_profiles(d)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the H-matrix path here is built and timed on a single MI355X "

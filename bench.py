@@ -351,7 +351,9 @@ def main():
                          "injection: adaptive implicit run of the HF x fault injection (paper's step controller); "
                          "copy: plain device copy of 2 GiB (calibrates HBM byte counters)")
     ap.add_argument("--meshes", type=int, default=64)
-    ap.add_argument("--hf-h", type=float, default=0.46, help="learned form: element leg of the HF x fault mesh (m)")
+    ap.add_argument("--hf-h", type=float, default=None,
+                    help="element leg of the HF x fault mesh (m); default 0.46 (199,880 triangles), "
+                         "1.0 for the coupled form (42,400 triangles)")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned form: passes over the 16 training states")
     ap.add_argument("--neighbors", type=int, default=16, help="learned form: neighbours per element")
     ap.add_argument("--train-extra-law", type=int, default=8,
@@ -366,6 +368,8 @@ def main():
     ap.add_argument("--summarize-profiles", default=None, metavar="DIR",
                     help="write the profiles/ summaries from rocprofv3 CSV output in DIR (no GPU)")
     args = ap.parse_args()
+    if args.hf_h is None:
+        args.hf_h = 1.0 if args.form == "coupled" else 0.46
     if args.summarize_profiles:
         d = args.summarize_profiles
         # every summary whose raw output is under d

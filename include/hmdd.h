@@ -163,7 +163,8 @@ typedef struct {
     int recompress;         /* 1: truncate each cross approximation by SVD at aca_tol / 2 and store it with
                                orthonormal left factors (any rank); default 1 */
     int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
-                               as stacked panels of at most this many rows (0: no cap, 1: no stacking); default 64 */
+                               as stacked panels of at most this many rows (1: no stacking, -1: no cap, 0: 128
+                               rows for HM_BF16_1, 64 otherwise); default 0 */
     int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
     int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..8; 0: 8 for a BF16
                                far field, 4 otherwise); default 0 */

@@ -1123,7 +1123,7 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
         auto it = group_of.emplace(std::make_pair(L.s_node, kind), (int)v.vgroups.size());
         if (it.second) {
             v.vgroups.emplace_back();
-        } else if (v.stackRowsA > 0 && v.vgroups[it.first->second].K + k > v.stackRowsA) {
+        } else if (v.stackRowsA >= 1 && v.vgroups[it.first->second].K + k > v.stackRowsA) {
             it.first->second = (int)v.vgroups.size();
             v.vgroups.emplace_back();
         }
@@ -1469,7 +1469,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.G = G;
     HM_REQUIRE(o.aca_tol > 0.0 && o.aca_tol < 1.0, HM_EINVAL, "aca_tol must be in (0, 1)");
     HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
-    HM_REQUIRE(o.stack_rows >= 0, HM_EINVAL, "stack_rows must be >= 0");
+    HM_REQUIRE(o.stack_rows >= -1, HM_EINVAL, "stack_rows must be >= -1");
     HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
     HM_REQUIRE(o.phase_b_window >= 0 && o.phase_b_window <= kTileWindowB, HM_EINVAL, "phase_b_window must be in [0, 8]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
@@ -1806,7 +1806,9 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     op.main.near_prec = o.near_prec;
     op.main.far_prec = o.far_prec;
     op.main.self_separate = o.near_prec != HM_F64;
-    op.main.stackRowsA = o.stack_rows;
+    // 0: 128 rows for single-BF16 in-vectors (fewer, taller stacks measured
+    // faster there), 64 otherwise; -1: no cap
+    op.main.stackRowsA = o.stack_rows ? o.stack_rows : (o.far_prec == HM_BF16_1 ? 128 : 64);
     op.main.leavesPerTaskA = o.phase_a_items;
     // 0: 8-tile windows when the far field is BF16 (its in-vectors cost the
     // most per panel byte), 4 otherwise
@@ -1818,7 +1820,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         op.ref->near_prec = HM_F64;
         op.ref->far_prec = HM_F64;
         op.ref->self_separate = false;
-        op.ref->stackRowsA = o.stack_rows;
+        op.ref->stackRowsA = o.stack_rows ? o.stack_rows : 64;
         op.ref->leavesPerTaskA = o.phase_a_items;
         op.ref->windowB = o.phase_b_window ? o.phase_b_window : kTileWindow;
         make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);

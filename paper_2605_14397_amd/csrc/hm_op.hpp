@@ -54,7 +54,7 @@ struct Variant {
     std::vector<TaskB> hTasksB;
     std::vector<PanelRef> hItemsB;
     int leavesPerTaskA = 8;
-    int stackRowsA = 64;                        // row cap of a stacked V^T panel set (0: none)
+    int stackRowsA = 64;                        // row cap of a stacked V^T panel set (-1: none)
     int windowB = kTileWindow;                  // row tiles per phase-B task window
     std::vector<TaskB> sectionsB;               // one per (target leaf, section): its rows and items (r0 = 0)
     // factorisations with one source cluster and one section set: their

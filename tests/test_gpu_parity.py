@@ -142,7 +142,7 @@ def test_apply_ragged_triangles_non_coplanar(two_disks):
         assert err <= bar
 
 
-@pytest.mark.parametrize("stack_rows,items,window", [(1, 8, 8), (0, 8, 3), (64, 1, 2), (0, 1, 1), (17, 3, 6)],
+@pytest.mark.parametrize("stack_rows,items,window", [(1, 8, 8), (-1, 8, 3), (64, 1, 2), (-1, 1, 1), (17, 3, 6)],
                          ids=["unstacked", "one_stack_per_cluster", "stacked_partials", "tall_partials", "odd"])
 def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items, window):
     # stacked V^T panels (any row cap), phase-A runs split into partial
@@ -160,7 +160,7 @@ def test_apply_product_layouts_match_oracle(c1, two_disks, stack_rows, items, wi
     assert err <= 1e-6
     if stack_rows == 1:      # one factorisation per stack: the shear and normal parts of each coplanar block
         assert st["phase_a_stacks"] >= st["n_lowrank_blocks"]
-    elif stack_rows in (0, 64):
+    elif stack_rows in (-1, 64):
         assert st["phase_a_stacks"] < st["n_lowrank_blocks"]
     if items == 1:
         assert st["phase_a_partial_bytes"] > 0

@@ -72,7 +72,9 @@ __global__ void k_dense_coef(const ElemGeo* __restrict__ geo, const DenseDesc* _
 // and the components of an element are always sampled together.  Stop when
 // the update of a step has ||U_k V_k^T||_F <= tol ||S_k||_F on two
 // consecutive steps.
-constexpr int kAcaThreads = 256;
+constexpr int kAcaThreads = 256;     // workgroup of a block below kAcaBig elements on both sides
+constexpr int kAcaThreadsBig = 512;  // the larger blocks (a whole CU at the kernel's register use)
+constexpr int kAcaBig = 512;
 constexpr int kAcaMaxRank = 192;
 
 struct AcaDesc {
@@ -97,6 +99,7 @@ __device__ inline void wave_argmax(double& v, int& i)
 }
 
 // block-wide argmax (ties -> smaller index); all threads get the result
+template <int NT>
 __device__ inline void block_argmax(double& v, int& i, double* s_v, int* s_i)
 {
     wave_argmax(v, i);
@@ -108,7 +111,7 @@ __device__ inline void block_argmax(double& v, int& i, double* s_v, int* s_i)
     __syncthreads();
     v = s_v[0];
     i = s_i[0];
-    for (int q = 1; q < kAcaThreads / 64; ++q) {
+    for (int q = 1; q < NT / 64; ++q) {
         double v2 = s_v[q];
         int i2 = s_i[q];
         if (v2 > v || (v2 == v && i2 >= 0 && (i < 0 || i2 < i))) {
@@ -127,13 +130,14 @@ __device__ inline double wave_sum(double v)
 
 // out[q] = A[q] . b for q < nq; A rows of length L with stride L.
 // Deterministic: fixed per-thread order, fixed shuffle tree, fixed wave order.
+template <int NT>
 __device__ void block_dots(const double* A, const double* b, int64_t L, int nq, double* out, double* s_red)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int q0 = 0; q0 < nq; q0 += 8) {
         double acc[8];
         for (int t = 0; t < 8; ++t) acc[t] = 0.0;
-        for (int64_t x = threadIdx.x; x < L; x += kAcaThreads) {
+        for (int64_t x = threadIdx.x; x < L; x += NT) {
             double bx = b[x];
             for (int t = 0; t < 8; ++t)
                 if (q0 + t < nq) acc[t] += A[(int64_t)(q0 + t) * L + x] * bx;
@@ -145,15 +149,15 @@ __device__ void block_dots(const double* A, const double* b, int64_t L, int nq, 
         __syncthreads();
         if (threadIdx.x < 8 && q0 + (int)threadIdx.x < nq) {
             double s = 0.0;
-            for (int ww = 0; ww < kAcaThreads / 64; ++ww) s += s_red[ww * 8 + threadIdx.x];
+            for (int ww = 0; ww < NT / 64; ++ww) s += s_red[ww * 8 + threadIdx.x];
             out[q0 + threadIdx.x] = s;
         }
         __syncthreads();
     }
 }
 
-template <int NC>
-__global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__ geo, const AcaDesc* __restrict__ descs,
+template <int NC, int NT>
+__global__ __launch_bounds__(NT) void k_aca(const ElemGeo* __restrict__ geo, const AcaDesc* __restrict__ descs,
                                                      double kG, double kN, double tol, double* __restrict__ ws,
                                                      uint8_t* __restrict__ flags, int* __restrict__ out_rank,
                                                      int* __restrict__ out_status)
@@ -169,13 +173,13 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
     uint8_t* colused = rowused + D.m;
 
     __shared__ double s_piv[NC * kAcaMaxRank];   // U rows of the pivot element, then V rows
-    __shared__ double s_red[64];
-    __shared__ int s_ired[8];
+    __shared__ double s_red[NT / 64 * 8];
+    __shared__ int s_ired[NT / 64];
     __shared__ double s_uu[NC][kAcaMaxRank], s_vv[NC][kAcaMaxRank];
     __shared__ double s_P[NC * NC];
 
-    for (int i = threadIdx.x; i < D.m; i += kAcaThreads) rowused[i] = 0;
-    for (int j = threadIdx.x; j < D.n; j += kAcaThreads) colused[j] = 0;
+    for (int i = threadIdx.x; i < D.m; i += NT) rowused[i] = 0;
+    for (int j = threadIdx.x; j < D.n; j += NT) colused[j] = 0;
     __syncthreads();
 
     int k = 0, ipiv = D.first_row, conv = 0, misses = 0;
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
     double normS2 = 0.0;
     while (k + 1 <= D.kmax) {
         // ---- residual of pivot row element ipiv ----
-        for (int idx = threadIdx.x; idx < NC * k; idx += kAcaThreads) {
+        for (int idx = threadIdx.x; idx < NC * k; idx += NT) {
             int a = idx / k, q = idx - a * k;
             s_piv[a * kAcaMaxRank + q] = U[(int64_t)q * m3 + NC * ipiv + a];
         }
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
             double x[3] = {R.c[0], R.c[1], R.c[2]};
             double fr[9];
             for (int t = 0; t < 9; ++t) fr[t] = R.fr[t];
-            for (int j = threadIdx.x; j < D.n; j += kAcaThreads) {
+            for (int j = threadIdx.x; j < D.n; j += NT) {
                 double full[9], blk[NC * NC];
                 dd_block(x, fr, geo[D.s_begin + j], kG, kN, full);
 #pragma unroll
@@ -223,19 +227,19 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
                 }
             }
         }
-        block_argmax(best, bestj, s_red, s_ired);
+        block_argmax<NT>(best, bestj, s_red, s_ired);
         const int jpiv = bestj;
         bool zero_row = (jpiv < 0) || !(best > 0.0);
         int k0 = k;
         if (!zero_row) {
             // ---- residual of pivot column element jpiv ----
-            for (int idx = threadIdx.x; idx < NC * k; idx += kAcaThreads) {
+            for (int idx = threadIdx.x; idx < NC * k; idx += NT) {
                 int b = idx / k, q = idx - b * k;
                 s_piv[b * kAcaMaxRank + q] = V[(int64_t)q * n3 + NC * jpiv + b];
             }
             __syncthreads();
             const ElemGeo& S = geo[D.s_begin + jpiv];
-            for (int i = threadIdx.x; i < D.m; i += kAcaThreads) {
+            for (int i = threadIdx.x; i < D.m; i += NT) {
                 const ElemGeo& R = geo[D.t_begin + i];
                 double x[3] = {R.c[0], R.c[1], R.c[2]};
                 double fr[9];
@@ -282,19 +286,19 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
                 const double inv = 1.0 / P[NC * r + c];
                 double* Uk = U + (int64_t)k * m3;
                 double* Vk = V + (int64_t)k * n3;
-                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) Uk[x] = Rcol[x * NC + c];
-                for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) Vk[y] = Rrow[r * n3 + y] * inv;
+                for (int64_t x = threadIdx.x; x < m3; x += NT) Uk[x] = Rcol[x * NC + c];
+                for (int64_t y = threadIdx.x; y < n3; y += NT) Vk[y] = Rrow[r * n3 + y] * inv;
                 __syncthreads();
                 double vj[NC], ui[NC];
                 for (int t = 0; t < NC; ++t) {
                     vj[t] = Vk[NC * jpiv + t];
                     ui[t] = Uk[NC * ipiv + t];
                 }
-                for (int64_t x = threadIdx.x; x < m3; x += kAcaThreads) {
+                for (int64_t x = threadIdx.x; x < m3; x += NT) {
                     double u = Uk[x];
                     for (int t = 0; t < NC; ++t) Rcol[x * NC + t] -= u * vj[t];
                 }
-                for (int64_t y = threadIdx.x; y < n3; y += kAcaThreads) {
+                for (int64_t y = threadIdx.x; y < n3; y += NT) {
                     double v = Vk[y];
                     for (int t = 0; t < NC; ++t) Rrow[t * n3 + y] -= ui[t] * v;
                 }
@@ -319,12 +323,12 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
             }
             double v = -1.0;
             int nxt = -1;
-            for (int i = threadIdx.x; i < D.m; i += kAcaThreads)
+            for (int i = threadIdx.x; i < D.m; i += NT)
                 if (!rowused[i] && nxt < 0) {
                     v = (double)(D.m - i);  // smallest unused index wins
                     nxt = i;
                 }
-            block_argmax(v, nxt, s_red, s_ired);
+            block_argmax<NT>(v, nxt, s_red, s_ired);
             if (nxt < 0) {
                 converged = true;
                 break;
@@ -335,8 +339,8 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
         // ---- Frobenius norm of the approximation, updated incrementally ----
         double step2 = 0.0;
         for (int qn = k0; qn < k; ++qn) {
-            block_dots(U, U + (int64_t)qn * m3, m3, qn + 1, s_uu[qn - k0], s_red);
-            block_dots(V, V + (int64_t)qn * n3, n3, qn + 1, s_vv[qn - k0], s_red);
+            block_dots<NT>(U, U + (int64_t)qn * m3, m3, qn + 1, s_uu[qn - k0], s_red);
+            block_dots<NT>(V, V + (int64_t)qn * n3, n3, qn + 1, s_vv[qn - k0], s_red);
         }
         for (int qn = k0; qn < k; ++qn) {
             double cross = 0.0;
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
         // ---- next pivot row: largest new column block among unused rows ----
         double v = -1.0;
         int nxt = -1;
-        for (int i = threadIdx.x; i < D.m; i += kAcaThreads) {
+        for (int i = threadIdx.x; i < D.m; i += NT) {
             if (rowused[i]) continue;
             double s = 0.0;
             for (int q = k0; q < k; ++q)
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const ElemGeo* __restrict__
                 nxt = i;
             }
         }
-        block_argmax(v, nxt, s_red, s_ired);
+        block_argmax<NT>(v, nxt, s_red, s_ired);
         if (nxt < 0) {
             converged = true;  // every row has been sampled: the block is reproduced
             break;
@@ -1615,40 +1619,69 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
                 }
             DevBuf ws(off * sizeof(double)), fl(std::max<int64_t>(1, foff));
             std::vector<int> rk(all.size()), st(all.size());
+            // blocks with a side of kAcaBig elements or more run with the
+            // larger workgroup on a second stream, beside the others
+            hipStream_t s2 = nullptr;
+            hipEvent_t e_in = nullptr, e_out = nullptr;
+            HM_CHECK_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+            HM_CHECK_HIP(hipEventCreateWithFlags(&e_in, hipEventDisableTiming));
+            HM_CHECK_HIP(hipEventCreateWithFlags(&e_out, hipEventDisableTiming));
             for (int nc = 3; nc >= 1; --nc) {
-                std::vector<AcaDesc> descs;
-                std::vector<int> idx;
+                std::vector<AcaDesc> descs[2];
+                std::vector<int> idx[2];
                 for (size_t q = 0; q < all.size(); ++q)
                     if (all[q]->nc == nc) {
-                        descs.push_back(all[q]->d);
-                        idx.push_back((int)q);
+                        const int big = std::max(all[q]->d.m, all[q]->d.n) >= kAcaBig ? 1 : 0;
+                        descs[big].push_back(all[q]->d);
+                        idx[big].push_back((int)q);
                     }
-                if (descs.empty()) continue;
-                DevBuf d_bd, d_rank(descs.size() * sizeof(int)), d_stat(descs.size() * sizeof(int));
-                upload(d_bd, descs, s);
-                const dim3 grid((unsigned)descs.size());
-                if (nc == 3)
-                    hipLaunchKernelGGL(k_aca<3>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
-                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
-                                       d_stat.as<int>());
-                else if (nc == 2)
-                    hipLaunchKernelGGL(k_aca<2>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
-                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
-                                       d_stat.as<int>());
-                else
-                    hipLaunchKernelGGL(k_aca<1>, grid, dim3(kAcaThreads), 0, s, d_geo.as<ElemGeo>(), d_bd.as<AcaDesc>(),
-                                       kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(), d_rank.as<int>(),
-                                       d_stat.as<int>());
-                HM_CHECK_HIP(hipGetLastError());
-                std::vector<int> r(descs.size()), t(descs.size());
-                HM_CHECK_HIP(hipMemcpyAsync(r.data(), d_rank.get(), r.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-                HM_CHECK_HIP(hipMemcpyAsync(t.data(), d_stat.get(), t.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-                HM_CHECK_HIP(hipStreamSynchronize(s));
-                for (size_t q = 0; q < idx.size(); ++q) {
-                    rk[idx[q]] = r[q];
-                    st[idx[q]] = t[q];
+                DevBuf d_bd[2], d_rank[2], d_stat[2];
+                for (int big = 0; big < 2; ++big) {
+                    if (descs[big].empty()) continue;
+                    d_rank[big].alloc(descs[big].size() * sizeof(int));
+                    d_stat[big].alloc(descs[big].size() * sizeof(int));
+                    upload(d_bd[big], descs[big], s);
+                }
+                HM_CHECK_HIP(hipEventRecord(e_in, s));
+                HM_CHECK_HIP(hipStreamWaitEvent(s2, e_in, 0));
+                for (int big = 0; big < 2; ++big) {
+                    if (descs[big].empty()) continue;
+                    const dim3 grid((unsigned)descs[big].size());
+                    hipStream_t sl = big ? s2 : s;
+                    const unsigned nt = big ? kAcaThreadsBig : kAcaThreads;
+                    auto args = [&](auto kernel) {
+                        hipLaunchKernelGGL(kernel, grid, dim3(nt), 0, sl, d_geo.as<ElemGeo>(), d_bd[big].as<AcaDesc>(),
+                                           kG, kN, o.aca_tol, ws.as<double>(), fl.as<uint8_t>(),
+                                           d_rank[big].as<int>(), d_stat[big].as<int>());
+                    };
+                    if (nc == 3)
+                        big ? args(k_aca<3, kAcaThreadsBig>) : args(k_aca<3, kAcaThreads>);
+                    else if (nc == 2)
+                        big ? args(k_aca<2, kAcaThreadsBig>) : args(k_aca<2, kAcaThreads>);
+                    else
+                        big ? args(k_aca<1, kAcaThreadsBig>) : args(k_aca<1, kAcaThreads>);
+                    HM_CHECK_HIP(hipGetLastError());
+                }
+                HM_CHECK_HIP(hipEventRecord(e_out, s2));
+                HM_CHECK_HIP(hipStreamWaitEvent(s, e_out, 0));
+                for (int big = 0; big < 2; ++big) {
+                    if (descs[big].empty()) continue;
+                    std::vector<int> r(descs[big].size()), t(descs[big].size());
+                    HM_CHECK_HIP(hipMemcpyAsync(r.data(), d_rank[big].get(), r.size() * sizeof(int),
+                                                hipMemcpyDeviceToHost, s));
+                    HM_CHECK_HIP(hipMemcpyAsync(t.data(), d_stat[big].get(), t.size() * sizeof(int),
+                                                hipMemcpyDeviceToHost, s));
+                    HM_CHECK_HIP(hipStreamSynchronize(s));
+                    for (size_t q = 0; q < idx[big].size(); ++q) {
+                        rk[idx[big][q]] = r[q];
+                        st[idx[big][q]] = t[q];
+                    }
                 }
             }
+            HM_CHECK_HIP(hipStreamSynchronize(s2));
+            HM_CHECK_HIP(hipEventDestroy(e_in));
+            HM_CHECK_HIP(hipEventDestroy(e_out));
+            HM_CHECK_HIP(hipStreamDestroy(s2));
             // a pair is kept when every part converged (compact copy of its
             // factors); otherwise it is split
             std::vector<int> jrank(all.size());

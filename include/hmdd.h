@@ -286,14 +286,18 @@ hm_status hm_tangent_set(hm_op* op, const double* d_D, const uint8_t* d_mask, vo
 /*
  * Several independent operators (e.g. many fault meshes, each its own
  * E, paper Sec. 3.1) applied together: their work lists are merged so one
- * gather, one low-rank phase, one reduction, one dense/low-rank phase per
- * row-tile class and one scatter cover all of them, and the sequence is
- * captured once as a HIP graph (use_graph) and replayed.  autotune times
- * candidate phase-A task sizes, then phase-B window heights, on the batch
- * at creation and keeps the fastest of each (this also changes the member
- * operators' own task lists).
+ * gather, one low-rank phase, one reduction, one dense/low-rank phase and
+ * one scatter cover all of them, and the sequence is captured once as a
+ * HIP graph (use_graph) and replayed.  The two phases run as queue-driven
+ * launches: the resident workgroups claim the merged tasks through
+ * per-XCD counters that the gather kernel clears at the start of every
+ * product (no memset node in the graph).  autotune times candidate
+ * phase-A task sizes, then phase-B window heights, on the batch at
+ * creation (each candidate in two rounds, keeping its faster time) and
+ * keeps the fastest of each (this also changes the member operators' own
+ * task lists and sets one phase-B window for all of them).
  * The operators must outlive the batch, share one precision form, and not
- * be applied concurrently with it.
+ * be applied concurrently with it, nor the batch on two streams at once.
  */
 typedef struct hm_batch hm_batch;
 typedef struct {
@@ -307,11 +311,11 @@ typedef struct {
     int use_graph;
     int leaves_per_task_a;     /* chosen phase-A task size */
     int tune_candidates[5];    /* candidate task sizes */
-    double tune_ms[5];         /* measured ms per batched product, 16 columns */
+    double tune_ms[5];         /* ms per batched product, 16 columns (faster of two rounds of 5) */
     int64_t bytes_operators;   /* stored panel bytes of all operators */
     int phase_b_window;        /* chosen phase-B window (16-row tiles) */
     int tune_b_candidates[3];  /* candidate phase-B windows (timed with the chosen phase-A size) */
-    double tune_b_ms[3];       /* measured ms per batched product, 16 columns */
+    double tune_b_ms[3];       /* ms per batched product, 16 columns (faster of two rounds of 5) */
 } hm_batch_info;
 
 void hm_batch_opts_default(hm_batch_opts* opts);

@@ -125,6 +125,40 @@ __host__ inline unsigned xcd_grid(const XcdSplit& sp, int per)
     return 8u * (unsigned)m;
 }
 
+// Queue-driven launches (merged batches): as many workgroups as fit on the
+// chip at once; workgroup b belongs to XCD b & 7 and works on that XCD's
+// range.  The first tasks of a range go one to each of its wavefronts
+// (phase A) or workgroups (phase B) by index; the rest are claimed through
+// the range's counter, the claim of the next task in flight while the
+// current one runs.  A wavefront or workgroup whose range is empty claims
+// from the other ranges.  Claims are taken in range order; every task runs
+// exactly once.
+__device__ inline int claim_wave(int* q, int lane)
+{
+    int t = 0;
+    if (lane == 0) t = atomicAdd(q, 1);
+    return __builtin_amdgcn_readfirstlane(t);
+}
+
+// true when the range's counter has reached `left` claims (a plain read)
+__device__ inline bool range_done(const int* q, int left)
+{
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= left;
+}
+
+// Workgroups of a queue-driven launch: as many as are resident at once
+// (registers and LDS of the kernel's build, compute units of the device), a
+// multiple of 8, at least 8.  Callers cap it by what the tasks can use.
+static unsigned queue_grid(const void* kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    HM_CHECK_HIP(hipGetDevice(&dev));
+    HM_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HM_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+    const int64_t g = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    return (unsigned)std::max<int64_t>(8, g / 8 * 8);
+}
+
 // Buffers of one operand pair: A panels and the in-vector chunks they read.
 struct Side {
     const char* A;     // panel storage
@@ -425,20 +459,15 @@ __device__ void phaseA_wave(const TaskA& T, const PanelRef* items, const MemberT
                 out[(16 * (T.r0 + r) + AccScalar<ACC>::row(lane, v)) * kNrhs + (lane & 15)] = acc[r][v];
 }
 
-// One launch for every task; one wavefront per task, compiled for each
-// window height (1 to 4 row tiles) and picked per task (wave-uniform).
-// The hardware deals the workgroups out as slots free up, which balances
-// the uneven task lengths.
+// Phase A runs one launch for every task, one wavefront per task; the
+// window height (1 to 4 row tiles) is compiled per case and picked per task
+// (wave-uniform).
 template <class FT, class ACC>
-__global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, XcdSplit sp,
-                                                const PanelRef* __restrict__ items,
-                                                const MemberT* __restrict__ members, const Bases* __restrict__ bases)
+__device__ __attribute__((always_inline)) inline void phaseA_task(const TaskA T, const PanelRef* items,
+                                                                   const MemberT* members, const Bases* bases,
+                                                                   int lane)
 {
     typedef typename AccScalar<ACC>::type S;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int t = xcd_task(blockIdx.x, sp, 4, wave);
-    if (t < 0) return;
-    const TaskA T = tasks[t];
     const Bases B = bases[T.op];
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.xfhi),
                     reinterpret_cast<const char*>(B.xflo), (int)sizeof(FT), Mma<FT>::w};
@@ -450,6 +479,47 @@ __global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks,
         case 2: phaseA_wave<2, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
         case 3: phaseA_wave<3, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
         default: phaseA_wave<4, FT, FT, ACC>(T, items, members, farS, tp, th, tl, lane); break;
+    }
+}
+
+// One workgroup per four tasks (one per wavefront) in XCD-range order: the
+// hardware deals the workgroups out as slots free up.
+template <class FT, class ACC>
+__global__ __launch_bounds__(256) void k_phaseA(const TaskA* __restrict__ tasks, XcdSplit sp,
+                                                const PanelRef* __restrict__ items,
+                                                const MemberT* __restrict__ members, const Bases* __restrict__ bases)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int t = xcd_task(blockIdx.x, sp, 4, wave);
+    if (t < 0) return;
+    phaseA_task<FT, ACC>(tasks[t], items, members, bases, lane);
+}
+
+// The resident workgroups work through the XCD ranges' queues, one task
+// per wavefront at a time.
+template <class FT, class ACC>
+__global__ __launch_bounds__(256) void k_phaseA_q(const TaskA* __restrict__ tasks, XcdSplit sp,
+                                                  const PanelRef* __restrict__ items,
+                                                  const MemberT* __restrict__ members,
+                                                  const Bases* __restrict__ bases, int* __restrict__ queue)
+{
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int home = blockIdx.x & 7;
+    const int nstatic = (gridDim.x >> 3) * 4, mine = (blockIdx.x >> 3) * 4 + wave;
+    for (int j = 0; j < 8; ++j) {
+        const int x = (home + j) & 7;
+        const int first = sp.begin[x], n = sp.begin[x + 1] - first;
+        int* q = queue + x * kQueueStride;
+        int t = mine;
+        if (j > 0) {
+            if (range_done(q, n - nstatic)) continue;
+            t = nstatic + claim_wave(q, lane);
+        }
+        while (t < n) {
+            const int next = nstatic + claim_wave(q, lane);
+            phaseA_task<FT, ACC>(tasks[first + t], items, members, bases, lane);
+            t = next;
+        }
     }
 }
 
@@ -502,19 +572,17 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
     reduce_and_store<R, ACC>(acc, T.rows, T.r0, Y, T.y_off, red, wave, lane);
 }
 
-// One launch for every task (one workgroup each), compiled for each window
-// height (1 to 8 row tiles) and picked per task.
+// Phase B runs one launch for every task, one workgroup per task (its four
+// waves share the units); the window height (1 to 8 row tiles) is compiled
+// per case and picked per task.
 template <class NT, class FT, class ACC>
-__global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, XcdSplit sp,
-                                                const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
+__device__ __attribute__((always_inline)) inline void phaseB_one(const TaskB T, const PanelRef* items,
+                                                                  const Bases* bases,
+                                                                  typename AccScalar<ACC>::type* red, int wave,
+                                                                  int lane)
 {
     typedef typename AccScalar<ACC>::type S;
-    __shared__ S red[3 * 256];
-    const int t = xcd_task(blockIdx.x, sp, 1, 0);
-    if (t < 0) return;
-    const TaskB T = tasks[t];
     const Bases B = bases[T.op];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const Side nearS{reinterpret_cast<const char*>(B.nearA), reinterpret_cast<const char*>(B.xnear), nullptr,
                      (int)sizeof(NT), Mma<NT>::w};
     const Side farS{reinterpret_cast<const char*>(B.farA), reinterpret_cast<const char*>(B.thi),
@@ -529,6 +597,54 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
         case 6: phaseB_task<6, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 7: phaseB_task<7, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         default: phaseB_task<8, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+    }
+}
+
+// One workgroup per task in XCD-range order.
+template <class NT, class FT, class ACC>
+__global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, XcdSplit sp,
+                                                const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
+{
+    typedef typename AccScalar<ACC>::type S;
+    __shared__ S red[3 * 256];
+    const int t = xcd_task(blockIdx.x, sp, 1, 0);
+    if (t < 0) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    phaseB_one<NT, FT, ACC>(tasks[t], items, bases, red, wave, lane);
+}
+
+// The resident workgroups work through the XCD ranges' queues, one task
+// per workgroup at a time.
+template <class NT, class FT, class ACC>
+__global__ __launch_bounds__(256) void k_phaseB_q(const TaskB* __restrict__ tasks, XcdSplit sp,
+                                                  const PanelRef* __restrict__ items,
+                                                  const Bases* __restrict__ bases, int* __restrict__ queue)
+{
+    typedef typename AccScalar<ACC>::type S;
+    __shared__ S red[3 * 256];
+    __shared__ int claimed;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int home = blockIdx.x & 7;
+    const int nstatic = gridDim.x >> 3, mine = blockIdx.x >> 3;
+    for (int j = 0; j < 8; ++j) {
+        const int x = (home + j) & 7;
+        const int first = sp.begin[x], n = sp.begin[x + 1] - first;
+        int* q = queue + (8 + x) * kQueueStride;
+        // thread 0 decides for the whole workgroup
+        if (threadIdx.x == 0)
+            claimed = j == 0 ? mine : range_done(q, n - nstatic) ? n : nstatic + atomicAdd(q, 1);
+        __syncthreads();
+        int t = __builtin_amdgcn_readfirstlane(claimed);
+        __syncthreads();
+        while (t < n) {
+            int next = 0;
+            if (threadIdx.x == 0) next = nstatic + atomicAdd(q, 1);
+            phaseB_one<NT, FT, ACC>(tasks[first + t], items, bases, red, wave, lane);
+            if (threadIdx.x == 0) claimed = next;
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(claimed);
+            __syncthreads();
+        }
     }
 }
 
@@ -566,13 +682,32 @@ __device__ inline void gather_leaf(const Segment& S, const Bases& B, int nrhs, i
     const LeafIo L = S.leaves[l];
     const int m = L.m;
     const int n_off = (int)chunk_n_off(m), len = (int)chunk_len(m);
-    for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) xs[idx / kNrhs][idx % kNrhs] = 0.0;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kNrhs * 3 * m; idx += blockDim.x) {
-        const int c = idx / (3 * m), r = idx - c * 3 * m, i = r / 3, a = r - 3 * i;
+    // the chunk's padding rows (past the shear and past the normal dofs) are zero
+    for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) {
+        const int q = idx / kNrhs;
+        if ((q >= 2 * m && q < n_off) || q >= n_off + m) xs[q][idx % kNrhs] = 0.0;
+    }
+    // lane i takes element i, wave w columns 4w .. 4w + 3 (256 threads, at
+    // most 64 elements): one index load, then its twelve values in flight
+    // together (columns past nrhs read column nrhs - 1 and store zeros)
+    const int i = threadIdx.x & 63, c0 = 4 * (threadIdx.x >> 6);
+    if (i < m) {
         const int64_t e = S.perm[L.begin + i];
-        const bool on = c < nrhs && (!S.mask || S.mask[e]);
-        xs[a < 2 ? 2 * i + a : n_off + i][c] = on ? S.X[c * S.ldx + 3 * e + a] : 0.0;
+        const bool act = !S.mask || S.mask[e];
+        double v[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double* x = S.X + (int64_t)min(c0 + k, nrhs - 1) * S.ldx + 3 * e;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[k][a] = x[a];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool on = act && c0 + k < nrhs;
+            xs[2 * i][c0 + k] = on ? v[k][0] : 0.0;
+            xs[2 * i + 1][c0 + k] = on ? v[k][1] : 0.0;
+            xs[n_off + i][c0 + k] = on ? v[k][2] : 0.0;
+        }
     }
     __syncthreads();
     const int64_t base = L.xoff * kNrhs;
@@ -593,16 +728,26 @@ __device__ inline void gather_leaf(const Segment& S, const Bases& B, int nrhs, i
     }
 }
 
-template <class NT, class FT>
-__global__ __launch_bounds__(256) void k_gather1(Segment S, const Bases* __restrict__ bases, int nrhs)
+// the product's first kernel also clears the claim counters of a
+// queue-driven launch
+__device__ inline void clear_queue(int* __restrict__ queue)
 {
+    if (queue && blockIdx.x == 0 && threadIdx.x < kQueueInts / kQueueStride) queue[threadIdx.x * kQueueStride] = 0;
+}
+
+template <class NT, class FT>
+__global__ __launch_bounds__(256) void k_gather1(Segment S, const Bases* __restrict__ bases, int nrhs,
+                                                 int* __restrict__ queue)
+{
+    clear_queue(queue);
     gather_leaf<NT, FT>(S, bases[S.op], nrhs, blockIdx.x);
 }
 
 template <class NT, class FT>
 __global__ __launch_bounds__(256) void k_gatherN(const Segment* __restrict__ segs, int nseg,
-                                                 const Bases* __restrict__ bases, int nrhs)
+                                                 const Bases* __restrict__ bases, int nrhs, int* __restrict__ queue)
 {
+    clear_queue(queue);
     const Segment S = segs[segment_of(segs, nseg, blockIdx.x)];
     gather_leaf<NT, FT>(S, bases[S.op], nrhs, blockIdx.x - S.leaf0);
 }
@@ -617,28 +762,48 @@ __device__ inline void scatter_leaf(const Segment& S, const Bases& B, int nrhs, 
     const S_t* Y = static_cast<const S_t*>(B.y) + L.xoff * kNrhs;
     for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) ys[idx / kNrhs][idx % kNrhs] = Y[idx];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nrhs * m; idx += blockDim.x) {
-        const int c = idx / m, i = idx - c * m;
-        const int64_t e = S.perm[L.begin + i];
-        double y[3], x[3];
-        for (int a = 0; a < 3; ++a) {
-            y[a] = (double)ys[a < 2 ? 2 * i + a : n_off + i][c];
-            x[a] = S.X[c * S.ldx + 3 * e + a];
-        }
+    // lane i takes element i, wave w columns 4w .. 4w + 3 (as in the gather):
+    // the element's index, self and tangent blocks are loaded once and the
+    // vector values of its four columns go out together
+    const int i = threadIdx.x & 63, c0 = 4 * (threadIdx.x >> 6);
+    if (i >= m || c0 >= nrhs) return;
+    const int64_t e = S.perm[L.begin + i];
+    double x[4][3], prev[4][3] = {};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = min(c0 + k, nrhs - 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[k][a] = S.X[c * S.ldx + 3 * e + a];
+        if (S.accumulate)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) prev[k][a] = S.Y[c * S.ldy + 3 * e + a];
+    }
+    double sf[9] = {}, dm[9] = {};
+    if (S.self)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sf[q] = S.self[9 * e + q];
+    const bool passive = S.tangent && S.mask && !S.mask[e];
+    const bool with_d = S.tangent && !passive && S.D;
+    if (with_d)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dm[q] = S.D[9 * e + q];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = c0 + k;
+        if (c >= nrhs) break;
+        double y[3];
+        for (int a = 0; a < 3; ++a) y[a] = (double)ys[a < 2 ? 2 * i + a : n_off + i][c];
         if (S.self)
             for (int a = 0; a < 3; ++a)
-                y[a] += S.self[9 * e + 3 * a] * x[0] + S.self[9 * e + 3 * a + 1] * x[1] +
-                        S.self[9 * e + 3 * a + 2] * x[2];
-        if (S.tangent) {
-            if (S.mask && !S.mask[e]) {
-                for (int a = 0; a < 3; ++a) y[a] = x[a];
-            } else if (S.D) {
-                for (int a = 0; a < 3; ++a)
-                    y[a] -= S.D[9 * e + 3 * a] * x[0] + S.D[9 * e + 3 * a + 1] * x[1] + S.D[9 * e + 3 * a + 2] * x[2];
-            }
+                y[a] += sf[3 * a] * x[k][0] + sf[3 * a + 1] * x[k][1] + sf[3 * a + 2] * x[k][2];
+        if (passive) {
+            for (int a = 0; a < 3; ++a) y[a] = x[k][a];
+        } else if (with_d) {
+            for (int a = 0; a < 3; ++a)
+                y[a] -= dm[3 * a] * x[k][0] + dm[3 * a + 1] * x[k][1] + dm[3 * a + 2] * x[k][2];
         }
         double* out = S.Y + c * S.ldy + 3 * e;
-        for (int a = 0; a < 3; ++a) out[a] = S.accumulate ? out[a] + y[a] : y[a];
+        for (int a = 0; a < 3; ++a) out[a] = S.accumulate ? prev[k][a] + y[a] : y[a];
     }
 }
 
@@ -754,7 +919,7 @@ void* Variant::workspace(hipStream_t s) const
     return w->block.get();
 }
 
-LaunchSet launch_set(const Variant& v, const void* block)
+LaunchSet launch_set(const Variant& v, void* block)
 {
     LaunchSet L;
     L.near_prec = v.near_prec;
@@ -805,21 +970,30 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
     auto mark = [&](int i) {
         if (ev) HM_CHECK_HIP(hipEventRecord(ev[i], s));
     };
+    static const unsigned gridA = queue_grid(reinterpret_cast<const void*>(&k_phaseA_q<FT, ACC>));
+    static const unsigned gridB = queue_grid(reinterpret_cast<const void*>(&k_phaseB_q<NT, FT, ACC>));
     mark(0);
     if (nseg == 1 && seg1)
-        hipLaunchKernelGGL((k_gather1<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs);
+        hipLaunchKernelGGL((k_gather1<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs,
+                           L.queue);
     else
         hipLaunchKernelGGL((k_gatherN<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, segs_dev, nseg,
-                           L.bases, nrhs);
+                           L.bases, nrhs, L.queue);
     mark(1);
-    if (L.nTasksA > 0)
+    if (L.nTasksA > 0 && L.queue)
+        hipLaunchKernelGGL((k_phaseA_q<FT, ACC>), dim3(std::min<unsigned>(gridA, 8u * ((L.nTasksA + 31) / 32))),
+                           dim3(256), 0, s, L.tasksA, L.splitA, L.itemsA, L.membersA, L.bases, L.queue);
+    else if (L.nTasksA > 0)
         hipLaunchKernelGGL((k_phaseA<FT, ACC>), dim3(xcd_grid(L.splitA, 4)), dim3(256), 0, s, L.tasksA, L.splitA,
                            L.itemsA, L.membersA, L.bases);
     mark(2);
     if (L.nReduce > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(L.nReduce), dim3(256), 0, s, L.reduce, L.bases);
     mark(3);
-    if (L.nTasksB > 0)
+    if (L.nTasksB > 0 && L.queue)
+        hipLaunchKernelGGL((k_phaseB_q<NT, FT, ACC>), dim3(std::min<unsigned>(gridB, 8u * ((L.nTasksB + 7) / 8))),
+                           dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB, L.bases, L.queue);
+    else if (L.nTasksB > 0)
         hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(xcd_grid(L.splitB, 1)), dim3(256), 0, s, L.tasksB, L.splitB,
                            L.itemsB, L.bases);
     mark(4);

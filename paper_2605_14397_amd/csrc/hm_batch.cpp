@@ -1,9 +1,10 @@
 // Batched products over many operators (independent meshes): their task
 // lists are merged so that one gather, one phase A, one reduction, one
-// phase B per row-tile class and one scatter cover every operator; the
+// phase B and one scatter cover every operator, the two phases each one
+// queue-driven launch over the merged, byte-balanced task list; the
 // sequence is captured once as a HIP graph and replayed.  A small
 // autotuner picks the phase-A task size (source leaves per wavefront task)
-// by timing candidates on the batch itself.
+// and the phase-B window height by timing candidates on the batch itself.
 #include <algorithm>
 #include <chrono>
 
@@ -14,7 +15,7 @@ namespace hm {
 struct Batch {
     std::vector<Op*> ops;
     int near_prec = HM_F64, far_prec = HM_F64;
-    DevBuf bases, tasksA, itemsA, membersA, reduce, tasksB, itemsB, segs;
+    DevBuf bases, tasksA, itemsA, membersA, reduce, tasksB, itemsB, segs, queue;
     std::vector<std::unique_ptr<ApplyWs>> ws;  // the batch's own workspace per operator
     LaunchSet L;
     int64_t max_ne = 0, total_ne = 0;
@@ -112,6 +113,8 @@ struct Batch {
         L.tasksB = tasksB.as<TaskB>();
         L.nTasksB = (int)tb.size();
         L.itemsB = itemsB.as<PanelRef>();
+        if (!queue.get()) queue.alloc(kQueueInts * sizeof(int));
+        L.queue = queue.as<int>();
         drop_graph();
     }
 
@@ -223,44 +226,49 @@ Batch* batch_create(const std::vector<Op*>& ops, const hm_batch_opts& o, hipStre
             Y.push_back(ys.back().as<double>());
         }
         b->set_vectors(kNrhs, X.data(), nullptr, Y.data(), nullptr, s);
-        double best = 1e300;
-        int best_l = 8;
-        for (int c = 0; c < 5; ++c) {
-            const int lpt = b->tune_cand[c];
+        // one candidate: rebuild and merge the task lists, then time 5 products
+        auto time_config = [&](int lpt, int wnd) {
             for (Op* op : ops) {
                 build_tasksA(*op, op->main, lpt);
-                upload_tasks(op->main, s);
-            }
-            b->merge(s);
-            b->hsegs.clear();
-            b->set_vectors(kNrhs, X.data(), nullptr, Y.data(), nullptr, s);
-            const double ms = time_runs(*b, kNrhs, 3, s);
-            b->tune_ms[c] = ms;
-            if (ms < best) {
-                best = ms;
-                best_l = lpt;
-            }
-        }
-        // then the phase-B window height with the chosen phase-A task size
-        double best_b = 1e300;
-        int best_w = kTileWindow;
-        for (int c = 0; c < 3; ++c) {
-            const int wnd = b->tune_b_cand[c];
-            for (Op* op : ops) {
-                build_tasksA(*op, op->main, best_l);
                 build_tasksB(op->main, wnd);
                 upload_tasks(op->main, s);
             }
             b->merge(s);
             b->hsegs.clear();
             b->set_vectors(kNrhs, X.data(), nullptr, Y.data(), nullptr, s);
-            const double ms = time_runs(*b, kNrhs, 3, s);
-            b->tune_b_ms[c] = ms;
-            if (ms < best_b) {
-                best_b = ms;
-                best_w = wnd;
+            return time_runs(*b, kNrhs, 5, s);
+        };
+        // each candidate is timed in two rounds (the second in reverse
+        // order) and keeps its faster time, so a slow moment of the device
+        // does not decide the choice
+        const int w0 = ops[0]->main.windowB;
+        for (int c = 0; c < 5; ++c) b->tune_ms[c] = 1e300;
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 5; ++k) {
+                const int c = r == 0 ? k : 4 - k;
+                b->tune_ms[c] = std::min(b->tune_ms[c], time_config(b->tune_cand[c], w0));
             }
-        }
+        int best_l = b->tune_cand[0];
+        double best = b->tune_ms[0];
+        for (int c = 1; c < 5; ++c)
+            if (b->tune_ms[c] < best) {
+                best = b->tune_ms[c];
+                best_l = b->tune_cand[c];
+            }
+        // then the phase-B window height with the chosen phase-A task size
+        for (int c = 0; c < 3; ++c) b->tune_b_ms[c] = 1e300;
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k) {
+                const int c = r == 0 ? k : 2 - k;
+                b->tune_b_ms[c] = std::min(b->tune_b_ms[c], time_config(best_l, b->tune_b_cand[c]));
+            }
+        int best_w = b->tune_b_cand[0];
+        double best_b = b->tune_b_ms[0];
+        for (int c = 1; c < 3; ++c)
+            if (b->tune_b_ms[c] < best_b) {
+                best_b = b->tune_b_ms[c];
+                best_w = b->tune_b_cand[c];
+            }
         for (Op* op : ops) {
             build_tasksA(*op, op->main, best_l);
             build_tasksB(op->main, best_w);

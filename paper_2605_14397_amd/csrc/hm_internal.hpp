@@ -230,6 +230,12 @@ struct XcdSplit {
     int32_t begin[9];
 };
 
+// Claim counters of the phase kernels' work queues: one per XCD range and
+// phase (8 for phase A, then 8 for phase B), each on its own 256-byte line.
+// The gather kernel that opens every product sets them to zero.
+constexpr int kQueueStride = 64;                 // ints between counters
+constexpr int kQueueInts = 16 * kQueueStride;
+
 struct TaskB {        // one row window of one section of a target leaf
     int64_t y_off;    // output rows start in Y (section start)
     int32_t rows;     // rows of the section (= rows of each of its panels)

@@ -96,6 +96,7 @@ struct LaunchSet {
     int nTasksB = 0;
     XcdSplit splitA{}, splitB{};
     const PanelRef* itemsB = nullptr;
+    int* queue = nullptr;   // kQueueInts claim counters: queue-driven phase launches (batches)
 };
 
 // One low-rank factorisation U V^T of the components comp0 .. comp0 + comps - 1
@@ -223,7 +224,7 @@ void apply(const Op& op, const Variant& v, int nrhs, const double* d_X, int64_t 
 // bytes at least, 256-byte aligned); zeroes its chunk sections first
 void apply_in(const Op& op, const Variant& v, void* block, int nrhs, const double* d_X, int64_t ldx, double* d_Y,
               int64_t ldy, bool tangent, hipStream_t s, bool accumulate);
-LaunchSet launch_set(const Variant& v, const void* block);
+LaunchSet launch_set(const Variant& v, void* block);
 Segment make_segment(const Op& op, const Variant& v, const double* X, int64_t ldx, double* Y, int64_t ldy,
                      bool tangent, int op_index, bool accumulate = false);
 // gather (one segment per operator, segs on the device when nseg > 1), phases, scatter

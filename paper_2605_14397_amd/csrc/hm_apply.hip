@@ -573,9 +573,11 @@ __device__ void phaseB_task(const TaskB& T, const PanelRef* items, const Side& n
 }
 
 // Phase B runs one launch for every task, one workgroup per task (its four
-// waves share the units); the window height (1 to 8 row tiles) is compiled
-// per case and picked per task.
-template <class NT, class FT, class ACC>
+// waves share the units); the window height (1 to WMAX row tiles) is
+// compiled per case and picked per task.  Task lists whose windows are at
+// most 4 tiles high launch the WMAX = 4 build, whose smaller register
+// footprint keeps more waves per SIMD resident.
+template <class NT, class FT, class ACC, int WMAX>
 __device__ __attribute__((always_inline)) inline void phaseB_one(const TaskB T, const PanelRef* items,
                                                                   const Bases* bases,
                                                                   typename AccScalar<ACC>::type* red, int wave,
@@ -592,16 +594,24 @@ __device__ __attribute__((always_inline)) inline void phaseB_one(const TaskB T, 
         case 1: phaseB_task<1, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 2: phaseB_task<2, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
         case 3: phaseB_task<3, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        case 4: phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        case 5: phaseB_task<5, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        case 6: phaseB_task<6, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        case 7: phaseB_task<7, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
-        default: phaseB_task<8, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+        default:
+            if constexpr (WMAX == 4) {
+                phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane);
+            } else {
+                switch (__builtin_amdgcn_readfirstlane(T.nt)) {
+                    case 4: phaseB_task<4, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+                    case 5: phaseB_task<5, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+                    case 6: phaseB_task<6, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+                    case 7: phaseB_task<7, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+                    default: phaseB_task<8, NT, FT, ACC>(T, items, nearS, farS, y, red, wave, lane); break;
+                }
+            }
+            break;
     }
 }
 
 // One workgroup per task in XCD-range order.
-template <class NT, class FT, class ACC>
+template <class NT, class FT, class ACC, int WMAX>
 __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks, XcdSplit sp,
                                                 const PanelRef* __restrict__ items, const Bases* __restrict__ bases)
 {
@@ -610,12 +620,12 @@ __global__ __launch_bounds__(256) void k_phaseB(const TaskB* __restrict__ tasks,
     const int t = xcd_task(blockIdx.x, sp, 1, 0);
     if (t < 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    phaseB_one<NT, FT, ACC>(tasks[t], items, bases, red, wave, lane);
+    phaseB_one<NT, FT, ACC, WMAX>(tasks[t], items, bases, red, wave, lane);
 }
 
 // The resident workgroups work through the XCD ranges' queues, one task
 // per workgroup at a time.
-template <class NT, class FT, class ACC>
+template <class NT, class FT, class ACC, int WMAX>
 __global__ __launch_bounds__(256) void k_phaseB_q(const TaskB* __restrict__ tasks, XcdSplit sp,
                                                   const PanelRef* __restrict__ items,
                                                   const Bases* __restrict__ bases, int* __restrict__ queue)
@@ -639,7 +649,7 @@ __global__ __launch_bounds__(256) void k_phaseB_q(const TaskB* __restrict__ task
         while (t < n) {
             int next = 0;
             if (threadIdx.x == 0) next = nstatic + atomicAdd(q, 1);
-            phaseB_one<NT, FT, ACC>(tasks[first + t], items, bases, red, wave, lane);
+            phaseB_one<NT, FT, ACC, WMAX>(tasks[first + t], items, bases, red, wave, lane);
             if (threadIdx.x == 0) claimed = next;
             __syncthreads();
             t = __builtin_amdgcn_readfirstlane(claimed);
@@ -936,6 +946,7 @@ LaunchSet launch_set(const Variant& v, void* block)
     L.tasksB = v.tasksB.as<TaskB>();
     L.nTasksB = v.nTasksB;
     L.itemsB = v.itemsB.as<PanelRef>();
+    L.maxNtB = v.maxNtB;
     return L;
 }
 
@@ -971,7 +982,8 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
         if (ev) HM_CHECK_HIP(hipEventRecord(ev[i], s));
     };
     static const unsigned gridA = queue_grid(reinterpret_cast<const void*>(&k_phaseA_q<FT, ACC>));
-    static const unsigned gridB = queue_grid(reinterpret_cast<const void*>(&k_phaseB_q<NT, FT, ACC>));
+    static const unsigned gridB4 = queue_grid(reinterpret_cast<const void*>(&k_phaseB_q<NT, FT, ACC, 4>));
+    static const unsigned gridB8 = queue_grid(reinterpret_cast<const void*>(&k_phaseB_q<NT, FT, ACC, 8>));
     mark(0);
     if (nseg == 1 && seg1)
         hipLaunchKernelGGL((k_gather1<NT, FT>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs,
@@ -990,12 +1002,23 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
     if (L.nReduce > 0)
         hipLaunchKernelGGL((k_reduceT<FT, S>), dim3(L.nReduce), dim3(256), 0, s, L.reduce, L.bases);
     mark(3);
-    if (L.nTasksB > 0 && L.queue)
-        hipLaunchKernelGGL((k_phaseB_q<NT, FT, ACC>), dim3(std::min<unsigned>(gridB, 8u * ((L.nTasksB + 7) / 8))),
-                           dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB, L.bases, L.queue);
-    else if (L.nTasksB > 0)
-        hipLaunchKernelGGL((k_phaseB<NT, FT, ACC>), dim3(xcd_grid(L.splitB, 1)), dim3(256), 0, s, L.tasksB, L.splitB,
-                           L.itemsB, L.bases);
+    if (L.nTasksB > 0) {
+        const bool w4 = L.maxNtB <= 4;
+        const unsigned gq = std::min<unsigned>(w4 ? gridB4 : gridB8, 8u * ((L.nTasksB + 7) / 8));
+        const unsigned gg = xcd_grid(L.splitB, 1);
+        if (L.queue && w4)
+            hipLaunchKernelGGL((k_phaseB_q<NT, FT, ACC, 4>), dim3(gq), dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB,
+                               L.bases, L.queue);
+        else if (L.queue)
+            hipLaunchKernelGGL((k_phaseB_q<NT, FT, ACC, 8>), dim3(gq), dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB,
+                               L.bases, L.queue);
+        else if (w4)
+            hipLaunchKernelGGL((k_phaseB<NT, FT, ACC, 4>), dim3(gg), dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB,
+                               L.bases);
+        else
+            hipLaunchKernelGGL((k_phaseB<NT, FT, ACC, 8>), dim3(gg), dim3(256), 0, s, L.tasksB, L.splitB, L.itemsB,
+                               L.bases);
+    }
     mark(4);
     if (nseg == 1 && seg1)
         hipLaunchKernelGGL((k_scatter1<S>), dim3((unsigned)total_leaves), dim3(256), 0, s, *seg1, L.bases, nrhs);

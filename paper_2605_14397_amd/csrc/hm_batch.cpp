@@ -113,6 +113,8 @@ struct Batch {
         L.tasksB = tasksB.as<TaskB>();
         L.nTasksB = (int)tb.size();
         L.itemsB = itemsB.as<PanelRef>();
+        L.maxNtB = 1;
+        for (const TaskB& t : tb) L.maxNtB = std::max(L.maxNtB, t.nt);
         if (!queue.get()) queue.alloc(kQueueInts * sizeof(int));
         L.queue = queue.as<int>();
         drop_graph();

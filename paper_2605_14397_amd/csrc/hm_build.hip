@@ -1350,6 +1350,8 @@ XcdSplit order_tasksB(std::vector<TaskB>& tb, const std::vector<PanelRef>& items
 // partial-slot section depends on the phase-A task list).
 void upload_tasks(Variant& v, hipStream_t s)
 {
+    v.maxNtB = 1;
+    for (const TaskB& t : v.hTasksB) v.maxNtB = std::max(v.maxNtB, t.nt);
     upload(v.tasksB, v.hTasksB, s);
     upload(v.itemsB, v.hItemsB, s);
     upload(v.tasksA, v.hTasksA, s);

@@ -56,6 +56,7 @@ struct Variant {
     int leavesPerTaskA = 8;
     int stackRowsA = 64;                        // row cap of a stacked V^T panel set (-1: none)
     int windowB = kTileWindow;                  // row tiles per phase-B task window
+    int maxNtB = kTileWindowB;                  // tallest window in hTasksB
     std::vector<TaskB> sectionsB;               // one per (target leaf, section): its rows and items (r0 = 0)
     // factorisations with one source cluster and one section set: their
     // V^T sub-panels are stacked (phase-A items)
@@ -97,6 +98,7 @@ struct LaunchSet {
     XcdSplit splitA{}, splitB{};
     const PanelRef* itemsB = nullptr;
     int* queue = nullptr;   // kQueueInts claim counters: queue-driven phase launches (batches)
+    int maxNtB = kTileWindowB;  // tallest phase-B window of the task list (row tiles)
 };
 
 // One low-rank factorisation U V^T of the components comp0 .. comp0 + comps - 1

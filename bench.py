@@ -180,6 +180,38 @@ def summarize_mixed_profile(prof_dir: str):
         fh.write("\n".join(lines) + "\n")
 
 
+BATCH_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_batch/trace "
+                         "-o batched -- python3 bench.py --form batched --steps 10 --warmup 3")
+BATCH_KERNELS = ("k_gatherN", "k_phaseA_q", "k_reduceT", "k_phaseB_q", "k_scatterN")
+
+
+def summarize_batch_profile(prof_dir: str):
+    """profiles/ kernel times of the batched form's merged product (64 planar
+    faults, FP32, 16 columns): the last 10 merged products of BATCH_PROFILE_
+    COMMAND (its 16-column timed loop), found in the kernel trace as the
+    five-kernel sequence gather, phase A, reduction, phase B, scatter."""
+    import csv
+
+    rows = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "batched_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [_kernel_base(r["Kernel_Name"]) for r in rows]
+    seqs = [rows[i:i + 5] for i in range(len(rows) - 4) if tuple(names[i:i + 5]) == BATCH_KERNELS]
+    last = seqs[-10:]
+    lines = ["# Kernel times: batched form, 64 planar faults (1,349,505 elements), FP32, 16 RHS", "",
+             "Command (from the repository root, `TMPDIR=/tmp`):", "", "```", BATCH_PROFILE_COMMAND, "```", "",
+             f"The last {len(last)} merged products of the run (its 16-column timed loop; one graph replay each), "
+             "from the kernel trace:", "", "| kernel | workgroups | average us | min us | max us |",
+             "|---|---|---|---|---|"]
+    for j, k in enumerate(BATCH_KERNELS):
+        d = [(int(q[j]["End_Timestamp"]) - int(q[j]["Start_Timestamp"])) / 1e3 for q in last]
+        wg = int(last[-1][j]["Grid_Size_X"]) // int(last[-1][j]["Workgroup_Size_X"])
+        lines.append(f"| `{k}` | {wg:,} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
+    span = [(int(q[4]["End_Timestamp"]) - int(q[0]["Start_Timestamp"])) / 1e3 for q in last]
+    lines += ["", f"Gather start to scatter end: {sum(span) / len(span):.1f} us on average."]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_batched_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 NEWTON_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_newton/trace "
                           "-o newton -- python3 bench.py --form newton")
 
@@ -379,6 +411,8 @@ def main():
             summarize_mixed_profile(d)
         if os.path.exists(os.path.join(d, "trace", "newton_kernel_stats.csv")):
             summarize_newton_profile(d)
+        if os.path.exists(os.path.join(d, "trace", "batched_kernel_trace.csv")):
+            summarize_batch_profile(d)
         if os.path.exists(os.path.join(d, "trace", "interface_kernel_stats.csv")):
             summarize_interface_profiles(d)
         if os.path.exists(os.path.join(d, "trace", "primary_kernel_stats.csv")) and os.path.exists(

@@ -557,7 +557,7 @@ def main():
         "wall_s_timed": round(head["wall"], 4),
         "stage_ms": {k: round(v, 4) for k, v in head["stages"].items()},
         "roofline": {
-            "kernel": "k_phaseB (dense pieces + U T; one workgroup per leaf section and 4-tile window; "
+            "kernel": "k_phaseB (dense pieces + U T; one workgroup per leaf section and 8-tile window; "
                       "all launches of one product)",
             "bound": "hbm",
             "achieved": round(achieved, 1),

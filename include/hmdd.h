@@ -166,8 +166,8 @@ typedef struct {
                                as stacked panels of at most this many rows (1: no stacking, -1: no cap, 0: 128
                                rows for HM_BF16_1, 64 otherwise); default 0 */
     int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
-    int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..8; 0: 8 for a BF16
-                               far field, 4 otherwise); default 0 */
+    int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..8; 0: 8);
+                               default 0 */
 } hm_build_opts;
 
 /* Fill opts with the defaults above (near = far = HM_F64). */

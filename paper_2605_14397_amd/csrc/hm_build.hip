@@ -1845,10 +1845,9 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     // faster there), 64 otherwise; -1: no cap
     op.main.stackRowsA = o.stack_rows ? o.stack_rows : (o.far_prec == HM_BF16_1 ? 128 : 64);
     op.main.leavesPerTaskA = o.phase_a_items;
-    // 0: 8-tile windows when the far field is BF16 (its in-vectors cost the
-    // most per panel byte), 4 otherwise
-    const int wdef = (o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1) ? kTileWindowB : kTileWindow;
-    op.main.windowB = o.phase_b_window ? o.phase_b_window : wdef;
+    // 0: 8-tile windows, so each in-vector k-step feeds up to 8 panel tiles
+    // (equal or faster than 4 tiles in every form)
+    op.main.windowB = o.phase_b_window ? o.phase_b_window : kTileWindowB;
     make_variant(op, op.main, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     if (o.keep_f64_reference && o.near_prec != HM_F64) {
         op.ref.reset(new Variant());
@@ -1857,7 +1856,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
         op.ref->self_separate = false;
         op.ref->stackRowsA = o.stack_rows ? o.stack_rows : 64;
         op.ref->leavesPerTaskA = o.phase_a_items;
-        op.ref->windowB = o.phase_b_window ? o.phase_b_window : kTileWindow;
+        op.ref->windowB = o.phase_b_window ? o.phase_b_window : kTileWindowB;
         make_variant(op, *op.ref, dd, d_dense.as<double>(), d_fac.as<double>(), s);
     }
     double t3 = now_ms();

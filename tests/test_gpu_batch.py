@@ -137,3 +137,28 @@ def test_full_size_batch_sampled_rows():
         worst = max(worst, err)
         assert err <= 1e-5, (k, err)
     print(f"64 meshes, every row: worst FP32 per-column error {worst:.2e}", flush=True)
+
+
+def test_batches_with_few_tasks_and_empty_phases():
+    """Queue-driven launches with fewer tasks than XCD ranges or resident
+    workgroups: a batch of one all-dense operator (no phase-A task), one of
+    a single small operator and one mixing both, each replayed twice, equal
+    bit for bit to the operators' own products."""
+    from workloads import square_fault
+
+    hm = _hm()
+    meshes = [square_fault(4), square_fault(24), square_fault(10)]
+    ops = [hm.Operator(hm.Mesh.from_workload(m), YOUNG, NU, leaf_size=32, near_prec=1, far_prec=1) for m in meshes]
+    assert ops[0].stats()["phase_a_tasks"] == 0 and ops[1].stats()["phase_a_tasks"] > 0
+    for sel in ([0], [1], [0, 1, 2]):
+        batch = hm.Batch([ops[k] for k in sel], use_graph=True, autotune=False)
+        for nrhs in (1, 16):
+            Xs = [torch.as_tensor(rhs_columns(meshes[k].ndof, nrhs, 4300 + k), device="cuda") for k in sel]
+            singles = [ops[k].apply(x).cpu().numpy() for k, x in zip(sel, Xs)]
+            for _ in range(2):
+                Ys = [torch.full_like(x, float("nan")) for x in Xs]
+                batch.apply(Xs, Ys)
+                torch.cuda.synchronize()
+                for j in range(len(sel)):
+                    assert np.array_equal(Ys[j].cpu().numpy(), singles[j]), (sel, nrhs, j)
+        del batch

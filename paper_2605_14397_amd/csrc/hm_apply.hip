@@ -769,34 +769,39 @@ __device__ inline void scatter_leaf(const Segment& S, const Bases& B, int nrhs, 
     const LeafIo L = S.leaves[l];
     const int m = L.m;
     const int n_off = (int)chunk_n_off(m), len = (int)chunk_len(m);
+    // lane i takes element i, wave w columns 4w .. 4w + 3 (as in the gather):
+    // the element's index, self and tangent blocks are loaded once and the
+    // vector values of its four columns go out together, before the leaf's
+    // output rows are staged in LDS, so both are in flight at once
+    const int i = threadIdx.x & 63, c0 = 4 * (threadIdx.x >> 6);
+    const bool act = i < m && c0 < nrhs;
+    int64_t e = 0;
+    double x[4][3] = {}, prev[4][3] = {}, sf[9] = {}, dm[9] = {};
+    bool passive = false, with_d = false;
+    if (act) {
+        e = S.perm[L.begin + i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = min(c0 + k, nrhs - 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[k][a] = S.X[c * S.ldx + 3 * e + a];
+            if (S.accumulate)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) prev[k][a] = S.Y[c * S.ldy + 3 * e + a];
+        }
+        if (S.self)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) sf[q] = S.self[9 * e + q];
+        passive = S.tangent && S.mask && !S.mask[e];
+        with_d = S.tangent && !passive && S.D;
+        if (with_d)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dm[q] = S.D[9 * e + q];
+    }
     const S_t* Y = static_cast<const S_t*>(B.y) + L.xoff * kNrhs;
     for (int idx = threadIdx.x; idx < len * kNrhs; idx += blockDim.x) ys[idx / kNrhs][idx % kNrhs] = Y[idx];
     __syncthreads();
-    // lane i takes element i, wave w columns 4w .. 4w + 3 (as in the gather):
-    // the element's index, self and tangent blocks are loaded once and the
-    // vector values of its four columns go out together
-    const int i = threadIdx.x & 63, c0 = 4 * (threadIdx.x >> 6);
-    if (i >= m || c0 >= nrhs) return;
-    const int64_t e = S.perm[L.begin + i];
-    double x[4][3], prev[4][3] = {};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = min(c0 + k, nrhs - 1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x[k][a] = S.X[c * S.ldx + 3 * e + a];
-        if (S.accumulate)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) prev[k][a] = S.Y[c * S.ldy + 3 * e + a];
-    }
-    double sf[9] = {}, dm[9] = {};
-    if (S.self)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) sf[q] = S.self[9 * e + q];
-    const bool passive = S.tangent && S.mask && !S.mask[e];
-    const bool with_d = S.tangent && !passive && S.D;
-    if (with_d)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) dm[q] = S.D[9 * e + q];
+    if (!act) return;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = c0 + k;

@@ -531,7 +531,9 @@ class Operator:
 
 class Batch:
     """Owner of an hm_batch: many operators applied by merged launches
-    (captured as one HIP graph).  Keeps its operators alive."""
+    (captured as one HIP graph; both product phases are queue-driven
+    launches over the merged task list).  Keeps its operators alive; the
+    batch and its operators are not to be applied concurrently."""
 
     def __init__(self, ops, use_graph=True, autotune=True, stream=None):
         self.ops = list(ops)

@@ -165,7 +165,8 @@ typedef struct {
     int stack_rows;         /* product layout: the V^T factors of the blocks sharing a source cluster are stored
                                as stacked panels of at most this many rows (1: no stacking, -1: no cap, 0: 128
                                rows for HM_BF16_1, 64 otherwise); default 0 */
-    int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096); default 8 */
+    int phase_a_items;      /* product layout: source-leaf sub-panels per V^T X task (1..4096; 0: 16 when that
+                               leaves at least 8 tasks per resident phase-A wavefront, else 8); default 0 */
     int phase_b_window;     /* product layout: 16-row tiles per dense + U T task window (1..8; 0: 8);
                                default 0 */
 } hm_build_opts;

@@ -1034,6 +1034,19 @@ static void launch_t(const LaunchSet& L, int nrhs, const Segment* segs_dev, cons
     HM_CHECK_HIP(hipGetLastError());
 }
 
+int phaseA_resident_waves(int near_prec, int far_prec)
+{
+    const void* k = near_prec == HM_F64   ? reinterpret_cast<const void*>(&k_phaseA<double, d4>)
+                    : far_prec == HM_F32  ? reinterpret_cast<const void*>(&k_phaseA<float, f4>)
+                    : far_prec == HM_BF16 ? reinterpret_cast<const void*>(&k_phaseA<uint16_t, f4>)
+                                          : reinterpret_cast<const void*>(&k_phaseA<bf16s, f4>);
+    int dev = 0, cus = 0, per_cu = 0;
+    HM_CHECK_HIP(hipGetDevice(&dev));
+    HM_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HM_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0));
+    return std::max(1, per_cu) * std::max(1, cus) * 4;
+}
+
 void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const Segment* seg1, int nseg,
                     int64_t total_leaves, hipStream_t s, hipEvent_t* ev)
 {

@@ -1176,7 +1176,16 @@ static void make_variant(Op& op, Variant& v, const std::vector<DenseDesc>& dd, c
     }
     build_tasksB(v, v.windowB);
     v.tfrag_elems = tfrag;
-    build_tasksA(op, v, v.leavesPerTaskA);
+    if (v.leavesPerTaskA > 0) {
+        build_tasksA(op, v, v.leavesPerTaskA);
+    } else {
+        // auto: 16 sub-panels per task (fewer partial slots) when that still
+        // leaves at least 8 tasks per resident phase-A wavefront, else 8
+        // (shorter tasks balance the launch's tail)
+        build_tasksA(op, v, 16);
+        if ((int64_t)v.hTasksA.size() < 8 * (int64_t)phaseA_resident_waves(v.near_prec, v.far_prec))
+            build_tasksA(op, v, 8);
+    }
     // ---- workspaces: the build stream's own is made now ----
     v.xel = op.xtot * kNrhs;
     upload_tasks(v, s);
@@ -1476,7 +1485,7 @@ void build_operator(Op& op, const Mesh& mesh_in, const hm_build_opts& o, hipStre
     HM_REQUIRE(o.aca_tol > 0.0 && o.aca_tol < 1.0, HM_EINVAL, "aca_tol must be in (0, 1)");
     HM_REQUIRE(o.max_rank >= 3 && o.max_rank <= kAcaMaxRank, HM_EINVAL, "max_rank must be in [3, 192]");
     HM_REQUIRE(o.stack_rows >= -1, HM_EINVAL, "stack_rows must be >= -1");
-    HM_REQUIRE(o.phase_a_items >= 1 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [1, 4096]");
+    HM_REQUIRE(o.phase_a_items >= 0 && o.phase_a_items <= 4096, HM_EINVAL, "phase_a_items must be in [0, 4096]");
     HM_REQUIRE(o.phase_b_window >= 0 && o.phase_b_window <= kTileWindowB, HM_EINVAL, "phase_b_window must be in [0, 8]");
     HM_REQUIRE(o.near_prec == HM_F64 || o.near_prec == HM_F32, HM_EUNSUPPORTED, "near_prec must be F64 or F32");
     HM_REQUIRE(o.far_prec == HM_F64 || o.far_prec == HM_F32 || o.far_prec == HM_BF16 || o.far_prec == HM_BF16_1,

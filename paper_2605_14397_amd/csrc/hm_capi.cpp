@@ -136,7 +136,7 @@ void hm_build_opts_default(hm_build_opts* o)
     o->keep_f64_reference = 0;
     o->recompress = 1;
     o->stack_rows = 0;
-    o->phase_a_items = 8;
+    o->phase_a_items = 0;
     o->phase_b_window = 0;
 }
 

@@ -234,6 +234,8 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
                     int64_t total_leaves, hipStream_t s, hipEvent_t* ev);
 // (re)build the phase-A task list of a variant with a given task size
 void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
+// phase-A wavefronts resident at once on the current device for a form
+int phaseA_resident_waves(int near_prec, int far_prec);
 // phase-B tasks: windows of `window` row tiles (1 .. kTileWindow) over each section
 void build_tasksB(Variant& v, int window);
 // Order a phase-A task list for launch: grouped by row-tile count (one

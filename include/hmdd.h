@@ -310,11 +310,11 @@ typedef struct {
     int n_ops;
     int64_t total_elements;
     int use_graph;
-    int leaves_per_task_a;     /* chosen phase-A task size */
+    int leaves_per_task_a;     /* chosen phase-A task size (without autotune: the first operator's) */
     int tune_candidates[5];    /* candidate task sizes */
     double tune_ms[5];         /* ms per batched product, 16 columns (faster of two rounds of 5) */
     int64_t bytes_operators;   /* stored panel bytes of all operators */
-    int phase_b_window;        /* chosen phase-B window (16-row tiles) */
+    int phase_b_window;        /* chosen phase-B window (16-row tiles; without autotune: the first operator's) */
     int tune_b_candidates[3];  /* candidate phase-B windows (timed with the chosen phase-A size) */
     double tune_b_ms[3];       /* ms per batched product, 16 columns (faster of two rounds of 5) */
 } hm_batch_info;

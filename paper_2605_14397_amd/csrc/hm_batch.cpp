@@ -28,7 +28,7 @@ struct Batch {
     int tuned_leaves = 8;
     double tune_ms[5] = {0, 0, 0, 0, 0};
     int tune_cand[5] = {8, 12, 16, 24, 32};  // smaller tasks only add partial slots (measured 2 and 4: no faster)
-    int tuned_window = kTileWindow;
+    int tuned_window = kTileWindowB;
     double tune_b_ms[3] = {0, 0, 0};
     int tune_b_cand[3] = {8, 4, 2};
 
@@ -212,6 +212,9 @@ Batch* batch_create(const std::vector<Op*>& ops, const hm_batch_opts& o, hipStre
     }
     b->use_graph = o.use_graph != 0;
     b->merge(s);
+    // without tuning each operator keeps its own layout; report the first's
+    b->tuned_leaves = ops[0]->main.leavesPerTaskA;
+    b->tuned_window = ops[0]->main.windowB;
     if (o.autotune) {
         // time each phase-A task size on zero vectors of the batch's own shape
         std::vector<DevBuf> xs;

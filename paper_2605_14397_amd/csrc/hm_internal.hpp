@@ -210,12 +210,14 @@ struct PanelRef {
     int32_t pad;
 };
 
-// Tasks cover a window of at most kTileWindow row tiles of their panels
-// (tiles r0 .. r0 + R - 1), so every launch runs a small accumulator set at
-// high occupancy; the windows of one panel set re-read its in-vector chunks.
+// Tasks cover a window of row tiles of their panels (tiles r0 .. r0 + R - 1),
+// so every launch runs a small accumulator set; the windows of one panel set
+// re-read its in-vector chunks.  Phase-A windows hold at most kTileWindow
+// tiles (a stack of up to 64 rows in one window).
 constexpr int kTileWindow = 4;
 // phase-B windows may be taller (whole 128-row shear sections): each unit's
-// in-vector load then feeds up to eight row tiles
+// in-vector load then feeds up to eight row tiles; lists whose windows stay
+// within kTileWindow tiles run a build with fewer registers
 constexpr int kTileWindowB = 8;
 __host__ __device__ inline int window_tiles(int rows, int r0)
 {

@@ -55,7 +55,7 @@ struct Variant {
     std::vector<PanelRef> hItemsB;
     int leavesPerTaskA = 8;
     int stackRowsA = 64;                        // row cap of a stacked V^T panel set (-1: none)
-    int windowB = kTileWindow;                  // row tiles per phase-B task window
+    int windowB = kTileWindowB;                 // row tiles per phase-B task window
     int maxNtB = kTileWindowB;                  // tallest window in hTasksB
     std::vector<TaskB> sectionsB;               // one per (target leaf, section): its rows and items (r0 = 0)
     // factorisations with one source cluster and one section set: their
@@ -236,7 +236,7 @@ void launch_product(const LaunchSet& L, int nrhs, const Segment* segs_dev, const
 void build_tasksA(const Op& op, Variant& v, int leaves_per_task);
 // phase-A wavefronts resident at once on the current device for a form
 int phaseA_resident_waves(int near_prec, int far_prec);
-// phase-B tasks: windows of `window` row tiles (1 .. kTileWindow) over each section
+// phase-B tasks: windows of `window` row tiles (1 .. kTileWindowB) over each section
 void build_tasksB(Variant& v, int window);
 // Order a phase-A task list for launch: grouped by row-tile count (one
 // launch per group, largest first); inside a group ordered by the in-vector

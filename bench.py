@@ -183,6 +183,14 @@ def summarize_mixed_profile(prof_dir: str):
 BATCH_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_batch/trace "
                          "-o batched -- python3 bench.py --form batched --steps 10 --warmup 3")
 BATCH_KERNELS = ("k_gatherN", "k_phaseA_q", "k_reduceT", "k_phaseB_q", "k_scatterN")
+# HBM reads and L2 hits of the batched form's phase kernels (one counter group per run)
+BATCH_COUNTER_COMMANDS = {
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_phaseA_q|k_phaseB_q\" --output-format csv "
+             "-d gpurun_out/prof_batch/fetch -o batched -- python3 bench.py --form batched --steps 2 --warmup 1",
+    "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --kernel-include-regex \"k_phaseA_q|k_phaseB_q\" "
+          "--output-format csv -d gpurun_out/prof_batch/l2 -o batched -- python3 bench.py --form batched --steps 2 "
+          "--warmup 1",
+}
 
 
 def summarize_batch_profile(prof_dir: str):
@@ -209,6 +217,38 @@ def summarize_batch_profile(prof_dir: str):
     span = [(int(q[4]["End_Timestamp"]) - int(q[0]["Start_Timestamp"])) / 1e3 for q in last]
     lines += ["", f"Gather start to scatter end: {sum(span) / len(span):.1f} us on average."]
     with open(os.path.join(ROOT, "profiles", "kernel_stats_batched_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    if os.path.exists(os.path.join(prof_dir, "fetch")) and os.path.exists(os.path.join(prof_dir, "l2")):
+        summarize_batch_counters(prof_dir)
+
+
+def summarize_batch_counters(prof_dir: str):
+    """profiles/traffic_batched_fp32.md: FETCH_SIZE (scaled by the copy
+    calibration in profiles/traffic.json) and L2 hits of the merged
+    product's phase kernels, the last dispatch of each (16 columns)."""
+    import csv
+    import glob
+
+    def last(sub):
+        f = glob.glob(os.path.join(prof_dir, sub, "*counter_collection.csv"))[0]
+        out = {}
+        for r in sorted(csv.DictReader(open(f)), key=lambda r: int(r.get("Dispatch_Id", 0) or 0)):
+            out[(_kernel_base(r["Kernel_Name"]), r["Counter_Name"])] = float(r["Counter_Value"])
+        return out
+
+    scale = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["fetch_scale"]
+    fe, l2 = last("fetch"), last("l2")
+    lines = ["# HBM reads and L2 hits: batched form, 64 planar faults, FP32, 16 RHS", "",
+             "Commands (one counter group per run, from the repository root, `TMPDIR=/tmp`):", "", "```",
+             BATCH_COUNTER_COMMANDS["fetch"], BATCH_COUNTER_COMMANDS["l2"], "```", "",
+             f"FETCH_SIZE scaled by {scale:.4f} (plain-copy calibration, `profiles/traffic.json`); the last "
+             "dispatch of each kernel (the 16-column timed loop).", "",
+             "| kernel | HBM bytes read | TCC_HIT | TCC_MISS | L2 hit rate |", "|---|---|---|---|---|"]
+    for k in ("k_phaseA_q", "k_phaseB_q"):
+        h, m = l2.get((k, "TCC_HIT_sum"), 0.0), l2.get((k, "TCC_MISS_sum"), 0.0)
+        lines.append(f"| `{k}` | {fe.get((k, 'FETCH_SIZE'), 0.0) * 1024 * scale:,.0f} | {h:.4g} | {m:.4g} | "
+                     f"{100 * h / max(1.0, h + m):.1f} % |")
+    with open(os.path.join(ROOT, "profiles", "traffic_batched_fp32.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 

@@ -136,8 +136,9 @@ def test_recompressed_factors_survive_short_formats_at_every_rank_class():
 
 def test_high_ranks_run_in_row_windows():
     """At ACA 1e-12 the low-rank blocks of a 48 x 48 fault exceed 64 (more
-    than four row tiles): their phase-A and phase-B tasks are split into
-    windows of four tiles.  The product still follows the tolerance."""
+    than four row tiles): their phase-A tasks are split into windows of four
+    tiles and their phase-B rows into windows of up to eight.  The product
+    still follows the tolerance."""
     m = rect_grid(48, 48, 1.0)
     op, err = _product_check(m, 1e-10, nrhs=16, leaf_size=32, eta=2.0, aca_tol=1e-12)
     assert op.stats()["max_rank"] > 64
